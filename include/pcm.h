@@ -1,0 +1,233 @@
+/*
+ * pcm.h -- C ABI of the MI355X (gfx950) C-PCM / ISWIG solvation library.
+ *
+ * The library implements the solvation hot path of Liu, Luehr, Kulik and
+ * Martinez, "Quantum Chemistry for Solvated Molecules on GPUs using Polarizable
+ * Continuum Models" (arXiv:1505.07851):
+ *   - the ISWIG surface (Sec. 2, Eqs. 3, 7, 9; parameters of Sec. 3),
+ *   - the screened electrostatic integrals L^k_{mu nu} (Sec. 2, Eq. 6) used as
+ *     c = L P (Eq. 5) and as the Fock correction sum_k q_k L^k (Eq. 10),
+ *   - a matrix-free preconditioned CG solve of A q = -f (B z + c) (Eq. 1) with
+ *     the dynamic threshold (Eq. 21) and randomized block-Jacobi preconditioner
+ *     (Sec. 4b),
+ *   - the energy (Eq. 13) and its gradient at fixed density (Eq. 14, Eq. 22).
+ *
+ * Conventions shared by every entry point:
+ *   - atomic units (bohr, hartree, elementary charge);
+ *   - FP64, row-major, contiguous arrays;
+ *   - arrays documented as DEVICE are device pointers on the context's GPU
+ *     (for example torch CUDA/HIP tensors); arrays documented as HOST are host
+ *     memory read during the call and not retained;
+ *   - the caller owns every numeric buffer; the library owns pcm_ctx and
+ *     pcm_mol and the device workspace inside them; no call frees a caller
+ *     buffer;
+ *   - work is enqueued on the context's stream; pcm_esp, pcm_fock and pcm_grad
+ *     are asynchronous with respect to the host, pcm_build_surface,
+ *     pcm_update_geometry, pcm_solve and pcm_energy return after their results
+ *     are complete;
+ *   - every call returns a pcm_status; the message of the last failure is kept
+ *     in the context (pcm_last_error); nothing throws or aborts across the ABI;
+ *   - argument checks run before any GPU call, so PCM_E_ARG / PCM_E_UNSUPPORTED
+ *     never leave partial device work behind;
+ *   - one context per host thread.
+ */
+#ifndef PCM_H
+#define PCM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PCM_OK = 0,
+    PCM_E_ARG = 1,          /* invalid argument (null, non-finite, non-positive, out of range) */
+    PCM_E_ALLOC = 2,        /* device or host allocation failed */
+    PCM_E_HIP = 3,          /* a HIP runtime call failed (includes: no GPU present) */
+    PCM_E_NOCONV = 4,       /* solver hit max_iter; q and info still hold the best iterate */
+    PCM_E_NOTPD = 5,        /* a preconditioner block is not positive definite */
+    PCM_E_UNSUPPORTED = 6,  /* angular momentum above d, or more than 8 primitives in a shell */
+    PCM_E_STATE = 7         /* call made on an object in the wrong state (e.g. stale sizes) */
+} pcm_status;
+
+enum { PCM_FP64 = 0, PCM_MIXED = 1 };
+enum { PCM_PRECOND_NONE = 0, PCM_PRECOND_JACOBI = 1, PCM_PRECOND_RBJ = 2 };
+
+typedef struct pcm_ctx pcm_ctx;
+typedef struct pcm_mol pcm_mol;
+
+/* Model parameters (Sec. 2 and Sec. 3).
+ *   eps            dielectric constant; f = (eps-1)/(eps+k_factor) (Eq. 1). Default 78.39.
+ *   k_factor       k of Eq. 1; 0 (C-PCM) by default, 0.5 gives COSMO.
+ *   zeta0          optimized exponent zeta of Eq. 7. Default 4.9.
+ *   switch_thresh  points with switching value S_k below this are dropped (Sec. 3). Default 1e-8.
+ *   schwarz_thresh primitive-pair screening cutoff (Eq. 15, Eq. 18). Default 1e-12.
+ *   diag_const     constant of Eq. 3: A_kk = diag_const * zeta_k / S_k. Default sqrt(2/pi),
+ *                  the r -> 0 limit of Eq. 2 for two equal Gaussians.
+ *   precision      PCM_FP64 or PCM_MIXED for the integral kernels (FP32 Hermite/Boys
+ *                  evaluation with FP64 accumulation). Default PCM_FP64. */
+typedef struct {
+    double eps, k_factor, zeta0, switch_thresh, schwarz_thresh, diag_const;
+    int precision;
+} pcm_params;
+
+void pcm_default_params(pcm_params *p);
+
+/* Contracted Cartesian Gaussian basis (Sec. 2, Eqs. 11-12).  HOST arrays.
+ *   shell_atom[s]  atom carrying shell s (0..n_atoms-1)
+ *   shell_l[s]     0, 1 or 2 (s, p, d); Cartesian components in lexicographic order
+ *                  (x, y, z; xx, xy, xz, yy, yz, zz); basis functions numbered shell by shell
+ *   shell_nprim[s] 1..8 primitives
+ *   shell_off[s]   offset of the shell's primitives in prim_exp / prim_coef
+ *   prim_exp, prim_coef  exponents (> 0) and raw contraction coefficients; the library
+ *                  normalises every Cartesian component of every contracted shell to unit
+ *                  self-overlap. */
+typedef struct {
+    int n_shells;
+    const int *shell_atom, *shell_l, *shell_nprim, *shell_off;
+    const double *prim_exp, *prim_coef;
+} pcm_basis;
+
+/* Solver options (Sec. 4b).
+ *   precond     PCM_PRECOND_NONE, _JACOBI (diag(A)^-1) or _RBJ (randomized block Jacobi)
+ *   block       RBJ block size l (paper: 100)
+ *   seed        SplitMix64 seed of the RBJ partition
+ *   tol         stop when ||A q - b||_2 < tol (Eq. 20), absolute, atomic units; use
+ *               pcm_dynamic_threshold for the Eq. 21 schedule
+ *   max_iter    bound on matrix-vector products
+ *   warm_start  nonzero: q holds the initial guess on entry; zero: start from q = 0
+ *   precision   PCM_FP64 (FP64 matvec) or PCM_MIXED (FP32 matvec inside FP64
+ *               iterative refinement; FP64 residual, dots and energy)
+ *   inner_rtol  relative residual reduction of each inner FP32 solve (mixed only; 0: 1e-4) */
+typedef struct {
+    int precond;
+    int block;
+    unsigned long long seed;
+    double tol;
+    int max_iter;
+    int warm_start;
+    int precision;
+    double inner_rtol;
+} pcm_solve_opts;
+
+void pcm_default_solve_opts(pcm_solve_opts *o);
+
+/* Solver report (HOST struct filled by pcm_solve). */
+typedef struct {
+    int iters;          /* matrix-vector products with A (all precisions) */
+    int refinements;    /* outer FP64 refinement steps (mixed) */
+    double resid;       /* final ||A q - b||_2 recomputed in FP64 */
+    double energy;      /* Eq. 13 energy at the returned q */
+    double setup_ms;    /* preconditioner setup time */
+    double solve_ms;    /* iteration time */
+} pcm_solve_info;
+
+/* Create a context bound to the current HIP device and `hip_stream` (a hipStream_t;
+ * NULL = default stream).  `params` may be NULL for defaults.  No GPU call is made
+ * here; device resources are created on first use.  Errors: PCM_E_ARG (null out,
+ * non-finite or non-positive eps/zeta0, negative thresholds), PCM_E_ALLOC. */
+pcm_status pcm_create(const pcm_params *params, void *hip_stream, pcm_ctx **out);
+void pcm_destroy(pcm_ctx *ctx);
+const char *pcm_last_error(const pcm_ctx *ctx);
+
+/* Build the ISWIG surface and the screened pair lists (Sec. 2, Eqs. 3, 7, 9; Sec. 3;
+ * Sec. 4a, Eq. 15).  HOST inputs: xyz[n_atoms*3], Z[n_atoms], radius[n_atoms] (cavity
+ * radius in bohr, e.g. 1.2 x Bondi), sph_dirs[n_sph*3] unit vectors and sph_w[n_sph]
+ * weights (sum 4 pi) of the unit-sphere rule, basis.  Point k = (atom I, sphere point j)
+ * sits at R_I + radius_I u_j with exponent zeta0/(radius_I sqrt(w_j)); points with
+ * S_k < switch_thresh are dropped; the kept points are ordered by atom, then j.  The
+ * kept set and the Eq. 15 pair list are fixed for the life of the molecule (later
+ * geometry updates do not re-prune), so energies stay smooth for differentiation.
+ * Outputs: *out (owned by the library), *M_out = number of kept points.
+ * Errors: PCM_E_ARG, PCM_E_UNSUPPORTED (l > 2 or nprim > 8), PCM_E_HIP, PCM_E_ALLOC. */
+pcm_status pcm_build_surface(pcm_ctx *ctx, int n_atoms, const double *xyz, const double *Z, const double *radius,
+                             int n_sph, const double *sph_dirs, const double *sph_w, const pcm_basis *basis,
+                             pcm_mol **out, int *M_out);
+
+/* Move nuclei (HOST xyz[n_atoms*3]) and, optionally, place surface points explicitly
+ * (HOST r_surf[M*3], NULL = points follow their atoms).  Recomputes S_k, A_kk and the
+ * pair geometry with the kept-point set and pair lists unchanged. */
+pcm_status pcm_update_geometry(pcm_ctx *ctx, pcm_mol *mol, const double *xyz, const double *r_surf);
+
+/* c_k = sum_{mu nu} P_{mu nu} L^k_{mu nu}, L^k = -(mu|erf(zeta_k|r-r_k|)/|r-r_k||nu)
+ * (Sec. 2, Eqs. 5-6, 12).  Primitive pairs are screened with |P| times the Eq. 15 bound
+ * (Eq. 18).  DEVICE: P[nbf*nbf] (symmetric), c[M] (written).  bz (DEVICE, may be NULL):
+ * written with (B z)_k = sum_J Z_J erf(zeta_k |r_k-R_J|)/|r_k-R_J| (Eq. 4). */
+pcm_status pcm_esp(pcm_ctx *ctx, pcm_mol *mol, const double *P, double *c, double *bz);
+
+/* F_{mu nu} += sum_k q_k L^k_{mu nu} (Sec. 2, Eq. 10; Sec. 4a, Eqs. 16-17), over the Eq. 15
+ * list; the full symmetric matrix is accumulated.  DEVICE: q[M], F[nbf*nbf] (in/out). */
+pcm_status pcm_fock(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F);
+
+/* Solve A q = -f v (Sec. 2, Eq. 1, with v = B z + c) by preconditioned CG (Sec. 4b).
+ * DEVICE: v[M], q[M] (in: initial guess when opts->warm_start; out: solution).
+ * HOST: opts (NULL = defaults), info (may be NULL).  Returns PCM_E_NOCONV when max_iter
+ * is reached (q and info hold the last iterate), PCM_E_NOTPD when an RBJ block is not
+ * positive definite. */
+pcm_status pcm_solve(pcm_ctx *ctx, pcm_mol *mol, const double *v, const pcm_solve_opts *opts, double *q,
+                     pcm_solve_info *info);
+
+/* Energy of Eq. 13: (Bz)^T q + c^T q + 1/(2f) q^T A q, in FP64.  DEVICE: bz[M], c[M], q[M].
+ * HOST: *E. */
+pcm_status pcm_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double *c, const double *q, double *E);
+
+/* Gradient of the Eq. 13 energy at fixed density (Sec. 2, Eq. 14; Sec. 4c, Eq. 22) for a
+ * solved q.  Primitive pairs are screened as in pcm_esp (Eq. 18).  DEVICE: P[nbf*nbf],
+ * q[M]; outputs g_nuc[n_atoms*3] (derivative with respect to nuclear positions with the
+ * surface points held fixed: basis centres, B, and the switching functions inside A_kk)
+ * and g_surf[M*3] (derivative with respect to each surface point).  Points move with
+ * their atom, so the total nuclear gradient is g_nuc[I] + sum_{k on I} g_surf[k]. */
+pcm_status pcm_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc, double *g_surf);
+
+/* Dynamic CG threshold (Sec. 4b-i, Eq. 21): the delta whose predicted energy error
+ * 0.01 delta^1.07 equals 1e-3 times the previous DIIS error, clamped to [1e-10, 1];
+ * 1.0 when diis_err_prev < 0 (first SCF step).  Pure host function. */
+double pcm_dynamic_threshold(double diis_err_prev);
+
+/* Randomized block-Jacobi partition (Sec. 4b-ii) of M points, on the host: a SplitMix64
+ * stream from `seed` picks a random pivot among the unassigned points (kept in ascending
+ * order; index floor(u n_left), u = (x >> 11) 2^-53); the block is the pivot plus the l-1
+ * unassigned points with the largest |A_kl| (ties: smaller index first); members are
+ * stored ascending; repeated until every point is assigned.  HOST: r[M*3], zeta[M];
+ * outputs perm[M] and blk_off[n_blocks+1] (capacity M+1); returns n_blocks, or -1 on a
+ * bad argument. */
+int pcm_rbj_partition(int M, const double *r, const double *zeta, int l, unsigned long long seed, int *perm,
+                      int *blk_off);
+
+/* Copy the surface out.  DEVICE outputs (any may be NULL): r[M*3], zeta[M], S[M],
+ * Akk[M], owner[M] (int32 atom index), sph[M] (int32 sphere-point index). */
+pcm_status pcm_surface_get(pcm_ctx *ctx, const pcm_mol *mol, double *r, double *zeta, double *S, double *Akk,
+                           int *owner, int *sph);
+
+/* Sizes.  HOST outputs (any may be NULL): M, nbf, n_atoms; pairs_fock[6] and
+ * pairs_esp[6] = surviving primitive pairs per class (ss, sp, sd, pp, pd, dd) of the
+ * Eq. 15 list and of the last Eq. 18 list built by pcm_esp / pcm_grad; sp_fock[6] and
+ * sp_esp[6] = surviving shell pairs per class. */
+pcm_status pcm_mol_sizes(const pcm_mol *mol, int *M, int *nbf, int *n_atoms, long long *pairs_fock,
+                         long long *pairs_esp, long long *sp_fock, long long *sp_esp);
+
+/* Copy a screened primitive-pair list out (HOST arrays of capacity sum(pairs_*)):
+ * list 0 = Eq. 15 (Fock) list, 1 = last Eq. 18 list; entries in the order class, shell
+ * pair (a, b) with l_a <= l_b (a <= b for equal l), primitive i of a, j of b. */
+pcm_status pcm_pair_list(pcm_ctx *ctx, const pcm_mol *mol, int which, int *cls, int *a, int *b, int *i, int *j);
+
+void pcm_mol_destroy(pcm_mol *mol);
+
+/* Per-kernel timing.  pcm_profile_enable(ctx, 1) clears previous records and makes every
+ * heavy launch (integral, matvec, gradient and preconditioner kernels) record a pair of HIP
+ * events on the context's stream; pcm_profile_collect synchronises the stream, aggregates
+ * the records by kernel name and returns the number of names (-1 on error);
+ * pcm_profile_entry(i) reports name (HOST buffer of name_cap bytes), total milliseconds,
+ * number of launches and work units (pair x point evaluations for integral kernels, matrix
+ * elements for matvec and preconditioner kernels).  Profiling adds two event records per
+ * launch and is off by default. */
+pcm_status pcm_profile_enable(pcm_ctx *ctx, int on);
+int pcm_profile_collect(pcm_ctx *ctx);
+pcm_status pcm_profile_entry(const pcm_ctx *ctx, int i, char *name, int name_cap, double *ms, long long *launches,
+                             double *work);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCM_H */

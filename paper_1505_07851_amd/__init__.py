@@ -1,0 +1,12 @@
+"""MI355X (gfx950) C-PCM / ISWIG solvation path of arXiv:1505.07851.
+
+Every computation runs in libpcm.so (hand-written HIP behind the C ABI of include/pcm.h);
+this package only marshals arguments.  Importing it without the built library fails.
+"""
+from ._lib import lib as _load_lib
+
+_load_lib()
+
+from .api import Context, Molecule, PCMError, dynamic_threshold, rbj_partition  # noqa: E402
+
+__all__ = ["Context", "Molecule", "PCMError", "dynamic_threshold", "rbj_partition"]

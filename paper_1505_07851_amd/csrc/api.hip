@@ -1,0 +1,514 @@
+// C ABI of the gfx950 C-PCM library (declared in include/pcm.h).  Argument validation runs
+// on the host before any HIP call; every failure is reported as a pcm_status with a message
+// kept in the context.
+#include "pcm_internal.h"
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+namespace {
+
+bool is_fin(double x) { return std::isfinite(x); }
+
+pcm_status fail(pcm_ctx *ctx, pcm_status st, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+template <typename F> pcm_status guarded(pcm_ctx *ctx, F &&f) {
+    try {
+        pcm_status st = f();
+        if (st == PCM_OK && ctx) ctx->err.clear();
+        return st;
+    } catch (const PcmError &e) {
+        return fail(ctx, e.st, e.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, PCM_E_ALLOC, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, PCM_E_HIP, "unexpected failure");
+    }
+}
+
+template <typename T> void upload(pcm_ctx *ctx, DevBuf<T> &d, const T *h, size_t n) {
+    d.ensure(n ? n : 1);
+    if (n) HIP_OK(hipMemcpyAsync(d.p, h, n * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+}
+
+void release_list(PairList &pl) {
+    pl.spo.release(); pl.cnt.release(); pl.mask.release();
+    pl.ent_sp.release(); pl.ent_ij.release(); pl.rec.release();
+}
+
+void release_mol(pcm_mol *m) {
+    DevBuf<double> *dbl[] = {&m->xyz, &m->Z, &m->rad, &m->dirs, &m->w, &m->pexp, &m->pcoef, &m->cn, &m->px, &m->py,
+                             &m->pz, &m->zeta, &m->S, &m->Akk, &m->pt64, &m->lim64, &m->part, &m->part2, &m->vbuf,
+                             &m->fprim, &m->gpair, &m->gsp, &m->sv, &m->hist, &m->rbj_inv};
+    for (auto *b : dbl) b->release();
+    DevBuf<int> *ints[] = {&m->sl, &m->snp, &m->soff, &m->satom, &m->bfo, &m->cnoff, &m->keep, &m->spa, &m->spb,
+                           &m->atom_sp_off_a, &m->atom_sp_a, &m->atom_sp_off_b, &m->atom_sp_b, &m->scan_tmp,
+                           &m->rbj_perm, &m->rbj_off, &m->rbj_inv_off};
+    for (auto *b : ints) b->release();
+    m->pt32.release();
+    release_list(m->fock);
+    release_list(m->esp);
+}
+
+// candidate shell pairs, classes concatenated; (a, b) with l_a <= l_b (a <= b for equal l)
+void build_candidates(pcm_mol *m) {
+    std::vector<int> by_l[3];
+    for (int s = 0; s < m->ns; ++s) by_l[m->h_sl[s]].push_back(s);
+    m->h_spa.clear();
+    m->h_spb.clear();
+    for (int c = 0; c < NCLS; ++c) {
+        m->sp_cls_off[c] = (long long)m->h_spa.size();
+        const auto &A = by_l[CLS_LA[c]], &B = by_l[CLS_LB[c]];
+        for (int a : A)
+            for (int b : B) {
+                if (CLS_LA[c] == CLS_LB[c] && b < a) continue;
+                m->h_spa.push_back(a);
+                m->h_spb.push_back(b);
+            }
+    }
+    m->sp_cls_off[NCLS] = (long long)m->h_spa.size();
+}
+
+void build_atom_lists(pcm_ctx *ctx, pcm_mol *m) {
+    long long nsp = m->sp_cls_off[NCLS];
+    std::vector<int> ca(m->N + 1, 0), cb(m->N + 1, 0);
+    for (long long s = 0; s < nsp; ++s) {
+        ++ca[m->h_satom[m->h_spa[s]] + 1];
+        ++cb[m->h_satom[m->h_spb[s]] + 1];
+    }
+    for (int i = 0; i < m->N; ++i) {
+        ca[i + 1] += ca[i];
+        cb[i + 1] += cb[i];
+    }
+    std::vector<int> la(nsp), lb(nsp), fa(ca.begin(), ca.end() - 1), fb(cb.begin(), cb.end() - 1);
+    for (long long s = 0; s < nsp; ++s) {
+        la[fa[m->h_satom[m->h_spa[s]]]++] = (int)s;
+        lb[fb[m->h_satom[m->h_spb[s]]]++] = (int)s;
+    }
+    upload(ctx, m->atom_sp_off_a, ca.data(), ca.size());
+    upload(ctx, m->atom_sp_off_b, cb.data(), cb.size());
+    upload(ctx, m->atom_sp_a, la.data(), la.size());
+    upload(ctx, m->atom_sp_b, lb.data(), lb.size());
+}
+
+pcm_status check_basis(pcm_ctx *ctx, int n_atoms, const pcm_basis *b, int *nprim_total) {
+    if (!b) return fail(ctx, PCM_E_ARG, "basis is NULL");
+    if (b->n_shells < 0) return fail(ctx, PCM_E_ARG, "n_shells < 0");
+    *nprim_total = 0;
+    if (b->n_shells == 0) return PCM_OK;
+    if (!b->shell_atom || !b->shell_l || !b->shell_nprim || !b->shell_off || !b->prim_exp || !b->prim_coef)
+        return fail(ctx, PCM_E_ARG, "basis array is NULL");
+    long long np = 0;
+    for (int s = 0; s < b->n_shells; ++s) {
+        int l = b->shell_l[s], n = b->shell_nprim[s];
+        if (l < 0) return fail(ctx, PCM_E_ARG, "negative angular momentum in shell " + std::to_string(s));
+        if (l > 2) return fail(ctx, PCM_E_UNSUPPORTED, "angular momentum above d in shell " + std::to_string(s));
+        if (n < 1) return fail(ctx, PCM_E_ARG, "shell " + std::to_string(s) + " has no primitives");
+        if (n > 8) return fail(ctx, PCM_E_UNSUPPORTED, "more than 8 primitives in shell " + std::to_string(s));
+        if (b->shell_atom[s] < 0 || b->shell_atom[s] >= n_atoms)
+            return fail(ctx, PCM_E_ARG, "shell_atom out of range in shell " + std::to_string(s));
+        if (b->shell_off[s] < 0) return fail(ctx, PCM_E_ARG, "negative shell_off");
+        np = std::max<long long>(np, (long long)b->shell_off[s] + n);
+    }
+    if (np > (1LL << 30)) return fail(ctx, PCM_E_ARG, "too many primitives");
+    for (int s = 0; s < b->n_shells; ++s)
+        for (int i = 0; i < b->shell_nprim[s]; ++i) {
+            double e = b->prim_exp[b->shell_off[s] + i], c = b->prim_coef[b->shell_off[s] + i];
+            if (!is_fin(e) || !(e > 0.0)) return fail(ctx, PCM_E_ARG, "non-positive or non-finite exponent");
+            if (!is_fin(c)) return fail(ctx, PCM_E_ARG, "non-finite contraction coefficient");
+        }
+    *nprim_total = (int)np;
+    return PCM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pcm_default_params(pcm_params *p) {
+    if (!p) return;
+    p->eps = 78.39;
+    p->k_factor = 0.0;
+    p->zeta0 = 4.9;
+    p->switch_thresh = 1e-8;
+    p->schwarz_thresh = 1e-12;
+    p->diag_const = std::sqrt(2.0 / M_PI);
+    p->precision = PCM_FP64;
+}
+
+void pcm_default_solve_opts(pcm_solve_opts *o) {
+    if (!o) return;
+    o->precond = PCM_PRECOND_JACOBI;
+    o->block = 100;
+    o->seed = 0;
+    o->tol = 1e-6;
+    o->max_iter = 10000;
+    o->warm_start = 0;
+    o->precision = PCM_FP64;
+    o->inner_rtol = 1e-4;
+}
+
+pcm_status pcm_create(const pcm_params *params, void *hip_stream, pcm_ctx **out) {
+    if (!out) return PCM_E_ARG;
+    *out = nullptr;
+    pcm_params p;
+    pcm_default_params(&p);
+    if (params) p = *params;
+    if (!is_fin(p.eps) || !(p.eps > 1.0) || !is_fin(p.k_factor) || p.k_factor < 0.0 || !is_fin(p.zeta0) ||
+        !(p.zeta0 > 0.0) || !is_fin(p.switch_thresh) || p.switch_thresh < 0.0 || !is_fin(p.schwarz_thresh) ||
+        p.schwarz_thresh < 0.0 || !is_fin(p.diag_const) || !(p.diag_const > 0.0) ||
+        (p.precision != PCM_FP64 && p.precision != PCM_MIXED))
+        return PCM_E_ARG;
+    pcm_ctx *c = new (std::nothrow) pcm_ctx();
+    if (!c) return PCM_E_ALLOC;
+    c->prm = p;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return PCM_OK;
+}
+
+void pcm_destroy(pcm_ctx *ctx) {
+    if (!ctx) return;
+    ctx->boys64.release();
+    ctx->boys32.release();
+    ctx->scal.release();
+    ctx->iscal.release();
+    delete ctx;
+}
+
+const char *pcm_last_error(const pcm_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+pcm_status pcm_build_surface(pcm_ctx *ctx, int n_atoms, const double *xyz, const double *Z, const double *radius,
+                             int n_sph, const double *sph_dirs, const double *sph_w, const pcm_basis *basis,
+                             pcm_mol **out, int *M_out) {
+    if (!ctx) return PCM_E_ARG;
+    if (!xyz || !Z || !radius || !sph_dirs || !sph_w || !out || !M_out) return fail(ctx, PCM_E_ARG, "NULL argument");
+    *out = nullptr;
+    *M_out = 0;
+    if (n_atoms < 1 || n_sph < 1) return fail(ctx, PCM_E_ARG, "n_atoms and n_sph must be positive");
+    if ((long long)n_atoms * n_sph > (1LL << 30)) return fail(ctx, PCM_E_ARG, "too many raw surface points");
+    for (int i = 0; i < 3 * n_atoms; ++i)
+        if (!is_fin(xyz[i])) return fail(ctx, PCM_E_ARG, "non-finite coordinate");
+    for (int i = 0; i < n_atoms; ++i) {
+        if (!is_fin(Z[i]) || Z[i] < 0.0) return fail(ctx, PCM_E_ARG, "nuclear charge must be finite and >= 0");
+        if (!is_fin(radius[i]) || !(radius[i] > 0.0)) return fail(ctx, PCM_E_ARG, "radius must be finite and > 0");
+    }
+    for (int j = 0; j < n_sph; ++j) {
+        if (!is_fin(sph_dirs[3 * j]) || !is_fin(sph_dirs[3 * j + 1]) || !is_fin(sph_dirs[3 * j + 2]))
+            return fail(ctx, PCM_E_ARG, "non-finite sphere direction");
+        if (!is_fin(sph_w[j]) || !(sph_w[j] > 0.0)) return fail(ctx, PCM_E_ARG, "sphere weight must be > 0");
+    }
+    int np = 0;
+    pcm_status st = check_basis(ctx, n_atoms, basis, &np);
+    if (st != PCM_OK) return st;
+    pcm_mol *m = new (std::nothrow) pcm_mol();
+    if (!m) return fail(ctx, PCM_E_ALLOC, "host allocation failed");
+    st = guarded(ctx, [&]() -> pcm_status {
+        ctx_ensure_device(ctx);
+        m->N = n_atoms;
+        m->nsph = n_sph;
+        m->h_xyz.assign(xyz, xyz + 3 * n_atoms);
+        m->h_Z.assign(Z, Z + n_atoms);
+        m->h_rad.assign(radius, radius + n_atoms);
+        m->h_dirs.assign(sph_dirs, sph_dirs + 3 * n_sph);
+        m->h_w.assign(sph_w, sph_w + n_sph);
+        m->ns = basis->n_shells;
+        m->nprim = np;
+        m->h_sl.assign(basis->shell_l, basis->shell_l + m->ns);
+        m->h_snp.assign(basis->shell_nprim, basis->shell_nprim + m->ns);
+        m->h_soff.assign(basis->shell_off, basis->shell_off + m->ns);
+        m->h_satom.assign(basis->shell_atom, basis->shell_atom + m->ns);
+        m->h_pexp.assign(basis->prim_exp, basis->prim_exp + np);
+        m->h_pcoef.assign(basis->prim_coef, basis->prim_coef + np);
+        m->h_bf.resize(m->ns);
+        m->h_cnoff.resize(m->ns);
+        int bf = 0, cno = 0;
+        for (int s = 0; s < m->ns; ++s) {
+            m->h_bf[s] = bf;
+            m->h_cnoff[s] = cno;
+            bf += ncart(m->h_sl[s]);
+            cno += ncart(m->h_sl[s]) * m->h_snp[s];
+        }
+        m->nbf = bf;
+        upload(ctx, m->xyz, m->h_xyz.data(), m->h_xyz.size());
+        upload(ctx, m->Z, m->h_Z.data(), m->h_Z.size());
+        upload(ctx, m->rad, m->h_rad.data(), m->h_rad.size());
+        upload(ctx, m->dirs, m->h_dirs.data(), m->h_dirs.size());
+        upload(ctx, m->w, m->h_w.data(), m->h_w.size());
+        upload(ctx, m->sl, m->h_sl.data(), m->h_sl.size());
+        upload(ctx, m->snp, m->h_snp.data(), m->h_snp.size());
+        upload(ctx, m->soff, m->h_soff.data(), m->h_soff.size());
+        upload(ctx, m->satom, m->h_satom.data(), m->h_satom.size());
+        upload(ctx, m->bfo, m->h_bf.data(), m->h_bf.size());
+        upload(ctx, m->cnoff, m->h_cnoff.data(), m->h_cnoff.size());
+        upload(ctx, m->pexp, m->h_pexp.data(), m->h_pexp.size());
+        upload(ctx, m->pcoef, m->h_pcoef.data(), m->h_pcoef.size());
+        m->cn.ensure(cno ? cno : 1);
+        if (m->ns) basis_normalise(ctx, m);
+        surface_build(ctx, m, true);
+        surface_points(ctx, m, nullptr);
+        build_candidates(m);
+        upload(ctx, m->spa, m->h_spa.data(), m->h_spa.size());
+        upload(ctx, m->spb, m->h_spb.data(), m->h_spb.size());
+        build_atom_lists(ctx, m);
+        pairs_build(ctx, m, m->fock, nullptr, 0);
+        pairs_prepare_geometry(ctx, m, m->fock, ctx->prm.precision);
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        return PCM_OK;
+    });
+    if (st != PCM_OK) {
+        release_mol(m);
+        delete m;
+        return st;
+    }
+    *out = m;
+    *M_out = m->M;
+    return PCM_OK;
+}
+
+pcm_status pcm_update_geometry(pcm_ctx *ctx, pcm_mol *mol, const double *xyz, const double *r_surf) {
+    if (!ctx) return PCM_E_ARG;
+    if (!mol || !xyz) return fail(ctx, PCM_E_ARG, "NULL argument");
+    for (int i = 0; i < 3 * mol->N; ++i)
+        if (!is_fin(xyz[i])) return fail(ctx, PCM_E_ARG, "non-finite coordinate");
+    if (r_surf)
+        for (long long i = 0; i < 3LL * mol->M; ++i)
+            if (!is_fin(r_surf[i])) return fail(ctx, PCM_E_ARG, "non-finite surface coordinate");
+    return guarded(ctx, [&]() -> pcm_status {
+        ctx_ensure_device(ctx);
+        mol->h_xyz.assign(xyz, xyz + 3 * mol->N);
+        upload(ctx, mol->xyz, mol->h_xyz.data(), mol->h_xyz.size());
+        DevBuf<double> rs;
+        if (r_surf) upload(ctx, rs, r_surf, 3 * (size_t)mol->M);
+        surface_points(ctx, mol, r_surf ? rs.p : nullptr);
+        pairs_prepare_geometry(ctx, mol, mol->fock, ctx->prm.precision);
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        rs.release();
+        mol->esp_valid = false;
+        mol->rbj_valid = false;
+        return PCM_OK;
+    });
+}
+
+static pcm_status density_list(pcm_ctx *ctx, pcm_mol *mol, const double *P) {
+    pairs_build(ctx, mol, mol->esp, P, 1);
+    pairs_prepare_density(ctx, mol, mol->esp, P, ctx->prm.precision);
+    mol->esp_valid = true;
+    return PCM_OK;
+}
+
+pcm_status pcm_esp(pcm_ctx *ctx, pcm_mol *mol, const double *P, double *c, double *bz) {
+    if (!ctx) return PCM_E_ARG;
+    if (!mol || !P || !c) return fail(ctx, PCM_E_ARG, "NULL argument");
+    return guarded(ctx, [&]() -> pcm_status {
+        ctx_ensure_device(ctx);
+        density_list(ctx, mol, P);
+        run_esp(ctx, mol, c, ctx->prm.precision);
+        if (bz) run_bz(ctx, mol, bz);
+        return PCM_OK;
+    });
+}
+
+pcm_status pcm_fock(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F) {
+    if (!ctx) return PCM_E_ARG;
+    if (!mol || !q || !F) return fail(ctx, PCM_E_ARG, "NULL argument");
+    return guarded(ctx, [&]() -> pcm_status {
+        ctx_ensure_device(ctx);
+        run_fock(ctx, mol, q, F, ctx->prm.precision);
+        return PCM_OK;
+    });
+}
+
+pcm_status pcm_solve(pcm_ctx *ctx, pcm_mol *mol, const double *v, const pcm_solve_opts *opts, double *q,
+                     pcm_solve_info *info) {
+    if (!ctx) return PCM_E_ARG;
+    if (!mol || !v || !q) return fail(ctx, PCM_E_ARG, "NULL argument");
+    pcm_solve_opts o;
+    pcm_default_solve_opts(&o);
+    if (opts) o = *opts;
+    if (o.precond < PCM_PRECOND_NONE || o.precond > PCM_PRECOND_RBJ) return fail(ctx, PCM_E_ARG, "bad precond");
+    if (o.precond == PCM_PRECOND_RBJ && (o.block < 1 || o.block > 1024))
+        return fail(ctx, PCM_E_ARG, "RBJ block size must be in [1, 1024]");
+    if (!is_fin(o.tol) || !(o.tol > 0.0)) return fail(ctx, PCM_E_ARG, "tol must be > 0");
+    if (o.max_iter < 1) return fail(ctx, PCM_E_ARG, "max_iter must be >= 1");
+    if (o.precision != PCM_FP64 && o.precision != PCM_MIXED) return fail(ctx, PCM_E_ARG, "bad precision");
+    if (!is_fin(o.inner_rtol) || o.inner_rtol < 0.0 || o.inner_rtol >= 1.0)
+        return fail(ctx, PCM_E_ARG, "inner_rtol must be in [0, 1)");
+    return guarded(ctx, [&]() -> pcm_status {
+        ctx_ensure_device(ctx);
+        pcm_status st = run_solve(ctx, mol, v, o, q, info);
+        if (st == PCM_E_NOCONV) ctx->err = "max_iter reached before the residual threshold";
+        return st;
+    });
+}
+
+pcm_status pcm_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double *c, const double *q, double *E) {
+    if (!ctx) return PCM_E_ARG;
+    if (!mol || !bz || !c || !q || !E) return fail(ctx, PCM_E_ARG, "NULL argument");
+    return guarded(ctx, [&]() -> pcm_status {
+        ctx_ensure_device(ctx);
+        *E = run_energy(ctx, mol, bz, c, q);
+        return PCM_OK;
+    });
+}
+
+pcm_status pcm_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc, double *g_surf) {
+    if (!ctx) return PCM_E_ARG;
+    if (!mol || !P || !q || !g_nuc || !g_surf) return fail(ctx, PCM_E_ARG, "NULL argument");
+    return guarded(ctx, [&]() -> pcm_status {
+        ctx_ensure_device(ctx);
+        density_list(ctx, mol, P);
+        run_grad(ctx, mol, P, q, g_nuc, g_surf, ctx->prm.precision);
+        return PCM_OK;
+    });
+}
+
+double pcm_dynamic_threshold(double e) {
+    if (!(e >= 0.0)) return 1.0;  // first SCF step (or NaN): delta = 1
+    if (e == 0.0) return 1e-10;
+    double d = std::pow(0.1 * e, 1.0 / 1.07);
+    return std::min(1.0, std::max(1e-10, d));
+}
+
+int pcm_rbj_partition(int M, const double *r, const double *zeta, int l, unsigned long long seed, int *perm,
+                      int *blk_off) {
+    try {
+        return host_rbj_partition(M, r, zeta, l, seed, perm, blk_off);
+    } catch (...) {
+        return -1;
+    }
+}
+
+__global__ void k_owner_sph(const int *__restrict__ keep, int M, int nsph, int *__restrict__ owner,
+                            int *__restrict__ sph) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    if (owner) owner[k] = keep[k] / nsph;
+    if (sph) sph[k] = keep[k] % nsph;
+}
+
+pcm_status pcm_surface_get(pcm_ctx *ctx, const pcm_mol *mol, double *r, double *zeta, double *S, double *Akk,
+                           int *owner, int *sph) {
+    if (!ctx) return PCM_E_ARG;
+    if (!mol) return fail(ctx, PCM_E_ARG, "NULL molecule");
+    return guarded(ctx, [&]() -> pcm_status {
+        ctx_ensure_device(ctx);
+        const size_t M = mol->M;
+        if (r)
+            HIP_OK(hipMemcpy2DAsync(r, 3 * sizeof(double), mol->pt64.p, 4 * sizeof(double), 3 * sizeof(double), M,
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+        if (zeta) HIP_OK(hipMemcpyAsync(zeta, mol->zeta.p, M * 8, hipMemcpyDeviceToDevice, ctx->stream));
+        if (S) HIP_OK(hipMemcpyAsync(S, mol->S.p, M * 8, hipMemcpyDeviceToDevice, ctx->stream));
+        if (Akk) HIP_OK(hipMemcpyAsync(Akk, mol->Akk.p, M * 8, hipMemcpyDeviceToDevice, ctx->stream));
+        if (owner || sph) {
+            k_owner_sph<<<div_up(M, 256), 256, 0, ctx->stream>>>(mol->keep.p, (int)M, mol->nsph, owner, sph);
+            HIP_LAUNCH_OK();
+        }
+        return PCM_OK;
+    });
+}
+
+pcm_status pcm_mol_sizes(const pcm_mol *mol, int *M, int *nbf, int *n_atoms, long long *pairs_fock,
+                         long long *pairs_esp, long long *sp_fock, long long *sp_esp) {
+    if (!mol) return PCM_E_ARG;
+    if (M) *M = mol->M;
+    if (nbf) *nbf = mol->nbf;
+    if (n_atoms) *n_atoms = mol->N;
+    for (int c = 0; c < NCLS; ++c) {
+        if (pairs_fock) pairs_fock[c] = mol->fock.cls_off[c + 1] - mol->fock.cls_off[c];
+        if (pairs_esp) pairs_esp[c] = mol->esp.cls_off[c + 1] - mol->esp.cls_off[c];
+        if (sp_fock) sp_fock[c] = mol->fock.sp_count[c];
+        if (sp_esp) sp_esp[c] = mol->esp.sp_count[c];
+    }
+    return PCM_OK;
+}
+
+pcm_status pcm_pair_list(pcm_ctx *ctx, const pcm_mol *mol, int which, int *cls, int *a, int *b, int *i, int *j) {
+    if (!ctx) return PCM_E_ARG;
+    if (!mol || !cls || !a || !b || !i || !j || (which != 0 && which != 1))
+        return fail(ctx, PCM_E_ARG, "bad argument");
+    const PairList &pl = which == 0 ? mol->fock : mol->esp;
+    return guarded(ctx, [&]() -> pcm_status {
+        long long n = pl.n;
+        std::vector<int> es(n), ei(n);
+        if (n) {
+            HIP_OK(hipMemcpyAsync(es.data(), pl.ent_sp.p, n * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+            HIP_OK(hipMemcpyAsync(ei.data(), pl.ent_ij.p, n * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+            HIP_OK(hipStreamSynchronize(ctx->stream));
+        }
+        for (long long t = 0; t < n; ++t) {
+            int sp = es[t];
+            int c = 0;
+            while (c + 1 < NCLS && sp >= mol->sp_cls_off[c + 1]) ++c;
+            cls[t] = c;
+            a[t] = mol->h_spa[sp];
+            b[t] = mol->h_spb[sp];
+            i[t] = ei[t] >> 3;
+            j[t] = ei[t] & 7;
+        }
+        return PCM_OK;
+    });
+}
+
+pcm_status pcm_profile_enable(pcm_ctx *ctx, int on) {
+    if (!ctx) return PCM_E_ARG;
+    for (auto &r : ctx->prof_recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    ctx->prof_recs.clear();
+    ctx->prof_agg.clear();
+    ctx->prof = on != 0;
+    return PCM_OK;
+}
+
+int pcm_profile_collect(pcm_ctx *ctx) {
+    if (!ctx) return -1;
+    if (ctx->stream || ctx->dev_ready) {
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess) return -1;
+    }
+    for (auto &r : ctx->prof_recs) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) ms = 0.f;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+        bool found = false;
+        for (auto &g : ctx->prof_agg)
+            if (g.name == r.name) {
+                g.ms += ms;
+                g.launches += 1;
+                g.work += r.work;
+                found = true;
+                break;
+            }
+        if (!found) ctx->prof_agg.push_back(ProfAgg{r.name, (double)ms, 1, r.work});
+    }
+    ctx->prof_recs.clear();
+    return (int)ctx->prof_agg.size();
+}
+
+pcm_status pcm_profile_entry(const pcm_ctx *ctx, int i, char *name, int name_cap, double *ms, long long *launches,
+                             double *work) {
+    if (!ctx || i < 0 || i >= (int)ctx->prof_agg.size()) return PCM_E_ARG;
+    const ProfAgg &g = ctx->prof_agg[i];
+    if (name && name_cap > 0) {
+        std::strncpy(name, g.name.c_str(), name_cap - 1);
+        name[name_cap - 1] = 0;
+    }
+    if (ms) *ms = g.ms;
+    if (launches) *launches = g.launches;
+    if (work) *work = g.work;
+    return PCM_OK;
+}
+
+void pcm_mol_destroy(pcm_mol *mol) {
+    if (!mol) return;
+    release_mol(mol);
+    delete mol;
+}
+
+}  // extern "C"

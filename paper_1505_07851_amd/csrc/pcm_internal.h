@@ -1,0 +1,348 @@
+// Internal declarations of the gfx950 C-PCM library: handle layouts, launch helpers
+// and the device math shared by the integral, solver and gradient kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pcm.h"
+#include "hermite_gen.h"
+
+// ----------------------------------------------------------------------------------------
+// error plumbing
+// ----------------------------------------------------------------------------------------
+struct PcmError {
+    pcm_status st;
+    std::string msg;
+};
+
+#define HIP_OK(expr)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            throw PcmError{PCM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)};      \
+    } while (0)
+
+#define HIP_LAUNCH_OK()                                                                        \
+    do {                                                                                       \
+        hipError_t e_ = hipGetLastError();                                                     \
+        if (e_ != hipSuccess)                                                                  \
+            throw PcmError{PCM_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e_)}; \
+    } while (0)
+
+// ----------------------------------------------------------------------------------------
+// classes of shell pairs (Sec. 4a: ss, sp, sd, pp, pd, dd)
+// ----------------------------------------------------------------------------------------
+constexpr int NCLS = 6;
+constexpr int CLS_LA[NCLS] = {0, 0, 0, 1, 1, 2};
+constexpr int CLS_LB[NCLS] = {0, 1, 2, 1, 2, 2};
+__host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+__host__ __device__ constexpr int ntuv(int L) { return (L + 1) * (L + 2) * (L + 3) / 6; }
+// position of (t,u,v) in the order: N = t+u+v ascending, t descending, u descending
+__host__ __device__ constexpr int tuv_idx(int t, int u, int v) {
+    int N = t + u + v;
+    return N * (N + 1) * (N + 2) / 6 + (N - t) * (N - t + 1) / 2 + (N - t - u);
+}
+// Cartesian component c of shell l in lexicographic order (x, y, z; xx, xy, xz, yy, yz, zz)
+__host__ __device__ inline void cart_comp(int l, int c, int &ax, int &ay, int &az) {
+    int n = 0;
+    for (int x = l; x >= 0; --x)
+        for (int y = l - x; y >= 0; --y) {
+            if (n == c) { ax = x; ay = y; az = l - x - y; return; }
+            ++n;
+        }
+    ax = ay = az = 0;
+}
+
+// ----------------------------------------------------------------------------------------
+// Boys function tables.  F_m(T_i) at T_i = i/8; Taylor expansion around the nearest node:
+// F_m(T) = sum_k F_{m+k}(T_i) (T_i - T)^k / k!.  FP64: order 8 on [0, 40); FP32: order 4 on
+// [0, 30).  Above the range the asymptotic form is exact to the working precision (see
+// aux_Rn).
+// ----------------------------------------------------------------------------------------
+template <typename T> struct BoysCfg;
+template <> struct BoysCfg<double> {
+    static constexpr int ORD = 8, MT = 14, NROW = 321;
+    static constexpr double TMAX = 40.0;
+};
+template <> struct BoysCfg<float> {
+    static constexpr int ORD = 4, MT = 10, NROW = 241;
+    static constexpr float TMAX = 30.0f;
+};
+constexpr int LMAX_TOT = 5;  // highest total L handled (d-d gradient)
+
+// ----------------------------------------------------------------------------------------
+// Pair records.  A "header" holds the Gaussian-product data of one primitive pair:
+//   P (double), p, TMAX/p (far-field test), (pi/p)^{3/2} (far prefactor), 2 pi/p (near).
+// The density-contracted Hermite coefficients D_tuv follow for the esp/gradient lists.
+// ----------------------------------------------------------------------------------------
+template <typename T> struct PairHdr {
+    double Px, Py, Pz;
+    T p, limp, pf, pref;
+};
+__host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+template <typename T> __host__ __device__ constexpr size_t rec_stride(int L) {
+    return align16(sizeof(PairHdr<T>) + sizeof(T) * ntuv(L));
+}
+
+// ----------------------------------------------------------------------------------------
+// Auxiliary values R^(n)_000 (n = 0..L) of one (pair, point) evaluation, prefactors included.
+//   near: (2 pi/p) sqrt(u) (-2 a)^n F_n(a r^2),  u = z^2/(z^2+p), a = p u;
+//   far (a r^2 >= TMAX): the smeared charge acts as a point charge and the attenuation
+//   drops out: (pi/p)^{3/2} (-1)^n (2n-1)!! / r^{2n+1}.
+// The far test a r^2 >= TMAX is r^2 >= TMAX/p + TMAX/z^2.
+// ----------------------------------------------------------------------------------------
+__device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
+__device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
+__device__ __forceinline__ float sqrt_t(float x) { return sqrtf(x); }
+
+template <int L, typename T>
+__device__ __forceinline__ void aux_Rn(T r2, T p, T limp, T pf, T pref, T zeta2, T limk,
+                                       const T *__restrict__ tab, T (&Rn)[L + 1]) {
+    using C = BoysCfg<T>;
+    if (r2 >= limp + limk) {
+        T ri = rsqrt_t(r2);
+        T ri2 = ri * ri;
+        Rn[0] = pf * ri;
+#pragma unroll
+        for (int n = 1; n <= L; ++n) Rn[n] = T(-(2 * n - 1)) * ri2 * Rn[n - 1];
+    } else {
+        T s = zeta2 + p;
+        T u = zeta2 / s;
+        T a = p * u;
+        T tb = a * r2;
+        int i = (int)(tb * T(8) + T(0.5));
+        i = i < C::NROW - 1 ? i : C::NROW - 1;
+        T d = T(i) * T(0.125) - tb;
+        T w[C::ORD + 1];
+        w[0] = T(1);
+#pragma unroll
+        for (int k = 1; k <= C::ORD; ++k) w[k] = w[k - 1] * d * (T(1) / T(k));
+        const T *row = tab + i * C::MT;
+        T fac = pref * sqrt_t(u);
+        T m2a = T(-2) * a;
+#pragma unroll
+        for (int n = 0; n <= L; ++n) {
+            T F = T(0);
+#pragma unroll
+            for (int k = C::ORD; k >= 0; --k) F = fma(row[n + k], w[k], F);
+            Rn[n] = fac * F;
+            fac *= m2a;
+        }
+    }
+}
+
+// R_tuv (t+u+v <= L) of one pair against one point; (X, Y, Z) = P - C.
+template <int L, typename T>
+__device__ __forceinline__ void eval_R(double X, double Y, double Z, const PairHdr<T> &h, T zeta2, T limk,
+                                       const T *__restrict__ tab, T (&R)[ntuv(L)]) {
+    T x = T(X), y = T(Y), z = T(Z);
+    T r2 = x * x + y * y + z * z;
+    T Rn[L + 1];
+    aux_Rn<L, T>(r2, h.p, h.limp, h.pf, h.pref, zeta2, limk, tab, Rn);
+    MdR<L>::run(x, y, z, Rn, R);
+}
+
+// Load the Boys table of type T into LDS (tab_g holds BoysCfg<T>::NROW * MT values).
+template <typename T>
+__device__ __forceinline__ void load_boys(T *lds, const T *__restrict__ tab_g) {
+    constexpr int n = BoysCfg<T>::NROW * BoysCfg<T>::MT;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = tab_g[i];
+    __syncthreads();
+}
+
+// ----------------------------------------------------------------------------------------
+// 1-D Hermite expansion coefficients of a Cartesian Gaussian product (without the
+// exponential prefactor): E[i][j][t] for i <= IM, j <= JM,
+//   E^{i+1,j}_t = E^{ij}_{t-1}/(2p) + X_PA E^{ij}_t + (t+1) E^{ij}_{t+1}, and likewise for j.
+// ----------------------------------------------------------------------------------------
+template <int IM, int JM>
+struct Herm1D {
+    double e[IM + 1][JM + 1][IM + JM + 1];
+    __device__ void build(double PA, double PB, double inv2p) {
+        for (int i = 0; i <= IM; ++i)
+            for (int j = 0; j <= JM; ++j)
+                for (int t = 0; t <= IM + JM; ++t) e[i][j][t] = 0.0;
+        e[0][0][0] = 1.0;
+        for (int i = 0; i <= IM; ++i) {
+            if (i > 0)
+                for (int t = 0; t <= i; ++t) {
+                    double v = PA * e[i - 1][0][t];
+                    if (t > 0) v += inv2p * e[i - 1][0][t - 1];
+                    if (t + 1 <= i - 1) v += (t + 1) * e[i - 1][0][t + 1];
+                    e[i][0][t] = v;
+                }
+            for (int j = 1; j <= JM; ++j)
+                for (int t = 0; t <= i + j; ++t) {
+                    double v = PB * e[i][j - 1][t];
+                    if (t > 0) v += inv2p * e[i][j - 1][t - 1];
+                    if (t + 1 <= i + j - 1) v += (t + 1) * e[i][j - 1][t + 1];
+                    e[i][j][t] = v;
+                }
+        }
+    }
+};
+
+// ----------------------------------------------------------------------------------------
+// host-side handles
+// ----------------------------------------------------------------------------------------
+template <typename T> struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;  // capacity in elements
+    void ensure(size_t want) {
+        if (want <= n && p) return;
+        if (p) HIP_OK(hipFree(p));
+        p = nullptr;
+        n = 0;
+        if (want == 0) return;
+        if (hipMalloc(&p, want * sizeof(T)) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            throw PcmError{PCM_E_ALLOC, "device allocation of " + std::to_string(want * sizeof(T)) + " bytes failed"};
+        }
+        n = want;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+// per-kernel timing with HIP events on the context stream (enabled by pcm_profile_enable)
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+    double work;
+};
+struct ProfAgg {
+    std::string name;
+    double ms;
+    long long launches;
+    double work;
+};
+
+struct pcm_ctx {
+    pcm_params prm{};
+    bool prof = false;
+    std::vector<ProfRec> prof_recs;
+    std::vector<ProfAgg> prof_agg;
+    hipStream_t stream = nullptr;
+    int device = -1;
+    bool dev_ready = false;
+    std::string err;
+    DevBuf<double> boys64;
+    DevBuf<float> boys32;
+    DevBuf<double> scal;  // small scalar workspace (reductions, solver scalars)
+    DevBuf<int> iscal;
+};
+
+// one screened primitive-pair list (all classes, concatenated by class)
+struct PairList {
+    long long cls_off[NCLS + 1] = {0};  // prim-pair offsets per class
+    long long sp_count[NCLS] = {0};     // shell pairs with at least one surviving primitive pair
+    long long n = 0;
+    DevBuf<int> spo;        // [n_sp_cand + 1] exclusive prefix of surviving counts per candidate
+    DevBuf<int> cnt;        // [n_sp_cand] surviving count per candidate shell pair
+    DevBuf<unsigned long long> mask;  // [n_sp_cand] surviving (i,j) bit mask
+    DevBuf<int> ent_sp, ent_ij;       // [n] candidate shell pair index, i*8+j
+    DevBuf<unsigned char> rec;        // pair records (type and stride depend on use)
+    size_t rec_off[NCLS + 1] = {0};   // byte offsets of each class in rec
+};
+
+struct pcm_mol {
+    int N = 0, nsph = 0, M = 0, Mraw = 0;
+    int ns = 0, nbf = 0, nprim = 0;
+    // host copies
+    std::vector<double> h_xyz, h_Z, h_rad, h_dirs, h_w;
+    std::vector<int> h_sl, h_snp, h_soff, h_satom, h_bf, h_cnoff;
+    std::vector<double> h_pexp, h_pcoef;
+    std::vector<int> h_keep;  // kept raw indices (atom * nsph + j)
+    // device: atoms and sphere rule
+    DevBuf<double> xyz, Z, rad, dirs, w;
+    // device: basis
+    DevBuf<int> sl, snp, soff, satom, bfo, cnoff;
+    DevBuf<double> pexp, pcoef, cn;
+    // device: surface (SoA, FP64) and packed point records
+    DevBuf<int> keep;  // [M]
+    DevBuf<double> px, py, pz, zeta, S, Akk;
+    DevBuf<double> pt64;  // [M][4]: x, y, z, zeta^2
+    DevBuf<double> lim64; // [M] TMAX64 / zeta^2
+    DevBuf<float> pt32;   // [M][4]: zeta^2, TMAX32/zeta^2, zeta^2/2 (matvec), zeta
+    // candidate shell pairs (classes concatenated)
+    long long sp_cls_off[NCLS + 1] = {0};
+    std::vector<int> h_spa, h_spb;
+    DevBuf<int> spa, spb;
+    // per-atom lists of candidate shell pairs (CSR) for the gradient reduction
+    DevBuf<int> atom_sp_off_a, atom_sp_a, atom_sp_off_b, atom_sp_b;
+    // screened lists
+    PairList fock, esp;
+    bool esp_valid = false;
+    // workspaces
+    DevBuf<double> part;   // partial sums (esp / matvec / gradient)
+    DevBuf<double> part2;
+    DevBuf<double> vbuf;   // V_tuv partials (fock / grad)
+    DevBuf<double> fprim;  // per prim pair Fock blocks
+    DevBuf<double> gpair;  // per prim pair gradient contributions
+    DevBuf<double> gsp;    // per candidate shell pair gradient sums
+    DevBuf<int> scan_tmp;
+    // solver
+    DevBuf<double> sv;     // solver vectors
+    DevBuf<double> hist;   // per-iteration CG scalars
+    DevBuf<double> rbj_inv;
+    DevBuf<int> rbj_perm, rbj_off, rbj_inv_off;
+    std::vector<int> h_rbj_perm, h_rbj_off;
+    int rbj_l = -1;
+    unsigned long long rbj_seed = 0;
+    bool rbj_valid = false;
+    pcm_ctx *owner_ctx = nullptr;
+};
+
+// records one launch (or a short sequence) between construction and destruction
+struct ProfScope {
+    pcm_ctx *c;
+    ProfRec r{};
+    bool on;
+    ProfScope(pcm_ctx *ctx, const std::string &name, double work) : c(ctx), on(ctx->prof) {
+        if (!on) return;
+        r.name = name;
+        r.work = work;
+        if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess ||
+            hipEventRecord(r.a, c->stream) != hipSuccess)
+            on = false;
+    }
+    ~ProfScope() {
+        if (on && hipEventRecord(r.b, c->stream) == hipSuccess) c->prof_recs.push_back(r);
+    }
+};
+
+// ----------------------------------------------------------------------------------------
+// internal entry points implemented in the .hip translation units
+// ----------------------------------------------------------------------------------------
+void ctx_ensure_device(pcm_ctx *ctx);
+void scan_exclusive(pcm_ctx *ctx, pcm_mol *mol, const int *in, int *out, long long n, long long *total);
+void surface_build(pcm_ctx *ctx, pcm_mol *mol, bool prune);
+void basis_normalise(pcm_ctx *ctx, pcm_mol *mol);
+void pairs_build(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P, int kind /*0 fock, 1 esp*/);
+void pairs_prepare_geometry(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, int prec);
+void pairs_prepare_density(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P, int prec);
+void run_bz(pcm_ctx *ctx, pcm_mol *mol, double *bz);
+void run_esp(pcm_ctx *ctx, pcm_mol *mol, double *c, int prec);
+void run_fock(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F, int prec);
+void run_matvec(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int prec);
+pcm_status run_solve(pcm_ctx *ctx, pcm_mol *mol, const double *v, const pcm_solve_opts &o, double *q,
+                     pcm_solve_info *info);
+double run_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double *c, const double *q);
+void run_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc, double *g_surf,
+              int prec);
+void surface_points(pcm_ctx *ctx, pcm_mol *mol, const double *r_explicit_dev);
+double dev_dot(pcm_ctx *ctx, pcm_mol *mol, const double *a, const double *b, long long n);
+int host_rbj_partition(int M, const double *r, const double *zeta, int l, unsigned long long seed, int *perm,
+                       int *blk_off);
+
+inline int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }

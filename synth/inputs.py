@@ -278,19 +278,27 @@ def protein_system(name: str, n_atoms: int, n_sph: int, cfg: int, polarized: boo
                          "pert": 100 * cfg + 5})
 
 
+# Raw unit-sphere rules are sized so that the kept surface has the configured density
+# (~50 points per atom, as in the paper's proteins: 26,025 points for 516 atoms).  The
+# seeded walk is more compact than those structures and buries ~75% of a 110-point rule.
+RAW_SPH_600 = 276    # -> ~30k kept points for 600 atoms
+RAW_SPH_2000 = 540   # -> ~150k kept points for 2,000 atoms
+RAW_SPH_300 = 270    # -> ~15k kept points for 300 atoms
+
+
 def protein_single_solve() -> System:
-    """600 atoms, 6-31G*-shaped basis, 110 raw points per atom."""
-    return protein_system("protein600_631gs", 600, 110, 2)
+    """600 atoms, 6-31G*-shaped basis, ~30k kept surface points."""
+    return protein_system("protein600_631gs", 600, RAW_SPH_600, 2)
 
 
 def linear_solve_stress() -> System:
-    """2,000 atoms, 6-31G*-shaped basis, 190 raw points per atom."""
-    return protein_system("protein2000_631gs", 2000, 190, 3)
+    """2,000 atoms, 6-31G*-shaped basis, ~150k kept surface points."""
+    return protein_system("protein2000_631gs", 2000, RAW_SPH_2000, 3)
 
 
 def gradient_path() -> System:
-    """300 atoms, 6-31G*-shaped basis, 110 raw points per atom."""
-    return protein_system("peptide300_631gs", 300, 110, 4)
+    """300 atoms, 6-31G*-shaped basis, ~15k kept surface points."""
+    return protein_system("peptide300_631gs", 300, RAW_SPH_300, 4)
 
 
 CONFORMER_SPH = (50, 74, 86, 110, 146)
