@@ -42,14 +42,15 @@ void release_list(PairList &pl) {
 
 void release_mol(pcm_mol *m) {
     DevBuf<double> *dbl[] = {&m->xyz, &m->Z, &m->rad, &m->dirs, &m->w, &m->pexp, &m->pcoef, &m->cn, &m->px, &m->py,
-                             &m->pz, &m->zeta, &m->S, &m->Akk, &m->pt64, &m->lim64, &m->part, &m->part2, &m->vbuf,
+                             &m->pz, &m->zeta, &m->S, &m->Akk, &m->qpad, &m->part, &m->part2, &m->vbuf,
                              &m->fprim, &m->gpair, &m->gsp, &m->sv, &m->hist, &m->rbj_inv};
     for (auto *b : dbl) b->release();
     DevBuf<int> *ints[] = {&m->sl, &m->snp, &m->soff, &m->satom, &m->bfo, &m->cnoff, &m->keep, &m->spa, &m->spb,
                            &m->atom_sp_off_a, &m->atom_sp_a, &m->atom_sp_off_b, &m->atom_sp_b, &m->scan_tmp,
                            &m->rbj_perm, &m->rbj_off, &m->rbj_inv_off};
     for (auto *b : ints) b->release();
-    m->pt32.release();
+    m->pti64.release();
+    m->pti32.release();
     release_list(m->fock);
     release_list(m->esp);
 }
@@ -211,6 +212,7 @@ pcm_status pcm_build_surface(pcm_ctx *ctx, int n_atoms, const double *xyz, const
         ctx_ensure_device(ctx);
         m->N = n_atoms;
         m->nsph = n_sph;
+        m->zeta0 = ctx->prm.zeta0;
         m->h_xyz.assign(xyz, xyz + 3 * n_atoms);
         m->h_Z.assign(Z, Z + n_atoms);
         m->h_rad.assign(radius, radius + n_atoms);
@@ -399,7 +401,7 @@ pcm_status pcm_surface_get(pcm_ctx *ctx, const pcm_mol *mol, double *r, double *
         ctx_ensure_device(ctx);
         const size_t M = mol->M;
         if (r)
-            HIP_OK(hipMemcpy2DAsync(r, 3 * sizeof(double), mol->pt64.p, 4 * sizeof(double), 3 * sizeof(double), M,
+            HIP_OK(hipMemcpy2DAsync(r, 3 * sizeof(double), mol->pti64.p, sizeof(PtInt<double>), 3 * sizeof(double), M,
                                     hipMemcpyDeviceToDevice, ctx->stream));
         if (zeta) HIP_OK(hipMemcpyAsync(zeta, mol->zeta.p, M * 8, hipMemcpyDeviceToDevice, ctx->stream));
         if (S) HIP_OK(hipMemcpyAsync(S, mol->S.p, M * 8, hipMemcpyDeviceToDevice, ctx->stream));

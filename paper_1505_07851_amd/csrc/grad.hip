@@ -17,43 +17,43 @@
 // gc: g_surf contribution of the c term, partial over a chunk of pairs (3 rows per chunk)
 // -------------------------------------------------------------------------------------------
 template <int L, typename T>
-__global__ __launch_bounds__(256) void k_grad_pts(const unsigned char *__restrict__ rec, int stride, int n_pairs,
-                                                  int chunk_len, const double *__restrict__ pt64,
-                                                  const double *__restrict__ lim64, const float *__restrict__ pt32,
-                                                  int M, const T *__restrict__ boys_g, double *__restrict__ part,
-                                                  int row0) {
+__global__ __launch_bounds__(256) void k_grad_pts(const unsigned char *__restrict__ rec, int stride, int n_pad,
+                                                  int chunk_len, const PtInt<T> *__restrict__ pts, int M,
+                                                  const T *__restrict__ boys_g, double *__restrict__ part, int row0) {
+    constexpr int NT = ntuv(L), PB = pair_batch<L + 1>();
     __shared__ T tab[BoysCfg<T>::NROW * BoysCfg<T>::MT];
     load_boys<T>(tab, boys_g);
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int kk = k < M ? k : M - 1;
-    const double cx = pt64[4 * kk], cy = pt64[4 * kk + 1], cz = pt64[4 * kk + 2];
-    T zeta2, limk;
-    if constexpr (sizeof(T) == 8) {
-        zeta2 = (T)pt64[4 * kk + 3];
-        limk = (T)lim64[kk];
-    } else {
-        zeta2 = pt32[4 * kk];
-        limk = pt32[4 * kk + 1];
-    }
+    const PtInt<T> me = pts[k < M ? k : M - 1];
     const int p0 = blockIdx.y * chunk_len;
-    const int p1 = min(n_pairs, p0 + chunk_len);
+    const int p1 = min(n_pad, p0 + chunk_len);
     double gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int ip = p0; ip < p1; ++ip) {
-        const unsigned char *r = rec + (size_t)ip * stride;
-        const PairHdr<T> h = *reinterpret_cast<const PairHdr<T> *>(r);
-        const T *D = reinterpret_cast<const T *>(r + sizeof(PairHdr<T>));
-        T R[ntuv(L + 1)];
-        eval_R<L + 1, T>(h.Px - cx, h.Py - cy, h.Pz - cz, h, zeta2, limk, tab, R);
-        T sx = T(0), sy = T(0), sz = T(0);
+    for (int ip = p0; ip < p1; ip += PB) {
+        PairHdr<T> h[PB];
+        T D[PB][NT];
 #pragma unroll
-        for (int t = 0; t < ntuv(L); ++t) {
-            sx = fma(D[t], R[TuvShift<L>::x(t)], sx);
-            sy = fma(D[t], R[TuvShift<L>::y(t)], sy);
-            sz = fma(D[t], R[TuvShift<L>::z(t)], sz);
+        for (int b = 0; b < PB; ++b) {
+            const unsigned char *r = rec + (size_t)(ip + b) * stride;
+            h[b] = *reinterpret_cast<const PairHdr<T> *>(r);
+            const T *d = reinterpret_cast<const T *>(r + sizeof(PairHdr<T>));
+#pragma unroll
+            for (int t = 0; t < NT; ++t) D[b][t] = d[t];
         }
-        gx += (double)sx;
-        gy += (double)sy;
-        gz += (double)sz;
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            T R[ntuv(L + 1)];
+            eval_R<L + 1, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab, R);
+            T sx = T(0), sy = T(0), sz = T(0);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                sx = fma(D[b][t], R[TuvShift<L>::x(t)], sx);
+                sy = fma(D[b][t], R[TuvShift<L>::y(t)], sy);
+                sz = fma(D[b][t], R[TuvShift<L>::z(t)], sz);
+            }
+            gx += (double)sx;
+            gy += (double)sy;
+            gz += (double)sz;
+        }
     }
     if (k < M) {
         size_t base = (size_t)(row0 + blockIdx.y) * 3 * M;
@@ -68,9 +68,8 @@ __global__ __launch_bounds__(256) void k_grad_pts(const unsigned char *__restric
 // -------------------------------------------------------------------------------------------
 template <int L, typename T>
 __global__ __launch_bounds__(256) void k_grad_v(const unsigned char *__restrict__ rec, int stride, int n_pairs,
-                                                const double *__restrict__ pt64, const double *__restrict__ lim64,
-                                                const float *__restrict__ pt32, const double *__restrict__ q, int M,
-                                                int chunk_len, const T *__restrict__ boys_g,
+                                                const PtInt<T> *__restrict__ pts, const double *__restrict__ q,
+                                                int Mpad, int chunk_len, const T *__restrict__ boys_g,
                                                 double *__restrict__ vout) {
     __shared__ T tab[BoysCfg<T>::NROW * BoysCfg<T>::MT];
     load_boys<T>(tab, boys_g);
@@ -79,24 +78,26 @@ __global__ __launch_bounds__(256) void k_grad_v(const unsigned char *__restrict_
     const int ipp = ip < n_pairs ? ip : n_pairs - 1;
     const PairHdr<T> h = *reinterpret_cast<const PairHdr<T> *>(rec + (size_t)ipp * stride);
     const int k0 = blockIdx.y * chunk_len;
-    const int k1 = min(M, k0 + chunk_len);
+    const int k1 = min(Mpad, k0 + chunk_len);
     double V[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) V[t] = 0.0;
-    for (int k = k0; k < k1; ++k) {
-        T zeta2, limk;
-        if constexpr (sizeof(T) == 8) {
-            zeta2 = (T)pt64[4 * k + 3];
-            limk = (T)lim64[k];
-        } else {
-            zeta2 = pt32[4 * k];
-            limk = pt32[4 * k + 1];
-        }
-        T R[NT];
-        eval_R<L + 1, T>(h.Px - pt64[4 * k], h.Py - pt64[4 * k + 1], h.Pz - pt64[4 * k + 2], h, zeta2, limk, tab, R);
-        const double qk = q[k];
+    for (int k = k0; k < k1; k += PT_BATCH) {
+        PtInt<T> pt[PT_BATCH];
+        double qk[PT_BATCH];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) V[t] = fma(qk, (double)R[t], V[t]);
+        for (int b = 0; b < PT_BATCH; ++b) {
+            pt[b] = pts[k + b];
+            qk[b] = q[k + b];
+        }
+#pragma unroll
+        for (int b = 0; b < PT_BATCH; ++b) {
+            T R[NT];
+            eval_R<L + 1, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta, pt[b].lim,
+                             tab, R);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) V[t] = fma(qk[b], (double)R[t], V[t]);
+        }
     }
     if (ip < n_pairs) {
         double *o = vout + (size_t)blockIdx.y * NT * n_pairs;
@@ -362,6 +363,9 @@ static void grad_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, const doubl
     const int M = mol->M;
     const double inv_f = (ctx->prm.eps + ctx->prm.k_factor) / (ctx->prm.eps - 1.0);
     const T *tab = sizeof(T) == 8 ? (const T *)ctx->boys64.p : (const T *)ctx->boys32.p;
+    const PtInt<T> *pts = reinterpret_cast<const PtInt<T> *>(sizeof(T) == 8 ? mol->pti64.p : mol->pti32.p);
+    const int Mpad = mol->Mpad;
+    HIP_OK(hipMemcpyAsync(mol->qpad.p, q, sizeof(double) * M, hipMemcpyDeviceToDevice, ctx->stream));
     // --- A off-diagonal
     int len_a = chunk_for(M, M);
     int rows_a = div_up(M, len_a);
@@ -369,7 +373,7 @@ static void grad_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, const doubl
     int rows_c = 0, chunk_c[NCLS];
     for (int cl = 0; cl < NCLS; ++cl) {
         long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
-        chunk_c[cl] = n ? chunk_for(n, M) : 1;
+        chunk_c[cl] = n ? (chunk_for(n, M) + REC_PAD - 1) / REC_PAD * REC_PAD : REC_PAD;
         rows_c += n ? div_up(n, chunk_c[cl]) : 0;
     }
     mol->part.ensure((size_t)(rows_a + rows_c + 1) * 3 * M);
@@ -386,6 +390,7 @@ static void grad_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, const doubl
         if (!n) continue;
         int L = CLS_LA[cl] + CLS_LB[cl];
         int nch = div_up(n, chunk_c[cl]);
+        int n_pad = (int)((n + REC_PAD - 1) / REC_PAD * REC_PAD);
         dim3 grid(div_up(M, 256), nch);
         const unsigned char *rec = pl.rec.p + pl.rec_off[cl];
         int stride = (int)rec_stride<T>(L);
@@ -394,8 +399,7 @@ static void grad_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, const doubl
         switch (L) {
 #define GP_CASE(LL)                                                                                                 \
     case LL:                                                                                                        \
-        k_grad_pts<LL, T><<<grid, 256, 0, ctx->stream>>>(rec, stride, (int)n, chunk_c[cl], mol->pt64.p, mol->lim64.p, \
-                                                         mol->pt32.p, M, tab, part_c, row0);                          \
+        k_grad_pts<LL, T><<<grid, 256, 0, ctx->stream>>>(rec, stride, n_pad, chunk_c[cl], pts, M, tab, part_c, row0); \
         break;
             GP_CASE(0) GP_CASE(1) GP_CASE(2) GP_CASE(3) GP_CASE(4)
 #undef GP_CASE
@@ -415,9 +419,10 @@ static void grad_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, const doubl
     int chunk_v[NCLS];
     for (int cl = 0; cl < NCLS; ++cl) {
         long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
-        chunk_v[cl] = chunk_for(M, n ? n : 1);
+        chunk_v[cl] = chunk_for(Mpad, n ? n : 1);
         if (chunk_v[cl] < 32) chunk_v[cl] = 32;
-        size_t v = (size_t)div_up(M, chunk_v[cl]) * ntuv(CLS_LA[cl] + CLS_LB[cl] + 1) * n;
+        chunk_v[cl] = (chunk_v[cl] + PT_BATCH - 1) / PT_BATCH * PT_BATCH;
+        size_t v = (size_t)div_up(Mpad, chunk_v[cl]) * ntuv(CLS_LA[cl] + CLS_LB[cl] + 1) * n;
         vneed = v > vneed ? v : vneed;
         gneed = (size_t)n * 6 > gneed ? (size_t)n * 6 : gneed;
     }
@@ -431,7 +436,7 @@ static void grad_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, const doubl
             continue;
         }
         int L = CLS_LA[cl] + CLS_LB[cl];
-        int nch = div_up(M, chunk_v[cl]);
+        int nch = div_up(Mpad, chunk_v[cl]);
         dim3 grid(div_up(n, 256), nch);
         const unsigned char *rec = pl.rec.p + pl.rec_off[cl];
         int stride = (int)rec_stride<T>(L);
@@ -440,8 +445,8 @@ static void grad_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, const doubl
         switch (L) {
 #define GV_CASE(LL)                                                                                                \
     case LL:                                                                                                       \
-        k_grad_v<LL, T><<<grid, 256, 0, ctx->stream>>>(rec, stride, (int)n, mol->pt64.p, mol->lim64.p, mol->pt32.p, \
-                                                       q, M, chunk_v[cl], tab, mol->vbuf.p);                        \
+        k_grad_v<LL, T><<<grid, 256, 0, ctx->stream>>>(rec, stride, (int)n, pts, mol->qpad.p, Mpad, chunk_v[cl],   \
+                                                       tab, mol->vbuf.p);                                           \
         break;
             GV_CASE(0) GV_CASE(1) GV_CASE(2) GV_CASE(3) GV_CASE(4)
 #undef GV_CASE

@@ -10,52 +10,54 @@
 // n_tuv-term dot product.
 //
 // Mapping.  esp: one lane per surface point; the wave walks a chunk of primitive pairs
-// whose records are wave-uniform (scalar loads into SGPRs), so the inner loop is pure VALU
-// and the k-sum stays in a register.  Fock: one lane per primitive pair; the wave walks a
-// chunk of points (wave-uniform) and accumulates V_tuv in registers.  Partial results per
-// chunk are reduced afterwards in a fixed order, so results are bitwise reproducible.
+// whose records are wave-uniform (scalar loads into SGPRs, a few pairs per batch so one
+// wait covers several evaluations); the k-sum stays in a register.  Fock: one lane per
+// primitive pair; the wave walks a chunk of points (wave-uniform, batches of four) and
+// accumulates V_tuv in registers.  Pair lists and point arrays are padded with
+// zero-contribution entries so batches never need a tail.  Partial results per chunk are
+// reduced afterwards in a fixed order, so results are bitwise reproducible.
 #include "pcm_internal.h"
 
 // ----------------------------------------------------------------------------------------
 // esp: partial c over one chunk of pairs of one class
 // ----------------------------------------------------------------------------------------
 template <int L, typename T>
-__global__ __launch_bounds__(256) void k_esp(const unsigned char *__restrict__ rec, int stride, int n_pairs,
-                                             int chunk_len, const double *__restrict__ pt64,
-                                             const double *__restrict__ lim64, const float *__restrict__ pt32,
-                                             int M, const T *__restrict__ boys_g, double *__restrict__ part,
-                                             int row0) {
+__global__ __launch_bounds__(256) void k_esp(const unsigned char *__restrict__ rec, int stride, int n_pad,
+                                             int chunk_len, const PtInt<T> *__restrict__ pts, int M,
+                                             const T *__restrict__ boys_g, double *__restrict__ part, int row0) {
+    constexpr int NT = ntuv(L), PB = pair_batch<L>();
     __shared__ T tab[BoysCfg<T>::NROW * BoysCfg<T>::MT];
     load_boys<T>(tab, boys_g);
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int kk = k < M ? k : M - 1;
-    const double cx = pt64[4 * kk], cy = pt64[4 * kk + 1], cz = pt64[4 * kk + 2];
-    T zeta2, limk;
-    if constexpr (sizeof(T) == 8) {
-        zeta2 = (T)pt64[4 * kk + 3];
-        limk = (T)lim64[kk];
-    } else {
-        zeta2 = pt32[4 * kk];
-        limk = pt32[4 * kk + 1];
-    }
+    const PtInt<T> me = pts[k < M ? k : M - 1];
     const int p0 = blockIdx.y * chunk_len;
-    const int p1 = min(n_pairs, p0 + chunk_len);
+    const int p1 = min(n_pad, p0 + chunk_len);
     double acc = 0.0;
-    for (int ip = p0; ip < p1; ++ip) {
-        const unsigned char *r = rec + (size_t)ip * stride;
-        const PairHdr<T> h = *reinterpret_cast<const PairHdr<T> *>(r);
-        const T *D = reinterpret_cast<const T *>(r + sizeof(PairHdr<T>));
-        T R[ntuv(L)];
-        eval_R<L, T>(h.Px - cx, h.Py - cy, h.Pz - cz, h, zeta2, limk, tab, R);
-        T s = T(0);
+    for (int ip = p0; ip < p1; ip += PB) {
+        PairHdr<T> h[PB];
+        T D[PB][NT];
 #pragma unroll
-        for (int t = 0; t < ntuv(L); ++t) s = fma(D[t], R[t], s);
-        acc += (double)s;
+        for (int b = 0; b < PB; ++b) {
+            const unsigned char *r = rec + (size_t)(ip + b) * stride;
+            h[b] = *reinterpret_cast<const PairHdr<T> *>(r);
+            const T *d = reinterpret_cast<const T *>(r + sizeof(PairHdr<T>));
+#pragma unroll
+            for (int t = 0; t < NT; ++t) D[b][t] = d[t];
+        }
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            T R[NT];
+            eval_R<L, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab, R);
+            T s = T(0);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) s = fma(D[b][t], R[t], s);
+            acc += (double)s;
+        }
     }
     if (k < M) part[(size_t)(row0 + blockIdx.y) * M + k] = acc;
 }
 
-// fixed-order sum of partial rows: out[k] = sum_r part[r*M + k] (+ add[k] if given)
+// fixed-order sum of partial rows: out[k] = sum_r part[r*M + k]
 __global__ void k_sum_rows(const double *__restrict__ part, int rows, int M, double *__restrict__ out) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= M) return;
@@ -67,11 +69,12 @@ __global__ void k_sum_rows(const double *__restrict__ part, int rows, int M, dou
 // ----------------------------------------------------------------------------------------
 // Bz (Eq. 4); coincident positions take the limit 2 zeta / sqrt(pi)
 // ----------------------------------------------------------------------------------------
-__global__ void k_bz(const double *__restrict__ pt64, int M, const double *__restrict__ zeta,
-                     const double *__restrict__ xyz, const double *__restrict__ Z, int N, double *__restrict__ bz) {
+__global__ void k_bz(const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz,
+                     int M, const double *__restrict__ zeta, const double *__restrict__ xyz,
+                     const double *__restrict__ Z, int N, double *__restrict__ bz) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= M) return;
-    double x = pt64[4 * k], y = pt64[4 * k + 1], z = pt64[4 * k + 2], zk = zeta[k];
+    double x = px[k], y = py[k], z = pz[k], zk = zeta[k];
     double s = 0.0;
     for (int J = 0; J < N; ++J) {
         double dx = x - xyz[3 * J], dy = y - xyz[3 * J + 1], dz = z - xyz[3 * J + 2];
@@ -90,8 +93,8 @@ __global__ void k_bz(const double *__restrict__ pt64, int M, const double *__res
 
 void run_bz(pcm_ctx *ctx, pcm_mol *mol, double *bz) {
     ProfScope ps(ctx, "bz", (double)mol->M * mol->N);
-    k_bz<<<div_up(mol->M, 256), 256, 0, ctx->stream>>>(mol->pt64.p, mol->M, mol->zeta.p, mol->xyz.p, mol->Z.p,
-                                                          mol->N, bz);
+    k_bz<<<div_up(mol->M, 256), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p, mol->M, mol->zeta.p,
+                                                          mol->xyz.p, mol->Z.p, mol->N, bz);
     HIP_LAUNCH_OK();
 }
 
@@ -105,8 +108,15 @@ static int esp_chunk_len(long long n_pairs, int M) {
     long long want = (target_groups() + tiles - 1) / tiles;
     if (want < 1) want = 1;
     long long len = (n_pairs + want - 1) / want;
-    if (len < 8) len = 8;
-    return (int)len;
+    if (len < 16) len = 16;
+    return (int)((len + REC_PAD - 1) / REC_PAD * REC_PAD);
+}
+
+template <typename T> static const T *boys_tab(pcm_ctx *ctx);
+template <> const double *boys_tab<double>(pcm_ctx *ctx) { return ctx->boys64.p; }
+template <> const float *boys_tab<float>(pcm_ctx *ctx) { return ctx->boys32.p; }
+template <typename T> static const PtInt<T> *points(pcm_mol *mol) {
+    return reinterpret_cast<const PtInt<T> *>(sizeof(T) == 8 ? mol->pti64.p : mol->pti32.p);
 }
 
 template <typename T>
@@ -117,7 +127,7 @@ static void esp_launch(pcm_ctx *ctx, pcm_mol *mol, double *c) {
     int chunk[NCLS];
     for (int cl = 0; cl < NCLS; ++cl) {
         long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
-        chunk[cl] = n ? esp_chunk_len(n, M) : 1;
+        chunk[cl] = n ? esp_chunk_len(n, M) : REC_PAD;
         rows += n ? div_up(n, chunk[cl]) : 0;
     }
     if (rows == 0) {
@@ -125,12 +135,13 @@ static void esp_launch(pcm_ctx *ctx, pcm_mol *mol, double *c) {
         return;
     }
     mol->part.ensure((size_t)rows * M);
-    const T *tab = sizeof(T) == 8 ? (const T *)ctx->boys64.p : (const T *)ctx->boys32.p;
+    const T *tab = boys_tab<T>(ctx);
     int row0 = 0;
     for (int cl = 0; cl < NCLS; ++cl) {
         long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
         if (!n) continue;
         int L = CLS_LA[cl] + CLS_LB[cl];
+        int n_pad = (int)((n + REC_PAD - 1) / REC_PAD * REC_PAD);
         int nch = div_up(n, chunk[cl]);
         dim3 grid(div_up(M, 256), nch);
         const unsigned char *rec = pl.rec.p + pl.rec_off[cl];
@@ -138,10 +149,10 @@ static void esp_launch(pcm_ctx *ctx, pcm_mol *mol, double *c) {
         {
             ProfScope ps(ctx, "esp_L" + std::to_string(L) + (sizeof(T) == 8 ? "_f64" : "_f32"), (double)n * M);
             switch (L) {
-#define ESP_CASE(LL)                                                                                               \
-    case LL:                                                                                                       \
-        k_esp<LL, T><<<grid, 256, 0, ctx->stream>>>(rec, stride, (int)n, chunk[cl], mol->pt64.p, mol->lim64.p,    \
-                                                    mol->pt32.p, M, tab, mol->part.p, row0);                       \
+#define ESP_CASE(LL)                                                                                                  \
+    case LL:                                                                                                          \
+        k_esp<LL, T><<<grid, 256, 0, ctx->stream>>>(rec, stride, n_pad, chunk[cl], points<T>(mol), M, tab, mol->part.p, \
+                                                    row0);                                                             \
         break;
                 ESP_CASE(0) ESP_CASE(1) ESP_CASE(2) ESP_CASE(3) ESP_CASE(4)
 #undef ESP_CASE
@@ -166,39 +177,40 @@ void run_esp(pcm_ctx *ctx, pcm_mol *mol, double *c, int prec) {
 // ----------------------------------------------------------------------------------------
 template <int L, typename T>
 __global__ __launch_bounds__(256) void k_fock_v(const unsigned char *__restrict__ rec, int stride, int n_pairs,
-                                                const double *__restrict__ pt64, const double *__restrict__ lim64,
-                                                const float *__restrict__ pt32, const double *__restrict__ q,
-                                                int M, int chunk_len, const T *__restrict__ boys_g,
+                                                const PtInt<T> *__restrict__ pts, const double *__restrict__ q,
+                                                int Mpad, int chunk_len, const T *__restrict__ boys_g,
                                                 double *__restrict__ vout) {
+    constexpr int NT = ntuv(L);
     __shared__ T tab[BoysCfg<T>::NROW * BoysCfg<T>::MT];
     load_boys<T>(tab, boys_g);
     const int ip = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ipp = ip < n_pairs ? ip : n_pairs - 1;
-    const PairHdr<T> h = *reinterpret_cast<const PairHdr<T> *>(rec + (size_t)ipp * stride);
+    const PairHdr<T> h = *reinterpret_cast<const PairHdr<T> *>(rec + (size_t)(ip < n_pairs ? ip : n_pairs - 1) * stride);
     const int k0 = blockIdx.y * chunk_len;
-    const int k1 = min(M, k0 + chunk_len);
-    double V[ntuv(L)];
+    const int k1 = min(Mpad, k0 + chunk_len);
+    double V[NT];
 #pragma unroll
-    for (int t = 0; t < ntuv(L); ++t) V[t] = 0.0;
-    for (int k = k0; k < k1; ++k) {
-        T zeta2, limk;
-        if constexpr (sizeof(T) == 8) {
-            zeta2 = (T)pt64[4 * k + 3];
-            limk = (T)lim64[k];
-        } else {
-            zeta2 = pt32[4 * k];
-            limk = pt32[4 * k + 1];
+    for (int t = 0; t < NT; ++t) V[t] = 0.0;
+    for (int k = k0; k < k1; k += PT_BATCH) {
+        PtInt<T> pt[PT_BATCH];
+        double qk[PT_BATCH];
+#pragma unroll
+        for (int b = 0; b < PT_BATCH; ++b) {
+            pt[b] = pts[k + b];
+            qk[b] = q[k + b];
         }
-        T R[ntuv(L)];
-        eval_R<L, T>(h.Px - pt64[4 * k], h.Py - pt64[4 * k + 1], h.Pz - pt64[4 * k + 2], h, zeta2, limk, tab, R);
-        const double qk = q[k];
 #pragma unroll
-        for (int t = 0; t < ntuv(L); ++t) V[t] = fma(qk, (double)R[t], V[t]);
+        for (int b = 0; b < PT_BATCH; ++b) {
+            T R[NT];
+            eval_R<L, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta, pt[b].lim, tab,
+                         R);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) V[t] = fma(qk[b], (double)R[t], V[t]);
+        }
     }
     if (ip < n_pairs) {
-        double *o = vout + (size_t)blockIdx.y * ntuv(L) * n_pairs;
+        double *o = vout + (size_t)blockIdx.y * NT * n_pairs;
 #pragma unroll
-        for (int t = 0; t < ntuv(L); ++t) o[(size_t)t * n_pairs + ip] = V[t];
+        for (int t = 0; t < NT; ++t) o[(size_t)t * n_pairs + ip] = V[t];
     }
 }
 
@@ -269,26 +281,27 @@ __global__ void k_fock_scatter(long long sp0, long long nsp, long long cls_off, 
         }
 }
 
-static int fock_chunk_len(long long n_pairs, int M) {
+static int fock_chunk_len(long long n_pairs, int Mpad) {
     int tiles = n_pairs > 0 ? div_up(n_pairs, 256) : 1;
     long long want = (target_groups() + tiles - 1) / tiles;
     if (want < 1) want = 1;
-    long long len = (M + want - 1) / want;
+    long long len = (Mpad + want - 1) / want;
     if (len < 32) len = 32;
-    return (int)len;
+    return (int)((len + PT_BATCH - 1) / PT_BATCH * PT_BATCH);
 }
 
 template <typename T>
 static void fock_launch(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F) {
     PairList &pl = mol->fock;
-    const int M = mol->M;
-    const T *tab = sizeof(T) == 8 ? (const T *)ctx->boys64.p : (const T *)ctx->boys32.p;
+    const int M = mol->M, Mpad = mol->Mpad;
+    const T *tab = boys_tab<T>(ctx);
+    HIP_OK(hipMemcpyAsync(mol->qpad.p, q, sizeof(double) * M, hipMemcpyDeviceToDevice, ctx->stream));
     size_t vneed = 0, fneed = 0;
     int chunk[NCLS];
     for (int cl = 0; cl < NCLS; ++cl) {
         long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
-        chunk[cl] = fock_chunk_len(n, M);
-        int nch = div_up(M, chunk[cl]);
+        chunk[cl] = fock_chunk_len(n, Mpad);
+        int nch = div_up(Mpad, chunk[cl]);
         size_t v = (size_t)nch * ntuv(CLS_LA[cl] + CLS_LB[cl]) * n;
         vneed = v > vneed ? v : vneed;
         size_t f = (size_t)n * ncart(CLS_LA[cl]) * ncart(CLS_LB[cl]);
@@ -300,22 +313,22 @@ static void fock_launch(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F) 
         long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
         if (!n) continue;
         int L = CLS_LA[cl] + CLS_LB[cl];
-        int nch = div_up(M, chunk[cl]);
+        int nch = div_up(Mpad, chunk[cl]);
         dim3 grid(div_up(n, 256), nch);
         const unsigned char *rec = pl.rec.p + pl.rec_off[cl];
         int stride = (int)align16(sizeof(PairHdr<T>));
         {
-        ProfScope ps(ctx, "fock_v_L" + std::to_string(L) + (sizeof(T) == 8 ? "_f64" : "_f32"), (double)n * M);
-        switch (L) {
-#define FV_CASE(LL)                                                                                                \
-    case LL:                                                                                                       \
-        k_fock_v<LL, T><<<grid, 256, 0, ctx->stream>>>(rec, stride, (int)n, mol->pt64.p, mol->lim64.p, mol->pt32.p, \
-                                                       q, M, chunk[cl], tab, mol->vbuf.p);                          \
+            ProfScope ps(ctx, "fock_v_L" + std::to_string(L) + (sizeof(T) == 8 ? "_f64" : "_f32"), (double)n * M);
+            switch (L) {
+#define FV_CASE(LL)                                                                                                 \
+    case LL:                                                                                                        \
+        k_fock_v<LL, T><<<grid, 256, 0, ctx->stream>>>(rec, stride, (int)n, points<T>(mol), mol->qpad.p, Mpad,      \
+                                                       chunk[cl], tab, mol->vbuf.p);                                \
         break;
-            FV_CASE(0) FV_CASE(1) FV_CASE(2) FV_CASE(3) FV_CASE(4)
+                FV_CASE(0) FV_CASE(1) FV_CASE(2) FV_CASE(3) FV_CASE(4)
 #undef FV_CASE
-        }
-        HIP_LAUNCH_OK();
+            }
+            HIP_LAUNCH_OK();
         }
         const int *es = pl.ent_sp.p + pl.cls_off[cl], *ei = pl.ent_ij.p + pl.cls_off[cl];
         long long sp0 = mol->sp_cls_off[cl], nsp = mol->sp_cls_off[cl + 1] - sp0;

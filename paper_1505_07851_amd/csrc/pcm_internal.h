@@ -101,19 +101,38 @@ __device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
 __device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
 __device__ __forceinline__ float sqrt_t(float x) { return sqrtf(x); }
 
+// 1/sqrt(x) for finite x > 0: hardware estimate refined by one cubic correction step,
+// y = y0 (1 - e)^(-1/2) ~ y0 (1 + e/2 + 3e^2/8) with e = 1 - x y0^2.
+__device__ __forceinline__ double rsq_fast(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+__device__ __forceinline__ float rsq_fast(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Surface point as the integral kernels read it (wave-uniform in the pair-per-lane kernels):
+// position in FP64 (differences P - C are taken in FP64 in both precisions), the exponent
+// zeta, its square and the far-field limit TMAX / zeta^2 in the kernel's precision.
+template <typename T> struct PtInt {
+    double x, y, z;
+    T zeta2, zeta, lim;
+};
+constexpr int PT_PAD = 64;  // point arrays are padded to a multiple of this with far dummies
+
 template <int L, typename T>
-__device__ __forceinline__ void aux_Rn(T r2, T p, T limp, T pf, T pref, T zeta2, T limk,
+__device__ __forceinline__ void aux_Rn(T r2, T p, T limp, T pf, T pref, T zeta2, T zeta, T limk,
                                        const T *__restrict__ tab, T (&Rn)[L + 1]) {
     using C = BoysCfg<T>;
     if (r2 >= limp + limk) {
-        T ri = rsqrt_t(r2);
+        T ri = rsq_fast(r2);
         T ri2 = ri * ri;
         Rn[0] = pf * ri;
 #pragma unroll
         for (int n = 1; n <= L; ++n) Rn[n] = T(-(2 * n - 1)) * ri2 * Rn[n - 1];
     } else {
-        T s = zeta2 + p;
-        T u = zeta2 / s;
+        // sqrt(u) = zeta / sqrt(zeta^2 + p), u = sqrt(u)^2, a = p u
+        T su = zeta * rsq_fast(zeta2 + p);
+        T u = su * su;
         T a = p * u;
         T tb = a * r2;
         int i = (int)(tb * T(8) + T(0.5));
@@ -124,7 +143,7 @@ __device__ __forceinline__ void aux_Rn(T r2, T p, T limp, T pf, T pref, T zeta2,
 #pragma unroll
         for (int k = 1; k <= C::ORD; ++k) w[k] = w[k - 1] * d * (T(1) / T(k));
         const T *row = tab + i * C::MT;
-        T fac = pref * sqrt_t(u);
+        T fac = pref * su;
         T m2a = T(-2) * a;
 #pragma unroll
         for (int n = 0; n <= L; ++n) {
@@ -139,14 +158,19 @@ __device__ __forceinline__ void aux_Rn(T r2, T p, T limp, T pf, T pref, T zeta2,
 
 // R_tuv (t+u+v <= L) of one pair against one point; (X, Y, Z) = P - C.
 template <int L, typename T>
-__device__ __forceinline__ void eval_R(double X, double Y, double Z, const PairHdr<T> &h, T zeta2, T limk,
+__device__ __forceinline__ void eval_R(double X, double Y, double Z, const PairHdr<T> &h, T zeta2, T zeta, T limk,
                                        const T *__restrict__ tab, T (&R)[ntuv(L)]) {
     T x = T(X), y = T(Y), z = T(Z);
     T r2 = x * x + y * y + z * z;
     T Rn[L + 1];
-    aux_Rn<L, T>(r2, h.p, h.limp, h.pf, h.pref, zeta2, limk, tab, Rn);
+    aux_Rn<L, T>(r2, h.p, h.limp, h.pf, h.pref, zeta2, zeta, limk, tab, Rn);
     MdR<L>::run(x, y, z, Rn, R);
 }
+
+// pairs per batch of wave-uniform record loads in the point-per-lane kernels
+template <int L> __host__ __device__ constexpr int pair_batch() { return L == 0 ? 4 : (L <= 2 ? 2 : 1); }
+constexpr int REC_PAD = 4;  // pair record lists are padded to a multiple of this with zero records
+constexpr int PT_BATCH = 4; // points per batch in the pair-per-lane kernels
 
 // Load the Boys table of type T into LDS (tab_g holds BoysCfg<T>::NROW * MT values).
 template <typename T>
@@ -257,6 +281,7 @@ struct PairList {
 
 struct pcm_mol {
     int N = 0, nsph = 0, M = 0, Mraw = 0;
+    double zeta0 = 4.9;
     int ns = 0, nbf = 0, nprim = 0;
     // host copies
     std::vector<double> h_xyz, h_Z, h_rad, h_dirs, h_w;
@@ -271,9 +296,10 @@ struct pcm_mol {
     // device: surface (SoA, FP64) and packed point records
     DevBuf<int> keep;  // [M]
     DevBuf<double> px, py, pz, zeta, S, Akk;
-    DevBuf<double> pt64;  // [M][4]: x, y, z, zeta^2
-    DevBuf<double> lim64; // [M] TMAX64 / zeta^2
-    DevBuf<float> pt32;   // [M][4]: zeta^2, TMAX32/zeta^2, zeta^2/2 (matvec), zeta
+    int Mpad = 0;                     // M rounded up to PT_PAD
+    DevBuf<unsigned char> pti64;      // [Mpad] PtInt<double> (far dummies past M)
+    DevBuf<unsigned char> pti32;      // [Mpad] PtInt<float>
+    DevBuf<double> qpad;              // [Mpad] charges copied for the point loops (zeros past M)
     // candidate shell pairs (classes concatenated)
     long long sp_cls_off[NCLS + 1] = {0};
     std::vector<int> h_spa, h_spb;

@@ -180,10 +180,16 @@ __global__ void k_surface_points(const double *__restrict__ xyz, const double *_
                                  const int *__restrict__ keep, int M, const double *__restrict__ r_explicit,
                                  double zeta0, double diag_const, double *__restrict__ px, double *__restrict__ py,
                                  double *__restrict__ pz, double *__restrict__ zeta_o, double *__restrict__ S_o,
-                                 double *__restrict__ Akk, double *__restrict__ pt64, double *__restrict__ lim64,
-                                 float *__restrict__ pt32) {
+                                 double *__restrict__ Akk, int Mpad, PtInt<double> *__restrict__ pti64,
+                                 PtInt<float> *__restrict__ pti32, double *__restrict__ qpad) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= M) return;
+    if (k >= Mpad) return;
+    if (k >= M) {  // far-away dummy points (zero charge) completing the last batch
+        pti64[k] = PtInt<double>{1e6, 1e6, 1e6, 1.0, 1.0, BoysCfg<double>::TMAX};
+        pti32[k] = PtInt<float>{1e6, 1e6, 1e6, 1.0f, 1.0f, BoysCfg<float>::TMAX};
+        qpad[k] = 0.0;
+        return;
+    }
     int kr = keep[k];
     int I = kr / nsph, j = kr - I * nsph;
     double zeta = zeta0 / (rad[I] * sqrt(w[j]));
@@ -201,12 +207,8 @@ __global__ void k_surface_points(const double *__restrict__ xyz, const double *_
     S_o[k] = s;
     Akk[k] = diag_const * zeta / s;
     double z2 = zeta * zeta;
-    pt64[4 * k] = x; pt64[4 * k + 1] = y; pt64[4 * k + 2] = z; pt64[4 * k + 3] = z2;
-    lim64[k] = BoysCfg<double>::TMAX / z2;
-    pt32[4 * k] = (float)z2;
-    pt32[4 * k + 1] = (float)((double)BoysCfg<float>::TMAX / z2);
-    pt32[4 * k + 2] = (float)(0.5 * z2);
-    pt32[4 * k + 3] = (float)zeta;
+    pti64[k] = PtInt<double>{x, y, z, z2, zeta, BoysCfg<double>::TMAX / z2};
+    pti32[k] = PtInt<float>{x, y, z, (float)z2, (float)zeta, (float)((double)BoysCfg<float>::TMAX / z2)};
 }
 
 void surface_build(pcm_ctx *ctx, pcm_mol *mol, bool prune) {
@@ -240,16 +242,20 @@ void surface_build(pcm_ctx *ctx, pcm_mol *mol, bool prune) {
         int Mi = mol->M;
         mol->px.ensure(Mi); mol->py.ensure(Mi); mol->pz.ensure(Mi);
         mol->zeta.ensure(Mi); mol->S.ensure(Mi); mol->Akk.ensure(Mi);
-        mol->pt64.ensure(4 * (size_t)Mi); mol->lim64.ensure(Mi); mol->pt32.ensure(4 * (size_t)Mi);
+        mol->Mpad = (Mi + PT_PAD - 1) / PT_PAD * PT_PAD;
+        mol->pti64.ensure(sizeof(PtInt<double>) * (size_t)mol->Mpad);
+        mol->pti32.ensure(sizeof(PtInt<float>) * (size_t)mol->Mpad);
+        mol->qpad.ensure(mol->Mpad);
     }
 }
 
 void surface_points(pcm_ctx *ctx, pcm_mol *mol, const double *r_explicit_dev) {
     const int T = 256;
-    k_surface_points<<<div_up(mol->M, T), T, 0, ctx->stream>>>(
+    k_surface_points<<<div_up(mol->Mpad, T), T, 0, ctx->stream>>>(
         mol->xyz.p, mol->rad.p, mol->N, mol->dirs.p, mol->w.p, mol->nsph, mol->keep.p, mol->M, r_explicit_dev,
         ctx->prm.zeta0, ctx->prm.diag_const, mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p, mol->S.p, mol->Akk.p,
-        mol->pt64.p, mol->lim64.p, mol->pt32.p);
+        mol->Mpad, reinterpret_cast<PtInt<double> *>(mol->pti64.p), reinterpret_cast<PtInt<float> *>(mol->pti32.p),
+        mol->qpad.p);
     HIP_LAUNCH_OK();
 }
 
@@ -523,6 +529,20 @@ __global__ void k_prep_density(long long n, const int *__restrict__ ent_sp, cons
     for (int t = 0; t < ntuv(L); ++t) Dd[t] = (T)D[t];
 }
 
+// zero-contribution records completing the last batch of a class: far away, D = 0
+template <typename T>
+__global__ void k_zero_records(unsigned char *__restrict__ rec, int n, size_t stride, int nt) {
+    int q = threadIdx.x;
+    if (q >= n) return;
+    unsigned char *r = rec + q * stride;
+    PairHdr<T> h;
+    h.Px = 1e6; h.Py = 1e6; h.Pz = 1e6;
+    h.p = T(1); h.limp = BoysCfg<T>::TMAX; h.pf = T(0); h.pref = T(0);
+    *reinterpret_cast<PairHdr<T> *>(r) = h;
+    T *D = reinterpret_cast<T *>(r + sizeof(PairHdr<T>));
+    for (int t = 0; t < nt; ++t) D[t] = T(0);
+}
+
 template <typename T>
 static void prep_lists(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P) {
     // byte layout: classes back to back, each with its own stride
@@ -530,8 +550,9 @@ static void prep_lists(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P
     for (int c = 0; c < NCLS; ++c) {
         pl.rec_off[c] = off;
         long long n = pl.cls_off[c + 1] - pl.cls_off[c];
+        long long npad = (n + REC_PAD - 1) / REC_PAD * REC_PAD;
         size_t stride = P ? rec_stride<T>(CLS_LA[c] + CLS_LB[c]) : align16(sizeof(PairHdr<T>));
-        off += align16(n * stride) + 256;
+        off += align16(npad * stride) + 256;
     }
     pl.rec_off[NCLS] = off;
     pl.rec.ensure(off);
@@ -563,6 +584,12 @@ static void prep_lists(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P
         }
 #undef PREP_CASE
         HIP_LAUNCH_OK();
+        if (P && n % REC_PAD) {
+            size_t stride = rec_stride<T>(CLS_LA[c] + CLS_LB[c]);
+            int npad = (int)(REC_PAD - n % REC_PAD);
+            k_zero_records<T><<<1, 64, 0, ctx->stream>>>(rec + n * stride, npad, stride, ntuv(CLS_LA[c] + CLS_LB[c]));
+            HIP_LAUNCH_OK();
+        }
     }
 }
 

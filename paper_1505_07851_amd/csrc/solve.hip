@@ -14,67 +14,94 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <numeric>
+#include <thread>
 
 constexpr int MV_T = 256;
+constexpr int MV_B = 8;  // columns per batch of wave-uniform loads
 
 // ----------------------------------------------------------------------------------------
-// matrix-free off-diagonal product, partial over a chunk of columns
+// matrix-free off-diagonal product, partial over a chunk of columns.  Point arrays are
+// padded to a multiple of 64 with far-away dummy points whose x entries are zero, so the
+// column loop runs over whole batches of 8.
 // ----------------------------------------------------------------------------------------
 template <typename T> struct Pt {
     T x, y, z, zeta;
 };
 
+inline int mv_pad(int M) { return (M + 63) & ~63; }
+
 __global__ void k_pack_pts(const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz,
-                           const double *__restrict__ zeta, int M, Pt<double> *__restrict__ p64,
-                           Pt<float> *__restrict__ p32) {
+                           const double *__restrict__ zeta, int M, int Mp, Pt<double> *__restrict__ p64,
+                           Pt<float> *__restrict__ p32, double *__restrict__ x64, float *__restrict__ x32) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= M) return;
-    p64[k] = Pt<double>{px[k], py[k], pz[k], zeta[k]};
-    p32[k] = Pt<float>{(float)px[k], (float)py[k], (float)pz[k], (float)zeta[k]};
+    if (k >= Mp) return;
+    if (k < M) {
+        p64[k] = Pt<double>{px[k], py[k], pz[k], zeta[k]};
+        p32[k] = Pt<float>{(float)px[k], (float)py[k], (float)pz[k], (float)zeta[k]};
+    } else {
+        p64[k] = Pt<double>{1e6, 1e6, 1e6, 1.0};
+        p32[k] = Pt<float>{1e6f, 1e6f, 1e6f, 1.0f};
+        x64[k] = 0.0;
+        x32[k] = 0.0f;
+    }
 }
 
-__global__ void k_to_f32(const double *__restrict__ x, float *__restrict__ y, int M) {
+template <typename T>
+__global__ void k_pad_x(const double *__restrict__ x, T *__restrict__ y, int M) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < M) y[k] = (float)x[k];
+    if (k < M) y[k] = (T)x[k];
 }
 
 __device__ __forceinline__ double erf_t(double x) { return erf(x); }
 __device__ __forceinline__ float erf_t(float x) { return erff(x); }
 
+// A_kl inside the cutoff radius (erf not yet 1): coincident points take 2 z'/sqrt(pi)
+template <typename T>
+__device__ __attribute__((noinline)) T mv_near(T zk, T zl, T r2, bool self) {
+    if (self) return T(0);
+    T zp = zk * zl * rsqrt_t(zk * zk + zl * zl);
+    if (r2 == T(0)) return T(1.1283791670955125739) * zp;
+    T r = sqrt_t(r2);
+    return erf_t(zp * r) / r;
+}
+
 template <typename T>
 __global__ __launch_bounds__(MV_T) void k_matvec(const Pt<T> *__restrict__ pts, const T *__restrict__ xv, int M,
-                                                 int chunk_len, double *__restrict__ part) {
-    constexpr T CUT2 = sizeof(T) == 8 ? T(36.0) : T(16.0);
-    constexpr T TWO_OVER_SQRTPI = T(1.1283791670955125739);
+                                                 int ncol, int chunk_len, T rc2, double *__restrict__ part) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int kk = k < M ? k : M - 1;
     const Pt<T> me = pts[kk];
-    const T hz = T(0.5) * me.zeta * me.zeta;
     const int l0 = blockIdx.y * chunk_len;
-    const int l1 = min(M, l0 + chunk_len);
+    const int l1 = min(ncol, l0 + chunk_len);
     T acc = T(0);
-    for (int l = l0; l < l1; ++l) {
-        const Pt<T> o = pts[l];
-        const T xl = xv[l];
-        T dx = me.x - o.x, dy = me.y - o.y, dz = me.z - o.z;
-        T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        T hzl = T(0.5) * o.zeta * o.zeta;
-        T a;
-        if (r2 * min(hz, hzl) >= CUT2) {
-            a = rsqrt_t(r2);
-        } else {
-            T zp = me.zeta * o.zeta * rsqrt_t(me.zeta * me.zeta + o.zeta * o.zeta);
-            if (l == kk) {
-                a = T(0);
-            } else if (r2 == T(0)) {
-                a = TWO_OVER_SQRTPI * zp;
-            } else {
-                T r = sqrt_t(r2);
-                a = erf_t(zp * r) / r;
-            }
+    for (int l = l0; l < l1; l += MV_B) {
+        Pt<T> o[MV_B];
+        T xl[MV_B], a[MV_B], r2[MV_B];
+#pragma unroll
+        for (int u = 0; u < MV_B; ++u) {
+            o[u] = pts[l + u];
+            xl[u] = xv[l + u];
         }
-        acc = fma(a, xl, acc);
+        bool near = false;
+#pragma unroll
+        for (int u = 0; u < MV_B; ++u) {
+            T dx = me.x - o[u].x, dy = me.y - o[u].y, dz = me.z - o[u].z;
+            r2[u] = fma(dx, dx, fma(dy, dy, dz * dz));
+            near |= r2[u] < rc2;
+            a[u] = rsq_fast(r2[u]);
+        }
+        if (near) {
+#pragma unroll
+            for (int u = 0; u < MV_B; ++u)
+                if (r2[u] < rc2) a[u] = mv_near<T>(me.zeta, o[u].zeta, r2[u], l + u == kk);
+        }
+#pragma unroll
+        for (int u = 0; u < MV_B; ++u) acc = fma(a[u], xl[u], acc);
     }
     if (k < M) part[(size_t)blockIdx.y * M + k] = (double)acc;
 }
@@ -105,21 +132,22 @@ __global__ __launch_bounds__(256) void k_mv_finish(const double *__restrict__ pa
     }
 }
 
-static int mv_chunk_len(int M) {
-    int tiles = div_up(M, MV_T);
+static int mv_chunk_len(int Mp) {
+    int tiles = div_up(Mp, MV_T);
     int want = div_up(2048, tiles);
-    int len = div_up(M, want);
+    int len = div_up(Mp, want);
+    len = (len + MV_B - 1) / MV_B * MV_B;
     return len < 64 ? 64 : len;
 }
 
 // solver workspace layout inside mol->sv (offsets in doubles, each slot 32-aligned)
 struct SolverLayout {
-    size_t r, z, p, Ap, y, dp1, dp2, dp3, b, d, res, dot, p64, p32, xf, total;
+    size_t r, z, p, Ap, y, dp1, dp2, dp3, b, d, res, dot, p64, p32, x64, x32, total;
 };
 
 static SolverLayout solver_layout(size_t M) {
     SolverLayout L{};
-    size_t o = 0;
+    size_t o = 0, Mp = mv_pad((int)M);
     auto take = [&](size_t n) {
         size_t s0 = o;
         o += (n + 31) & ~size_t(31);
@@ -128,7 +156,7 @@ static SolverLayout solver_layout(size_t M) {
     L.r = take(M); L.z = take(M); L.p = take(M); L.Ap = take(M); L.y = take(M);
     L.dp1 = take(2 * M + 4096); L.dp2 = take(2 * M + 4096); L.dp3 = take(2 * M + 4096);
     L.b = take(M); L.d = take(M); L.res = take(M); L.dot = take(M / 256 + 64);
-    L.p64 = take(4 * M); L.p32 = take(2 * M + 2); L.xf = take(M / 2 + 2);
+    L.p64 = take(4 * Mp); L.p32 = take(2 * Mp); L.x64 = take(Mp); L.x32 = take(Mp / 2 + 2);
     L.total = o;
     return L;
 }
@@ -136,7 +164,8 @@ static SolverLayout solver_layout(size_t M) {
 struct MatvecWS {
     Pt<double> *p64;
     Pt<float> *p32;
-    float *xf;
+    double *x64;
+    float *x32;
 };
 
 static MatvecWS mv_ws(pcm_mol *mol) {
@@ -144,36 +173,54 @@ static MatvecWS mv_ws(pcm_mol *mol) {
     MatvecWS w;
     w.p64 = reinterpret_cast<Pt<double> *>(mol->sv.p + L.p64);
     w.p32 = reinterpret_cast<Pt<float> *>(mol->sv.p + L.p32);
-    w.xf = reinterpret_cast<float *>(mol->sv.p + L.xf);
+    w.x64 = mol->sv.p + L.x64;
+    w.x32 = reinterpret_cast<float *>(mol->sv.p + L.x32);
     return w;
+}
+
+// cutoff radius^2 beyond which erf(z' r) rounds to 1 for every pair: z'^2 >= zeta_min^2 / 2
+static void mv_cutoffs(pcm_mol *mol, double &rc2_64, double &rc2_32) {
+    double zmin = 1e300;
+    for (int kr : mol->h_keep) {
+        int I = kr / mol->nsph, j = kr - I * mol->nsph;
+        zmin = std::min(zmin, mol->zeta0 / (mol->h_rad[I] * std::sqrt(mol->h_w[j])));
+    }
+    zmin *= 1.0 - 1e-9;
+    rc2_64 = 2.0 * 36.0 / (zmin * zmin);
+    rc2_32 = 2.0 * 16.0 / (zmin * zmin);
 }
 
 static void ensure_solver_ws(pcm_ctx *ctx, pcm_mol *mol) {
     size_t M = mol->M;
+    int Mp = mv_pad((int)M);
     mol->sv.ensure(solver_layout(M).total);
     MatvecWS w = mv_ws(mol);
-    k_pack_pts<<<div_up(M, 256), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p, (int)M, w.p64,
-                                                        w.p32);
+    k_pack_pts<<<div_up(Mp, 256), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p, (int)M, Mp,
+                                                         w.p64, w.p32, w.x64, w.x32);
     HIP_LAUNCH_OK();
 }
 
 // y = A x (FP64 or FP32 off-diagonal); dotpart (may be null) receives per-block x.y partials
 static void matvec(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int prec, double *dotpart) {
-    const int M = mol->M;
+    const int M = mol->M, Mp = mv_pad(M);
     MatvecWS w = mv_ws(mol);
-    int len = mv_chunk_len(M);
-    int rows = div_up(M, len);
+    int len = mv_chunk_len(Mp);
+    int rows = div_up(Mp, len);
     mol->part2.ensure((size_t)rows * M);
     dim3 grid(div_up(M, MV_T), rows);
+    double rc64, rc32;
+    mv_cutoffs(mol, rc64, rc32);
     if (prec == PCM_MIXED) {
-        k_to_f32<<<div_up(M, 256), 256, 0, ctx->stream>>>(x, w.xf, M);
+        k_pad_x<float><<<div_up(M, 256), 256, 0, ctx->stream>>>(x, w.x32, M);
         HIP_LAUNCH_OK();
         ProfScope ps(ctx, "matvec_f32", (double)M * M);
-        k_matvec<float><<<grid, MV_T, 0, ctx->stream>>>(w.p32, w.xf, M, len, mol->part2.p);
+        k_matvec<float><<<grid, MV_T, 0, ctx->stream>>>(w.p32, w.x32, M, Mp, len, (float)rc32, mol->part2.p);
         HIP_LAUNCH_OK();
     } else {
+        k_pad_x<double><<<div_up(M, 256), 256, 0, ctx->stream>>>(x, w.x64, M);
+        HIP_LAUNCH_OK();
         ProfScope ps(ctx, "matvec_f64", (double)M * M);
-        k_matvec<double><<<grid, MV_T, 0, ctx->stream>>>(w.p64, x, M, len, mol->part2.p);
+        k_matvec<double><<<grid, MV_T, 0, ctx->stream>>>(w.p64, w.x64, M, Mp, len, rc64, mol->part2.p);
         HIP_LAUNCH_OK();
     }
     k_mv_finish<<<div_up(M, 256), 256, 0, ctx->stream>>>(mol->part2.p, rows, M, mol->Akk.p, x, y, dotpart);
@@ -665,7 +712,12 @@ double run_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double *c,
 
 // ----------------------------------------------------------------------------------------
 // host partition (Sec. 4b-ii); built with IEEE double and no contraction so that the ranking
-// values are the plain expressions erf(z' d)/d, z' = z_k z_l / sqrt(z_k^2 + z_l^2)
+// values are the plain expressions erf(z' d)/d, z' = z_k z_l / sqrt(z_k^2 + z_l^2).  For
+// z' d >= 6 erf rounds to exactly 1 in double precision, so 1/d is the same value.
+// The l-1 best candidates of a pivot are kept in a bounded heap.  Because |A_kl| <= 1/d, a
+// candidate farther than 1/(worst kept value) cannot enter and is rejected from its distance
+// alone; the ranking is a total order (value, then index), so the selected set is the same as
+// a full sort would give.
 // ----------------------------------------------------------------------------------------
 static inline uint64_t splitmix64_next(uint64_t &s) {
     uint64_t z = (s += 0x9e3779b97f4a7c15ULL);
@@ -681,50 +733,102 @@ static inline double coupling(const double *r, const double *zeta, int k, int l)
     double dx = r[3 * k] - r[3 * l], dy = r[3 * k + 1] - r[3 * l + 1], dz = r[3 * k + 2] - r[3 * l + 2];
     double d = std::sqrt(dx * dx + dy * dy + dz * dz);
     if (d == 0.0) return 2.0 * zp / std::sqrt(M_PI);
-    return std::erf(zp * d) / d;
+    double x = zp * d;
+    if (x >= 6.0) return 1.0 / d;
+    return std::erf(x) / d;
 }
 
 int host_rbj_partition(int M, const double *r, const double *zeta, int l, unsigned long long seed, int *perm,
                        int *blk_off) {
     if (M <= 0 || l <= 0 || !r || !zeta || !perm || !blk_off) return -1;
+    // unassigned indices: a Fenwick tree over [0, M) answers "k-th unassigned in ascending
+    // order" for the pivot pick; the scan list is compacted lazily
+    std::vector<int> bit(M + 1, 0);
+    for (int i = 1; i <= M; ++i) {
+        bit[i] += 1;
+        int j = i + (i & -i);
+        if (j <= M) bit[j] += bit[i];
+    }
+    int top_pow = 1;
+    while (top_pow * 2 <= M) top_pow *= 2;
+    auto kth = [&](int k) {  // 0-based k-th unassigned index
+        int p0 = 0;
+        for (int step = top_pow; step > 0; step >>= 1)
+            if (p0 + step <= M && bit[p0 + step] <= k) {
+                p0 += step;
+                k -= bit[p0];
+            }
+        return p0;  // index (0-based) of the element
+    };
+    auto remove = [&](int i) {
+        for (int j = i + 1; j <= M; j += j & -j) bit[j] -= 1;
+    };
     std::vector<int> left(M);
     std::iota(left.begin(), left.end(), 0);
+    int n_scan = M;  // entries in left[], some possibly assigned already
     std::vector<unsigned char> take(M, 0);
-    std::vector<std::pair<double, int>> cand;
-    cand.reserve(M);
+    using Cand = std::pair<double, int>;
+    // heap ordered so that top() is the worst kept candidate (smallest value, then largest index)
+    auto better = [](const Cand &a, const Cand &b) {
+        return a.first > b.first || (a.first == b.first && a.second < b.second);
+    };
+    std::vector<Cand> heap;
+    heap.reserve(std::min(l, M) + 1);
     uint64_t st = seed;
     int n_left = M, nb = 0, filled = 0;
     blk_off[0] = 0;
-    auto better = [](const std::pair<double, int> &a, const std::pair<double, int> &b) {
-        return a.first > b.first || (a.first == b.first && a.second < b.second);
-    };
     while (n_left > 0) {
         uint64_t x = splitmix64_next(st);
         double u = (double)(x >> 11) * (1.0 / 9007199254740992.0);
         int pos = (int)std::floor(u * (double)n_left);
         if (pos >= n_left) pos = n_left - 1;
-        int piv = left[pos];
-        cand.clear();
-        for (int t = 0; t < n_left; ++t) {
-            int c = left[t];
-            if (c == piv) continue;
-            cand.emplace_back(std::fabs(coupling(r, zeta, piv, c)), c);
+        const int piv = kth(pos);
+        const int want = std::min(l - 1, n_left - 1);
+        heap.clear();
+        if (want > 0) {
+            if (n_scan > 2 * n_left) {  // drop assigned entries before scanning
+                int w = 0;
+                for (int t = 0; t < n_scan; ++t)
+                    if (!take[left[t]]) left[w++] = left[t];
+                n_scan = w;
+            }
+            const double px = r[3 * piv], py = r[3 * piv + 1], pz = r[3 * piv + 2];
+            double reject_d2 = 1e300;  // candidates with d^2 above this cannot enter the heap
+            for (int t = 0; t < n_scan; ++t) {
+                const int q = left[t];
+                if (q == piv || take[q]) continue;
+                const double dx = px - r[3 * q], dy = py - r[3 * q + 1], dz = pz - r[3 * q + 2];
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                if ((int)heap.size() == want && d2 > reject_d2) continue;  // |A| <= 1/d < worst kept
+                Cand c(std::fabs(coupling(r, zeta, piv, q)), q);
+                if ((int)heap.size() < want) {
+                    heap.push_back(c);
+                    std::push_heap(heap.begin(), heap.end(), better);
+                } else if (better(c, heap.front())) {
+                    std::pop_heap(heap.begin(), heap.end(), better);
+                    heap.back() = c;
+                    std::push_heap(heap.begin(), heap.end(), better);
+                } else {
+                    continue;
+                }
+                if ((int)heap.size() == want) {
+                    const double w = heap.front().first;
+                    // |A| <= 1/d: reject when d^2 w^2 > 1 (with a relative margin far above rounding)
+                    reject_d2 = w > 0.0 ? (1.0 + 1e-9) / (w * w) : 1e300;
+                }
+            }
         }
-        int take_n = std::min<int>(l - 1, (int)cand.size());
-        if (take_n > 0 && take_n < (int)cand.size())
-            std::nth_element(cand.begin(), cand.begin() + (take_n - 1), cand.end(), better);
         int start = filled;
         perm[filled++] = piv;
         take[piv] = 1;
-        for (int t = 0; t < take_n; ++t) {
-            perm[filled++] = cand[t].second;
-            take[cand[t].second] = 1;
+        remove(piv);
+        for (const Cand &c : heap) {
+            perm[filled++] = c.second;
+            take[c.second] = 1;
+            remove(c.second);
         }
         std::sort(perm + start, perm + filled);
-        int w = 0;
-        for (int t = 0; t < n_left; ++t)
-            if (!take[left[t]]) left[w++] = left[t];
-        n_left = w;
+        n_left -= filled - start;
         blk_off[++nb] = filled;
     }
     return nb;
