@@ -2,7 +2,7 @@
 """Benchmark of the C-PCM solvation hot path on one MI355X.
 
 One step = one pass of the whole path over the 600-atom protein-shaped solute
-(6-31G*-shaped basis, 110 raw surface points per atom):
+(6-31G*-shaped basis, ~50 kept surface points per atom, M ~ 30k):
   geometry update (surface switching values, A_kk, pair geometry), c = L P with Bz,
   the randomized block-Jacobi PCG solve of A q = -f (Bz + c), the Eq. 13 energy,
   F += L^T q, and the Eq. 14 gradient.
