@@ -331,6 +331,19 @@ class OracleMol:
         gs = gs.reshape(4, self.M, 3)
         return {"g_nuc_terms": gn, "g_surf_terms": gs, "g_nuc": gn.sum(0), "g_surf": gs.sum(0)}
 
+    def grad_surface_points(self, P, q, kidx, pairs=None):
+        """g_surf (sum of the Eq. 14 terms) for the listed points only: shape [len(kidx), 3]."""
+        P = _f64(P)
+        pr = self.pairs(P) if pairs is None else pairs
+        kk = _i32(kidx)
+        out = np.zeros(3 * kk.shape[0])
+        lib().or_grad_points(*self._basis_args(), _p(self.Z), _p(self.rad), ctypes.c_int(self.N), _p(P),
+                             ctypes.c_long(pr["a"].shape[0]), _p(pr["a"]), _p(pr["b"]), _p(pr["i"]), _p(pr["j"]),
+                             _p(pr["w"]), ctypes.c_int(self.M), _p(_f64(self.r.ravel())), _p(self.zeta),
+                             _p(self.Akk), _p(self.owner), _p(_f64(q)), ctypes.c_double(self.f),
+                             ctypes.c_int(kk.shape[0]), _p(kk), _p(out))
+        return out.reshape(-1, 3)
+
     def total_nuclear_gradient(self, g_nuc, g_surf):
         """Points move with their atom: total_I = g_nuc[I] + sum_{k in I} g_surf[k]."""
         tot = g_nuc.copy()

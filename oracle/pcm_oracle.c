@@ -455,6 +455,74 @@ static double dg_erf(double z, double d) { /* d/dd [erf(z d)/d] */
     return 2.0 * z / sqrt(M_PI) * exp(-z * z * d * d) / d - erf(z * d) / (d * d);
 }
 
+/* all four terms for one surface point k: gsk[t*3 + d] (point side) and, when gnl is
+ * given, the nucleus-side contributions accumulated into gnl[t*3N + 3J + d] */
+static void grad_point(const basis_view *bv, const double *Zn, const double *rad, int N, const double *P,
+                       long npairs, const int *pa, const int *pb, const int *pi, const int *pj, const double *pw,
+                       int M, const double *r, const double *zeta, const double *Akk, const int *owner,
+                       const double *q, double f, int k, double *gsk, double *gnl) {
+    const int *sl = bv->sl, *soff = bv->soff, *satom = bv->satom;
+    const double *pexp = bv->pexp, *xyz = bv->xyz;
+    const double *rk = r + 3 * k;
+    memset(gsk, 0, sizeof(double) * 12);
+    /* term 0: q_k z_J d/dx erf(zeta_k d)/d */
+    for (int J = 0; J < N; ++J) {
+        double v[3] = {rk[0] - xyz[3 * J], rk[1] - xyz[3 * J + 1], rk[2] - xyz[3 * J + 2]};
+        double d = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (d == 0.0) continue;
+        double g = q[k] * Zn[J] * dg_erf(zeta[k], d) / d;
+        for (int e = 0; e < 3; ++e) {
+            gsk[e] += g * v[e];
+            if (gnl) gnl[3 * J + e] -= g * v[e];
+        }
+    }
+    /* term 1: q_k d c_k */
+    double dA[3 * 36], dB[3 * 36];
+    for (long t = 0; t < npairs; ++t) {
+        int a = pa[t], b = pb[t];
+        or_prim_block_deriv(sl[a], sl[b], xyz + 3 * satom[a], pexp[soff[a] + pi[t]], xyz + 3 * satom[b],
+                            pexp[soff[b] + pj[t]], rk, zeta[k], dA, dB);
+        int nn = ncart(sl[a]) * ncart(sl[b]);
+        for (int e = 0; e < 3; ++e) {
+            double ga = -pw[t] * q[k] * contract_block(bv, a, b, pi[t], pj[t], P, dA + e * nn);
+            double gb = -pw[t] * q[k] * contract_block(bv, a, b, pi[t], pj[t], P, dB + e * nn);
+            if (gnl) {
+                gnl[3 * N + 3 * satom[a] + e] += ga;
+                gnl[3 * N + 3 * satom[b] + e] += gb;
+            }
+            gsk[3 + e] -= ga + gb;
+        }
+    }
+    /* term 2: (1/2f) q^T dA_off q, d/dr_k picks up both A_kl and A_lk */
+    for (int l = 0; l < M; ++l) {
+        if (l == k) continue;
+        const double *rl = r + 3 * l;
+        double v[3] = {rk[0] - rl[0], rk[1] - rl[1], rk[2] - rl[2]};
+        double d = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (d == 0.0) continue;
+        double zp = zeta[k] * zeta[l] / sqrt(zeta[k] * zeta[k] + zeta[l] * zeta[l]);
+        double g = q[k] * q[l] / f * dg_erf(zp, d) / d;
+        for (int e = 0; e < 3; ++e) gsk[6 + e] += g * v[e];
+    }
+    /* term 3: (1/2f) q_k^2 dA_kk, A_kk = const zeta / prod S_wf */
+    int I = owner[k];
+    double zk = zeta[k];
+    for (int J = 0; J < N; ++J) {
+        if (J == I) continue;
+        double v[3] = {rk[0] - xyz[3 * J], rk[1] - xyz[3 * J + 1], rk[2] - xyz[3 * J + 2]};
+        double d = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (d == 0.0) continue;
+        double sw = 0.5 * (erfc(zk * (rad[J] - d)) + erfc(zk * (rad[J] + d)));
+        double dsw = zk / sqrt(M_PI) *
+                     (exp(-zk * zk * (rad[J] - d) * (rad[J] - d)) - exp(-zk * zk * (rad[J] + d) * (rad[J] + d)));
+        double g = 0.5 / f * q[k] * q[k] * (-Akk[k]) * dsw / sw / d;
+        for (int e = 0; e < 3; ++e) {
+            gsk[9 + e] += g * v[e];
+            if (gnl) gnl[3 * 3 * N + 3 * J + e] -= g * v[e];
+        }
+    }
+}
+
 void or_grad(int ns, const int *sl, const int *snp, const int *soff, const int *satom, const double *pexp,
              const int *cn_off, const double *cn, const double *xyz, const int *bf_off, int nbf, const double *Zn,
              const double *rad, int N, const double *P, long npairs, const int *pa, const int *pb, const int *pi,
@@ -476,62 +544,34 @@ void or_grad(int ns, const int *sl, const int *snp, const int *soff, const int *
         tid = omp_get_thread_num();
 #endif
         double *gnl = gn_thr + (size_t)tid * 4 * 3 * N;
+        double gsk[12];
 #pragma omp for schedule(dynamic, 1)
         for (int k = 0; k < M; ++k) {
-            const double *rk = r + 3 * k;
-            /* term 0: q_k z_J d/dx erf(zeta_k d)/d */
-            for (int J = 0; J < N; ++J) {
-                double v[3] = {rk[0] - xyz[3 * J], rk[1] - xyz[3 * J + 1], rk[2] - xyz[3 * J + 2]};
-                double d = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-                if (d == 0.0) continue;
-                double g = q[k] * Zn[J] * dg_erf(zeta[k], d) / d;
-                for (int e = 0; e < 3; ++e) { gs[3 * k + e] += g * v[e]; gnl[3 * J + e] -= g * v[e]; }
-            }
-            /* term 1: q_k d c_k */
-            double dA[3 * 36], dB[3 * 36];
-            for (long t = 0; t < npairs; ++t) {
-                int a = pa[t], b = pb[t];
-                or_prim_block_deriv(sl[a], sl[b], xyz + 3 * satom[a], pexp[soff[a] + pi[t]], xyz + 3 * satom[b],
-                                    pexp[soff[b] + pj[t]], rk, zeta[k], dA, dB);
-                int nn = ncart(sl[a]) * ncart(sl[b]);
-                for (int e = 0; e < 3; ++e) {
-                    double ga = -pw[t] * q[k] * contract_block(&bv, a, b, pi[t], pj[t], P, dA + e * nn);
-                    double gb = -pw[t] * q[k] * contract_block(&bv, a, b, pi[t], pj[t], P, dB + e * nn);
-                    gnl[3 * N + 3 * satom[a] + e] += ga;
-                    gnl[3 * N + 3 * satom[b] + e] += gb;
-                    gs[3 * M + 3 * k + e] -= ga + gb;
-                }
-            }
-            /* term 2: (1/2f) q^T dA_off q, d/dr_k picks up both A_kl and A_lk */
-            for (int l = 0; l < M; ++l) {
-                if (l == k) continue;
-                const double *rl = r + 3 * l;
-                double v[3] = {rk[0] - rl[0], rk[1] - rl[1], rk[2] - rl[2]};
-                double d = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-                if (d == 0.0) continue;
-                double zp = zeta[k] * zeta[l] / sqrt(zeta[k] * zeta[k] + zeta[l] * zeta[l]);
-                double g = q[k] * q[l] / f * dg_erf(zp, d) / d;
-                for (int e = 0; e < 3; ++e) gs[2 * 3 * M + 3 * k + e] += g * v[e];
-            }
-            /* term 3: (1/2f) q_k^2 dA_kk, A_kk = const zeta / prod S_wf */
-            int I = owner[k];
-            double zk = zeta[k];
-            for (int J = 0; J < N; ++J) {
-                if (J == I) continue;
-                double v[3] = {rk[0] - xyz[3 * J], rk[1] - xyz[3 * J + 1], rk[2] - xyz[3 * J + 2]};
-                double d = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-                if (d == 0.0) continue;
-                double sw = 0.5 * (erfc(zk * (rad[J] - d)) + erfc(zk * (rad[J] + d)));
-                double dsw = zk / sqrt(M_PI) *
-                             (exp(-zk * zk * (rad[J] - d) * (rad[J] - d)) - exp(-zk * zk * (rad[J] + d) * (rad[J] + d)));
-                double g = 0.5 / f * q[k] * q[k] * (-Akk[k]) * dsw / sw / d;
-                for (int e = 0; e < 3; ++e) { gs[3 * 3 * M + 3 * k + e] += g * v[e]; gnl[3 * 3 * N + 3 * J + e] -= g * v[e]; }
-            }
+            grad_point(&bv, Zn, rad, N, P, npairs, pa, pb, pi, pj, pw, M, r, zeta, Akk, owner, q, f, k, gsk, gnl);
+            for (int t = 0; t < 4; ++t)
+                for (int e = 0; e < 3; ++e) gs[t * 3 * M + 3 * k + e] = gsk[3 * t + e];
         }
     }
     for (int t = 0; t < nthr; ++t)
         for (int i = 0; i < 4 * 3 * N; ++i) gn[i] += gn_thr[(size_t)t * 4 * 3 * N + i];
     free(gn_thr);
+}
+
+/* surface-point gradient (sum of the four terms) for the points listed in kidx only */
+void or_grad_points(int ns, const int *sl, const int *snp, const int *soff, const int *satom, const double *pexp,
+                    const int *cn_off, const double *cn, const double *xyz, const int *bf_off, int nbf,
+                    const double *Zn, const double *rad, int N, const double *P, long npairs, const int *pa,
+                    const int *pb, const int *pi, const int *pj, const double *pw, int M, const double *r,
+                    const double *zeta, const double *Akk, const int *owner, const double *q, double f, int nk,
+                    const int *kidx, double *gs_out) {
+    basis_view bv = {sl, snp, soff, satom, cn_off, bf_off, pexp, cn, xyz, nbf};
+    (void)ns;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int t = 0; t < nk; ++t) {
+        double gsk[12];
+        grad_point(&bv, Zn, rad, N, P, npairs, pa, pb, pi, pj, pw, M, r, zeta, Akk, owner, q, f, kidx[t], gsk, NULL);
+        for (int e = 0; e < 3; ++e) gs_out[3 * t + e] = gsk[e] + gsk[3 + e] + gsk[6 + e] + gsk[9 + e];
+    }
 }
 
 /* ------------------------------------------------------------------------ */

@@ -1,0 +1,193 @@
+"""Parity at full workload sizes, in the launch configuration bench.py times.
+
+* 600-atom protein (M ~ 30k, nbf 5100): surface keep list and both screening lists bit-exact;
+  c on sampled points, the Fock correction on sampled shell pairs, and the solve through
+  oracle rows of A q - b (the oracle computes these one by one).
+* 300-atom peptide (M ~ 15k): the energy through PCMEnergy; dE/dP equals pcm_fock bitwise;
+  the gradient obeys translation invariance, matches central finite differences (h = 1e-4
+  bohr) on 20 seeded coordinates and the oracle on sampled surface points; the mixed form's
+  analytic gradient is compared with the FP64 one.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def big(torch_cuda):
+    from paper_1505_07851_amd import Context, Molecule
+    print("\n[case protein600]", flush=True)
+    s = I.protein_single_solve()
+    ctx = Context()
+    mol = Molecule.from_system(ctx, s)
+    om = O.mol_from_system(s)
+    P = torch_cuda.tensor(s.P, dtype=torch_cuda.float64, device="cuda")
+    return s, ctx, mol, om, P
+
+
+def test_big_lists_bit_exact(big):
+    s, ctx, mol, om, P = big
+    assert mol.M == om.M
+    sf = mol.surface()
+    raw = sf["owner"].cpu().numpy().astype(np.int64) * om.nsph + sf["sph"].cpu().numpy()
+    assert np.array_equal(raw, om.keep_idx)
+    got, ref = mol.pair_list(0), om.pairs()
+    for k in ("cls", "a", "b", "i", "j"):
+        assert np.array_equal(got[k], ref[k]), k
+    mol.esp(P)
+    got, ref = mol.pair_list(1), om.pairs(s.P)
+    for k in ("cls", "a", "b", "i", "j"):
+        assert np.array_equal(got[k], ref[k]), k
+
+
+def test_big_esp_sampled(big):
+    s, ctx, mol, om, P = big
+    c, bz = mol.esp(P)
+    rng = np.random.default_rng(s.seeds["pert"])
+    kidx = np.sort(rng.choice(mol.M, 24, replace=False))
+    c_or = om.esp(s.P, kidx=kidx)
+    c_h = c.cpu().numpy()[kidx]
+    assert np.abs(c_h - c_or).max() <= 1e-10 * np.abs(c_or).max()
+    bz_or = om.bz()
+    assert np.abs(bz.cpu().numpy() - bz_or).max() <= 1e-12 * np.abs(bz_or).max()
+
+
+def test_big_fock_sampled(big, torch_cuda):
+    s, ctx, mol, om, P = big
+    rng = np.random.default_rng(7)
+    qh = rng.normal(size=mol.M) * 1e-2
+    F = mol.fock(torch_cuda.tensor(qh, dtype=torch_cuda.float64, device="cuda")).cpu().numpy()
+    pl = mol.pair_list(0)
+    # a few shell pairs of every class that is present
+    sel = []
+    for c in range(6):
+        idx = np.nonzero(pl["cls"] == c)[0]
+        if idx.size:
+            for t in rng.choice(idx, min(4, idx.size), replace=False):
+                sel.append((int(pl["a"][t]), int(pl["b"][t])))
+    Fr = om.fock(qh, shell_pairs=sel)
+    for a, b in sel:
+        ra = slice(om.bf_off[a], om.bf_off[a] + (om.sl[a] + 1) * (om.sl[a] + 2) // 2)
+        rb = slice(om.bf_off[b], om.bf_off[b] + (om.sl[b] + 1) * (om.sl[b] + 2) // 2)
+        ref = Fr[ra, rb]
+        assert np.abs(F[ra, rb] - ref).max() <= 1e-10 * max(np.abs(ref).max(), 1e-12), (a, b)
+        assert np.array_equal(F[rb, ra], F[ra, rb].T) or a == b
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_big_solve_residual_rows(big, torch_cuda, precision):
+    s, ctx, mol, om, P = big
+    c, bz = mol.esp(P)
+    v = bz + c
+    q, info = mol.solve(v, precond="rbj", block=100, seed=s.seeds["rbj"], tol=1e-8, precision=precision)
+    assert info["resid"] < 1e-8
+    qh, vh = q.cpu().numpy(), v.cpu().numpy()
+    rng = np.random.default_rng(11)
+    kidx = np.sort(rng.choice(mol.M, 64, replace=False))
+    Aq = om.matvec(qh, kidx=kidx)
+    r = Aq + om.f * vh[kidx]
+    assert np.abs(r).max() < 1e-8
+    E = 0.5 * float(vh @ qh)
+    assert abs(info["energy"] - E) <= 1e-6 * abs(E)
+
+
+# ------------------------------------------------------------------ gradient path
+
+@pytest.fixture(scope="module")
+def pep(torch_cuda):
+    from paper_1505_07851_amd import Context, Molecule
+    print("\n[case peptide300]", flush=True)
+    s = I.gradient_path()
+    ctx = Context()
+    mol = Molecule.from_system(ctx, s)
+    P = torch_cuda.tensor(s.P, dtype=torch_cuda.float64, device="cuda")
+    return s, ctx, mol, P
+
+
+def _energy(mol, P, xyz, r_surf=None, tol=1e-10):
+    mol.update_geometry(xyz, r_surf)
+    c, bz = mol.esp(P)
+    q, info = mol.solve(bz + c, precond="rbj", block=100, seed=404, tol=tol)
+    return info["energy"]
+
+
+def test_autograd_and_fd(pep, torch_cuda):
+    from paper_1505_07851_amd import PCMEnergy
+    s, ctx, mol, P = pep
+    torch = torch_cuda
+    sf = mol.surface()
+    r0 = sf["r"].cpu().numpy()
+    R = torch.tensor(s.xyz, dtype=torch.float64, requires_grad=True)
+    rs = torch.tensor(r0, dtype=torch.float64, requires_grad=True)
+    Pg = P.clone().requires_grad_(True)
+    E = PCMEnergy.apply(Pg, R, rs, mol, {"precond": "rbj", "block": 100, "seed": 404, "tol": 1e-10})
+    E.backward()
+    # dE/dP is the Fock correction, bitwise (same geometry, deterministic kernels -> same q)
+    c, bz = mol.esp(P)
+    q, _ = mol.solve(bz + c, precond="rbj", block=100, seed=404, tol=1e-10)
+    F = mol.fock(q)
+    assert torch.equal(Pg.grad, F)
+    gn, gs = R.grad.numpy(), rs.grad.numpy()
+    # translation invariance
+    tot = gn.sum(0) + gs.sum(0)
+    assert np.abs(tot).max() <= 1e-10 * (np.abs(gn).sum() + np.abs(gs).sum())
+    # central differences: 10 nuclear coordinates (points held fixed) and 10 surface coordinates
+    rng = np.random.default_rng(405)
+    h = 1e-4
+    for I_ in rng.choice(s.n_atoms, 10, replace=False):
+        d = int(rng.integers(3))
+        xp = s.xyz.copy(); xp[I_, d] += h
+        xm = s.xyz.copy(); xm[I_, d] -= h
+        fd = (_energy(mol, P, xp, r0) - _energy(mol, P, xm, r0)) / (2 * h)
+        assert abs(fd - gn[I_, d]) <= max(1e-7, 1e-5 * abs(gn[I_, d])), ("nuc", I_, d, fd, gn[I_, d])
+    for k in rng.choice(mol.M, 10, replace=False):
+        d = int(rng.integers(3))
+        rp = r0.copy(); rp[k, d] += h
+        rm = r0.copy(); rm[k, d] -= h
+        fd = (_energy(mol, P, s.xyz, rp) - _energy(mol, P, s.xyz, rm)) / (2 * h)
+        assert abs(fd - gs[k, d]) <= max(1e-7, 1e-5 * abs(gs[k, d])), ("surf", k, d, fd, gs[k, d])
+    mol.update_geometry(s.xyz)
+
+
+def test_gradient_sampled_vs_oracle(pep, torch_cuda):
+    s, ctx, mol, P = pep
+    mol.update_geometry(s.xyz)
+    c, bz = mol.esp(P)
+    q, info = mol.solve(bz + c, precond="rbj", block=100, seed=404, tol=1e-10)
+    gn, gs = mol.grad(P, q)
+    om = O.mol_from_system(s)
+    rng = np.random.default_rng(406)
+    kidx = np.sort(rng.choice(mol.M, 6, replace=False))
+    ref = om.grad_surface_points(s.P, q.cpu().numpy(), kidx)
+    got = gs.cpu().numpy()[kidx]
+    assert np.abs(got - ref).max() <= 1e-8 * max(1.0, np.abs(ref).max())
+
+
+def test_mixed_gradient_error_statement(pep, torch_cuda):
+    from paper_1505_07851_amd import Context, Molecule
+    s, ctx, mol, P = pep
+    mol.update_geometry(s.xyz)
+    c, bz = mol.esp(P)
+    q, info = mol.solve(bz + c, precond="rbj", block=100, seed=404, tol=1e-10)
+    gn, gs = mol.grad(P, q)
+    cm = Context(precision="mixed")
+    mm = Molecule.from_system(cm, s)
+    c2, bz2 = mm.esp(P)
+    q2, info2 = mm.solve(bz2 + c2, precond="rbj", block=100, seed=404, tol=1e-10, precision="mixed")
+    gn2, gs2 = mm.grad(P, q2)
+    err = {"E_abs": abs(info2["energy"] - info["energy"]),
+           "g_nuc_abs": (gn2 - gn).abs().max().item(), "g_surf_abs": (gs2 - gs).abs().max().item()}
+    print("mixed vs FP64 (300 atoms):", {k: f"{v:.2e}" for k, v in err.items()}, flush=True)
+    assert err["E_abs"] <= 5e-5 and err["g_nuc_abs"] <= 5e-5 and err["g_surf_abs"] <= 5e-5
