@@ -70,7 +70,9 @@ def flop_model():
         b1 = 12 + 2 * (L + 1) + H[L + 1]
         m[f"grad_pts_L{L}"] = b1 + 3 * 2 * ntuv(L) + 3
         m[f"grad_v_L{L}"] = b1 + 2 * ntuv(L + 1)
-    m["matvec"] = 14   # d (3), r^2 (5), far test (3), 1/sqrt (1), FMA (2)
+    # per unordered point pair (A is symmetric and each pair is evaluated once): d (3), r^2 (5),
+    # far test (1), 1/sqrt (1), row FMA (2), column product (1), column sum (1)
+    m["matvec"] = 14
     m["grad_aoff"] = 23
     return m
 

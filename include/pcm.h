@@ -56,6 +56,7 @@ enum { PCM_PRECOND_NONE = 0, PCM_PRECOND_JACOBI = 1, PCM_PRECOND_RBJ = 2 };
 
 typedef struct pcm_ctx pcm_ctx;
 typedef struct pcm_mol pcm_mol;
+typedef struct pcm_batch pcm_batch;
 
 /* Model parameters (Sec. 2 and Sec. 3).
  *   eps            dielectric constant; f = (eps-1)/(eps+k_factor) (Eq. 1). Default 78.39.
@@ -99,7 +100,9 @@ typedef struct {
  *   warm_start  nonzero: q holds the initial guess on entry; zero: start from q = 0
  *   precision   PCM_FP64 (FP64 matvec) or PCM_MIXED (FP32 matvec inside FP64
  *               iterative refinement; FP64 residual, dots and energy)
- *   inner_rtol  relative residual reduction of each inner FP32 solve (mixed only; 0: 1e-4) */
+ *   inner_rtol  relative residual reduction of each inner FP32 solve (mixed only; 0: 1e-4);
+ *               an inner solve also stops after 400 iterations, and the outer FP64
+ *               residual restarts it */
 typedef struct {
     int precond;
     int block;
@@ -214,13 +217,29 @@ pcm_status pcm_pair_list(pcm_ctx *ctx, const pcm_mol *mol, int which, int *cls, 
 
 void pcm_mol_destroy(pcm_mol *mol);
 
+/* Batches: several molecules (e.g. conformers with uneven surface sizes) whose kernels run
+ * as one launch over a shared table of work items, with per-molecule scalars, iteration
+ * counters and convergence flags kept on the device.  pcm_batch_create records the HOST
+ * array mols[n] (n >= 1, distinct molecules built on ctx); the batch holds no reference
+ * count, so destroy it before any of its molecules.  Errors: PCM_E_ARG. */
+pcm_status pcm_batch_create(pcm_ctx *ctx, pcm_mol *const *mols, int n, pcm_batch **out);
+void pcm_batch_destroy(pcm_batch *batch);
+
+/* pcm_solve for every molecule of the batch at once (Sec. 2, Eq. 1; Sec. 4b).  HOST arrays
+ * of DEVICE pointers v[n] and q[n] (molecule i: v[i][M_i], q[i][M_i]); HOST info[n] (may be
+ * NULL).  Groups of PCG iterations are replayed from a captured hipGraph; molecules that
+ * have converged skip the remaining work of their group, so every molecule receives the
+ * iterates it would get alone.  PCM_E_NOCONV when any molecule reached max_iter. */
+pcm_status pcm_solve_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *v, const pcm_solve_opts *opts,
+                             double *const *q, pcm_solve_info *info);
+
 /* Per-kernel timing.  pcm_profile_enable(ctx, 1) clears previous records and makes every
  * heavy launch (integral, matvec, gradient and preconditioner kernels) record a pair of HIP
  * events on the context's stream; pcm_profile_collect synchronises the stream, aggregates
  * the records by kernel name and returns the number of names (-1 on error);
  * pcm_profile_entry(i) reports name (HOST buffer of name_cap bytes), total milliseconds,
- * number of launches and work units (pair x point evaluations for integral kernels, matrix
- * elements for matvec and preconditioner kernels).  Profiling adds two event records per
+ * number of launches and work units (pair x point evaluations for integral kernels,
+ * unordered point pairs for the matvec, inverse-block elements for the preconditioner).  Profiling adds two event records per
  * launch and is off by default. */
 pcm_status pcm_profile_enable(pcm_ctx *ctx, int on);
 int pcm_profile_collect(pcm_ctx *ctx);

@@ -7,7 +7,7 @@ from ._lib import lib as _load_lib
 
 _load_lib()
 
-from .api import Context, Molecule, PCMError, dynamic_threshold, rbj_partition  # noqa: E402
+from .api import Batch, Context, Molecule, PCMError, dynamic_threshold, rbj_partition  # noqa: E402
 from .autograd import PCMEnergy, pcm_energy  # noqa: E402
 
-__all__ = ["Context", "Molecule", "PCMError", "PCMEnergy", "dynamic_threshold", "pcm_energy", "rbj_partition"]
+__all__ = ["Batch", "Context", "Molecule", "PCMError", "PCMEnergy", "dynamic_threshold", "pcm_energy", "rbj_partition"]

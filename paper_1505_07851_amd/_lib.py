@@ -19,7 +19,8 @@ PCM_PRECOND_NONE, PCM_PRECOND_JACOBI, PCM_PRECOND_RBJ = 0, 1, 2
 EXPORTED = ["pcm_default_params", "pcm_default_solve_opts", "pcm_create", "pcm_destroy", "pcm_last_error",
             "pcm_build_surface", "pcm_update_geometry", "pcm_esp", "pcm_fock", "pcm_solve", "pcm_energy", "pcm_grad",
             "pcm_dynamic_threshold", "pcm_rbj_partition", "pcm_surface_get", "pcm_mol_sizes", "pcm_pair_list",
-            "pcm_mol_destroy", "pcm_profile_enable", "pcm_profile_collect", "pcm_profile_entry"]
+            "pcm_mol_destroy", "pcm_batch_create", "pcm_batch_destroy", "pcm_solve_batched",
+            "pcm_profile_enable", "pcm_profile_collect", "pcm_profile_entry"]
 
 
 class pcm_params(ctypes.Structure):
@@ -71,6 +72,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "pcm_mol_sizes": (i, [vp, P(i), P(i), P(i), vp, vp, vp, vp]),
         "pcm_pair_list": (i, [vp, vp, i, vp, vp, vp, vp, vp]),
         "pcm_mol_destroy": (None, [vp]),
+        "pcm_batch_create": (i, [vp, P(vp), i, P(vp)]),
+        "pcm_batch_destroy": (None, [vp]),
+        "pcm_solve_batched": (i, [vp, vp, P(vp), P(pcm_solve_opts), P(vp), P(pcm_solve_info)]),
         "pcm_profile_enable": (i, [vp, i]),
         "pcm_profile_collect": (i, [vp]),
         "pcm_profile_entry": (i, [vp, i, ctypes.c_char_p, i, P(d), P(ctypes.c_longlong), P(d)]),

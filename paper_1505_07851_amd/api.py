@@ -204,12 +204,7 @@ class Molecule:
               precision="fp64", inner_rtol=1e-4, q=None, raise_noconv=True):
         """q solving A q = -f v (Eq. 1); returns (q, info dict)."""
         v = _f64(v, self.M, "v").contiguous()
-        o = C.pcm_solve_opts()
-        self.ctx.lib.pcm_default_solve_opts(ctypes.byref(o))
-        o.precond = {"none": C.PCM_PRECOND_NONE, "jacobi": C.PCM_PRECOND_JACOBI, "rbj": C.PCM_PRECOND_RBJ}[precond]
-        o.block, o.seed, o.tol, o.max_iter = int(block), int(seed), float(tol), int(max_iter)
-        o.precision = C.PCM_MIXED if precision == "mixed" else C.PCM_FP64
-        o.inner_rtol = float(inner_rtol)
+        o = _solve_opts(self.ctx.lib, precond, block, seed, tol, max_iter, precision, inner_rtol)
         if q is None:
             q = self._zeros(self.M)
         if q0 is not None:
@@ -217,8 +212,7 @@ class Molecule:
             o.warm_start = 1
         info = C.pcm_solve_info()
         st = self.ctx.lib.pcm_solve(self.ctx.h, self.h, _dp(v), ctypes.byref(o), _dp(q), ctypes.byref(info))
-        res = {"iters": info.iters, "refinements": info.refinements, "resid": info.resid, "energy": info.energy,
-               "setup_ms": info.setup_ms, "solve_ms": info.solve_ms, "status": st}
+        res = _info_dict(info, st)
         if st != C.PCM_OK and (raise_noconv or st != C.PCM_E_NOCONV):
             self.ctx.check(st)
         return q, res
@@ -251,6 +245,70 @@ class Molecule:
             pass
 
 
+def _solve_opts(lib, precond, block, seed, tol, max_iter, precision, inner_rtol):
+    o = C.pcm_solve_opts()
+    lib.pcm_default_solve_opts(ctypes.byref(o))
+    o.precond = {"none": C.PCM_PRECOND_NONE, "jacobi": C.PCM_PRECOND_JACOBI, "rbj": C.PCM_PRECOND_RBJ}[precond]
+    o.block, o.seed, o.tol, o.max_iter = int(block), int(seed), float(tol), int(max_iter)
+    o.precision = C.PCM_MIXED if precision == "mixed" else C.PCM_FP64
+    o.inner_rtol = float(inner_rtol)
+    return o
+
+
+def _info_dict(info, st):
+    return {"iters": info.iters, "refinements": info.refinements, "resid": info.resid, "energy": info.energy,
+            "setup_ms": info.setup_ms, "solve_ms": info.solve_ms, "status": st}
+
+
+class Batch:
+    """Molecules whose kernels run as one launch over a shared work table (pcm_batch_*).
+
+    Destroy (close) the batch before its molecules."""
+
+    def __init__(self, ctx: Context, mols):
+        self.ctx = ctx
+        self.mols = list(mols)
+        n = len(self.mols)
+        arr = (ctypes.c_void_p * n)(*[m.h for m in self.mols])
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.pcm_batch_create(ctx.h, arr, n, ctypes.byref(h)))
+        self.h = h
+
+    def solve(self, vs, precond="jacobi", block=100, seed=0, tol=1e-6, max_iter=10000, q0s=None,
+              precision="fp64", inner_rtol=1e-4, qs=None, raise_noconv=True):
+        """Solve A_i q_i = -f v_i for every molecule; returns (list of q, list of info dicts)."""
+        n = len(self.mols)
+        if len(vs) != n:
+            raise ValueError(f"expected {n} right-hand sides")
+        vs = [_f64(v, m.M, "v").contiguous() for v, m in zip(vs, self.mols)]
+        o = _solve_opts(self.ctx.lib, precond, block, seed, tol, max_iter, precision, inner_rtol)
+        if qs is None:
+            qs = [m._zeros(m.M) for m in self.mols]
+        if q0s is not None:
+            for q, q0 in zip(qs, q0s):
+                q.copy_(q0)
+            o.warm_start = 1
+        va = (ctypes.c_void_p * n)(*[_dp(v) for v in vs])
+        qa = (ctypes.c_void_p * n)(*[_dp(q) for q in qs])
+        infos = (C.pcm_solve_info * n)()
+        st = self.ctx.lib.pcm_solve_batched(self.ctx.h, self.h, va, ctypes.byref(o), qa, infos)
+        res = [_info_dict(infos[i], st) for i in range(n)]
+        if st != C.PCM_OK and (raise_noconv or st != C.PCM_E_NOCONV):
+            self.ctx.check(st)
+        return qs, res
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.pcm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def dynamic_threshold(e_prev: float) -> float:
     """Eq. 21 schedule (pure host)."""
     return C.lib().pcm_dynamic_threshold(float(-1.0 if e_prev is None else e_prev))
@@ -273,4 +331,4 @@ def default_f(eps=78.39, k=0.0):
     return (eps - 1.0) / (eps + k)
 
 
-__all__ = ["Context", "Molecule", "PCMError", "dynamic_threshold", "rbj_partition", "math"]
+__all__ = ["Context", "Molecule", "Batch", "PCMError", "dynamic_threshold", "rbj_partition", "math"]

@@ -42,15 +42,18 @@ void release_list(PairList &pl) {
 
 void release_mol(pcm_mol *m) {
     DevBuf<double> *dbl[] = {&m->xyz, &m->Z, &m->rad, &m->dirs, &m->w, &m->pexp, &m->pcoef, &m->cn, &m->px, &m->py,
-                             &m->pz, &m->zeta, &m->S, &m->Akk, &m->qpad, &m->part, &m->part2, &m->vbuf,
-                             &m->fprim, &m->gpair, &m->gsp, &m->sv, &m->hist, &m->rbj_inv};
+                             &m->pz, &m->zeta, &m->S, &m->Akk, &m->qpad, &m->part, &m->vbuf,
+                             &m->fprim, &m->gpair, &m->gsp, &m->sv, &m->rbj_inv};
     for (auto *b : dbl) b->release();
     DevBuf<int> *ints[] = {&m->sl, &m->snp, &m->soff, &m->satom, &m->bfo, &m->cnoff, &m->keep, &m->spa, &m->spb,
                            &m->atom_sp_off_a, &m->atom_sp_a, &m->atom_sp_off_b, &m->atom_sp_b, &m->scan_tmp,
-                           &m->rbj_perm, &m->rbj_off, &m->rbj_inv_off};
+                           &m->rbj_perm, &m->rbj_off};
     for (auto *b : ints) b->release();
+    m->rbj_ioff.release();
     m->pti64.release();
     m->pti32.release();
+    if (m->solo) solve_batch_free(m->solo);
+    m->solo = nullptr;
     release_list(m->fock);
     release_list(m->esp);
 }
@@ -126,7 +129,26 @@ pcm_status check_basis(pcm_ctx *ctx, int n_atoms, const pcm_basis *b, int *nprim
     return PCM_OK;
 }
 
+pcm_status check_solve_opts(pcm_ctx *ctx, const pcm_solve_opts *opts, pcm_solve_opts &o) {
+    pcm_default_solve_opts(&o);
+    if (opts) o = *opts;
+    if (o.precond < PCM_PRECOND_NONE || o.precond > PCM_PRECOND_RBJ) return fail(ctx, PCM_E_ARG, "bad precond");
+    if (o.precond == PCM_PRECOND_RBJ && (o.block < 1 || o.block > 1024))
+        return fail(ctx, PCM_E_ARG, "RBJ block size must be in [1, 1024]");
+    if (!is_fin(o.tol) || !(o.tol > 0.0)) return fail(ctx, PCM_E_ARG, "tol must be > 0");
+    if (o.max_iter < 1) return fail(ctx, PCM_E_ARG, "max_iter must be >= 1");
+    if (o.precision != PCM_FP64 && o.precision != PCM_MIXED) return fail(ctx, PCM_E_ARG, "bad precision");
+    if (!is_fin(o.inner_rtol) || o.inner_rtol < 0.0 || o.inner_rtol >= 1.0)
+        return fail(ctx, PCM_E_ARG, "inner_rtol must be in [0, 1)");
+    return PCM_OK;
+}
+
 }  // namespace
+
+struct pcm_batch {
+    std::vector<pcm_mol *> mols;
+    SolveBatch *solve = nullptr;
+};
 
 extern "C" {
 
@@ -208,6 +230,7 @@ pcm_status pcm_build_surface(pcm_ctx *ctx, int n_atoms, const double *xyz, const
     if (st != PCM_OK) return st;
     pcm_mol *m = new (std::nothrow) pcm_mol();
     if (!m) return fail(ctx, PCM_E_ALLOC, "host allocation failed");
+    m->owner_ctx = ctx;
     st = guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         m->N = n_atoms;
@@ -330,16 +353,8 @@ pcm_status pcm_solve(pcm_ctx *ctx, pcm_mol *mol, const double *v, const pcm_solv
     if (!ctx) return PCM_E_ARG;
     if (!mol || !v || !q) return fail(ctx, PCM_E_ARG, "NULL argument");
     pcm_solve_opts o;
-    pcm_default_solve_opts(&o);
-    if (opts) o = *opts;
-    if (o.precond < PCM_PRECOND_NONE || o.precond > PCM_PRECOND_RBJ) return fail(ctx, PCM_E_ARG, "bad precond");
-    if (o.precond == PCM_PRECOND_RBJ && (o.block < 1 || o.block > 1024))
-        return fail(ctx, PCM_E_ARG, "RBJ block size must be in [1, 1024]");
-    if (!is_fin(o.tol) || !(o.tol > 0.0)) return fail(ctx, PCM_E_ARG, "tol must be > 0");
-    if (o.max_iter < 1) return fail(ctx, PCM_E_ARG, "max_iter must be >= 1");
-    if (o.precision != PCM_FP64 && o.precision != PCM_MIXED) return fail(ctx, PCM_E_ARG, "bad precision");
-    if (!is_fin(o.inner_rtol) || o.inner_rtol < 0.0 || o.inner_rtol >= 1.0)
-        return fail(ctx, PCM_E_ARG, "inner_rtol must be in [0, 1)");
+    pcm_status vs = check_solve_opts(ctx, opts, o);
+    if (vs != PCM_OK) return vs;
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         pcm_status st = run_solve(ctx, mol, v, o, q, info);
@@ -511,6 +526,53 @@ void pcm_mol_destroy(pcm_mol *mol) {
     if (!mol) return;
     release_mol(mol);
     delete mol;
+}
+
+pcm_status pcm_batch_create(pcm_ctx *ctx, pcm_mol *const *mols, int n, pcm_batch **out) {
+    if (!ctx) return PCM_E_ARG;
+    if (!out) return fail(ctx, PCM_E_ARG, "NULL out");
+    *out = nullptr;
+    if (!mols || n < 1) return fail(ctx, PCM_E_ARG, "a batch needs n >= 1 molecules");
+    std::vector<pcm_mol *> v(mols, mols + n);
+    for (int i = 0; i < n; ++i) {
+        if (!v[i]) return fail(ctx, PCM_E_ARG, "NULL molecule in batch");
+        if (v[i]->owner_ctx != ctx) return fail(ctx, PCM_E_ARG, "molecule built on another context");
+        for (int j = 0; j < i; ++j)
+            if (v[j] == v[i]) return fail(ctx, PCM_E_ARG, "molecule listed twice in batch");
+    }
+    return guarded(ctx, [&]() -> pcm_status {
+        pcm_batch *b = new pcm_batch();
+        b->mols = v;
+        b->solve = solve_batch_new(v);
+        *out = b;
+        return PCM_OK;
+    });
+}
+
+void pcm_batch_destroy(pcm_batch *batch) {
+    if (!batch) return;
+    if (batch->solve) solve_batch_free(batch->solve);
+    delete batch;
+}
+
+pcm_status pcm_solve_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *v, const pcm_solve_opts *opts,
+                             double *const *q, pcm_solve_info *info) {
+    if (!ctx) return PCM_E_ARG;
+    if (!batch || !v || !q) return fail(ctx, PCM_E_ARG, "NULL argument");
+    const int n = (int)batch->mols.size();
+    for (int i = 0; i < n; ++i)
+        if (!v[i] || !q[i]) return fail(ctx, PCM_E_ARG, "NULL vector in batch");
+    pcm_solve_opts o;
+    pcm_status vs = check_solve_opts(ctx, opts, o);
+    if (vs != PCM_OK) return vs;
+    return guarded(ctx, [&]() -> pcm_status {
+        ctx_ensure_device(ctx);
+        std::vector<const double *> vv(v, v + n);
+        std::vector<double *> qq(q, q + n);
+        pcm_status st = solve_batch_run(ctx, *batch->solve, vv, qq, o, info);
+        if (st == PCM_E_NOCONV) ctx->err = "max_iter reached before the residual threshold";
+        return st;
+    });
 }
 
 }  // extern "C"

@@ -279,6 +279,8 @@ struct PairList {
     size_t rec_off[NCLS + 1] = {0};   // byte offsets of each class in rec
 };
 
+struct SolveBatch;
+
 struct pcm_mol {
     int N = 0, nsph = 0, M = 0, Mraw = 0;
     double zeta0 = 4.9;
@@ -310,20 +312,20 @@ struct pcm_mol {
     PairList fock, esp;
     bool esp_valid = false;
     // workspaces
-    DevBuf<double> part;   // partial sums (esp / matvec / gradient)
-    DevBuf<double> part2;
+    DevBuf<double> part;   // partial sums (esp / gradient)
     DevBuf<double> vbuf;   // V_tuv partials (fock / grad)
     DevBuf<double> fprim;  // per prim pair Fock blocks
     DevBuf<double> gpair;  // per prim pair gradient contributions
     DevBuf<double> gsp;    // per candidate shell pair gradient sums
     DevBuf<int> scan_tmp;
     // solver
-    DevBuf<double> sv;     // solver vectors
-    DevBuf<double> hist;   // per-iteration CG scalars
+    DevBuf<double> sv;     // solver vectors, packed points
+    SolveBatch *solo = nullptr;  // solver tables of this molecule alone
     DevBuf<double> rbj_inv;
-    DevBuf<int> rbj_perm, rbj_off, rbj_inv_off;
+    DevBuf<int> rbj_perm, rbj_off;
+    DevBuf<long long> rbj_ioff;
     std::vector<int> h_rbj_perm, h_rbj_off;
-    int rbj_l = -1;
+    int rbj_l = -1, rbj_lmax = 0;
     unsigned long long rbj_seed = 0;
     bool rbj_valid = false;
     pcm_ctx *owner_ctx = nullptr;
@@ -334,7 +336,7 @@ struct ProfScope {
     pcm_ctx *c;
     ProfRec r{};
     bool on;
-    ProfScope(pcm_ctx *ctx, const std::string &name, double work) : c(ctx), on(ctx->prof) {
+    ProfScope(pcm_ctx *ctx, const std::string &name, double work) : c(ctx), on(ctx && ctx->prof) {
         if (!on) return;
         r.name = name;
         r.work = work;
@@ -360,14 +362,17 @@ void pairs_prepare_density(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const doubl
 void run_bz(pcm_ctx *ctx, pcm_mol *mol, double *bz);
 void run_esp(pcm_ctx *ctx, pcm_mol *mol, double *c, int prec);
 void run_fock(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F, int prec);
-void run_matvec(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int prec);
 pcm_status run_solve(pcm_ctx *ctx, pcm_mol *mol, const double *v, const pcm_solve_opts &o, double *q,
                      pcm_solve_info *info);
 double run_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double *c, const double *q);
 void run_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc, double *g_surf,
               int prec);
 void surface_points(pcm_ctx *ctx, pcm_mol *mol, const double *r_explicit_dev);
-double dev_dot(pcm_ctx *ctx, pcm_mol *mol, const double *a, const double *b, long long n);
+void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int l, unsigned long long seed);
+SolveBatch *solve_batch_new(const std::vector<pcm_mol *> &mols);
+void solve_batch_free(SolveBatch *b);
+pcm_status solve_batch_run(pcm_ctx *ctx, SolveBatch &B, const std::vector<const double *> &v,
+                           const std::vector<double *> &q, const pcm_solve_opts &o, pcm_solve_info *info);
 int host_rbj_partition(int M, const double *r, const double *zeta, int l, unsigned long long seed, int *perm,
                        int *blk_off);
 

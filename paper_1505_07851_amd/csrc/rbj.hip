@@ -1,0 +1,250 @@
+// Randomized block-Jacobi preconditioner (Sec. 4b-ii): the partition (host), the explicit
+// inverses of the diagonal blocks of the permuted A (device) and their application.
+#include "pcm_internal.h"
+
+#include <algorithm>
+#include <cstdlib>
+#include <numeric>
+
+// ----------------------------------------------------------------------------------------
+// blocks of A gathered by the partition; A_kl from Eqs. 2-3, 8
+// ----------------------------------------------------------------------------------------
+__global__ void k_rbj_fill(const double *__restrict__ px, const double *__restrict__ py,
+                           const double *__restrict__ pz, const double *__restrict__ zeta,
+                           const double *__restrict__ Akk, const int *__restrict__ perm, const int *__restrict__ off,
+                           const long long *__restrict__ ioff, double *__restrict__ blk) {
+    int b = blockIdx.x;
+    int o = off[b], l = off[b + 1] - o;
+    long long e = (long long)blockIdx.y * blockDim.x + threadIdx.x;
+    if (e >= (long long)l * l) return;
+    int i = (int)(e / l), j = (int)(e % l);
+    int ki = perm[o + i], kj = perm[o + j];
+    double v;
+    if (ki == kj) {
+        v = Akk[ki];
+    } else {
+        double dx = px[ki] - px[kj], dy = py[ki] - py[kj], dz = pz[ki] - pz[kj];
+        double d = sqrt(dx * dx + dy * dy + dz * dz);
+        double za = zeta[ki], zc = zeta[kj];
+        double zp = za * zc / sqrt(za * za + zc * zc);
+        v = d == 0.0 ? 1.1283791670955125739 * zp : erf(zp * d) / d;
+    }
+    blk[ioff[b] + e] = v;
+}
+
+// In-place Gauss-Jordan inversion of one SPD block per workgroup (no pivoting needed for SPD);
+// a non-positive pivot flags the block as not positive definite.
+__global__ __launch_bounds__(256) void k_rbj_invert(const int *__restrict__ off, const long long *__restrict__ ioff,
+                                                    double *__restrict__ blk, int *__restrict__ bad) {
+    int b = blockIdx.x;
+    int l = off[b + 1] - off[b];
+    double *A = blk + ioff[b];
+    __shared__ double rowk[1024];
+    __shared__ double colk[1024];
+    __shared__ double piv_s;
+    for (int k = 0; k < l; ++k) {
+        if (threadIdx.x == 0) {
+            piv_s = A[(long long)k * l + k];
+            if (!(piv_s > 0.0)) bad[0] = 1;
+        }
+        __syncthreads();
+        double piv = piv_s;
+        if (!(piv > 0.0)) return;
+        double ip = 1.0 / piv;
+        for (int j = threadIdx.x; j < l; j += blockDim.x) {
+            rowk[j] = A[(long long)k * l + j] * ip;
+            colk[j] = A[(long long)j * l + k];
+        }
+        __syncthreads();
+        // update every element outside row k (rows walked uniformly, columns across lanes)
+        for (int i = 0; i < l; ++i) {
+            if (i == k) continue;
+            const double ci = colk[i];
+            double *Ai = A + (long long)i * l;
+            for (int j = threadIdx.x; j < l; j += blockDim.x) Ai[j] = (j == k) ? -ci * ip : Ai[j] - ci * rowk[j];
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < l; j += blockDim.x) A[(long long)k * l + j] = (j == k) ? ip : rowk[j];
+        __syncthreads();
+    }
+}
+
+void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int l, unsigned long long seed) {
+    if (mol->rbj_valid && mol->rbj_l == l && mol->rbj_seed == seed) return;
+    const int M = mol->M;
+    std::vector<double> r(3 * (size_t)M), px(M), py(M), pz(M), zeta(M);
+    HIP_OK(hipMemcpyAsync(px.data(), mol->px.p, M * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipMemcpyAsync(py.data(), mol->py.p, M * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipMemcpyAsync(pz.data(), mol->pz.p, M * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipMemcpyAsync(zeta.data(), mol->zeta.p, M * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < M; ++k) {
+        r[3 * k] = px[k];
+        r[3 * k + 1] = py[k];
+        r[3 * k + 2] = pz[k];
+    }
+    mol->h_rbj_perm.assign(M, 0);
+    mol->h_rbj_off.assign(M + 1, 0);
+    int nb = host_rbj_partition(M, r.data(), zeta.data(), l, seed, mol->h_rbj_perm.data(), mol->h_rbj_off.data());
+    if (nb <= 0) throw PcmError{PCM_E_ARG, "randomized block-Jacobi partition failed"};
+    mol->h_rbj_off.resize(nb + 1);
+    std::vector<long long> ioff(nb + 1, 0);
+    int lmax = 0;
+    for (int b = 0; b < nb; ++b) {
+        int sz = mol->h_rbj_off[b + 1] - mol->h_rbj_off[b];
+        ioff[b + 1] = ioff[b] + (long long)sz * sz;
+        lmax = std::max(lmax, sz);
+    }
+    if (lmax > 1024) throw PcmError{PCM_E_ARG, "RBJ block size above 1024 is not supported"};
+    mol->rbj_lmax = lmax;
+    mol->rbj_perm.ensure(M);
+    mol->rbj_off.ensure(nb + 1);
+    mol->rbj_ioff.ensure(nb + 1);
+    mol->rbj_inv.ensure(ioff[nb]);
+    HIP_OK(hipMemcpyAsync(mol->rbj_perm.p, mol->h_rbj_perm.data(), M * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    HIP_OK(hipMemcpyAsync(mol->rbj_off.p, mol->h_rbj_off.data(), (nb + 1) * sizeof(int), hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIP_OK(hipMemcpyAsync(mol->rbj_ioff.p, ioff.data(), (nb + 1) * sizeof(long long), hipMemcpyHostToDevice,
+                          ctx->stream));
+    dim3 g1(nb, div_up((long long)lmax * lmax, 256));
+    k_rbj_fill<<<g1, 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p, mol->Akk.p,
+                                            mol->rbj_perm.p, mol->rbj_off.p, mol->rbj_ioff.p, mol->rbj_inv.p);
+    HIP_LAUNCH_OK();
+    HIP_OK(hipMemsetAsync(ctx->iscal.p, 0, sizeof(int), ctx->stream));
+    {
+        ProfScope psi(ctx, "rbj_invert", (double)ioff[nb]);
+        k_rbj_invert<<<nb, 256, 0, ctx->stream>>>(mol->rbj_off.p, mol->rbj_ioff.p, mol->rbj_inv.p, ctx->iscal.p);
+        HIP_LAUNCH_OK();
+    }
+    int bad = 0;
+    HIP_OK(hipMemcpyAsync(&bad, ctx->iscal.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    if (bad) throw PcmError{PCM_E_NOTPD, "a randomized block-Jacobi block is not positive definite"};
+    mol->rbj_l = l;
+    mol->rbj_seed = seed;
+    mol->rbj_valid = true;
+}
+
+// ----------------------------------------------------------------------------------------
+// host partition (Sec. 4b-ii); built with IEEE double and no contraction so that the ranking
+// values are the plain expressions erf(z' d)/d, z' = z_k z_l / sqrt(z_k^2 + z_l^2).  For
+// z' d >= 6 erf rounds to exactly 1 in double precision, so 1/d is the same value.
+// The l-1 best candidates of a pivot are kept in a bounded heap.  Because |A_kl| <= 1/d, a
+// candidate farther than 1/(worst kept value) cannot enter and is rejected from its distance
+// alone; the ranking is a total order (value, then index), so the selected set is the same as
+// a full sort would give.
+// ----------------------------------------------------------------------------------------
+static inline uint64_t splitmix64_next(uint64_t &s) {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ULL);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+#pragma clang fp contract(off)
+static inline double coupling(const double *r, const double *zeta, int k, int l) {
+    double zk = zeta[k], zl = zeta[l];
+    double zp = zk * zl / std::sqrt(zk * zk + zl * zl);
+    double dx = r[3 * k] - r[3 * l], dy = r[3 * k + 1] - r[3 * l + 1], dz = r[3 * k + 2] - r[3 * l + 2];
+    double d = std::sqrt(dx * dx + dy * dy + dz * dz);
+    if (d == 0.0) return 2.0 * zp / std::sqrt(M_PI);
+    double x = zp * d;
+    if (x >= 6.0) return 1.0 / d;
+    return std::erf(x) / d;
+}
+
+int host_rbj_partition(int M, const double *r, const double *zeta, int l, unsigned long long seed, int *perm,
+                       int *blk_off) {
+    if (M <= 0 || l <= 0 || !r || !zeta || !perm || !blk_off) return -1;
+    // unassigned indices: a Fenwick tree over [0, M) answers "k-th unassigned in ascending
+    // order" for the pivot pick; the scan list is compacted lazily
+    std::vector<int> bit(M + 1, 0);
+    for (int i = 1; i <= M; ++i) {
+        bit[i] += 1;
+        int j = i + (i & -i);
+        if (j <= M) bit[j] += bit[i];
+    }
+    int top_pow = 1;
+    while (top_pow * 2 <= M) top_pow *= 2;
+    auto kth = [&](int k) {  // 0-based k-th unassigned index
+        int p0 = 0;
+        for (int step = top_pow; step > 0; step >>= 1)
+            if (p0 + step <= M && bit[p0 + step] <= k) {
+                p0 += step;
+                k -= bit[p0];
+            }
+        return p0;
+    };
+    auto remove = [&](int i) {
+        for (int j = i + 1; j <= M; j += j & -j) bit[j] -= 1;
+    };
+    std::vector<int> left(M);
+    std::iota(left.begin(), left.end(), 0);
+    int n_scan = M;  // entries in left[], some possibly assigned already
+    std::vector<unsigned char> take(M, 0);
+    using Cand = std::pair<double, int>;
+    // heap ordered so that top() is the worst kept candidate (smallest value, then largest index)
+    auto better = [](const Cand &a, const Cand &b) {
+        return a.first > b.first || (a.first == b.first && a.second < b.second);
+    };
+    std::vector<Cand> heap;
+    heap.reserve(std::min(l, M) + 1);
+    uint64_t st = seed;
+    int n_left = M, nb = 0, filled = 0;
+    blk_off[0] = 0;
+    while (n_left > 0) {
+        uint64_t x = splitmix64_next(st);
+        double u = (double)(x >> 11) * (1.0 / 9007199254740992.0);
+        int pos = (int)std::floor(u * (double)n_left);
+        if (pos >= n_left) pos = n_left - 1;
+        const int piv = kth(pos);
+        const int want = std::min(l - 1, n_left - 1);
+        heap.clear();
+        if (want > 0) {
+            if (n_scan > 2 * n_left) {  // drop assigned entries before scanning
+                int w = 0;
+                for (int t = 0; t < n_scan; ++t)
+                    if (!take[left[t]]) left[w++] = left[t];
+                n_scan = w;
+            }
+            const double px = r[3 * piv], py = r[3 * piv + 1], pz = r[3 * piv + 2];
+            double reject_d2 = 1e300;  // candidates with d^2 above this cannot enter the heap
+            for (int t = 0; t < n_scan; ++t) {
+                const int q = left[t];
+                if (q == piv || take[q]) continue;
+                const double dx = px - r[3 * q], dy = py - r[3 * q + 1], dz = pz - r[3 * q + 2];
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                if ((int)heap.size() == want && d2 > reject_d2) continue;  // |A| <= 1/d < worst kept
+                Cand c(std::fabs(coupling(r, zeta, piv, q)), q);
+                if ((int)heap.size() < want) {
+                    heap.push_back(c);
+                    std::push_heap(heap.begin(), heap.end(), better);
+                } else if (better(c, heap.front())) {
+                    std::pop_heap(heap.begin(), heap.end(), better);
+                    heap.back() = c;
+                    std::push_heap(heap.begin(), heap.end(), better);
+                } else {
+                    continue;
+                }
+                if ((int)heap.size() == want) {
+                    const double w = heap.front().first;
+                    // |A| <= 1/d: reject when d^2 w^2 > 1 (with a relative margin far above rounding)
+                    reject_d2 = w > 0.0 ? (1.0 + 1e-9) / (w * w) : 1e300;
+                }
+            }
+        }
+        int start = filled;
+        perm[filled++] = piv;
+        take[piv] = 1;
+        remove(piv);
+        for (const Cand &c : heap) {
+            perm[filled++] = c.second;
+            take[c.second] = 1;
+            remove(c.second);
+        }
+        std::sort(perm + start, perm + filled);
+        n_left -= filled - start;
+        blk_off[++nb] = filled;
+    }
+    return nb;
+}

@@ -1,62 +1,83 @@
-// Linear solve of Sec. 2, Eq. 1 (A q = -f (Bz + c)) on gfx950.
+// Linear solve of Sec. 2, Eq. 1 (A q = -f (Bz + c)) on gfx950, for one molecule or a batch.
 //
 //  * A x is applied matrix-free (A is never stored): A_kl = erf(zeta'_kl r)/r (Eqs. 2, 8) for
-//    k != l, A_kk from Eq. 3.  One lane per row k; the wave walks a chunk of columns l whose
-//    data are wave-uniform.  erf(zeta' r) rounds to 1 once zeta' r >= 6 (FP64) / 4 (FP32):
-//    those pairs take the plain 1/r branch, tested with zeta'^2 >= min(zeta_k^2, zeta_l^2)/2.
+//    k != l, A_kk from Eq. 3.  A is symmetric, so the off-diagonal part is swept over the
+//    upper triangle of 256 x 256 point tiles: one workgroup takes the tile pair (I, J), J >= I,
+//    one lane per row of I, columns of J wave-uniform.  Each evaluated A_kl feeds the row sum
+//    of k and (off-diagonal tiles) the column sum of l, reduced across each 16-lane row by a
+//    fixed DPP butterfly and across rows through LDS.  Every (tile, row) partial is written to its own slot and the slots are summed
+//    in fixed order: results are bitwise reproducible and independent of the launch grid.
+//  * erf(zeta' r) rounds to 1 once zeta' r >= 6 (FP64) / 4 (FP32): those pairs take the plain
+//    1/r branch, tested with zeta'^2 >= min(zeta_k^2, zeta_l^2)/2.
 //  * Preconditioned CG (Sec. 4b) with the residual test ||A q - b||_2 < delta (Eq. 20);
-//    Jacobi or randomized block-Jacobi (Sec. 4b-ii) preconditioners; the block inverses are
-//    built on the device and applied as a batched GEMV (HBM-bound).
+//    Jacobi or randomized block-Jacobi (Sec. 4b-ii) preconditioners.
 //  * Mixed precision: FP32 matvec inside FP64 iterative refinement; FP64 vectors, dots and
 //    the outer residual.
-//  * Every reduction is a fixed-order tree: results are bitwise reproducible.
+//  * Batching: every kernel walks a table of work items over a set of molecules; scalars,
+//    iteration counters and convergence flags live on the device, per molecule, so groups of
+//    iterations run without host round trips and are replayed from a captured hipGraph.
 #include "pcm_internal.h"
 
 #include <algorithm>
 #include <chrono>
-#include <cstdlib>
-#include <condition_variable>
-#include <functional>
-#include <mutex>
-#include <numeric>
-#include <thread>
+#include <map>
 
-constexpr int MV_T = 256;
-constexpr int MV_B = 8;  // columns per batch of wave-uniform loads
+constexpr int TILE = 256;  // points per tile (rows per workgroup)
+constexpr int MV_B = 8;    // columns per batch of wave-uniform loads
+constexpr int GROUP_K = 8; // PCG iterations per launch group (even: scalar slots alternate)
+// Bound on each inner FP32 solve of the refinement: FP32 rounding can stall the inner
+// residual above its target on ill-conditioned systems; the outer FP64 residual then restarts.
+constexpr int INNER_MAX_IT = 400;
 
-// ----------------------------------------------------------------------------------------
-// matrix-free off-diagonal product, partial over a chunk of columns.  Point arrays are
-// padded to a multiple of 64 with far-away dummy points whose x entries are zero, so the
-// column loop runs over whole batches of 8.
-// ----------------------------------------------------------------------------------------
 template <typename T> struct Pt {
     T x, y, z, zeta;
 };
 
-inline int mv_pad(int M) { return (M + 63) & ~63; }
+inline int sv_pad(int M) { return (M + TILE - 1) / TILE * TILE; }
 
-__global__ void k_pack_pts(const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz,
-                           const double *__restrict__ zeta, int M, int Mp, Pt<double> *__restrict__ p64,
-                           Pt<float> *__restrict__ p32, double *__restrict__ x64, float *__restrict__ x32) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= Mp) return;
-    if (k < M) {
-        p64[k] = Pt<double>{px[k], py[k], pz[k], zeta[k]};
-        p32[k] = Pt<float>{(float)px[k], (float)py[k], (float)pz[k], (float)zeta[k]};
-    } else {
-        p64[k] = Pt<double>{1e6, 1e6, 1e6, 1.0};
-        p32[k] = Pt<float>{1e6f, 1e6f, 1e6f, 1.0f};
-        x64[k] = 0.0;
-        x32[k] = 0.0f;
-    }
-}
+// solver vectors of one molecule, each [Mp] with zero tails
+enum SolverVec { V_XQ, V_B, V_V, V_RES, V_D, V_R, V_Z, V_P, V_AP, V_Y, V_T, NVEC };
 
-template <typename T>
-__global__ void k_pad_x(const double *__restrict__ x, T *__restrict__ y, int M) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < M) y[k] = (T)x[k];
-}
+// per-molecule view used by every solver kernel
+struct CGMol {
+    double *v[NVEC];
+    float *p32;               // FP32 copy of the search direction (mixed matvec source)
+    const Pt<double> *pt64;   // packed points [Mp]; far dummies past M
+    const Pt<float> *pt32;
+    const double *Akk;
+    double *part;             // [nT][M] matvec partials, slot = the other tile of the pair
+    double *dp;               // [3][ndp] reduction partials: 0 p.Ap / residual, 1 r.r, 2 r.z
+    const int *perm, *boff;   // RBJ partition (null without RBJ)
+    const long long *ioff;
+    const double *inv;
+    double rc2_64;
+    float rc2_32;
+    int M, Mp, nT, ndp, n_rz, precond;
+};
 
+// per-molecule device state
+struct CGState {
+    double rz[2];   // r.z of the last two iterations (slot = iteration parity)
+    double rr;      // r.r after the last iteration
+    double res2;    // ||b - A x||^2 of the last explicit residual
+    double tol;     // stop when sqrt(rr) < tol
+    double dots[3];
+    int it, max_it, done, act;
+};
+
+struct MvItem {
+    int mol, I, J;
+};
+struct TileItem {
+    int mol, t;
+};
+struct RbjItem {
+    int mol, blk, i0, slot;
+};
+
+// ----------------------------------------------------------------------------------------
+// device helpers
+// ----------------------------------------------------------------------------------------
 __device__ __forceinline__ double erf_t(double x) { return erf(x); }
 __device__ __forceinline__ float erf_t(float x) { return erff(x); }
 
@@ -70,112 +91,426 @@ __device__ __attribute__((noinline)) T mv_near(T zk, T zl, T r2, bool self) {
     return erf_t(zp * r) / r;
 }
 
-template <typename T>
-__global__ __launch_bounds__(MV_T) void k_matvec(const Pt<T> *__restrict__ pts, const T *__restrict__ xv, int M,
-                                                 int ncol, int chunk_len, T rc2, double *__restrict__ part) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int kk = k < M ? k : M - 1;
-    const Pt<T> me = pts[kk];
-    const int l0 = blockIdx.y * chunk_len;
-    const int l1 = min(ncol, l0 + chunk_len);
-    T acc = T(0);
-    for (int l = l0; l < l1; l += MV_B) {
-        Pt<T> o[MV_B];
-        T xl[MV_B], a[MV_B], r2[MV_B];
-#pragma unroll
-        for (int u = 0; u < MV_B; ++u) {
-            o[u] = pts[l + u];
-            xl[u] = xv[l + u];
-        }
-        bool near = false;
-#pragma unroll
-        for (int u = 0; u < MV_B; ++u) {
-            T dx = me.x - o[u].x, dy = me.y - o[u].y, dz = me.z - o[u].z;
-            r2[u] = fma(dx, dx, fma(dy, dy, dz * dz));
-            near |= r2[u] < rc2;
-            a[u] = rsq_fast(r2[u]);
-        }
-        if (near) {
-#pragma unroll
-            for (int u = 0; u < MV_B; ++u)
-                if (r2[u] < rc2) a[u] = mv_near<T>(me.zeta, o[u].zeta, r2[u], l + u == kk);
-        }
-#pragma unroll
-        for (int u = 0; u < MV_B; ++u) acc = fma(a[u], xl[u], acc);
+template <typename T> __device__ __forceinline__ const Pt<T> *mv_pts(const CGMol &m);
+template <> __device__ __forceinline__ const Pt<double> *mv_pts<double>(const CGMol &m) { return m.pt64; }
+template <> __device__ __forceinline__ const Pt<float> *mv_pts<float>(const CGMol &m) { return m.pt32; }
+template <typename T> __device__ __forceinline__ const T *mv_src(const CGMol &m, int src);
+template <> __device__ __forceinline__ const double *mv_src<double>(const CGMol &m, int src) { return m.v[src]; }
+template <> __device__ __forceinline__ const float *mv_src<float>(const CGMol &m, int) { return m.p32; }
+template <typename T> __device__ __forceinline__ T mv_rc2(const CGMol &m);
+template <> __device__ __forceinline__ double mv_rc2<double>(const CGMol &m) { return m.rc2_64; }
+template <> __device__ __forceinline__ float mv_rc2<float>(const CGMol &m) { return m.rc2_32; }
+
+// Read-only view through the constant address space: wave-uniform loads from it become
+// scalar loads.  Only for data that no thread of the running kernel writes.
+// (The host pass of the compiler only needs the declarations to type-check.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T> using cptr = const __attribute__((address_space(4))) T *;
+#else
+template <typename T> using cptr = const T *;
+#endif
+template <typename T> __device__ __forceinline__ cptr<T> as_const(const T *p) { return (cptr<T>)(p); }
+
+// gate 0: skip molecules whose PCG is done; gate 1: skip molecules not active in this call
+__device__ __forceinline__ bool skip(const CGState &s, int gate) { return gate ? !s.act : s.done; }
+
+// sum over the 256 threads of a block, fixed tree; every thread gets the result
+__device__ __forceinline__ double blk_sum(double v, double *s) {
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
     }
-    if (k < M) part[(size_t)blockIdx.y * M + k] = (double)acc;
+    double r = s[0];
+    __syncthreads();
+    return r;
 }
 
-// y = Akk x + sum of partial rows; optionally the per-block partial of sum_k x_k y_k
-__global__ __launch_bounds__(256) void k_mv_finish(const double *__restrict__ part, int rows, int M,
-                                                   const double *__restrict__ Akk, const double *__restrict__ x,
-                                                   double *__restrict__ y, double *__restrict__ dotpart) {
-    __shared__ double s[256];
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    double d = 0.0;
-    if (k < M) {
-        double acc = Akk[k] * x[k];
-        double off = 0.0;
-        for (int r = 0; r < rows; ++r) off += part[(size_t)r * M + k];
-        acc += off;
-        y[k] = acc;
-        d = x[k] * acc;
+// sum of n partials by one block (strided, then the tree)
+__device__ __forceinline__ double blk_sum_parts(const double *__restrict__ part, int n, double *s) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+    return blk_sum(acc, s);
+}
+
+// DPP moves within a row of 16 lanes (VALU only, no LDS round trip)
+constexpr int DPP_ROW_ROR8 = 0x128;     // lane i <- lane (i + 8) mod 16: partner differs in bit 3
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;  // lane i <- lane 7 - i within 8: partner differs in bit 2
+constexpr int DPP_QUAD_XOR2 = 0x4E;     // quad_perm [2, 3, 0, 1]
+constexpr int DPP_QUAD_XOR1 = 0xB1;     // quad_perm [1, 0, 3, 2]
+
+template <int CTRL> __device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Column sums of an 8-column batch over each row of 16 lanes: a reduce-scatter butterfly
+// (partners differ in lane bit 3, then 2, then 1) halves the values held per lane at each
+// step, then lanes 2c and 2c+1 of the row exchange and both hold the row's sum of column c.
+// Every sum is formed once, in a fixed order, so the result is deterministic.
+template <typename T> __device__ __forceinline__ T row_colsum8(const T (&v)[MV_B], int lane) {
+    const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
+    T w4[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        T send = b3 ? v[j] : v[4 + j];
+        T keep = b3 ? v[4 + j] : v[j];
+        w4[j] = keep + dpp<DPP_ROW_ROR8>(send);
     }
-    if (dotpart) {
-        s[threadIdx.x] = d;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    T w2[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        T send = b2 ? w4[j] : w4[2 + j];
+        T keep = b2 ? w4[2 + j] : w4[j];
+        w2[j] = keep + dpp<DPP_ROW_HALF_MIRROR>(send);
+    }
+    T send = b1 ? w2[0] : w2[1];
+    T keep = b1 ? w2[1] : w2[0];
+    T w1 = keep + dpp<DPP_QUAD_XOR2>(send);
+    return w1 + dpp<DPP_QUAD_XOR1>(w1);
+}
+
+// ----------------------------------------------------------------------------------------
+// matrix-free off-diagonal product over the tile pairs of the item table.
+// Writes part[J][k] (row sums of tile I against tile J) and, for I != J, part[I][l] (column
+// sums of tile J against tile I).  Padded points are far dummies whose x entries are zero.
+// ----------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(TILE) void k_mv_sym(const CGMol *__restrict__ tab, const CGState *__restrict__ st,
+                                                 const MvItem *__restrict__ items, int n_items, int gate, int src) {
+    __shared__ T colbuf[TILE / 16][TILE];  // one row of partial column sums per 16-lane row
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const MvItem w = items[it];
+        if (skip(st[w.mol], gate)) continue;
+        const CGMol &m = tab[w.mol];
+        const cptr<Pt<T>> __restrict__ pts = as_const(mv_pts<T>(m));
+        const cptr<T> __restrict__ xv = as_const(mv_src<T>(m, src));
+        const T rc2 = mv_rc2<T>(m);
+        const int k = w.I * TILE + threadIdx.x;
+        const Pt<T> me = pts[k];
+        const T xk = xv[k];
+        const int c0 = w.J * TILE;
+        const bool diag = w.I == w.J;
+        T racc = T(0);
+        for (int l = c0; l < c0 + TILE; l += MV_B) {
+            Pt<T> o[MV_B];
+            T xl[MV_B], a[MV_B], r2[MV_B];
+#pragma unroll
+            for (int u = 0; u < MV_B; ++u) {
+                o[u] = pts[l + u];
+                xl[u] = xv[l + u];
+            }
+            bool near = false;
+#pragma unroll
+            for (int u = 0; u < MV_B; ++u) {
+                T dx = me.x - o[u].x, dy = me.y - o[u].y, dz = me.z - o[u].z;
+                r2[u] = fma(dx, dx, fma(dy, dy, dz * dz));
+                near |= r2[u] < rc2;
+                a[u] = rsq_fast(r2[u]);
+            }
+            if (near) {
+#pragma unroll
+                for (int u = 0; u < MV_B; ++u)
+                    if (r2[u] < rc2) a[u] = mv_near<T>(me.zeta, o[u].zeta, r2[u], l + u == k);
+            }
+#pragma unroll
+            for (int u = 0; u < MV_B; ++u) racc = fma(a[u], xl[u], racc);
+            if (!diag) {
+                T cv[MV_B];
+#pragma unroll
+                for (int u = 0; u < MV_B; ++u) cv[u] = a[u] * xk;
+                T s = row_colsum8<T>(cv, lane);
+                if ((lane & 1) == 0) colbuf[wv * 4 + (lane >> 4)][l - c0 + ((lane >> 1) & 7)] = s;
+            }
+        }
+        if (k < m.M) m.part[(size_t)w.J * m.M + k] = (double)racc;
+        if (!diag) {
+            __syncthreads();
+            const int c = c0 + threadIdx.x;
+            T s = colbuf[0][threadIdx.x];
+#pragma unroll
+            for (int q = 1; q < TILE / 16; ++q) s += colbuf[q][threadIdx.x];
+            if (c < m.M) m.part[(size_t)w.I * m.M + c] = (double)s;
             __syncthreads();
         }
-        if (threadIdx.x == 0) dotpart[blockIdx.x] = s[0];
     }
 }
 
-static int mv_chunk_len(int Mp) {
-    int tiles = div_up(Mp, MV_T);
-    int want = div_up(2048, tiles);
-    int len = div_up(Mp, want);
-    len = (len + MV_B - 1) / MV_B * MV_B;
-    return len < 64 ? 64 : len;
+// y = Akk x + sum of the nT partial slots (fixed order).
+//   mode 0: v[dst] = y, dp[0] <- partials of x.y
+//   mode 1: v[dst] = v[bvec] - y, dp[0] <- partials of its square
+//   mode 2: v[dst] = y
+__global__ __launch_bounds__(TILE) void k_mv_finish(const CGMol *__restrict__ tab, const CGState *__restrict__ st,
+                                                    const TileItem *__restrict__ items, int n, int gate, int src,
+                                                    int dst, int bvec, int mode) {
+    __shared__ double s[TILE];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const TileItem w = items[it];
+        if (skip(st[w.mol], gate)) continue;
+        const CGMol &m = tab[w.mol];
+        const int k = w.t * TILE + threadIdx.x;
+        double d = 0.0;
+        if (k < m.M) {
+            const double xk = m.v[src][k];
+            double acc = m.Akk[k] * xk;
+            double off = 0.0;
+            for (int r = 0; r < m.nT; ++r) off += m.part[(size_t)r * m.M + k];
+            acc += off;
+            if (mode == 1) {
+                double res = m.v[bvec][k] - acc;
+                m.v[dst][k] = res;
+                d = res * res;
+            } else {
+                m.v[dst][k] = acc;
+                d = xk * acc;
+            }
+        }
+        if (mode != 2) {
+            double t = blk_sum(d, s);
+            if (threadIdx.x == 0) m.dp[w.t] = t;
+        }
+    }
 }
 
-// solver workspace layout inside mol->sv (offsets in doubles, each slot 32-aligned)
-struct SolverLayout {
-    size_t r, z, p, Ap, y, dp1, dp2, dp3, b, d, res, dot, p64, p32, x64, x32, total;
+// ----------------------------------------------------------------------------------------
+// PCG kernels.  x = v[xi], b = v[bi].
+// ----------------------------------------------------------------------------------------
+// r = b - (zero_x ? 0 : v[V_Y]); x = 0 when zero_x; z = C r (Jacobi / none); partials r.r, r.z
+__global__ __launch_bounds__(TILE) void k_cg_init(const CGMol *__restrict__ tab, const CGState *__restrict__ st,
+                                                  const TileItem *__restrict__ items, int n, int xi, int bi,
+                                                  int zero_x) {
+    __shared__ double s[TILE];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const TileItem w = items[it];
+        if (st[w.mol].done) continue;
+        const CGMol &m = tab[w.mol];
+        const int k = w.t * TILE + threadIdx.x;
+        double rr = 0.0, rz = 0.0;
+        if (k < m.M) {
+            double rk = m.v[bi][k] - (zero_x ? 0.0 : m.v[V_Y][k]);
+            if (zero_x) m.v[xi][k] = 0.0;
+            m.v[V_R][k] = rk;
+            rr = rk * rk;
+            if (m.precond != PCM_PRECOND_RBJ) {
+                double zk = m.precond == PCM_PRECOND_JACOBI ? rk / m.Akk[k] : rk;
+                m.v[V_Z][k] = zk;
+                rz = rk * zk;
+            }
+        }
+        double a = blk_sum(rr, s);
+        if (threadIdx.x == 0) m.dp[m.ndp + w.t] = a;
+        if (m.precond != PCM_PRECOND_RBJ) {
+            double b = blk_sum(rz, s);
+            if (threadIdx.x == 0) m.dp[2 * m.ndp + w.t] = b;
+        }
+    }
+}
+
+// alpha = r.z / p.Ap; x += alpha p; r -= alpha Ap; z = C r (Jacobi / none); partials r.r, r.z
+__global__ __launch_bounds__(TILE) void k_cg_update(const CGMol *__restrict__ tab, const CGState *__restrict__ st,
+                                                    const TileItem *__restrict__ items, int n, int xi, int par_prev) {
+    __shared__ double s[TILE];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const TileItem w = items[it];
+        const CGState &S = st[w.mol];
+        if (S.done) continue;
+        const CGMol &m = tab[w.mol];
+        const double pAp = blk_sum_parts(m.dp, m.nT, s);
+        const double alpha = S.rz[par_prev] / pAp;
+        const int k = w.t * TILE + threadIdx.x;
+        double rr = 0.0, rz = 0.0;
+        if (k < m.M) {
+            m.v[xi][k] += alpha * m.v[V_P][k];
+            double rk = m.v[V_R][k] - alpha * m.v[V_AP][k];
+            m.v[V_R][k] = rk;
+            rr = rk * rk;
+            if (m.precond != PCM_PRECOND_RBJ) {
+                double zk = m.precond == PCM_PRECOND_JACOBI ? rk / m.Akk[k] : rk;
+                m.v[V_Z][k] = zk;
+                rz = rk * zk;
+            }
+        }
+        double a = blk_sum(rr, s);
+        if (threadIdx.x == 0) m.dp[m.ndp + w.t] = a;
+        if (m.precond != PCM_PRECOND_RBJ) {
+            double b = blk_sum(rz, s);
+            if (threadIdx.x == 0) m.dp[2 * m.ndp + w.t] = b;
+        }
+    }
+}
+
+// randomized block-Jacobi: z[perm[o+i]] = sum_j inv[j][i] r[perm[o+j]] (inverse symmetric);
+// partials of r.z per item
+__global__ __launch_bounds__(TILE) void k_rbj_items(const CGMol *__restrict__ tab, const CGState *__restrict__ st,
+                                                    const RbjItem *__restrict__ items, int n) {
+    __shared__ double s[TILE];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const RbjItem w = items[it];
+        if (st[w.mol].done) continue;
+        const CGMol &m = tab[w.mol];
+        const int o = m.boff[w.blk], l = m.boff[w.blk + 1] - o;
+        const int i = w.i0 + threadIdx.x;
+        const double *__restrict__ r = m.v[V_R];
+        double rz = 0.0;
+        if (i < l) {
+            const double *__restrict__ Ab = m.inv + m.ioff[w.blk];
+            const int *__restrict__ pm = m.perm + o;
+            double acc = 0.0;
+            for (int j = 0; j < l; ++j) acc = fma(Ab[(long long)j * l + i], r[pm[j]], acc);
+            const int ki = pm[i];
+            m.v[V_Z][ki] = acc;
+            rz = acc * r[ki];
+        }
+        double t = blk_sum(rz, s);
+        if (threadIdx.x == 0) m.dp[2 * m.ndp + w.slot] = t;
+    }
+}
+
+// beta = r.z / r.z_prev (0 on the first call); p = z + beta p (p = z first); optional FP32
+// copy of p.  The block of tile 0 records r.r, r.z, the iteration count and the stop flag.
+__global__ __launch_bounds__(TILE) void k_cg_dir(const CGMol *__restrict__ tab, CGState *__restrict__ st,
+                                                 const TileItem *__restrict__ items, int n, int par, int first,
+                                                 int w32) {
+    __shared__ double s[TILE];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const TileItem w = items[it];
+        CGState *S = st + w.mol;
+        if (S->done) continue;
+        const CGMol &m = tab[w.mol];
+        const double rr = blk_sum_parts(m.dp + m.ndp, m.nT, s);
+        const double rz = blk_sum_parts(m.dp + 2 * m.ndp, m.n_rz, s);
+        const double beta = first ? 0.0 : rz / S->rz[par ^ 1];
+        const int k = w.t * TILE + threadIdx.x;
+        if (k < m.M) {
+            const double zk = m.v[V_Z][k];
+            const double pk = first ? zk : zk + beta * m.v[V_P][k];
+            m.v[V_P][k] = pk;
+            if (w32) m.p32[k] = (float)pk;
+        }
+        if (w.t == 0 && threadIdx.x == 0) {
+            S->rz[par] = rz;
+            S->rr = rr;
+            const int itn = first ? 0 : S->it + 1;
+            S->it = itn;
+            S->done = (!(sqrt(rr) >= S->tol) || itn >= S->max_it) ? 1 : 0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(TILE) void k_count_active(const CGState *__restrict__ st, int n, int *__restrict__ out) {
+    __shared__ double s[TILE];
+    double c = 0.0;
+    for (int i = threadIdx.x; i < n; i += TILE) c += st[i].done ? 0.0 : 1.0;
+    double t = blk_sum(c, s);
+    if (threadIdx.x == 0) out[0] = (int)t;
+}
+
+// ----------------------------------------------------------------------------------------
+// vector plumbing over the tile table (gate 1: molecules with act set)
+// ----------------------------------------------------------------------------------------
+__global__ __launch_bounds__(TILE) void k_vec_op(const CGMol *__restrict__ tab, const CGState *__restrict__ st,
+                                                 const TileItem *__restrict__ items, int n, int op, double a, int src,
+                                                 int dst, const double *const *__restrict__ ext) {
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const TileItem w = items[it];
+        if (!st[w.mol].act) continue;
+        const CGMol &m = tab[w.mol];
+        const int k = w.t * TILE + threadIdx.x;
+        if (k >= m.M) continue;
+        switch (op) {
+        case 0: m.v[dst][k] = ext[w.mol][k]; break;                       // load caller vector
+        case 1: const_cast<double *>(ext[w.mol])[k] = m.v[src][k]; break;  // store to caller
+        case 2: m.v[dst][k] = a * m.v[src][k]; break;                     // scale
+        case 3: m.v[dst][k] += a * m.v[src][k]; break;                    // axpy
+        default: m.v[dst][k] = 0.0; break;                                // zero
+        }
+    }
+}
+
+// partials of three dot products v[a_j].v[b_j] into dp[j]
+__global__ __launch_bounds__(TILE) void k_dots3(const CGMol *__restrict__ tab, const CGState *__restrict__ st,
+                                                const TileItem *__restrict__ items, int n, int a0, int b0, int a1,
+                                                int b1, int a2, int b2) {
+    __shared__ double s[TILE];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const TileItem w = items[it];
+        if (!st[w.mol].act) continue;
+        const CGMol &m = tab[w.mol];
+        const int k = w.t * TILE + threadIdx.x;
+        double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+        if (k < m.M) {
+            d0 = m.v[a0][k] * m.v[b0][k];
+            d1 = m.v[a1][k] * m.v[b1][k];
+            d2 = m.v[a2][k] * m.v[b2][k];
+        }
+        double t0 = blk_sum(d0, s), t1 = blk_sum(d1, s), t2 = blk_sum(d2, s);
+        if (threadIdx.x == 0) {
+            m.dp[w.t] = t0;
+            m.dp[m.ndp + w.t] = t1;
+            m.dp[2 * m.ndp + w.t] = t2;
+        }
+    }
+}
+
+// one block per molecule: what = 0: res2 <- sum dp[0]; what = 1: dots[j] <- sum dp[j]
+__global__ __launch_bounds__(TILE) void k_mol_reduce(const CGMol *__restrict__ tab, CGState *__restrict__ st,
+                                                     int what) {
+    __shared__ double s[TILE];
+    CGState *S = st + blockIdx.x;
+    if (!S->act) return;
+    const CGMol &m = tab[blockIdx.x];
+    if (what == 0) {
+        double t = blk_sum_parts(m.dp, m.nT, s);
+        if (threadIdx.x == 0) S->res2 = t;
+    } else {
+        for (int j = 0; j < 3; ++j) {
+            double t = blk_sum_parts(m.dp + j * m.ndp, m.nT, s);
+            if (threadIdx.x == 0) S->dots[j] = t;
+        }
+    }
+}
+
+__global__ void k_pack_pts(const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz,
+                           const double *__restrict__ zeta, int M, int Mp, Pt<double> *__restrict__ p64,
+                           Pt<float> *__restrict__ p32) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Mp) return;
+    if (k < M) {
+        p64[k] = Pt<double>{px[k], py[k], pz[k], zeta[k]};
+        p32[k] = Pt<float>{(float)px[k], (float)py[k], (float)pz[k], (float)zeta[k]};
+    } else {
+        p64[k] = Pt<double>{1e6, 1e6, 1e6, 1.0};
+        p32[k] = Pt<float>{1e6f, 1e6f, 1e6f, 1.0f};
+    }
+}
+
+// ----------------------------------------------------------------------------------------
+// host side
+// ----------------------------------------------------------------------------------------
+// per-molecule solver storage inside mol->sv (offsets in doubles)
+struct SvLayout {
+    size_t vec[NVEC], p32, pt64, pt32, total;
 };
 
-static SolverLayout solver_layout(size_t M) {
-    SolverLayout L{};
-    size_t o = 0, Mp = mv_pad((int)M);
-    auto take = [&](size_t n) {
-        size_t s0 = o;
-        o += (n + 31) & ~size_t(31);
-        return s0;
-    };
-    L.r = take(M); L.z = take(M); L.p = take(M); L.Ap = take(M); L.y = take(M);
-    L.dp1 = take(2 * M + 4096); L.dp2 = take(2 * M + 4096); L.dp3 = take(2 * M + 4096);
-    L.b = take(M); L.d = take(M); L.res = take(M); L.dot = take(M / 256 + 64);
-    L.p64 = take(4 * Mp); L.p32 = take(2 * Mp); L.x64 = take(Mp); L.x32 = take(Mp / 2 + 2);
+static SvLayout sv_layout(int M) {
+    SvLayout L{};
+    const size_t Mp = sv_pad(M);
+    size_t o = 0;
+    for (int i = 0; i < NVEC; ++i, o += Mp) L.vec[i] = o;
+    L.p32 = o;
+    o += Mp / 2;
+    L.pt64 = o;
+    o += 4 * Mp;
+    L.pt32 = o;
+    o += 2 * Mp;
     L.total = o;
     return L;
-}
-
-struct MatvecWS {
-    Pt<double> *p64;
-    Pt<float> *p32;
-    double *x64;
-    float *x32;
-};
-
-static MatvecWS mv_ws(pcm_mol *mol) {
-    SolverLayout L = solver_layout(mol->M);
-    MatvecWS w;
-    w.p64 = reinterpret_cast<Pt<double> *>(mol->sv.p + L.p64);
-    w.p32 = reinterpret_cast<Pt<float> *>(mol->sv.p + L.p32);
-    w.x64 = mol->sv.p + L.x64;
-    w.x32 = reinterpret_cast<float *>(mol->sv.p + L.x32);
-    return w;
 }
 
 // cutoff radius^2 beyond which erf(z' r) rounds to 1 for every pair: z'^2 >= zeta_min^2 / 2
@@ -190,646 +525,481 @@ static void mv_cutoffs(pcm_mol *mol, double &rc2_64, double &rc2_32) {
     rc2_32 = 2.0 * 16.0 / (zmin * zmin);
 }
 
-static void ensure_solver_ws(pcm_ctx *ctx, pcm_mol *mol) {
-    size_t M = mol->M;
-    int Mp = mv_pad((int)M);
-    mol->sv.ensure(solver_layout(M).total);
-    MatvecWS w = mv_ws(mol);
-    k_pack_pts<<<div_up(Mp, 256), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p, (int)M, Mp,
-                                                         w.p64, w.p32, w.x64, w.x32);
+// allocate (once; zero tails) and pack the current points
+static void solver_prepare(pcm_ctx *ctx, pcm_mol *mol) {
+    const SvLayout L = sv_layout(mol->M);
+    if (mol->sv.n < L.total || !mol->sv.p) {
+        mol->sv.ensure(L.total);
+        HIP_OK(hipMemsetAsync(mol->sv.p, 0, L.total * sizeof(double), ctx->stream));
+    }
+    const int Mp = sv_pad(mol->M);
+    k_pack_pts<<<div_up(Mp, 256), 256, 0, ctx->stream>>>(
+        mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p, mol->M, Mp,
+        reinterpret_cast<Pt<double> *>(mol->sv.p + L.pt64), reinterpret_cast<Pt<float> *>(mol->sv.p + L.pt32));
     HIP_LAUNCH_OK();
 }
 
-// y = A x (FP64 or FP32 off-diagonal); dotpart (may be null) receives per-block x.y partials
-static void matvec(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int prec, double *dotpart) {
-    const int M = mol->M, Mp = mv_pad(M);
-    MatvecWS w = mv_ws(mol);
-    int len = mv_chunk_len(Mp);
-    int rows = div_up(Mp, len);
-    mol->part2.ensure((size_t)rows * M);
-    dim3 grid(div_up(M, MV_T), rows);
-    double rc64, rc32;
-    mv_cutoffs(mol, rc64, rc32);
-    if (prec == PCM_MIXED) {
-        k_pad_x<float><<<div_up(M, 256), 256, 0, ctx->stream>>>(x, w.x32, M);
-        HIP_LAUNCH_OK();
-        ProfScope ps(ctx, "matvec_f32", (double)M * M);
-        k_matvec<float><<<grid, MV_T, 0, ctx->stream>>>(w.p32, w.x32, M, Mp, len, (float)rc32, mol->part2.p);
-        HIP_LAUNCH_OK();
-    } else {
-        k_pad_x<double><<<div_up(M, 256), 256, 0, ctx->stream>>>(x, w.x64, M);
-        HIP_LAUNCH_OK();
-        ProfScope ps(ctx, "matvec_f64", (double)M * M);
-        k_matvec<double><<<grid, MV_T, 0, ctx->stream>>>(w.p64, w.x64, M, Mp, len, rc64, mol->part2.p);
-        HIP_LAUNCH_OK();
+struct GraphSig {
+    const void *tab, *st, *mv, *tiles, *rbj;
+    int n_mv, n_tiles, n_rbj, grid, rbj_on, prec;
+    bool operator==(const GraphSig &o) const {
+        return tab == o.tab && st == o.st && mv == o.mv && tiles == o.tiles && rbj == o.rbj && n_mv == o.n_mv &&
+               n_tiles == o.n_tiles && n_rbj == o.n_rbj && grid == o.grid && rbj_on == o.rbj_on && prec == o.prec;
     }
-    k_mv_finish<<<div_up(M, 256), 256, 0, ctx->stream>>>(mol->part2.p, rows, M, mol->Akk.p, x, y, dotpart);
-    HIP_LAUNCH_OK();
-}
-
-void run_matvec(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int prec) {
-    ensure_solver_ws(ctx, mol);
-    matvec(ctx, mol, x, y, prec, nullptr);
-}
-
-// ----------------------------------------------------------------------------------------
-// deterministic dot products
-// ----------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_dot_part(const double *__restrict__ a, const double *__restrict__ b,
-                                                  long long n, double *__restrict__ part) {
-    __shared__ double s[256];
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    s[threadIdx.x] = i < n ? a[i] * b[i] : 0.0;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
-}
-
-// sum of nparts partials by one block (fixed order), written to out[0]
-__global__ __launch_bounds__(256) void k_sum_parts(const double *__restrict__ part, int nparts,
-                                                   double *__restrict__ out) {
-    __shared__ double s[256];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += 256) acc += part[i];
-    s[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = s[0];
-}
-
-__device__ __forceinline__ double block_sum_parts(const double *__restrict__ part, int nparts, double *s) {
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += part[i];
-    s[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-        __syncthreads();
-    }
-    double r = s[0];
-    __syncthreads();
-    return r;
-}
-
-double dev_dot(pcm_ctx *ctx, pcm_mol *mol, const double *a, const double *b, long long n) {
-    int nb = div_up(n, 256);
-    double *part = mol->sv.p + solver_layout(mol->M).dot;
-    k_dot_part<<<nb, 256, 0, ctx->stream>>>(a, b, n, part);
-    HIP_LAUNCH_OK();
-    k_sum_parts<<<1, 256, 0, ctx->stream>>>(part, nb, ctx->scal.p);
-    HIP_LAUNCH_OK();
-    double r = 0.0;
-    HIP_OK(hipMemcpyAsync(&r, ctx->scal.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_OK(hipStreamSynchronize(ctx->stream));
-    return r;
-}
-
-// ----------------------------------------------------------------------------------------
-// PCG building blocks.  Scalars live on the device in hist[it][*]:
-//   0: p.Ap   1: alpha   2: r.r (after the update)   3: r.z   4: beta
-// ----------------------------------------------------------------------------------------
-constexpr int HS = 8;
-
-// x += alpha p, r -= alpha Ap, z = r / Akk (jacobi) or z = r (none); partials of r.r and r.z
-__global__ __launch_bounds__(256) void k_cg_update(int M, const double *__restrict__ dp_pAp, int n_dp,
-                                                   double *__restrict__ hist, int it, double *__restrict__ x,
-                                                   double *__restrict__ r, const double *__restrict__ p,
-                                                   const double *__restrict__ Ap, double *__restrict__ z,
-                                                   const double *__restrict__ Akk, int precond,
-                                                   double *__restrict__ dp_rr, double *__restrict__ dp_rz) {
-    __shared__ double s[256];
-    double pAp = block_sum_parts(dp_pAp, n_dp, s);
-    double rz_old = hist[(it - 1) * HS + 3];
-    double alpha = rz_old / pAp;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        hist[it * HS + 0] = pAp;
-        hist[it * HS + 1] = alpha;
-    }
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    double rr = 0.0, rz = 0.0;
-    if (k < M) {
-        x[k] += alpha * p[k];
-        double rk = r[k] - alpha * Ap[k];
-        r[k] = rk;
-        rr = rk * rk;
-        if (precond != PCM_PRECOND_RBJ) {
-            double zk = precond == PCM_PRECOND_JACOBI ? rk / Akk[k] : rk;
-            z[k] = zk;
-            rz = rk * zk;
-        }
-    }
-    s[threadIdx.x] = rr;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) dp_rr[blockIdx.x] = s[0];
-    __syncthreads();
-    s[threadIdx.x] = rz;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && precond != PCM_PRECOND_RBJ) dp_rz[blockIdx.x] = s[0];
-}
-
-// reduce r.r (n_rr partials) and r.z (n_rz partials); beta = rz_new / rz_old; p = z + beta p
-__global__ __launch_bounds__(256) void k_cg_direction(int M, const double *__restrict__ dp_rr, int n_rr,
-                                                      const double *__restrict__ dp_rz, int n_rz,
-                                                      double *__restrict__ hist, int it, double *__restrict__ p,
-                                                      const double *__restrict__ z) {
-    __shared__ double s[256];
-    double rr = block_sum_parts(dp_rr, n_rr, s);
-    double rz = block_sum_parts(dp_rz, n_rz, s);
-    double beta = rz / hist[(it - 1) * HS + 3];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        hist[it * HS + 2] = rr;
-        hist[it * HS + 3] = rz;
-        hist[it * HS + 4] = beta;
-    }
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < M) p[k] = z[k] + beta * p[k];
-}
-
-// initial: r = b - y (y = A x0 or 0), z = C r (jacobi/none), p = z; partials of r.r, r.z
-__global__ __launch_bounds__(256) void k_cg_init(int M, const double *__restrict__ b, const double *__restrict__ y,
-                                                 double *__restrict__ r, double *__restrict__ z,
-                                                 const double *__restrict__ Akk, int precond,
-                                                 double *__restrict__ dp_rr, double *__restrict__ dp_rz) {
-    __shared__ double s[256];
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    double rr = 0.0, rz = 0.0;
-    if (k < M) {
-        double rk = b[k] - (y ? y[k] : 0.0);
-        r[k] = rk;
-        rr = rk * rk;
-        if (precond != PCM_PRECOND_RBJ) {
-            double zk = precond == PCM_PRECOND_JACOBI ? rk / Akk[k] : rk;
-            z[k] = zk;
-            rz = rk * zk;
-        }
-    }
-    s[threadIdx.x] = rr;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) dp_rr[blockIdx.x] = s[0];
-    __syncthreads();
-    s[threadIdx.x] = rz;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && precond != PCM_PRECOND_RBJ) dp_rz[blockIdx.x] = s[0];
-}
-
-__global__ void k_axpy(int M, double a, const double *__restrict__ x, double *__restrict__ y) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < M) y[k] += a * x[k];
-}
-
-__global__ void k_scale_copy(int M, double a, const double *__restrict__ x, double *__restrict__ y) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < M) y[k] = a * x[k];
-}
-
-// ----------------------------------------------------------------------------------------
-// randomized block-Jacobi: block matrices, in-place SPD inversion, application
-// ----------------------------------------------------------------------------------------
-__global__ void k_rbj_fill(const Pt<double> *__restrict__ pts, const double *__restrict__ Akk,
-                           const int *__restrict__ perm, const int *__restrict__ off, const long long *__restrict__ ioff,
-                           double *__restrict__ blk) {
-    int b = blockIdx.x;
-    int o = off[b], l = off[b + 1] - o;
-    long long e = (long long)blockIdx.y * blockDim.x + threadIdx.x;
-    if (e >= (long long)l * l) return;
-    int i = (int)(e / l), j = (int)(e % l);
-    int ki = perm[o + i], kj = perm[o + j];
-    double v;
-    if (ki == kj) {
-        v = Akk[ki];
-    } else {
-        Pt<double> a = pts[ki], c = pts[kj];
-        double dx = a.x - c.x, dy = a.y - c.y, dz = a.z - c.z;
-        double d = sqrt(dx * dx + dy * dy + dz * dz);
-        double zp = a.zeta * c.zeta / sqrt(a.zeta * a.zeta + c.zeta * c.zeta);
-        v = d == 0.0 ? 1.1283791670955125739 * zp : erf(zp * d) / d;
-    }
-    blk[ioff[b] + e] = v;
-}
-
-// In-place Gauss-Jordan inversion of one SPD block per workgroup (no pivoting needed for SPD);
-// a non-positive pivot flags the block as not positive definite.
-__global__ __launch_bounds__(256) void k_rbj_invert(const int *__restrict__ off, const long long *__restrict__ ioff,
-                                                    double *__restrict__ blk, int *__restrict__ bad) {
-    int b = blockIdx.x;
-    int l = off[b + 1] - off[b];
-    double *A = blk + ioff[b];
-    __shared__ double rowk[1024];
-    __shared__ double colk[1024];
-    __shared__ double piv_s;
-    for (int k = 0; k < l; ++k) {
-        if (threadIdx.x == 0) {
-            piv_s = A[(long long)k * l + k];
-            if (!(piv_s > 0.0)) bad[0] = 1;
-        }
-        __syncthreads();
-        double piv = piv_s;
-        if (!(piv > 0.0)) return;
-        double ip = 1.0 / piv;
-        for (int j = threadIdx.x; j < l; j += blockDim.x) {
-            rowk[j] = A[(long long)k * l + j] * ip;
-            colk[j] = A[(long long)j * l + k];
-        }
-        __syncthreads();
-        // update every element outside row k (rows walked uniformly, columns across lanes)
-        for (int i = 0; i < l; ++i) {
-            if (i == k) continue;
-            const double ci = colk[i];
-            double *Ai = A + (long long)i * l;
-            for (int j = threadIdx.x; j < l; j += blockDim.x) Ai[j] = (j == k) ? -ci * ip : Ai[j] - ci * rowk[j];
-        }
-        __syncthreads();
-        for (int j = threadIdx.x; j < l; j += blockDim.x) A[(long long)k * l + j] = (j == k) ? ip : rowk[j];
-        __syncthreads();
-    }
-}
-
-// z[perm[o+i]] = sum_j inv[j][i] r[perm[o+j]] (inverse symmetric); per-group partial of r.z
-__global__ __launch_bounds__(256) void k_rbj_apply(const int *__restrict__ perm, const int *__restrict__ off,
-                                                   const long long *__restrict__ ioff,
-                                                   const double *__restrict__ blk, const double *__restrict__ r,
-                                                   double *__restrict__ z, double *__restrict__ dp_rz, int tiles) {
-    __shared__ double s[256];
-    int b = blockIdx.x;
-    int o = off[b], l = off[b + 1] - o;
-    int i = blockIdx.y * blockDim.x + threadIdx.x;
-    double rz = 0.0;
-    if (i < l) {
-        const double *Ab = blk + ioff[b];
-        double acc = 0.0;
-        for (int j = 0; j < l; ++j) acc = fma(Ab[(long long)j * l + i], r[perm[o + j]], acc);
-        int ki = perm[o + i];
-        z[ki] = acc;
-        rz = acc * r[ki];
-    }
-    s[threadIdx.x] = rz;
-    __syncthreads();
-    for (int q = 128; q > 0; q >>= 1) {
-        if (threadIdx.x < q) s[threadIdx.x] += s[threadIdx.x + q];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) dp_rz[b * tiles + blockIdx.y] = s[0];
-}
-
-static void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int l, unsigned long long seed) {
-    if (mol->rbj_valid && mol->rbj_l == l && mol->rbj_seed == seed) return;
-    const int M = mol->M;
-    std::vector<double> r(3 * (size_t)M), px(M), py(M), pz(M), zeta(M);
-    HIP_OK(hipMemcpyAsync(px.data(), mol->px.p, M * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_OK(hipMemcpyAsync(py.data(), mol->py.p, M * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_OK(hipMemcpyAsync(pz.data(), mol->pz.p, M * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_OK(hipMemcpyAsync(zeta.data(), mol->zeta.p, M * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_OK(hipStreamSynchronize(ctx->stream));
-    for (int k = 0; k < M; ++k) {
-        r[3 * k] = px[k];
-        r[3 * k + 1] = py[k];
-        r[3 * k + 2] = pz[k];
-    }
-    mol->h_rbj_perm.assign(M, 0);
-    mol->h_rbj_off.assign(M + 1, 0);
-    int nb = host_rbj_partition(M, r.data(), zeta.data(), l, seed, mol->h_rbj_perm.data(), mol->h_rbj_off.data());
-    if (nb <= 0) throw PcmError{PCM_E_ARG, "randomized block-Jacobi partition failed"};
-    mol->h_rbj_off.resize(nb + 1);
-    std::vector<long long> ioff(nb + 1, 0);
-    int lmax = 0;
-    for (int b = 0; b < nb; ++b) {
-        int sz = mol->h_rbj_off[b + 1] - mol->h_rbj_off[b];
-        ioff[b + 1] = ioff[b] + (long long)sz * sz;
-        lmax = std::max(lmax, sz);
-    }
-    if (lmax > 1024) throw PcmError{PCM_E_ARG, "RBJ block size above 1024 is not supported"};
-    mol->rbj_perm.ensure(M);
-    mol->rbj_off.ensure(nb + 1);
-    mol->rbj_inv_off.ensure(2 * (nb + 1));  // long long stored in int pairs
-    mol->rbj_inv.ensure(ioff[nb]);
-    HIP_OK(hipMemcpyAsync(mol->rbj_perm.p, mol->h_rbj_perm.data(), M * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
-    HIP_OK(hipMemcpyAsync(mol->rbj_off.p, mol->h_rbj_off.data(), (nb + 1) * sizeof(int), hipMemcpyHostToDevice,
-                          ctx->stream));
-    long long *d_ioff = reinterpret_cast<long long *>(mol->rbj_inv_off.p);
-    HIP_OK(hipMemcpyAsync(d_ioff, ioff.data(), (nb + 1) * sizeof(long long), hipMemcpyHostToDevice, ctx->stream));
-    MatvecWS w = mv_ws(mol);
-    dim3 g1(nb, div_up((long long)lmax * lmax, 256));
-    k_rbj_fill<<<g1, 256, 0, ctx->stream>>>(w.p64, mol->Akk.p, mol->rbj_perm.p, mol->rbj_off.p, d_ioff,
-                                            mol->rbj_inv.p);
-    HIP_LAUNCH_OK();
-    HIP_OK(hipMemsetAsync(ctx->iscal.p, 0, sizeof(int), ctx->stream));
-    {
-        ProfScope psi(ctx, "rbj_invert", (double)ioff[nb]);
-        k_rbj_invert<<<nb, 256, 0, ctx->stream>>>(mol->rbj_off.p, d_ioff, mol->rbj_inv.p, ctx->iscal.p);
-        HIP_LAUNCH_OK();
-    }
-    int bad = 0;
-    HIP_OK(hipMemcpyAsync(&bad, ctx->iscal.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_OK(hipStreamSynchronize(ctx->stream));
-    if (bad) throw PcmError{PCM_E_NOTPD, "a randomized block-Jacobi block is not positive definite"};
-    mol->rbj_l = l;
-    mol->rbj_seed = seed;
-    mol->rbj_valid = true;
-}
-
-static void rbj_apply(pcm_ctx *ctx, pcm_mol *mol, const double *r, double *z, double *dp_rz, int &n_parts) {
-    int nb = (int)mol->h_rbj_off.size() - 1;
-    int lmax = 0;
-    for (int b = 0; b < nb; ++b) lmax = std::max(lmax, mol->h_rbj_off[b + 1] - mol->h_rbj_off[b]);
-    int tiles = div_up(lmax, 256);
-    dim3 g(nb, tiles);
-    ProfScope ps(ctx, "rbj_apply", (double)mol->M * lmax);
-    k_rbj_apply<<<g, 256, 0, ctx->stream>>>(mol->rbj_perm.p, mol->rbj_off.p,
-                                            reinterpret_cast<const long long *>(mol->rbj_inv_off.p), mol->rbj_inv.p, r,
-                                            z, dp_rz, tiles);
-    HIP_LAUNCH_OK();
-    n_parts = tiles * nb;
-}
-
-// ----------------------------------------------------------------------------------------
-// one PCG run on A x = b starting from x (in/out); stops on ||r||_2 < tol or max_it
-// returns the number of matvecs; *rn_out = final recurrence residual norm
-// ----------------------------------------------------------------------------------------
-struct CGVecs {
-    double *r, *z, *p, *Ap, *y, *dp1, *dp2, *dp3;
 };
 
-static CGVecs cg_vecs(pcm_mol *mol) {
-    SolverLayout L = solver_layout(mol->M);
-    double *b = mol->sv.p;
-    return CGVecs{b + L.r, b + L.z, b + L.p, b + L.Ap, b + L.y, b + L.dp1, b + L.dp2, b + L.dp3};
+struct SolveBatch {
+    std::vector<pcm_mol *> mols;
+    int n = 0;
+    DevBuf<CGMol> tab;
+    DevBuf<CGState> st;
+    DevBuf<MvItem> mv;
+    DevBuf<TileItem> tiles;
+    DevBuf<RbjItem> rbj;
+    DevBuf<double> part, dp;
+    DevBuf<const double *> ext;
+    DevBuf<int> cnt;
+    int n_mv = 0, n_tiles = 0, n_rbj = 0;
+    std::vector<CGMol> h_tab;
+    std::vector<CGState> h_st;
+    std::vector<size_t> part_off, dp_off;
+    int *h_cnt = nullptr;  // pinned [2]
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    GraphSig gsig[2] = {};
+    ~SolveBatch() {
+        for (auto &g : gexec)
+            if (g) (void)hipGraphExecDestroy(g);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (h_cnt) (void)hipHostFree(h_cnt);
+    }
+};
+
+void solve_batch_free(SolveBatch *b) { delete b; }
+
+SolveBatch *solve_batch_new(const std::vector<pcm_mol *> &mols) {
+    SolveBatch *b = new SolveBatch();
+    b->mols = mols;
+    b->n = (int)mols.size();
+    return b;
 }
 
-static int pcg_run(pcm_ctx *ctx, pcm_mol *mol, const double *b, double *x, bool x_zero, double tol, int max_it,
-                   int precond, int mv_prec, double *hist, double *rn_out) {
-    const int M = mol->M;
-    CGVecs v = cg_vecs(mol);
-    const int nbk = div_up(M, 256);
-    int n_rz = nbk;
-    // initial residual
-    if (!x_zero) {
-        matvec(ctx, mol, x, v.y, mv_prec, nullptr);
+static int grid_of(int n) { return n < 1 ? 1 : n; }
+
+// tables that depend on sizes and the RBJ partition; per-call pointers are refreshed each run
+static void batch_tables(pcm_ctx *ctx, SolveBatch &B, int precond) {
+    const int n = B.n;
+    std::vector<MvItem> mv;
+    std::vector<TileItem> tl;
+    std::vector<RbjItem> rb;
+    B.part_off.assign(n + 1, 0);
+    B.dp_off.assign(n + 1, 0);
+    B.h_tab.assign(n, CGMol{});
+    for (int i = 0; i < n; ++i) {
+        pcm_mol *mol = B.mols[i];
+        const int M = mol->M, Mp = sv_pad(M), nT = Mp / TILE;
+        for (int I = 0; I < nT; ++I)
+            for (int J = I; J < nT; ++J) mv.push_back(MvItem{i, I, J});
+        for (int t = 0; t < nT; ++t) tl.push_back(TileItem{i, t});
+        int n_rz = nT;
+        if (precond == PCM_PRECOND_RBJ) {
+            const int nb = (int)mol->h_rbj_off.size() - 1;
+            int slot = 0;
+            for (int bk = 0; bk < nb; ++bk) {
+                const int l = mol->h_rbj_off[bk + 1] - mol->h_rbj_off[bk];
+                for (int i0 = 0; i0 < l; i0 += TILE) rb.push_back(RbjItem{i, bk, i0, slot++});
+            }
+            n_rz = slot;
+        }
+        CGMol &m = B.h_tab[i];
+        m.M = M;
+        m.Mp = Mp;
+        m.nT = nT;
+        m.n_rz = n_rz;
+        m.ndp = std::max(nT, n_rz);
+        m.precond = precond;
+        B.part_off[i + 1] = B.part_off[i] + (size_t)nT * M;
+        B.dp_off[i + 1] = B.dp_off[i] + 3 * (size_t)m.ndp;
     }
-    k_cg_init<<<nbk, 256, 0, ctx->stream>>>(M, b, x_zero ? nullptr : v.y, v.r, v.z, mol->Akk.p, precond, v.dp1, v.dp2);
-    HIP_LAUNCH_OK();
-    if (precond == PCM_PRECOND_RBJ) rbj_apply(ctx, mol, v.r, v.z, v.dp2, n_rz);
-    // hist[0]: rr from dp1 (nbk parts), rz from dp2 (n_rz parts); p = z
-    {
-        // k_cg_start sums both with the same count; pad when counts differ by summing separately
-        k_sum_parts<<<1, 256, 0, ctx->stream>>>(v.dp1, nbk, hist + 2);
-        k_sum_parts<<<1, 256, 0, ctx->stream>>>(v.dp2, n_rz, hist + 3);
-        k_scale_copy<<<nbk, 256, 0, ctx->stream>>>(M, 1.0, v.z, v.p);
-        HIP_LAUNCH_OK();
+    B.n_mv = (int)mv.size();
+    B.n_tiles = (int)tl.size();
+    B.n_rbj = (int)rb.size();
+    B.tab.ensure(n);
+    B.st.ensure(n);
+    B.ext.ensure(n);
+    B.cnt.ensure(2);
+    B.mv.ensure(std::max<size_t>(mv.size(), 1));
+    B.tiles.ensure(std::max<size_t>(tl.size(), 1));
+    B.rbj.ensure(std::max<size_t>(rb.size(), 1));
+    B.part.ensure(std::max<size_t>(B.part_off[n], 1));
+    B.dp.ensure(std::max<size_t>(B.dp_off[n], 1));
+    HIP_OK(hipMemcpyAsync(B.mv.p, mv.data(), mv.size() * sizeof(MvItem), hipMemcpyHostToDevice, ctx->stream));
+    HIP_OK(hipMemcpyAsync(B.tiles.p, tl.data(), tl.size() * sizeof(TileItem), hipMemcpyHostToDevice, ctx->stream));
+    if (!rb.empty())
+        HIP_OK(hipMemcpyAsync(B.rbj.p, rb.data(), rb.size() * sizeof(RbjItem), hipMemcpyHostToDevice, ctx->stream));
+    for (int i = 0; i < n; ++i) {
+        pcm_mol *mol = B.mols[i];
+        CGMol &m = B.h_tab[i];
+        const SvLayout L = sv_layout(mol->M);
+        for (int v = 0; v < NVEC; ++v) m.v[v] = mol->sv.p + L.vec[v];
+        m.p32 = reinterpret_cast<float *>(mol->sv.p + L.p32);
+        m.pt64 = reinterpret_cast<const Pt<double> *>(mol->sv.p + L.pt64);
+        m.pt32 = reinterpret_cast<const Pt<float> *>(mol->sv.p + L.pt32);
+        m.Akk = mol->Akk.p;
+        m.part = B.part.p + B.part_off[i];
+        m.dp = B.dp.p + B.dp_off[i];
+        if (precond == PCM_PRECOND_RBJ) {
+            m.perm = mol->rbj_perm.p;
+            m.boff = mol->rbj_off.p;
+            m.ioff = mol->rbj_ioff.p;
+            m.inv = mol->rbj_inv.p;
+        }
+        double r32;
+        mv_cutoffs(mol, m.rc2_64, r32);
+        m.rc2_32 = (float)r32;
     }
-    double rr = 0.0;
-    HIP_OK(hipMemcpyAsync(&rr, hist + 2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipMemcpyAsync(B.tab.p, B.h_tab.data(), n * sizeof(CGMol), hipMemcpyHostToDevice, ctx->stream));
+    if (!B.h_cnt) HIP_OK(hipHostMalloc((void **)&B.h_cnt, 2 * sizeof(int), hipHostMallocDefault));
+    for (auto &e : B.ev)
+        if (!e) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+}
+
+static void upload_states(pcm_ctx *ctx, SolveBatch &B) {
+    HIP_OK(hipMemcpyAsync(B.st.p, B.h_st.data(), B.n * sizeof(CGState), hipMemcpyHostToDevice, ctx->stream));
+}
+
+static void download_states(pcm_ctx *ctx, SolveBatch &B) {
+    HIP_OK(hipMemcpyAsync(B.h_st.data(), B.st.p, B.n * sizeof(CGState), hipMemcpyDeviceToHost, ctx->stream));
     HIP_OK(hipStreamSynchronize(ctx->stream));
-    int it = 0;
-    double rn = sqrt(rr);
-    while (rn >= tol && it < max_it) {
-        ++it;
-        matvec(ctx, mol, v.p, v.Ap, mv_prec, v.dp3);
-        k_cg_update<<<nbk, 256, 0, ctx->stream>>>(M, v.dp3, nbk, hist, it, x, v.r, v.p, v.Ap, v.z, mol->Akk.p,
-                                                  precond, v.dp1, v.dp2);
-        HIP_LAUNCH_OK();
-        if (precond == PCM_PRECOND_RBJ) rbj_apply(ctx, mol, v.r, v.z, v.dp2, n_rz);
-        k_cg_direction<<<nbk, 256, 0, ctx->stream>>>(M, v.dp1, nbk, v.dp2, n_rz, hist, it, v.p, v.z);
-        HIP_LAUNCH_OK();
-        HIP_OK(hipMemcpyAsync(&rr, hist + it * HS + 2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-        HIP_OK(hipStreamSynchronize(ctx->stream));
-        rn = sqrt(rr);
+}
+
+static double mv_work(const SolveBatch &B) {
+    double w = 0.0;  // unordered point pairs (the algorithmic count)
+    for (const auto &m : B.h_tab) w += 0.5 * (double)m.M * (double)(m.M - 1);
+    return w;
+}
+
+// ---------------------------------------------------------------- launch grid of the matvec
+// The autotuner times the persistent matvec at a few grid sizes on first use for a given
+// (precision, item count) and caches the fastest.  The grid does not change any result.
+static std::map<std::pair<int, int>, int> g_mv_grid;
+
+static void launch_mv(pcm_ctx *ctx, SolveBatch &B, hipStream_t s, int prec, int gate, int src, int grid) {
+    if (prec == PCM_MIXED)
+        k_mv_sym<float><<<grid, TILE, 0, s>>>(B.tab.p, B.st.p, B.mv.p, B.n_mv, gate, src);
+    else
+        k_mv_sym<double><<<grid, TILE, 0, s>>>(B.tab.p, B.st.p, B.mv.p, B.n_mv, gate, src);
+    HIP_LAUNCH_OK();
+}
+
+static int mv_grid(pcm_ctx *ctx, SolveBatch &B, int prec, int gate, int src) {
+    auto key = std::make_pair(prec, B.n_mv);
+    auto f = g_mv_grid.find(key);
+    if (f != g_mv_grid.end()) return f->second;
+    std::vector<int> cand{B.n_mv};
+    for (int c : {512, 1024, 2048, 4096, 8192})
+        if (c < B.n_mv) cand.push_back(c);
+    int best = B.n_mv;
+    if (cand.size() > 1) {
+        hipEvent_t a, b;
+        HIP_OK(hipEventCreate(&a));
+        HIP_OK(hipEventCreate(&b));
+        float best_ms = 1e30f;
+        for (int g : cand) {
+            launch_mv(ctx, B, ctx->stream, prec, gate, src, g);
+            HIP_OK(hipEventRecord(a, ctx->stream));
+            for (int r = 0; r < 3; ++r) launch_mv(ctx, B, ctx->stream, prec, gate, src, g);
+            HIP_OK(hipEventRecord(b, ctx->stream));
+            HIP_OK(hipEventSynchronize(b));
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, a, b));
+            if (ms < best_ms * 0.98f) {
+                best_ms = ms;
+                best = g;
+            }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
     }
-    *rn_out = rn;
-    return it;
+    g_mv_grid[key] = best;
+    return best;
+}
+
+// one matvec: part <- off-diagonal partials of v[src]; then the finish kernel
+static void matvec(pcm_ctx *ctx, SolveBatch &B, hipStream_t s, int prec, int gate, int src, int dst, int bvec,
+                   int mode, int grid, bool prof) {
+    {
+        ProfScope ps(prof ? ctx : nullptr, prec == PCM_MIXED ? "matvec_f32" : "matvec_f64", mv_work(B));
+        launch_mv(ctx, B, s, prec, gate, src, grid);
+    }
+    k_mv_finish<<<grid_of(B.n_tiles), TILE, 0, s>>>(B.tab.p, B.st.p, B.tiles.p, B.n_tiles, gate, src, dst, bvec,
+                                                    mode);
+    HIP_LAUNCH_OK();
+}
+
+// one PCG iteration for every molecule still running; par = iteration parity
+static void pcg_iteration(pcm_ctx *ctx, SolveBatch &B, hipStream_t s, int prec, int xi, int par, int grid,
+                          bool rbj, bool prof) {
+    matvec(ctx, B, s, prec, 0, V_P, V_AP, 0, 0, grid, prof);
+    k_cg_update<<<grid_of(B.n_tiles), TILE, 0, s>>>(B.tab.p, B.st.p, B.tiles.p, B.n_tiles, xi, par ^ 1);
+    HIP_LAUNCH_OK();
+    if (rbj) {
+        ProfScope ps(prof ? ctx : nullptr, "rbj_apply", 0.0);
+        k_rbj_items<<<grid_of(B.n_rbj), TILE, 0, s>>>(B.tab.p, B.st.p, B.rbj.p, B.n_rbj);
+        HIP_LAUNCH_OK();
+    }
+    k_cg_dir<<<grid_of(B.n_tiles), TILE, 0, s>>>(B.tab.p, B.st.p, B.tiles.p, B.n_tiles, par, 0,
+                                                 prec == PCM_MIXED ? 1 : 0);
+    HIP_LAUNCH_OK();
+}
+
+// GROUP_K iterations, replayed from a captured graph unless per-kernel profiling is on
+static void launch_group(pcm_ctx *ctx, SolveBatch &B, int prec, int xi, int grid, bool rbj, bool use_graph) {
+    if (!use_graph) {
+        for (int g = 1; g <= GROUP_K; ++g) pcg_iteration(ctx, B, ctx->stream, prec, xi, g & 1, grid, rbj, ctx->prof);
+        return;
+    }
+    const int slot = prec == PCM_MIXED ? 1 : 0;
+    GraphSig sig{B.tab.p, B.st.p, B.mv.p, B.tiles.p, B.rbj.p, B.n_mv, B.n_tiles, B.n_rbj, grid, rbj ? 1 : 0, prec};
+    // xi is fixed per precision: FP64 solves x = V_XQ, mixed inner solves x = V_D
+    if (!B.gexec[slot] || !(B.gsig[slot] == sig)) {
+        if (B.gexec[slot]) HIP_OK(hipGraphExecDestroy(B.gexec[slot]));
+        B.gexec[slot] = nullptr;
+        if (!B.cap) HIP_OK(hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        HIP_OK(hipStreamBeginCapture(B.cap, hipStreamCaptureModeRelaxed));
+        try {
+            for (int g = 1; g <= GROUP_K; ++g) pcg_iteration(ctx, B, B.cap, prec, xi, g & 1, grid, rbj, false);
+        } catch (...) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(B.cap, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            throw;
+        }
+        HIP_OK(hipStreamEndCapture(B.cap, &graph));
+        hipError_t e = hipGraphInstantiate(&B.gexec[slot], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIP_OK(e);
+        B.gsig[slot] = sig;
+    }
+    HIP_OK(hipGraphLaunch(B.gexec[slot], ctx->stream));
+}
+
+// PCG on A x = b for every molecule with act set (state already uploaded: act, tol, max_it);
+// x = v[xi], b = v[bi].  Returns after every molecule has stopped.
+static void pcg_batch(pcm_ctx *ctx, SolveBatch &B, int prec, int xi, int bi, bool zero_x, bool rbj) {
+    hipStream_t s = ctx->stream;
+    int max_it = 0;
+    for (auto &h : B.h_st)
+        if (h.act) max_it = std::max(max_it, h.max_it);
+    const int grid = mv_grid(ctx, B, prec, 1, xi);
+    if (!zero_x) matvec(ctx, B, s, PCM_FP64, 1, xi, V_Y, 0, 2, grid, ctx->prof);
+    k_cg_init<<<grid_of(B.n_tiles), TILE, 0, s>>>(B.tab.p, B.st.p, B.tiles.p, B.n_tiles, xi, bi, zero_x ? 1 : 0);
+    HIP_LAUNCH_OK();
+    if (rbj) {
+        k_rbj_items<<<grid_of(B.n_rbj), TILE, 0, s>>>(B.tab.p, B.st.p, B.rbj.p, B.n_rbj);
+        HIP_LAUNCH_OK();
+    }
+    k_cg_dir<<<grid_of(B.n_tiles), TILE, 0, s>>>(B.tab.p, B.st.p, B.tiles.p, B.n_tiles, 0, 1,
+                                                 prec == PCM_MIXED ? 1 : 0);
+    HIP_LAUNCH_OK();
+    const bool use_graph = !ctx->prof;
+    const int max_groups = max_it / GROUP_K + 2;
+    // launch group j+1 before waiting for the active count of group j: the device never idles
+    int launched = 0, slot = 0;
+    auto group = [&](int sl) {
+        launch_group(ctx, B, prec, xi, grid, rbj, use_graph);
+        k_count_active<<<1, TILE, 0, s>>>(B.st.p, B.n, B.cnt.p);
+        HIP_LAUNCH_OK();
+        HIP_OK(hipMemcpyAsync(B.h_cnt + sl, B.cnt.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipEventRecord(B.ev[sl], s));
+        ++launched;
+    };
+    // a molecule may already be done after the initial residual
+    k_count_active<<<1, TILE, 0, s>>>(B.st.p, B.n, B.cnt.p);
+    HIP_LAUNCH_OK();
+    HIP_OK(hipMemcpyAsync(B.h_cnt + 1, B.cnt.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipEventRecord(B.ev[1], s));
+    HIP_OK(hipEventSynchronize(B.ev[1]));
+    if (B.h_cnt[1] == 0) return;
+    group(slot);
+    while (true) {
+        const int prev = slot;
+        slot ^= 1;
+        const bool more = launched < max_groups;
+        if (more) group(slot);
+        HIP_OK(hipEventSynchronize(B.ev[prev]));
+        if (B.h_cnt[prev] == 0 || !more) break;
+    }
+}
+
+// explicit residual v[V_RES] = b - A64 v[xi] and its squared norm into res2 (act molecules)
+static void residual(pcm_ctx *ctx, SolveBatch &B, int xi, int bi) {
+    const int grid = mv_grid(ctx, B, PCM_FP64, 1, xi);
+    matvec(ctx, B, ctx->stream, PCM_FP64, 1, xi, V_RES, bi, 1, grid, ctx->prof);
+    k_mol_reduce<<<B.n, TILE, 0, ctx->stream>>>(B.tab.p, B.st.p, 0);
+    HIP_LAUNCH_OK();
+}
+
+static void vec_op(pcm_ctx *ctx, SolveBatch &B, int op, double a, int src, int dst,
+                   const std::vector<const double *> *ext) {
+    if (ext) HIP_OK(hipMemcpyAsync(B.ext.p, ext->data(), B.n * sizeof(double *), hipMemcpyHostToDevice, ctx->stream));
+    k_vec_op<<<grid_of(B.n_tiles), TILE, 0, ctx->stream>>>(B.tab.p, B.st.p, B.tiles.p, B.n_tiles, op, a, src, dst,
+                                                           B.ext.p);
+    HIP_LAUNCH_OK();
+}
+
+static void dots3(pcm_ctx *ctx, SolveBatch &B, int a0, int b0, int a1, int b1, int a2, int b2) {
+    k_dots3<<<grid_of(B.n_tiles), TILE, 0, ctx->stream>>>(B.tab.p, B.st.p, B.tiles.p, B.n_tiles, a0, b0, a1, b1, a2,
+                                                          b2);
+    HIP_LAUNCH_OK();
+    k_mol_reduce<<<B.n, TILE, 0, ctx->stream>>>(B.tab.p, B.st.p, 1);
+    HIP_LAUNCH_OK();
+}
+
+static void set_all(SolveBatch &B, int act, double tol, int max_it) {
+    B.h_st.assign(B.n, CGState{});
+    for (auto &h : B.h_st) {
+        h.act = act;
+        h.done = act ? 0 : 1;
+        h.tol = tol;
+        h.max_it = max_it;
+    }
+}
+
+// Solve for every molecule of the batch.  v[i], q[i] are device vectors of molecule i.
+pcm_status solve_batch_run(pcm_ctx *ctx, SolveBatch &B, const std::vector<const double *> &v,
+                           const std::vector<double *> &q, const pcm_solve_opts &o, pcm_solve_info *info) {
+    const int n = B.n;
+    const double f = (ctx->prm.eps - 1.0) / (ctx->prm.eps + ctx->prm.k_factor);
+    const bool rbj = o.precond == PCM_PRECOND_RBJ;
+    auto t0 = std::chrono::steady_clock::now();
+    for (pcm_mol *mol : B.mols) {
+        solver_prepare(ctx, mol);
+        if (rbj) rbj_setup(ctx, mol, o.block, o.seed);
+    }
+    batch_tables(ctx, B, o.precond);
+    std::vector<const double *> qc(q.begin(), q.end());
+    set_all(B, 1, o.tol, o.max_iter);
+    upload_states(ctx, B);
+    vec_op(ctx, B, 0, 0.0, 0, V_V, &v);  // V = v
+    if (o.warm_start)
+        vec_op(ctx, B, 0, 0.0, 0, V_XQ, &qc);
+    else
+        vec_op(ctx, B, 4, 0.0, 0, V_XQ, nullptr);
+    vec_op(ctx, B, 2, -f, V_V, V_B, nullptr);  // b = -f v
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    auto t1 = std::chrono::steady_clock::now();
+    std::vector<int> iters(n, 0), refs(n, 0), conv(n, 0);
+    std::vector<double> rn(n, 0.0);
+    if (o.precision == PCM_MIXED) {
+        // iterative refinement: r = b - A64 q; inner FP32-matvec PCG on A d = r; q += d
+        const double eta = o.inner_rtol > 0 ? o.inner_rtol : 1e-4;
+        std::vector<int> act(n, 1);
+        while (true) {
+            set_all(B, 0, o.tol, 0);
+            for (int i = 0; i < n; ++i) B.h_st[i].act = act[i], B.h_st[i].done = 1;
+            upload_states(ctx, B);
+            residual(ctx, B, V_XQ, V_B);
+            download_states(ctx, B);
+            int n_act = 0;
+            for (int i = 0; i < n; ++i) {
+                if (!act[i]) continue;
+                ++iters[i];
+                rn[i] = std::sqrt(B.h_st[i].res2);
+                if (rn[i] < o.tol) {
+                    conv[i] = 1;
+                    act[i] = 0;
+                } else if (iters[i] >= o.max_iter || refs[i] > 200) {
+                    act[i] = 0;
+                }
+                n_act += act[i];
+            }
+            if (!n_act) break;
+            for (int i = 0; i < n; ++i) {
+                CGState &h = B.h_st[i];
+                h = CGState{};
+                h.act = act[i];
+                h.done = act[i] ? 0 : 1;
+                h.tol = act[i] ? std::max(eta * rn[i], 0.5 * o.tol) : 0.0;
+                h.max_it = act[i] ? std::min(o.max_iter - iters[i], INNER_MAX_IT) : 0;
+            }
+            upload_states(ctx, B);
+            pcg_batch(ctx, B, PCM_MIXED, V_D, V_RES, true, rbj);
+            vec_op(ctx, B, 3, 1.0, V_D, V_XQ, nullptr);  // q += d (act molecules)
+            download_states(ctx, B);
+            for (int i = 0; i < n; ++i)
+                if (act[i]) {
+                    iters[i] += B.h_st[i].it;
+                    ++refs[i];
+                }
+        }
+    } else {
+        pcg_batch(ctx, B, PCM_FP64, V_XQ, V_B, !o.warm_start, rbj);
+        download_states(ctx, B);
+        for (int i = 0; i < n; ++i) {
+            iters[i] = B.h_st[i].it;
+            conv[i] = std::sqrt(B.h_st[i].rr) < o.tol;
+        }
+        // true FP64 residual at exit
+        for (auto &h : B.h_st) h.act = 1;
+        upload_states(ctx, B);
+        residual(ctx, B, V_XQ, V_B);
+        download_states(ctx, B);
+        for (int i = 0; i < n; ++i) rn[i] = std::sqrt(B.h_st[i].res2);
+    }
+    for (auto &h : B.h_st) h.act = 1;
+    upload_states(ctx, B);
+    vec_op(ctx, B, 1, 0.0, V_XQ, 0, &qc);  // q = XQ
+    // Eq. 13 at q: v.q + 1/(2f) q.Aq with A q = b - res
+    dots3(ctx, B, V_V, V_XQ, V_B, V_XQ, V_RES, V_XQ);
+    download_states(ctx, B);
+    auto t2 = std::chrono::steady_clock::now();
+    bool all = true;
+    for (int i = 0; i < n; ++i) {
+        all = all && conv[i];
+        if (!info) continue;
+        pcm_solve_info &I = info[i];
+        I.iters = iters[i];
+        I.refinements = refs[i];
+        I.resid = rn[i];
+        const double *d = B.h_st[i].dots;
+        I.energy = d[0] + 0.5 / f * (d[1] - d[2]);
+        I.setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        I.solve_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    }
+    return all ? PCM_OK : PCM_E_NOCONV;
+}
+
+static SolveBatch &solo(pcm_mol *mol) {
+    if (!mol->solo) mol->solo = solve_batch_new({mol});
+    return *mol->solo;
 }
 
 pcm_status run_solve(pcm_ctx *ctx, pcm_mol *mol, const double *vin, const pcm_solve_opts &o, double *q,
                      pcm_solve_info *info) {
-    const int M = mol->M;
-    ensure_solver_ws(ctx, mol);
-    const double f = (ctx->prm.eps - 1.0) / (ctx->prm.eps + ctx->prm.k_factor);
-    SolverLayout SL = solver_layout(M);
-    double *b = mol->sv.p + SL.b;      // right-hand side -f v
-    double *d = mol->sv.p + SL.d;      // correction (mixed)
-    double *res = mol->sv.p + SL.res;  // FP64 residual
-    DevBuf<double> &hist = mol->hist;
-    hist.ensure((size_t)HS * (o.max_iter + 2) + 16);
-    const int nbk = div_up(M, 256);
-    auto t0 = std::chrono::steady_clock::now();
-    k_scale_copy<<<nbk, 256, 0, ctx->stream>>>(M, -f, vin, b);
-    HIP_LAUNCH_OK();
-    if (!o.warm_start) HIP_OK(hipMemsetAsync(q, 0, sizeof(double) * M, ctx->stream));
-    if (o.precond == PCM_PRECOND_RBJ) rbj_setup(ctx, mol, o.block, o.seed);
-    HIP_OK(hipStreamSynchronize(ctx->stream));
-    auto t1 = std::chrono::steady_clock::now();
-    int iters = 0, refinements = 0;
-    double rn = 0.0;
-    bool conv = false;
-    if (o.precision == PCM_MIXED) {
-        // iterative refinement: r = b - A64 q; inner FP32-matvec PCG on A d = r; q += d
-        double eta = o.inner_rtol > 0 ? o.inner_rtol : 1e-4;
-        while (true) {
-            matvec(ctx, mol, q, res, PCM_FP64, nullptr);
-            ++iters;
-            // res = b - A q
-            k_scale_copy<<<nbk, 256, 0, ctx->stream>>>(M, -1.0, res, res);
-            k_axpy<<<nbk, 256, 0, ctx->stream>>>(M, 1.0, b, res);
-            HIP_LAUNCH_OK();
-            double rr = dev_dot(ctx, mol, res, res, M);
-            rn = sqrt(rr);
-            if (rn < o.tol) {
-                conv = true;
-                break;
-            }
-            if (iters >= o.max_iter) break;
-            HIP_OK(hipMemsetAsync(d, 0, sizeof(double) * M, ctx->stream));
-            double rin = 0.0;
-            int left = o.max_iter - iters;
-            int n = pcg_run(ctx, mol, res, d, true, std::max(eta * rn, 0.5 * o.tol), left, o.precond, PCM_MIXED,
-                            hist.p, &rin);
-            iters += n;
-            k_axpy<<<nbk, 256, 0, ctx->stream>>>(M, 1.0, d, q);
-            HIP_LAUNCH_OK();
-            ++refinements;
-            if (refinements > 200) break;
-        }
-    } else {
-        double rin = 0.0;
-        iters = pcg_run(ctx, mol, b, q, !o.warm_start, o.tol, o.max_iter, o.precond, PCM_FP64, hist.p, &rin);
-        // true FP64 residual at exit
-        matvec(ctx, mol, q, res, PCM_FP64, nullptr);
-        k_scale_copy<<<nbk, 256, 0, ctx->stream>>>(M, -1.0, res, res);
-        k_axpy<<<nbk, 256, 0, ctx->stream>>>(M, 1.0, b, res);
-        HIP_LAUNCH_OK();
-        rn = sqrt(dev_dot(ctx, mol, res, res, M));
-        conv = rin < o.tol;
-    }
-    HIP_OK(hipStreamSynchronize(ctx->stream));
-    auto t2 = std::chrono::steady_clock::now();
-    if (info) {
-        info->iters = iters;
-        info->refinements = refinements;
-        info->resid = rn;
-        // Eq. 13 at q: v.q + 1/(2f) q.Aq with A q = b - res
-        double vq = dev_dot(ctx, mol, vin, q, M);
-        double bq = dev_dot(ctx, mol, b, q, M);
-        double rq = dev_dot(ctx, mol, res, q, M);
-        info->energy = vq + 0.5 / f * (bq - rq);
-        info->setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-        info->solve_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
-    }
-    return conv ? PCM_OK : PCM_E_NOCONV;
+    return solve_batch_run(ctx, solo(mol), {vin}, {q}, o, info);
 }
 
+// E = bz.q + c.q + q.Aq / (2f)  (Eq. 13)
 double run_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double *c, const double *q) {
-    ensure_solver_ws(ctx, mol);
-    const int M = mol->M;
+    SolveBatch &B = solo(mol);
+    solver_prepare(ctx, mol);
+    if (B.n_tiles == 0) batch_tables(ctx, B, PCM_PRECOND_NONE);  // item tables do not depend on precond
     const double f = (ctx->prm.eps - 1.0) / (ctx->prm.eps + ctx->prm.k_factor);
-    double *Aq = mol->sv.p + solver_layout(M).res;
-    matvec(ctx, mol, q, Aq, PCM_FP64, nullptr);
-    double e1 = dev_dot(ctx, mol, bz, q, M);
-    double e2 = dev_dot(ctx, mol, c, q, M);
-    double e3 = dev_dot(ctx, mol, q, Aq, M);
-    return e1 + e2 + 0.5 / f * e3;
-}
-
-// ----------------------------------------------------------------------------------------
-// host partition (Sec. 4b-ii); built with IEEE double and no contraction so that the ranking
-// values are the plain expressions erf(z' d)/d, z' = z_k z_l / sqrt(z_k^2 + z_l^2).  For
-// z' d >= 6 erf rounds to exactly 1 in double precision, so 1/d is the same value.
-// The l-1 best candidates of a pivot are kept in a bounded heap.  Because |A_kl| <= 1/d, a
-// candidate farther than 1/(worst kept value) cannot enter and is rejected from its distance
-// alone; the ranking is a total order (value, then index), so the selected set is the same as
-// a full sort would give.
-// ----------------------------------------------------------------------------------------
-static inline uint64_t splitmix64_next(uint64_t &s) {
-    uint64_t z = (s += 0x9e3779b97f4a7c15ULL);
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
-    return z ^ (z >> 31);
-}
-
-#pragma clang fp contract(off)
-static inline double coupling(const double *r, const double *zeta, int k, int l) {
-    double zk = zeta[k], zl = zeta[l];
-    double zp = zk * zl / std::sqrt(zk * zk + zl * zl);
-    double dx = r[3 * k] - r[3 * l], dy = r[3 * k + 1] - r[3 * l + 1], dz = r[3 * k + 2] - r[3 * l + 2];
-    double d = std::sqrt(dx * dx + dy * dy + dz * dz);
-    if (d == 0.0) return 2.0 * zp / std::sqrt(M_PI);
-    double x = zp * d;
-    if (x >= 6.0) return 1.0 / d;
-    return std::erf(x) / d;
-}
-
-int host_rbj_partition(int M, const double *r, const double *zeta, int l, unsigned long long seed, int *perm,
-                       int *blk_off) {
-    if (M <= 0 || l <= 0 || !r || !zeta || !perm || !blk_off) return -1;
-    // unassigned indices: a Fenwick tree over [0, M) answers "k-th unassigned in ascending
-    // order" for the pivot pick; the scan list is compacted lazily
-    std::vector<int> bit(M + 1, 0);
-    for (int i = 1; i <= M; ++i) {
-        bit[i] += 1;
-        int j = i + (i & -i);
-        if (j <= M) bit[j] += bit[i];
-    }
-    int top_pow = 1;
-    while (top_pow * 2 <= M) top_pow *= 2;
-    auto kth = [&](int k) {  // 0-based k-th unassigned index
-        int p0 = 0;
-        for (int step = top_pow; step > 0; step >>= 1)
-            if (p0 + step <= M && bit[p0 + step] <= k) {
-                p0 += step;
-                k -= bit[p0];
-            }
-        return p0;  // index (0-based) of the element
-    };
-    auto remove = [&](int i) {
-        for (int j = i + 1; j <= M; j += j & -j) bit[j] -= 1;
-    };
-    std::vector<int> left(M);
-    std::iota(left.begin(), left.end(), 0);
-    int n_scan = M;  // entries in left[], some possibly assigned already
-    std::vector<unsigned char> take(M, 0);
-    using Cand = std::pair<double, int>;
-    // heap ordered so that top() is the worst kept candidate (smallest value, then largest index)
-    auto better = [](const Cand &a, const Cand &b) {
-        return a.first > b.first || (a.first == b.first && a.second < b.second);
-    };
-    std::vector<Cand> heap;
-    heap.reserve(std::min(l, M) + 1);
-    uint64_t st = seed;
-    int n_left = M, nb = 0, filled = 0;
-    blk_off[0] = 0;
-    while (n_left > 0) {
-        uint64_t x = splitmix64_next(st);
-        double u = (double)(x >> 11) * (1.0 / 9007199254740992.0);
-        int pos = (int)std::floor(u * (double)n_left);
-        if (pos >= n_left) pos = n_left - 1;
-        const int piv = kth(pos);
-        const int want = std::min(l - 1, n_left - 1);
-        heap.clear();
-        if (want > 0) {
-            if (n_scan > 2 * n_left) {  // drop assigned entries before scanning
-                int w = 0;
-                for (int t = 0; t < n_scan; ++t)
-                    if (!take[left[t]]) left[w++] = left[t];
-                n_scan = w;
-            }
-            const double px = r[3 * piv], py = r[3 * piv + 1], pz = r[3 * piv + 2];
-            double reject_d2 = 1e300;  // candidates with d^2 above this cannot enter the heap
-            for (int t = 0; t < n_scan; ++t) {
-                const int q = left[t];
-                if (q == piv || take[q]) continue;
-                const double dx = px - r[3 * q], dy = py - r[3 * q + 1], dz = pz - r[3 * q + 2];
-                const double d2 = dx * dx + dy * dy + dz * dz;
-                if ((int)heap.size() == want && d2 > reject_d2) continue;  // |A| <= 1/d < worst kept
-                Cand c(std::fabs(coupling(r, zeta, piv, q)), q);
-                if ((int)heap.size() < want) {
-                    heap.push_back(c);
-                    std::push_heap(heap.begin(), heap.end(), better);
-                } else if (better(c, heap.front())) {
-                    std::pop_heap(heap.begin(), heap.end(), better);
-                    heap.back() = c;
-                    std::push_heap(heap.begin(), heap.end(), better);
-                } else {
-                    continue;
-                }
-                if ((int)heap.size() == want) {
-                    const double w = heap.front().first;
-                    // |A| <= 1/d: reject when d^2 w^2 > 1 (with a relative margin far above rounding)
-                    reject_d2 = w > 0.0 ? (1.0 + 1e-9) / (w * w) : 1e300;
-                }
-            }
-        }
-        int start = filled;
-        perm[filled++] = piv;
-        take[piv] = 1;
-        remove(piv);
-        for (const Cand &c : heap) {
-            perm[filled++] = c.second;
-            take[c.second] = 1;
-            remove(c.second);
-        }
-        std::sort(perm + start, perm + filled);
-        n_left -= filled - start;
-        blk_off[++nb] = filled;
-    }
-    return nb;
+    set_all(B, 1, 0.0, 0);
+    upload_states(ctx, B);
+    std::vector<const double *> e_q{q}, e_bz{bz}, e_c{c};
+    vec_op(ctx, B, 0, 0.0, 0, V_T, &e_q);
+    vec_op(ctx, B, 0, 0.0, 0, V_V, &e_bz);
+    vec_op(ctx, B, 0, 0.0, 0, V_RES, &e_c);
+    const int grid = mv_grid(ctx, B, PCM_FP64, 1, V_T);
+    matvec(ctx, B, ctx->stream, PCM_FP64, 1, V_T, V_Y, 0, 2, grid, ctx->prof);
+    dots3(ctx, B, V_V, V_T, V_RES, V_T, V_T, V_Y);
+    download_states(ctx, B);
+    const double *d = B.h_st[0].dots;
+    return d[0] + d[1] + 0.5 / f * d[2];
 }

@@ -128,6 +128,14 @@ def test_null_arguments(L):
     assert L.pcm_energy(ctx, None, None, None, None, None) == _lib.PCM_E_ARG
     assert L.pcm_esp(None, None, None, None, None) == _lib.PCM_E_ARG
     assert L.pcm_mol_sizes(None, None, None, None, None, None, None, None) == _lib.PCM_E_ARG
+    out = ctypes.c_void_p()
+    assert L.pcm_batch_create(ctx, None, 0, ctypes.byref(out)) == _lib.PCM_E_ARG
+    assert not out.value
+    nulls = (ctypes.c_void_p * 2)(None, None)
+    assert L.pcm_batch_create(ctx, nulls, 2, ctypes.byref(out)) == _lib.PCM_E_ARG
+    assert L.pcm_batch_create(ctx, nulls, 2, None) == _lib.PCM_E_ARG
+    assert L.pcm_solve_batched(ctx, None, None, None, None, None) == _lib.PCM_E_ARG
+    L.pcm_batch_destroy(None)
     L.pcm_destroy(ctx)
 
 
