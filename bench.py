@@ -11,7 +11,14 @@ passes: c, F and the gradient), with the PCG solve time and its residual reporte
 it, for the FP64 path and for the mixed form (FP32 evaluation, FP64 accumulation, FP32
 matvec inside FP64 refinement).  Inputs are synthetic and seeded (see synth/inputs.py).
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+Second workload (--workload conformers64): 64 seeded conformers of a 150-atom peptide
+(6-31G-shaped basis, nbf 825, 3.9k-9k kept points each).  One step = c = L P with Bz,
+the RBJ-100 PCG solve, the Eq. 13 energy and F += L^T q for all 64, batched (one launch per
+class for the integrals, hipGraph-replayed PCG iteration groups over all conformers),
+against the same 64 done one after another with the plain FP64 single-molecule calls.
+The geometries are fixed, so surfaces, pair lists and RBJ blocks are built before timing.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload protein600|conformers64]
 """
 from __future__ import annotations
 
@@ -92,11 +99,14 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--block", type=int, default=100)
+    ap.add_argument("--workload", default="protein600", choices=["protein600", "conformers64"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding of the path is "
                                    "described in DESIGN.md but not built", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "conformers64":
+        return bench_conformers(args)
 
     import numpy as np
     import torch
@@ -234,6 +244,89 @@ def main():
         if "mixed" in out:
             c_m = rmx["state"]["c"].cpu().numpy()[kidx]
             out["mixed"]["c_sample_rel_err_vs_oracle"] = float(np.abs(c_m - c_or).max() / np.abs(c_or).max())
+    print(json.dumps(out))
+
+
+def bench_conformers(args):
+    import numpy as np
+    import torch
+
+    from paper_1505_07851_amd import Batch, Context, Molecule
+    from synth import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    n_conf = 64
+    t = time.time()
+    systems = [I.conformer(j) for j in range(n_conf)]
+    log(f"[bench] {n_conf} conformers generated in {time.time() - t:.1f}s")
+    Ps = [torch.tensor(s.P, dtype=torch.float64, device="cuda") for s in systems]
+    kw = dict(precond="rbj", block=args.block, seed=7, tol=args.tol, max_iter=10000)
+
+    def setup(prec):
+        ctx = Context(precision=prec)
+        mols = [Molecule.from_system(ctx, s) for s in systems]
+        return ctx, mols
+
+    def seq_step(mols):
+        out = []
+        for m, P in zip(mols, Ps):
+            c, bz = m.esp(P)
+            q, info = m.solve(bz + c, **kw)
+            F = m.fock(q)
+            out.append((q, info, F))
+        return out
+
+    def batch_step(b, prec):
+        cs, bzs = b.esp(Ps)
+        qs, infos = b.solve([bz + c for c, bz in zip(cs, bzs)], precision=prec, **kw)
+        Fs = b.fock(qs)
+        return list(zip(qs, infos, Fs))
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps * 1e3, res
+
+    ctx64, mols64 = setup("fp64")
+    M = [m.M for m in mols64]
+    log(f"[bench] surfaces built: M min {min(M)} max {max(M)} mean {np.mean(M):.0f}, nbf {mols64[0].nbf}")
+    ms_seq, r_seq = timed(lambda: seq_step(mols64))
+    log(f"[bench] sequential FP64: {ms_seq:.1f} ms per step")
+    b64 = Batch(ctx64, mols64)
+    ms_b64, r_b64 = timed(lambda: batch_step(b64, "fp64"))
+    log(f"[bench] batched FP64: {ms_b64:.1f} ms per step")
+    ctxm, molsm = setup("mixed")
+    bm = Batch(ctxm, molsm)
+    ms_bm, r_bm = timed(lambda: batch_step(bm, "mixed"))
+    log(f"[bench] batched mixed: {ms_bm:.1f} ms per step")
+
+    def errs(res):
+        dE = max(abs(r[1]["energy"] - s[1]["energy"]) for r, s in zip(res, r_seq))
+        dq = max((r[0] - s[0]).abs().max().item() / s[0].abs().max().item() for r, s in zip(res, r_seq))
+        dF = max((r[2] - s[2]).abs().max().item() / s[2].abs().max().item() for r, s in zip(res, r_seq))
+        bitwise = all(torch.equal(r[0], s[0]) and torch.equal(r[2], s[2]) for r, s in zip(res, r_seq))
+        return {"E_abs_max": dE, "q_rel_max": dq, "F_rel_max": dF, "bitwise_equal": bitwise}
+
+    iters = [r[1]["iters"] for r in r_seq]
+    out = {"metric": "conformers/s (64-conformer batch: c = L P, PCG solve, energy, F += L^T q)",
+           "value": n_conf / (ms_b64 * 1e-3), "unit": "conformers/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_b64, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "conformers64_peptide150_631g", "conformers": n_conf, "atoms": 150,
+                      "nbf": mols64[0].nbf, "M_min": min(M), "M_max": max(M), "M_mean": round(float(np.mean(M)), 1),
+                      "precond": f"rbj{args.block}", "tol": args.tol},
+           "sequential_fp64": {"ms_per_step": round(ms_seq, 3), "ms_per_conformer": round(ms_seq / n_conf, 3),
+                               "pcg_iters_min": min(iters), "pcg_iters_max": max(iters)},
+           "batched_fp64": {"ms_per_step": round(ms_b64, 3), "ms_per_conformer": round(ms_b64 / n_conf, 3),
+                            "speedup_vs_sequential": round(ms_seq / ms_b64, 3), "err_vs_sequential": errs(r_b64)},
+           "batched_mixed": {"ms_per_step": round(ms_bm, 3), "ms_per_conformer": round(ms_bm / n_conf, 3),
+                             "speedup_vs_sequential": round(ms_seq / ms_bm, 3), "err_vs_sequential": errs(r_bm)}}
     print(json.dumps(out))
 
 

@@ -67,10 +67,16 @@ typedef struct pcm_batch pcm_batch;
  *   diag_const     constant of Eq. 3: A_kk = diag_const * zeta_k / S_k. Default sqrt(2/pi),
  *                  the r -> 0 limit of Eq. 2 for two equal Gaussians.
  *   precision      PCM_FP64 or PCM_MIXED for the integral kernels (FP32 Hermite/Boys
- *                  evaluation with FP64 accumulation). Default PCM_FP64. */
+ *                  evaluation with FP64 accumulation). Default PCM_FP64.
+ *   autotune       1 (default): on first use of an integral kernel for a (class, precision,
+ *                  size bucket) the library times a few pair/point chunk shapes and keeps the
+ *                  fastest for the life of the context; results then depend on that choice
+ *                  within rounding (chunk partial sums are added in a fixed order, so repeated
+ *                  calls in one context are bitwise identical).  0: fixed shapes. */
 typedef struct {
     double eps, k_factor, zeta0, switch_thresh, schwarz_thresh, diag_const;
     int precision;
+    int autotune;
 } pcm_params;
 
 void pcm_default_params(pcm_params *p);
@@ -224,6 +230,19 @@ void pcm_mol_destroy(pcm_mol *mol);
  * count, so destroy it before any of its molecules.  Errors: PCM_E_ARG. */
 pcm_status pcm_batch_create(pcm_ctx *ctx, pcm_mol *const *mols, int n, pcm_batch **out);
 void pcm_batch_destroy(pcm_batch *batch);
+
+/* pcm_esp for every molecule of the batch (Sec. 2, Eqs. 5-6, 12, 18): the density-screened
+ * pair lists are built per molecule, then one launch per angular class evaluates every
+ * molecule's pairs against its points.  HOST arrays of DEVICE pointers P[n] (nbf_i^2),
+ * c[n] (M_i, written); bz may be NULL, or hold DEVICE pointers (NULL entries skipped).
+ * Molecule i gets bitwise the c of pcm_esp on the same context. */
+pcm_status pcm_esp_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *P, double *const *c,
+                           double *const *bz);
+
+/* pcm_fock for every molecule of the batch (Sec. 2, Eq. 10; Sec. 4a, Eqs. 16-17): one launch
+ * per angular class for the point sums, then per-molecule contraction into F.  HOST arrays
+ * of DEVICE pointers q[n] (M_i), F[n] (nbf_i^2, accumulated). */
+pcm_status pcm_fock_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *q, double *const *F);
 
 /* pcm_solve for every molecule of the batch at once (Sec. 2, Eq. 1; Sec. 4b).  HOST arrays
  * of DEVICE pointers v[n] and q[n] (molecule i: v[i][M_i], q[i][M_i]); HOST info[n] (may be

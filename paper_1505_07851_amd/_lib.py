@@ -19,14 +19,15 @@ PCM_PRECOND_NONE, PCM_PRECOND_JACOBI, PCM_PRECOND_RBJ = 0, 1, 2
 EXPORTED = ["pcm_default_params", "pcm_default_solve_opts", "pcm_create", "pcm_destroy", "pcm_last_error",
             "pcm_build_surface", "pcm_update_geometry", "pcm_esp", "pcm_fock", "pcm_solve", "pcm_energy", "pcm_grad",
             "pcm_dynamic_threshold", "pcm_rbj_partition", "pcm_surface_get", "pcm_mol_sizes", "pcm_pair_list",
-            "pcm_mol_destroy", "pcm_batch_create", "pcm_batch_destroy", "pcm_solve_batched",
+            "pcm_mol_destroy", "pcm_batch_create", "pcm_batch_destroy", "pcm_esp_batched", "pcm_fock_batched",
+            "pcm_solve_batched",
             "pcm_profile_enable", "pcm_profile_collect", "pcm_profile_entry"]
 
 
 class pcm_params(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("k_factor", ctypes.c_double), ("zeta0", ctypes.c_double),
                 ("switch_thresh", ctypes.c_double), ("schwarz_thresh", ctypes.c_double),
-                ("diag_const", ctypes.c_double), ("precision", ctypes.c_int)]
+                ("diag_const", ctypes.c_double), ("precision", ctypes.c_int), ("autotune", ctypes.c_int)]
 
 
 class pcm_basis(ctypes.Structure):
@@ -74,6 +75,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "pcm_mol_destroy": (None, [vp]),
         "pcm_batch_create": (i, [vp, P(vp), i, P(vp)]),
         "pcm_batch_destroy": (None, [vp]),
+        "pcm_esp_batched": (i, [vp, vp, P(vp), P(vp), P(vp)]),
+        "pcm_fock_batched": (i, [vp, vp, P(vp), P(vp)]),
         "pcm_solve_batched": (i, [vp, vp, P(vp), P(pcm_solve_opts), P(vp), P(pcm_solve_info)]),
         "pcm_profile_enable": (i, [vp, i]),
         "pcm_profile_collect": (i, [vp]),

@@ -52,7 +52,7 @@ class Context:
     """Library context: model parameters, device, stream."""
 
     def __init__(self, eps=78.39, k_factor=0.0, zeta0=4.9, switch_thresh=1e-8, schwarz_thresh=1e-12,
-                 diag_const=None, precision="fp64", stream=None, device=None):
+                 diag_const=None, precision="fp64", stream=None, device=None, autotune=True):
         import torch
         self.lib = C.lib()
         if device is not None:
@@ -65,6 +65,7 @@ class Context:
         if diag_const is not None:
             p.diag_const = diag_const
         p.precision = C.PCM_MIXED if precision == "mixed" else C.PCM_FP64
+        p.autotune = 1 if autotune else 0
         self.params = p
         self.precision = precision
         if stream is None:
@@ -273,6 +274,27 @@ class Batch:
         h = ctypes.c_void_p()
         ctx.check(ctx.lib.pcm_batch_create(ctx.h, arr, n, ctypes.byref(h)))
         self.h = h
+
+    def _ptrs(self, ts):
+        return (ctypes.c_void_p * len(ts))(*[_dp(t) for t in ts])
+
+    def esp(self, Ps, want_bz=True):
+        """(list of c, list of Bz or None) for every molecule (Eqs. 4-6)."""
+        Ps = [_f64(P, m.nbf * m.nbf, "P").contiguous() for P, m in zip(Ps, self.mols)]
+        cs = [m._zeros(m.M) for m in self.mols]
+        bzs = [m._zeros(m.M) for m in self.mols] if want_bz else None
+        st = self.ctx.lib.pcm_esp_batched(self.ctx.h, self.h, self._ptrs(Ps), self._ptrs(cs),
+                                          self._ptrs(bzs) if want_bz else None)
+        self.ctx.check(st)
+        return cs, bzs
+
+    def fock(self, qs, Fs=None):
+        """F_i += sum_k q_ik L_i^k for every molecule (Eq. 10); returns the list of F."""
+        qs = [_f64(q, m.M, "q").contiguous() for q, m in zip(qs, self.mols)]
+        if Fs is None:
+            Fs = [m._zeros(m.nbf, m.nbf) for m in self.mols]
+        self.ctx.check(self.ctx.lib.pcm_fock_batched(self.ctx.h, self.h, self._ptrs(qs), self._ptrs(Fs)))
+        return Fs
 
     def solve(self, vs, precond="jacobi", block=100, seed=0, tol=1e-6, max_iter=10000, q0s=None,
               precision="fp64", inner_rtol=1e-4, qs=None, raise_noconv=True):

@@ -161,6 +161,7 @@ void pcm_default_params(pcm_params *p) {
     p->schwarz_thresh = 1e-12;
     p->diag_const = std::sqrt(2.0 / M_PI);
     p->precision = PCM_FP64;
+    p->autotune = 1;
 }
 
 void pcm_default_solve_opts(pcm_solve_opts *o) {
@@ -184,7 +185,7 @@ pcm_status pcm_create(const pcm_params *params, void *hip_stream, pcm_ctx **out)
     if (!is_fin(p.eps) || !(p.eps > 1.0) || !is_fin(p.k_factor) || p.k_factor < 0.0 || !is_fin(p.zeta0) ||
         !(p.zeta0 > 0.0) || !is_fin(p.switch_thresh) || p.switch_thresh < 0.0 || !is_fin(p.schwarz_thresh) ||
         p.schwarz_thresh < 0.0 || !is_fin(p.diag_const) || !(p.diag_const > 0.0) ||
-        (p.precision != PCM_FP64 && p.precision != PCM_MIXED))
+        (p.precision != PCM_FP64 && p.precision != PCM_MIXED) || (p.autotune != 0 && p.autotune != 1))
         return PCM_E_ARG;
     pcm_ctx *c = new (std::nothrow) pcm_ctx();
     if (!c) return PCM_E_ALLOC;
@@ -553,6 +554,38 @@ void pcm_batch_destroy(pcm_batch *batch) {
     if (!batch) return;
     if (batch->solve) solve_batch_free(batch->solve);
     delete batch;
+}
+
+pcm_status pcm_esp_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *P, double *const *c,
+                           double *const *bz) {
+    if (!ctx) return PCM_E_ARG;
+    if (!batch || !P || !c) return fail(ctx, PCM_E_ARG, "NULL argument");
+    const int n = (int)batch->mols.size();
+    for (int i = 0; i < n; ++i)
+        if (!P[i] || !c[i]) return fail(ctx, PCM_E_ARG, "NULL matrix or vector in batch");
+    return guarded(ctx, [&]() -> pcm_status {
+        ctx_ensure_device(ctx);
+        for (int i = 0; i < n; ++i) density_list(ctx, batch->mols[i], P[i]);
+        run_esp_batch(ctx, batch->mols, std::vector<double *>(c, c + n), ctx->prm.precision);
+        if (bz)
+            for (int i = 0; i < n; ++i)
+                if (bz[i]) run_bz(ctx, batch->mols[i], bz[i]);
+        return PCM_OK;
+    });
+}
+
+pcm_status pcm_fock_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *q, double *const *F) {
+    if (!ctx) return PCM_E_ARG;
+    if (!batch || !q || !F) return fail(ctx, PCM_E_ARG, "NULL argument");
+    const int n = (int)batch->mols.size();
+    for (int i = 0; i < n; ++i)
+        if (!q[i] || !F[i]) return fail(ctx, PCM_E_ARG, "NULL matrix or vector in batch");
+    return guarded(ctx, [&]() -> pcm_status {
+        ctx_ensure_device(ctx);
+        run_fock_batch(ctx, batch->mols, std::vector<const double *>(q, q + n), std::vector<double *>(F, F + n),
+                       ctx->prm.precision);
+        return PCM_OK;
+    });
 }
 
 pcm_status pcm_solve_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *v, const pcm_solve_opts *opts,

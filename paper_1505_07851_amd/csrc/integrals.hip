@@ -16,54 +16,113 @@
 // accumulates V_tuv in registers.  Pair lists and point arrays are padded with
 // zero-contribution entries so batches never need a tail.  Partial results per chunk are
 // reduced afterwards in a fixed order, so results are bitwise reproducible.
+//
+// Batching.  One launch per angular class covers every molecule of a batch: work items are
+// (molecule, tile, chunk) triples located through per-molecule descriptors; the workgroups
+// are persistent (the Boys table is staged into LDS once per workgroup).  The chunk shape of
+// each (class, size bucket) is chosen by timing a few candidates on first use.
 #include "pcm_internal.h"
 
+#include <algorithm>
+#include <array>
+#include <cstring>
+
 // ----------------------------------------------------------------------------------------
-// esp: partial c over one chunk of pairs of one class
+// Work items.  A launch covers one class for a set of molecules; each (molecule, class) has
+// a descriptor with the base index of its items, and an item index maps to (molecule, tile,
+// chunk) by a binary search over the bases, so the tables stay one entry per molecule.
+// ----------------------------------------------------------------------------------------
+struct EspDesc {
+    const unsigned char *rec;  // class records (header + D_tuv), padded to REC_PAD
+    const void *pts;           // PtInt<T> [Mpad]
+    double *part;              // partial rows of this molecule
+    long long base;            // first item
+    int M, stride, n_pad, chunk, ntile, row0;
+};
+
+struct FockDesc {
+    const unsigned char *rec;  // class headers
+    const void *pts;           // PtInt<T> [Mpad]
+    const double *q;           // charges, zero past M [Mpad]
+    double *vout;              // [nch][NT][n_pairs]
+    long long base;
+    int n_pairs, Mpad, chunk, nptile, stride;
+};
+
+struct SumDesc {
+    const double *part;
+    double *out;
+    long long base;
+    int M, rows;
+};
+
+template <typename D> __device__ __forceinline__ int find_desc(const D *__restrict__ ds, int nd, long long it) {
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (ds[mid].base <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ----------------------------------------------------------------------------------------
+// esp: partial c over one chunk of pairs of one class; lane = surface point
 // ----------------------------------------------------------------------------------------
 template <int L, typename T>
-__global__ __launch_bounds__(256) void k_esp(const unsigned char *__restrict__ rec, int stride, int n_pad,
-                                             int chunk_len, const PtInt<T> *__restrict__ pts, int M,
-                                             const T *__restrict__ boys_g, double *__restrict__ part, int row0) {
+__global__ __launch_bounds__(256) void k_esp(const EspDesc *__restrict__ ds, int nd, long long n_items,
+                                             const T *__restrict__ boys_g) {
     constexpr int NT = ntuv(L), PB = pair_batch<L>();
     __shared__ T tab[BoysCfg<T>::NROW * BoysCfg<T>::MT];
     load_boys<T>(tab, boys_g);
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const PtInt<T> me = pts[k < M ? k : M - 1];
-    const int p0 = blockIdx.y * chunk_len;
-    const int p1 = min(n_pad, p0 + chunk_len);
-    double acc = 0.0;
-    for (int ip = p0; ip < p1; ip += PB) {
-        PairHdr<T> h[PB];
-        T D[PB][NT];
+    for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const EspDesc &d = ds[find_desc(ds, nd, it)];
+        const long long local = it - d.base;
+        const int tile = (int)(local % d.ntile), ch = (int)(local / d.ntile);
+        const cptr<unsigned char> rec = as_const(d.rec);
+        const PtInt<T> *__restrict__ pts = reinterpret_cast<const PtInt<T> *>(d.pts);
+        const int M = d.M, stride = d.stride;
+        const int k = tile * 256 + threadIdx.x;
+        const PtInt<T> me = pts[k < M ? k : M - 1];
+        const int p0 = ch * d.chunk;
+        const int p1 = min(d.n_pad, p0 + d.chunk);
+        double acc = 0.0;
+        for (int ip = p0; ip < p1; ip += PB) {
+            PairHdr<T> h[PB];
+            T D[PB][NT];
 #pragma unroll
-        for (int b = 0; b < PB; ++b) {
-            const unsigned char *r = rec + (size_t)(ip + b) * stride;
-            h[b] = *reinterpret_cast<const PairHdr<T> *>(r);
-            const T *d = reinterpret_cast<const T *>(r + sizeof(PairHdr<T>));
+            for (int b = 0; b < PB; ++b) {
+                const cptr<unsigned char> r = rec + (size_t)(ip + b) * stride;
+                h[b] = *(cptr<PairHdr<T>>)(r);
+                const cptr<T> dd = (cptr<T>)(r + sizeof(PairHdr<T>));
 #pragma unroll
-            for (int t = 0; t < NT; ++t) D[b][t] = d[t];
+                for (int t = 0; t < NT; ++t) D[b][t] = dd[t];
+            }
+#pragma unroll
+            for (int b = 0; b < PB; ++b) {
+                T R[NT];
+                eval_R<L, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
+                             R);
+                T s = T(0);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) s = fma(D[b][t], R[t], s);
+                acc += (double)s;
+            }
         }
-#pragma unroll
-        for (int b = 0; b < PB; ++b) {
-            T R[NT];
-            eval_R<L, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab, R);
-            T s = T(0);
-#pragma unroll
-            for (int t = 0; t < NT; ++t) s = fma(D[b][t], R[t], s);
-            acc += (double)s;
-        }
+        if (k < M) d.part[(size_t)(d.row0 + ch) * M + k] = acc;
     }
-    if (k < M) part[(size_t)(row0 + blockIdx.y) * M + k] = acc;
 }
 
-// fixed-order sum of partial rows: out[k] = sum_r part[r*M + k]
-__global__ void k_sum_rows(const double *__restrict__ part, int rows, int M, double *__restrict__ out) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= M) return;
-    double s = 0.0;
-    for (int r = 0; r < rows; ++r) s += part[(size_t)r * M + k];
-    out[k] = s;
+// fixed-order sum of partial rows: out[k] = sum_r part[r*M + k]; item = 256 points
+__global__ __launch_bounds__(256) void k_sum_rows(const SumDesc *__restrict__ ds, int nd, long long n_items) {
+    for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const SumDesc &d = ds[find_desc(ds, nd, it)];
+        const int k = (int)(it - d.base) * 256 + threadIdx.x;
+        if (k >= d.M) continue;
+        double s = 0.0;
+        for (int r = 0; r < d.rows; ++r) s += d.part[(size_t)r * d.M + k];
+        d.out[k] = s;
+    }
 }
 
 // ----------------------------------------------------------------------------------------
@@ -99,118 +158,50 @@ void run_bz(pcm_ctx *ctx, pcm_mol *mol, double *bz) {
 }
 
 // ----------------------------------------------------------------------------------------
-// launch geometry
-// ----------------------------------------------------------------------------------------
-static int target_groups() { return 4096; }
-
-static int esp_chunk_len(long long n_pairs, int M) {
-    int tiles = M > 0 ? div_up(M, 256) : 1;
-    long long want = (target_groups() + tiles - 1) / tiles;
-    if (want < 1) want = 1;
-    long long len = (n_pairs + want - 1) / want;
-    if (len < 16) len = 16;
-    return (int)((len + REC_PAD - 1) / REC_PAD * REC_PAD);
-}
-
-template <typename T> static const T *boys_tab(pcm_ctx *ctx);
-template <> const double *boys_tab<double>(pcm_ctx *ctx) { return ctx->boys64.p; }
-template <> const float *boys_tab<float>(pcm_ctx *ctx) { return ctx->boys32.p; }
-template <typename T> static const PtInt<T> *points(pcm_mol *mol) {
-    return reinterpret_cast<const PtInt<T> *>(sizeof(T) == 8 ? mol->pti64.p : mol->pti32.p);
-}
-
-template <typename T>
-static void esp_launch(pcm_ctx *ctx, pcm_mol *mol, double *c) {
-    PairList &pl = mol->esp;
-    const int M = mol->M;
-    int rows = 0;
-    int chunk[NCLS];
-    for (int cl = 0; cl < NCLS; ++cl) {
-        long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
-        chunk[cl] = n ? esp_chunk_len(n, M) : REC_PAD;
-        rows += n ? div_up(n, chunk[cl]) : 0;
-    }
-    if (rows == 0) {
-        HIP_OK(hipMemsetAsync(c, 0, sizeof(double) * M, ctx->stream));
-        return;
-    }
-    mol->part.ensure((size_t)rows * M);
-    const T *tab = boys_tab<T>(ctx);
-    int row0 = 0;
-    for (int cl = 0; cl < NCLS; ++cl) {
-        long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
-        if (!n) continue;
-        int L = CLS_LA[cl] + CLS_LB[cl];
-        int n_pad = (int)((n + REC_PAD - 1) / REC_PAD * REC_PAD);
-        int nch = div_up(n, chunk[cl]);
-        dim3 grid(div_up(M, 256), nch);
-        const unsigned char *rec = pl.rec.p + pl.rec_off[cl];
-        int stride = (int)rec_stride<T>(L);
-        {
-            ProfScope ps(ctx, "esp_L" + std::to_string(L) + (sizeof(T) == 8 ? "_f64" : "_f32"), (double)n * M);
-            switch (L) {
-#define ESP_CASE(LL)                                                                                                  \
-    case LL:                                                                                                          \
-        k_esp<LL, T><<<grid, 256, 0, ctx->stream>>>(rec, stride, n_pad, chunk[cl], points<T>(mol), M, tab, mol->part.p, \
-                                                    row0);                                                             \
-        break;
-                ESP_CASE(0) ESP_CASE(1) ESP_CASE(2) ESP_CASE(3) ESP_CASE(4)
-#undef ESP_CASE
-            }
-            HIP_LAUNCH_OK();
-        }
-        row0 += nch;
-    }
-    k_sum_rows<<<div_up(M, 256), 256, 0, ctx->stream>>>(mol->part.p, rows, M, c);
-    HIP_LAUNCH_OK();
-}
-
-void run_esp(pcm_ctx *ctx, pcm_mol *mol, double *c, int prec) {
-    if (prec == PCM_MIXED)
-        esp_launch<float>(ctx, mol, c);
-    else
-        esp_launch<double>(ctx, mol, c);
-}
-
-// ----------------------------------------------------------------------------------------
-// Fock: V_tuv(pair) = sum_k q_k R_tuv(pair, k) over one chunk of points
+// Fock: V_tuv(pair) = sum_k q_k R_tuv(pair, k) over one chunk of points; lane = primitive pair
 // ----------------------------------------------------------------------------------------
 template <int L, typename T>
-__global__ __launch_bounds__(256) void k_fock_v(const unsigned char *__restrict__ rec, int stride, int n_pairs,
-                                                const PtInt<T> *__restrict__ pts, const double *__restrict__ q,
-                                                int Mpad, int chunk_len, const T *__restrict__ boys_g,
-                                                double *__restrict__ vout) {
+__global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds, int nd, long long n_items,
+                                                const T *__restrict__ boys_g) {
     constexpr int NT = ntuv(L);
     __shared__ T tab[BoysCfg<T>::NROW * BoysCfg<T>::MT];
     load_boys<T>(tab, boys_g);
-    const int ip = blockIdx.x * blockDim.x + threadIdx.x;
-    const PairHdr<T> h = *reinterpret_cast<const PairHdr<T> *>(rec + (size_t)(ip < n_pairs ? ip : n_pairs - 1) * stride);
-    const int k0 = blockIdx.y * chunk_len;
-    const int k1 = min(Mpad, k0 + chunk_len);
-    double V[NT];
+    for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const FockDesc &d = ds[find_desc(ds, nd, it)];
+        const long long local = it - d.base;
+        const int pt_tile = (int)(local % d.nptile), ch = (int)(local / d.nptile);
+        const int n = d.n_pairs;
+        const int ip = pt_tile * 256 + threadIdx.x;
+        const PairHdr<T> h = *reinterpret_cast<const PairHdr<T> *>(d.rec + (size_t)(ip < n ? ip : n - 1) * d.stride);
+        const cptr<PtInt<T>> pts = as_const(reinterpret_cast<const PtInt<T> *>(d.pts));
+        const cptr<double> q = as_const(d.q);
+        const int k0 = ch * d.chunk;
+        const int k1 = min(d.Mpad, k0 + d.chunk);
+        double V[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) V[t] = 0.0;
-    for (int k = k0; k < k1; k += PT_BATCH) {
-        PtInt<T> pt[PT_BATCH];
-        double qk[PT_BATCH];
+        for (int t = 0; t < NT; ++t) V[t] = 0.0;
+        for (int k = k0; k < k1; k += PT_BATCH) {
+            PtInt<T> pt[PT_BATCH];
+            double qk[PT_BATCH];
 #pragma unroll
-        for (int b = 0; b < PT_BATCH; ++b) {
-            pt[b] = pts[k + b];
-            qk[b] = q[k + b];
+            for (int b = 0; b < PT_BATCH; ++b) {
+                pt[b] = pts[k + b];
+                qk[b] = q[k + b];
+            }
+#pragma unroll
+            for (int b = 0; b < PT_BATCH; ++b) {
+                T R[NT];
+                eval_R<L, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta, pt[b].lim,
+                             tab, R);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) V[t] = fma(qk[b], (double)R[t], V[t]);
+            }
         }
+        if (ip < n) {
+            double *o = d.vout + (size_t)ch * NT * n;
 #pragma unroll
-        for (int b = 0; b < PT_BATCH; ++b) {
-            T R[NT];
-            eval_R<L, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta, pt[b].lim, tab,
-                         R);
-#pragma unroll
-            for (int t = 0; t < NT; ++t) V[t] = fma(qk[b], (double)R[t], V[t]);
+            for (int t = 0; t < NT; ++t) o[(size_t)t * n + ip] = V[t];
         }
-    }
-    if (ip < n_pairs) {
-        double *o = vout + (size_t)blockIdx.y * NT * n_pairs;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) o[(size_t)t * n_pairs + ip] = V[t];
     }
 }
 
@@ -281,84 +272,388 @@ __global__ void k_fock_scatter(long long sp0, long long nsp, long long cls_off, 
         }
 }
 
-static int fock_chunk_len(long long n_pairs, int Mpad) {
+// ----------------------------------------------------------------------------------------
+// host side
+// ----------------------------------------------------------------------------------------
+template <typename T> static const T *boys_tab(pcm_ctx *ctx);
+template <> const double *boys_tab<double>(pcm_ctx *ctx) { return ctx->boys64.p; }
+template <> const float *boys_tab<float>(pcm_ctx *ctx) { return ctx->boys32.p; }
+template <typename T> static const PtInt<T> *points(pcm_mol *mol) {
+    return reinterpret_cast<const PtInt<T> *>(sizeof(T) == 8 ? mol->pti64.p : mol->pti32.p);
+}
+
+int autotune_pick(pcm_ctx *ctx, const std::string &key, const std::vector<int> &cands,
+                  const std::function<void(int)> &launch, int reps) {
+    auto f = ctx->tuned.find(key);
+    if (f != ctx->tuned.end()) return f->second;
+    int best = cands.front();
+    if (cands.size() > 1) {
+        hipEvent_t a, b;
+        HIP_OK(hipEventCreate(&a));
+        HIP_OK(hipEventCreate(&b));
+        float best_ms = 1e30f;
+        for (int c : cands) {
+            launch(c);  // warm-up
+            float ms_c = 1e30f;
+            for (int r = 0; r < reps; ++r) {
+                HIP_OK(hipEventRecord(a, ctx->stream));
+                launch(c);
+                HIP_OK(hipEventRecord(b, ctx->stream));
+                HIP_OK(hipEventSynchronize(b));
+                float ms = 0.f;
+                HIP_OK(hipEventElapsedTime(&ms, a, b));
+                ms_c = std::min(ms_c, ms);
+            }
+            if (ms_c < best_ms * 0.97f) {  // prefer the earlier (default-like) shape on near ties
+                best_ms = ms_c;
+                best = c;
+            }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    ctx->tuned[key] = best;
+    return best;
+}
+
+// Chunk shapes: a (molecule, class) is split into about `target` items (point tiles x pair
+// chunks for esp, pair tiles x point chunks for Fock).
+constexpr int TARGET_DEFAULT = 4096;
+static const std::vector<int> TARGETS{4096, 1024, 2048, 8192};
+
+static int esp_chunk_len(long long n_pairs, int M, int target) {
+    int tiles = M > 0 ? div_up(M, 256) : 1;
+    long long want = (target + tiles - 1) / tiles;
+    if (want < 1) want = 1;
+    long long len = (n_pairs + want - 1) / want;
+    if (len < 16) len = 16;
+    return (int)((len + REC_PAD - 1) / REC_PAD * REC_PAD);
+}
+
+static int fock_chunk_len(long long n_pairs, int Mpad, int target) {
     int tiles = n_pairs > 0 ? div_up(n_pairs, 256) : 1;
-    long long want = (target_groups() + tiles - 1) / tiles;
+    long long want = (target + tiles - 1) / tiles;
     if (want < 1) want = 1;
     long long len = (Mpad + want - 1) / want;
     if (len < 32) len = 32;
     return (int)((len + PT_BATCH - 1) / PT_BATCH * PT_BATCH);
 }
 
+static int ilog2(long long x) {
+    int r = 0;
+    while (x > 1) {
+        x >>= 1;
+        ++r;
+    }
+    return r;
+}
+
+static std::string shape_key(const char *kind, int L, bool f64, long long n, long long M) {
+    return std::string(kind) + ":L" + std::to_string(L) + (f64 ? ":f64:" : ":f32:") + std::to_string(ilog2(n)) +
+           ":" + std::to_string(ilog2(M));
+}
+
+// persistent grid for the integral item loops (the Boys table is staged once per workgroup)
+static int int_grid(long long n_items) { return (int)std::min<long long>(n_items, 2048); }
+
+// device scratch for descriptor tables of one call (all classes uploaded at once)
+static void *upload_desc(pcm_ctx *ctx, const void *h, size_t bytes) {
+    ctx->desc.ensure(bytes ? bytes : 1);
+    if (bytes) HIP_OK(hipMemcpyAsync(ctx->desc.p, h, bytes, hipMemcpyHostToDevice, ctx->stream));
+    return ctx->desc.p;
+}
+
 template <typename T>
-static void fock_launch(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F) {
-    PairList &pl = mol->fock;
-    const int M = mol->M, Mpad = mol->Mpad;
+static void esp_class_launch(pcm_ctx *ctx, int L, const EspDesc *d, int nd, long long n_items) {
     const T *tab = boys_tab<T>(ctx);
-    HIP_OK(hipMemcpyAsync(mol->qpad.p, q, sizeof(double) * M, hipMemcpyDeviceToDevice, ctx->stream));
+    const int grid = int_grid(n_items);
+    switch (L) {
+#define ESP_CASE(LL)                                                                        \
+    case LL:                                                                                \
+        k_esp<LL, T><<<grid, 256, 0, ctx->stream>>>(d, nd, n_items, tab);                   \
+        break;
+        ESP_CASE(0) ESP_CASE(1) ESP_CASE(2) ESP_CASE(3) ESP_CASE(4)
+#undef ESP_CASE
+    }
+    HIP_LAUNCH_OK();
+}
+
+template <typename T> static EspDesc esp_desc(pcm_mol *mol, int cl, int chunk, int row0) {
+    PairList &pl = mol->esp;
+    const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
+    const int L = CLS_LA[cl] + CLS_LB[cl];
+    EspDesc d{};
+    d.rec = pl.rec.p + pl.rec_off[cl];
+    d.pts = points<T>(mol);
+    d.part = mol->part.p;
+    d.M = mol->M;
+    d.stride = (int)rec_stride<T>(L);
+    d.n_pad = (int)((n + REC_PAD - 1) / REC_PAD * REC_PAD);
+    d.chunk = chunk;
+    d.ntile = div_up(mol->M, 256);
+    d.row0 = row0;
+    return d;
+}
+
+// chunk of (molecule, class), autotuned on first use of its shape key
+template <typename T> static int esp_chunk(pcm_ctx *ctx, pcm_mol *mol, int cl) {
+    const long long n = mol->esp.cls_off[cl + 1] - mol->esp.cls_off[cl];
+    const int L = CLS_LA[cl] + CLS_LB[cl];
+    if (!ctx->prm.autotune) return esp_chunk_len(n, mol->M, TARGET_DEFAULT);
+    std::vector<int> cands;
+    for (int t : TARGETS) {
+        int c = esp_chunk_len(n, mol->M, t);
+        if (std::find(cands.begin(), cands.end(), c) == cands.end()) cands.push_back(c);
+    }
+    const std::string key = shape_key("esp", L, sizeof(T) == 8, n, mol->M);
+    if (ctx->tuned.count(key)) {  // cached target for this shape bucket: map it to this size
+        return esp_chunk_len(n, mol->M, ctx->tuned[key]);
+    }
+    int rows_max = 0;
+    for (int c : cands) rows_max = std::max(rows_max, div_up(n, c));
+    mol->part.ensure((size_t)rows_max * mol->M);
+    int best_chunk = autotune_pick(ctx, key + ":chunk", cands, [&](int c) {
+        EspDesc d = esp_desc<T>(mol, cl, c, 0);
+        d.base = 0;
+        long long items = (long long)d.ntile * div_up(n, c);
+        EspDesc *dd = (EspDesc *)upload_desc(ctx, &d, sizeof(d));
+        esp_class_launch<T>(ctx, L, dd, 1, items);
+    });
+    int target = TARGET_DEFAULT;
+    for (int t : TARGETS)
+        if (esp_chunk_len(n, mol->M, t) == best_chunk) {
+            target = t;
+            break;
+        }
+    ctx->tuned[key] = target;
+    return best_chunk;
+}
+
+template <typename T>
+static void esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<double *> &c) {
+    const int n = (int)mols.size();
+    std::vector<std::array<int, NCLS>> chunk(n);
+    std::vector<int> rows(n, 0);
+    for (int i = 0; i < n; ++i) {
+        for (int cl = 0; cl < NCLS; ++cl) {
+            long long np = mols[i]->esp.cls_off[cl + 1] - mols[i]->esp.cls_off[cl];
+            chunk[i][cl] = np ? esp_chunk<T>(ctx, mols[i], cl) : REC_PAD;
+            rows[i] += np ? div_up(np, chunk[i][cl]) : 0;
+        }
+        mols[i]->part.ensure((size_t)std::max(rows[i], 1) * mols[i]->M);
+    }
+    // descriptors of every class, then the row-sum descriptors
+    std::vector<EspDesc> all;
+    long long cls_items[NCLS];
+    int cls_first[NCLS], cls_n[NCLS];
+    std::vector<int> row0(n, 0);
+    for (int cl = 0; cl < NCLS; ++cl) {
+        cls_first[cl] = (int)all.size();
+        long long base = 0;
+        for (int i = 0; i < n; ++i) {
+            long long np = mols[i]->esp.cls_off[cl + 1] - mols[i]->esp.cls_off[cl];
+            if (!np) continue;
+            EspDesc d = esp_desc<T>(mols[i], cl, chunk[i][cl], row0[i]);
+            d.base = base;
+            base += (long long)d.ntile * div_up(np, chunk[i][cl]);
+            row0[i] += div_up(np, chunk[i][cl]);
+            all.push_back(d);
+        }
+        cls_n[cl] = (int)all.size() - cls_first[cl];
+        cls_items[cl] = base;
+    }
+    std::vector<SumDesc> sums;
+    long long sbase = 0;
+    for (int i = 0; i < n; ++i) {
+        SumDesc d{mols[i]->part.p, c[i], sbase, mols[i]->M, rows[i]};
+        sbase += div_up(mols[i]->M, 256);
+        sums.push_back(d);
+    }
+    const size_t eb = all.size() * sizeof(EspDesc), sb = sums.size() * sizeof(SumDesc);
+    std::vector<unsigned char> blob(eb + sb);
+    if (eb) std::memcpy(blob.data(), all.data(), eb);
+    std::memcpy(blob.data() + eb, sums.data(), sb);
+    unsigned char *dev = (unsigned char *)upload_desc(ctx, blob.data(), blob.size());
+    const EspDesc *dd = reinterpret_cast<const EspDesc *>(dev);
+    for (int cl = 0; cl < NCLS; ++cl) {
+        if (!cls_n[cl]) continue;
+        const int L = CLS_LA[cl] + CLS_LB[cl];
+        double work = 0.0;
+        for (int i = 0; i < n; ++i)
+            work += (double)(mols[i]->esp.cls_off[cl + 1] - mols[i]->esp.cls_off[cl]) * mols[i]->M;
+        ProfScope ps(ctx, "esp_L" + std::to_string(L) + (sizeof(T) == 8 ? "_f64" : "_f32"), work);
+        esp_class_launch<T>(ctx, L, dd + cls_first[cl], cls_n[cl], cls_items[cl]);
+    }
+    k_sum_rows<<<int_grid(sbase), 256, 0, ctx->stream>>>(reinterpret_cast<const SumDesc *>(dev + eb), n, sbase);
+    HIP_LAUNCH_OK();
+}
+
+void run_esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<double *> &c, int prec) {
+    if (prec == PCM_MIXED)
+        esp_batch<float>(ctx, mols, c);
+    else
+        esp_batch<double>(ctx, mols, c);
+}
+
+void run_esp(pcm_ctx *ctx, pcm_mol *mol, double *c, int prec) { run_esp_batch(ctx, {mol}, {c}, prec); }
+
+// ---------------------------------------------------------------------------------- Fock
+template <typename T>
+static void fock_class_launch(pcm_ctx *ctx, int L, const FockDesc *d, int nd, long long n_items) {
+    const T *tab = boys_tab<T>(ctx);
+    const int grid = int_grid(n_items);
+    switch (L) {
+#define FV_CASE(LL)                                                                         \
+    case LL:                                                                                \
+        k_fock_v<LL, T><<<grid, 256, 0, ctx->stream>>>(d, nd, n_items, tab);                \
+        break;
+        FV_CASE(0) FV_CASE(1) FV_CASE(2) FV_CASE(3) FV_CASE(4)
+#undef FV_CASE
+    }
+    HIP_LAUNCH_OK();
+}
+
+template <typename T> static FockDesc fock_desc(pcm_mol *mol, int cl, int chunk) {
+    PairList &pl = mol->fock;
+    FockDesc d{};
+    d.rec = pl.rec.p + pl.rec_off[cl];
+    d.pts = points<T>(mol);
+    d.q = mol->qpad.p;
+    d.vout = mol->vbuf.p;
+    d.n_pairs = (int)(pl.cls_off[cl + 1] - pl.cls_off[cl]);
+    d.Mpad = mol->Mpad;
+    d.chunk = chunk;
+    d.nptile = div_up(d.n_pairs, 256);
+    d.stride = (int)align16(sizeof(PairHdr<T>));
+    return d;
+}
+
+template <typename T> static int fock_chunk(pcm_ctx *ctx, pcm_mol *mol, int cl) {
+    const long long n = mol->fock.cls_off[cl + 1] - mol->fock.cls_off[cl];
+    const int L = CLS_LA[cl] + CLS_LB[cl];
+    if (!ctx->prm.autotune) return fock_chunk_len(n, mol->Mpad, TARGET_DEFAULT);
+    const std::string key = shape_key("fock", L, sizeof(T) == 8, n, mol->M);
+    if (ctx->tuned.count(key)) return fock_chunk_len(n, mol->Mpad, ctx->tuned[key]);
+    std::vector<int> cands;
+    for (int t : TARGETS) {
+        int c = fock_chunk_len(n, mol->Mpad, t);
+        if (std::find(cands.begin(), cands.end(), c) == cands.end()) cands.push_back(c);
+    }
+    int best_chunk = autotune_pick(ctx, key + ":chunk", cands, [&](int c) {
+        FockDesc d = fock_desc<T>(mol, cl, c);
+        d.base = 0;
+        long long items = (long long)d.nptile * div_up(mol->Mpad, c);
+        FockDesc *dd = (FockDesc *)upload_desc(ctx, &d, sizeof(d));
+        fock_class_launch<T>(ctx, L, dd, 1, items);
+    });
+    int target = TARGET_DEFAULT;
+    for (int t : TARGETS)
+        if (fock_chunk_len(n, mol->Mpad, t) == best_chunk) {
+            target = t;
+            break;
+        }
+    ctx->tuned[key] = target;
+    return best_chunk;
+}
+
+// V buffer and primitive-block buffer large enough for every class and every tuning candidate
+static void fock_buffers(pcm_mol *mol) {
+    PairList &pl = mol->fock;
     size_t vneed = 0, fneed = 0;
-    int chunk[NCLS];
     for (int cl = 0; cl < NCLS; ++cl) {
         long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
-        chunk[cl] = fock_chunk_len(n, Mpad);
-        int nch = div_up(Mpad, chunk[cl]);
-        size_t v = (size_t)nch * ntuv(CLS_LA[cl] + CLS_LB[cl]) * n;
-        vneed = v > vneed ? v : vneed;
-        size_t f = (size_t)n * ncart(CLS_LA[cl]) * ncart(CLS_LB[cl]);
-        fneed = f > fneed ? f : fneed;
+        int cmin = fock_chunk_len(n, mol->Mpad, TARGET_DEFAULT);
+        for (int t : TARGETS) cmin = std::min(cmin, fock_chunk_len(n, mol->Mpad, t));
+        size_t v = (size_t)div_up(mol->Mpad, cmin) * ntuv(CLS_LA[cl] + CLS_LB[cl]) * n;
+        vneed = std::max(vneed, v);
+        fneed = std::max(fneed, (size_t)n * ncart(CLS_LA[cl]) * ncart(CLS_LB[cl]));
     }
     mol->vbuf.ensure(vneed + 1);
     mol->fprim.ensure(fneed + 1);
+}
+
+template <typename T>
+static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<const double *> &q,
+                       const std::vector<double *> &F) {
+    const int n = (int)mols.size();
+    for (int i = 0; i < n; ++i) {
+        HIP_OK(hipMemcpyAsync(mols[i]->qpad.p, q[i], sizeof(double) * mols[i]->M, hipMemcpyDeviceToDevice,
+                              ctx->stream));
+        fock_buffers(mols[i]);
+    }
+    std::vector<std::array<int, NCLS>> chunk(n);
+    for (int i = 0; i < n; ++i)
+        for (int cl = 0; cl < NCLS; ++cl)
+            chunk[i][cl] = mols[i]->fock.cls_off[cl + 1] > mols[i]->fock.cls_off[cl] ? fock_chunk<T>(ctx, mols[i], cl)
+                                                                                  : PT_BATCH;
+    std::vector<FockDesc> all;
+    long long cls_items[NCLS];
+    int cls_first[NCLS], cls_n[NCLS];
     for (int cl = 0; cl < NCLS; ++cl) {
-        long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
-        if (!n) continue;
-        int L = CLS_LA[cl] + CLS_LB[cl];
-        int nch = div_up(Mpad, chunk[cl]);
-        dim3 grid(div_up(n, 256), nch);
-        const unsigned char *rec = pl.rec.p + pl.rec_off[cl];
-        int stride = (int)align16(sizeof(PairHdr<T>));
+        cls_first[cl] = (int)all.size();
+        long long base = 0;
+        for (int i = 0; i < n; ++i) {
+            if (mols[i]->fock.cls_off[cl + 1] == mols[i]->fock.cls_off[cl]) continue;
+            FockDesc d = fock_desc<T>(mols[i], cl, chunk[i][cl]);
+            d.base = base;
+            base += (long long)d.nptile * div_up(mols[i]->Mpad, chunk[i][cl]);
+            all.push_back(d);
+        }
+        cls_n[cl] = (int)all.size() - cls_first[cl];
+        cls_items[cl] = base;
+    }
+    const FockDesc *dd = (const FockDesc *)upload_desc(ctx, all.data(), all.size() * sizeof(FockDesc));
+    for (int cl = 0; cl < NCLS; ++cl) {
+        if (!cls_n[cl]) continue;
+        const int L = CLS_LA[cl] + CLS_LB[cl];
+        double work = 0.0;
+        for (int i = 0; i < n; ++i)
+            work += (double)(mols[i]->fock.cls_off[cl + 1] - mols[i]->fock.cls_off[cl]) * mols[i]->M;
         {
-            ProfScope ps(ctx, "fock_v_L" + std::to_string(L) + (sizeof(T) == 8 ? "_f64" : "_f32"), (double)n * M);
-            switch (L) {
-#define FV_CASE(LL)                                                                                                 \
-    case LL:                                                                                                        \
-        k_fock_v<LL, T><<<grid, 256, 0, ctx->stream>>>(rec, stride, (int)n, points<T>(mol), mol->qpad.p, Mpad,      \
-                                                       chunk[cl], tab, mol->vbuf.p);                                \
+            ProfScope ps(ctx, "fock_v_L" + std::to_string(L) + (sizeof(T) == 8 ? "_f64" : "_f32"), work);
+            fock_class_launch<T>(ctx, L, dd + cls_first[cl], cls_n[cl], cls_items[cl]);
+        }
+        for (int i = 0; i < n; ++i) {
+            pcm_mol *mol = mols[i];
+            PairList &pl = mol->fock;
+            const long long np = pl.cls_off[cl + 1] - pl.cls_off[cl];
+            if (!np) continue;
+            const int nch = div_up(mol->Mpad, chunk[i][cl]);
+            const int *es = pl.ent_sp.p + pl.cls_off[cl], *ei = pl.ent_ij.p + pl.cls_off[cl];
+            const long long sp0 = mol->sp_cls_off[cl], nsp = mol->sp_cls_off[cl + 1] - sp0;
+            const int g = div_up(np, 128), gs = div_up(nsp, 128);
+            ProfScope ps2(ctx, "fock_contract", (double)np);
+#define FC_CASE(CI, LA_, LB_)                                                                                       \
+    case CI:                                                                                                        \
+        k_fock_contract<LA_, LB_><<<g, 128, 0, ctx->stream>>>(np, nch, mol->vbuf.p, es, ei, mol->spa.p, mol->spb.p, \
+                                                              mol->snp.p, mol->soff.p, mol->satom.p, mol->cnoff.p,  \
+                                                              mol->pexp.p, mol->cn.p, mol->xyz.p, mol->fprim.p);    \
+        HIP_LAUNCH_OK();                                                                                            \
+        k_fock_scatter<LA_, LB_><<<gs, 128, 0, ctx->stream>>>(sp0, nsp, pl.cls_off[cl], pl.spo.p, mol->spa.p,       \
+                                                              mol->spb.p, mol->bfo.p, mol->fprim.p, mol->nbf, F[i]); \
         break;
-                FV_CASE(0) FV_CASE(1) FV_CASE(2) FV_CASE(3) FV_CASE(4)
-#undef FV_CASE
+            switch (cl) {
+                FC_CASE(0, 0, 0)
+                FC_CASE(1, 0, 1)
+                FC_CASE(2, 0, 2)
+                FC_CASE(3, 1, 1)
+                FC_CASE(4, 1, 2)
+                FC_CASE(5, 2, 2)
             }
+#undef FC_CASE
             HIP_LAUNCH_OK();
         }
-        const int *es = pl.ent_sp.p + pl.cls_off[cl], *ei = pl.ent_ij.p + pl.cls_off[cl];
-        long long sp0 = mol->sp_cls_off[cl], nsp = mol->sp_cls_off[cl + 1] - sp0;
-        int g = div_up(n, 128), gs = div_up(nsp, 128);
-        ProfScope ps2(ctx, "fock_contract", (double)n);
-#define FC_CASE(CI, LA_, LB_)                                                                                      \
-    case CI:                                                                                                       \
-        k_fock_contract<LA_, LB_><<<g, 128, 0, ctx->stream>>>(n, nch, mol->vbuf.p, es, ei, mol->spa.p, mol->spb.p, \
-                                                              mol->snp.p, mol->soff.p, mol->satom.p, mol->cnoff.p, \
-                                                              mol->pexp.p, mol->cn.p, mol->xyz.p, mol->fprim.p);   \
-        HIP_LAUNCH_OK();                                                                                           \
-        k_fock_scatter<LA_, LB_><<<gs, 128, 0, ctx->stream>>>(sp0, nsp, pl.cls_off[cl], pl.spo.p, mol->spa.p,      \
-                                                              mol->spb.p, mol->bfo.p, mol->fprim.p, mol->nbf, F);  \
-        break;
-        switch (cl) {
-            FC_CASE(0, 0, 0)
-            FC_CASE(1, 0, 1)
-            FC_CASE(2, 0, 2)
-            FC_CASE(3, 1, 1)
-            FC_CASE(4, 1, 2)
-            FC_CASE(5, 2, 2)
-        }
-#undef FC_CASE
-        HIP_LAUNCH_OK();
     }
 }
 
-void run_fock(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F, int prec) {
+void run_fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<const double *> &q,
+                    const std::vector<double *> &F, int prec) {
     if (prec == PCM_MIXED)
-        fock_launch<float>(ctx, mol, q, F);
+        fock_batch<float>(ctx, mols, q, F);
     else
-        fock_launch<double>(ctx, mol, q, F);
+        fock_batch<double>(ctx, mols, q, F);
+}
+
+void run_fock(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F, int prec) {
+    run_fock_batch(ctx, {mol}, {q}, {F}, prec);
 }

@@ -6,6 +6,8 @@
 
 #include <cmath>
 #include <cstdint>
+#include <functional>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -172,6 +174,16 @@ template <int L> __host__ __device__ constexpr int pair_batch() { return L == 0 
 constexpr int REC_PAD = 4;  // pair record lists are padded to a multiple of this with zero records
 constexpr int PT_BATCH = 4; // points per batch in the pair-per-lane kernels
 
+// Read-only view through the constant address space: wave-uniform loads from it become
+// scalar loads.  Only for data that no thread of the running kernel writes.  (The host pass
+// of the compiler only type-checks these declarations.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T> using cptr = const __attribute__((address_space(4))) T *;
+#else
+template <typename T> using cptr = const T *;
+#endif
+template <typename T> __device__ __forceinline__ cptr<T> as_const(const T *p) { return (cptr<T>)(p); }
+
 // Load the Boys table of type T into LDS (tab_g holds BoysCfg<T>::NROW * MT values).
 template <typename T>
 __device__ __forceinline__ void load_boys(T *lds, const T *__restrict__ tab_g) {
@@ -264,7 +276,14 @@ struct pcm_ctx {
     DevBuf<float> boys32;
     DevBuf<double> scal;  // small scalar workspace (reductions, solver scalars)
     DevBuf<int> iscal;
+    std::map<std::string, int> tuned;  // autotuner choices by kernel / shape key
+    DevBuf<unsigned char> desc;        // descriptor tables of the current integral launch
 };
+
+// Time launch(c) for every candidate c (one warm-up, then the best of `reps` timed runs on
+// the context stream) and return the fastest; the choice is cached under `key`.
+int autotune_pick(pcm_ctx *ctx, const std::string &key, const std::vector<int> &cands,
+                  const std::function<void(int)> &launch, int reps = 2);
 
 // one screened primitive-pair list (all classes, concatenated by class)
 struct PairList {
@@ -362,6 +381,9 @@ void pairs_prepare_density(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const doubl
 void run_bz(pcm_ctx *ctx, pcm_mol *mol, double *bz);
 void run_esp(pcm_ctx *ctx, pcm_mol *mol, double *c, int prec);
 void run_fock(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F, int prec);
+void run_esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<double *> &c, int prec);
+void run_fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<const double *> &q,
+                    const std::vector<double *> &F, int prec);
 pcm_status run_solve(pcm_ctx *ctx, pcm_mol *mol, const double *v, const pcm_solve_opts &o, double *q,
                      pcm_solve_info *info);
 double run_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double *c, const double *q);

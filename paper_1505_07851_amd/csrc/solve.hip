@@ -101,16 +101,6 @@ template <typename T> __device__ __forceinline__ T mv_rc2(const CGMol &m);
 template <> __device__ __forceinline__ double mv_rc2<double>(const CGMol &m) { return m.rc2_64; }
 template <> __device__ __forceinline__ float mv_rc2<float>(const CGMol &m) { return m.rc2_32; }
 
-// Read-only view through the constant address space: wave-uniform loads from it become
-// scalar loads.  Only for data that no thread of the running kernel writes.
-// (The host pass of the compiler only needs the declarations to type-check.)
-#if defined(__HIP_DEVICE_COMPILE__)
-template <typename T> using cptr = const __attribute__((address_space(4))) T *;
-#else
-template <typename T> using cptr = const T *;
-#endif
-template <typename T> __device__ __forceinline__ cptr<T> as_const(const T *p) { return (cptr<T>)(p); }
-
 // gate 0: skip molecules whose PCG is done; gate 1: skip molecules not active in this call
 __device__ __forceinline__ bool skip(const CGState &s, int gate) { return gate ? !s.act : s.done; }
 

@@ -301,7 +301,7 @@ def gradient_path() -> System:
     return protein_system("peptide300_631gs", 300, RAW_SPH_300, 4)
 
 
-CONFORMER_SPH = (50, 74, 86, 110, 146)
+CONFORMER_SPH = (96, 116, 136, 162, 194)  # -> 4k-9k kept points per conformer
 
 
 def conformer(j: int) -> System:

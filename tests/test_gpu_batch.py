@@ -102,3 +102,36 @@ def test_batch_warm_start_and_noconv(setup):
         assert i["status"] == 4 and i["iters"] == 3
         assert np.isfinite(i["resid"]) and np.isfinite(i["energy"])
     b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_esp_fock_equal_single(precision):
+    """Batched c = L P and F += L^T q: one launch per class over all molecules; each molecule
+    must get bitwise what the single-molecule call gives on the same context."""
+    import torch
+    from paper_1505_07851_amd import Batch, Context, Molecule
+    print(f"\n[case batched esp/fock {precision}]", flush=True)
+    ctx = Context(precision=precision)
+    systems = [f() for _, f in SYSTEMS]
+    mols = [Molecule.from_system(ctx, s) for s in systems]
+    Ps = [torch.tensor(s.P, dtype=torch.float64, device="cuda") for s in systems]
+    rng = np.random.default_rng(31)
+    qs = [torch.tensor(rng.normal(size=m.M) * 1e-2, dtype=torch.float64, device="cuda") for m in mols]
+    single_c = [m.esp(P) for m, P in zip(mols, Ps)]
+    single_F = [m.fock(q) for m, q in zip(mols, qs)]
+    b = Batch(ctx, mols)
+    cs, bzs = b.esp(Ps)
+    Fs = b.fock(qs)
+    for (c1, bz1), c2, bz2, F1, F2, (name, _) in zip(single_c, cs, bzs, single_F, Fs, SYSTEMS):
+        assert torch.equal(c1, c2), name
+        assert torch.equal(bz1, bz2), name
+        assert torch.equal(F1, F2), name
+    # and against the oracle (FP64 tolerance of the single path; mixed: its error statement)
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    for s, c, F, q in zip(systems, cs, Fs, qs):
+        om = O.mol_from_system(s)
+        cr = om.esp(s.P)
+        assert np.linalg.norm(c.cpu().numpy() - cr) <= tol * np.linalg.norm(cr)
+        Fr = om.fock(q.cpu().numpy())
+        assert np.abs(F.cpu().numpy() - Fr).max() <= tol * max(np.abs(Fr).max(), 1e-12)
+    b.close()
