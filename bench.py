@@ -18,7 +18,13 @@ class for the integrals, hipGraph-replayed PCG iteration groups over all conform
 against the same 64 done one after another with the plain FP64 single-molecule calls.
 The geometries are fixed, so surfaces, pair lists and RBJ blocks are built before timing.
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload protein600|conformers64]
+Third workload (--workload stress2000): the 2,000-atom solute (M ~ 150k).  Fifteen
+SCF-like outer iterations t = 1..15 solve A q = -f v_t with v_t = Bz + L (P + dP_t) for a
+sparse seeded perturbation dP_t, the threshold tightening as delta_t = 10^(-3 - 4(t-1)/14)
+(the Eq. 21 range), each solve warm-started from the previous q; unpreconditioned and RBJ
+with blocks of 1,024 points, FP64 and mixed (FP32 matvec in FP64 refinement).
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload protein600|conformers64|stress2000]
 """
 from __future__ import annotations
 
@@ -99,7 +105,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--block", type=int, default=100)
-    ap.add_argument("--workload", default="protein600", choices=["protein600", "conformers64"])
+    ap.add_argument("--workload", default="protein600", choices=["protein600", "conformers64", "stress2000"])
+    ap.add_argument("--max-iter-none", type=int, default=300,
+                    help="stress2000: matvec budget of each unpreconditioned outer solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding of the path is "
@@ -107,6 +115,8 @@ def main():
         sys.exit(2)
     if args.workload == "conformers64":
         return bench_conformers(args)
+    if args.workload == "stress2000":
+        return bench_stress(args)
 
     import numpy as np
     import torch
@@ -244,6 +254,81 @@ def main():
         if "mixed" in out:
             c_m = rmx["state"]["c"].cpu().numpy()[kidx]
             out["mixed"]["c_sample_rel_err_vs_oracle"] = float(np.abs(c_m - c_or).max() / np.abs(c_or).max())
+    print(json.dumps(out))
+
+
+def bench_stress(args):
+    import numpy as np
+    import torch
+
+    from paper_1505_07851_amd import Context, Molecule
+    from synth import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t = time.time()
+    s = I.linear_solve_stress()
+    log(f"[bench] inputs in {time.time() - t:.1f}s: {s.n_atoms} atoms, nbf {s.basis.nbf}")
+    P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
+    nbf = s.basis.nbf
+    n_out = 15
+    deltas = [10.0 ** (-3.0 - 4.0 * t / (n_out - 1)) for t in range(n_out)]
+    rng = np.random.default_rng(s.seeds["pert"])
+    # sparse symmetric perturbations: 256 local entries per step, size ~ 10 delta_t
+    dPs = []
+    for t in range(n_out):
+        i = rng.integers(0, nbf, 256)
+        j = np.clip(i + rng.integers(-32, 33, 256), 0, nbf - 1)
+        val = rng.normal(size=256) * 10.0 * deltas[t]
+        dPs.append((torch.tensor(i), torch.tensor(j), torch.tensor(val)))
+    runs = {}
+    ctx = Context(precision="fp64")  # integrals in FP64: this workload measures the solver
+    t = time.time()
+    mol = Molecule.from_system(ctx, s)
+    torch.cuda.synchronize()
+    log(f"[bench] surface + lists in {time.time() - t:.1f}s, M = {mol.M}")
+    t = time.time()
+    c0, bz = mol.esp(P)
+    dP = torch.zeros_like(P)
+    vs = []
+    for (i, j, val) in dPs:
+        dP.zero_()
+        dP.index_put_((i.cuda(), j.cuda()), val.cuda(), accumulate=True)
+        dP.index_put_((j.cuda(), i.cuda()), val.cuda(), accumulate=True)
+        dc, _ = mol.esp(dP, want_bz=False)
+        vs.append(bz + c0 + dc)
+    del dP
+    torch.cuda.synchronize()
+    log(f"[bench] c = L P and the 15 perturbed right-hand sides in {time.time() - t:.1f}s")
+    for prec in ("fp64", "mixed"):
+        for pc, blk, cap in (("rbj", 1024, 10000), ("none", 0, args.max_iter_none)):
+            q = None
+            per = []
+            t0 = time.perf_counter()
+            for t_, (v, d) in enumerate(zip(vs, deltas)):
+                q, info = mol.solve(v, precond=pc, block=max(blk, 1), seed=s.seeds["rbj"], tol=d, q0=q,
+                                    max_iter=cap, precision=prec, raise_noconv=False)
+                per.append(info)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) * 1e3
+            key = f"{prec}_{pc}{blk if blk else ''}"
+            runs[key] = {"wall_ms": round(wall, 1), "solve_ms": round(sum(i["solve_ms"] for i in per), 1),
+                         "setup_ms": round(sum(i["setup_ms"] for i in per), 1),
+                         "iters": [i["iters"] for i in per], "converged": sum(i["status"] == 0 for i in per),
+                         "final_resid": per[-1]["resid"], "final_energy": per[-1]["energy"],
+                         "energies": [i["energy"] for i in per]}
+            log(f"[bench] {key}: {wall:.0f} ms, iters {runs[key]['iters']}, converged {runs[key]['converged']}/15")
+    ref = runs["fp64_rbj1024"]["energies"]
+    for k, r in runs.items():
+        r["E_abs_err_vs_fp64_rbj_max"] = max(abs(a - b) for a, b in zip(r.pop("energies"), ref))
+    out = {"metric": "PCG solve ms over 15 outer iterations at the Eq. 21 thresholds (1e-3 -> 1e-7)",
+           "value": runs["mixed_rbj1024"]["wall_ms"], "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": runs["mixed_rbj1024"]["wall_ms"], "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64/f32-matvec", "data": "synthetic",
+           "config": {"workload": "protein2000_631gs_stress", "atoms": s.n_atoms, "nbf": nbf, "surface_points": mol.M,
+                      "outer_iterations": n_out, "deltas": deltas, "rbj_block": 1024,
+                      "max_iter_unpreconditioned": args.max_iter_none},
+           "runs": runs}
     print(json.dumps(out))
 
 

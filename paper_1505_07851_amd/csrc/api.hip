@@ -41,6 +41,7 @@ void release_list(PairList &pl) {
 }
 
 void release_mol(pcm_mol *m) {
+    rbj_pending_drop(m);
     DevBuf<double> *dbl[] = {&m->xyz, &m->Z, &m->rad, &m->dirs, &m->w, &m->pexp, &m->pcoef, &m->cn, &m->px, &m->py,
                              &m->pz, &m->zeta, &m->S, &m->Akk, &m->qpad, &m->part, &m->vbuf,
                              &m->fprim, &m->gpair, &m->gsp, &m->sv, &m->rbj_inv};
@@ -316,6 +317,7 @@ pcm_status pcm_update_geometry(pcm_ctx *ctx, pcm_mol *mol, const double *xyz, co
         rs.release();
         mol->esp_valid = false;
         mol->rbj_valid = false;
+        rbj_prefetch(ctx, mol);
         return PCM_OK;
     });
 }

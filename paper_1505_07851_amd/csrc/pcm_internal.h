@@ -299,6 +299,7 @@ struct PairList {
 };
 
 struct SolveBatch;
+struct RbjPending;
 
 struct pcm_mol {
     int N = 0, nsph = 0, M = 0, Mraw = 0;
@@ -345,6 +346,7 @@ struct pcm_mol {
     DevBuf<long long> rbj_ioff;
     std::vector<int> h_rbj_perm, h_rbj_off;
     int rbj_l = -1, rbj_lmax = 0;
+    RbjPending *rbj_pending = nullptr;  // partition started on a host thread after a geometry update
     unsigned long long rbj_seed = 0;
     bool rbj_valid = false;
     pcm_ctx *owner_ctx = nullptr;
@@ -391,6 +393,8 @@ void run_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, doub
               int prec);
 void surface_points(pcm_ctx *ctx, pcm_mol *mol, const double *r_explicit_dev);
 void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int l, unsigned long long seed);
+void rbj_prefetch(pcm_ctx *ctx, pcm_mol *mol);
+void rbj_pending_drop(pcm_mol *mol);
 SolveBatch *solve_batch_new(const std::vector<pcm_mol *> &mols);
 void solve_batch_free(SolveBatch *b);
 pcm_status solve_batch_run(pcm_ctx *ctx, SolveBatch &B, const std::vector<const double *> &v,

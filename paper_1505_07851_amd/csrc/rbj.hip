@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <future>
 #include <numeric>
 
 // ----------------------------------------------------------------------------------------
@@ -69,10 +70,12 @@ __global__ __launch_bounds__(256) void k_rbj_invert(const int *__restrict__ off,
     }
 }
 
-void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int l, unsigned long long seed) {
-    if (mol->rbj_valid && mol->rbj_l == l && mol->rbj_seed == seed) return;
+// current kept points (interleaved xyz) and exponents, copied to the host
+static void positions_to_host(pcm_ctx *ctx, pcm_mol *mol, std::vector<double> &r, std::vector<double> &zeta) {
     const int M = mol->M;
-    std::vector<double> r(3 * (size_t)M), px(M), py(M), pz(M), zeta(M);
+    std::vector<double> px(M), py(M), pz(M);
+    zeta.resize(M);
+    r.resize(3 * (size_t)M);
     HIP_OK(hipMemcpyAsync(px.data(), mol->px.p, M * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIP_OK(hipMemcpyAsync(py.data(), mol->py.p, M * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIP_OK(hipMemcpyAsync(pz.data(), mol->pz.p, M * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -83,9 +86,67 @@ void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int l, unsigned long long seed) {
         r[3 * k + 1] = py[k];
         r[3 * k + 2] = pz[k];
     }
-    mol->h_rbj_perm.assign(M, 0);
-    mol->h_rbj_off.assign(M + 1, 0);
-    int nb = host_rbj_partition(M, r.data(), zeta.data(), l, seed, mol->h_rbj_perm.data(), mol->h_rbj_off.data());
+}
+
+// The partition depends only on the points, so after a geometry update it is started on a
+// host thread for the block size and seed used last; the next solve with the same options
+// joins it instead of partitioning while the GPU waits.
+struct RbjPending {
+    int l = 0;
+    unsigned long long seed = 0;
+    std::vector<double> r, zeta;
+    std::vector<int> perm, off;
+    std::future<int> nb;
+};
+
+void rbj_pending_drop(pcm_mol *mol) {
+    if (!mol->rbj_pending) return;
+    if (mol->rbj_pending->nb.valid()) mol->rbj_pending->nb.wait();
+    delete mol->rbj_pending;
+    mol->rbj_pending = nullptr;
+}
+
+void rbj_prefetch(pcm_ctx *ctx, pcm_mol *mol) {
+    rbj_pending_drop(mol);
+    if (mol->rbj_l < 1 || mol->M < 1) return;  // no RBJ solve on this molecule yet
+    RbjPending *p = new RbjPending();
+    p->l = mol->rbj_l;
+    p->seed = mol->rbj_seed;
+    try {
+        positions_to_host(ctx, mol, p->r, p->zeta);
+        const int M = mol->M;
+        p->perm.assign(M, 0);
+        p->off.assign(M + 1, 0);
+        p->nb = std::async(std::launch::async, [p, M]() {
+            return host_rbj_partition(M, p->r.data(), p->zeta.data(), p->l, p->seed, p->perm.data(), p->off.data());
+        });
+    } catch (const std::system_error &) {
+        delete p;  // no thread available: the solve partitions synchronously
+        return;
+    } catch (...) {
+        delete p;
+        throw;
+    }
+    mol->rbj_pending = p;
+}
+
+void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int l, unsigned long long seed) {
+    if (mol->rbj_valid && mol->rbj_l == l && mol->rbj_seed == seed) return;
+    const int M = mol->M;
+    int nb;
+    if (mol->rbj_pending && mol->rbj_pending->l == l && mol->rbj_pending->seed == seed) {
+        nb = mol->rbj_pending->nb.get();
+        mol->h_rbj_perm = std::move(mol->rbj_pending->perm);
+        mol->h_rbj_off = std::move(mol->rbj_pending->off);
+        rbj_pending_drop(mol);
+    } else {
+        rbj_pending_drop(mol);
+        std::vector<double> r, zeta;
+        positions_to_host(ctx, mol, r, zeta);
+        mol->h_rbj_perm.assign(M, 0);
+        mol->h_rbj_off.assign(M + 1, 0);
+        nb = host_rbj_partition(M, r.data(), zeta.data(), l, seed, mol->h_rbj_perm.data(), mol->h_rbj_off.data());
+    }
     if (nb <= 0) throw PcmError{PCM_E_ARG, "randomized block-Jacobi partition failed"};
     mol->h_rbj_off.resize(nb + 1);
     std::vector<long long> ioff(nb + 1, 0);

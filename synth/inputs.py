@@ -229,6 +229,26 @@ def density_matrix(nbf: int, n_occ: int, p_seed: int):
     return 0.5 * (P + P.T)
 
 
+def density_matrix_blocked(nbf: int, n_occ: int, p_seed: int, window: int = 1024):
+    """P = 2 C C^T with C block-diagonal over windows of `window` consecutive functions, each
+    window holding its share of the n_occ occupied columns as a seeded orthonormal block.
+    The columns of C are orthonormal, so P/2 is a projector of rank n_occ, as for the dense
+    generator, but the cost is linear in nbf (used where nbf ~ 17k)."""
+    rng = np.random.default_rng(p_seed)
+    P = np.zeros((nbf, nbf))
+    starts = list(range(0, nbf, window))
+    done = 0
+    for b, s0 in enumerate(starts):
+        s1 = min(nbf, s0 + window)
+        k = round(n_occ * s1 / nbf) - done
+        k = max(0, min(k, s1 - s0))
+        done += k
+        if k:
+            C = orthonormal_columns(s1 - s0, k, rng)
+            P[s0:s1, s0:s1] = 2.0 * (C @ C.T)
+    return 0.5 * (P + P.T)
+
+
 # ----------------------------------------------------------------------------
 # configurations
 # ----------------------------------------------------------------------------
@@ -264,14 +284,15 @@ def water_tiny() -> System:
 
 
 def protein_system(name: str, n_atoms: int, n_sph: int, cfg: int, polarized: bool = True,
-                   radius_scale: float = 1.0, geom_seed=None, p_seed=None) -> System:
+                   radius_scale: float = 1.0, geom_seed=None, p_seed=None, blocked_p: bool = False) -> System:
     gs = 100 * cfg + 1 if geom_seed is None else geom_seed
     ps = 100 * cfg + 3 if p_seed is None else p_seed
     elements, xyz = protein_like(n_atoms, gs, radius_scale)
     basis = basis_631g_shape(elements, 100 * cfg + 2, polarized)
     Z = _znuc(elements)
     n_occ = int(Z.sum()) // 2
-    P = density_matrix(basis.nbf, min(n_occ, basis.nbf), ps)
+    dm = density_matrix_blocked if blocked_p else density_matrix
+    P = dm(basis.nbf, min(n_occ, basis.nbf), ps)
     dirs, w = sphere_rule(n_sph)
     return System(name, xyz, Z, _radii(elements), elements, basis, dirs, w, P,
                   seeds={"geometry": gs, "basis": 100 * cfg + 2, "P": ps, "rbj": 100 * cfg + 4,
@@ -293,7 +314,7 @@ def protein_single_solve() -> System:
 
 def linear_solve_stress() -> System:
     """2,000 atoms, 6-31G*-shaped basis, ~150k kept surface points."""
-    return protein_system("protein2000_631gs", 2000, RAW_SPH_2000, 3)
+    return protein_system("protein2000_631gs", 2000, RAW_SPH_2000, 3, blocked_p=True)
 
 
 def gradient_path() -> System:
