@@ -191,3 +191,73 @@ def test_mixed_gradient_error_statement(pep, torch_cuda):
            "g_nuc_abs": (gn2 - gn).abs().max().item(), "g_surf_abs": (gs2 - gs).abs().max().item()}
     print("mixed vs FP64 (300 atoms):", {k: f"{v:.2e}" for k, v in err.items()}, flush=True)
     assert err["E_abs"] <= 5e-5 and err["g_nuc_abs"] <= 5e-5 and err["g_surf_abs"] <= 5e-5
+
+
+# ------------------------------------------------------------------ batched conformers
+
+def test_conformer_batch_full_size(torch_cuda):
+    """Eight of the 150-atom conformers (M from ~3.9k to ~9k) in one batch, with the options
+    the conformer benchmark uses: batched c, q, E and F equal the single-molecule results
+    bitwise; c on sampled points and the solve through oracle residual rows."""
+    from paper_1505_07851_amd import Batch, Context, Molecule
+    torch = torch_cuda
+    print("\n[case conformers 0..7, batched]", flush=True)
+    systems = [I.conformer(j) for j in range(8)]
+    ctx = Context()
+    mols = [Molecule.from_system(ctx, s) for s in systems]
+    Ps = [torch.tensor(s.P, dtype=torch.float64, device="cuda") for s in systems]
+    kw = dict(precond="rbj", block=100, seed=7, tol=1e-8, max_iter=10000)
+    single = []
+    for m, P in zip(mols, Ps):
+        c, bz = m.esp(P)
+        q, info = m.solve(bz + c, **kw)
+        single.append((c, bz, q, info, m.fock(q)))
+    b = Batch(ctx, mols)
+    cs, bzs = b.esp(Ps)
+    qs, infos = b.solve([bz + c for c, bz in zip(cs, bzs)], **kw)
+    Fs = b.fock(qs)
+    for (c1, bz1, q1, i1, F1), c2, q2, i2, F2 in zip(single, cs, qs, infos, Fs):
+        assert torch.equal(c1, c2) and torch.equal(q1, q2) and torch.equal(F1, F2)
+        assert i1["iters"] == i2["iters"] and i1["energy"] == i2["energy"]
+    rng = np.random.default_rng(77)
+    for j in (0, 4):  # smallest and a large one
+        s, m = systems[j], mols[j]
+        om = O.mol_from_system(s)
+        kidx = np.sort(rng.choice(m.M, 16, replace=False))
+        c_or = om.esp(s.P, kidx=kidx)
+        assert np.abs(cs[j].cpu().numpy()[kidx] - c_or).max() <= 1e-10 * np.abs(c_or).max()
+        v = (bzs[j] + cs[j]).cpu().numpy()
+        r = om.matvec(qs[j].cpu().numpy(), kidx=kidx) + om.f * v[kidx]
+        assert np.abs(r).max() < 1e-8
+    b.close()
+
+
+# ------------------------------------------------------------------ 2,000-atom solve
+
+def test_stress_solve_residual_rows(torch_cuda):
+    """M ~ 150k: RBJ-1024 solves, FP64 and mixed, at the tightest threshold of the stress
+    schedule (1e-7), checked through oracle rows of A q - b (the oracle computes rows one by
+    one); the symmetric tile matvec spans ~586 tiles here."""
+    from paper_1505_07851_amd import Context, Molecule
+    torch = torch_cuda
+    print("\n[case protein2000 stress]", flush=True)
+    s = I.linear_solve_stress()
+    ctx = Context()
+    mol = Molecule.from_system(ctx, s)
+    P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
+    c, bz = mol.esp(P)
+    v = bz + c
+    del P
+    print("  M =", mol.M, flush=True)
+    om = O.mol_from_system(s)
+    assert om.M == mol.M
+    rng = np.random.default_rng(2024)
+    kidx = np.sort(rng.choice(mol.M, 48, replace=False))
+    vh = v.cpu().numpy()
+    for prec in ("fp64", "mixed"):
+        q, info = mol.solve(v, precond="rbj", block=1024, seed=s.seeds["rbj"], tol=1e-7, precision=prec)
+        print(f"  {prec}: iters {info['iters']} resid {info['resid']:.2e} solve {info['solve_ms']:.0f} ms",
+              flush=True)
+        assert info["resid"] < 1e-7
+        r = om.matvec(q.cpu().numpy(), kidx=kidx) + om.f * vh[kidx]
+        assert np.abs(r).max() < 1e-7
