@@ -368,7 +368,7 @@ def bench_stress(args):
         dP.zero_()
         dP.index_put_((i.cuda(), j.cuda()), val.cuda(), accumulate=True)
         dP.index_put_((j.cuda(), i.cuda()), val.cuda(), accumulate=True)
-        dc, _ = mol.esp(dP, want_bz=False)
+        dc = mol.esp(dP, want_bz=False)
         vs.append(bz + c0 + dc)
     del dP
     torch.cuda.synchronize()
