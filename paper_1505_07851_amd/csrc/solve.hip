@@ -666,9 +666,25 @@ static void download_states(pcm_ctx *ctx, SolveBatch &B) {
     HIP_OK(hipStreamSynchronize(ctx->stream));
 }
 
-static double mv_work(const SolveBatch &B) {
-    double w = 0.0;  // unordered point pairs (the algorithmic count)
-    for (const auto &m : B.h_tab) w += 0.5 * (double)m.M * (double)(m.M - 1);
+// Work of one launch for per-kernel profiling, counted over the molecules that take part
+// (host copy of the states, kept current while profiling): unordered point pairs for the
+// matvec, inverse-block elements for the RBJ apply.
+static bool takes_part(const CGState &h, int gate) { return gate ? h.act != 0 : h.done == 0; }
+
+static double mv_work(const SolveBatch &B, int gate) {
+    double w = 0.0;
+    for (int i = 0; i < B.n; ++i)
+        if (takes_part(B.h_st[i], gate)) w += 0.5 * (double)B.h_tab[i].M * (double)(B.h_tab[i].M - 1);
+    return w;
+}
+
+static double rbj_work(const SolveBatch &B) {
+    double w = 0.0;
+    for (int i = 0; i < B.n; ++i) {
+        if (!takes_part(B.h_st[i], 0)) continue;
+        const std::vector<int> &off = B.mols[i]->h_rbj_off;
+        for (size_t b = 0; b + 1 < off.size(); ++b) w += (double)(off[b + 1] - off[b]) * (off[b + 1] - off[b]);
+    }
     return w;
 }
 
@@ -722,7 +738,8 @@ static int mv_grid(pcm_ctx *ctx, SolveBatch &B, int prec, int gate, int src) {
 static void matvec(pcm_ctx *ctx, SolveBatch &B, hipStream_t s, int prec, int gate, int src, int dst, int bvec,
                    int mode, int grid, bool prof) {
     {
-        ProfScope ps(prof ? ctx : nullptr, prec == PCM_MIXED ? "matvec_f32" : "matvec_f64", mv_work(B));
+        ProfScope ps(prof ? ctx : nullptr, prec == PCM_MIXED ? "matvec_f32" : "matvec_f64",
+                     prof ? mv_work(B, gate) : 0.0);
         launch_mv(ctx, B, s, prec, gate, src, grid);
     }
     k_mv_finish<<<grid_of(B.n_tiles), TILE, 0, s>>>(B.tab.p, B.st.p, B.tiles.p, B.n_tiles, gate, src, dst, bvec,
@@ -737,7 +754,7 @@ static void pcg_iteration(pcm_ctx *ctx, SolveBatch &B, hipStream_t s, int prec, 
     k_cg_update<<<grid_of(B.n_tiles), TILE, 0, s>>>(B.tab.p, B.st.p, B.tiles.p, B.n_tiles, xi, par ^ 1);
     HIP_LAUNCH_OK();
     if (rbj) {
-        ProfScope ps(prof ? ctx : nullptr, "rbj_apply", 0.0);
+        ProfScope ps(prof ? ctx : nullptr, "rbj_apply", prof ? rbj_work(B) : 0.0);
         k_rbj_items<<<grid_of(B.n_rbj), TILE, 0, s>>>(B.tab.p, B.st.p, B.rbj.p, B.n_rbj);
         HIP_LAUNCH_OK();
     }
@@ -746,12 +763,9 @@ static void pcg_iteration(pcm_ctx *ctx, SolveBatch &B, hipStream_t s, int prec, 
     HIP_LAUNCH_OK();
 }
 
-// GROUP_K iterations, replayed from a captured graph unless per-kernel profiling is on
-static void launch_group(pcm_ctx *ctx, SolveBatch &B, int prec, int xi, int grid, bool rbj, bool use_graph) {
-    if (!use_graph) {
-        for (int g = 1; g <= GROUP_K; ++g) pcg_iteration(ctx, B, ctx->stream, prec, xi, g & 1, grid, rbj, ctx->prof);
-        return;
-    }
+// GROUP_K iterations replayed from a captured graph (captured on first use and whenever the
+// tables or the launch shape change)
+static void launch_group(pcm_ctx *ctx, SolveBatch &B, int prec, int xi, int grid, bool rbj) {
     const int slot = prec == PCM_MIXED ? 1 : 0;
     GraphSig sig{B.tab.p, B.st.p, B.mv.p, B.tiles.p, B.rbj.p, B.n_mv, B.n_tiles, B.n_rbj, grid, rbj ? 1 : 0, prec};
     // xi is fixed per precision: FP64 solves x = V_XQ, mixed inner solves x = V_D
@@ -796,12 +810,24 @@ static void pcg_batch(pcm_ctx *ctx, SolveBatch &B, int prec, int xi, int bi, boo
     k_cg_dir<<<grid_of(B.n_tiles), TILE, 0, s>>>(B.tab.p, B.st.p, B.tiles.p, B.n_tiles, 0, 1,
                                                  prec == PCM_MIXED ? 1 : 0);
     HIP_LAUNCH_OK();
-    const bool use_graph = !ctx->prof;
+    if (ctx->prof) {
+        // per-kernel profiling: one iteration at a time with the states read back after each,
+        // so no launch runs after convergence and every record carries the work it did
+        download_states(ctx, B);
+        for (int g = 1; g <= max_it + 1; ++g) {
+            bool any = false;
+            for (const auto &h : B.h_st) any = any || takes_part(h, 0);
+            if (!any) break;
+            pcg_iteration(ctx, B, s, prec, xi, g & 1, grid, rbj, true);
+            download_states(ctx, B);
+        }
+        return;
+    }
     const int max_groups = max_it / GROUP_K + 2;
     // launch group j+1 before waiting for the active count of group j: the device never idles
     int launched = 0, slot = 0;
     auto group = [&](int sl) {
-        launch_group(ctx, B, prec, xi, grid, rbj, use_graph);
+        launch_group(ctx, B, prec, xi, grid, rbj);
         k_count_active<<<1, TILE, 0, s>>>(B.st.p, B.n, B.cnt.p);
         HIP_LAUNCH_OK();
         HIP_OK(hipMemcpyAsync(B.h_cnt + sl, B.cnt.p, sizeof(int), hipMemcpyDeviceToHost, s));
