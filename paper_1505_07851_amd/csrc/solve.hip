@@ -5,8 +5,9 @@
 //    upper triangle of 256 x 256 point tiles: one workgroup takes the tile pair (I, J), J >= I,
 //    one lane per row of I, columns of J wave-uniform.  Each evaluated A_kl feeds the row sum
 //    of k and (off-diagonal tiles) the column sum of l, reduced across each 16-lane row by a
-//    fixed DPP butterfly and across rows through LDS.  Every (tile, row) partial is written to its own slot and the slots are summed
-//    in fixed order: results are bitwise reproducible and independent of the launch grid.
+//    fixed DPP butterfly and across rows through LDS.
+//    Every (tile, row) partial is written to its own slot and the slots are summed in fixed
+//    order: results are bitwise reproducible and independent of the launch grid.
 //  * erf(zeta' r) rounds to 1 once zeta' r >= 6 (FP64) / 4 (FP32): those pairs take the plain
 //    1/r branch, tested with zeta'^2 >= min(zeta_k^2, zeta_l^2)/2.
 //  * Preconditioned CG (Sec. 4b) with the residual test ||A q - b||_2 < delta (Eq. 20);
@@ -28,6 +29,9 @@ constexpr int GROUP_K = 8; // PCG iterations per launch group (even: scalar slot
 // Bound on each inner FP32 solve of the refinement: FP32 rounding can stall the inner
 // residual above its target on ill-conditioned systems; the outer FP64 residual then restarts.
 constexpr int INNER_MAX_IT = 400;
+// FP64 solves: restarts from the current q when the recurrence residual converged but the
+// recomputed one is not below the threshold
+constexpr int MAX_RESTARTS = 3;
 
 template <typename T> struct Pt {
     T x, y, z, zeta;
@@ -130,12 +134,14 @@ constexpr int DPP_ROW_HALF_MIRROR = 0x141;  // lane i <- lane 7 - i within 8: pa
 constexpr int DPP_QUAD_XOR2 = 0x4E;     // quad_perm [2, 3, 0, 1]
 constexpr int DPP_QUAD_XOR1 = 0xB1;     // quad_perm [1, 0, 3, 2]
 
+// Every lane of every row and bank is written and every source lane exists for these
+// patterns, so no "old" operand is needed.
 template <int CTRL> __device__ __forceinline__ float dpp(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 template <int CTRL> __device__ __forceinline__ double dpp(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 
@@ -215,7 +221,7 @@ __global__ __launch_bounds__(TILE) void k_mv_sym(const CGMol *__restrict__ tab, 
                 T cv[MV_B];
 #pragma unroll
                 for (int u = 0; u < MV_B; ++u) cv[u] = a[u] * xk;
-                T s = row_colsum8<T>(cv, lane);
+                const T s = row_colsum8<T>(cv, lane);
                 if ((lane & 1) == 0) colbuf[wv * 4 + (lane >> 4)][l - c0 + ((lane >> 1) & 7)] = s;
             }
         }
@@ -954,18 +960,44 @@ pcm_status solve_batch_run(pcm_ctx *ctx, SolveBatch &B, const std::vector<const 
                 }
         }
     } else {
-        pcg_batch(ctx, B, PCM_FP64, V_XQ, V_B, !o.warm_start, rbj);
-        download_states(ctx, B);
-        for (int i = 0; i < n; ++i) {
-            iters[i] = B.h_st[i].it;
-            conv[i] = std::sqrt(B.h_st[i].rr) < o.tol;
+        // The iteration runs on the recurrence residual; Eq. 20 is a test on b - A q itself,
+        // so the recomputed residual decides, and a molecule whose recurrence converged while
+        // its true residual did not restarts from the current q (a few times at most).
+        std::vector<int> run(n, 1);
+        bool first = true;
+        for (int restart = 0; restart <= MAX_RESTARTS; ++restart) {
+            pcg_batch(ctx, B, PCM_FP64, V_XQ, V_B, first ? !o.warm_start : false, rbj);
+            download_states(ctx, B);
+            std::vector<int> rec(n, 0);
+            for (int i = 0; i < n; ++i)
+                if (run[i]) {
+                    iters[i] += B.h_st[i].it + (first && !o.warm_start ? 0 : 1);  // + the restart product
+                    rec[i] = std::sqrt(B.h_st[i].rr) < o.tol;
+                }
+            for (int i = 0; i < n; ++i) B.h_st[i].act = run[i];
+            upload_states(ctx, B);
+            residual(ctx, B, V_XQ, V_B);
+            download_states(ctx, B);
+            int again = 0;
+            for (int i = 0; i < n; ++i) {
+                if (!run[i]) continue;
+                rn[i] = std::sqrt(B.h_st[i].res2);
+                conv[i] = rn[i] < o.tol;
+                run[i] = rec[i] && !conv[i] && iters[i] < o.max_iter;
+                again += run[i];
+            }
+            if (!again) break;
+            first = false;
+            for (int i = 0; i < n; ++i) {
+                CGState &h = B.h_st[i];
+                h = CGState{};
+                h.act = run[i];
+                h.done = run[i] ? 0 : 1;
+                h.tol = o.tol;
+                h.max_it = run[i] ? o.max_iter - iters[i] - 1 : 0;
+            }
+            upload_states(ctx, B);
         }
-        // true FP64 residual at exit
-        for (auto &h : B.h_st) h.act = 1;
-        upload_states(ctx, B);
-        residual(ctx, B, V_XQ, V_B);
-        download_states(ctx, B);
-        for (int i = 0; i < n; ++i) rn[i] = std::sqrt(B.h_st[i].res2);
     }
     for (auto &h : B.h_st) h.act = 1;
     upload_states(ctx, B);
