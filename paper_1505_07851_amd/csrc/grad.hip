@@ -21,8 +21,8 @@ __global__ __launch_bounds__(256) void k_grad_pts(const unsigned char *__restric
                                                   int chunk_len, const PtInt<T> *__restrict__ pts, int M,
                                                   const T *__restrict__ boys_g, double *__restrict__ part, int row0) {
     constexpr int NT = ntuv(L), PB = pair_batch<L + 1>();
-    __shared__ T tab[BoysCfg<T>::NROW * BoysCfg<T>::MT];
-    load_boys<T>(tab, boys_g);
+    __shared__ T tab[boys_lds_size<T, L + 1>()];
+    load_boys<T, L + 1>(tab, boys_g);
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const PtInt<T> me = pts[k < M ? k : M - 1];
     const int p0 = blockIdx.y * chunk_len;
@@ -71,8 +71,8 @@ __global__ __launch_bounds__(256) void k_grad_v(const unsigned char *__restrict_
                                                 const PtInt<T> *__restrict__ pts, const double *__restrict__ q,
                                                 int Mpad, int chunk_len, const T *__restrict__ boys_g,
                                                 double *__restrict__ vout) {
-    __shared__ T tab[BoysCfg<T>::NROW * BoysCfg<T>::MT];
-    load_boys<T>(tab, boys_g);
+    __shared__ T tab[boys_lds_size<T, L + 1>()];
+    load_boys<T, L + 1>(tab, boys_g);
     constexpr int NT = ntuv(L + 1);
     const int ip = blockIdx.x * blockDim.x + threadIdx.x;
     const int ipp = ip < n_pairs ? ip : n_pairs - 1;

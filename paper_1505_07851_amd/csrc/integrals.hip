@@ -18,9 +18,10 @@
 // reduced afterwards in a fixed order, so results are bitwise reproducible.
 //
 // Batching.  One launch per angular class covers every molecule of a batch: work items are
-// (molecule, tile, chunk) triples located through per-molecule descriptors; the workgroups
-// are persistent (the Boys table is staged into LDS once per workgroup).  The chunk shape of
-// each (class, size bucket) is chosen by timing a few candidates on first use.
+// (molecule, tile, chunk) triples located through per-molecule descriptors, one per
+// workgroup.  Each kernel stages only the Boys-table columns its order needs, so low-L
+// kernels keep more workgroups resident.  The chunk shape of each (class, size bucket) is
+// chosen by timing a few candidates on first use.
 #include "pcm_internal.h"
 
 #include <algorithm>
@@ -73,8 +74,8 @@ template <int L, typename T>
 __global__ __launch_bounds__(256) void k_esp(const EspDesc *__restrict__ ds, int nd, long long n_items,
                                              const T *__restrict__ boys_g) {
     constexpr int NT = ntuv(L), PB = pair_batch<L>();
-    __shared__ T tab[BoysCfg<T>::NROW * BoysCfg<T>::MT];
-    load_boys<T>(tab, boys_g);
+    __shared__ T tab[boys_lds_size<T, L>()];
+    load_boys<T, L>(tab, boys_g);
     for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
         const EspDesc &d = ds[find_desc(ds, nd, it)];
         const long long local = it - d.base;
@@ -164,8 +165,8 @@ template <int L, typename T>
 __global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds, int nd, long long n_items,
                                                 const T *__restrict__ boys_g) {
     constexpr int NT = ntuv(L);
-    __shared__ T tab[BoysCfg<T>::NROW * BoysCfg<T>::MT];
-    load_boys<T>(tab, boys_g);
+    __shared__ T tab[boys_lds_size<T, L>()];
+    load_boys<T, L>(tab, boys_g);
     for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
         const FockDesc &d = ds[find_desc(ds, nd, it)];
         const long long local = it - d.base;
@@ -353,8 +354,11 @@ static std::string shape_key(const char *kind, int L, bool f64, long long n, lon
            ":" + std::to_string(ilog2(M));
 }
 
-// persistent grid for the integral item loops (the Boys table is staged once per workgroup)
-static int int_grid(long long n_items) { return (int)std::min<long long>(n_items, 2048); }
+// Grid of the integral item loops: one item per workgroup and the hardware scheduler balances
+// them (items differ in cost: chunk tails, near-field fractions).  Re-staging the Boys table
+// per workgroup costs well under 1% of these launches.  The item loop still allows a smaller
+// grid (at most 2^30 workgroups).
+static int int_grid(long long n_items) { return (int)std::min<long long>(std::max<long long>(n_items, 1), 1 << 30); }
 
 // device scratch for descriptor tables of one call (all classes uploaded at once)
 static void *upload_desc(pcm_ctx *ctx, const void *h, size_t bytes) {
@@ -366,11 +370,10 @@ static void *upload_desc(pcm_ctx *ctx, const void *h, size_t bytes) {
 template <typename T>
 static void esp_class_launch(pcm_ctx *ctx, int L, const EspDesc *d, int nd, long long n_items) {
     const T *tab = boys_tab<T>(ctx);
-    const int grid = int_grid(n_items);
     switch (L) {
 #define ESP_CASE(LL)                                                                        \
     case LL:                                                                                \
-        k_esp<LL, T><<<grid, 256, 0, ctx->stream>>>(d, nd, n_items, tab);                   \
+        k_esp<LL, T><<<int_grid(n_items), 256, 0, ctx->stream>>>(d, nd, n_items, tab);      \
         break;
         ESP_CASE(0) ESP_CASE(1) ESP_CASE(2) ESP_CASE(3) ESP_CASE(4)
 #undef ESP_CASE
@@ -501,11 +504,10 @@ void run_esp(pcm_ctx *ctx, pcm_mol *mol, double *c, int prec) { run_esp_batch(ct
 template <typename T>
 static void fock_class_launch(pcm_ctx *ctx, int L, const FockDesc *d, int nd, long long n_items) {
     const T *tab = boys_tab<T>(ctx);
-    const int grid = int_grid(n_items);
     switch (L) {
-#define FV_CASE(LL)                                                                         \
-    case LL:                                                                                \
-        k_fock_v<LL, T><<<grid, 256, 0, ctx->stream>>>(d, nd, n_items, tab);                \
+#define FV_CASE(LL)                                                                                      \
+    case LL:                                                                                             \
+        k_fock_v<LL, T><<<int_grid(n_items), 256, 0, ctx->stream>>>(d, nd, n_items, tab);                \
         break;
         FV_CASE(0) FV_CASE(1) FV_CASE(2) FV_CASE(3) FV_CASE(4)
 #undef FV_CASE

@@ -121,10 +121,15 @@ template <typename T> struct PtInt {
 };
 constexpr int PT_PAD = 64;  // point arrays are padded to a multiple of this with far dummies
 
+// Columns of the LDS copy of the Boys table a kernel needs: F_0 .. F_{L+ORD} for R^(n),
+// n <= L.  Kernels stage only these columns, so low-L kernels keep more workgroups resident.
+template <typename T, int L> __host__ __device__ constexpr int boys_cols() { return L + BoysCfg<T>::ORD + 1; }
+
 template <int L, typename T>
 __device__ __forceinline__ void aux_Rn(T r2, T p, T limp, T pf, T pref, T zeta2, T zeta, T limk,
                                        const T *__restrict__ tab, T (&Rn)[L + 1]) {
     using C = BoysCfg<T>;
+    static_assert(boys_cols<T, L>() <= C::MT, "Boys table has too few columns for this L");
     if (r2 >= limp + limk) {
         T ri = rsq_fast(r2);
         T ri2 = ri * ri;
@@ -144,7 +149,7 @@ __device__ __forceinline__ void aux_Rn(T r2, T p, T limp, T pf, T pref, T zeta2,
         w[0] = T(1);
 #pragma unroll
         for (int k = 1; k <= C::ORD; ++k) w[k] = w[k - 1] * d * (T(1) / T(k));
-        const T *row = tab + i * C::MT;
+        const T *row = tab + i * boys_cols<T, L>();
         T fac = pref * su;
         T m2a = T(-2) * a;
 #pragma unroll
@@ -184,13 +189,18 @@ template <typename T> using cptr = const T *;
 #endif
 template <typename T> __device__ __forceinline__ cptr<T> as_const(const T *p) { return (cptr<T>)(p); }
 
-// Load the Boys table of type T into LDS (tab_g holds BoysCfg<T>::NROW * MT values).
-template <typename T>
+// Stage the Boys columns an order-L evaluation reads into LDS (row stride boys_cols<T, L>);
+// tab_g holds BoysCfg<T>::NROW rows of MT values.
+template <typename T, int L>
 __device__ __forceinline__ void load_boys(T *lds, const T *__restrict__ tab_g) {
-    constexpr int n = BoysCfg<T>::NROW * BoysCfg<T>::MT;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = tab_g[i];
+    constexpr int NC = boys_cols<T, L>(), n = BoysCfg<T>::NROW * NC;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int row = i / NC, col = i - row * NC;
+        lds[i] = tab_g[row * BoysCfg<T>::MT + col];
+    }
     __syncthreads();
 }
+template <typename T, int L> constexpr int boys_lds_size() { return BoysCfg<T>::NROW * boys_cols<T, L>(); }
 
 // ----------------------------------------------------------------------------------------
 // 1-D Hermite expansion coefficients of a Cartesian Gaussian product (without the
