@@ -346,6 +346,7 @@ __global__ __launch_bounds__(TILE) void k_cg_update(const CGMol *__restrict__ ta
 __global__ __launch_bounds__(TILE) void k_rbj_items(const CGMol *__restrict__ tab, const CGState *__restrict__ st,
                                                     const RbjItem *__restrict__ items, int n) {
     __shared__ double s[TILE];
+    __shared__ double rb[1024];  // the block's residual entries, gathered once (l <= 1024)
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const RbjItem w = items[it];
         if (st[w.mol].done) continue;
@@ -353,17 +354,19 @@ __global__ __launch_bounds__(TILE) void k_rbj_items(const CGMol *__restrict__ ta
         const int o = m.boff[w.blk], l = m.boff[w.blk + 1] - o;
         const int i = w.i0 + threadIdx.x;
         const double *__restrict__ r = m.v[V_R];
+        const int *__restrict__ pm = m.perm + o;
+        for (int j = threadIdx.x; j < l; j += TILE) rb[j] = r[pm[j]];
+        __syncthreads();
         double rz = 0.0;
         if (i < l) {
             const double *__restrict__ Ab = m.inv + m.ioff[w.blk];
-            const int *__restrict__ pm = m.perm + o;
             double acc = 0.0;
-            for (int j = 0; j < l; ++j) acc = fma(Ab[(long long)j * l + i], r[pm[j]], acc);
+            for (int j = 0; j < l; ++j) acc = fma(Ab[(long long)j * l + i], rb[j], acc);
             const int ki = pm[i];
             m.v[V_Z][ki] = acc;
-            rz = acc * r[ki];
+            rz = acc * rb[i];
         }
-        double t = blk_sum(rz, s);
+        double t = blk_sum(rz, s);  // its barriers also keep rb intact until every lane is done
         if (threadIdx.x == 0) m.dp[2 * m.ndp + w.slot] = t;
     }
 }
@@ -898,6 +901,8 @@ pcm_status solve_batch_run(pcm_ctx *ctx, SolveBatch &B, const std::vector<const 
     const int n = B.n;
     const double f = (ctx->prm.eps - 1.0) / (ctx->prm.eps + ctx->prm.k_factor);
     const bool rbj = o.precond == PCM_PRECOND_RBJ;
+    // work already queued on the stream (e.g. the esp that produced v) is not the solve's
+    HIP_OK(hipStreamSynchronize(ctx->stream));
     auto t0 = std::chrono::steady_clock::now();
     for (pcm_mol *mol : B.mols) {
         solver_prepare(ctx, mol);
