@@ -425,7 +425,7 @@ pcm_status pcm_surface_get(pcm_ctx *ctx, const pcm_mol *mol, double *r, double *
         if (S) HIP_OK(hipMemcpyAsync(S, mol->S.p, M * 8, hipMemcpyDeviceToDevice, ctx->stream));
         if (Akk) HIP_OK(hipMemcpyAsync(Akk, mol->Akk.p, M * 8, hipMemcpyDeviceToDevice, ctx->stream));
         if (owner || sph) {
-            k_owner_sph<<<div_up(M, 256), 256, 0, ctx->stream>>>(mol->keep.p, (int)M, mol->nsph, owner, sph);
+            k_owner_sph<<<grid_for(M, 256), 256, 0, ctx->stream>>>(mol->keep.p, (int)M, mol->nsph, owner, sph);
             HIP_LAUNCH_OK();
         }
         return PCM_OK;

@@ -365,6 +365,10 @@ static void grad_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, const doubl
     const T *tab = sizeof(T) == 8 ? (const T *)ctx->boys64.p : (const T *)ctx->boys32.p;
     const PtInt<T> *pts = reinterpret_cast<const PtInt<T> *>(sizeof(T) == 8 ? mol->pti64.p : mol->pti32.p);
     const int Mpad = mol->Mpad;
+    if (M == 0) {  // no surface charge: every term of Eq. 14 carries a factor q
+        HIP_OK(hipMemsetAsync(g_nuc, 0, sizeof(double) * 3 * mol->N, ctx->stream));
+        return;
+    }
     HIP_OK(hipMemcpyAsync(mol->qpad.p, q, sizeof(double) * M, hipMemcpyDeviceToDevice, ctx->stream));
     // --- A off-diagonal
     int len_a = chunk_for(M, M);

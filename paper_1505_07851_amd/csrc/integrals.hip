@@ -153,7 +153,7 @@ __global__ void k_bz(const double *__restrict__ px, const double *__restrict__ p
 
 void run_bz(pcm_ctx *ctx, pcm_mol *mol, double *bz) {
     ProfScope ps(ctx, "bz", (double)mol->M * mol->N);
-    k_bz<<<div_up(mol->M, 256), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p, mol->M, mol->zeta.p,
+    k_bz<<<grid_for(mol->M, 256), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p, mol->M, mol->zeta.p,
                                                           mol->xyz.p, mol->Z.p, mol->N, bz);
     HIP_LAUNCH_OK();
 }

@@ -413,3 +413,6 @@ int host_rbj_partition(int M, const double *r, const double *zeta, int l, unsign
                        int *blk_off);
 
 inline int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
+// grid size for a bounds-checked 1-D launch over n items; never 0 (an empty molecule, e.g.
+// with every surface point pruned, still launches one workgroup whose lanes all exit)
+inline int grid_for(long long n, int block) { return n > 0 ? div_up(n, block) : 1; }

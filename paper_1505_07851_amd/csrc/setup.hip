@@ -251,7 +251,7 @@ void surface_build(pcm_ctx *ctx, pcm_mol *mol, bool prune) {
 
 void surface_points(pcm_ctx *ctx, pcm_mol *mol, const double *r_explicit_dev) {
     const int T = 256;
-    k_surface_points<<<div_up(mol->Mpad, T), T, 0, ctx->stream>>>(
+    k_surface_points<<<grid_for(mol->Mpad, T), T, 0, ctx->stream>>>(
         mol->xyz.p, mol->rad.p, mol->N, mol->dirs.p, mol->w.p, mol->nsph, mol->keep.p, mol->M, r_explicit_dev,
         ctx->prm.zeta0, ctx->prm.diag_const, mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p, mol->S.p, mol->Akk.p,
         mol->Mpad, reinterpret_cast<PtInt<double> *>(mol->pti64.p), reinterpret_cast<PtInt<float> *>(mol->pti32.p),

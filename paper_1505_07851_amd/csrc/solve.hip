@@ -532,7 +532,7 @@ static void solver_prepare(pcm_ctx *ctx, pcm_mol *mol) {
         HIP_OK(hipMemsetAsync(mol->sv.p, 0, L.total * sizeof(double), ctx->stream));
     }
     const int Mp = sv_pad(mol->M);
-    k_pack_pts<<<div_up(Mp, 256), 256, 0, ctx->stream>>>(
+    k_pack_pts<<<grid_for(Mp, 256), 256, 0, ctx->stream>>>(
         mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p, mol->M, Mp,
         reinterpret_cast<Pt<double> *>(mol->sv.p + L.pt64), reinterpret_cast<Pt<float> *>(mol->sv.p + L.pt32));
     HIP_LAUNCH_OK();
@@ -667,6 +667,10 @@ static void batch_tables(pcm_ctx *ctx, SolveBatch &B, int precond) {
 }
 
 static void upload_states(pcm_ctx *ctx, SolveBatch &B) {
+    // a molecule without surface points has nothing to iterate (its tile kernels never run,
+    // so the device would never set its stop flag)
+    for (int i = 0; i < B.n; ++i)
+        if (B.h_tab[i].M == 0) B.h_st[i].done = 1;
     HIP_OK(hipMemcpyAsync(B.st.p, B.h_st.data(), B.n * sizeof(CGState), hipMemcpyHostToDevice, ctx->stream));
 }
 
@@ -711,6 +715,7 @@ static void launch_mv(pcm_ctx *ctx, SolveBatch &B, hipStream_t s, int prec, int 
 }
 
 static int mv_grid(pcm_ctx *ctx, SolveBatch &B, int prec, int gate, int src) {
+    if (B.n_mv == 0) return 1;  // every molecule of the batch is empty
     auto key = std::make_pair(prec, B.n_mv);
     auto f = g_mv_grid.find(key);
     if (f != g_mv_grid.end()) return f->second;
@@ -906,7 +911,7 @@ pcm_status solve_batch_run(pcm_ctx *ctx, SolveBatch &B, const std::vector<const 
     auto t0 = std::chrono::steady_clock::now();
     for (pcm_mol *mol : B.mols) {
         solver_prepare(ctx, mol);
-        if (rbj) rbj_setup(ctx, mol, o.block, o.seed);
+        if (rbj && mol->M > 0) rbj_setup(ctx, mol, o.block, o.seed);
     }
     batch_tables(ctx, B, o.precond);
     std::vector<const double *> qc(q.begin(), q.end());
