@@ -52,7 +52,7 @@ typedef enum {
 } pcm_status;
 
 enum { PCM_FP64 = 0, PCM_MIXED = 1 };
-enum { PCM_PRECOND_NONE = 0, PCM_PRECOND_JACOBI = 1, PCM_PRECOND_RBJ = 2 };
+enum { PCM_PRECOND_NONE = 0, PCM_PRECOND_JACOBI = 1, PCM_PRECOND_RBJ = 2, PCM_PRECOND_OCTREE = 3 };
 
 typedef struct pcm_ctx pcm_ctx;
 typedef struct pcm_mol pcm_mol;
@@ -97,9 +97,12 @@ typedef struct {
 } pcm_basis;
 
 /* Solver options (Sec. 4b).
- *   precond     PCM_PRECOND_NONE, _JACOBI (diag(A)^-1) or _RBJ (randomized block Jacobi)
- *   block       RBJ block size l (paper: 100)
- *   seed        SplitMix64 seed of the RBJ partition
+ *   precond     PCM_PRECOND_NONE, _JACOBI (diag(A)^-1), _RBJ (randomized block Jacobi) or
+ *               _OCTREE (block Jacobi over the leaves of a spatial octree, the scheme RBJ is
+ *               compared with in Sec. 4b-ii; see pcm_octree_partition)
+ *   block       RBJ block size l (paper: 100), or the largest octree leaf (paper: 800);
+ *               1..1024 for both
+ *   seed        SplitMix64 seed of the RBJ partition (unused by the octree)
  *   tol         stop when ||A q - b||_2 < tol (Eq. 20), absolute, atomic units; use
  *               pcm_dynamic_threshold for the Eq. 21 schedule
  *   max_iter    bound on matrix-vector products
@@ -194,6 +197,28 @@ pcm_status pcm_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q
  * 1.0 when diis_err_prev < 0 (first SCF step).  Pure host function. */
 double pcm_dynamic_threshold(double diis_err_prev);
 
+/* CG threshold policies of Sec. 4b-i, one call per SCF step with the previous step's DIIS
+ * error (max element of X^T (SPF - FPS) X; negative on the first step).  Pure host functions.
+ *   PCM_THRESH_FIXED      delta every step
+ *   PCM_THRESH_TWO_DELTA  2-delta switching: the loose delta_1 = scale * delta until the DIIS
+ *                         error has reached switch_at, the tight delta_2 = delta from then on
+ *                         (the switch happens once: `switched` latches; paper: scale 1e4,
+ *                         switch_at 1e-3, delta 1e-5..1e-7)
+ *   PCM_THRESH_DYNAMIC    pcm_dynamic_threshold (Eq. 21); delta, scale, switch_at unused
+ * pcm_default_threshold_policy fills delta 1e-6, scale 1e4, switch_at 1e-3, switched 0.
+ * pcm_cg_threshold returns the threshold for this step (and updates `switched`), or -1 on a
+ * bad policy (NULL, unknown kind, non-finite or non-positive delta, scale < 1, switch_at < 0). */
+enum { PCM_THRESH_FIXED = 0, PCM_THRESH_TWO_DELTA = 1, PCM_THRESH_DYNAMIC = 2 };
+typedef struct {
+    int kind;
+    double delta;
+    double scale;
+    double switch_at;
+    int switched;
+} pcm_threshold_policy;
+void pcm_default_threshold_policy(pcm_threshold_policy *p, int kind);
+double pcm_cg_threshold(pcm_threshold_policy *p, double diis_err_prev);
+
 /* Randomized block-Jacobi partition (Sec. 4b-ii) of M points, on the host: a SplitMix64
  * stream from `seed` picks a random pivot among the unassigned points (kept in ascending
  * order; index floor(u n_left), u = (x >> 11) 2^-53); the block is the pivot plus the l-1
@@ -203,6 +228,16 @@ double pcm_dynamic_threshold(double diis_err_prev);
  * bad argument. */
 int pcm_rbj_partition(int M, const double *r, const double *zeta, int l, unsigned long long seed, int *perm,
                       int *blk_off);
+
+/* Spatial octree partition (the block-Jacobi scheme of Sec. 4b-ii that RBJ is compared
+ * with), on the host.  The root is the cube centred on the midpoint of the points' bounding
+ * box with half-side half its largest extent; a cell with more than leaf_max points is cut
+ * into octants at its centre (octant = [x >= cx] + 2 [y >= cy] + 4 [z >= cz]); leaves are
+ * emitted depth first in octant order, empty cells dropped, members ascending; a cell still
+ * too full at depth 40 (coincident points) is cut into consecutive runs of leaf_max.
+ * HOST: r[M*3]; outputs perm[M] and blk_off[n_blocks+1] (capacity M+1); returns
+ * n_blocks, or -1 on a bad argument (M < 1, leaf_max < 1, NULL, non-finite r). */
+int pcm_octree_partition(int M, const double *r, int leaf_max, int *perm, int *blk_off);
 
 /* Copy the surface out.  DEVICE outputs (any may be NULL): r[M*3], zeta[M], S[M],
  * Akk[M], owner[M] (int32 atom index), sph[M] (int32 sphere-point index). */

@@ -16,7 +16,11 @@ Readings of the paper that this oracle takes (listed in the design doc as well):
 * Eq. 20 residual: Euclidean norm of A q - b, absolute, in atomic units;
 * Eq. 21 dynamic threshold: 0.01 delta^1.07 = 1e-3 e_prev, i.e.
   delta = (0.1 e_prev)^(1/1.07), clamped to [1e-10, 1], delta = 1 at the
-  first SCF step.
+  first SCF step;
+* 2-delta switching (Sec. 4b-i): the switch to the tight threshold is made once,
+  at the first step whose previous DIIS error is at or below 1e-3;
+* octree block Jacobi (Sec. 4b-ii, the comparison scheme): the cell rules in
+  ``octree_partition``.
 """
 from __future__ import annotations
 
@@ -107,6 +111,78 @@ def dynamic_threshold(e_prev: float) -> float:
         return 1e-10
     d = (0.1 * e_prev) ** (1.0 / 1.07)
     return min(1.0, max(1e-10, d))
+
+
+def threshold_schedule(kind, diis_errors, delta=1e-6, scale=1e4, switch_at=1e-3):
+    """CG thresholds of the SCF steps whose previous DIIS errors are ``diis_errors`` (None
+    or a negative value for the first step), Sec. 4b-i:
+
+    * fixed: delta at every step;
+    * two_delta: the loose scale * delta until a previous DIIS error is at or below
+      switch_at, the tight delta from that step on (reading: the switch is made once);
+    * dynamic: Eq. 21 through ``dynamic_threshold``.
+    """
+    out, switched = [], False
+    for e in diis_errors:
+        first = e is None or e < 0
+        if kind == "fixed":
+            out.append(delta)
+        elif kind == "two_delta":
+            if not first and e <= switch_at:
+                switched = True
+            out.append(delta if switched else scale * delta)
+        elif kind == "dynamic":
+            out.append(dynamic_threshold(-1.0 if first else e))
+        else:
+            raise ValueError(f"unknown threshold policy {kind!r}")
+    return out
+
+
+OCTREE_MAX_DEPTH = 40
+
+
+def octree_partition(r, leaf_max):
+    """Spatial octree partition of points r[M, 3] for block Jacobi (the comparison
+    preconditioner of Sec. 4b-ii): a leaf holds at most ``leaf_max`` points.
+
+    Reading (the paper names the scheme only): the root is the cube centred on the
+    midpoint of the bounding box with half-side half the largest extent; a cell with more
+    than ``leaf_max`` points is cut into 8 octants at its centre, a point going to octant
+    (x >= cx) + 2 (y >= cy) + 4 (z >= cz); children are visited depth first in octant
+    order and empty cells are dropped; a leaf stores its points in ascending index.  A
+    cell still too full at depth 40 (coincident points) is cut into consecutive runs of
+    ``leaf_max`` points.  Returns (perm, off) like the randomized partition.
+    """
+    r = np.asarray(r, dtype=np.float64).reshape(-1, 3)
+    M = r.shape[0]
+    if M < 1 or leaf_max < 1:
+        raise ValueError("octree_partition needs M >= 1 and leaf_max >= 1")
+    lo, hi = r.min(axis=0), r.max(axis=0)
+    centre = (lo + hi) * 0.5
+    half = float((hi - lo).max()) * 0.5
+    leaves = []
+
+    def visit(idx, c, h, depth):
+        if idx.size <= leaf_max:
+            leaves.append(idx)
+            return
+        if depth == OCTREE_MAX_DEPTH:
+            for s in range(0, idx.size, leaf_max):
+                leaves.append(idx[s:s + leaf_max])
+            return
+        octant = ((r[idx, 0] >= c[0]).astype(np.int64) + 2 * (r[idx, 1] >= c[1]) + 4 * (r[idx, 2] >= c[2]))
+        for o in range(8):
+            sub = idx[octant == o]
+            if sub.size == 0:
+                continue
+            cc = np.array([c[d] + (0.5 * h if (o >> d) & 1 else -0.5 * h) for d in range(3)])
+            visit(sub, cc, 0.5 * h, depth + 1)
+
+    visit(np.arange(M, dtype=np.int64), centre, half, 0)
+    perm = np.concatenate(leaves).astype(np.int32)
+    off = np.zeros(len(leaves) + 1, np.int32)
+    off[1:] = np.cumsum([lf.size for lf in leaves])
+    return perm, off
 
 
 class OracleMol:
@@ -266,14 +342,23 @@ class OracleMol:
                                     _p(perm), _p(off))
         return perm, off[: nb + 1].copy()
 
+    def octree_partition(self, leaf_max):
+        return octree_partition(self.r, leaf_max)
+
     def preconditioner(self, kind="jacobi", block=100, seed=0, A=None):
-        """Return a function z = C r for kind in {none, jacobi, rbj} (Sec. 4b-ii)."""
+        """Return a function z = C r for kind in {none, jacobi, rbj, octree} (Sec. 4b-ii);
+        for octree, ``block`` is the largest leaf."""
         if kind == "none":
             return lambda r: r.copy()
         if kind == "jacobi":
             d = 1.0 / self.Akk
             return lambda r: d * r
-        perm, off = self.rbj_partition(block, seed)
+        if kind == "octree":
+            perm, off = self.octree_partition(block)
+        elif kind == "rbj":
+            perm, off = self.rbj_partition(block, seed)
+        else:
+            raise ValueError(f"unknown preconditioner {kind!r}")
         blocks = []
         for b in range(off.shape[0] - 1):
             idx = perm[off[b]:off[b + 1]]

@@ -14,11 +14,13 @@ PCM_OK, PCM_E_ARG, PCM_E_ALLOC, PCM_E_HIP, PCM_E_NOCONV, PCM_E_NOTPD, PCM_E_UNSU
 STATUS_NAMES = {0: "PCM_OK", 1: "PCM_E_ARG", 2: "PCM_E_ALLOC", 3: "PCM_E_HIP", 4: "PCM_E_NOCONV",
                 5: "PCM_E_NOTPD", 6: "PCM_E_UNSUPPORTED", 7: "PCM_E_STATE"}
 PCM_FP64, PCM_MIXED = 0, 1
-PCM_PRECOND_NONE, PCM_PRECOND_JACOBI, PCM_PRECOND_RBJ = 0, 1, 2
+PCM_PRECOND_NONE, PCM_PRECOND_JACOBI, PCM_PRECOND_RBJ, PCM_PRECOND_OCTREE = 0, 1, 2, 3
+PCM_THRESH_FIXED, PCM_THRESH_TWO_DELTA, PCM_THRESH_DYNAMIC = 0, 1, 2
 
 EXPORTED = ["pcm_default_params", "pcm_default_solve_opts", "pcm_create", "pcm_destroy", "pcm_last_error",
             "pcm_build_surface", "pcm_update_geometry", "pcm_esp", "pcm_fock", "pcm_solve", "pcm_energy", "pcm_grad",
-            "pcm_dynamic_threshold", "pcm_rbj_partition", "pcm_surface_get", "pcm_mol_sizes", "pcm_pair_list",
+            "pcm_dynamic_threshold", "pcm_default_threshold_policy", "pcm_cg_threshold", "pcm_rbj_partition",
+            "pcm_octree_partition", "pcm_surface_get", "pcm_mol_sizes", "pcm_pair_list",
             "pcm_mol_destroy", "pcm_batch_create", "pcm_batch_destroy", "pcm_esp_batched", "pcm_fock_batched",
             "pcm_solve_batched",
             "pcm_profile_enable", "pcm_profile_collect", "pcm_profile_entry"]
@@ -40,6 +42,11 @@ class pcm_solve_opts(ctypes.Structure):
     _fields_ = [("precond", ctypes.c_int), ("block", ctypes.c_int), ("seed", ctypes.c_ulonglong),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("warm_start", ctypes.c_int),
                 ("precision", ctypes.c_int), ("inner_rtol", ctypes.c_double)]
+
+
+class pcm_threshold_policy(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("delta", ctypes.c_double), ("scale", ctypes.c_double),
+                ("switch_at", ctypes.c_double), ("switched", ctypes.c_int)]
 
 
 class pcm_solve_info(ctypes.Structure):
@@ -68,7 +75,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "pcm_energy": (i, [vp, vp, vp, vp, vp, P(d)]),
         "pcm_grad": (i, [vp, vp, vp, vp, vp, vp]),
         "pcm_dynamic_threshold": (d, [d]),
+        "pcm_default_threshold_policy": (None, [P(pcm_threshold_policy), i]),
+        "pcm_cg_threshold": (d, [P(pcm_threshold_policy), d]),
         "pcm_rbj_partition": (i, [i, vp, vp, i, ctypes.c_ulonglong, vp, vp]),
+        "pcm_octree_partition": (i, [i, vp, i, vp, vp]),
         "pcm_surface_get": (i, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "pcm_mol_sizes": (i, [vp, P(i), P(i), P(i), vp, vp, vp, vp]),
         "pcm_pair_list": (i, [vp, vp, i, vp, vp, vp, vp, vp]),

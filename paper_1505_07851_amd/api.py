@@ -249,7 +249,8 @@ class Molecule:
 def _solve_opts(lib, precond, block, seed, tol, max_iter, precision, inner_rtol):
     o = C.pcm_solve_opts()
     lib.pcm_default_solve_opts(ctypes.byref(o))
-    o.precond = {"none": C.PCM_PRECOND_NONE, "jacobi": C.PCM_PRECOND_JACOBI, "rbj": C.PCM_PRECOND_RBJ}[precond]
+    o.precond = {"none": C.PCM_PRECOND_NONE, "jacobi": C.PCM_PRECOND_JACOBI, "rbj": C.PCM_PRECOND_RBJ,
+                 "octree": C.PCM_PRECOND_OCTREE}[precond]
     o.block, o.seed, o.tol, o.max_iter = int(block), int(seed), float(tol), int(max_iter)
     o.precision = C.PCM_MIXED if precision == "mixed" else C.PCM_FP64
     o.inner_rtol = float(inner_rtol)
@@ -349,8 +350,46 @@ def rbj_partition(r, zeta, block: int, seed: int):
     return perm, off[: nb + 1].copy()
 
 
+def octree_partition(r, leaf_max: int):
+    """Spatial octree partition on the host (the block-Jacobi scheme RBJ is compared with in
+    Sec. 4b-ii); returns (perm, blk_off)."""
+    r = _np(r, np.float64).reshape(-1, 3)
+    M = r.shape[0]
+    perm = np.zeros(M, np.int32)
+    off = np.zeros(M + 1, np.int32)
+    nb = C.lib().pcm_octree_partition(M, _hp(r), int(leaf_max), _hp(perm), _hp(off))
+    if nb < 0:
+        raise PCMError(C.PCM_E_ARG, "bad partition arguments")
+    return perm, off[: nb + 1].copy()
+
+
+class ThresholdPolicy:
+    """CG threshold per SCF step (Sec. 4b-i): ``fixed`` (delta every step), ``two_delta``
+    (scale * delta until the previous DIIS error reaches switch_at, delta afterwards) or
+    ``dynamic`` (Eq. 21).  Call with the previous step's DIIS error (None on the first)."""
+
+    KINDS = {"fixed": C.PCM_THRESH_FIXED, "two_delta": C.PCM_THRESH_TWO_DELTA, "dynamic": C.PCM_THRESH_DYNAMIC}
+
+    def __init__(self, kind="dynamic", delta=1e-6, scale=1e4, switch_at=1e-3):
+        self.kind = kind
+        self._p = C.pcm_threshold_policy()
+        C.lib().pcm_default_threshold_policy(ctypes.byref(self._p), self.KINDS[kind])
+        self._p.delta, self._p.scale, self._p.switch_at = float(delta), float(scale), float(switch_at)
+
+    @property
+    def switched(self) -> bool:
+        return bool(self._p.switched)
+
+    def __call__(self, diis_err_prev=None) -> float:
+        d = C.lib().pcm_cg_threshold(ctypes.byref(self._p), float(-1.0 if diis_err_prev is None else diis_err_prev))
+        if d < 0:
+            raise PCMError(C.PCM_E_ARG, "bad threshold policy")
+        return d
+
+
 def default_f(eps=78.39, k=0.0):
     return (eps - 1.0) / (eps + k)
 
 
-__all__ = ["Context", "Molecule", "Batch", "PCMError", "dynamic_threshold", "rbj_partition", "math"]
+__all__ = ["Context", "Molecule", "Batch", "PCMError", "ThresholdPolicy", "dynamic_threshold", "octree_partition",
+           "rbj_partition", "math"]

@@ -133,9 +133,9 @@ pcm_status check_basis(pcm_ctx *ctx, int n_atoms, const pcm_basis *b, int *nprim
 pcm_status check_solve_opts(pcm_ctx *ctx, const pcm_solve_opts *opts, pcm_solve_opts &o) {
     pcm_default_solve_opts(&o);
     if (opts) o = *opts;
-    if (o.precond < PCM_PRECOND_NONE || o.precond > PCM_PRECOND_RBJ) return fail(ctx, PCM_E_ARG, "bad precond");
-    if (o.precond == PCM_PRECOND_RBJ && (o.block < 1 || o.block > 1024))
-        return fail(ctx, PCM_E_ARG, "RBJ block size must be in [1, 1024]");
+    if (o.precond < PCM_PRECOND_NONE || o.precond > PCM_PRECOND_OCTREE) return fail(ctx, PCM_E_ARG, "bad precond");
+    if ((o.precond == PCM_PRECOND_RBJ || o.precond == PCM_PRECOND_OCTREE) && (o.block < 1 || o.block > 1024))
+        return fail(ctx, PCM_E_ARG, "block-Jacobi block size must be in [1, 1024]");
     if (!is_fin(o.tol) || !(o.tol > 0.0)) return fail(ctx, PCM_E_ARG, "tol must be > 0");
     if (o.max_iter < 1) return fail(ctx, PCM_E_ARG, "max_iter must be >= 1");
     if (o.precision != PCM_FP64 && o.precision != PCM_MIXED) return fail(ctx, PCM_E_ARG, "bad precision");
@@ -394,10 +394,46 @@ double pcm_dynamic_threshold(double e) {
     return std::min(1.0, std::max(1e-10, d));
 }
 
+void pcm_default_threshold_policy(pcm_threshold_policy *p, int kind) {
+    if (!p) return;
+    p->kind = kind;
+    p->delta = 1e-6;
+    p->scale = 1e4;
+    p->switch_at = 1e-3;
+    p->switched = 0;
+}
+
+double pcm_cg_threshold(pcm_threshold_policy *p, double e) {
+    if (!p) return -1.0;
+    switch (p->kind) {
+    case PCM_THRESH_FIXED:
+        return is_fin(p->delta) && p->delta > 0.0 ? p->delta : -1.0;
+    case PCM_THRESH_TWO_DELTA:
+        if (!is_fin(p->delta) || !(p->delta > 0.0) || !is_fin(p->scale) || !(p->scale >= 1.0) ||
+            !is_fin(p->switch_at) || !(p->switch_at >= 0.0))
+            return -1.0;
+        // the switch to the tight threshold is made once, when the DIIS error has reached switch_at
+        if (!p->switched && e >= 0.0 && e <= p->switch_at) p->switched = 1;
+        return p->switched ? p->delta : p->scale * p->delta;
+    case PCM_THRESH_DYNAMIC:
+        return pcm_dynamic_threshold(e);
+    default:
+        return -1.0;
+    }
+}
+
 int pcm_rbj_partition(int M, const double *r, const double *zeta, int l, unsigned long long seed, int *perm,
                       int *blk_off) {
     try {
         return host_rbj_partition(M, r, zeta, l, seed, perm, blk_off);
+    } catch (...) {
+        return -1;
+    }
+}
+
+int pcm_octree_partition(int M, const double *r, int leaf_max, int *perm, int *blk_off) {
+    try {
+        return host_octree_partition(M, r, leaf_max, perm, blk_off);
     } catch (...) {
         return -1;
     }

@@ -355,7 +355,7 @@ struct pcm_mol {
     DevBuf<int> rbj_perm, rbj_off;
     DevBuf<long long> rbj_ioff;
     std::vector<int> h_rbj_perm, h_rbj_off;
-    int rbj_l = -1, rbj_lmax = 0;
+    int rbj_kind = 0, rbj_l = -1, rbj_lmax = 0;
     RbjPending *rbj_pending = nullptr;  // partition started on a host thread after a geometry update
     unsigned long long rbj_seed = 0;
     bool rbj_valid = false;
@@ -402,7 +402,8 @@ double run_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double *c,
 void run_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc, double *g_surf,
               int prec);
 void surface_points(pcm_ctx *ctx, pcm_mol *mol, const double *r_explicit_dev);
-void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int l, unsigned long long seed);
+// kind: PCM_PRECOND_RBJ (l = block size) or PCM_PRECOND_OCTREE (l = largest leaf)
+void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int kind, int l, unsigned long long seed);
 void rbj_prefetch(pcm_ctx *ctx, pcm_mol *mol);
 void rbj_pending_drop(pcm_mol *mol);
 SolveBatch *solve_batch_new(const std::vector<pcm_mol *> &mols);
@@ -411,6 +412,9 @@ pcm_status solve_batch_run(pcm_ctx *ctx, SolveBatch &B, const std::vector<const 
                            const std::vector<double *> &q, const pcm_solve_opts &o, pcm_solve_info *info);
 int host_rbj_partition(int M, const double *r, const double *zeta, int l, unsigned long long seed, int *perm,
                        int *blk_off);
+int host_octree_partition(int M, const double *r, int leaf_max, int *perm, int *blk_off);
+int block_partition(int kind, int M, const double *r, const double *zeta, int l, unsigned long long seed, int *perm,
+                    int *blk_off);
 
 inline int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
 // grid size for a bounds-checked 1-D launch over n items; never 0 (an empty molecule, e.g.

@@ -1,5 +1,6 @@
-// Randomized block-Jacobi preconditioner (Sec. 4b-ii): the partition (host), the explicit
-// inverses of the diagonal blocks of the permuted A (device) and their application.
+// Block-Jacobi preconditioners (Sec. 4b-ii): the randomized partition and the spatial octree
+// partition it is compared with (host), and the explicit inverses of the diagonal blocks of
+// the permuted A (device).
 #include "pcm_internal.h"
 
 #include <algorithm>
@@ -92,6 +93,7 @@ static void positions_to_host(pcm_ctx *ctx, pcm_mol *mol, std::vector<double> &r
 // host thread for the block size and seed used last; the next solve with the same options
 // joins it instead of partitioning while the GPU waits.
 struct RbjPending {
+    int kind = 0;
     int l = 0;
     unsigned long long seed = 0;
     std::vector<double> r, zeta;
@@ -108,8 +110,9 @@ void rbj_pending_drop(pcm_mol *mol) {
 
 void rbj_prefetch(pcm_ctx *ctx, pcm_mol *mol) {
     rbj_pending_drop(mol);
-    if (mol->rbj_l < 1 || mol->M < 1) return;  // no RBJ solve on this molecule yet
+    if (mol->rbj_l < 1 || mol->M < 1) return;  // no block-Jacobi solve on this molecule yet
     RbjPending *p = new RbjPending();
+    p->kind = mol->rbj_kind;
     p->l = mol->rbj_l;
     p->seed = mol->rbj_seed;
     try {
@@ -118,7 +121,8 @@ void rbj_prefetch(pcm_ctx *ctx, pcm_mol *mol) {
         p->perm.assign(M, 0);
         p->off.assign(M + 1, 0);
         p->nb = std::async(std::launch::async, [p, M]() {
-            return host_rbj_partition(M, p->r.data(), p->zeta.data(), p->l, p->seed, p->perm.data(), p->off.data());
+            return block_partition(p->kind, M, p->r.data(), p->zeta.data(), p->l, p->seed, p->perm.data(),
+                                   p->off.data());
         });
     } catch (const std::system_error &) {
         delete p;  // no thread available: the solve partitions synchronously
@@ -130,11 +134,13 @@ void rbj_prefetch(pcm_ctx *ctx, pcm_mol *mol) {
     mol->rbj_pending = p;
 }
 
-void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int l, unsigned long long seed) {
-    if (mol->rbj_valid && mol->rbj_l == l && mol->rbj_seed == seed) return;
+void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int kind, int l, unsigned long long seed) {
+    if (kind == PCM_PRECOND_OCTREE) seed = 0;  // the octree partition draws no random numbers
+    if (mol->rbj_valid && mol->rbj_kind == kind && mol->rbj_l == l && mol->rbj_seed == seed) return;
     const int M = mol->M;
     int nb;
-    if (mol->rbj_pending && mol->rbj_pending->l == l && mol->rbj_pending->seed == seed) {
+    RbjPending *pd = mol->rbj_pending;
+    if (pd && pd->kind == kind && pd->l == l && pd->seed == seed) {
         nb = mol->rbj_pending->nb.get();
         mol->h_rbj_perm = std::move(mol->rbj_pending->perm);
         mol->h_rbj_off = std::move(mol->rbj_pending->off);
@@ -145,9 +151,9 @@ void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int l, unsigned long long seed) {
         positions_to_host(ctx, mol, r, zeta);
         mol->h_rbj_perm.assign(M, 0);
         mol->h_rbj_off.assign(M + 1, 0);
-        nb = host_rbj_partition(M, r.data(), zeta.data(), l, seed, mol->h_rbj_perm.data(), mol->h_rbj_off.data());
+        nb = block_partition(kind, M, r.data(), zeta.data(), l, seed, mol->h_rbj_perm.data(), mol->h_rbj_off.data());
     }
-    if (nb <= 0) throw PcmError{PCM_E_ARG, "randomized block-Jacobi partition failed"};
+    if (nb <= 0) throw PcmError{PCM_E_ARG, "block-Jacobi partition failed"};
     mol->h_rbj_off.resize(nb + 1);
     std::vector<long long> ioff(nb + 1, 0);
     int lmax = 0;
@@ -156,7 +162,7 @@ void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int l, unsigned long long seed) {
         ioff[b + 1] = ioff[b] + (long long)sz * sz;
         lmax = std::max(lmax, sz);
     }
-    if (lmax > 1024) throw PcmError{PCM_E_ARG, "RBJ block size above 1024 is not supported"};
+    if (lmax > 1024) throw PcmError{PCM_E_ARG, "block-Jacobi block size above 1024 is not supported"};
     mol->rbj_lmax = lmax;
     mol->rbj_perm.ensure(M);
     mol->rbj_off.ensure(nb + 1);
@@ -180,7 +186,8 @@ void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int l, unsigned long long seed) {
     int bad = 0;
     HIP_OK(hipMemcpyAsync(&bad, ctx->iscal.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIP_OK(hipStreamSynchronize(ctx->stream));
-    if (bad) throw PcmError{PCM_E_NOTPD, "a randomized block-Jacobi block is not positive definite"};
+    if (bad) throw PcmError{PCM_E_NOTPD, "a block-Jacobi block is not positive definite"};
+    mol->rbj_kind = kind;
     mol->rbj_l = l;
     mol->rbj_seed = seed;
     mol->rbj_valid = true;
@@ -308,4 +315,88 @@ int host_rbj_partition(int M, const double *r, const double *zeta, int l, unsign
         blk_off[++nb] = filled;
     }
     return nb;
+}
+
+// ----------------------------------------------------------------------------------------
+// spatial octree partition (the block-Jacobi scheme RBJ is compared with in Sec. 4b-ii): the
+// root is the cube centred on the bounding-box midpoint with half-side half the largest
+// extent; a cell with more than leaf_max points is cut into octants at its centre (octant
+// bit d set when coordinate d >= centre d), children are visited depth first in octant order,
+// empty cells are dropped and a leaf keeps its points in ascending index.  Cells still too
+// full at depth 40 (coincident points) are cut into consecutive runs of leaf_max points.
+// ----------------------------------------------------------------------------------------
+namespace {
+constexpr int OCTREE_MAX_DEPTH = 40;
+
+struct OctreeBuild {
+    const double *r;
+    int leaf_max;
+    int *perm, *off;
+    int nb = 0, pos = 0;
+    std::vector<int> buf;
+    std::vector<unsigned char> oct;
+
+    void leaf(const int *p, int n) {
+        for (int i = 0; i < n; ++i) perm[pos++] = p[i];
+        off[++nb] = pos;
+    }
+    // p[0, n) is ascending; the stable split keeps every octant ascending
+    void visit(int *p, int n, double cx, double cy, double cz, double h, int depth) {
+        if (n <= leaf_max) {
+            leaf(p, n);
+            return;
+        }
+        if (depth == OCTREE_MAX_DEPTH) {
+            for (int s = 0; s < n; s += leaf_max) leaf(p + s, std::min(leaf_max, n - s));
+            return;
+        }
+        int start[9] = {0};
+        for (int i = 0; i < n; ++i) {
+            const double *x = r + 3 * (size_t)p[i];
+            const int o = (x[0] >= cx ? 1 : 0) | (x[1] >= cy ? 2 : 0) | (x[2] >= cz ? 4 : 0);
+            oct[i] = (unsigned char)o;
+            ++start[o + 1];
+        }
+        for (int o = 0; o < 8; ++o) start[o + 1] += start[o];
+        int fill[8];
+        std::copy(start, start + 8, fill);
+        for (int i = 0; i < n; ++i) buf[fill[oct[i]]++] = p[i];
+        std::copy(buf.begin(), buf.begin() + n, p);
+        for (int o = 0; o < 8; ++o) {
+            const int cnt = start[o + 1] - start[o];
+            if (cnt == 0) continue;
+            const double ox = (o & 1) ? 0.5 * h : -0.5 * h, oy = (o & 2) ? 0.5 * h : -0.5 * h,
+                         oz = (o & 4) ? 0.5 * h : -0.5 * h;
+            visit(p + start[o], cnt, cx + ox, cy + oy, cz + oz, 0.5 * h, depth + 1);
+        }
+    }
+};
+}  // namespace
+
+int host_octree_partition(int M, const double *r, int leaf_max, int *perm, int *blk_off) {
+    if (M <= 0 || leaf_max <= 0 || !r || !perm || !blk_off) return -1;
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) lo[d] = hi[d] = r[d];
+    for (int k = 0; k < M; ++k)
+        for (int d = 0; d < 3; ++d) {
+            const double x = r[3 * (size_t)k + d];
+            if (!std::isfinite(x)) return -1;
+            lo[d] = std::min(lo[d], x);
+            hi[d] = std::max(hi[d], x);
+        }
+    const double half = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2])) * 0.5;
+    std::vector<int> idx(M);
+    std::iota(idx.begin(), idx.end(), 0);
+    OctreeBuild ob{r, leaf_max, perm, blk_off};
+    ob.buf.resize(M);
+    ob.oct.resize(M);
+    blk_off[0] = 0;
+    ob.visit(idx.data(), M, (lo[0] + hi[0]) * 0.5, (lo[1] + hi[1]) * 0.5, (lo[2] + hi[2]) * 0.5, half, 0);
+    return ob.nb;
+}
+
+int block_partition(int kind, int M, const double *r, const double *zeta, int l, unsigned long long seed, int *perm,
+                    int *blk_off) {
+    if (kind == PCM_PRECOND_OCTREE) return host_octree_partition(M, r, l, perm, blk_off);
+    return host_rbj_partition(M, r, zeta, l, seed, perm, blk_off);
 }

@@ -590,6 +590,8 @@ static int grid_of(int n) { return n < 1 ? 1 : n; }
 
 // tables that depend on sizes and the RBJ partition; per-call pointers are refreshed each run
 static void batch_tables(pcm_ctx *ctx, SolveBatch &B, int precond) {
+    // the octree differs from RBJ only in its partition; both apply explicit block inverses
+    if (precond == PCM_PRECOND_OCTREE) precond = PCM_PRECOND_RBJ;
     const int n = B.n;
     std::vector<MvItem> mv;
     std::vector<TileItem> tl;
@@ -905,13 +907,13 @@ pcm_status solve_batch_run(pcm_ctx *ctx, SolveBatch &B, const std::vector<const 
                            const std::vector<double *> &q, const pcm_solve_opts &o, pcm_solve_info *info) {
     const int n = B.n;
     const double f = (ctx->prm.eps - 1.0) / (ctx->prm.eps + ctx->prm.k_factor);
-    const bool rbj = o.precond == PCM_PRECOND_RBJ;
+    const bool blocks = o.precond == PCM_PRECOND_RBJ || o.precond == PCM_PRECOND_OCTREE;
     // work already queued on the stream (e.g. the esp that produced v) is not the solve's
     HIP_OK(hipStreamSynchronize(ctx->stream));
     auto t0 = std::chrono::steady_clock::now();
     for (pcm_mol *mol : B.mols) {
         solver_prepare(ctx, mol);
-        if (rbj && mol->M > 0) rbj_setup(ctx, mol, o.block, o.seed);
+        if (blocks && mol->M > 0) rbj_setup(ctx, mol, o.precond, o.block, o.seed);
     }
     batch_tables(ctx, B, o.precond);
     std::vector<const double *> qc(q.begin(), q.end());
@@ -960,7 +962,7 @@ pcm_status solve_batch_run(pcm_ctx *ctx, SolveBatch &B, const std::vector<const 
                 h.max_it = act[i] ? std::min(o.max_iter - iters[i], INNER_MAX_IT) : 0;
             }
             upload_states(ctx, B);
-            pcg_batch(ctx, B, PCM_MIXED, V_D, V_RES, true, rbj);
+            pcg_batch(ctx, B, PCM_MIXED, V_D, V_RES, true, blocks);
             vec_op(ctx, B, 3, 1.0, V_D, V_XQ, nullptr);  // q += d (act molecules)
             download_states(ctx, B);
             for (int i = 0; i < n; ++i)
@@ -976,7 +978,7 @@ pcm_status solve_batch_run(pcm_ctx *ctx, SolveBatch &B, const std::vector<const 
         std::vector<int> run(n, 1);
         bool first = true;
         for (int restart = 0; restart <= MAX_RESTARTS; ++restart) {
-            pcg_batch(ctx, B, PCM_FP64, V_XQ, V_B, first ? !o.warm_start : false, rbj);
+            pcg_batch(ctx, B, PCM_FP64, V_XQ, V_B, first ? !o.warm_start : false, blocks);
             download_states(ctx, B);
             std::vector<int> rec(n, 0);
             for (int i = 0; i < n; ++i)

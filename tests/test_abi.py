@@ -166,3 +166,62 @@ def test_rbj_partition_bit_exact_protein():
 
 def test_rbj_partition_bad_arguments(L):
     assert L.pcm_rbj_partition(0, None, None, 4, 1, None, None) == -1
+
+
+@pytest.mark.parametrize("leaf", [1, 5, 32, 800, 10000])
+def test_octree_partition_bit_exact_water(water_oracle, leaf):
+    from paper_1505_07851_amd import octree_partition
+    om = water_oracle
+    perm, off = octree_partition(om.r, leaf)
+    operm, ooff = om.octree_partition(leaf)
+    assert np.array_equal(off, ooff) and np.array_equal(perm, operm)
+
+
+def test_octree_partition_bit_exact_protein():
+    from paper_1505_07851_amd import octree_partition
+    s = I.small_protein(10, 74, seed=11)
+    om = O.mol_from_system(s)
+    for leaf in (37, 100, 289, 800):
+        perm, off = octree_partition(om.r, leaf)
+        operm, ooff = om.octree_partition(leaf)
+        assert np.array_equal(off, ooff) and np.array_equal(perm, operm)
+    # coincident points: runs after the depth limit
+    perm, off = octree_partition(np.zeros((7, 3)), 3)
+    assert np.array_equal(off, [0, 3, 6, 7]) and np.array_equal(perm, np.arange(7))
+
+
+def test_octree_partition_bad_arguments(L):
+    r = np.zeros(6)
+    out = np.zeros(3, np.int32)
+    assert L.pcm_octree_partition(0, _hp(r), 4, _hp(out), _hp(out)) == -1
+    assert L.pcm_octree_partition(2, _hp(r), 0, _hp(out), _hp(out)) == -1
+    assert L.pcm_octree_partition(2, None, 4, _hp(out), _hp(out)) == -1
+    r[4] = np.nan
+    assert L.pcm_octree_partition(2, _hp(r), 4, _hp(out), _hp(out)) == -1
+
+
+def test_threshold_policies_match_oracle():
+    from paper_1505_07851_amd import ThresholdPolicy
+    errs = [None, 0.3, 2e-2, 1.2e-3, 1e-3, 4e-3, 2e-4, 1e-6, 0.0]
+    for kind, kw in [("fixed", dict(delta=3e-7)), ("two_delta", dict(delta=1e-6, scale=1e4, switch_at=1e-3)),
+                     ("two_delta", dict(delta=1e-5, scale=1e3, switch_at=5e-3)), ("dynamic", {})]:
+        pol = ThresholdPolicy(kind, **kw)
+        got = [pol(e) for e in errs]
+        assert got == O.threshold_schedule(kind, errs, **kw), kind
+    pol = ThresholdPolicy("two_delta")
+    assert not pol.switched and pol(None) == 1e-2 and pol(1e-3) == 1e-6 and pol.switched and pol(0.5) == 1e-6
+
+
+def test_threshold_policy_bad_arguments(L):
+    from paper_1505_07851_amd import _lib
+    p = _lib.pcm_threshold_policy()
+    assert L.pcm_cg_threshold(None, 1.0) == -1.0
+    L.pcm_default_threshold_policy(ctypes.byref(p), 7)
+    assert L.pcm_cg_threshold(ctypes.byref(p), 1.0) == -1.0
+    L.pcm_default_threshold_policy(ctypes.byref(p), _lib.PCM_THRESH_TWO_DELTA)
+    assert (p.delta, p.scale, p.switch_at, p.switched) == (1e-6, 1e4, 1e-3, 0)
+    p.scale = 0.5
+    assert L.pcm_cg_threshold(ctypes.byref(p), 1.0) == -1.0
+    L.pcm_default_threshold_policy(ctypes.byref(p), _lib.PCM_THRESH_FIXED)
+    p.delta = -1.0
+    assert L.pcm_cg_threshold(ctypes.byref(p), 1.0) == -1.0

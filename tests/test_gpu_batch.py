@@ -41,7 +41,8 @@ def setup():
 
 
 @pytest.mark.parametrize("precond,precision", [("none", "fp64"), ("jacobi", "fp64"), ("rbj", "fp64"),
-                                                ("jacobi", "mixed"), ("rbj", "mixed")])
+                                                ("octree", "fp64"), ("jacobi", "mixed"), ("rbj", "mixed"),
+                                                ("octree", "mixed")])
 def test_batch_equals_single(setup, precond, precision):
     # Unpreconditioned refinement is left out: points near the switching cut have
     # A_kk ~ 1/S_k up to ~1e8, cond(A) ~ 1e10, and restarted FP32 CG does not reduce the

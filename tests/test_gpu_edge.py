@@ -57,3 +57,31 @@ def test_single_atom(torch_cuda):
     g = om.grad_terms(s.P, ref["q"])
     assert np.abs(gn.cpu().numpy() - g["g_nuc"]).max() <= 1e-8 * max(1.0, np.abs(g["g_nuc"]).max())
     assert np.abs(gs.cpu().numpy() - g["g_surf"]).max() <= 1e-8 * max(1.0, np.abs(g["g_surf"]).max())
+
+
+def test_preconditioner_switch_keeps_results(torch_cuda):
+    """The block inverses are cached per (partition kind, size, seed): switching between the
+    randomized and the octree partition on one molecule rebuilds them, and going back gives
+    the first result bit for bit."""
+    from paper_1505_07851_amd import Context, Molecule, octree_partition
+    torch = torch_cuda
+    print("\n[case precond switch frag8]", flush=True)
+    s = I.small_protein(8, 74, seed=21)
+    om = O.mol_from_system(s)
+    ref = O.full_solution(om, s.P)
+    mol = Molecule.from_system(Context(), s)
+    v = torch.tensor(ref["bz"] + ref["c"], dtype=torch.float64, device="cuda")
+    runs = [("rbj", 48, 3), ("octree", 48, 0), ("rbj", 48, 3), ("octree", 200, 0), ("rbj", 48, 9)]
+    out = []
+    for kind, block, seed in runs:
+        q, info = mol.solve(v, precond=kind, block=block, seed=seed, tol=1e-10)
+        assert info["resid"] < 1e-10
+        assert np.abs(q.cpu().numpy() - ref["q"]).max() <= 1e-7 * np.abs(ref["q"]).max()
+        out.append((q.clone(), info["iters"]))
+    assert torch.equal(out[0][0], out[2][0]) and out[0][1] == out[2][1]
+    b = -om.f * (ref["bz"] + ref["c"])
+    for (kind, block, seed), (_, iters) in zip(runs, out):
+        _, it = om.pcg(b, 1e-10, precond=kind, block=block, seed=seed, A=ref["A"])
+        assert abs(iters - it) <= 2, (kind, block, iters, it)
+    perm, off = octree_partition(om.r, 200)
+    assert np.diff(off).max() <= 200

@@ -94,7 +94,7 @@ def test_fock(case, torch_cuda):
     assert np.abs(d - d.T).max() <= 1e-10 * np.abs(Fr).max()
 
 
-@pytest.mark.parametrize("precond", ["none", "jacobi", "rbj"])
+@pytest.mark.parametrize("precond", ["none", "jacobi", "rbj", "octree"])
 def test_solve_fp64(case, torch_cuda, precond):
     mol, om, ref = case["mol"], case["om"], case["ref"]
     v = torch_cuda.tensor(ref["bz"] + ref["c"], dtype=torch_cuda.float64, device="cuda")
@@ -112,7 +112,7 @@ def test_solve_fp64(case, torch_cuda, precond):
     assert abs(info["iters"] - it) <= allow, (info["iters"], it)
 
 
-@pytest.mark.parametrize("precond", ["jacobi", "rbj"])
+@pytest.mark.parametrize("precond", ["jacobi", "rbj", "octree"])
 def test_solve_mixed_refinement(case, torch_cuda, precond):
     mol, ref = case["mol"], case["ref"]
     v = torch_cuda.tensor(ref["bz"] + ref["c"], dtype=torch_cuda.float64, device="cuda")

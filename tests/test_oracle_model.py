@@ -327,3 +327,108 @@ def test_small_protein_gradient(small):
         xm = om.xyz.copy(); xm[I_, d] -= h
         fd = (energy_at(s, pr, om.keep_idx, xyz=xp) - energy_at(s, pr, om.keep_idx, xyz=xm)) / (2 * h)
         assert abs(fd - total[I_, d]) <= max(1e-7, 1e-5 * abs(total[I_, d])), (I_, d, fd, total[I_, d])
+
+
+# ------------------------------------------------------------------ octree partition
+def _morton(ix, iy, iz, levels):
+    """Z-order code of integer cell coordinates, most significant level first."""
+    code = 0
+    for lev in range(levels - 1, -1, -1):
+        code = (code << 3) | ((ix >> lev) & 1) | (((iy >> lev) & 1) << 1) | (((iz >> lev) & 1) << 2)
+    return code
+
+
+def test_octree_cube_corners_octant_order():
+    # octant o holds the corner with x > 0 iff bit 0, y > 0 iff bit 1, z > 0 iff bit 2
+    rng = np.random.default_rng(3)
+    corners = np.array([[sx, sy, sz] for sz in (-1, 1) for sy in (-1, 1) for sx in (-1, 1)], float)
+    order = rng.permutation(8)
+    r = corners[order]
+    perm, off = O.octree_partition(r, 1)
+    assert np.array_equal(off, np.arange(9))
+    octant = (r[perm, 0] > 0) + 2 * (r[perm, 1] > 0) + 4 * (r[perm, 2] > 0)
+    assert np.array_equal(octant, np.arange(8))
+
+
+def test_octree_regular_grid_is_z_order():
+    # a 4x4x4 grid with one point per leaf: depth-first octant order is the Morton order
+    g = np.array([[x, y, z] for x in range(4) for y in range(4) for z in range(4)], float)
+    rng = np.random.default_rng(8)
+    g = g[rng.permutation(len(g))]
+    perm, off = O.octree_partition(g, 1)
+    assert np.array_equal(off, np.arange(65))
+    codes = [_morton(int(x), int(y), int(z), 2) for x, y, z in g]
+    assert np.array_equal(perm, np.argsort(codes, kind="stable"))
+    # leaves of 8: the 2x2x2 blocks of the grid, in Morton order of the block, members ascending
+    perm8, off8 = O.octree_partition(g, 8)
+    assert np.array_equal(off8, 8 * np.arange(9))
+    for b in range(8):
+        idx = perm8[off8[b]:off8[b + 1]]
+        assert np.all(np.diff(idx) > 0)
+        cell = {(int(x) // 2, int(y) // 2, int(z) // 2) for x, y, z in g[idx]}
+        assert len(cell) == 1
+        (cx, cy, cz), = cell
+        assert _morton(cx, cy, cz, 1) == b
+
+
+def test_octree_clusters_and_limits():
+    rng = np.random.default_rng(5)
+    centres = np.array([[-5.0, -5.0, -5.0], [5.0, -5.0, 5.0], [-5.0, 5.0, 5.0], [5.0, 5.0, -5.0]])
+    sizes = [5, 3, 5, 4]
+    r = np.concatenate([c + 0.1 * rng.normal(size=(n, 3)) for c, n in zip(centres, sizes)])
+    sh = rng.permutation(len(r))
+    r = r[sh]
+    label = np.repeat(np.arange(4), sizes)[sh]
+    perm, off = O.octree_partition(r, 5)
+    blocks = [set(label[perm[off[b]:off[b + 1]]].tolist()) for b in range(len(off) - 1)]
+    assert len(blocks) == 4 and all(len(s) == 1 for s in blocks)
+    # octant order of the cluster centres: (-,-,-)=0, (+,+,-)=3, (+,-,+)=5, (-,+,+)=6
+    assert [s.pop() for s in blocks] == [0, 3, 1, 2]
+    # leaf_max >= M: one block of every point, ascending
+    perm, off = O.octree_partition(r, len(r))
+    assert np.array_equal(off, [0, len(r)]) and np.array_equal(perm, np.arange(len(r)))
+    # coincident points cannot be split: runs of leaf_max after the depth limit
+    perm, off = O.octree_partition(np.zeros((7, 3)), 3)
+    assert np.array_equal(off, [0, 3, 6, 7]) and np.array_equal(perm, np.arange(7))
+
+
+def test_octree_leaves_are_disjoint_cells():
+    s = I.small_protein(10, 74, seed=11)
+    om = O.mol_from_system(s)
+    for leaf in (800, 100, 37):
+        perm, off = om.octree_partition(leaf)
+        assert sorted(perm.tolist()) == list(range(om.M))
+        sizes = np.diff(off)
+        assert sizes.min() >= 1 and sizes.max() <= leaf
+        boxes = [(om.r[perm[off[b]:off[b + 1]]].min(0), om.r[perm[off[b]:off[b + 1]]].max(0))
+                 for b in range(len(sizes))]
+        # points of different leaves lie in different octree cells: their bounding boxes
+        # are separated (touching at most) along some axis
+        for a in range(len(boxes)):
+            for b in range(a + 1, len(boxes)):
+                (la, ha), (lb, hb) = boxes[a], boxes[b]
+                assert np.any((ha <= lb) | (hb <= la)), (leaf, a, b)
+
+
+def test_octree_block_jacobi_limits(water, water_oracle):
+    om = water_oracle
+    sol = O.full_solution(om, water.P)
+    b = -om.f * (sol["bz"] + sol["c"])
+    x, it = om.pcg(b, 1e-10, precond="octree", block=32, A=sol["A"])
+    assert np.linalg.norm(sol["A"] @ x - b) < 1e-10
+    _, it_M = om.pcg(b, 1e-10, precond="octree", block=om.M, A=sol["A"])
+    assert it_M == 1                          # one leaf: the exact inverse
+
+
+# ------------------------------------------------------------------ threshold policies
+def test_threshold_policies_follow_sec_4b_i():
+    errs = [None, 0.3, 2e-2, 1.2e-3, 1e-3, 4e-3, 2e-4, 1e-6]
+    assert O.threshold_schedule("fixed", errs, delta=1e-6) == [1e-6] * len(errs)
+    # 2-delta: delta_1 = 1e4 delta_2 until the DIIS error reaches 1e-3, then delta_2 for good
+    two = O.threshold_schedule("two_delta", errs, delta=1e-6, scale=1e4, switch_at=1e-3)
+    assert two == [1e-2, 1e-2, 1e-2, 1e-2, 1e-6, 1e-6, 1e-6, 1e-6]
+    dyn = O.threshold_schedule("dynamic", errs)
+    assert dyn[0] == 1.0                      # first SCF step: delta = 1
+    for e, d in zip(errs[1:], dyn[1:]):
+        # Eq. 21 at the chosen delta predicts an error 1e-3 times the previous DIIS error
+        assert 0.01 * d ** 1.07 == pytest.approx(1e-3 * e, rel=1e-12)
