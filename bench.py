@@ -24,11 +24,18 @@ sparse seeded perturbation dP_t, the threshold tightening as delta_t = 10^(-3 - 
 (the Eq. 21 range), each solve warm-started from the previous q; unpreconditioned and RBJ
 with blocks of 1,024 points, FP64 and mixed (FP32 matvec in FP64 refinement).
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload protein600|conformers64|stress2000]
+Studies (--workload scf_policies, eq21_fit): the synthetic analogues of the solver-policy
+and threshold experiments of Sec. 4b (CG steps per SCF iteration under fixed, 2-delta and
+dynamic thresholds; RBJ against the octree partition over seeds; the power-law fit of the
+energy error against the CG threshold).  They print one JSON line each, with the counts.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+                       [--workload protein600|conformers64|stress2000|scf_policies|eq21_fit]
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import re
@@ -106,10 +113,11 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--block", type=int, default=100)
     ap.add_argument("--workload", default="protein600",
-                    choices=["protein600", "conformers64", "stress2000", "copy"],
+                    choices=["protein600", "conformers64", "stress2000", "scf_policies", "eq21_fit", "copy"],
                     help="copy: a plain device copy of known size, to calibrate rocprofv3 byte counters")
     ap.add_argument("--max-iter-none", type=int, default=300,
                     help="stress2000: matvec budget of each unpreconditioned outer solve")
+    ap.add_argument("--seeds", type=int, default=20, help="scf_policies: RBJ seeds per block size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding of the path is "
@@ -121,6 +129,10 @@ def main():
         return bench_stress(args)
     if args.workload == "copy":
         return bench_copy(args)
+    if args.workload == "scf_policies":
+        return bench_scf_policies(args)
+    if args.workload == "eq21_fit":
+        return bench_eq21_fit(args)
 
     import numpy as np
     import torch
@@ -485,6 +497,163 @@ def bench_conformers(args):
                             "speedup_vs_sequential": round(ms_seq / ms_b64, 3), "err_vs_sequential": errs(r_b64)},
            "batched_mixed": {"ms_per_step": round(ms_bm, 3), "ms_per_conformer": round(ms_bm / n_conf, 3),
                              "speedup_vs_sequential": round(ms_seq / ms_bm, 3), "err_vs_sequential": errs(r_bm)}}
+    print(json.dumps(out))
+
+
+def scf_trajectory(n_steps=16, e_first=1e-1, e_last=1e-6):
+    """Synthetic SCF: DIIS errors falling geometrically from e_first to e_last; the density
+    of step t is P* + (e_t / e_first) D, i.e. its error is proportional to the DIIS error."""
+    return [e_first * (e_last / e_first) ** (t / (n_steps - 1)) for t in range(n_steps)]
+
+
+def bench_scf_policies(args):
+    """Sec. 4b-i/4b-ii solver policies on the 600-atom solute over a 16-step synthetic SCF.
+
+    Step t solves A q = -f (Bz + L P_t) warm-started from the previous step's q, at the
+    threshold the policy gives from the previous step's DIIS error.  Reported per run: CG
+    matrix-vector products per step and in total, wall time of the solves (preconditioner
+    setup included), and the Eq. 13 energy error against a 1e-10 solve at the same density,
+    also as a ratio to 1e-3 times the previous step's DIIS error (the target of Sec. 4b-i)."""
+    import numpy as np
+    import torch
+
+    from paper_1505_07851_amd import Context, Molecule, ThresholdPolicy, octree_partition
+    from synth import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    s = I.protein_single_solve()
+    nbf = s.basis.nbf
+    P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
+    D = I.density_matrix(nbf, int(s.Z.sum()) // 2, s.seeds["pert"]) - s.P
+    D = torch.tensor(D, dtype=torch.float64, device="cuda")
+    ctx = Context(precision="fp64")
+    mol = Molecule.from_system(ctx, s)
+    c0, bz = mol.esp(P)
+    cD = mol.esp(D, want_bz=False)
+    errs = scf_trajectory()
+    vs = [bz + c0 + (e / errs[0]) * cD for e in errs]
+    torch.cuda.synchronize()
+    log(f"[bench] scf_policies: M = {mol.M}, nbf = {nbf}, trajectory ready in {time.time() - t0:.1f}s")
+    E_ref = []
+    for v in vs:
+        _, info = mol.solve(v, precond="rbj", block=100, seed=s.seeds["rbj"], tol=1e-10)
+        E_ref.append(info["energy"])
+
+    def run(policy, precond, block=100, seed=0, max_iter=10000):
+        pol = ThresholdPolicy(policy, delta=1e-6, scale=1e4, switch_at=1e-3)
+        q, iters, dE, deltas, conv = None, [], [], [], 0
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k, v in enumerate(vs):
+            d = pol(errs[k - 1] if k else None)
+            q, info = mol.solve(v, precond=precond, block=block, seed=seed, tol=d, q0=q, max_iter=max_iter,
+                                raise_noconv=False)
+            iters.append(info["iters"])
+            deltas.append(d)
+            conv += info["status"] == 0
+            dE.append(abs(info["energy"] - E_ref[k]))
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) * 1e3
+        # Sec. 4b-i aims the CG error of step t at 1e-3 times the DIIS error of step t-1
+        return {"iters": iters, "total_iters": sum(iters), "wall_ms": round(wall, 1), "converged": conv,
+                "deltas": deltas, "E_err": dE,
+                "E_err_over_target_max": max(dE[k] / (1e-3 * errs[k - 1]) for k in range(1, len(dE))),
+                "E_err_final": dE[-1]}
+
+    runs = {}
+    for policy, precond, block in [("fixed", "none", 0), ("fixed", "jacobi", 0), ("fixed", "rbj", 100),
+                                   ("fixed", "octree", 800), ("two_delta", "jacobi", 0), ("two_delta", "rbj", 100),
+                                   ("dynamic", "jacobi", 0), ("dynamic", "rbj", 100), ("dynamic", "octree", 800)]:
+        key = f"{policy}+{precond}{block if block else ''}"
+        runs[key] = run(policy, precond, max(block, 1), s.seeds["rbj"], 3000 if precond == "none" else 10000)
+        log(f"[bench] {key}: total {runs[key]['total_iters']} matvecs, {runs[key]['wall_ms']:.0f} ms, "
+            f"per step {runs[key]['iters']}")
+    # randomized partition over seeds against the deterministic octree (fixed delta)
+    seeds = {}
+    for block in (100, 800):
+        tot = [run("fixed", "rbj", block, 1000 + j)["total_iters"] for j in range(args.seeds)]
+        seeds[f"rbj{block}"] = {"mean": float(np.mean(tot)), "std": float(np.std(tot)), "min": int(min(tot)),
+                                "max": int(max(tot)), "n_seeds": args.seeds}
+        log(f"[bench] fixed+rbj{block} over {args.seeds} seeds: {seeds[f'rbj{block}']}")
+    r = mol.surface()["r"].cpu().numpy()
+    _, off = octree_partition(r, 800)
+    sizes = np.diff(off)
+    out = {"metric": "CG matrix-vector products over a 16-step synthetic SCF (DIIS error 1e-1 -> 1e-6)",
+           "value": runs["dynamic+rbj100"]["total_iters"], "unit": "matvecs", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": runs["dynamic+rbj100"]["wall_ms"], "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "protein600_631gs_scf16", "atoms": s.n_atoms, "nbf": nbf, "surface_points": mol.M,
+                      "diis_errors": errs, "fixed_delta": 1e-6, "two_delta": {"delta2": 1e-6, "s": 1e4,
+                                                                              "switch_at": 1e-3}},
+           "runs": runs, "rbj_seeds": seeds,
+           "octree800_blocks": {"n": int(sizes.size), "mean": float(sizes.mean()), "min": int(sizes.min()),
+                                "max": int(sizes.max())}}
+    print(json.dumps(out))
+
+
+def bench_eq21_fit(args):
+    """Sec. 4b-i, Eq. 21 re-derived on synthetic solutes: six sizes, each at its generated
+    geometry and with seeded displacements (0.1 A rms), 6-31G-shaped basis.  The first solve
+    (q from zero) at thresholds 10^-9 .. 1 is compared with a 1e-10 solve: the error of the
+    Eq. 13 energy and the largest element of the Fock-matrix error sum_k dq_k L^k.  Both are
+    averaged over the twelve structures and fitted with a power law err = a delta^b."""
+    import numpy as np
+    import torch
+
+    from paper_1505_07851_amd import Context, Molecule
+    from synth import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    deltas = [10.0 ** (-9 + 0.5 * i) for i in range(19)]
+    sizes = (16, 24, 36, 50, 70, 96)
+    ctx = Context(precision="fp64")
+    e_rows, f_rows, meta = [], [], []
+    for n in sizes:
+        base = I.small_protein(n, 110, seed=300 + n, polarized=False)
+        for distorted in (False, True):
+            s = base
+            if distorted:
+                rng = np.random.default_rng(700 + n)
+                shift = rng.normal(scale=0.1 / 0.52917721092 / np.sqrt(3), size=base.xyz.shape)
+                s = dataclasses.replace(base, xyz=base.xyz + shift)
+            mol = Molecule.from_system(ctx, s)
+            P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
+            c, bz = mol.esp(P)
+            v = bz + c
+            q_ref, info = mol.solve(v, precond="jacobi", tol=1e-10)
+            E_ref = info["energy"]
+            er, fr = [], []
+            for d in deltas:
+                q, info = mol.solve(v, precond="jacobi", tol=d)
+                er.append(abs(info["energy"] - E_ref))
+                fr.append(mol.fock(q - q_ref).abs().max().item())
+            e_rows.append(er)
+            f_rows.append(fr)
+            meta.append({"atoms": n, "distorted": distorted, "M": mol.M, "E": E_ref})
+            log(f"[bench] eq21: {n} atoms{' distorted' if distorted else ''}, M = {mol.M}")
+            mol.close()
+    e_mean = np.mean(e_rows, axis=0)
+    f_mean = np.mean(f_rows, axis=0)
+
+    def fit(y):
+        keep = [i for i, v in enumerate(y) if v > 1e-13]
+        b, la = np.polyfit(np.log10(np.array(deltas)[keep]), np.log10(np.array(y)[keep]), 1)
+        return {"a": float(10.0 ** la), "b": float(b), "points": len(keep)}
+
+    bound = [0.01 * d ** 1.07 for d in deltas]
+    out = {"metric": "power-law fit of the energy error against the CG threshold (Eq. 21 re-derived)",
+           "value": fit(e_mean)["b"], "unit": "exponent b", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": None, "higher_is_better": None, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "six_solutes_x2_geometries_631g", "structures": meta, "deltas": deltas,
+                      "precond": "jacobi", "reference_delta": 1e-10},
+           "energy_error": {"mean": e_mean.tolist(), "fit": fit(e_mean),
+                            "below_eq21_all": bool(np.all(np.max(e_rows, axis=0) <= bound))},
+           "fock_error_max": {"mean": f_mean.tolist(), "fit": fit(f_mean)},
+           "eq21": {"a": 0.01, "b": 1.07}}
     print(json.dumps(out))
 
 
