@@ -34,40 +34,150 @@ __global__ void k_rbj_fill(const double *__restrict__ px, const double *__restri
     blk[ioff[b] + e] = v;
 }
 
-// In-place Gauss-Jordan inversion of one SPD block per workgroup (no pivoting needed for SPD);
-// a non-positive pivot flags the block as not positive definite.
-__global__ __launch_bounds__(256) void k_rbj_invert(const int *__restrict__ off, const long long *__restrict__ ioff,
-                                                    double *__restrict__ blk, int *__restrict__ bad) {
-    int b = blockIdx.x;
-    int l = off[b + 1] - off[b];
-    double *A = blk + ioff[b];
-    __shared__ double rowk[1024];
-    __shared__ double colk[1024];
-    __shared__ double piv_s;
-    for (int k = 0; k < l; ++k) {
-        if (threadIdx.x == 0) {
-            piv_s = A[(long long)k * l + k];
-            if (!(piv_s > 0.0)) bad[0] = 1;
+// In-place blocked Gauss-Jordan inversion of every SPD block (no pivoting is needed for SPD
+// matrices).  Panel K of width GJ_PB is eliminated in four launches over all blocks:
+//   diag      A_KK <- P^-1, P = A_KK (scalar Gauss-Jordan in LDS; a non-positive pivot flags
+//             the block as not positive definite)
+//   row       A_Kj <- P^-1 A_Kj                  (j outside K)
+//   trailing  A_ij <- A_ij - A_iK A_Kj           (i, j outside K; A_Kj already updated)
+//   column    A_iK <- -A_iK P^-1                 (i outside K)
+// After the last panel the block holds its inverse.  Each pass over the block is one rank-GJ_PB
+// update, so HBM traffic is l^2 per panel instead of per pivot.
+constexpr int GJ_PB = 64;
+constexpr int GJ_LD = GJ_PB + 1;  // LDS row stride (odd: column walks do not hit one bank)
+
+__device__ inline bool gj_panel(const int *__restrict__ off, const long long *__restrict__ ioff, int b, int p,
+                                double *__restrict__ blk, double *&A, int &l, int &K0, int &kb) {
+    l = off[b + 1] - off[b];
+    K0 = p * GJ_PB;
+    if (K0 >= l) return false;
+    kb = min(GJ_PB, l - K0);
+    A = blk + ioff[b];
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_gj_diag(const int *__restrict__ off, const long long *__restrict__ ioff,
+                                                 double *__restrict__ blk, int p, int *__restrict__ bad) {
+    double *A;
+    int l, K0, kb;
+    if (!gj_panel(off, ioff, blockIdx.x, p, blk, A, l, K0, kb)) return;
+    __shared__ double T[GJ_PB * GJ_LD];
+    __shared__ double rowk[GJ_PB], colk[GJ_PB];
+    for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
+        const int i = e / kb, j = e % kb;
+        T[i * GJ_LD + j] = A[(long long)(K0 + i) * l + K0 + j];
+    }
+    __syncthreads();
+    for (int k = 0; k < kb; ++k) {
+        const double piv = T[k * GJ_LD + k];
+        if (!(piv > 0.0)) {  // uniform: every lane read the same pivot
+            if (threadIdx.x == 0) bad[0] = 1;
+            return;
+        }
+        const double ip = 1.0 / piv;
+        if (threadIdx.x < kb) {
+            rowk[threadIdx.x] = T[k * GJ_LD + threadIdx.x] * ip;
+            colk[threadIdx.x] = T[threadIdx.x * GJ_LD + k];
         }
         __syncthreads();
-        double piv = piv_s;
-        if (!(piv > 0.0)) return;
-        double ip = 1.0 / piv;
-        for (int j = threadIdx.x; j < l; j += blockDim.x) {
-            rowk[j] = A[(long long)k * l + j] * ip;
-            colk[j] = A[(long long)j * l + k];
+        for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
+            const int i = e / kb, j = e % kb;
+            double v;
+            if (i == k)
+                v = j == k ? ip : rowk[j];
+            else
+                v = j == k ? -colk[i] * ip : T[i * GJ_LD + j] - colk[i] * rowk[j];
+            T[i * GJ_LD + j] = v;
         }
         __syncthreads();
-        // update every element outside row k (rows walked uniformly, columns across lanes)
-        for (int i = 0; i < l; ++i) {
-            if (i == k) continue;
-            const double ci = colk[i];
-            double *Ai = A + (long long)i * l;
-            for (int j = threadIdx.x; j < l; j += blockDim.x) Ai[j] = (j == k) ? -ci * ip : Ai[j] - ci * rowk[j];
+    }
+    for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
+        const int i = e / kb, j = e % kb;
+        A[(long long)(K0 + i) * l + K0 + j] = T[i * GJ_LD + j];
+    }
+}
+
+// row (side = 0): A_Kj <- P^-1 A_Kj for the 64-column tile blockIdx.y of block blockIdx.x;
+// column (side = 1): A_iK <- -A_iK P^-1 for the 64-row tile blockIdx.y
+__global__ __launch_bounds__(256) void k_gj_side(const int *__restrict__ off, const long long *__restrict__ ioff,
+                                                 double *__restrict__ blk, int p, int side) {
+    double *A;
+    int l, K0, kb;
+    if (!gj_panel(off, ioff, blockIdx.x, p, blk, A, l, K0, kb)) return;
+    const int t0 = blockIdx.y * GJ_PB;
+    if (t0 >= l || (int)blockIdx.y == p) return;
+    const int tn = min(GJ_PB, l - t0);
+    __shared__ double Pi[GJ_PB * GJ_LD];
+    __shared__ double X[GJ_PB * GJ_LD];
+    for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
+        const int i = e / kb, j = e % kb;
+        Pi[i * GJ_LD + j] = A[(long long)(K0 + i) * l + K0 + j];
+    }
+    // X holds the tile with the panel index first: X[m][t] = A[K0+m][t0+t] (row) or A[t0+t][K0+m]
+    for (int e = threadIdx.x; e < kb * tn; e += blockDim.x) {
+        if (side == 0) {
+            const int m = e / tn, t = e % tn;
+            X[m * GJ_LD + t] = A[(long long)(K0 + m) * l + t0 + t];
+        } else {
+            const int t = e / kb, m = e % kb;
+            X[m * GJ_LD + t] = A[(long long)(t0 + t) * l + K0 + m];
         }
-        __syncthreads();
-        for (int j = threadIdx.x; j < l; j += blockDim.x) A[(long long)k * l + j] = (j == k) ? ip : rowk[j];
-        __syncthreads();
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kb * tn; e += blockDim.x) {
+        if (side == 0) {
+            const int r = e / tn, t = e % tn;  // out[r][t] = sum_m Pi[r][m] X[m][t]
+            double acc = 0.0;
+            for (int m = 0; m < kb; ++m) acc = fma(Pi[r * GJ_LD + m], X[m * GJ_LD + t], acc);
+            A[(long long)(K0 + r) * l + t0 + t] = acc;
+        } else {
+            const int t = e / kb, c = e % kb;  // out[t][c] = -sum_m X[m][t] Pi[m][c]
+            double acc = 0.0;
+            for (int m = 0; m < kb; ++m) acc = fma(X[m * GJ_LD + t], Pi[m * GJ_LD + c], acc);
+            A[(long long)(t0 + t) * l + K0 + c] = -acc;
+        }
+    }
+}
+
+// trailing update of the 64x64 tile (ti, tj) = (blockIdx.y / nt, blockIdx.y % nt) of block
+// blockIdx.x; each lane owns a 4x4 sub-tile (rows 4 (lane / 16) .., columns lane % 16 + 16 c)
+__global__ __launch_bounds__(256) void k_gj_trail(const int *__restrict__ off, const long long *__restrict__ ioff,
+                                                  double *__restrict__ blk, int p, int nt) {
+    double *A;
+    int l, K0, kb;
+    if (!gj_panel(off, ioff, blockIdx.x, p, blk, A, l, K0, kb)) return;
+    const int ti = blockIdx.y / nt, tj = blockIdx.y % nt;
+    const int i0 = ti * GJ_PB, j0 = tj * GJ_PB;
+    if (i0 >= l || j0 >= l || ti == p || tj == p) return;
+    const int in = min(GJ_PB, l - i0), jn = min(GJ_PB, l - j0);
+    __shared__ double C[GJ_PB * GJ_LD];  // C[m][i] = A[i0+i][K0+m]
+    __shared__ double R[GJ_PB * GJ_LD];  // R[m][j] = A[K0+m][j0+j]
+    for (int e = threadIdx.x; e < in * kb; e += blockDim.x) {
+        const int i = e / kb, m = e % kb;
+        C[m * GJ_LD + i] = A[(long long)(i0 + i) * l + K0 + m];
+    }
+    for (int e = threadIdx.x; e < kb * jn; e += blockDim.x) {
+        const int m = e / jn, j = e % jn;
+        R[m * GJ_LD + j] = A[(long long)(K0 + m) * l + j0 + j];
+    }
+    __syncthreads();
+    const int r0 = 4 * (threadIdx.x / 16), c0 = threadIdx.x % 16;
+    double acc[4][4] = {};
+    for (int m = 0; m < kb; ++m) {
+        double a[4], bb[4];
+        for (int u = 0; u < 4; ++u) a[u] = C[m * GJ_LD + r0 + u];
+        for (int v = 0; v < 4; ++v) bb[v] = R[m * GJ_LD + c0 + 16 * v];
+        for (int u = 0; u < 4; ++u)
+            for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], bb[v], acc[u][v]);
+    }
+    for (int u = 0; u < 4; ++u) {
+        const int i = r0 + u;
+        if (i >= in) continue;
+        double *Ai = A + (long long)(i0 + i) * l + j0;
+        for (int v = 0; v < 4; ++v) {
+            const int j = c0 + 16 * v;
+            if (j < jn) Ai[j] -= acc[u][v];
+        }
     }
 }
 
@@ -180,8 +290,19 @@ void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int kind, int l, unsigned long long s
     HIP_OK(hipMemsetAsync(ctx->iscal.p, 0, sizeof(int), ctx->stream));
     {
         ProfScope psi(ctx, "rbj_invert", (double)ioff[nb]);
-        k_rbj_invert<<<nb, 256, 0, ctx->stream>>>(mol->rbj_off.p, mol->rbj_ioff.p, mol->rbj_inv.p, ctx->iscal.p);
-        HIP_LAUNCH_OK();
+        const int nt = div_up(lmax, GJ_PB);
+        for (int p = 0; p < nt; ++p) {
+            k_gj_diag<<<nb, 256, 0, ctx->stream>>>(mol->rbj_off.p, mol->rbj_ioff.p, mol->rbj_inv.p, p, ctx->iscal.p);
+            HIP_LAUNCH_OK();
+            if (nt == 1) continue;  // a single panel: the block is inverted
+            k_gj_side<<<dim3(nb, nt), 256, 0, ctx->stream>>>(mol->rbj_off.p, mol->rbj_ioff.p, mol->rbj_inv.p, p, 0);
+            HIP_LAUNCH_OK();
+            k_gj_trail<<<dim3(nb, nt * nt), 256, 0, ctx->stream>>>(mol->rbj_off.p, mol->rbj_ioff.p,
+                                                                    mol->rbj_inv.p, p, nt);
+            HIP_LAUNCH_OK();
+            k_gj_side<<<dim3(nb, nt), 256, 0, ctx->stream>>>(mol->rbj_off.p, mol->rbj_ioff.p, mol->rbj_inv.p, p, 1);
+            HIP_LAUNCH_OK();
+        }
     }
     int bad = 0;
     HIP_OK(hipMemcpyAsync(&bad, ctx->iscal.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
