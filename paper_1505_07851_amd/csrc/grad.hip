@@ -180,6 +180,105 @@ __global__ void k_grad_contract(long long n, int nch, const double *__restrict__
     for (int d = 0; d < 6; ++d) gpair[(size_t)q * 6 + d] = g[d];
 }
 
+// The same per-pair (ga, gb) for classes with many Cartesian products (L >= 3): one wave per
+// primitive pair.  V' and the three Hermite tables go to LDS, lane mu * ncart(LB) + nu takes
+// one product of components, and the six sums over products are taken in that lane order,
+// which is the loop order of k_grad_contract.
+constexpr int GCW_WAVES = 4;
+template <int LA, int LB>
+__global__ __launch_bounds__(64 * GCW_WAVES) void k_grad_contract_w(
+    long long n, int nch, const double *__restrict__ vin, const int *__restrict__ ent_sp,
+    const int *__restrict__ ent_ij, const int *__restrict__ spa, const int *__restrict__ spb,
+    const int *__restrict__ snp, const int *__restrict__ soff, const int *__restrict__ satom,
+    const int *__restrict__ bfo, const int *__restrict__ cnoff, const double *__restrict__ pexp,
+    const double *__restrict__ cn, const double *__restrict__ xyz, const double *__restrict__ P, int nbf,
+    double *__restrict__ gpair) {
+    constexpr int L = LA + LB, NT = ntuv(L + 1), IM = LA + 1, JM = LB + 1, TS = IM + JM + 1;
+    constexpr int ES = herm1d_size<IM, JM>(), NA = ncart(LA), NB = ncart(LB);
+    static_assert(NA * NB <= 64, "one lane per product of Cartesian components");
+    __shared__ double sV[GCW_WAVES][NT];
+    __shared__ double sE[GCW_WAVES][3][ES];
+    __shared__ double sG[GCW_WAVES][6][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const long long q = (long long)blockIdx.x * GCW_WAVES + w;
+    const bool valid = q < n;
+    int a = 0, b = 0, i = 0, j = 0;
+    double ea = 0.0, eb = 0.0;
+    if (valid) {
+        const int sp = ent_sp[q], ij = ent_ij[q];
+        a = spa[sp];
+        b = spb[sp];
+        i = ij >> 3;
+        j = ij & 7;
+        ea = pexp[soff[a] + i];
+        eb = pexp[soff[b] + j];
+        if (lane < NT) {
+            double acc = 0.0;
+            for (int c = 0; c < nch; ++c) acc += vin[((size_t)c * NT + lane) * n + q];
+            sV[w][lane] = acc;
+        }
+        if (lane < 3) {
+            const double p = ea + eb;
+            const double Ad = xyz[3 * satom[a] + lane], Bd = xyz[3 * satom[b] + lane];
+            const double Pd = (ea * Ad + eb * Bd) / p;
+            herm1d_build_lds<IM, JM>(sE[w][lane], Pd - Ad, Pd - Bd, 0.5 / p);
+        }
+    }
+    __syncthreads();
+    double g[6] = {0, 0, 0, 0, 0, 0};
+    if (valid && lane < NA * NB) {
+        const int mu = lane / NB, nu = lane - mu * NB;
+        int a3[3], b3[3];
+        cart_comp(LA, mu, a3[0], a3[1], a3[2]);
+        cart_comp(LB, nu, b3[0], b3[1], b3[2]);
+        const double w2 = (a == b) ? -1.0 : -2.0;
+        const double cf = w2 * P[(long long)(bfo[a] + mu) * nbf + bfo[b] + nu] * cn[cnoff[a] + mu * snp[a] + i] *
+                          cn[cnoff[b] + nu * snp[b] + j];
+        const double *ex = sE[w][0], *ey = sE[w][1], *ez = sE[w][2];
+        const double *V = sV[w];
+        auto hv = [&](int ax, int ay, int az, int bx, int by, int bz) -> double {
+            double s = 0.0;
+            for (int t = 0; t <= ax + bx; ++t)
+                for (int u = 0; u <= ay + by; ++u) {
+                    const double etu = ex[(ax * (JM + 1) + bx) * TS + t] * ey[(ay * (JM + 1) + by) * TS + u];
+                    for (int v = 0; v <= az + bz; ++v)
+                        s += etu * ez[(az * (JM + 1) + bz) * TS + v] * V[tuv_idx(t, u, v)];
+                }
+            return s;
+        };
+        if (cf != 0.0) {
+            for (int d = 0; d < 3; ++d) {
+                int ap[3] = {a3[0], a3[1], a3[2]};
+                ap[d] += 1;
+                double va = 2.0 * ea * hv(ap[0], ap[1], ap[2], b3[0], b3[1], b3[2]);
+                if (a3[d] > 0) {
+                    int am[3] = {a3[0], a3[1], a3[2]};
+                    am[d] -= 1;
+                    va -= a3[d] * hv(am[0], am[1], am[2], b3[0], b3[1], b3[2]);
+                }
+                int bp[3] = {b3[0], b3[1], b3[2]};
+                bp[d] += 1;
+                double vb = 2.0 * eb * hv(a3[0], a3[1], a3[2], bp[0], bp[1], bp[2]);
+                if (b3[d] > 0) {
+                    int bm[3] = {b3[0], b3[1], b3[2]};
+                    bm[d] -= 1;
+                    vb -= b3[d] * hv(a3[0], a3[1], a3[2], bm[0], bm[1], bm[2]);
+                }
+                g[d] = cf * va;
+                g[3 + d] = cf * vb;
+            }
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) sG[w][d][lane] = g[d];
+    __syncthreads();
+    if (valid && lane < 6) {
+        double acc = 0.0;
+        for (int l = 0; l < NA * NB; ++l) acc += sG[w][lane][l];
+        gpair[(size_t)q * 6 + lane] = acc;
+    }
+}
+
 // per candidate shell pair: sum of its primitive pairs' (ga, gb) in list order
 __global__ void k_grad_sp(long long sp0, long long nsp, long long cls_off, const int *__restrict__ spo,
                           const double *__restrict__ gpair, double *__restrict__ gsp) {
@@ -467,15 +566,22 @@ static void grad_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, const doubl
                                                              mol->cnoff.p, mol->pexp.p, mol->cn.p, mol->xyz.p,     \
                                                              P, mol->nbf, mol->gpair.p);                               \
         break;
+#define GCW_CASE(CI, LA_, LB_)                                                                                     \
+    case CI:                                                                                                       \
+        k_grad_contract_w<LA_, LB_><<<div_up(n, GCW_WAVES), 64 * GCW_WAVES, 0, ctx->stream>>>(                      \
+            n, nch, mol->vbuf.p, es, ei, mol->spa.p, mol->spb.p, mol->snp.p, mol->soff.p, mol->satom.p, mol->bfo.p, \
+            mol->cnoff.p, mol->pexp.p, mol->cn.p, mol->xyz.p, P, mol->nbf, mol->gpair.p);                           \
+        break;
         switch (cl) {
             GC_CASE(0, 0, 0)
             GC_CASE(1, 0, 1)
             GC_CASE(2, 0, 2)
             GC_CASE(3, 1, 1)
-            GC_CASE(4, 1, 2)
-            GC_CASE(5, 2, 2)
+            GCW_CASE(4, 1, 2)
+            GCW_CASE(5, 2, 2)
         }
 #undef GC_CASE
+#undef GCW_CASE
         HIP_LAUNCH_OK();
         k_grad_sp<<<div_up(ncs, 128), 128, 0, ctx->stream>>>(sp0, ncs, pl.cls_off[cl], pl.spo.p, mol->gpair.p,
                                                              mol->gsp.p);

@@ -251,6 +251,59 @@ __global__ void k_fock_contract(long long n, int nch, const double *__restrict__
     }
 }
 
+// The same for classes with many Cartesian products (L >= 3): one wave per primitive pair,
+// V and the Hermite tables in LDS, lane mu * ncart(LB) + nu writes one product.
+constexpr int FCW_WAVES = 4;
+template <int LA, int LB>
+__global__ __launch_bounds__(64 * FCW_WAVES) void k_fock_contract_w(
+    long long n, int nch, const double *__restrict__ vin, const int *__restrict__ ent_sp,
+    const int *__restrict__ ent_ij, const int *__restrict__ spa, const int *__restrict__ spb,
+    const int *__restrict__ snp, const int *__restrict__ soff, const int *__restrict__ satom,
+    const int *__restrict__ cnoff, const double *__restrict__ pexp, const double *__restrict__ cn,
+    const double *__restrict__ xyz, double *__restrict__ fprim) {
+    constexpr int L = LA + LB, NT = ntuv(L), TS = LA + LB + 1, ES = herm1d_size<LA, LB>();
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = NA * NB;
+    static_assert(NC <= 64, "one lane per product of Cartesian components");
+    __shared__ double sV[FCW_WAVES][NT];
+    __shared__ double sE[FCW_WAVES][3][ES];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const long long q = (long long)blockIdx.x * FCW_WAVES + w;
+    const bool valid = q < n;
+    int a = 0, b = 0, i = 0, j = 0;
+    if (valid) {
+        const int sp = ent_sp[q], ij = ent_ij[q];
+        a = spa[sp];
+        b = spb[sp];
+        i = ij >> 3;
+        j = ij & 7;
+        if (lane < NT) {
+            double acc = 0.0;
+            for (int c = 0; c < nch; ++c) acc += vin[((size_t)c * NT + lane) * n + q];
+            sV[w][lane] = acc;
+        }
+        if (lane < 3) {
+            const double ea = pexp[soff[a] + i], eb = pexp[soff[b] + j], p = ea + eb;
+            const double Ad = xyz[3 * satom[a] + lane], Bd = xyz[3 * satom[b] + lane];
+            const double Pd = (ea * Ad + eb * Bd) / p;
+            herm1d_build_lds<LA, LB>(sE[w][lane], Pd - Ad, Pd - Bd, 0.5 / p);
+        }
+    }
+    __syncthreads();
+    if (!valid || lane >= NC) return;
+    const int mu = lane / NB, nu = lane - mu * NB;
+    int ax, ay, az, bx, by, bz;
+    cart_comp(LA, mu, ax, ay, az);
+    cart_comp(LB, nu, bx, by, bz);
+    const double *ex = sE[w][0], *ey = sE[w][1], *ez = sE[w][2];
+    double s = 0.0;
+    for (int t = 0; t <= ax + bx; ++t)
+        for (int u = 0; u <= ay + by; ++u) {
+            const double etu = ex[(ax * (LB + 1) + bx) * TS + t] * ey[(ay * (LB + 1) + by) * TS + u];
+            for (int v = 0; v <= az + bz; ++v) s += etu * ez[(az * (LB + 1) + bz) * TS + v] * sV[w][tuv_idx(t, u, v)];
+        }
+    fprim[(size_t)q * NC + lane] = -cn[cnoff[a] + mu * snp[a] + i] * cn[cnoff[b] + nu * snp[b] + j] * s;
+}
+
 // per candidate shell pair: sum its primitive pairs in list order and add the block to F
 template <int LA, int LB>
 __global__ void k_fock_scatter(long long sp0, long long nsp, long long cls_off, const int *__restrict__ spo,
@@ -634,15 +687,25 @@ static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const s
         k_fock_scatter<LA_, LB_><<<gs, 128, 0, ctx->stream>>>(sp0, nsp, pl.cls_off[cl], pl.spo.p, mol->spa.p,       \
                                                               mol->spb.p, mol->bfo.p, mol->fprim.p, mol->nbf, F[i]); \
         break;
+#define FCW_CASE(CI, LA_, LB_)                                                                                      \
+    case CI:                                                                                                        \
+        k_fock_contract_w<LA_, LB_><<<div_up(np, FCW_WAVES), 64 * FCW_WAVES, 0, ctx->stream>>>(                      \
+            np, nch, mol->vbuf.p, es, ei, mol->spa.p, mol->spb.p, mol->snp.p, mol->soff.p, mol->satom.p, mol->cnoff.p, \
+            mol->pexp.p, mol->cn.p, mol->xyz.p, mol->fprim.p);                                                       \
+        HIP_LAUNCH_OK();                                                                                            \
+        k_fock_scatter<LA_, LB_><<<gs, 128, 0, ctx->stream>>>(sp0, nsp, pl.cls_off[cl], pl.spo.p, mol->spa.p,       \
+                                                              mol->spb.p, mol->bfo.p, mol->fprim.p, mol->nbf, F[i]); \
+        break;
             switch (cl) {
                 FC_CASE(0, 0, 0)
                 FC_CASE(1, 0, 1)
                 FC_CASE(2, 0, 2)
                 FC_CASE(3, 1, 1)
-                FC_CASE(4, 1, 2)
-                FC_CASE(5, 2, 2)
+                FCW_CASE(4, 1, 2)
+                FCW_CASE(5, 2, 2)
             }
 #undef FC_CASE
+#undef FCW_CASE
             HIP_LAUNCH_OK();
         }
     }

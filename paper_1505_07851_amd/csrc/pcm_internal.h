@@ -179,6 +179,23 @@ template <int L> __host__ __device__ constexpr int pair_batch() { return L == 0 
 constexpr int REC_PAD = 4;  // pair record lists are padded to a multiple of this with zero records
 constexpr int PT_BATCH = 4; // points per batch in the pair-per-lane kernels
 
+// DPP moves within a row of 16 lanes (VALU only, no LDS round trip)
+constexpr int DPP_ROW_ROR8 = 0x128;     // lane i <- lane (i + 8) mod 16: partner differs in bit 3
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;  // lane i <- lane 7 - i within 8: partner differs in bit 2
+constexpr int DPP_QUAD_XOR2 = 0x4E;     // quad_perm [2, 3, 0, 1]
+constexpr int DPP_QUAD_XOR1 = 0xB1;     // quad_perm [1, 0, 3, 2]
+
+// Every lane of every row and bank is written and every source lane exists for these
+// patterns, so no "old" operand is needed.
+template <int CTRL> __device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 // Read-only view through the constant address space: wave-uniform loads from it become
 // scalar loads.  Only for data that no thread of the running kernel writes.  (The host pass
 // of the compiler only type-checks these declarations.)
@@ -233,6 +250,33 @@ struct Herm1D {
         }
     }
 };
+
+// The same coefficients built in LDS by one lane (runtime indices), for kernels that give a
+// whole wave to one primitive pair: e[(i * (JM + 1) + j) * (IM + JM + 1) + t].
+template <int IM, int JM> constexpr int herm1d_size() { return (IM + 1) * (JM + 1) * (IM + JM + 1); }
+template <int IM, int JM>
+__device__ void herm1d_build_lds(double *e, double PA, double PB, double inv2p) {
+    constexpr int TS = IM + JM + 1;
+    auto E = [&](int i, int j, int t) -> double & { return e[(i * (JM + 1) + j) * TS + t]; };
+    for (int x = 0; x < herm1d_size<IM, JM>(); ++x) e[x] = 0.0;
+    E(0, 0, 0) = 1.0;
+    for (int i = 0; i <= IM; ++i) {
+        if (i > 0)
+            for (int t = 0; t <= i; ++t) {
+                double v = PA * E(i - 1, 0, t);
+                if (t > 0) v += inv2p * E(i - 1, 0, t - 1);
+                if (t + 1 <= i - 1) v += (t + 1) * E(i - 1, 0, t + 1);
+                E(i, 0, t) = v;
+            }
+        for (int j = 1; j <= JM; ++j)
+            for (int t = 0; t <= i + j; ++t) {
+                double v = PB * E(i, j - 1, t);
+                if (t > 0) v += inv2p * E(i, j - 1, t - 1);
+                if (t + 1 <= i + j - 1) v += (t + 1) * E(i, j - 1, t + 1);
+                E(i, j, t) = v;
+            }
+    }
+}
 
 // ----------------------------------------------------------------------------------------
 // host-side handles

@@ -128,23 +128,6 @@ __device__ __forceinline__ double blk_sum_parts(const double *__restrict__ part,
     return blk_sum(acc, s);
 }
 
-// DPP moves within a row of 16 lanes (VALU only, no LDS round trip)
-constexpr int DPP_ROW_ROR8 = 0x128;     // lane i <- lane (i + 8) mod 16: partner differs in bit 3
-constexpr int DPP_ROW_HALF_MIRROR = 0x141;  // lane i <- lane 7 - i within 8: partner differs in bit 2
-constexpr int DPP_QUAD_XOR2 = 0x4E;     // quad_perm [2, 3, 0, 1]
-constexpr int DPP_QUAD_XOR1 = 0xB1;     // quad_perm [1, 0, 3, 2]
-
-// Every lane of every row and bank is written and every source lane exists for these
-// patterns, so no "old" operand is needed.
-template <int CTRL> __device__ __forceinline__ float dpp(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL> __device__ __forceinline__ double dpp(double v) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
 // Column sums of an 8-column batch over each row of 16 lanes: a reduce-scatter butterfly
 // (partners differ in lane bit 3, then 2, then 1) halves the values held per lane at each
 // step, then lanes 2c and 2c+1 of the row exchange and both hold the row's sum of column c.
