@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--max-iter-none", type=int, default=300,
                     help="stress2000: matvec budget of each unpreconditioned outer solve")
     ap.add_argument("--seeds", type=int, default=20, help="scf_policies: RBJ seeds per block size")
+    ap.add_argument("--scf-system", default="protein600", choices=["protein600", "protein2000"],
+                    help="scf_policies: the 600-atom solute (M ~ 30k) or the 2,000-atom one (M ~ 150k)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding of the path is "
@@ -507,7 +509,9 @@ def scf_trajectory(n_steps=16, e_first=1e-1, e_last=1e-6):
 
 
 def bench_scf_policies(args):
-    """Sec. 4b-i/4b-ii solver policies on the 600-atom solute over a 16-step synthetic SCF.
+    """Sec. 4b-i/4b-ii solver policies over a 16-step synthetic SCF on the 600-atom solute
+    (default) or the 2,000-atom one (--scf-system protein2000; no unpreconditioned run there,
+    Jacobi capped at 2,000 products per solve, RBJ blocks of 100 and 1,024).
 
     Step t solves A q = -f (Bz + L P_t) warm-started from the previous step's q, at the
     threshold the policy gives from the previous step's DIIS error.  Reported per run: CG
@@ -523,10 +527,12 @@ def bench_scf_policies(args):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     t0 = time.time()
-    s = I.protein_single_solve()
+    big = args.scf_system == "protein2000"
+    s = I.linear_solve_stress() if big else I.protein_single_solve()
     nbf = s.basis.nbf
     P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
-    D = I.density_matrix(nbf, int(s.Z.sum()) // 2, s.seeds["pert"]) - s.P
+    n_occ = min(int(s.Z.sum()) // 2, nbf)
+    D = (I.density_matrix_blocked if big else I.density_matrix)(nbf, n_occ, s.seeds["pert"]) - s.P
     D = torch.tensor(D, dtype=torch.float64, device="cuda")
     ctx = Context(precision="fp64")
     mol = Molecule.from_system(ctx, s)
@@ -537,9 +543,11 @@ def bench_scf_policies(args):
     torch.cuda.synchronize()
     log(f"[bench] scf_policies: M = {mol.M}, nbf = {nbf}, trajectory ready in {time.time() - t0:.1f}s")
     E_ref = []
+    ref_block, ref_tol = (1024, 1e-9) if big else (100, 1e-10)
     for v in vs:
-        _, info = mol.solve(v, precond="rbj", block=100, seed=s.seeds["rbj"], tol=1e-10)
+        _, info = mol.solve(v, precond="rbj", block=ref_block, seed=s.seeds["rbj"], tol=ref_tol)
         E_ref.append(info["energy"])
+    log(f"[bench] reference energies at {ref_tol:g} done in {time.time() - t0:.1f}s")
 
     def run(policy, precond, block=100, seed=0, max_iter=10000):
         pol = ThresholdPolicy(policy, delta=1e-6, scale=1e4, switch_at=1e-3)
@@ -563,16 +571,25 @@ def bench_scf_policies(args):
                 "E_err_final": dE[-1]}
 
     runs = {}
-    for policy, precond, block in [("fixed", "none", 0), ("fixed", "jacobi", 0), ("fixed", "rbj", 100),
-                                   ("fixed", "octree", 800), ("two_delta", "jacobi", 0), ("two_delta", "rbj", 100),
-                                   ("dynamic", "jacobi", 0), ("dynamic", "rbj", 100), ("dynamic", "octree", 800)]:
+    if big:
+        plan = [("fixed", "jacobi", 0), ("fixed", "rbj", 100), ("fixed", "rbj", 1024), ("fixed", "octree", 800),
+                ("two_delta", "rbj", 100), ("dynamic", "jacobi", 0), ("dynamic", "rbj", 100), ("dynamic", "rbj", 1024),
+                ("dynamic", "octree", 800)]
+        seed_blocks = (100, 1024)
+    else:
+        plan = [("fixed", "none", 0), ("fixed", "jacobi", 0), ("fixed", "rbj", 100), ("fixed", "octree", 800),
+                ("two_delta", "jacobi", 0), ("two_delta", "rbj", 100), ("dynamic", "jacobi", 0), ("dynamic", "rbj", 100),
+                ("dynamic", "octree", 800)]
+        seed_blocks = (100, 800)
+    for policy, precond, block in plan:
         key = f"{policy}+{precond}{block if block else ''}"
-        runs[key] = run(policy, precond, max(block, 1), s.seeds["rbj"], 3000 if precond == "none" else 10000)
+        cap = 3000 if precond == "none" else (2000 if big and precond == "jacobi" else 10000)
+        runs[key] = run(policy, precond, max(block, 1), s.seeds["rbj"], cap)
         log(f"[bench] {key}: total {runs[key]['total_iters']} matvecs, {runs[key]['wall_ms']:.0f} ms, "
             f"per step {runs[key]['iters']}")
     # randomized partition over seeds against the deterministic octree (fixed delta)
     seeds = {}
-    for block in (100, 800):
+    for block in seed_blocks:
         tot = [run("fixed", "rbj", block, 1000 + j)["total_iters"] for j in range(args.seeds)]
         seeds[f"rbj{block}"] = {"mean": float(np.mean(tot)), "std": float(np.std(tot)), "min": int(min(tot)),
                                 "max": int(max(tot)), "n_seeds": args.seeds}
@@ -584,9 +601,9 @@ def bench_scf_policies(args):
            "value": runs["dynamic+rbj100"]["total_iters"], "unit": "matvecs", "n_gpus": 1, "steps": 1, "warmup": 0,
            "ms_per_step": runs["dynamic+rbj100"]["wall_ms"], "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "protein600_631gs_scf16", "atoms": s.n_atoms, "nbf": nbf, "surface_points": mol.M,
-                      "diis_errors": errs, "fixed_delta": 1e-6, "two_delta": {"delta2": 1e-6, "s": 1e4,
-                                                                              "switch_at": 1e-3}},
+           "config": {"workload": f"{s.name}_scf16", "atoms": s.n_atoms, "nbf": nbf, "surface_points": mol.M,
+                      "diis_errors": errs, "reference_tol": ref_tol, "fixed_delta": 1e-6,
+                      "two_delta": {"delta2": 1e-6, "s": 1e4, "switch_at": 1e-3}},
            "runs": runs, "rbj_seeds": seeds,
            "octree800_blocks": {"n": int(sizes.size), "mean": float(sizes.mean()), "min": int(sizes.min()),
                                 "max": int(sizes.max())}}
