@@ -2,7 +2,8 @@
 
 * 600-atom protein (M ~ 30k, nbf 5100): surface keep list and both screening lists bit-exact;
   c on sampled points, the Fock correction on sampled shell pairs, and the solve through
-  oracle rows of A q - b (the oracle computes these one by one).
+  oracle rows of A q - b (the oracle computes these one by one), with RBJ-100, RBJ-1024 (several
+  panels of the blocked block inversion) and the octree of at most 800 points per leaf.
 * 300-atom peptide (M ~ 15k): the energy through PCMEnergy; dE/dP equals pcm_fock bitwise;
   the gradient obeys translation invariance, matches central finite differences (h = 1e-4
   bohr) on 20 seeded coordinates and the oracle on sampled surface points; the mixed form's
@@ -86,12 +87,13 @@ def test_big_fock_sampled(big, torch_cuda):
         assert np.array_equal(F[rb, ra], F[ra, rb].T) or a == b
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_big_solve_residual_rows(big, torch_cuda, precision):
+@pytest.mark.parametrize("precision,precond,block", [("fp64", "rbj", 100), ("mixed", "rbj", 100),
+                                                     ("fp64", "octree", 800), ("mixed", "rbj", 1024)])
+def test_big_solve_residual_rows(big, torch_cuda, precision, precond, block):
     s, ctx, mol, om, P = big
     c, bz = mol.esp(P)
     v = bz + c
-    q, info = mol.solve(v, precond="rbj", block=100, seed=s.seeds["rbj"], tol=1e-8, precision=precision)
+    q, info = mol.solve(v, precond=precond, block=block, seed=s.seeds["rbj"], tol=1e-8, precision=precision)
     assert info["resid"] < 1e-8
     qh, vh = q.cpu().numpy(), v.cpu().numpy()
     rng = np.random.default_rng(11)
