@@ -24,7 +24,6 @@
 #include <map>
 
 constexpr int TILE = 256;  // points per tile (rows per workgroup)
-constexpr int MV_B = 8;    // columns per batch of wave-uniform loads
 constexpr int GROUP_K = 8; // PCG iterations per launch group (even: scalar slots alternate)
 // Bound on each inner FP32 solve of the refinement: FP32 rounding can stall the inner
 // residual above its target on ill-conditioned systems; the outer FP64 residual then restarts.
@@ -128,96 +127,87 @@ __device__ __forceinline__ double blk_sum_parts(const double *__restrict__ part,
     return blk_sum(acc, s);
 }
 
-// Column sums of an 8-column batch over each row of 16 lanes: a reduce-scatter butterfly
-// (partners differ in lane bit 3, then 2, then 1) halves the values held per lane at each
-// step, then lanes 2c and 2c+1 of the row exchange and both hold the row's sum of column c.
-// Every sum is formed once, in a fixed order, so the result is deterministic.
-template <typename T> __device__ __forceinline__ T row_colsum8(const T (&v)[MV_B], int lane) {
-    const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
-    T w4[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        T send = b3 ? v[j] : v[4 + j];
-        T keep = b3 ? v[4 + j] : v[j];
-        w4[j] = keep + dpp<DPP_ROW_ROR8>(send);
-    }
-    T w2[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        T send = b2 ? w4[j] : w4[2 + j];
-        T keep = b2 ? w4[2 + j] : w4[j];
-        w2[j] = keep + dpp<DPP_ROW_HALF_MIRROR>(send);
-    }
-    T send = b1 ? w2[0] : w2[1];
-    T keep = b1 ? w2[1] : w2[0];
-    T w1 = keep + dpp<DPP_QUAD_XOR2>(send);
-    return w1 + dpp<DPP_QUAD_XOR1>(w1);
-}
-
 // ----------------------------------------------------------------------------------------
 // matrix-free off-diagonal product over the tile pairs of the item table.
 // Writes part[J][k] (row sums of tile I against tile J) and, for I != J, part[I][l] (column
 // sums of tile J against tile I).  Padded points are far dummies whose x entries are zero.
+//
+// Lane = 8 i + j.  Wave w owns rows 64 w + 8 a + i (a = 0..7) of tile I, kept in registers
+// with their x; tile J's points are staged in LDS and walked in groups of 8 columns
+// (8 b + j).  In a group the lane evaluates its 8 pairs (row 8 a + i, column 8 b + j) once:
+// the row terms accumulate per a over the whole tile, the column terms per group.  The column
+// sum of a group is folded over lane bit 3 by DPP and written to LDS per 16-lane row; rows and
+// waves are added at the end of the tile.  Row sums are folded over j (lane bits 0-2) by DPP
+// once per tile.  Every sum has a fixed order, so results are bitwise reproducible.
 // ----------------------------------------------------------------------------------------
+constexpr int MV_R = 8;  // rows per lane (a) and columns per group (j)
+
 template <typename T>
 __global__ __launch_bounds__(TILE) void k_mv_sym(const CGMol *__restrict__ tab, const CGState *__restrict__ st,
                                                  const MvItem *__restrict__ items, int n_items, int gate, int src) {
-    __shared__ T colbuf[TILE / 16][TILE];  // one row of partial column sums per 16-lane row
+    __shared__ T colbuf[TILE / 16][TILE];  // column sums per (wave, 16-lane row)
+    __shared__ Pt<T> cpt[TILE];             // tile J points
+    __shared__ T cx[TILE];                  // and their x
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = lane >> 3, j = lane & 7;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const MvItem w = items[it];
         if (skip(st[w.mol], gate)) continue;
         const CGMol &m = tab[w.mol];
-        const cptr<Pt<T>> __restrict__ pts = as_const(mv_pts<T>(m));
-        const cptr<T> __restrict__ xv = as_const(mv_src<T>(m, src));
+        const Pt<T> *__restrict__ pts = mv_pts<T>(m);
+        const T *__restrict__ xv = mv_src<T>(m, src);
         const T rc2 = mv_rc2<T>(m);
-        const int k = w.I * TILE + threadIdx.x;
-        const Pt<T> me = pts[k];
-        const T xk = xv[k];
-        const int c0 = w.J * TILE;
+        const int r0 = w.I * TILE + wv * 64 + i, c0 = w.J * TILE;
         const bool diag = w.I == w.J;
-        T racc = T(0);
-        for (int l = c0; l < c0 + TILE; l += MV_B) {
-            Pt<T> o[MV_B];
-            T xl[MV_B], a[MV_B], r2[MV_B];
+        cpt[threadIdx.x] = pts[c0 + threadIdx.x];
+        cx[threadIdx.x] = xv[c0 + threadIdx.x];
+        Pt<T> rp[MV_R];
+        T rx[MV_R], racc[MV_R];
 #pragma unroll
-            for (int u = 0; u < MV_B; ++u) {
-                o[u] = pts[l + u];
-                xl[u] = xv[l + u];
+        for (int a = 0; a < MV_R; ++a) {
+            rp[a] = pts[r0 + 8 * a];
+            rx[a] = xv[r0 + 8 * a];
+            racc[a] = T(0);
+        }
+        __syncthreads();
+        for (int b = 0; b < TILE / MV_R; ++b) {
+            const int cl = 8 * b + j;
+            const Pt<T> cp = cpt[cl];
+            const T xc = cx[cl];
+            T cacc = T(0);
+#pragma unroll
+            for (int a = 0; a < MV_R; ++a) {
+                const T dx = rp[a].x - cp.x, dy = rp[a].y - cp.y, dz = rp[a].z - cp.z;
+                const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                T A = rsq_fast(r2);
+                if (r2 < rc2) A = mv_near<T>(rp[a].zeta, cp.zeta, r2, diag && r0 + 8 * a == c0 + cl);
+                racc[a] = fma(A, xc, racc[a]);
+                cacc = fma(A, rx[a], cacc);
             }
-            bool near = false;
-#pragma unroll
-            for (int u = 0; u < MV_B; ++u) {
-                T dx = me.x - o[u].x, dy = me.y - o[u].y, dz = me.z - o[u].z;
-                r2[u] = fma(dx, dx, fma(dy, dy, dz * dz));
-                near |= r2[u] < rc2;
-                a[u] = rsq_fast(r2[u]);
-            }
-            if (near) {
-#pragma unroll
-                for (int u = 0; u < MV_B; ++u)
-                    if (r2[u] < rc2) a[u] = mv_near<T>(me.zeta, o[u].zeta, r2[u], l + u == k);
-            }
-#pragma unroll
-            for (int u = 0; u < MV_B; ++u) racc = fma(a[u], xl[u], racc);
             if (!diag) {
-                T cv[MV_B];
-#pragma unroll
-                for (int u = 0; u < MV_B; ++u) cv[u] = a[u] * xk;
-                const T s = row_colsum8<T>(cv, lane);
-                if ((lane & 1) == 0) colbuf[wv * 4 + (lane >> 4)][l - c0 + ((lane >> 1) & 7)] = s;
+                cacc += dpp<DPP_ROW_ROR8>(cacc);  // lanes i and i ^ 1 (bit 3) hold the same column
+                if ((lane & 8) == 0) colbuf[wv * 4 + (lane >> 4)][cl] = cacc;
             }
         }
-        if (k < m.M) m.part[(size_t)w.J * m.M + k] = (double)racc;
+        // row sums over j (lane bits 0-2): quad pairs, quads, half rows
+#pragma unroll
+        for (int a = 0; a < MV_R; ++a) {
+            T v = racc[a];
+            v += dpp<DPP_QUAD_XOR1>(v);
+            v += dpp<DPP_QUAD_XOR2>(v);
+            v += dpp<DPP_ROW_HALF_MIRROR>(v);
+            const int k = r0 + 8 * a;
+            if (j == 0 && k < m.M) m.part[(size_t)w.J * m.M + k] = (double)v;
+        }
+        __syncthreads();
         if (!diag) {
-            __syncthreads();
             const int c = c0 + threadIdx.x;
             T s = colbuf[0][threadIdx.x];
 #pragma unroll
             for (int q = 1; q < TILE / 16; ++q) s += colbuf[q][threadIdx.x];
             if (c < m.M) m.part[(size_t)w.I * m.M + c] = (double)s;
-            __syncthreads();
         }
+        __syncthreads();
     }
 }
 
