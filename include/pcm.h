@@ -51,7 +51,7 @@ typedef enum {
     PCM_E_STATE = 7         /* call made on an object in the wrong state (e.g. stale sizes) */
 } pcm_status;
 
-enum { PCM_FP64 = 0, PCM_MIXED = 1 };
+enum { PCM_FP64 = 0, PCM_MIXED = 1, PCM_DYNAMIC = 2 };
 enum { PCM_PRECOND_NONE = 0, PCM_PRECOND_JACOBI = 1, PCM_PRECOND_RBJ = 2, PCM_PRECOND_OCTREE = 3 };
 
 typedef struct pcm_ctx pcm_ctx;
@@ -66,8 +66,13 @@ typedef struct pcm_batch pcm_batch;
  *   schwarz_thresh primitive-pair screening cutoff (Eq. 15, Eq. 18). Default 1e-12.
  *   diag_const     constant of Eq. 3: A_kk = diag_const * zeta_k / S_k. Default sqrt(2/pi),
  *                  the r -> 0 limit of Eq. 2 for two equal Gaussians.
- *   precision      PCM_FP64 or PCM_MIXED for the integral kernels (FP32 Hermite/Boys
- *                  evaluation with FP64 accumulation). Default PCM_FP64.
+ *   precision      PCM_FP64, PCM_MIXED (FP32 Hermite/Boys evaluation with FP64 accumulation)
+ *                  or PCM_DYNAMIC (per primitive pair: FP64 when its screening bound -- Eq. 18
+ *                  for c and the gradient, Eq. 15 for F -- reaches dp_thresh, FP32 with FP64
+ *                  accumulation otherwise; the per-pair precision choice of the paper's
+ *                  ref. 51, applied to these one-electron integrals) for the integral
+ *                  kernels. Default PCM_FP64.
+ *   dp_thresh      PCM_DYNAMIC split threshold. Default 1e-6.
  *   autotune       1 (default): on first use of an integral kernel for a (class, precision,
  *                  size bucket) the library times a few pair/point chunk shapes and keeps the
  *                  fastest for the life of the context; results then depend on that choice
@@ -77,6 +82,7 @@ typedef struct {
     double eps, k_factor, zeta0, switch_thresh, schwarz_thresh, diag_const;
     int precision;
     int autotune;
+    double dp_thresh;
 } pcm_params;
 
 void pcm_default_params(pcm_params *p);

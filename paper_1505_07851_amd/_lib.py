@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libpcm.so")
 PCM_OK, PCM_E_ARG, PCM_E_ALLOC, PCM_E_HIP, PCM_E_NOCONV, PCM_E_NOTPD, PCM_E_UNSUPPORTED, PCM_E_STATE = range(8)
 STATUS_NAMES = {0: "PCM_OK", 1: "PCM_E_ARG", 2: "PCM_E_ALLOC", 3: "PCM_E_HIP", 4: "PCM_E_NOCONV",
                 5: "PCM_E_NOTPD", 6: "PCM_E_UNSUPPORTED", 7: "PCM_E_STATE"}
-PCM_FP64, PCM_MIXED = 0, 1
+PCM_FP64, PCM_MIXED, PCM_DYNAMIC = 0, 1, 2
 PCM_PRECOND_NONE, PCM_PRECOND_JACOBI, PCM_PRECOND_RBJ, PCM_PRECOND_OCTREE = 0, 1, 2, 3
 PCM_THRESH_FIXED, PCM_THRESH_TWO_DELTA, PCM_THRESH_DYNAMIC = 0, 1, 2
 
@@ -29,7 +29,8 @@ EXPORTED = ["pcm_default_params", "pcm_default_solve_opts", "pcm_create", "pcm_d
 class pcm_params(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("k_factor", ctypes.c_double), ("zeta0", ctypes.c_double),
                 ("switch_thresh", ctypes.c_double), ("schwarz_thresh", ctypes.c_double),
-                ("diag_const", ctypes.c_double), ("precision", ctypes.c_int), ("autotune", ctypes.c_int)]
+                ("diag_const", ctypes.c_double), ("precision", ctypes.c_int), ("autotune", ctypes.c_int),
+                ("dp_thresh", ctypes.c_double)]
 
 
 class pcm_basis(ctypes.Structure):

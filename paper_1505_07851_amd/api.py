@@ -52,7 +52,8 @@ class Context:
     """Library context: model parameters, device, stream."""
 
     def __init__(self, eps=78.39, k_factor=0.0, zeta0=4.9, switch_thresh=1e-8, schwarz_thresh=1e-12,
-                 diag_const=None, precision="fp64", stream=None, device=None, autotune=True):
+                 diag_const=None, precision="fp64", stream=None, device=None, autotune=True,
+                 dp_thresh=1e-6):
         import torch
         self.lib = C.lib()
         if device is not None:
@@ -64,7 +65,8 @@ class Context:
         p.switch_thresh, p.schwarz_thresh = switch_thresh, schwarz_thresh
         if diag_const is not None:
             p.diag_const = diag_const
-        p.precision = C.PCM_MIXED if precision == "mixed" else C.PCM_FP64
+        p.precision = {"fp64": C.PCM_FP64, "mixed": C.PCM_MIXED, "dynamic": C.PCM_DYNAMIC}[precision]
+        p.dp_thresh = float(dp_thresh)
         p.autotune = 1 if autotune else 0
         self.params = p
         self.precision = precision

@@ -4,6 +4,7 @@
 #include "pcm_internal.h"
 
 #include <algorithm>
+#include <iterator>
 #include <cstring>
 #include <new>
 
@@ -57,6 +58,8 @@ void release_mol(pcm_mol *m) {
     m->solo = nullptr;
     release_list(m->fock);
     release_list(m->esp);
+    release_list(m->fock_w);
+    release_list(m->esp_w);
 }
 
 // candidate shell pairs, classes concatenated; (a, b) with l_a <= l_b (a <= b for equal l)
@@ -144,6 +147,16 @@ pcm_status check_solve_opts(pcm_ctx *ctx, const pcm_solve_opts *opts, pcm_solve_
     return PCM_OK;
 }
 
+// pair-geometry records of the Fock list(s) in the context's precision
+static void lists_geometry(pcm_ctx *ctx, pcm_mol *mol) {
+    if (ctx->prm.precision == PCM_DYNAMIC) {
+        pairs_prepare_geometry(ctx, mol, mol->fock, PCM_FP64);
+        pairs_prepare_geometry(ctx, mol, mol->fock_w, PCM_MIXED);
+    } else {
+        pairs_prepare_geometry(ctx, mol, mol->fock, ctx->prm.precision);
+    }
+}
+
 }  // namespace
 
 struct pcm_batch {
@@ -163,6 +176,7 @@ void pcm_default_params(pcm_params *p) {
     p->diag_const = std::sqrt(2.0 / M_PI);
     p->precision = PCM_FP64;
     p->autotune = 1;
+    p->dp_thresh = 1e-6;
 }
 
 void pcm_default_solve_opts(pcm_solve_opts *o) {
@@ -186,7 +200,8 @@ pcm_status pcm_create(const pcm_params *params, void *hip_stream, pcm_ctx **out)
     if (!is_fin(p.eps) || !(p.eps > 1.0) || !is_fin(p.k_factor) || p.k_factor < 0.0 || !is_fin(p.zeta0) ||
         !(p.zeta0 > 0.0) || !is_fin(p.switch_thresh) || p.switch_thresh < 0.0 || !is_fin(p.schwarz_thresh) ||
         p.schwarz_thresh < 0.0 || !is_fin(p.diag_const) || !(p.diag_const > 0.0) ||
-        (p.precision != PCM_FP64 && p.precision != PCM_MIXED) || (p.autotune != 0 && p.autotune != 1))
+        (p.precision != PCM_FP64 && p.precision != PCM_MIXED && p.precision != PCM_DYNAMIC) ||
+        (p.autotune != 0 && p.autotune != 1) || !is_fin(p.dp_thresh) || p.dp_thresh < 0.0)
         return PCM_E_ARG;
     pcm_ctx *c = new (std::nothrow) pcm_ctx();
     if (!c) return PCM_E_ALLOC;
@@ -283,7 +298,8 @@ pcm_status pcm_build_surface(pcm_ctx *ctx, int n_atoms, const double *xyz, const
         upload(ctx, m->spb, m->h_spb.data(), m->h_spb.size());
         build_atom_lists(ctx, m);
         pairs_build(ctx, m, m->fock, nullptr, 0);
-        pairs_prepare_geometry(ctx, m, m->fock, ctx->prm.precision);
+        if (ctx->prm.precision == PCM_DYNAMIC) pairs_split(ctx, m, m->fock, m->fock_w, nullptr, ctx->prm.dp_thresh);
+        lists_geometry(ctx, m);
         HIP_OK(hipStreamSynchronize(ctx->stream));
         return PCM_OK;
     });
@@ -312,7 +328,7 @@ pcm_status pcm_update_geometry(pcm_ctx *ctx, pcm_mol *mol, const double *xyz, co
         DevBuf<double> rs;
         if (r_surf) upload(ctx, rs, r_surf, 3 * (size_t)mol->M);
         surface_points(ctx, mol, r_surf ? rs.p : nullptr);
-        pairs_prepare_geometry(ctx, mol, mol->fock, ctx->prm.precision);
+        lists_geometry(ctx, mol);
         HIP_OK(hipStreamSynchronize(ctx->stream));
         rs.release();
         mol->esp_valid = false;
@@ -324,7 +340,13 @@ pcm_status pcm_update_geometry(pcm_ctx *ctx, pcm_mol *mol, const double *xyz, co
 
 static pcm_status density_list(pcm_ctx *ctx, pcm_mol *mol, const double *P) {
     pairs_build(ctx, mol, mol->esp, P, 1);
-    pairs_prepare_density(ctx, mol, mol->esp, P, ctx->prm.precision);
+    if (ctx->prm.precision == PCM_DYNAMIC) {
+        pairs_split(ctx, mol, mol->esp, mol->esp_w, P, ctx->prm.dp_thresh);
+        pairs_prepare_density(ctx, mol, mol->esp, P, PCM_FP64);
+        pairs_prepare_density(ctx, mol, mol->esp_w, P, PCM_MIXED);
+    } else {
+        pairs_prepare_density(ctx, mol, mol->esp, P, ctx->prm.precision);
+    }
     mol->esp_valid = true;
     return PCM_OK;
 }
@@ -474,11 +496,16 @@ pcm_status pcm_mol_sizes(const pcm_mol *mol, int *M, int *nbf, int *n_atoms, lon
     if (M) *M = mol->M;
     if (nbf) *nbf = mol->nbf;
     if (n_atoms) *n_atoms = mol->N;
+    // with a precision split the weak lists are empty unless PCM_DYNAMIC built them
     for (int c = 0; c < NCLS; ++c) {
-        if (pairs_fock) pairs_fock[c] = mol->fock.cls_off[c + 1] - mol->fock.cls_off[c];
-        if (pairs_esp) pairs_esp[c] = mol->esp.cls_off[c + 1] - mol->esp.cls_off[c];
-        if (sp_fock) sp_fock[c] = mol->fock.sp_count[c];
-        if (sp_esp) sp_esp[c] = mol->esp.sp_count[c];
+        if (pairs_fock)
+            pairs_fock[c] = mol->fock.cls_off[c + 1] - mol->fock.cls_off[c] + mol->fock_w.cls_off[c + 1] -
+                            mol->fock_w.cls_off[c];
+        if (pairs_esp)
+            pairs_esp[c] =
+                mol->esp.cls_off[c + 1] - mol->esp.cls_off[c] + mol->esp_w.cls_off[c + 1] - mol->esp_w.cls_off[c];
+        if (sp_fock) sp_fock[c] = mol->fock.sp_union[c];
+        if (sp_esp) sp_esp[c] = mol->esp.sp_union[c];
     }
     return PCM_OK;
 }
@@ -488,13 +515,29 @@ pcm_status pcm_pair_list(pcm_ctx *ctx, const pcm_mol *mol, int which, int *cls, 
     if (!mol || !cls || !a || !b || !i || !j || (which != 0 && which != 1))
         return fail(ctx, PCM_E_ARG, "bad argument");
     const PairList &pl = which == 0 ? mol->fock : mol->esp;
+    const PairList &pw = which == 0 ? mol->fock_w : mol->esp_w;  // empty unless PCM_DYNAMIC split it
     return guarded(ctx, [&]() -> pcm_status {
-        long long n = pl.n;
+        // entries (shell pair, i*8+j) of both parts, merged back into list order
+        auto fetch = [&](const PairList &l) {
+            std::vector<std::pair<int, int>> e(l.n);
+            std::vector<int> es(l.n), ei(l.n);
+            if (l.n) {
+                HIP_OK(hipMemcpyAsync(es.data(), l.ent_sp.p, l.n * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+                HIP_OK(hipMemcpyAsync(ei.data(), l.ent_ij.p, l.n * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+                HIP_OK(hipStreamSynchronize(ctx->stream));
+            }
+            for (long long t = 0; t < l.n; ++t) e[t] = {es[t], ei[t]};
+            return e;
+        };
+        const auto e1 = fetch(pl), e2 = fetch(pw);
+        std::vector<std::pair<int, int>> ent;
+        ent.reserve(e1.size() + e2.size());
+        std::merge(e1.begin(), e1.end(), e2.begin(), e2.end(), std::back_inserter(ent));
+        const long long n = (long long)ent.size();
         std::vector<int> es(n), ei(n);
-        if (n) {
-            HIP_OK(hipMemcpyAsync(es.data(), pl.ent_sp.p, n * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-            HIP_OK(hipMemcpyAsync(ei.data(), pl.ent_ij.p, n * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-            HIP_OK(hipStreamSynchronize(ctx->stream));
+        for (long long t = 0; t < n; ++t) {
+            es[t] = ent[t].first;
+            ei[t] = ent[t].second;
         }
         for (long long t = 0; t < n; ++t) {
             int sp = es[t];

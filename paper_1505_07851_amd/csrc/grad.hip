@@ -281,7 +281,7 @@ __global__ __launch_bounds__(64 * GCW_WAVES) void k_grad_contract_w(
 
 // per candidate shell pair: sum of its primitive pairs' (ga, gb) in list order
 __global__ void k_grad_sp(long long sp0, long long nsp, long long cls_off, const int *__restrict__ spo,
-                          const double *__restrict__ gpair, double *__restrict__ gsp) {
+                          const double *__restrict__ gpair, double *__restrict__ gsp, int add) {
     long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nsp) return;
     long long sp = sp0 + s;
@@ -289,7 +289,7 @@ __global__ void k_grad_sp(long long sp0, long long nsp, long long cls_off, const
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int g = g0; g < g1; ++g)
         for (int d = 0; d < 6; ++d) acc[d] += gpair[(size_t)(g - cls_off) * 6 + d];
-    for (int d = 0; d < 6; ++d) gsp[(size_t)sp * 6 + d] = acc[d];
+    for (int d = 0; d < 6; ++d) gsp[(size_t)sp * 6 + d] = add ? gsp[(size_t)sp * 6 + d] + acc[d] : acc[d];
 }
 
 // -------------------------------------------------------------------------------------------
@@ -455,109 +455,91 @@ static int chunk_for(long long n_work, long long n_lanes) {
     return (int)(len < 16 ? 16 : len);
 }
 
+// rows of the c-term point side for list `ls` (one per pair chunk per class)
+static int grad_pts_chunk(long long n, int M) { return (chunk_for(n, M) + REC_PAD - 1) / REC_PAD * REC_PAD; }
+static int grad_rows(pcm_mol *mol, ListSel ls) {
+    const PairList &pl = mol->*ls;
+    int rows = 0;
+    for (int cl = 0; cl < NCLS; ++cl) {
+        const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
+        rows += n ? div_up(n, grad_pts_chunk(n, mol->M)) : 0;
+    }
+    return rows;
+}
+
+// c term of one pair list: the point side (gc) as partial rows of part_c from row0 on, the
+// pair side (ga, gb) summed per candidate shell pair into gsp (added to it when `add`)
 template <typename T>
-static void grad_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc,
-                        double *g_surf) {
-    PairList &pl = mol->esp;
-    const int M = mol->M;
-    const double inv_f = (ctx->prm.eps + ctx->prm.k_factor) / (ctx->prm.eps - 1.0);
+static void grad_cterm(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, ListSel ls, double *part_c,
+                       int &row0, bool add) {
+    PairList &pl = mol->*ls;
+    const int M = mol->M, Mpad = mol->Mpad;
     const T *tab = sizeof(T) == 8 ? (const T *)ctx->boys64.p : (const T *)ctx->boys32.p;
     const PtInt<T> *pts = reinterpret_cast<const PtInt<T> *>(sizeof(T) == 8 ? mol->pti64.p : mol->pti32.p);
-    const int Mpad = mol->Mpad;
-    if (M == 0) {  // no surface charge: every term of Eq. 14 carries a factor q
-        HIP_OK(hipMemsetAsync(g_nuc, 0, sizeof(double) * 3 * mol->N, ctx->stream));
-        return;
-    }
-    HIP_OK(hipMemcpyAsync(mol->qpad.p, q, sizeof(double) * M, hipMemcpyDeviceToDevice, ctx->stream));
-    // --- A off-diagonal
-    int len_a = chunk_for(M, M);
-    int rows_a = div_up(M, len_a);
-    // --- c term, point side: rows per class
-    int rows_c = 0, chunk_c[NCLS];
+    const char *suffix = sizeof(T) == 8 ? "_f64" : "_f32";
     for (int cl = 0; cl < NCLS; ++cl) {
-        long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
-        chunk_c[cl] = n ? (chunk_for(n, M) + REC_PAD - 1) / REC_PAD * REC_PAD : REC_PAD;
-        rows_c += n ? div_up(n, chunk_c[cl]) : 0;
-    }
-    mol->part.ensure((size_t)(rows_a + rows_c + 1) * 3 * M);
-    double *part_a = mol->part.p, *part_c = mol->part.p + (size_t)rows_a * 3 * M;
-    {
-        ProfScope psa(ctx, "grad_aoff", (double)M * M);
-        k_grad_aoff<<<dim3(div_up(M, 256), rows_a), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p,
-                                                                             mol->zeta.p, q, M, len_a, part_a);
-        HIP_LAUNCH_OK();
-    }
-    int row0 = 0;
-    for (int cl = 0; cl < NCLS; ++cl) {
-        long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
+        const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
         if (!n) continue;
-        int L = CLS_LA[cl] + CLS_LB[cl];
-        int nch = div_up(n, chunk_c[cl]);
-        int n_pad = (int)((n + REC_PAD - 1) / REC_PAD * REC_PAD);
+        const int L = CLS_LA[cl] + CLS_LB[cl];
+        const int chunk = grad_pts_chunk(n, M);
+        const int nch = div_up(n, chunk);
+        const int n_pad = (int)((n + REC_PAD - 1) / REC_PAD * REC_PAD);
         dim3 grid(div_up(M, 256), nch);
         const unsigned char *rec = pl.rec.p + pl.rec_off[cl];
-        int stride = (int)rec_stride<T>(L);
-        {
-        ProfScope ps(ctx, "grad_pts_L" + std::to_string(L) + (sizeof(T) == 8 ? "_f64" : "_f32"), (double)n * M);
+        const int stride = (int)rec_stride<T>(L);
+        ProfScope ps(ctx, "grad_pts_L" + std::to_string(L) + suffix, (double)n * M);
         switch (L) {
 #define GP_CASE(LL)                                                                                                 \
     case LL:                                                                                                        \
-        k_grad_pts<LL, T><<<grid, 256, 0, ctx->stream>>>(rec, stride, n_pad, chunk_c[cl], pts, M, tab, part_c, row0); \
+        k_grad_pts<LL, T><<<grid, 256, 0, ctx->stream>>>(rec, stride, n_pad, chunk, pts, M, tab, part_c, row0);     \
         break;
             GP_CASE(0) GP_CASE(1) GP_CASE(2) GP_CASE(3) GP_CASE(4)
 #undef GP_CASE
         }
         HIP_LAUNCH_OK();
-        }
         row0 += nch;
     }
-    k_grad_surf<<<div_up(M, 256), 256, 0, ctx->stream>>>(M, mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p, mol->Akk.p,
-                                                         mol->keep.p, mol->nsph, q, mol->xyz.p, mol->Z.p, mol->rad.p,
-                                                         mol->N, inv_f, part_a, rows_a, part_c, rows_c, g_surf);
-    HIP_LAUNCH_OK();
-    // --- c term, pair side: V' (L+1) per pair, contraction, per shell pair, per atom
-    long long nsp = mol->sp_cls_off[NCLS];
-    mol->gsp.ensure((size_t)nsp * 6 + 6);
+    // pair side: V' (L+1) per pair, contraction, per shell pair
     size_t vneed = 0, gneed = 0;
     int chunk_v[NCLS];
     for (int cl = 0; cl < NCLS; ++cl) {
-        long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
+        const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
         chunk_v[cl] = chunk_for(Mpad, n ? n : 1);
         if (chunk_v[cl] < 32) chunk_v[cl] = 32;
         chunk_v[cl] = (chunk_v[cl] + PT_BATCH - 1) / PT_BATCH * PT_BATCH;
-        size_t v = (size_t)div_up(Mpad, chunk_v[cl]) * ntuv(CLS_LA[cl] + CLS_LB[cl] + 1) * n;
+        const size_t v = (size_t)div_up(Mpad, chunk_v[cl]) * ntuv(CLS_LA[cl] + CLS_LB[cl] + 1) * n;
         vneed = v > vneed ? v : vneed;
         gneed = (size_t)n * 6 > gneed ? (size_t)n * 6 : gneed;
     }
     mol->vbuf.ensure(vneed + 1);
     mol->gpair.ensure(gneed + 1);
     for (int cl = 0; cl < NCLS; ++cl) {
-        long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
-        long long sp0 = mol->sp_cls_off[cl], ncs = mol->sp_cls_off[cl + 1] - sp0;
+        const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
+        const long long sp0 = mol->sp_cls_off[cl], ncs = mol->sp_cls_off[cl + 1] - sp0;
         if (!n) {
-            if (ncs) HIP_OK(hipMemsetAsync(mol->gsp.p + sp0 * 6, 0, sizeof(double) * 6 * ncs, ctx->stream));
+            if (ncs && !add) HIP_OK(hipMemsetAsync(mol->gsp.p + sp0 * 6, 0, sizeof(double) * 6 * ncs, ctx->stream));
             continue;
         }
-        int L = CLS_LA[cl] + CLS_LB[cl];
-        int nch = div_up(Mpad, chunk_v[cl]);
-        dim3 grid(div_up(n, 256), nch);
+        const int L = CLS_LA[cl] + CLS_LB[cl];
+        const int nch = div_up(Mpad, chunk_v[cl]);
         const unsigned char *rec = pl.rec.p + pl.rec_off[cl];
-        int stride = (int)rec_stride<T>(L);
+        const int stride = (int)rec_stride<T>(L);
         {
-        ProfScope ps(ctx, "grad_v_L" + std::to_string(L) + (sizeof(T) == 8 ? "_f64" : "_f32"), (double)n * M);
-        switch (L) {
+            ProfScope ps(ctx, "grad_v_L" + std::to_string(L) + suffix, (double)n * M);
+            dim3 grid(div_up(n, 256), nch);
+            switch (L) {
 #define GV_CASE(LL)                                                                                                \
     case LL:                                                                                                       \
         k_grad_v<LL, T><<<grid, 256, 0, ctx->stream>>>(rec, stride, (int)n, pts, mol->qpad.p, Mpad, chunk_v[cl],   \
                                                        tab, mol->vbuf.p);                                           \
         break;
-            GV_CASE(0) GV_CASE(1) GV_CASE(2) GV_CASE(3) GV_CASE(4)
+                GV_CASE(0) GV_CASE(1) GV_CASE(2) GV_CASE(3) GV_CASE(4)
 #undef GV_CASE
-        }
-        HIP_LAUNCH_OK();
+            }
+            HIP_LAUNCH_OK();
         }
         const int *es = pl.ent_sp.p + pl.cls_off[cl], *ei = pl.ent_ij.p + pl.cls_off[cl];
-        int g = div_up(n, 64);
+        const int g = div_up(n, 64);
         ProfScope ps2(ctx, "grad_contract", (double)n);
 #define GC_CASE(CI, LA_, LB_)                                                                                      \
     case CI:                                                                                                       \
@@ -584,9 +566,47 @@ static void grad_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, const doubl
 #undef GCW_CASE
         HIP_LAUNCH_OK();
         k_grad_sp<<<div_up(ncs, 128), 128, 0, ctx->stream>>>(sp0, ncs, pl.cls_off[cl], pl.spo.p, mol->gpair.p,
-                                                             mol->gsp.p);
+                                                             mol->gsp.p, add ? 1 : 0);
         HIP_LAUNCH_OK();
     }
+}
+
+// Eq. 14 at fixed density: A off-diagonal rows, the c term of the list(s), then per point
+// (g_surf) and per atom (g_nuc) with the B and switching terms
+static void grad_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc, double *g_surf,
+                        int prec) {
+    const int M = mol->M;
+    const double inv_f = (ctx->prm.eps + ctx->prm.k_factor) / (ctx->prm.eps - 1.0);
+    if (M == 0) {  // no surface charge: every term of Eq. 14 carries a factor q
+        HIP_OK(hipMemsetAsync(g_nuc, 0, sizeof(double) * 3 * mol->N, ctx->stream));
+        return;
+    }
+    const bool dyn = prec == PCM_DYNAMIC;
+    HIP_OK(hipMemcpyAsync(mol->qpad.p, q, sizeof(double) * M, hipMemcpyDeviceToDevice, ctx->stream));
+    const int len_a = chunk_for(M, M);
+    const int rows_a = div_up(M, len_a);
+    const int rows_c = grad_rows(mol, &pcm_mol::esp) + (dyn ? grad_rows(mol, &pcm_mol::esp_w) : 0);
+    mol->part.ensure((size_t)(rows_a + rows_c + 1) * 3 * M);
+    double *part_a = mol->part.p, *part_c = mol->part.p + (size_t)rows_a * 3 * M;
+    const long long nsp = mol->sp_cls_off[NCLS];
+    mol->gsp.ensure((size_t)nsp * 6 + 6);
+    {
+        ProfScope psa(ctx, "grad_aoff", (double)M * M);
+        k_grad_aoff<<<dim3(div_up(M, 256), rows_a), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p,
+                                                                             mol->zeta.p, q, M, len_a, part_a);
+        HIP_LAUNCH_OK();
+    }
+    int row0 = 0;
+    if (prec == PCM_MIXED) {
+        grad_cterm<float>(ctx, mol, P, q, &pcm_mol::esp, part_c, row0, false);
+    } else {
+        grad_cterm<double>(ctx, mol, P, q, &pcm_mol::esp, part_c, row0, false);
+        if (dyn) grad_cterm<float>(ctx, mol, P, q, &pcm_mol::esp_w, part_c, row0, true);
+    }
+    k_grad_surf<<<div_up(M, 256), 256, 0, ctx->stream>>>(M, mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p, mol->Akk.p,
+                                                         mol->keep.p, mol->nsph, q, mol->xyz.p, mol->Z.p, mol->rad.p,
+                                                         mol->N, inv_f, part_a, rows_a, part_c, rows_c, g_surf);
+    HIP_LAUNCH_OK();
     k_grad_nuc<<<mol->N, 256, 0, ctx->stream>>>(mol->N, M, mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p, mol->Akk.p,
                                                 mol->keep.p, mol->nsph, q, mol->xyz.p, mol->Z.p, mol->rad.p, inv_f,
                                                 mol->atom_sp_off_a.p, mol->atom_sp_a.p, mol->atom_sp_off_b.p,
@@ -596,8 +616,5 @@ static void grad_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, const doubl
 
 void run_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc, double *g_surf,
               int prec) {
-    if (prec == PCM_MIXED)
-        grad_launch<float>(ctx, mol, P, q, g_nuc, g_surf);
-    else
-        grad_launch<double>(ctx, mol, P, q, g_nuc, g_surf);
+    grad_launch(ctx, mol, P, q, g_nuc, g_surf, prec);
 }

@@ -54,7 +54,7 @@ struct SumDesc {
     const double *part;
     double *out;
     long long base;
-    int M, rows;
+    int M, rows, acc;  // acc: add to out instead of overwriting it
 };
 
 template <typename D> __device__ __forceinline__ int find_desc(const D *__restrict__ ds, int nd, long long it) {
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_sum_rows(const SumDesc *__restrict__ ds
         if (k >= d.M) continue;
         double s = 0.0;
         for (int r = 0; r < d.rows; ++r) s += d.part[(size_t)r * d.M + k];
-        d.out[k] = s;
+        d.out[k] = d.acc ? d.out[k] + s : s;
     }
 }
 
@@ -434,8 +434,8 @@ static void esp_class_launch(pcm_ctx *ctx, int L, const EspDesc *d, int nd, long
     HIP_LAUNCH_OK();
 }
 
-template <typename T> static EspDesc esp_desc(pcm_mol *mol, int cl, int chunk, int row0) {
-    PairList &pl = mol->esp;
+template <typename T> static EspDesc esp_desc(pcm_mol *mol, ListSel ls, int cl, int chunk, int row0) {
+    PairList &pl = mol->*ls;
     const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
     const int L = CLS_LA[cl] + CLS_LB[cl];
     EspDesc d{};
@@ -452,8 +452,8 @@ template <typename T> static EspDesc esp_desc(pcm_mol *mol, int cl, int chunk, i
 }
 
 // chunk of (molecule, class), autotuned on first use of its shape key
-template <typename T> static int esp_chunk(pcm_ctx *ctx, pcm_mol *mol, int cl) {
-    const long long n = mol->esp.cls_off[cl + 1] - mol->esp.cls_off[cl];
+template <typename T> static int esp_chunk(pcm_ctx *ctx, pcm_mol *mol, ListSel ls, int cl) {
+    const long long n = (mol->*ls).cls_off[cl + 1] - (mol->*ls).cls_off[cl];
     const int L = CLS_LA[cl] + CLS_LB[cl];
     if (!ctx->prm.autotune) return esp_chunk_len(n, mol->M, TARGET_DEFAULT);
     std::vector<int> cands;
@@ -469,7 +469,7 @@ template <typename T> static int esp_chunk(pcm_ctx *ctx, pcm_mol *mol, int cl) {
     for (int c : cands) rows_max = std::max(rows_max, div_up(n, c));
     mol->part.ensure((size_t)rows_max * mol->M);
     int best_chunk = autotune_pick(ctx, key + ":chunk", cands, [&](int c) {
-        EspDesc d = esp_desc<T>(mol, cl, c, 0);
+        EspDesc d = esp_desc<T>(mol, ls, cl, c, 0);
         d.base = 0;
         long long items = (long long)d.ntile * div_up(n, c);
         EspDesc *dd = (EspDesc *)upload_desc(ctx, &d, sizeof(d));
@@ -485,15 +485,17 @@ template <typename T> static int esp_chunk(pcm_ctx *ctx, pcm_mol *mol, int cl) {
     return best_chunk;
 }
 
+// c[i] = (acc ? c[i] : 0) + the contribution of list `ls` of every molecule
 template <typename T>
-static void esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<double *> &c) {
+static void esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<double *> &c, ListSel ls,
+                      bool acc) {
     const int n = (int)mols.size();
     std::vector<std::array<int, NCLS>> chunk(n);
     std::vector<int> rows(n, 0);
     for (int i = 0; i < n; ++i) {
         for (int cl = 0; cl < NCLS; ++cl) {
-            long long np = mols[i]->esp.cls_off[cl + 1] - mols[i]->esp.cls_off[cl];
-            chunk[i][cl] = np ? esp_chunk<T>(ctx, mols[i], cl) : REC_PAD;
+            long long np = (mols[i]->*ls).cls_off[cl + 1] - (mols[i]->*ls).cls_off[cl];
+            chunk[i][cl] = np ? esp_chunk<T>(ctx, mols[i], ls, cl) : REC_PAD;
             rows[i] += np ? div_up(np, chunk[i][cl]) : 0;
         }
         mols[i]->part.ensure((size_t)std::max(rows[i], 1) * mols[i]->M);
@@ -507,9 +509,9 @@ static void esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const st
         cls_first[cl] = (int)all.size();
         long long base = 0;
         for (int i = 0; i < n; ++i) {
-            long long np = mols[i]->esp.cls_off[cl + 1] - mols[i]->esp.cls_off[cl];
+            long long np = (mols[i]->*ls).cls_off[cl + 1] - (mols[i]->*ls).cls_off[cl];
             if (!np) continue;
-            EspDesc d = esp_desc<T>(mols[i], cl, chunk[i][cl], row0[i]);
+            EspDesc d = esp_desc<T>(mols[i], ls, cl, chunk[i][cl], row0[i]);
             d.base = base;
             base += (long long)d.ntile * div_up(np, chunk[i][cl]);
             row0[i] += div_up(np, chunk[i][cl]);
@@ -521,7 +523,7 @@ static void esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const st
     std::vector<SumDesc> sums;
     long long sbase = 0;
     for (int i = 0; i < n; ++i) {
-        SumDesc d{mols[i]->part.p, c[i], sbase, mols[i]->M, rows[i]};
+        SumDesc d{mols[i]->part.p, c[i], sbase, mols[i]->M, rows[i], acc ? 1 : 0};
         sbase += div_up(mols[i]->M, 256);
         sums.push_back(d);
     }
@@ -536,7 +538,7 @@ static void esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const st
         const int L = CLS_LA[cl] + CLS_LB[cl];
         double work = 0.0;
         for (int i = 0; i < n; ++i)
-            work += (double)(mols[i]->esp.cls_off[cl + 1] - mols[i]->esp.cls_off[cl]) * mols[i]->M;
+            work += (double)((mols[i]->*ls).cls_off[cl + 1] - (mols[i]->*ls).cls_off[cl]) * mols[i]->M;
         ProfScope ps(ctx, "esp_L" + std::to_string(L) + (sizeof(T) == 8 ? "_f64" : "_f32"), work);
         esp_class_launch<T>(ctx, L, dd + cls_first[cl], cls_n[cl], cls_items[cl]);
     }
@@ -545,10 +547,14 @@ static void esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const st
 }
 
 void run_esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<double *> &c, int prec) {
-    if (prec == PCM_MIXED)
-        esp_batch<float>(ctx, mols, c);
-    else
-        esp_batch<double>(ctx, mols, c);
+    if (prec == PCM_MIXED) {
+        esp_batch<float>(ctx, mols, c, &pcm_mol::esp, false);
+    } else if (prec == PCM_DYNAMIC) {  // strong pairs in FP64, then the weak ones in FP32 added on
+        esp_batch<double>(ctx, mols, c, &pcm_mol::esp, false);
+        esp_batch<float>(ctx, mols, c, &pcm_mol::esp_w, true);
+    } else {
+        esp_batch<double>(ctx, mols, c, &pcm_mol::esp, false);
+    }
 }
 
 void run_esp(pcm_ctx *ctx, pcm_mol *mol, double *c, int prec) { run_esp_batch(ctx, {mol}, {c}, prec); }
@@ -568,8 +574,8 @@ static void fock_class_launch(pcm_ctx *ctx, int L, const FockDesc *d, int nd, lo
     HIP_LAUNCH_OK();
 }
 
-template <typename T> static FockDesc fock_desc(pcm_mol *mol, int cl, int chunk) {
-    PairList &pl = mol->fock;
+template <typename T> static FockDesc fock_desc(pcm_mol *mol, ListSel ls, int cl, int chunk) {
+    PairList &pl = mol->*ls;
     FockDesc d{};
     d.rec = pl.rec.p + pl.rec_off[cl];
     d.pts = points<T>(mol);
@@ -583,8 +589,8 @@ template <typename T> static FockDesc fock_desc(pcm_mol *mol, int cl, int chunk)
     return d;
 }
 
-template <typename T> static int fock_chunk(pcm_ctx *ctx, pcm_mol *mol, int cl) {
-    const long long n = mol->fock.cls_off[cl + 1] - mol->fock.cls_off[cl];
+template <typename T> static int fock_chunk(pcm_ctx *ctx, pcm_mol *mol, ListSel ls, int cl) {
+    const long long n = (mol->*ls).cls_off[cl + 1] - (mol->*ls).cls_off[cl];
     const int L = CLS_LA[cl] + CLS_LB[cl];
     if (!ctx->prm.autotune) return fock_chunk_len(n, mol->Mpad, TARGET_DEFAULT);
     const std::string key = shape_key("fock", L, sizeof(T) == 8, n, mol->M);
@@ -595,7 +601,7 @@ template <typename T> static int fock_chunk(pcm_ctx *ctx, pcm_mol *mol, int cl) 
         if (std::find(cands.begin(), cands.end(), c) == cands.end()) cands.push_back(c);
     }
     int best_chunk = autotune_pick(ctx, key + ":chunk", cands, [&](int c) {
-        FockDesc d = fock_desc<T>(mol, cl, c);
+        FockDesc d = fock_desc<T>(mol, ls, cl, c);
         d.base = 0;
         long long items = (long long)d.nptile * div_up(mol->Mpad, c);
         FockDesc *dd = (FockDesc *)upload_desc(ctx, &d, sizeof(d));
@@ -612,8 +618,8 @@ template <typename T> static int fock_chunk(pcm_ctx *ctx, pcm_mol *mol, int cl) 
 }
 
 // V buffer and primitive-block buffer large enough for every class and every tuning candidate
-static void fock_buffers(pcm_mol *mol) {
-    PairList &pl = mol->fock;
+static void fock_buffers(pcm_mol *mol, ListSel ls) {
+    PairList &pl = mol->*ls;
     size_t vneed = 0, fneed = 0;
     for (int cl = 0; cl < NCLS; ++cl) {
         long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
@@ -629,18 +635,19 @@ static void fock_buffers(pcm_mol *mol) {
 
 template <typename T>
 static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<const double *> &q,
-                       const std::vector<double *> &F) {
+                       const std::vector<double *> &F, ListSel ls) {
     const int n = (int)mols.size();
     for (int i = 0; i < n; ++i) {
         HIP_OK(hipMemcpyAsync(mols[i]->qpad.p, q[i], sizeof(double) * mols[i]->M, hipMemcpyDeviceToDevice,
                               ctx->stream));
-        fock_buffers(mols[i]);
+        fock_buffers(mols[i], ls);
     }
     std::vector<std::array<int, NCLS>> chunk(n);
     for (int i = 0; i < n; ++i)
         for (int cl = 0; cl < NCLS; ++cl)
-            chunk[i][cl] = mols[i]->fock.cls_off[cl + 1] > mols[i]->fock.cls_off[cl] ? fock_chunk<T>(ctx, mols[i], cl)
-                                                                                  : PT_BATCH;
+            chunk[i][cl] = (mols[i]->*ls).cls_off[cl + 1] > (mols[i]->*ls).cls_off[cl]
+                               ? fock_chunk<T>(ctx, mols[i], ls, cl)
+                               : PT_BATCH;
     std::vector<FockDesc> all;
     long long cls_items[NCLS];
     int cls_first[NCLS], cls_n[NCLS];
@@ -648,8 +655,8 @@ static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const s
         cls_first[cl] = (int)all.size();
         long long base = 0;
         for (int i = 0; i < n; ++i) {
-            if (mols[i]->fock.cls_off[cl + 1] == mols[i]->fock.cls_off[cl]) continue;
-            FockDesc d = fock_desc<T>(mols[i], cl, chunk[i][cl]);
+            if ((mols[i]->*ls).cls_off[cl + 1] == (mols[i]->*ls).cls_off[cl]) continue;
+            FockDesc d = fock_desc<T>(mols[i], ls, cl, chunk[i][cl]);
             d.base = base;
             base += (long long)d.nptile * div_up(mols[i]->Mpad, chunk[i][cl]);
             all.push_back(d);
@@ -663,14 +670,14 @@ static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const s
         const int L = CLS_LA[cl] + CLS_LB[cl];
         double work = 0.0;
         for (int i = 0; i < n; ++i)
-            work += (double)(mols[i]->fock.cls_off[cl + 1] - mols[i]->fock.cls_off[cl]) * mols[i]->M;
+            work += (double)((mols[i]->*ls).cls_off[cl + 1] - (mols[i]->*ls).cls_off[cl]) * mols[i]->M;
         {
             ProfScope ps(ctx, "fock_v_L" + std::to_string(L) + (sizeof(T) == 8 ? "_f64" : "_f32"), work);
             fock_class_launch<T>(ctx, L, dd + cls_first[cl], cls_n[cl], cls_items[cl]);
         }
         for (int i = 0; i < n; ++i) {
             pcm_mol *mol = mols[i];
-            PairList &pl = mol->fock;
+            PairList &pl = mol->*ls;
             const long long np = pl.cls_off[cl + 1] - pl.cls_off[cl];
             if (!np) continue;
             const int nch = div_up(mol->Mpad, chunk[i][cl]);
@@ -713,10 +720,14 @@ static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const s
 
 void run_fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<const double *> &q,
                     const std::vector<double *> &F, int prec) {
-    if (prec == PCM_MIXED)
-        fock_batch<float>(ctx, mols, q, F);
-    else
-        fock_batch<double>(ctx, mols, q, F);
+    if (prec == PCM_MIXED) {
+        fock_batch<float>(ctx, mols, q, F, &pcm_mol::fock);
+    } else if (prec == PCM_DYNAMIC) {  // both lists add their blocks to F
+        fock_batch<double>(ctx, mols, q, F, &pcm_mol::fock);
+        fock_batch<float>(ctx, mols, q, F, &pcm_mol::fock_w);
+    } else {
+        fock_batch<double>(ctx, mols, q, F, &pcm_mol::fock);
+    }
 }
 
 void run_fock(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F, int prec) {

@@ -343,6 +343,7 @@ int autotune_pick(pcm_ctx *ctx, const std::string &key, const std::vector<int> &
 struct PairList {
     long long cls_off[NCLS + 1] = {0};  // prim-pair offsets per class
     long long sp_count[NCLS] = {0};     // shell pairs with at least one surviving primitive pair
+    long long sp_union[NCLS] = {0};     // the same before a precision split (both parts together)
     long long n = 0;
     DevBuf<int> spo;        // [n_sp_cand + 1] exclusive prefix of surviving counts per candidate
     DevBuf<int> cnt;        // [n_sp_cand] surviving count per candidate shell pair
@@ -382,8 +383,9 @@ struct pcm_mol {
     DevBuf<int> spa, spb;
     // per-atom lists of candidate shell pairs (CSR) for the gradient reduction
     DevBuf<int> atom_sp_off_a, atom_sp_a, atom_sp_off_b, atom_sp_b;
-    // screened lists
-    PairList fock, esp;
+    // screened lists; with PCM_DYNAMIC precision fock / esp hold the pairs whose bound reaches
+    // dp_thresh (FP64 records) and fock_w / esp_w the others (FP32 records), both in list order
+    PairList fock, esp, fock_w, esp_w;
     bool esp_valid = false;
     // workspaces
     DevBuf<double> part;   // partial sums (esp / gradient)
@@ -405,6 +407,9 @@ struct pcm_mol {
     bool rbj_valid = false;
     pcm_ctx *owner_ctx = nullptr;
 };
+
+// which list of a molecule a kernel sequence reads
+using ListSel = PairList pcm_mol::*;
 
 // records one launch (or a short sequence) between construction and destruction
 struct ProfScope {
@@ -434,6 +439,9 @@ void basis_normalise(pcm_ctx *ctx, pcm_mol *mol);
 void pairs_build(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P, int kind /*0 fock, 1 esp*/);
 void pairs_prepare_geometry(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, int prec);
 void pairs_prepare_density(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P, int prec);
+// keep in `pl` the survivors whose Eq. 15 bound (times max |P| when P is given) reaches thresh,
+// move the others to `weak`; both keep the list order
+void pairs_split(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, PairList &weak, const double *P, double thresh);
 void run_bz(pcm_ctx *ctx, pcm_mol *mol, double *bz);
 void run_esp(pcm_ctx *ctx, pcm_mol *mol, double *c, int prec);
 void run_fock(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F, int prec);

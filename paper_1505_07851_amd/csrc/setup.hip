@@ -383,21 +383,22 @@ __global__ void k_count_sp(int nsp, const int *__restrict__ cnt, const long long
     if (threadIdx.x == 0) out[c] = s[0];
 }
 
-void pairs_build(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P, int kind) {
-    (void)kind;
-    long long nsp = mol->sp_cls_off[NCLS];
-    pl.mask.ensure(nsp + 1);
-    pl.cnt.ensure(nsp + 1);
-    pl.spo.ensure(nsp + 1);
+static void screen_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, double thresh, unsigned long long *mask,
+                          int *cnt) {
+    const long long nsp = mol->sp_cls_off[NCLS];
+    if (nsp <= 0) return;
     const int T = 256;
     const double c2 = 2.0 * pow(M_PI, 2.5);
-    if (nsp > 0) {
-        k_screen<<<div_up(nsp, T), T, 0, ctx->stream>>>((int)nsp, mol->spa.p, mol->spb.p, mol->sl.p, mol->snp.p,
-                                                         mol->soff.p, mol->satom.p, mol->bfo.p, mol->cnoff.p,
-                                                         mol->pexp.p, mol->cn.p, mol->xyz.p, P, mol->nbf, c2,
-                                                         ctx->prm.schwarz_thresh, pl.mask.p, pl.cnt.p);
-        HIP_LAUNCH_OK();
-    }
+    k_screen<<<div_up(nsp, T), T, 0, ctx->stream>>>((int)nsp, mol->spa.p, mol->spb.p, mol->sl.p, mol->snp.p,
+                                                     mol->soff.p, mol->satom.p, mol->bfo.p, mol->cnoff.p, mol->pexp.p,
+                                                     mol->cn.p, mol->xyz.p, P, mol->nbf, c2, thresh, mask, cnt);
+    HIP_LAUNCH_OK();
+}
+
+// entries, per-shell-pair offsets and class offsets of a list from its survivor masks and counts
+static void pairs_compact(pcm_ctx *ctx, pcm_mol *mol, PairList &pl) {
+    const long long nsp = mol->sp_cls_off[NCLS];
+    const int T = 256;
     long long total = 0;
     scan_exclusive(ctx, mol, pl.cnt.p, pl.spo.p, nsp, &total);
     if (total > 2000000000LL) throw PcmError{PCM_E_ALLOC, "screened pair list exceeds 2^31 entries"};
@@ -438,6 +439,50 @@ void pairs_build(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P, int 
         HIP_OK(hipMemcpyAsync(pl.spo.p + nsp, &t, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
         HIP_OK(hipStreamSynchronize(ctx->stream));
     }
+}
+
+void pairs_build(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P, int kind) {
+    (void)kind;
+    const long long nsp = mol->sp_cls_off[NCLS];
+    pl.mask.ensure(nsp + 1);
+    pl.cnt.ensure(nsp + 1);
+    pl.spo.ensure(nsp + 1);
+    screen_launch(ctx, mol, P, ctx->prm.schwarz_thresh, pl.mask.p, pl.cnt.p);
+    pairs_compact(ctx, mol, pl);
+    for (int c = 0; c < NCLS; ++c) pl.sp_union[c] = pl.sp_count[c];
+}
+
+// strong = survivors whose bound also reaches the split threshold; weak = the other survivors
+__global__ void k_mask_split(int nsp, const unsigned long long *__restrict__ strong_bits,
+                             unsigned long long *__restrict__ mask, int *__restrict__ cnt,
+                             unsigned long long *__restrict__ wmask, int *__restrict__ wcnt) {
+    int sp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sp >= nsp) return;
+    const unsigned long long all = mask[sp], s = all & strong_bits[sp], w = all & ~s;
+    mask[sp] = s;
+    cnt[sp] = __popcll(s);
+    wmask[sp] = w;
+    wcnt[sp] = __popcll(w);
+}
+
+void pairs_split(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, PairList &weak, const double *P, double thresh) {
+    const long long nsp = mol->sp_cls_off[NCLS];
+    weak.mask.ensure(nsp + 1);
+    weak.cnt.ensure(nsp + 1);
+    weak.spo.ensure(nsp + 1);
+    if (nsp > 0) {
+        DevBuf<unsigned long long> sbits;
+        DevBuf<int> scnt;
+        sbits.ensure(nsp);
+        scnt.ensure(nsp);
+        screen_launch(ctx, mol, P, std::max(thresh, ctx->prm.schwarz_thresh), sbits.p, scnt.p);
+        k_mask_split<<<div_up(nsp, 256), 256, 0, ctx->stream>>>((int)nsp, sbits.p, pl.mask.p, pl.cnt.p, weak.mask.p,
+                                                                weak.cnt.p);
+        HIP_LAUNCH_OK();
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+    }
+    pairs_compact(ctx, mol, pl);
+    pairs_compact(ctx, mol, weak);
 }
 
 // ----------------------------------------------------------------------------------------

@@ -47,6 +47,7 @@ def test_default_params_match_paper(L):
     assert p.schwarz_thresh == g["schwarz_thresh"]["value"]
     assert abs(p.diag_const - np.sqrt(2 / np.pi)) < 1e-16
     assert p.zeta0 == 4.9
+    assert p.precision == _lib.PCM_FP64 and p.dp_thresh == 1e-6
 
 
 def test_create_validation(L):
@@ -55,7 +56,7 @@ def test_create_validation(L):
     p = _lib.pcm_params()
     L.pcm_default_params(ctypes.byref(p))
     for field, bad in [("eps", float("nan")), ("eps", 0.5), ("zeta0", -1.0), ("schwarz_thresh", -1e-3),
-                       ("precision", 7)]:
+                       ("precision", 7), ("dp_thresh", -1e-6), ("dp_thresh", float("inf"))]:
         q = _lib.pcm_params.from_buffer_copy(p)
         setattr(q, field, bad)
         assert L.pcm_create(ctypes.byref(q), None, ctypes.byref(h)) == _lib.PCM_E_ARG
