@@ -8,8 +8,10 @@ One step = one pass of the whole path over the 600-atom protein-shaped solute
   F += L^T q, and the Eq. 14 gradient.
 The value is shell-pair x point integrals per second over the whole step (three integral
 passes: c, F and the gradient), with the PCG solve time and its residual reported beside
-it, for the FP64 path and for the mixed form (FP32 evaluation, FP64 accumulation, FP32
-matvec inside FP64 refinement).  Inputs are synthetic and seeded (see synth/inputs.py).
+it, for the FP64 path (the line's value), for the mixed form (FP32 evaluation, FP64
+accumulation, FP32 matvec inside FP64 refinement) and for the per-pair dynamic form (FP64 or
+FP32 integral evaluation by screening bound, FP64 solve).  Inputs are synthetic and seeded
+(see synth/inputs.py).
 
 Second workload (--workload conformers64): 64 seeded conformers of a 150-atom peptide
 (6-31G-shaped basis, nbf 825, 3.9k-9k kept points each).  One step = c = L P with Bz,
@@ -162,7 +164,7 @@ def main():
             mol.update_geometry(s.xyz)
             c, bz = mol.esp(P)
             q, info = mol.solve(bz + c, precond="rbj", block=args.block, seed=s.seeds["rbj"], tol=args.tol,
-                                precision=prec, q0=state.get("q"))
+                                precision="mixed" if prec == "mixed" else "fp64", q0=state.get("q"))
             F = mol.fock(q)
             gn, gs = mol.grad(P, q)
             state.update(c=c, bz=bz, q=q, info=info, F=F, gn=gn, gs=gs)
@@ -240,8 +242,11 @@ def main():
            "pcg_iters": info64["iters"], "pcg_resid": info64["resid"], "energy": info64["energy"],
            "roofline": roof, "integrals_per_s_by_L": by_L, "kernels": kernels}
 
-    if not args.no_mixed:
-        rmx = run_form("mixed")
+    # the mixed form (FP32 integrals and FP32 matvec in FP64 refinement) and the per-pair dynamic
+    # form (FP64 or FP32 integrals by screening bound, FP64 solve), each against the FP64 path
+    forms = {}
+    for form in ([] if args.no_mixed else ["mixed", "dynamic"]):
+        rmx = forms[form] = run_form(form)
         infm = rmx["infos"][-1]
         stm = rmx["state"]
         sm = rmx["sizes"]
@@ -250,14 +255,16 @@ def main():
         dq = (stm["q"] - st64["q"]).abs().max().item() / st64["q"].abs().max().item()
         dF = (stm["F"] - st64["F"]).norm().item() / st64["F"].norm().item()
         dg = (stm["gn"] - st64["gn"]).abs().max().item()
-        out["mixed"] = {"value": integ_m / (rmx["ms"] * 1e-3), "ms_per_step": round(rmx["ms"], 3),
-                        "speedup_vs_fp64": round(r64["ms"] / rmx["ms"], 3),
-                        "pcg_solve_ms": round(infm["solve_ms"], 3), "pcg_iters": infm["iters"],
-                        "pcg_refinements": infm["refinements"], "pcg_resid": infm["resid"],
-                        "err_vs_fp64_path": {"E_abs": abs(infm["energy"] - info64["energy"]), "c_rel": dc,
-                                             "q_rel_max": dq, "F_rel": dF, "g_nuc_abs_max": dg},
-                        "kernels": {k: round(v["ms"] / args.steps, 3) for k, v in
-                                    sorted(rmx["prof"].items(), key=lambda kv: -kv[1]["ms"])[:8]}}
+        out[form] = {"value": integ_m / (rmx["ms"] * 1e-3), "ms_per_step": round(rmx["ms"], 3),
+                     "speedup_vs_fp64": round(r64["ms"] / rmx["ms"], 3),
+                     "pcg_solve_ms": round(infm["solve_ms"], 3), "pcg_iters": infm["iters"],
+                     "pcg_refinements": infm["refinements"], "pcg_resid": infm["resid"],
+                     "err_vs_fp64_path": {"E_abs": abs(infm["energy"] - info64["energy"]), "c_rel": dc,
+                                          "q_rel_max": dq, "F_rel": dF, "g_nuc_abs_max": dg},
+                     "kernels": {k: round(v["ms"] / args.steps, 3) for k, v in
+                                 sorted(rmx["prof"].items(), key=lambda kv: -kv[1]["ms"])[:8]}}
+        if form == "dynamic":
+            out[form]["dp_thresh"] = 1e-6
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -283,9 +290,9 @@ def main():
                                "sample": f"c_k = sum P L^k for {n_sample} seeded surface points over the full "
                                          f"Eq. 18 pair list ({t_cpu:.1f} s)"}
         out["c_sample_rel_err_fp64"] = float(np.abs(c_gpu - c_or).max() / np.abs(c_or).max())
-        if "mixed" in out:
-            c_m = rmx["state"]["c"].cpu().numpy()[kidx]
-            out["mixed"]["c_sample_rel_err_vs_oracle"] = float(np.abs(c_m - c_or).max() / np.abs(c_or).max())
+        for form, rf in forms.items():
+            c_m = rf["state"]["c"].cpu().numpy()[kidx]
+            out[form]["c_sample_rel_err_vs_oracle"] = float(np.abs(c_m - c_or).max() / np.abs(c_or).max())
     print(json.dumps(out))
 
 
