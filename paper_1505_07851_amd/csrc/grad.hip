@@ -467,11 +467,11 @@ static int grad_rows(pcm_mol *mol, ListSel ls) {
     return rows;
 }
 
-// c term of one pair list: the point side (gc) as partial rows of part_c from row0 on, the
-// pair side (ga, gb) summed per candidate shell pair into gsp (added to it when `add`)
+// c term of one pair list (charges already in qpad): the point side (gc) as partial rows of part_c
+// from row0 on, the pair side (ga, gb) summed per candidate shell pair into gsp (added when `add`)
 template <typename T>
-static void grad_cterm(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, ListSel ls, double *part_c,
-                       int &row0, bool add) {
+static void grad_cterm(pcm_ctx *ctx, pcm_mol *mol, const double *P, ListSel ls, double *part_c, int &row0,
+                       bool add) {
     PairList &pl = mol->*ls;
     const int M = mol->M, Mpad = mol->Mpad;
     const T *tab = sizeof(T) == 8 ? (const T *)ctx->boys64.p : (const T *)ctx->boys32.p;
@@ -598,10 +598,10 @@ static void grad_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, const doubl
     }
     int row0 = 0;
     if (prec == PCM_MIXED) {
-        grad_cterm<float>(ctx, mol, P, q, &pcm_mol::esp, part_c, row0, false);
+        grad_cterm<float>(ctx, mol, P, &pcm_mol::esp, part_c, row0, false);
     } else {
-        grad_cterm<double>(ctx, mol, P, q, &pcm_mol::esp, part_c, row0, false);
-        if (dyn) grad_cterm<float>(ctx, mol, P, q, &pcm_mol::esp_w, part_c, row0, true);
+        grad_cterm<double>(ctx, mol, P, &pcm_mol::esp, part_c, row0, false);
+        if (dyn) grad_cterm<float>(ctx, mol, P, &pcm_mol::esp_w, part_c, row0, true);
     }
     k_grad_surf<<<div_up(M, 256), 256, 0, ctx->stream>>>(M, mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p, mol->Akk.p,
                                                          mol->keep.p, mol->nsph, q, mol->xyz.p, mol->Z.p, mol->rad.p,

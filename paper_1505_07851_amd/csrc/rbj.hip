@@ -508,7 +508,7 @@ int host_octree_partition(int M, const double *r, int leaf_max, int *perm, int *
     const double half = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2])) * 0.5;
     std::vector<int> idx(M);
     std::iota(idx.begin(), idx.end(), 0);
-    OctreeBuild ob{r, leaf_max, perm, blk_off};
+    OctreeBuild ob{r, leaf_max, perm, blk_off, 0, 0, {}, {}};
     ob.buf.resize(M);
     ob.oct.resize(M);
     blk_off[0] = 0;
