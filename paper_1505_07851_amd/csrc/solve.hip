@@ -132,22 +132,37 @@ __device__ __forceinline__ double blk_sum_parts(const double *__restrict__ part,
 // Writes part[J][k] (row sums of tile I against tile J) and, for I != J, part[I][l] (column
 // sums of tile J against tile I).  Padded points are far dummies whose x entries are zero.
 //
-// Lane = 8 i + j.  Wave w owns rows 64 w + 8 a + i (a = 0..7) of tile I, kept in registers
-// with their x; tile J's points are staged in LDS and walked in groups of 8 columns
-// (8 b + j).  In a group the lane evaluates its 8 pairs (row 8 a + i, column 8 b + j) once:
-// the row terms accumulate per a over the whole tile, the column terms per group.  The column
-// sum of a group is folded over lane bit 3 by DPP and written to LDS per 16-lane row; rows and
+// Lane = 8 i + j.  Wave w owns rows 32 w + 8 a + i (a = 0..3) of tile I, kept in registers with
+// their x; tile J's points are staged in LDS and walked in groups of 8 columns (8 b + j).  In a
+// group the lane evaluates its 4 pairs (row 8 a + i, column 8 b + j) once: the row terms
+// accumulate per a over the whole tile, the column terms per group.  The column sum of a group is
+// folded over lane bits 3 (DPP) and 4 (swizzle) and written to LDS per 32-lane half; halves and
 // waves are added at the end of the tile.  Row sums are folded over j (lane bits 0-2) by DPP
 // once per tile.  Every sum has a fixed order, so results are bitwise reproducible.
 // ----------------------------------------------------------------------------------------
-constexpr int MV_R = 8;  // rows per lane (a) and columns per group (j)
+constexpr int MV_R = 4;                 // rows per lane (a)
+constexpr int MV_WAVES = TILE / (8 * MV_R);  // waves per tile pair: 8 i-lanes x MV_R rows each
+constexpr int MV_THREADS = 64 * MV_WAVES;
+
+// lanes l and l ^ 16 exchange values (LDS-free swizzle within 32-lane halves)
+__device__ __forceinline__ double swz16(double v) {
+    constexpr int XOR16 = (0x10 << 10) | 0x1F;  // bit mode: and 0x1F, or 0, xor 0x10
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), XOR16);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), XOR16);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float swz16(float v) {
+    constexpr int XOR16 = (0x10 << 10) | 0x1F;
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), XOR16));
+}
 
 template <typename T>
-__global__ __launch_bounds__(TILE) void k_mv_sym(const CGMol *__restrict__ tab, const CGState *__restrict__ st,
-                                                 const MvItem *__restrict__ items, int n_items, int gate, int src) {
-    __shared__ T colbuf[TILE / 16][TILE];  // column sums per (wave, 16-lane row)
-    __shared__ Pt<T> cpt[TILE];             // tile J points
-    __shared__ T cx[TILE];                  // and their x
+__global__ __launch_bounds__(MV_THREADS) void k_mv_sym(const CGMol *__restrict__ tab, const CGState *__restrict__ st,
+                                                       const MvItem *__restrict__ items, int n_items, int gate,
+                                                       int src) {
+    __shared__ T colbuf[2 * MV_WAVES][TILE];  // column sums per (wave, 32-lane half)
+    __shared__ Pt<T> cpt[TILE];              // tile J points
+    __shared__ T cx[TILE];                   // and their x
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = lane >> 3, j = lane & 7;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -157,10 +172,12 @@ __global__ __launch_bounds__(TILE) void k_mv_sym(const CGMol *__restrict__ tab, 
         const Pt<T> *__restrict__ pts = mv_pts<T>(m);
         const T *__restrict__ xv = mv_src<T>(m, src);
         const T rc2 = mv_rc2<T>(m);
-        const int r0 = w.I * TILE + wv * 64 + i, c0 = w.J * TILE;
+        const int r0 = w.I * TILE + wv * (8 * MV_R) + i, c0 = w.J * TILE;
         const bool diag = w.I == w.J;
-        cpt[threadIdx.x] = pts[c0 + threadIdx.x];
-        cx[threadIdx.x] = xv[c0 + threadIdx.x];
+        if (threadIdx.x < TILE) {
+            cpt[threadIdx.x] = pts[c0 + threadIdx.x];
+            cx[threadIdx.x] = xv[c0 + threadIdx.x];
+        }
         Pt<T> rp[MV_R];
         T rx[MV_R], racc[MV_R];
 #pragma unroll
@@ -170,7 +187,7 @@ __global__ __launch_bounds__(TILE) void k_mv_sym(const CGMol *__restrict__ tab, 
             racc[a] = T(0);
         }
         __syncthreads();
-        for (int b = 0; b < TILE / MV_R; ++b) {
+        for (int b = 0; b < TILE / 8; ++b) {
             const int cl = 8 * b + j;
             const Pt<T> cp = cpt[cl];
             const T xc = cx[cl];
@@ -185,8 +202,9 @@ __global__ __launch_bounds__(TILE) void k_mv_sym(const CGMol *__restrict__ tab, 
                 cacc = fma(A, rx[a], cacc);
             }
             if (!diag) {
-                cacc += dpp<DPP_ROW_ROR8>(cacc);  // lanes i and i ^ 1 (bit 3) hold the same column
-                if ((lane & 8) == 0) colbuf[wv * 4 + (lane >> 4)][cl] = cacc;
+                cacc += dpp<DPP_ROW_ROR8>(cacc);  // i bit 0 (lane bit 3)
+                cacc += swz16(cacc);               // i bit 1 (lane bit 4)
+                if ((lane & 24) == 0) colbuf[wv * 2 + (lane >> 5)][cl] = cacc;
             }
         }
         // row sums over j (lane bits 0-2): quad pairs, quads, half rows
@@ -200,11 +218,11 @@ __global__ __launch_bounds__(TILE) void k_mv_sym(const CGMol *__restrict__ tab, 
             if (j == 0 && k < m.M) m.part[(size_t)w.J * m.M + k] = (double)v;
         }
         __syncthreads();
-        if (!diag) {
+        if (!diag && threadIdx.x < TILE) {
             const int c = c0 + threadIdx.x;
             T s = colbuf[0][threadIdx.x];
 #pragma unroll
-            for (int q = 1; q < TILE / 16; ++q) s += colbuf[q][threadIdx.x];
+            for (int q = 1; q < 2 * MV_WAVES; ++q) s += colbuf[q][threadIdx.x];
             if (c < m.M) m.part[(size_t)w.I * m.M + c] = (double)s;
         }
         __syncthreads();
@@ -683,9 +701,9 @@ static std::map<std::pair<int, int>, int> g_mv_grid;
 
 static void launch_mv(pcm_ctx *ctx, SolveBatch &B, hipStream_t s, int prec, int gate, int src, int grid) {
     if (prec == PCM_MIXED)
-        k_mv_sym<float><<<grid, TILE, 0, s>>>(B.tab.p, B.st.p, B.mv.p, B.n_mv, gate, src);
+        k_mv_sym<float><<<grid, MV_THREADS, 0, s>>>(B.tab.p, B.st.p, B.mv.p, B.n_mv, gate, src);
     else
-        k_mv_sym<double><<<grid, TILE, 0, s>>>(B.tab.p, B.st.p, B.mv.p, B.n_mv, gate, src);
+        k_mv_sym<double><<<grid, MV_THREADS, 0, s>>>(B.tab.p, B.st.p, B.mv.p, B.n_mv, gate, src);
     HIP_LAUNCH_OK();
 }
 
