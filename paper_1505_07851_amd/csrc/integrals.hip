@@ -206,27 +206,48 @@ __global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds,
     }
 }
 
+// Contraction and scatter of one class for every molecule of a call: one descriptor per
+// molecule; contraction items are primitive pairs (from `base`), scatter items candidate shell
+// pairs (from `sbase`).
+struct FockCDesc {
+    long long base, sbase;   // first contraction / scatter item of this molecule
+    long long n, nsp;        // primitive pairs of the class, candidate shell pairs of the class
+    long long sp0, cls_off;  // first candidate shell pair, offset of the class in the list
+    int nch, nbf;
+    const double *vin;
+    const int *es, *ei, *spo, *spa, *spb, *snp, *soff, *satom, *cnoff, *bfo;
+    const double *pexp, *cn, *xyz;
+    double *fprim, *F;
+};
+
+__device__ __forceinline__ int find_sdesc(const FockCDesc *__restrict__ ds, int nd, long long it) {
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (ds[mid].sbase <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // per primitive pair: F_prim[mu nu] = -c_mu_i c_nu_j sum_tuv E^{mu nu}_tuv V_tuv
 template <int LA, int LB>
-__global__ void k_fock_contract(long long n, int nch, const double *__restrict__ vin, const int *__restrict__ ent_sp,
-                                const int *__restrict__ ent_ij, const int *__restrict__ spa,
-                                const int *__restrict__ spb, const int *__restrict__ snp, const int *__restrict__ soff,
-                                const int *__restrict__ satom, const int *__restrict__ cnoff,
-                                const double *__restrict__ pexp, const double *__restrict__ cn,
-                                const double *__restrict__ xyz, double *__restrict__ fprim) {
+__global__ void k_fock_contract(const FockCDesc *__restrict__ ds, int nd, long long total) {
     constexpr int L = LA + LB, NT = ntuv(L), NC = ncart(LA) * ncart(LB);
-    long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
+    const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= total) return;
+    const FockCDesc &d = ds[find_desc(ds, nd, it)];
+    const long long q = it - d.base, n = d.n;
     double V[NT];
     for (int t = 0; t < NT; ++t) {
         double s = 0.0;
-        for (int c = 0; c < nch; ++c) s += vin[((size_t)c * NT + t) * n + q];
+        for (int c = 0; c < d.nch; ++c) s += d.vin[((size_t)c * NT + t) * n + q];
         V[t] = s;
     }
-    int sp = ent_sp[q], ij = ent_ij[q];
-    int a = spa[sp], b = spb[sp], i = ij >> 3, j = ij & 7;
-    double ea = pexp[soff[a] + i], eb = pexp[soff[b] + j], p = ea + eb;
-    const double *A = xyz + 3 * satom[a], *B = xyz + 3 * satom[b];
+    int sp = d.es[q], ij = d.ei[q];
+    int a = d.spa[sp], b = d.spb[sp], i = ij >> 3, j = ij & 7;
+    double ea = d.pexp[d.soff[a] + i], eb = d.pexp[d.soff[b] + j], p = ea + eb;
+    const double *A = d.xyz + 3 * d.satom[a], *B = d.xyz + 3 * d.satom[b];
     double P[3] = {(ea * A[0] + eb * B[0]) / p, (ea * A[1] + eb * B[1]) / p, (ea * A[2] + eb * B[2]) / p};
     Herm1D<LA, LB> ex, ey, ez;
     double inv2p = 0.5 / p;
@@ -236,7 +257,7 @@ __global__ void k_fock_contract(long long n, int nch, const double *__restrict__
     for (int mu = 0; mu < ncart(LA); ++mu) {
         int ax, ay, az;
         cart_comp(LA, mu, ax, ay, az);
-        double cmu = cn[cnoff[a] + mu * snp[a] + i];
+        double cmu = d.cn[d.cnoff[a] + mu * d.snp[a] + i];
         for (int nu = 0; nu < ncart(LB); ++nu) {
             int bx, by, bz;
             cart_comp(LB, nu, bx, by, bz);
@@ -246,7 +267,7 @@ __global__ void k_fock_contract(long long n, int nch, const double *__restrict__
                     double etu = ex.e[ax][bx][t] * ey.e[ay][by][u];
                     for (int v = 0; v <= az + bz; ++v) s += etu * ez.e[az][bz][v] * V[tuv_idx(t, u, v)];
                 }
-            fprim[(size_t)q * NC + mu * ncart(LB) + nu] = -cmu * cn[cnoff[b] + nu * snp[b] + j] * s;
+            d.fprim[(size_t)q * NC + mu * ncart(LB) + nu] = -cmu * d.cn[d.cnoff[b] + nu * d.snp[b] + j] * s;
         }
     }
 }
@@ -255,35 +276,33 @@ __global__ void k_fock_contract(long long n, int nch, const double *__restrict__
 // V and the Hermite tables in LDS, lane mu * ncart(LB) + nu writes one product.
 constexpr int FCW_WAVES = 4;
 template <int LA, int LB>
-__global__ __launch_bounds__(64 * FCW_WAVES) void k_fock_contract_w(
-    long long n, int nch, const double *__restrict__ vin, const int *__restrict__ ent_sp,
-    const int *__restrict__ ent_ij, const int *__restrict__ spa, const int *__restrict__ spb,
-    const int *__restrict__ snp, const int *__restrict__ soff, const int *__restrict__ satom,
-    const int *__restrict__ cnoff, const double *__restrict__ pexp, const double *__restrict__ cn,
-    const double *__restrict__ xyz, double *__restrict__ fprim) {
+__global__ __launch_bounds__(64 * FCW_WAVES) void k_fock_contract_w(const FockCDesc *__restrict__ ds, int nd,
+                                                                     long long total) {
     constexpr int L = LA + LB, NT = ntuv(L), TS = LA + LB + 1, ES = herm1d_size<LA, LB>();
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = NA * NB;
     static_assert(NC <= 64, "one lane per product of Cartesian components");
     __shared__ double sV[FCW_WAVES][NT];
     __shared__ double sE[FCW_WAVES][3][ES];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const long long q = (long long)blockIdx.x * FCW_WAVES + w;
-    const bool valid = q < n;
+    const long long it = (long long)blockIdx.x * FCW_WAVES + w;
+    const bool valid = it < total;
+    const FockCDesc &d = ds[valid ? find_desc(ds, nd, it) : 0];
+    const long long q = it - d.base, n = d.n;
     int a = 0, b = 0, i = 0, j = 0;
     if (valid) {
-        const int sp = ent_sp[q], ij = ent_ij[q];
-        a = spa[sp];
-        b = spb[sp];
+        const int sp = d.es[q], ij = d.ei[q];
+        a = d.spa[sp];
+        b = d.spb[sp];
         i = ij >> 3;
         j = ij & 7;
         if (lane < NT) {
             double acc = 0.0;
-            for (int c = 0; c < nch; ++c) acc += vin[((size_t)c * NT + lane) * n + q];
+            for (int c = 0; c < d.nch; ++c) acc += d.vin[((size_t)c * NT + lane) * n + q];
             sV[w][lane] = acc;
         }
         if (lane < 3) {
-            const double ea = pexp[soff[a] + i], eb = pexp[soff[b] + j], p = ea + eb;
-            const double Ad = xyz[3 * satom[a] + lane], Bd = xyz[3 * satom[b] + lane];
+            const double ea = d.pexp[d.soff[a] + i], eb = d.pexp[d.soff[b] + j], p = ea + eb;
+            const double Ad = d.xyz[3 * d.satom[a] + lane], Bd = d.xyz[3 * d.satom[b] + lane];
             const double Pd = (ea * Ad + eb * Bd) / p;
             herm1d_build_lds<LA, LB>(sE[w][lane], Pd - Ad, Pd - Bd, 0.5 / p);
         }
@@ -301,28 +320,27 @@ __global__ __launch_bounds__(64 * FCW_WAVES) void k_fock_contract_w(
             const double etu = ex[(ax * (LB + 1) + bx) * TS + t] * ey[(ay * (LB + 1) + by) * TS + u];
             for (int v = 0; v <= az + bz; ++v) s += etu * ez[(az * (LB + 1) + bz) * TS + v] * sV[w][tuv_idx(t, u, v)];
         }
-    fprim[(size_t)q * NC + lane] = -cn[cnoff[a] + mu * snp[a] + i] * cn[cnoff[b] + nu * snp[b] + j] * s;
+    d.fprim[(size_t)q * NC + lane] = -d.cn[d.cnoff[a] + mu * d.snp[a] + i] * d.cn[d.cnoff[b] + nu * d.snp[b] + j] * s;
 }
 
 // per candidate shell pair: sum its primitive pairs in list order and add the block to F
 template <int LA, int LB>
-__global__ void k_fock_scatter(long long sp0, long long nsp, long long cls_off, const int *__restrict__ spo,
-                               const int *__restrict__ spa, const int *__restrict__ spb, const int *__restrict__ bfo,
-                               const double *__restrict__ fprim, int nbf, double *__restrict__ F) {
+__global__ void k_fock_scatter(const FockCDesc *__restrict__ ds, int nd, long long total) {
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = NA * NB;
-    long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nsp) return;
-    long long sp = sp0 + s;
-    int g0 = spo[sp], g1 = spo[sp + 1];
+    const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= total) return;
+    const FockCDesc &d = ds[find_sdesc(ds, nd, it)];
+    const long long sp = d.sp0 + (it - d.sbase);
+    int g0 = d.spo[sp], g1 = d.spo[sp + 1];
     if (g0 == g1) return;
-    int a = spa[sp], b = spb[sp];
+    int a = d.spa[sp], b = d.spb[sp];
     for (int mu = 0; mu < NA; ++mu)
         for (int nu = 0; nu < NB; ++nu) {
             double acc = 0.0;
-            for (int g = g0; g < g1; ++g) acc += fprim[(size_t)(g - cls_off) * NC + mu * NB + nu];
-            long long r = bfo[a] + mu, c = bfo[b] + nu;
-            F[r * nbf + c] += acc;
-            if (a != b) F[c * nbf + r] += acc;
+            for (int g = g0; g < g1; ++g) acc += d.fprim[(size_t)(g - d.cls_off) * NC + mu * NB + nu];
+            long long r = d.bfo[a] + mu, c = d.bfo[b] + nu;
+            d.F[r * d.nbf + c] += acc;
+            if (a != b) d.F[c * d.nbf + r] += acc;
         }
 }
 
@@ -664,7 +682,58 @@ static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const s
         cls_n[cl] = (int)all.size() - cls_first[cl];
         cls_items[cl] = base;
     }
-    const FockDesc *dd = (const FockDesc *)upload_desc(ctx, all.data(), all.size() * sizeof(FockDesc));
+    // contraction / scatter descriptors of every class (one per molecule with pairs in the class)
+    std::vector<FockCDesc> cds;
+    int c_first[NCLS], c_n[NCLS];
+    long long c_items[NCLS], s_items[NCLS];
+    for (int cl = 0; cl < NCLS; ++cl) {
+        c_first[cl] = (int)cds.size();
+        long long base = 0, sbase = 0;
+        for (int i = 0; i < n; ++i) {
+            pcm_mol *mol = mols[i];
+            PairList &pl = mol->*ls;
+            const long long np = pl.cls_off[cl + 1] - pl.cls_off[cl];
+            if (!np) continue;
+            FockCDesc d{};
+            d.base = base;
+            d.sbase = sbase;
+            d.n = np;
+            d.sp0 = mol->sp_cls_off[cl];
+            d.nsp = mol->sp_cls_off[cl + 1] - d.sp0;
+            d.cls_off = pl.cls_off[cl];
+            d.nch = div_up(mol->Mpad, chunk[i][cl]);
+            d.nbf = mol->nbf;
+            d.vin = mol->vbuf.p;
+            d.es = pl.ent_sp.p + pl.cls_off[cl];
+            d.ei = pl.ent_ij.p + pl.cls_off[cl];
+            d.spo = pl.spo.p;
+            d.spa = mol->spa.p;
+            d.spb = mol->spb.p;
+            d.snp = mol->snp.p;
+            d.soff = mol->soff.p;
+            d.satom = mol->satom.p;
+            d.cnoff = mol->cnoff.p;
+            d.bfo = mol->bfo.p;
+            d.pexp = mol->pexp.p;
+            d.cn = mol->cn.p;
+            d.xyz = mol->xyz.p;
+            d.fprim = mol->fprim.p;
+            d.F = F[i];
+            base += np;
+            sbase += d.nsp;
+            cds.push_back(d);
+        }
+        c_n[cl] = (int)cds.size() - c_first[cl];
+        c_items[cl] = base;
+        s_items[cl] = sbase;
+    }
+    const size_t fb = all.size() * sizeof(FockDesc), cb = cds.size() * sizeof(FockCDesc);
+    std::vector<unsigned char> blob(fb + cb);
+    if (fb) std::memcpy(blob.data(), all.data(), fb);
+    if (cb) std::memcpy(blob.data() + fb, cds.data(), cb);
+    unsigned char *dev = (unsigned char *)upload_desc(ctx, blob.data(), blob.size());
+    const FockDesc *dd = reinterpret_cast<const FockDesc *>(dev);
+    const FockCDesc *cd = reinterpret_cast<const FockCDesc *>(dev + fb);
     for (int cl = 0; cl < NCLS; ++cl) {
         if (!cls_n[cl]) continue;
         const int L = CLS_LA[cl] + CLS_LB[cl];
@@ -675,46 +744,34 @@ static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const s
             ProfScope ps(ctx, "fock_v_L" + std::to_string(L) + (sizeof(T) == 8 ? "_f64" : "_f32"), work);
             fock_class_launch<T>(ctx, L, dd + cls_first[cl], cls_n[cl], cls_items[cl]);
         }
-        for (int i = 0; i < n; ++i) {
-            pcm_mol *mol = mols[i];
-            PairList &pl = mol->*ls;
-            const long long np = pl.cls_off[cl + 1] - pl.cls_off[cl];
-            if (!np) continue;
-            const int nch = div_up(mol->Mpad, chunk[i][cl]);
-            const int *es = pl.ent_sp.p + pl.cls_off[cl], *ei = pl.ent_ij.p + pl.cls_off[cl];
-            const long long sp0 = mol->sp_cls_off[cl], nsp = mol->sp_cls_off[cl + 1] - sp0;
-            const int g = div_up(np, 128), gs = div_up(nsp, 128);
-            ProfScope ps2(ctx, "fock_contract", (double)np);
-#define FC_CASE(CI, LA_, LB_)                                                                                       \
-    case CI:                                                                                                        \
-        k_fock_contract<LA_, LB_><<<g, 128, 0, ctx->stream>>>(np, nch, mol->vbuf.p, es, ei, mol->spa.p, mol->spb.p, \
-                                                              mol->snp.p, mol->soff.p, mol->satom.p, mol->cnoff.p,  \
-                                                              mol->pexp.p, mol->cn.p, mol->xyz.p, mol->fprim.p);    \
-        HIP_LAUNCH_OK();                                                                                            \
-        k_fock_scatter<LA_, LB_><<<gs, 128, 0, ctx->stream>>>(sp0, nsp, pl.cls_off[cl], pl.spo.p, mol->spa.p,       \
-                                                              mol->spb.p, mol->bfo.p, mol->fprim.p, mol->nbf, F[i]); \
+        const FockCDesc *cdc = cd + c_first[cl];
+        const int ncd = c_n[cl];
+        const long long np = c_items[cl], nsp = s_items[cl];
+        const int g = grid_for(np, 128), gs = grid_for(nsp, 128);
+        ProfScope ps2(ctx, "fock_contract", (double)np);
+#define FC_CASE(CI, LA_, LB_)                                                                                      \
+    case CI:                                                                                                       \
+        k_fock_contract<LA_, LB_><<<g, 128, 0, ctx->stream>>>(cdc, ncd, np);                                       \
+        HIP_LAUNCH_OK();                                                                                           \
+        k_fock_scatter<LA_, LB_><<<gs, 128, 0, ctx->stream>>>(cdc, ncd, nsp);                                      \
         break;
-#define FCW_CASE(CI, LA_, LB_)                                                                                      \
-    case CI:                                                                                                        \
-        k_fock_contract_w<LA_, LB_><<<div_up(np, FCW_WAVES), 64 * FCW_WAVES, 0, ctx->stream>>>(                      \
-            np, nch, mol->vbuf.p, es, ei, mol->spa.p, mol->spb.p, mol->snp.p, mol->soff.p, mol->satom.p, mol->cnoff.p, \
-            mol->pexp.p, mol->cn.p, mol->xyz.p, mol->fprim.p);                                                       \
-        HIP_LAUNCH_OK();                                                                                            \
-        k_fock_scatter<LA_, LB_><<<gs, 128, 0, ctx->stream>>>(sp0, nsp, pl.cls_off[cl], pl.spo.p, mol->spa.p,       \
-                                                              mol->spb.p, mol->bfo.p, mol->fprim.p, mol->nbf, F[i]); \
+#define FCW_CASE(CI, LA_, LB_)                                                                                     \
+    case CI:                                                                                                       \
+        k_fock_contract_w<LA_, LB_><<<grid_for(np, FCW_WAVES), 64 * FCW_WAVES, 0, ctx->stream>>>(cdc, ncd, np);     \
+        HIP_LAUNCH_OK();                                                                                           \
+        k_fock_scatter<LA_, LB_><<<gs, 128, 0, ctx->stream>>>(cdc, ncd, nsp);                                      \
         break;
-            switch (cl) {
-                FC_CASE(0, 0, 0)
-                FC_CASE(1, 0, 1)
-                FC_CASE(2, 0, 2)
-                FC_CASE(3, 1, 1)
-                FCW_CASE(4, 1, 2)
-                FCW_CASE(5, 2, 2)
-            }
+        switch (cl) {
+            FC_CASE(0, 0, 0)
+            FC_CASE(1, 0, 1)
+            FC_CASE(2, 0, 2)
+            FC_CASE(3, 1, 1)
+            FCW_CASE(4, 1, 2)
+            FCW_CASE(5, 2, 2)
+        }
 #undef FC_CASE
 #undef FCW_CASE
-            HIP_LAUNCH_OK();
-        }
+        HIP_LAUNCH_OK();
     }
 }
 
