@@ -391,7 +391,7 @@ int autotune_pick(pcm_ctx *ctx, const std::string &key, const std::vector<int> &
 // Chunk shapes: a (molecule, class) is split into about `target` items (point tiles x pair
 // chunks for esp, pair tiles x point chunks for Fock).
 constexpr int TARGET_DEFAULT = 4096;
-static const std::vector<int> TARGETS{4096, 1024, 2048, 8192};
+static const std::vector<int> TARGETS{4096, 1024, 2048, 8192, 16384, 32768};
 
 static int esp_chunk_len(long long n_pairs, int M, int target) {
     int tiles = M > 0 ? div_up(M, 256) : 1;
