@@ -82,16 +82,18 @@ __global__ __launch_bounds__(256) void k_grad_v(const unsigned char *__restrict_
     double V[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) V[t] = 0.0;
-    for (int k = k0; k < k1; k += PT_BATCH) {
-        PtInt<T> pt[PT_BATCH];
-        double qk[PT_BATCH];
+    // points per batch: fewer for the larger V' sets so that more waves stay resident
+    constexpr int PB = L <= 1 ? PT_BATCH : (L == 2 ? 2 : 1);
+    for (int k = k0; k < k1; k += PB) {
+        PtInt<T> pt[PB];
+        double qk[PB];
 #pragma unroll
-        for (int b = 0; b < PT_BATCH; ++b) {
+        for (int b = 0; b < PB; ++b) {
             pt[b] = pts[k + b];
             qk[b] = q[k + b];
         }
 #pragma unroll
-        for (int b = 0; b < PT_BATCH; ++b) {
+        for (int b = 0; b < PB; ++b) {
             T R[NT];
             eval_R<L + 1, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta, pt[b].lim,
                              tab, R);
