@@ -26,13 +26,17 @@ sparse seeded perturbation dP_t, the threshold tightening as delta_t = 10^(-3 - 
 (the Eq. 21 range), each solve warm-started from the previous q; unpreconditioned and RBJ
 with blocks of 1,024 points, FP64 and mixed (FP32 matvec in FP64 refinement).
 
+One GPU's share of the sharded matvec (--workload shard8): the 2,000-atom solute's product split
+over 8 ranks as a multi-GPU solve would split it; each rank's kernel time at its real shape,
+the balance, and the reduce-scatter volume per CG iteration.
+
 Studies (--workload scf_policies, eq21_fit): the synthetic analogues of the solver-policy
 and threshold experiments of Sec. 4b (CG steps per SCF iteration under fixed, 2-delta and
 dynamic thresholds; RBJ against the octree partition over seeds; the power-law fit of the
 energy error against the CG threshold).  They print one JSON line each, with the counts.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
-                       [--workload protein600|conformers64|stress2000|scf_policies|eq21_fit]
+                       [--workload protein600|conformers64|stress2000|scf_policies|eq21_fit|shard8]
 """
 from __future__ import annotations
 
@@ -115,7 +119,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--block", type=int, default=100)
     ap.add_argument("--workload", default="protein600",
-                    choices=["protein600", "conformers64", "stress2000", "scf_policies", "eq21_fit", "copy"],
+                    choices=["protein600", "conformers64", "stress2000", "scf_policies", "eq21_fit", "shard8", "copy"],
                     help="copy: a plain device copy of known size, to calibrate rocprofv3 byte counters")
     ap.add_argument("--max-iter-none", type=int, default=300,
                     help="stress2000: matvec budget of each unpreconditioned outer solve")
@@ -137,6 +141,8 @@ def main():
         return bench_scf_policies(args)
     if args.workload == "eq21_fit":
         return bench_eq21_fit(args)
+    if args.workload == "shard8":
+        return bench_shard(args)
 
     import numpy as np
     import torch
@@ -678,6 +684,63 @@ def bench_eq21_fit(args):
                             "below_eq21_all": bool(np.all(np.max(e_rows, axis=0) <= bound))},
            "fock_error_max": {"mean": f_mean.tolist(), "fit": fit(f_mean)},
            "eq21": {"a": 0.01, "b": 1.07}}
+    print(json.dumps(out))
+
+
+def bench_shard(args):
+    """Sec. 5 / Table 3 scale-out, one GPU's part: the FP64 product of the 2,000-atom solute
+    (M ~ 150k) computed whole and as the 8 shares of an 8-GPU run (tile pairs dealt out round
+    robin), each share timed on this GPU at its real shape; the shares must add up to A x."""
+    import numpy as np
+    import torch
+
+    from paper_1505_07851_amd import Context, Molecule
+    from synth import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    s = I.linear_solve_stress()
+    ctx = Context(precision="fp64")
+    mol = Molecule.from_system(ctx, s)
+    rng = np.random.default_rng(s.seeds["pert"])
+    x = torch.tensor(rng.normal(size=mol.M), dtype=torch.float64, device="cuda")
+    n_ranks = 8
+    mol.matvec_share(x, 0, 1)
+    mol.matvec_share(x, 0, n_ranks)
+    torch.cuda.synchronize()
+
+    def timed_share(r, n):
+        ms = []
+        for _ in range(max(args.steps, 1)):
+            ctx.profile(True)
+            y = mol.matvec_share(x, r, n)
+            prof = ctx.profile_read()
+            ctx.profile(False)
+            ms.append(prof["matvec_share_f64"]["ms"] if "matvec_share_f64" in prof else 0.0)
+            work = prof["matvec_share_f64"]["work"] if "matvec_share_f64" in prof else 0.0
+        return min(ms), work, y
+
+    full_ms, full_pairs, y_full = timed_share(0, 1)
+    shares = [timed_share(r, n_ranks) for r in range(n_ranks)]
+    y_sum = sum(sh[2] for sh in shares)
+    rel = ((y_sum - y_full).norm() / y_full.norm()).item()
+    per = [sh[0] for sh in shares]
+    log(f"[bench] shard8: full product {full_ms:.3f} ms; shares {['%.3f' % t for t in per]} ms; "
+        f"sum of shares vs whole {rel:.1e}")
+    flops = 14.0 * full_pairs
+    rs_bytes = mol.M * 8 * (n_ranks - 1) / n_ranks
+    out = {"metric": "one rank's share of the FP64 product, 8-way sharded (ms per CG iteration)",
+           "value": max(per), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+           "ms_per_step": max(per), "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "protein2000_631gs_matvec_shard8", "atoms": s.n_atoms, "surface_points": mol.M,
+                      "ranks": n_ranks, "tile": 256},
+           "whole_product_ms": full_ms, "whole_product_tflops": flops / (full_ms * 1e-3) / 1e12,
+           "share_ms": per, "share_max_over_mean": max(per) / (sum(per) / len(per)),
+           "speedup_whole_over_max_share": full_ms / max(per),
+           "sum_of_shares_rel_err": rel,
+           "reduce_scatter_bytes_per_rank_per_iteration": rs_bytes,
+           "reduce_scatter_us_at_153GBps": rs_bytes / 153e9 * 1e6}
     print(json.dumps(out))
 
 

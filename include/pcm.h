@@ -190,6 +190,15 @@ pcm_status pcm_solve(pcm_ctx *ctx, pcm_mol *mol, const double *v, const pcm_solv
  * HOST: *E. */
 pcm_status pcm_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double *c, const double *q, double *E);
 
+/* One rank's share of the product y = A x (Sec. 2, Eqs. 2-3, 8), the per-GPU work of the
+ * sharded matvec: A is split into 256 x 256 tile pairs (I, J >= I) taken in the order
+ * I = 0.., J = I..; rank r of nranks evaluates the pairs at positions p with p mod nranks = r
+ * (each unordered point pair once, feeding both its row and its column) and adds A_kk x_k on
+ * the rows of the diagonal tile pairs it owns.  Summing y over ranks 0 .. nranks-1 gives A x,
+ * which is the reduce-scatter a multi-GPU solve would perform.  DEVICE: x[M], y[M] (written).
+ * Errors: PCM_E_ARG (NULL, nranks < 1, rank outside [0, nranks)). */
+pcm_status pcm_matvec_share(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int rank, int nranks);
+
 /* Gradient of the Eq. 13 energy at fixed density (Sec. 2, Eq. 14; Sec. 4c, Eq. 22) for a
  * solved q.  Primitive pairs are screened as in pcm_esp (Eq. 18).  DEVICE: P[nbf*nbf],
  * q[M]; outputs g_nuc[n_atoms*3] (derivative with respect to nuclear positions with the

@@ -227,6 +227,14 @@ class Molecule:
                                                _dp(q.contiguous()), ctypes.byref(E)))
         return E.value
 
+    def matvec_share(self, x, rank=0, nranks=1, y=None):
+        """One rank's share of A x in the sharded matvec (tile pairs at positions = rank mod
+        nranks); the shares of all ranks add up to A x."""
+        x = _f64(x, self.M, "x").contiguous()
+        y = self._zeros(self.M) if y is None else y
+        self.ctx.check(self.ctx.lib.pcm_matvec_share(self.ctx.h, self.h, _dp(x), _dp(y), int(rank), int(nranks)))
+        return y
+
     def grad(self, P, q):
         """(g_nuc [N,3], g_surf [M,3]) of Eq. 14 at fixed density."""
         P = _f64(P, self.nbf * self.nbf, "P").contiguous()

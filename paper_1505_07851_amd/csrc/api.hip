@@ -398,6 +398,18 @@ pcm_status pcm_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double
     });
 }
 
+pcm_status pcm_matvec_share(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int rank, int nranks) {
+    if (!ctx) return PCM_E_ARG;
+    if (!mol || !x || !y) return fail(ctx, PCM_E_ARG, "NULL argument");
+    if (nranks < 1 || rank < 0 || rank >= nranks) return fail(ctx, PCM_E_ARG, "rank outside [0, nranks)");
+    return guarded(ctx, [&]() -> pcm_status {
+        ctx_ensure_device(ctx);
+        run_matvec_share(ctx, mol, x, y, rank, nranks);
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        return PCM_OK;
+    });
+}
+
 pcm_status pcm_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc, double *g_surf) {
     if (!ctx) return PCM_E_ARG;
     if (!mol || !P || !q || !g_nuc || !g_surf) return fail(ctx, PCM_E_ARG, "NULL argument");

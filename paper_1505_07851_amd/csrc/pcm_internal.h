@@ -451,6 +451,7 @@ void run_fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std:
 pcm_status run_solve(pcm_ctx *ctx, pcm_mol *mol, const double *v, const pcm_solve_opts &o, double *q,
                      pcm_solve_info *info);
 double run_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double *c, const double *q);
+void run_matvec_share(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int rank, int nranks);
 void run_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc, double *g_surf,
               int prec);
 void surface_points(pcm_ctx *ctx, pcm_mol *mol, const double *r_explicit_dev);

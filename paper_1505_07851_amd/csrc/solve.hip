@@ -546,6 +546,7 @@ struct SolveBatch {
     DevBuf<MvItem> mv;
     DevBuf<TileItem> tiles;
     DevBuf<RbjItem> rbj;
+    DevBuf<MvItem> share;  // tile pairs of one rank's share of the product
     DevBuf<double> part, dp;
     DevBuf<const double *> ext;
     DevBuf<int> cnt;
@@ -1033,6 +1034,57 @@ static SolveBatch &solo(pcm_mol *mol) {
 pcm_status run_solve(pcm_ctx *ctx, pcm_mol *mol, const double *vin, const pcm_solve_opts &o, double *q,
                      pcm_solve_info *info) {
     return solve_batch_run(ctx, solo(mol), {vin}, {q}, o, info);
+}
+
+// ----------------------------------------------------------------------------------------
+// One rank's share of the product, the per-GPU kernel of the sharded matvec: the tile pairs
+// (I, J >= I) whose position in the item order is rank mod nranks, plus A_kk x_k on the rows
+// of the diagonal tile pairs it owns.  The shares of ranks 0 .. nranks-1 add up to A x.
+// ----------------------------------------------------------------------------------------
+__global__ __launch_bounds__(TILE) void k_share_finish(const CGMol *__restrict__ tab, int rank, int nranks, int src,
+                                                       double *__restrict__ y) {
+    const CGMol &m = tab[0];
+    const int t = blockIdx.x, k = t * TILE + threadIdx.x;
+    if (k >= m.M) return;
+    double acc = 0.0;
+    for (int r = 0; r < m.nT; ++r) acc += m.part[(size_t)r * m.M + k];
+    const long long diag_item = (long long)t * m.nT - (long long)t * (t - 1) / 2;  // position of (t, t)
+    if (diag_item % nranks == rank) acc += m.Akk[k] * m.v[src][k];
+    y[k] = acc;
+}
+
+void run_matvec_share(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int rank, int nranks) {
+    SolveBatch &B = solo(mol);
+    solver_prepare(ctx, mol);
+    if (B.n_tiles == 0) batch_tables(ctx, B, PCM_PRECOND_NONE);
+    set_all(B, 1, 0.0, 0);
+    upload_states(ctx, B);
+    std::vector<const double *> e_x{x};
+    vec_op(ctx, B, 0, 0.0, 0, V_T, &e_x);
+    const int nT = B.h_tab[0].nT, M = mol->M;
+    std::vector<MvItem> items;
+    long long pairs = 0;
+    int idx = 0;
+    for (int I = 0; I < nT; ++I)
+        for (int J = I; J < nT; ++J, ++idx)
+            if (idx % nranks == rank) {
+                items.push_back(MvItem{0, I, J});
+                const long long rI = std::min(TILE, M - I * TILE), rJ = std::min(TILE, M - J * TILE);
+                pairs += I == J ? rI * (rI - 1) / 2 : rI * rJ;
+            }
+    B.share.ensure(std::max<size_t>(items.size(), 1));
+    if (!items.empty())
+        HIP_OK(hipMemcpyAsync(B.share.p, items.data(), items.size() * sizeof(MvItem), hipMemcpyHostToDevice,
+                              ctx->stream));
+    HIP_OK(hipMemsetAsync(B.part.p, 0, sizeof(double) * (size_t)nT * M, ctx->stream));
+    if (!items.empty()) {
+        ProfScope ps(ctx, "matvec_share_f64", (double)pairs);
+        k_mv_sym<double><<<(int)items.size(), MV_THREADS, 0, ctx->stream>>>(B.tab.p, B.st.p, B.share.p,
+                                                                             (int)items.size(), 1, V_T);
+        HIP_LAUNCH_OK();
+    }
+    k_share_finish<<<nT, TILE, 0, ctx->stream>>>(B.tab.p, rank, nranks, V_T, y);
+    HIP_LAUNCH_OK();
 }
 
 // E = bz.q + c.q + q.Aq / (2f)  (Eq. 13)

@@ -226,3 +226,15 @@ def test_threshold_policy_bad_arguments(L):
     L.pcm_default_threshold_policy(ctypes.byref(p), _lib.PCM_THRESH_FIXED)
     p.delta = -1.0
     assert L.pcm_cg_threshold(ctypes.byref(p), 1.0) == -1.0
+
+
+def test_matvec_share_bad_arguments(L):
+    from paper_1505_07851_amd import _lib
+    ctx = ctypes.c_void_p()
+    assert L.pcm_create(None, None, ctypes.byref(ctx)) == _lib.PCM_OK
+    x = np.zeros(4)
+    fake_mol = ctypes.c_void_p(1)  # never dereferenced: the arguments are rejected first
+    assert L.pcm_matvec_share(ctx, None, _hp(x), _hp(x), 0, 1) == _lib.PCM_E_ARG
+    for rank, nranks in [(0, 0), (-1, 2), (2, 2)]:
+        assert L.pcm_matvec_share(ctx, fake_mol, _hp(x), _hp(x), rank, nranks) == _lib.PCM_E_ARG
+    L.pcm_destroy(ctx)

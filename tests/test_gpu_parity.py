@@ -182,3 +182,16 @@ def test_mixed_integrals_error_statement(case, torch_cuda):
     assert err["E_abs"] <= 1e-6
     assert err["q_rel_max"] <= 1e-3
     assert err["g_nuc_abs"] <= 1e-5 and err["g_surf_abs"] <= 1e-5
+
+
+def test_matvec_shares_add_up(case, torch_cuda):
+    """The per-rank shares of the sharded product add up to A x (dense oracle A), for rank counts
+    below, at and above the number of tile pairs."""
+    mol, ref = case["mol"], case["ref"]
+    rng = np.random.default_rng(23)
+    xh = rng.normal(size=mol.M)
+    x = torch_cuda.tensor(xh, dtype=torch_cuda.float64, device="cuda")
+    Ax = ref["A"] @ xh
+    for nranks in (1, 2, 3, 7, 40):
+        y = sum(mol.matvec_share(x, r, nranks).cpu().numpy() for r in range(nranks))
+        assert rel(y, Ax) <= 1e-12, nranks
