@@ -53,6 +53,8 @@ struct CGMol {
     const int *perm, *boff;   // RBJ partition (null without RBJ)
     const long long *ioff;
     const double *inv;
+    const double *boys64;     // Boys tables (near-field A_kl)
+    const float *boys32;
     double rc2_64;
     float rc2_32;
     int M, Mp, nT, ndp, n_rz, precond;
@@ -81,17 +83,29 @@ struct RbjItem {
 // ----------------------------------------------------------------------------------------
 // device helpers
 // ----------------------------------------------------------------------------------------
-__device__ __forceinline__ double erf_t(double x) { return erf(x); }
-__device__ __forceinline__ float erf_t(float x) { return erff(x); }
-
-// A_kl inside the cutoff radius (erf not yet 1): coincident points take 2 z'/sqrt(pi)
+// A_kl inside the cutoff radius, from the Boys table: erf(z' r)/r = (2/sqrt(pi)) z' F_0(z'^2 r^2)
+// (Eq. 3 with F_0(T) = sqrt(pi) erf(sqrt T) / (2 sqrt T)), F_0 by its Taylor series about the
+// nearest table node (order 8 in FP64, 4 in FP32; nodes 1/8 apart).  Past z'^2 r^2 = MV_TCUT
+// erf has rounded to 1 and A_kl = 1/r = ri.  Coincident points (T = 0) take 2 z'/sqrt(pi).
+template <typename T> struct MvCut;
+template <> struct MvCut<double> { static constexpr double T_CUT = 36.0; };  // erfc(6) < 3e-17
+template <> struct MvCut<float> { static constexpr float T_CUT = 16.0f; };   // erfc(4) < 2e-8
 template <typename T>
-__device__ __attribute__((noinline)) T mv_near(T zk, T zl, T r2, bool self) {
+__device__ __attribute__((noinline)) T mv_near(T zk, T zl, T r2, T ri, bool self, const T *__restrict__ tab) {
+    using C = BoysCfg<T>;
     if (self) return T(0);
-    T zp = zk * zl * rsqrt_t(zk * zk + zl * zl);
-    if (r2 == T(0)) return T(1.1283791670955125739) * zp;
-    T r = sqrt_t(r2);
-    return erf_t(zp * r) / r;
+    const T zp = zk * zl * rsq_fast(fma(zk, zk, zl * zl));
+    const T tb = zp * zp * r2;
+    if (tb >= MvCut<T>::T_CUT) return ri;
+    int i = (int)(tb * T(8) + T(0.5));
+    i = i < C::NROW - 1 ? i : C::NROW - 1;
+    const T d = T(i) * T(0.125) - tb;
+    const T *row = tab + i * C::MT;
+    // sum_k F_k(T_i) d^k / k!, nested: F_0 + d (F_1 + d/2 (F_2 + d/3 (...)))
+    T F = row[C::ORD];
+#pragma unroll
+    for (int k = C::ORD; k >= 1; --k) F = fma(F, d * (T(1) / T(k)), row[k - 1]);
+    return T(1.1283791670955125739) * zp * F;
 }
 
 template <typename T> __device__ __forceinline__ const Pt<T> *mv_pts(const CGMol &m);
@@ -103,6 +117,9 @@ template <> __device__ __forceinline__ const float *mv_src<float>(const CGMol &m
 template <typename T> __device__ __forceinline__ T mv_rc2(const CGMol &m);
 template <> __device__ __forceinline__ double mv_rc2<double>(const CGMol &m) { return m.rc2_64; }
 template <> __device__ __forceinline__ float mv_rc2<float>(const CGMol &m) { return m.rc2_32; }
+template <typename T> __device__ __forceinline__ const T *mv_boys(const CGMol &m);
+template <> __device__ __forceinline__ const double *mv_boys<double>(const CGMol &m) { return m.boys64; }
+template <> __device__ __forceinline__ const float *mv_boys<float>(const CGMol &m) { return m.boys32; }
 
 // gate 0: skip molecules whose PCG is done; gate 1: skip molecules not active in this call
 __device__ __forceinline__ bool skip(const CGState &s, int gate) { return gate ? !s.act : s.done; }
@@ -172,6 +189,7 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_sym(const CGMol *__restrict__
         const Pt<T> *__restrict__ pts = mv_pts<T>(m);
         const T *__restrict__ xv = mv_src<T>(m, src);
         const T rc2 = mv_rc2<T>(m);
+        const T *__restrict__ boys = mv_boys<T>(m);
         const int r0 = w.I * TILE + wv * (8 * MV_R) + i, c0 = w.J * TILE;
         const bool diag = w.I == w.J;
         if (threadIdx.x < TILE) {
@@ -197,7 +215,7 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_sym(const CGMol *__restrict__
                 const T dx = rp[a].x - cp.x, dy = rp[a].y - cp.y, dz = rp[a].z - cp.z;
                 const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
                 T A = rsq_fast(r2);
-                if (r2 < rc2) A = mv_near<T>(rp[a].zeta, cp.zeta, r2, diag && r0 + 8 * a == c0 + cl);
+                if (r2 < rc2) A = mv_near<T>(rp[a].zeta, cp.zeta, r2, A, diag && r0 + 8 * a == c0 + cl, boys);
                 racc[a] = fma(A, xc, racc[a]);
                 cacc = fma(A, rx[a], cacc);
             }
@@ -650,6 +668,9 @@ static void batch_tables(pcm_ctx *ctx, SolveBatch &B, int precond) {
             m.ioff = mol->rbj_ioff.p;
             m.inv = mol->rbj_inv.p;
         }
+        if (!ctx->boys64.p || !ctx->boys32.p) throw PcmError{PCM_E_STATE, "Boys tables not initialised"};
+        m.boys64 = ctx->boys64.p;
+        m.boys32 = ctx->boys32.p;
         double r32;
         mv_cutoffs(mol, m.rc2_64, r32);
         m.rc2_32 = (float)r32;
