@@ -86,3 +86,43 @@ def test_preconditioner_switch_keeps_results(torch_cuda):
         assert abs(iters - it) <= 2, (kind, block, iters, it)
     perm, off = octree_partition(om.r, 200)
     assert np.diff(off).max() <= 200
+
+
+def test_coincident_surface_points(torch_cuda):
+    """Two distinct surface points at the same position take the r -> 0 limit 2 z'/sqrt(pi) of
+    Eq. 2 in the products (FP64 and FP32 near field), in a diagonal tile and across tiles;
+    the product and the mixed-precision solve against the oracle at the same points."""
+    from paper_1505_07851_amd import Context, Molecule
+    torch = torch_cuda
+    print("\n[case coincident points: small_protein(30, 50, seed=7)]", flush=True)
+    s = I.small_protein(30, 50, seed=7)
+    ctx = Context()
+    mol = Molecule.from_system(ctx, s)
+    M = mol.M
+    assert M > 2 * 256
+    sf = mol.surface()
+    r = sf["r"].cpu().numpy().copy()
+    own = sf["owner"].cpu().numpy()
+    # each moved point lands on a point of another atom, inside that atom's switching zone, so
+    # S_k drops to about 1/2 and A stays positive definite
+    a = int(np.nonzero(own != own[0])[0][0])
+    b = 256 + int(np.nonzero(own[256:] != own[300])[0][0])
+    assert a < 256 and own[M - 1] != own[0] and b != 300
+    r[a] = r[0]            # first (diagonal) tile
+    r[M - 1] = r[0]        # last (ragged) tile against the first
+    r[300] = r[b]          # second tile
+    om = O.mol_from_system(s, r_override=r)
+    mol.update_geometry(s.xyz, r)
+    x = np.random.default_rng(31).normal(size=M)
+    y_ref = om.matvec(x)
+    xt = torch.tensor(x, dtype=torch.float64, device="cuda")
+    for n in (1, 3):
+        y = sum(mol.matvec_share(xt, rk, n) for rk in range(n)).cpu().numpy()
+        assert np.abs(y - y_ref).max() <= 1e-12 * np.abs(y_ref).max(), n
+    ref = O.full_solution(om, s.P)
+    P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
+    c, bz = mol.esp(P)
+    for prec, tol_q in (("fp64", 1e-8), ("mixed", 1e-6)):
+        q, info = mol.solve(bz + c, precond="rbj", block=64, seed=3, tol=1e-10, precision=prec)
+        assert np.abs(q.cpu().numpy() - ref["q"]).max() <= tol_q * np.abs(ref["q"]).max(), prec
+        assert abs(info["energy"] - ref["E"]) <= 1e-7 * abs(ref["E"]), prec
