@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <type_traits>
 
 constexpr int TILE = 256;  // points per tile (rows per workgroup)
 constexpr int GROUP_K = 8; // PCG iterations per launch group (even: scalar slots alternate)
@@ -53,6 +54,7 @@ struct CGMol {
     const int *perm, *boff;   // RBJ partition (null without RBJ)
     const long long *ioff;
     const double *inv;
+    const double *tbox;       // [nT][6] bounding box of each tile's points: min x, y, z, max x, y, z
     const double *boys64;     // Boys tables (near-field A_kl)
     const float *boys32;
     double rc2_64;
@@ -205,25 +207,53 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_sym(const CGMol *__restrict__
             racc[a] = T(0);
         }
         __syncthreads();
-        for (int b = 0; b < TILE / 8; ++b) {
-            const int cl = 8 * b + j;
-            const Pt<T> cp = cpt[cl];
-            const T xc = cx[cl];
-            T cacc = T(0);
+        // A tile pair whose boxes are farther apart than the cutoff has no near pair: its loop
+        // skips the per-pair test.  The diagonal pair (self term, padding dummies) always tests.
+        // FP32 keeps the single tested loop: a second copy costs it a wave per SIMD.
+        bool near_item = diag || sizeof(T) == 4;
+        if (!near_item) {
+            const double *bi = m.tbox + 6 * w.I, *bj = m.tbox + 6 * w.J;
+            double g2 = 0.0;
 #pragma unroll
-            for (int a = 0; a < MV_R; ++a) {
-                const T dx = rp[a].x - cp.x, dy = rp[a].y - cp.y, dz = rp[a].z - cp.z;
-                const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                T A = rsq_fast(r2);
-                if (r2 < rc2) A = mv_near<T>(rp[a].zeta, cp.zeta, r2, A, diag && r0 + 8 * a == c0 + cl, boys);
-                racc[a] = fma(A, xc, racc[a]);
-                cacc = fma(A, rx[a], cacc);
+            for (int c = 0; c < 3; ++c) {
+                const double g = fmax(fmax(bj[c] - bi[c + 3], bi[c] - bj[c + 3]), 0.0);
+                g2 = fma(g, g, g2);
             }
-            if (!diag) {
-                cacc += dpp<DPP_ROW_ROR8>(cacc);  // i bit 0 (lane bit 3)
-                cacc += swz16(cacc);               // i bit 1 (lane bit 4)
-                if ((lane & 24) == 0) colbuf[wv * 2 + (lane >> 5)][cl] = cacc;
+            near_item = g2 < 1.01 * (double)rc2 + 1e-3;
+        }
+        auto jloop = [&](auto near_c) {
+            constexpr bool NEAR = decltype(near_c)::value;
+            for (int b = 0; b < TILE / 8; ++b) {
+                const int cl = 8 * b + j;
+                const Pt<T> cp = cpt[cl];
+                const T xc = cx[cl];
+                T cacc = T(0);
+#pragma unroll
+                for (int a = 0; a < MV_R; ++a) {
+                    const T dx = rp[a].x - cp.x, dy = rp[a].y - cp.y, dz = rp[a].z - cp.z;
+                    const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    T A = rsq_fast(r2);
+                    if constexpr (NEAR) {
+                        if (r2 < rc2)
+                            A = mv_near<T>(rp[a].zeta, cp.zeta, r2, A, diag && r0 + 8 * a == c0 + cl, boys);
+                    }
+                    racc[a] = fma(A, xc, racc[a]);
+                    cacc = fma(A, rx[a], cacc);
+                }
+                if (!diag) {
+                    cacc += dpp<DPP_ROW_ROR8>(cacc);  // i bit 0 (lane bit 3)
+                    cacc += swz16(cacc);               // i bit 1 (lane bit 4)
+                    if ((lane & 24) == 0) colbuf[wv * 2 + (lane >> 5)][cl] = cacc;
+                }
             }
+        };
+        if constexpr (sizeof(T) == 4) {
+            jloop(std::true_type{});
+        } else {
+            if (__builtin_amdgcn_readfirstlane((int)near_item))
+                jloop(std::true_type{});
+            else
+                jloop(std::false_type{});
         }
         // row sums over j (lane bits 0-2): quad pairs, quads, half rows
 #pragma unroll
@@ -498,12 +528,38 @@ __global__ void k_pack_pts(const double *__restrict__ px, const double *__restri
     }
 }
 
+// bounding box of each tile's real points (block = tile); an empty tail tile gets an empty box
+__global__ __launch_bounds__(TILE) void k_tile_box(const Pt<double> *__restrict__ p64, int M, double *__restrict__ tbox) {
+    __shared__ double red[6][TILE];
+    const int k = blockIdx.x * TILE + threadIdx.x;
+    const bool in = k < M;
+    const Pt<double> p = p64[in ? k : 0];
+    red[0][threadIdx.x] = in ? p.x : 1e300;
+    red[1][threadIdx.x] = in ? p.y : 1e300;
+    red[2][threadIdx.x] = in ? p.z : 1e300;
+    red[3][threadIdx.x] = in ? p.x : -1e300;
+    red[4][threadIdx.x] = in ? p.y : -1e300;
+    red[5][threadIdx.x] = in ? p.z : -1e300;
+    __syncthreads();
+    for (int o = TILE / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                red[c][threadIdx.x] = fmin(red[c][threadIdx.x], red[c][threadIdx.x + o]);
+                red[c + 3][threadIdx.x] = fmax(red[c + 3][threadIdx.x], red[c + 3][threadIdx.x + o]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) tbox[6 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
 // ----------------------------------------------------------------------------------------
 // host side
 // ----------------------------------------------------------------------------------------
 // per-molecule solver storage inside mol->sv (offsets in doubles)
 struct SvLayout {
-    size_t vec[NVEC], p32, pt64, pt32, total;
+    size_t vec[NVEC], p32, pt64, pt32, tbox, total;
 };
 
 static SvLayout sv_layout(int M) {
@@ -517,6 +573,8 @@ static SvLayout sv_layout(int M) {
     o += 4 * Mp;
     L.pt32 = o;
     o += 2 * Mp;
+    L.tbox = o;
+    o += 6 * (Mp / TILE);
     L.total = o;
     return L;
 }
@@ -545,6 +603,11 @@ static void solver_prepare(pcm_ctx *ctx, pcm_mol *mol) {
         mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p, mol->M, Mp,
         reinterpret_cast<Pt<double> *>(mol->sv.p + L.pt64), reinterpret_cast<Pt<float> *>(mol->sv.p + L.pt32));
     HIP_LAUNCH_OK();
+    if (Mp > 0) {
+        k_tile_box<<<Mp / TILE, TILE, 0, ctx->stream>>>(reinterpret_cast<const Pt<double> *>(mol->sv.p + L.pt64),
+                                                        mol->M, mol->sv.p + L.tbox);
+        HIP_LAUNCH_OK();
+    }
 }
 
 struct GraphSig {
@@ -659,6 +722,7 @@ static void batch_tables(pcm_ctx *ctx, SolveBatch &B, int precond) {
         m.p32 = reinterpret_cast<float *>(mol->sv.p + L.p32);
         m.pt64 = reinterpret_cast<const Pt<double> *>(mol->sv.p + L.pt64);
         m.pt32 = reinterpret_cast<const Pt<float> *>(mol->sv.p + L.pt32);
+        m.tbox = mol->sv.p + L.tbox;
         m.Akk = mol->Akk.p;
         m.part = B.part.p + B.part_off[i];
         m.dp = B.dp.p + B.dp_off[i];
