@@ -43,16 +43,25 @@ __global__ __launch_bounds__(256) void k_grad_pts(const unsigned char *__restric
         for (int b = 0; b < PB; ++b) {
             T R[ntuv(L + 1)];
             eval_R<L + 1, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab, R);
-            T sx = T(0), sy = T(0), sz = T(0);
+            if constexpr (sizeof(T) == 8) {  // FP64: straight into the accumulators
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                sx = fma(D[b][t], R[TuvShift<L>::x(t)], sx);
-                sy = fma(D[b][t], R[TuvShift<L>::y(t)], sy);
-                sz = fma(D[b][t], R[TuvShift<L>::z(t)], sz);
+                for (int t = 0; t < NT; ++t) {
+                    gx = fma(D[b][t], R[TuvShift<L>::x(t)], gx);
+                    gy = fma(D[b][t], R[TuvShift<L>::y(t)], gy);
+                    gz = fma(D[b][t], R[TuvShift<L>::z(t)], gz);
+                }
+            } else {  // FP32 evaluation, one FP64 add per pair
+                T sx = T(0), sy = T(0), sz = T(0);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    sx = fma(D[b][t], R[TuvShift<L>::x(t)], sx);
+                    sy = fma(D[b][t], R[TuvShift<L>::y(t)], sy);
+                    sz = fma(D[b][t], R[TuvShift<L>::z(t)], sz);
+                }
+                gx += (double)sx;
+                gy += (double)sy;
+                gz += (double)sz;
             }
-            gx += (double)sx;
-            gy += (double)sy;
-            gz += (double)sz;
         }
     }
     if (k < M) {

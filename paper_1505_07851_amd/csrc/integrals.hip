@@ -104,10 +104,15 @@ __global__ __launch_bounds__(256) void k_esp(const EspDesc *__restrict__ ds, int
                 T R[NT];
                 eval_R<L, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
                              R);
-                T s = T(0);
+                if constexpr (sizeof(T) == 8) {  // FP64: straight into the accumulator
 #pragma unroll
-                for (int t = 0; t < NT; ++t) s = fma(D[b][t], R[t], s);
-                acc += (double)s;
+                    for (int t = 0; t < NT; ++t) acc = fma(D[b][t], R[t], acc);
+                } else {  // FP32 evaluation, one FP64 add per pair
+                    T s = T(0);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) s = fma(D[b][t], R[t], s);
+                    acc += (double)s;
+                }
             }
         }
         if (k < M) d.part[(size_t)(d.row0 + ch) * M + k] = acc;
