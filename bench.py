@@ -486,6 +486,13 @@ def bench_conformers(args):
     b64 = Batch(ctx64, mols64)
     ms_b64, r_b64 = timed(lambda: batch_step(b64, "fp64"))
     log(f"[bench] batched FP64: {ms_b64:.1f} ms per step")
+    # Eq. 14 gradient of every conformer at its solved q: 64 pcm_grad calls against one
+    # pcm_grad_batched (not part of the step above)
+    qs64 = [r[0] for r in r_b64]
+    ms_gseq, g_seq = timed(lambda: [m.grad(P, q) for m, P, q in zip(mols64, Ps, qs64)])
+    ms_gb, g_b = timed(lambda: b64.grad(Ps, qs64))
+    g_bitwise = all(torch.equal(a[0], c[0]) and torch.equal(a[1], c[1]) for a, c in zip(g_seq, g_b))
+    log(f"[bench] gradient FP64: sequential {ms_gseq:.1f} ms, batched {ms_gb:.1f} ms, bitwise equal {g_bitwise}")
     ctxm, molsm = setup("mixed")
     bm = Batch(ctxm, molsm)
     ms_bm, r_bm = timed(lambda: batch_step(bm, "mixed"))
@@ -511,7 +518,9 @@ def bench_conformers(args):
            "batched_fp64": {"ms_per_step": round(ms_b64, 3), "ms_per_conformer": round(ms_b64 / n_conf, 3),
                             "speedup_vs_sequential": round(ms_seq / ms_b64, 3), "err_vs_sequential": errs(r_b64)},
            "batched_mixed": {"ms_per_step": round(ms_bm, 3), "ms_per_conformer": round(ms_bm / n_conf, 3),
-                             "speedup_vs_sequential": round(ms_seq / ms_bm, 3), "err_vs_sequential": errs(r_bm)}}
+                             "speedup_vs_sequential": round(ms_seq / ms_bm, 3), "err_vs_sequential": errs(r_bm)},
+           "gradient_fp64": {"sequential_ms": round(ms_gseq, 3), "batched_ms": round(ms_gb, 3),
+                             "speedup": round(ms_gseq / ms_gb, 3), "bitwise_equal": g_bitwise}}
     print(json.dumps(out))
 
 

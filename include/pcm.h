@@ -302,6 +302,15 @@ pcm_status pcm_fock_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const 
 pcm_status pcm_solve_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *v, const pcm_solve_opts *opts,
                              double *const *q, pcm_solve_info *info);
 
+/* pcm_grad for every molecule of the batch (Sec. 2, Eq. 14; Sec. 4c, Eq. 22): per angular
+ * class one launch of the point side and one of the pair side over all molecules, then
+ * per-molecule contraction and the per-point and per-atom sums.  Each molecule's work split
+ * does not depend on the others, so the results equal those of pcm_grad bit for bit.  HOST
+ * arrays of DEVICE pointers P[n] (nbf_i^2), q[n] (M_i), g_nuc[n] (n_atoms_i*3, written),
+ * g_surf[n] (M_i*3, written).  Errors: PCM_E_ARG (NULL array or entry). */
+pcm_status pcm_grad_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *P, const double *const *q,
+                            double *const *g_nuc, double *const *g_surf);
+
 /* Per-kernel timing.  pcm_profile_enable(ctx, 1) clears previous records and makes every
  * heavy launch (integral, matvec, gradient and preconditioner kernels) record a pair of HIP
  * events on the context's stream; pcm_profile_collect synchronises the stream, aggregates

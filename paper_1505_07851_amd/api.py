@@ -307,6 +307,16 @@ class Batch:
         self.ctx.check(self.ctx.lib.pcm_fock_batched(self.ctx.h, self.h, self._ptrs(qs), self._ptrs(Fs)))
         return Fs
 
+    def grad(self, Ps, qs):
+        """[(g_nuc, g_surf)] of Eq. 14 at fixed density for every molecule, in shared launches."""
+        Ps = [_f64(P, m.nbf * m.nbf, "P").contiguous() for P, m in zip(Ps, self.mols)]
+        qs = [_f64(q, m.M, "q").contiguous() for q, m in zip(qs, self.mols)]
+        gns = [m._zeros(m.n_atoms, 3) for m in self.mols]
+        gss = [m._zeros(m.M, 3) for m in self.mols]
+        self.ctx.check(self.ctx.lib.pcm_grad_batched(self.ctx.h, self.h, self._ptrs(Ps), self._ptrs(qs),
+                                                     self._ptrs(gns), self._ptrs(gss)))
+        return list(zip(gns, gss))
+
     def solve(self, vs, precond="jacobi", block=100, seed=0, tol=1e-6, max_iter=10000, q0s=None,
               precision="fp64", inner_rtol=1e-4, qs=None, raise_noconv=True):
         """Solve A_i q_i = -f v_i for every molecule; returns (list of q, list of info dicts)."""

@@ -681,6 +681,23 @@ pcm_status pcm_fock_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const 
     });
 }
 
+pcm_status pcm_grad_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *P, const double *const *q,
+                            double *const *g_nuc, double *const *g_surf) {
+    if (!ctx) return PCM_E_ARG;
+    if (!batch || !P || !q || !g_nuc || !g_surf) return fail(ctx, PCM_E_ARG, "NULL argument");
+    const int n = (int)batch->mols.size();
+    for (int i = 0; i < n; ++i)
+        if (!P[i] || !q[i] || !g_nuc[i] || !g_surf[i]) return fail(ctx, PCM_E_ARG, "NULL matrix or vector in batch");
+    return guarded(ctx, [&]() -> pcm_status {
+        ctx_ensure_device(ctx);
+        for (int i = 0; i < n; ++i) density_list(ctx, batch->mols[i], P[i]);
+        run_grad_batch(ctx, batch->mols, std::vector<const double *>(P, P + n), std::vector<const double *>(q, q + n),
+                       std::vector<double *>(g_nuc, g_nuc + n), std::vector<double *>(g_surf, g_surf + n),
+                       ctx->prm.precision);
+        return PCM_OK;
+    });
+}
+
 pcm_status pcm_solve_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *v, const pcm_solve_opts *opts,
                              double *const *q, pcm_solve_info *info) {
     if (!ctx) return PCM_E_ARG;

@@ -13,62 +13,92 @@
 // Per-atom sums run over fixed per-atom lists, so every result is bitwise reproducible.
 #include "pcm_internal.h"
 
+#include <array>
+#include <cstring>
+
 // -------------------------------------------------------------------------------------------
 // gc: g_surf contribution of the c term, partial over a chunk of pairs (3 rows per chunk)
 // -------------------------------------------------------------------------------------------
+// Work of one molecule and class in a (possibly batched) launch; items are numbered from `base`.
+struct GradPtsDesc {
+    const unsigned char *rec;  // class records (header + D_tuv), padded to REC_PAD
+    const void *pts;           // PtInt<T> [Mpad]
+    double *part;              // partial rows [row][3][M]
+    long long base;            // first item: (point tile, pair chunk), tile fastest
+    int stride, n_pad, chunk, M, ntile, row0;
+};
+struct GradVDesc {
+    const unsigned char *rec;  // class records
+    const void *pts;           // PtInt<T> [Mpad]
+    const double *q;           // charges, zero past M [Mpad]
+    double *vout;              // [chunk][tuv][pair]
+    long long base;            // first item: (pair tile, point chunk), tile fastest
+    int stride, n_pairs, Mpad, chunk, nptile;
+};
+
 template <int L, typename T>
-__global__ __launch_bounds__(256) void k_grad_pts(const unsigned char *__restrict__ rec, int stride, int n_pad,
-                                                  int chunk_len, const PtInt<T> *__restrict__ pts, int M,
-                                                  const T *__restrict__ boys_g, double *__restrict__ part, int row0) {
+__global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict__ ds, int nd, long long n_items,
+                                                  const T *__restrict__ boys_g) {
     constexpr int NT = ntuv(L), PB = pair_batch<L + 1>();
     __shared__ T tab[boys_lds_size<T, L + 1>()];
     load_boys<T, L + 1>(tab, boys_g);
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const PtInt<T> me = pts[k < M ? k : M - 1];
-    const int p0 = blockIdx.y * chunk_len;
-    const int p1 = min(n_pad, p0 + chunk_len);
-    double gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int ip = p0; ip < p1; ip += PB) {
-        PairHdr<T> h[PB];
-        T D[PB][NT];
+    {  // one item per block (the grid covers every item; a loop over items costs registers here)
+        const long long it = blockIdx.x;
+        if (it >= n_items) return;
+        const GradPtsDesc &d = ds[find_desc(ds, nd, it)];
+        const long long local = it - d.base;
+        const int tile = (int)(local % d.ntile), ch = (int)(local / d.ntile);
+        const cptr<unsigned char> rec = as_const(d.rec);
+        const PtInt<T> *__restrict__ pts = reinterpret_cast<const PtInt<T> *>(d.pts);
+        const int M = d.M, stride = d.stride;
+        const int k = tile * 256 + threadIdx.x;
+        const PtInt<T> me = pts[k < M ? k : M - 1];
+        const int p0 = ch * d.chunk;
+        const int p1 = min(d.n_pad, p0 + d.chunk);
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int ip = p0; ip < p1; ip += PB) {
+            PairHdr<T> h[PB];
+            T D[PB][NT];
 #pragma unroll
-        for (int b = 0; b < PB; ++b) {
-            const unsigned char *r = rec + (size_t)(ip + b) * stride;
-            h[b] = *reinterpret_cast<const PairHdr<T> *>(r);
-            const T *d = reinterpret_cast<const T *>(r + sizeof(PairHdr<T>));
+            for (int b = 0; b < PB; ++b) {
+                const cptr<unsigned char> r = rec + (size_t)(ip + b) * stride;
+                h[b] = *(cptr<PairHdr<T>>)(r);
+                const cptr<T> dd = (cptr<T>)(r + sizeof(PairHdr<T>));
 #pragma unroll
-            for (int t = 0; t < NT; ++t) D[b][t] = d[t];
-        }
+                for (int t = 0; t < NT; ++t) D[b][t] = dd[t];
+            }
 #pragma unroll
-        for (int b = 0; b < PB; ++b) {
-            T R[ntuv(L + 1)];
-            eval_R<L + 1, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab, R);
-            if constexpr (sizeof(T) == 8) {  // FP64: straight into the accumulators
+            for (int b = 0; b < PB; ++b) {
+                T R[ntuv(L + 1)];
+                eval_R<L + 1, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
+                                 R);
+                if constexpr (sizeof(T) == 8) {  // FP64: straight into the accumulators
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    gx = fma(D[b][t], R[TuvShift<L>::x(t)], gx);
-                    gy = fma(D[b][t], R[TuvShift<L>::y(t)], gy);
-                    gz = fma(D[b][t], R[TuvShift<L>::z(t)], gz);
+                    for (int t = 0; t < NT; ++t) {
+                        gx = fma(D[b][t], R[TuvShift<L>::x(t)], gx);
+                        gy = fma(D[b][t], R[TuvShift<L>::y(t)], gy);
+                        gz = fma(D[b][t], R[TuvShift<L>::z(t)], gz);
+                    }
+                } else {  // FP32 evaluation, one FP64 add per pair
+                    T sx = T(0), sy = T(0), sz = T(0);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        sx = fma(D[b][t], R[TuvShift<L>::x(t)], sx);
+                        sy = fma(D[b][t], R[TuvShift<L>::y(t)], sy);
+                        sz = fma(D[b][t], R[TuvShift<L>::z(t)], sz);
+                    }
+                    gx += (double)sx;
+                    gy += (double)sy;
+                    gz += (double)sz;
                 }
-            } else {  // FP32 evaluation, one FP64 add per pair
-                T sx = T(0), sy = T(0), sz = T(0);
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    sx = fma(D[b][t], R[TuvShift<L>::x(t)], sx);
-                    sy = fma(D[b][t], R[TuvShift<L>::y(t)], sy);
-                    sz = fma(D[b][t], R[TuvShift<L>::z(t)], sz);
-                }
-                gx += (double)sx;
-                gy += (double)sy;
-                gz += (double)sz;
             }
         }
-    }
-    if (k < M) {
-        size_t base = (size_t)(row0 + blockIdx.y) * 3 * M;
-        part[base + k] = gx;
-        part[base + M + k] = gy;
-        part[base + 2 * M + k] = gz;
+        if (k < M) {
+            const size_t base = (size_t)(d.row0 + ch) * 3 * M;
+            d.part[base + k] = gx;
+            d.part[base + M + k] = gy;
+            d.part[base + 2 * M + k] = gz;
+        }
     }
 }
 
@@ -76,44 +106,52 @@ __global__ __launch_bounds__(256) void k_grad_pts(const unsigned char *__restric
 // V'_tuv up to L+1 per pair (lane = pair), weights q_k; same as the Fock accumulation
 // -------------------------------------------------------------------------------------------
 template <int L, typename T>
-__global__ __launch_bounds__(256) void k_grad_v(const unsigned char *__restrict__ rec, int stride, int n_pairs,
-                                                const PtInt<T> *__restrict__ pts, const double *__restrict__ q,
-                                                int Mpad, int chunk_len, const T *__restrict__ boys_g,
-                                                double *__restrict__ vout) {
+__global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds, int nd, long long n_items,
+                                                const T *__restrict__ boys_g) {
     __shared__ T tab[boys_lds_size<T, L + 1>()];
     load_boys<T, L + 1>(tab, boys_g);
     constexpr int NT = ntuv(L + 1);
-    const int ip = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ipp = ip < n_pairs ? ip : n_pairs - 1;
-    const PairHdr<T> h = *reinterpret_cast<const PairHdr<T> *>(rec + (size_t)ipp * stride);
-    const int k0 = blockIdx.y * chunk_len;
-    const int k1 = min(Mpad, k0 + chunk_len);
-    double V[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) V[t] = 0.0;
     // points per batch: fewer for the larger V' sets so that more waves stay resident
     constexpr int PB = L <= 1 ? PT_BATCH : (L == 2 ? 2 : 1);
-    for (int k = k0; k < k1; k += PB) {
-        PtInt<T> pt[PB];
-        double qk[PB];
+    {  // one item per block, as in k_grad_pts
+        const long long it = blockIdx.x;
+        if (it >= n_items) return;
+        const GradVDesc &d = ds[find_desc(ds, nd, it)];
+        const long long local = it - d.base;
+        const int ptile = (int)(local % d.nptile), ch = (int)(local / d.nptile);
+        const int n_pairs = d.n_pairs;
+        const int ip = ptile * 256 + threadIdx.x;
+        const int ipp = ip < n_pairs ? ip : n_pairs - 1;
+        const PairHdr<T> h = *reinterpret_cast<const PairHdr<T> *>(d.rec + (size_t)ipp * d.stride);
+        const cptr<PtInt<T>> pts = as_const(reinterpret_cast<const PtInt<T> *>(d.pts));
+        const cptr<double> q = as_const(d.q);
+        const int k0 = ch * d.chunk;
+        const int k1 = min(d.Mpad, k0 + d.chunk);
+        double V[NT];
 #pragma unroll
-        for (int b = 0; b < PB; ++b) {
-            pt[b] = pts[k + b];
-            qk[b] = q[k + b];
+        for (int t = 0; t < NT; ++t) V[t] = 0.0;
+        for (int k = k0; k < k1; k += PB) {
+            PtInt<T> pt[PB];
+            double qk[PB];
+#pragma unroll
+            for (int b = 0; b < PB; ++b) {
+                pt[b] = pts[k + b];
+                qk[b] = q[k + b];
+            }
+#pragma unroll
+            for (int b = 0; b < PB; ++b) {
+                T R[NT];
+                eval_R<L + 1, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
+                                 pt[b].lim, tab, R);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) V[t] = fma(qk[b], (double)R[t], V[t]);
+            }
         }
+        if (ip < n_pairs) {
+            double *o = d.vout + (size_t)ch * NT * n_pairs;
 #pragma unroll
-        for (int b = 0; b < PB; ++b) {
-            T R[NT];
-            eval_R<L + 1, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta, pt[b].lim,
-                             tab, R);
-#pragma unroll
-            for (int t = 0; t < NT; ++t) V[t] = fma(qk[b], (double)R[t], V[t]);
+            for (int t = 0; t < NT; ++t) o[(size_t)t * n_pairs + ip] = V[t];
         }
-    }
-    if (ip < n_pairs) {
-        double *o = vout + (size_t)blockIdx.y * NT * n_pairs;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) o[(size_t)t * n_pairs + ip] = V[t];
     }
 }
 
@@ -458,19 +496,24 @@ __global__ __launch_bounds__(256) void k_grad_nuc(int N, int M, const double *__
 }
 
 // -------------------------------------------------------------------------------------------
-// work split into about 16,384 items (lane tiles x chunks of the other dimension): shorter
+// Work split into about 16,384 items (lane tiles x chunks of the other dimension): shorter
 // chunks than the integral defaults balance the long gradient loops better (measured on the
-// 600-atom protein: 145 ms per gradient at 4,096 items, 135 ms at 16,384)
-static int chunk_for(long long n_work, long long n_lanes) {
+// 600-atom protein: 145 ms per gradient at 4,096 items, 135 ms at 16,384).  A chunk is never
+// shorter than `min_len`: classes with few pairs and small molecules would otherwise be cut into
+// chunks of a few dozen points or pairs, whose partial sums cost more traffic than the work.
+constexpr int GRAD_MIN_PTS = 512, GRAD_MIN_PAIRS = 512, GRAD_MIN_AOFF = 128;
+static int chunk_for(long long n_work, long long n_lanes, int min_len) {
     int tiles = n_lanes > 0 ? div_up(n_lanes, 256) : 1;
     long long want = (16384 + tiles - 1) / tiles;
     if (want < 1) want = 1;
     long long len = (n_work + want - 1) / want;
-    return (int)(len < 16 ? 16 : len);
+    return (int)(len < min_len ? min_len : len);
 }
 
 // rows of the c-term point side for list `ls` (one per pair chunk per class)
-static int grad_pts_chunk(long long n, int M) { return (chunk_for(n, M) + REC_PAD - 1) / REC_PAD * REC_PAD; }
+static int grad_pts_chunk(long long n, int M) {
+    return (chunk_for(n, M, GRAD_MIN_PAIRS) + REC_PAD - 1) / REC_PAD * REC_PAD;
+}
 static int grad_rows(pcm_mol *mol, ListSel ls) {
     const PairList &pl = mol->*ls;
     int rows = 0;
@@ -481,80 +524,143 @@ static int grad_rows(pcm_mol *mol, ListSel ls) {
     return rows;
 }
 
-// c term of one pair list (charges already in qpad): the point side (gc) as partial rows of part_c
-// from row0 on, the pair side (ga, gb) summed per candidate shell pair into gsp (added when `add`)
+// Per molecule of a gradient call: its inputs, outputs and the partial-row layout.
+struct GradJob {
+    pcm_mol *mol;
+    const double *P, *q;
+    double *g_nuc, *g_surf;
+    int rows_a, rows_c, row0;  // A_off rows, c-term rows, next free c-term row
+    double *part_a, *part_c;
+};
+
+// c term of one pair list for every molecule (charges already in qpad): per class, one launch of
+// the point side (gc, partial rows of part_c from each job's row0 on) and one of the pair side
+// (V' up to L+1) over all molecules, then per molecule the contraction to ga/gb and the sums per
+// candidate shell pair into gsp (added when `add`).  The work split of a molecule does not
+// depend on the other molecules, so a batched call gives the same bits as single calls.
 template <typename T>
-static void grad_cterm(pcm_ctx *ctx, pcm_mol *mol, const double *P, ListSel ls, double *part_c, int &row0,
-                       bool add) {
-    PairList &pl = mol->*ls;
-    const int M = mol->M, Mpad = mol->Mpad;
+static void grad_cterm(pcm_ctx *ctx, std::vector<GradJob> &jobs, ListSel ls, bool add) {
     const T *tab = sizeof(T) == 8 ? (const T *)ctx->boys64.p : (const T *)ctx->boys32.p;
-    const PtInt<T> *pts = reinterpret_cast<const PtInt<T> *>(sizeof(T) == 8 ? mol->pti64.p : mol->pti32.p);
     const char *suffix = sizeof(T) == 8 ? "_f64" : "_f32";
+    auto pts_of = [](pcm_mol *mol) -> const void * { return sizeof(T) == 8 ? (const void *)mol->pti64.p
+                                                                             : (const void *)mol->pti32.p; };
+    // V' chunking per molecule and class; V' and per-pair buffers sized for the largest class
+    const size_t nj = jobs.size();
+    std::vector<std::array<int, NCLS>> chunk_v(nj);
+    for (size_t i = 0; i < nj; ++i) {
+        pcm_mol *mol = jobs[i].mol;
+        const PairList &pl = mol->*ls;
+        size_t vneed = 0, gneed = 0;
+        for (int cl = 0; cl < NCLS; ++cl) {
+            const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
+            int c = chunk_for(mol->Mpad, n ? n : 1, GRAD_MIN_PTS);
+            if (c < 32) c = 32;
+            c = (c + PT_BATCH - 1) / PT_BATCH * PT_BATCH;
+            chunk_v[i][cl] = c;
+            const size_t v = (size_t)div_up(mol->Mpad, c) * ntuv(CLS_LA[cl] + CLS_LB[cl] + 1) * n;
+            vneed = std::max(vneed, v);
+            gneed = std::max(gneed, (size_t)n * 6);
+        }
+        mol->vbuf.ensure(vneed + 1);
+        mol->gpair.ensure(gneed + 1);
+    }
     for (int cl = 0; cl < NCLS; ++cl) {
-        const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
-        if (!n) continue;
         const int L = CLS_LA[cl] + CLS_LB[cl];
-        const int chunk = grad_pts_chunk(n, M);
-        const int nch = div_up(n, chunk);
-        const int n_pad = (int)((n + REC_PAD - 1) / REC_PAD * REC_PAD);
-        dim3 grid(div_up(M, 256), nch);
-        const unsigned char *rec = pl.rec.p + pl.rec_off[cl];
         const int stride = (int)rec_stride<T>(L);
-        ProfScope ps(ctx, "grad_pts_L" + std::to_string(L) + suffix, (double)n * M);
-        switch (L) {
-#define GP_CASE(LL)                                                                                                 \
-    case LL:                                                                                                        \
-        k_grad_pts<LL, T><<<grid, 256, 0, ctx->stream>>>(rec, stride, n_pad, chunk, pts, M, tab, part_c, row0);     \
+        std::vector<GradPtsDesc> dp;
+        std::vector<GradVDesc> dv;
+        long long items_p = 0, items_v = 0;
+        double work = 0.0;
+        for (size_t i = 0; i < nj; ++i) {
+            GradJob &j = jobs[i];
+            pcm_mol *mol = j.mol;
+            const PairList &pl = mol->*ls;
+            const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
+            if (!n) continue;
+            const unsigned char *rec = pl.rec.p + pl.rec_off[cl];
+            GradPtsDesc a{};
+            a.rec = rec;
+            a.pts = pts_of(mol);
+            a.part = j.part_c;
+            a.base = items_p;
+            a.stride = stride;
+            a.n_pad = (int)((n + REC_PAD - 1) / REC_PAD * REC_PAD);
+            a.chunk = grad_pts_chunk(n, mol->M);
+            a.M = mol->M;
+            a.ntile = div_up(mol->M, 256);
+            a.row0 = j.row0;
+            const int nch = div_up(n, a.chunk);
+            items_p += (long long)a.ntile * nch;
+            j.row0 += nch;
+            dp.push_back(a);
+            GradVDesc b{};
+            b.rec = rec;
+            b.pts = a.pts;
+            b.q = mol->qpad.p;
+            b.vout = mol->vbuf.p;
+            b.base = items_v;
+            b.stride = stride;
+            b.n_pairs = (int)n;
+            b.Mpad = mol->Mpad;
+            b.chunk = chunk_v[i][cl];
+            b.nptile = div_up(n, 256);
+            items_v += (long long)b.nptile * div_up(mol->Mpad, b.chunk);
+            dv.push_back(b);
+            work += (double)n * mol->M;
+        }
+        if (!dp.empty()) {
+            if (items_p > (1LL << 30) || items_v > (1LL << 30))
+                throw PcmError{PCM_E_UNSUPPORTED, "gradient call too large for one launch per class"};
+            const size_t pb = dp.size() * sizeof(GradPtsDesc), vb = dv.size() * sizeof(GradVDesc);
+            std::vector<unsigned char> blob(pb + vb);
+            std::memcpy(blob.data(), dp.data(), pb);
+            std::memcpy(blob.data() + pb, dv.data(), vb);
+            unsigned char *dev = (unsigned char *)upload_desc(ctx, blob.data(), blob.size());
+            const GradPtsDesc *dpp = reinterpret_cast<const GradPtsDesc *>(dev);
+            const GradVDesc *dvp = reinterpret_cast<const GradVDesc *>(dev + pb);
+            const int nd = (int)dp.size();
+            {
+                ProfScope ps(ctx, "grad_pts_L" + std::to_string(L) + suffix, work);
+                switch (L) {
+#define GP_CASE(LL)                                                                                    \
+    case LL:                                                                                           \
+        k_grad_pts<LL, T><<<int_grid(items_p), 256, 0, ctx->stream>>>(dpp, nd, items_p, tab);          \
         break;
-            GP_CASE(0) GP_CASE(1) GP_CASE(2) GP_CASE(3) GP_CASE(4)
+                    GP_CASE(0) GP_CASE(1) GP_CASE(2) GP_CASE(3) GP_CASE(4)
 #undef GP_CASE
-        }
-        HIP_LAUNCH_OK();
-        row0 += nch;
-    }
-    // pair side: V' (L+1) per pair, contraction, per shell pair
-    size_t vneed = 0, gneed = 0;
-    int chunk_v[NCLS];
-    for (int cl = 0; cl < NCLS; ++cl) {
-        const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
-        chunk_v[cl] = chunk_for(Mpad, n ? n : 1);
-        if (chunk_v[cl] < 32) chunk_v[cl] = 32;
-        chunk_v[cl] = (chunk_v[cl] + PT_BATCH - 1) / PT_BATCH * PT_BATCH;
-        const size_t v = (size_t)div_up(Mpad, chunk_v[cl]) * ntuv(CLS_LA[cl] + CLS_LB[cl] + 1) * n;
-        vneed = v > vneed ? v : vneed;
-        gneed = (size_t)n * 6 > gneed ? (size_t)n * 6 : gneed;
-    }
-    mol->vbuf.ensure(vneed + 1);
-    mol->gpair.ensure(gneed + 1);
-    for (int cl = 0; cl < NCLS; ++cl) {
-        const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
-        const long long sp0 = mol->sp_cls_off[cl], ncs = mol->sp_cls_off[cl + 1] - sp0;
-        if (!n) {
-            if (ncs && !add) HIP_OK(hipMemsetAsync(mol->gsp.p + sp0 * 6, 0, sizeof(double) * 6 * ncs, ctx->stream));
-            continue;
-        }
-        const int L = CLS_LA[cl] + CLS_LB[cl];
-        const int nch = div_up(Mpad, chunk_v[cl]);
-        const unsigned char *rec = pl.rec.p + pl.rec_off[cl];
-        const int stride = (int)rec_stride<T>(L);
-        {
-            ProfScope ps(ctx, "grad_v_L" + std::to_string(L) + suffix, (double)n * M);
-            dim3 grid(div_up(n, 256), nch);
-            switch (L) {
-#define GV_CASE(LL)                                                                                                \
-    case LL:                                                                                                       \
-        k_grad_v<LL, T><<<grid, 256, 0, ctx->stream>>>(rec, stride, (int)n, pts, mol->qpad.p, Mpad, chunk_v[cl],   \
-                                                       tab, mol->vbuf.p);                                           \
-        break;
-                GV_CASE(0) GV_CASE(1) GV_CASE(2) GV_CASE(3) GV_CASE(4)
-#undef GV_CASE
+                }
+                HIP_LAUNCH_OK();
             }
-            HIP_LAUNCH_OK();
+            {
+                ProfScope ps(ctx, "grad_v_L" + std::to_string(L) + suffix, work);
+                switch (L) {
+#define GV_CASE(LL)                                                                                    \
+    case LL:                                                                                           \
+        k_grad_v<LL, T><<<int_grid(items_v), 256, 0, ctx->stream>>>(dvp, nd, items_v, tab);            \
+        break;
+                    GV_CASE(0) GV_CASE(1) GV_CASE(2) GV_CASE(3) GV_CASE(4)
+#undef GV_CASE
+                }
+                HIP_LAUNCH_OK();
+            }
         }
-        const int *es = pl.ent_sp.p + pl.cls_off[cl], *ei = pl.ent_ij.p + pl.cls_off[cl];
-        const int g = div_up(n, 64);
-        ProfScope ps2(ctx, "grad_contract", (double)n);
+        // per molecule: contraction of V' to (ga, gb) per primitive pair, sums per shell pair
+        for (size_t i = 0; i < nj; ++i) {
+            GradJob &j = jobs[i];
+            pcm_mol *mol = j.mol;
+            const PairList &pl = mol->*ls;
+            const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
+            const long long sp0 = mol->sp_cls_off[cl], ncs = mol->sp_cls_off[cl + 1] - sp0;
+            if (!n) {
+                if (ncs && !add)
+                    HIP_OK(hipMemsetAsync(mol->gsp.p + sp0 * 6, 0, sizeof(double) * 6 * ncs, ctx->stream));
+                continue;
+            }
+            const int nch = div_up(mol->Mpad, chunk_v[i][cl]);
+            const int *es = pl.ent_sp.p + pl.cls_off[cl], *ei = pl.ent_ij.p + pl.cls_off[cl];
+            const int g = div_up(n, 64);
+            const double *P = j.P;
+            ProfScope ps2(ctx, "grad_contract", (double)n);
 #define GC_CASE(CI, LA_, LB_)                                                                                      \
     case CI:                                                                                                       \
         k_grad_contract<LA_, LB_><<<g, 64, 0, ctx->stream>>>(n, nch, mol->vbuf.p, es, ei, mol->spa.p, mol->spb.p,  \
@@ -568,67 +674,88 @@ static void grad_cterm(pcm_ctx *ctx, pcm_mol *mol, const double *P, ListSel ls, 
             n, nch, mol->vbuf.p, es, ei, mol->spa.p, mol->spb.p, mol->snp.p, mol->soff.p, mol->satom.p, mol->bfo.p, \
             mol->cnoff.p, mol->pexp.p, mol->cn.p, mol->xyz.p, P, mol->nbf, mol->gpair.p);                           \
         break;
-        switch (cl) {
-            GC_CASE(0, 0, 0)
-            GC_CASE(1, 0, 1)
-            GC_CASE(2, 0, 2)
-            GC_CASE(3, 1, 1)
-            GCW_CASE(4, 1, 2)
-            GCW_CASE(5, 2, 2)
-        }
+            switch (cl) {
+                GC_CASE(0, 0, 0)
+                GC_CASE(1, 0, 1)
+                GC_CASE(2, 0, 2)
+                GC_CASE(3, 1, 1)
+                GCW_CASE(4, 1, 2)
+                GCW_CASE(5, 2, 2)
+            }
 #undef GC_CASE
 #undef GCW_CASE
-        HIP_LAUNCH_OK();
-        k_grad_sp<<<div_up(ncs, 128), 128, 0, ctx->stream>>>(sp0, ncs, pl.cls_off[cl], pl.spo.p, mol->gpair.p,
-                                                             mol->gsp.p, add ? 1 : 0);
-        HIP_LAUNCH_OK();
+            HIP_LAUNCH_OK();
+            k_grad_sp<<<div_up(ncs, 128), 128, 0, ctx->stream>>>(sp0, ncs, pl.cls_off[cl], pl.spo.p, mol->gpair.p,
+                                                                 mol->gsp.p, add ? 1 : 0);
+            HIP_LAUNCH_OK();
+        }
     }
 }
 
-// Eq. 14 at fixed density: A off-diagonal rows, the c term of the list(s), then per point
-// (g_surf) and per atom (g_nuc) with the B and switching terms
-static void grad_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc, double *g_surf,
-                        int prec) {
-    const int M = mol->M;
+// Eq. 14 at fixed density for one or more molecules: A off-diagonal rows, the c term of the
+// list(s), then per point (g_surf) and per atom (g_nuc) with the B and switching terms
+static void grad_run(pcm_ctx *ctx, std::vector<GradJob> &all, int prec) {
     const double inv_f = (ctx->prm.eps + ctx->prm.k_factor) / (ctx->prm.eps - 1.0);
-    if (M == 0) {  // no surface charge: every term of Eq. 14 carries a factor q
-        HIP_OK(hipMemsetAsync(g_nuc, 0, sizeof(double) * 3 * mol->N, ctx->stream));
-        return;
-    }
     const bool dyn = prec == PCM_DYNAMIC;
-    HIP_OK(hipMemcpyAsync(mol->qpad.p, q, sizeof(double) * M, hipMemcpyDeviceToDevice, ctx->stream));
-    const int len_a = chunk_for(M, M);
-    const int rows_a = div_up(M, len_a);
-    const int rows_c = grad_rows(mol, &pcm_mol::esp) + (dyn ? grad_rows(mol, &pcm_mol::esp_w) : 0);
-    mol->part.ensure((size_t)(rows_a + rows_c + 1) * 3 * M);
-    double *part_a = mol->part.p, *part_c = mol->part.p + (size_t)rows_a * 3 * M;
-    const long long nsp = mol->sp_cls_off[NCLS];
-    mol->gsp.ensure((size_t)nsp * 6 + 6);
-    {
+    std::vector<GradJob> jobs;
+    for (GradJob &j : all) {
+        pcm_mol *mol = j.mol;
+        const int M = mol->M;
+        if (M == 0) {  // no surface charge: every term of Eq. 14 carries a factor q
+            HIP_OK(hipMemsetAsync(j.g_nuc, 0, sizeof(double) * 3 * mol->N, ctx->stream));
+            continue;
+        }
+        HIP_OK(hipMemcpyAsync(mol->qpad.p, j.q, sizeof(double) * M, hipMemcpyDeviceToDevice, ctx->stream));
+        const int len_a = chunk_for(M, M, GRAD_MIN_AOFF);
+        j.rows_a = div_up(M, len_a);
+        j.rows_c = grad_rows(mol, &pcm_mol::esp) + (dyn ? grad_rows(mol, &pcm_mol::esp_w) : 0);
+        j.row0 = 0;
+        mol->part.ensure((size_t)(j.rows_a + j.rows_c + 1) * 3 * M);
+        j.part_a = mol->part.p;
+        j.part_c = mol->part.p + (size_t)j.rows_a * 3 * M;
+        mol->gsp.ensure((size_t)mol->sp_cls_off[NCLS] * 6 + 6);
         ProfScope psa(ctx, "grad_aoff", (double)M * M);
-        k_grad_aoff<<<dim3(div_up(M, 256), rows_a), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p,
-                                                                             mol->zeta.p, q, M, len_a, part_a);
+        k_grad_aoff<<<dim3(div_up(M, 256), j.rows_a), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p,
+                                                                               mol->zeta.p, j.q, M, len_a, j.part_a);
+        HIP_LAUNCH_OK();
+        jobs.push_back(j);
+    }
+    if (jobs.empty()) return;
+    if (prec == PCM_MIXED) {
+        grad_cterm<float>(ctx, jobs, &pcm_mol::esp, false);
+    } else {
+        grad_cterm<double>(ctx, jobs, &pcm_mol::esp, false);
+        if (dyn) grad_cterm<float>(ctx, jobs, &pcm_mol::esp_w, true);
+    }
+    for (GradJob &j : jobs) {
+        pcm_mol *mol = j.mol;
+        const int M = mol->M;
+        const long long nsp = mol->sp_cls_off[NCLS];
+        k_grad_surf<<<div_up(M, 256), 256, 0, ctx->stream>>>(M, mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p,
+                                                             mol->Akk.p, mol->keep.p, mol->nsph, j.q, mol->xyz.p,
+                                                             mol->Z.p, mol->rad.p, mol->N, inv_f, j.part_a, j.rows_a,
+                                                             j.part_c, j.rows_c, j.g_surf);
+        HIP_LAUNCH_OK();
+        k_grad_nuc<<<mol->N, 256, 0, ctx->stream>>>(mol->N, M, mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p,
+                                                    mol->Akk.p, mol->keep.p, mol->nsph, j.q, mol->xyz.p, mol->Z.p,
+                                                    mol->rad.p, inv_f, mol->atom_sp_off_a.p, mol->atom_sp_a.p,
+                                                    mol->atom_sp_off_b.p, mol->atom_sp_b.p, nsp ? mol->gsp.p : nullptr,
+                                                    j.g_nuc);
         HIP_LAUNCH_OK();
     }
-    int row0 = 0;
-    if (prec == PCM_MIXED) {
-        grad_cterm<float>(ctx, mol, P, &pcm_mol::esp, part_c, row0, false);
-    } else {
-        grad_cterm<double>(ctx, mol, P, &pcm_mol::esp, part_c, row0, false);
-        if (dyn) grad_cterm<float>(ctx, mol, P, &pcm_mol::esp_w, part_c, row0, true);
-    }
-    k_grad_surf<<<div_up(M, 256), 256, 0, ctx->stream>>>(M, mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p, mol->Akk.p,
-                                                         mol->keep.p, mol->nsph, q, mol->xyz.p, mol->Z.p, mol->rad.p,
-                                                         mol->N, inv_f, part_a, rows_a, part_c, rows_c, g_surf);
-    HIP_LAUNCH_OK();
-    k_grad_nuc<<<mol->N, 256, 0, ctx->stream>>>(mol->N, M, mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p, mol->Akk.p,
-                                                mol->keep.p, mol->nsph, q, mol->xyz.p, mol->Z.p, mol->rad.p, inv_f,
-                                                mol->atom_sp_off_a.p, mol->atom_sp_a.p, mol->atom_sp_off_b.p,
-                                                mol->atom_sp_b.p, nsp ? mol->gsp.p : nullptr, g_nuc);
-    HIP_LAUNCH_OK();
 }
 
 void run_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc, double *g_surf,
               int prec) {
-    grad_launch(ctx, mol, P, q, g_nuc, g_surf, prec);
+    std::vector<GradJob> jobs{GradJob{mol, P, q, g_nuc, g_surf, 0, 0, 0, nullptr, nullptr}};
+    grad_run(ctx, jobs, prec);
+}
+
+void run_grad_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<const double *> &P,
+                    const std::vector<const double *> &q, const std::vector<double *> &g_nuc,
+                    const std::vector<double *> &g_surf, int prec) {
+    std::vector<GradJob> jobs;
+    for (size_t i = 0; i < mols.size(); ++i)
+        jobs.push_back(GradJob{mols[i], P[i], q[i], g_nuc[i], g_surf[i], 0, 0, 0, nullptr, nullptr});
+    grad_run(ctx, jobs, prec);
 }

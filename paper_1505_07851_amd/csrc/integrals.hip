@@ -57,15 +57,6 @@ struct SumDesc {
     int M, rows, acc;  // acc: add to out instead of overwriting it
 };
 
-template <typename D> __device__ __forceinline__ int find_desc(const D *__restrict__ ds, int nd, long long it) {
-    int lo = 0, hi = nd - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (ds[mid].base <= it) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
 
 // ----------------------------------------------------------------------------------------
 // esp: partial c over one chunk of pairs of one class; lane = surface point
@@ -434,14 +425,8 @@ static std::string shape_key(const char *kind, int L, bool f64, long long n, lon
 // them (items differ in cost: chunk tails, near-field fractions).  Re-staging the Boys table
 // per workgroup costs well under 1% of these launches.  The item loop still allows a smaller
 // grid (at most 2^30 workgroups).
-static int int_grid(long long n_items) { return (int)std::min<long long>(std::max<long long>(n_items, 1), 1 << 30); }
 
 // device scratch for descriptor tables of one call (all classes uploaded at once)
-static void *upload_desc(pcm_ctx *ctx, const void *h, size_t bytes) {
-    ctx->desc.ensure(bytes ? bytes : 1);
-    if (bytes) HIP_OK(hipMemcpyAsync(ctx->desc.p, h, bytes, hipMemcpyHostToDevice, ctx->stream));
-    return ctx->desc.p;
-}
 
 template <typename T>
 static void esp_class_launch(pcm_ctx *ctx, int L, const EspDesc *d, int nd, long long n_items) {

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstdint>
 #include <functional>
 #include <map>
@@ -205,6 +206,18 @@ template <typename T> using cptr = const __attribute__((address_space(4))) T *;
 template <typename T> using cptr = const T *;
 #endif
 template <typename T> __device__ __forceinline__ cptr<T> as_const(const T *p) { return (cptr<T>)(p); }
+
+// descriptor of work item `it` in a table sorted by first item `base` (batched launches; `it`
+// may differ between lanes, as in the per-pair contraction kernels)
+template <typename D> __device__ __forceinline__ int find_desc(const D *__restrict__ ds, int nd, long long it) {
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (ds[mid].base <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 // Stage the Boys columns an order-L evaluation reads into LDS (row stride boys_cols<T, L>);
 // tab_g holds BoysCfg<T>::NROW rows of MT values.
@@ -454,6 +467,9 @@ double run_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double *c,
 void run_matvec_share(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int rank, int nranks);
 void run_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc, double *g_surf,
               int prec);
+void run_grad_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<const double *> &P,
+                    const std::vector<const double *> &q, const std::vector<double *> &g_nuc,
+                    const std::vector<double *> &g_surf, int prec);
 void surface_points(pcm_ctx *ctx, pcm_mol *mol, const double *r_explicit_dev);
 // kind: PCM_PRECOND_RBJ (l = block size) or PCM_PRECOND_OCTREE (l = largest leaf)
 void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int kind, int l, unsigned long long seed);
@@ -473,3 +489,11 @@ inline int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
 // grid size for a bounds-checked 1-D launch over n items; never 0 (an empty molecule, e.g.
 // with every surface point pruned, still launches one workgroup whose lanes all exit)
 inline int grid_for(long long n, int block) { return n > 0 ? div_up(n, block) : 1; }
+// grid of a grid-stride launch over n_items work items (one block per item up to 2^30 blocks)
+inline int int_grid(long long n_items) { return (int)std::min<long long>(std::max<long long>(n_items, 1), 1 << 30); }
+// copy a host descriptor table into the context's descriptor buffer (stream ordered)
+inline void *upload_desc(pcm_ctx *ctx, const void *h, size_t bytes) {
+    ctx->desc.ensure(bytes ? bytes : 1);
+    if (bytes) HIP_OK(hipMemcpyAsync(ctx->desc.p, h, bytes, hipMemcpyHostToDevice, ctx->stream));
+    return ctx->desc.p;
+}

@@ -136,6 +136,8 @@ def test_null_arguments(L):
     assert L.pcm_batch_create(ctx, nulls, 2, ctypes.byref(out)) == _lib.PCM_E_ARG
     assert L.pcm_batch_create(ctx, nulls, 2, None) == _lib.PCM_E_ARG
     assert L.pcm_solve_batched(ctx, None, None, None, None, None) == _lib.PCM_E_ARG
+    assert L.pcm_grad_batched(ctx, None, None, None, None, None) == _lib.PCM_E_ARG
+    assert L.pcm_grad_batched(None, None, None, None, None, None) == _lib.PCM_E_ARG
     L.pcm_batch_destroy(None)
     L.pcm_destroy(ctx)
 
