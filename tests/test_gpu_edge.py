@@ -126,3 +126,36 @@ def test_coincident_surface_points(torch_cuda):
         q, info = mol.solve(bz + c, precond="rbj", block=64, seed=3, tol=1e-10, precision=prec)
         assert np.abs(q.cpu().numpy() - ref["q"]).max() <= tol_q * np.abs(ref["q"]).max(), prec
         assert abs(info["energy"] - ref["E"]) <= 1e-7 * abs(ref["E"]), prec
+
+
+def test_zero_density(torch_cuda):
+    """P = 0 screens every pair out of the Eq. 18 list: c = 0 exactly, and the gradient keeps only
+    the B and A terms of Eq. 14.  Single calls and a batch that mixes this molecule with one of
+    nonzero density, against the oracle."""
+    from paper_1505_07851_amd import Batch, Context, Molecule
+    torch = torch_cuda
+    print("\n[case zero density: small_protein(6, 50, seed=3) with P = 0, plus water]", flush=True)
+    s0 = I.small_protein(6, 50, seed=3)
+    s1 = I.water_tiny()
+    ctx = Context()
+    m0 = Molecule.from_system(ctx, s0)
+    m1 = Molecule.from_system(ctx, s1)
+    P0 = torch.zeros(m0.nbf, m0.nbf, dtype=torch.float64, device="cuda")
+    P1 = torch.tensor(s1.P, dtype=torch.float64, device="cuda")
+    c0, bz0 = m0.esp(P0)
+    assert torch.count_nonzero(c0).item() == 0
+    om0 = O.mol_from_system(s0)
+    assert np.abs(bz0.cpu().numpy() - om0.bz()).max() <= 1e-12 * np.abs(om0.bz()).max()
+    q0, info = m0.solve(bz0 + c0, precond="rbj", block=32, seed=2, tol=1e-11)
+    gn, gs = m0.grad(P0, q0)
+    g = om0.grad_terms(np.zeros((m0.nbf, m0.nbf)), q0.cpu().numpy())
+    assert np.abs(gn.cpu().numpy() - g["g_nuc"]).max() <= 1e-8 * max(1.0, np.abs(g["g_nuc"]).max())
+    assert np.abs(gs.cpu().numpy() - g["g_surf"]).max() <= 1e-8 * max(1.0, np.abs(g["g_surf"]).max())
+    c1, bz1 = m1.esp(P1)
+    q1, _ = m1.solve(bz1 + c1, precond="jacobi", tol=1e-11)
+    single1 = m1.grad(P1, q1)
+    b = Batch(ctx, [m0, m1])
+    (gn0b, gs0b), (gn1b, gs1b) = b.grad([P0, P1], [q0, q1])
+    assert torch.equal(gn0b, gn) and torch.equal(gs0b, gs)
+    assert torch.equal(gn1b, single1[0]) and torch.equal(gs1b, single1[1])
+    b.close()
