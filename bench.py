@@ -128,8 +128,9 @@ def main():
                     help="scf_policies: the 600-atom solute (M ~ 30k) or the 2,000-atom one (M ~ 150k)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding of the path is "
-                                   "described in DESIGN.md but not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the collectives of a multi-GPU run are "
+                                   "not implemented (--workload shard8 times one GPU's share of the sharded "
+                                   "product)", "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "conformers64":
         return bench_conformers(args)

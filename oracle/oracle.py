@@ -6,7 +6,7 @@ lives in ``pcm_oracle.c`` (plain C, FP64, OpenMP); this wrapper marshals
 arguments and uses numpy/scipy for the dense linear algebra (Cholesky solve,
 block inverses) of Sec. 2, Eq. 1 and Sec. 4b of the paper.
 
-Readings of the paper that this oracle takes (listed in the design doc as well):
+Readings of the paper that this oracle takes:
 * Eq. 3 constant: A_kk = sqrt(2/pi) zeta_k / S_k (the r -> 0 limit of Eq. 2
   for k = l), passed as ``diag_const``;
 * sphere weights sum to 4 pi, so zeta_k = zeta0 / (rho_I sqrt(w_k)) (Eq. 7);
