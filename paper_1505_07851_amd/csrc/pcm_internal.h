@@ -146,18 +146,18 @@ __device__ __forceinline__ void aux_Rn(T r2, T p, T limp, T pf, T pref, T zeta2,
         int i = (int)(tb * T(8) + T(0.5));
         i = i < C::NROW - 1 ? i : C::NROW - 1;
         T d = T(i) * T(0.125) - tb;
-        T w[C::ORD + 1];
-        w[0] = T(1);
+        // F_n(T) = sum_k F_{n+k}(T_i) d^k / k!, nested: F_n + d (F_{n+1} + d/2 (F_{n+2} + ...))
+        T dk[C::ORD + 1];
 #pragma unroll
-        for (int k = 1; k <= C::ORD; ++k) w[k] = w[k - 1] * d * (T(1) / T(k));
+        for (int k = 1; k <= C::ORD; ++k) dk[k] = d * (T(1) / T(k));
         const T *row = tab + i * boys_cols<T, L>();
         T fac = pref * su;
         T m2a = T(-2) * a;
 #pragma unroll
         for (int n = 0; n <= L; ++n) {
-            T F = T(0);
+            T F = row[n + C::ORD];
 #pragma unroll
-            for (int k = C::ORD; k >= 0; --k) F = fma(row[n + k], w[k], F);
+            for (int k = C::ORD; k >= 1; --k) F = fma(F, dk[k], row[n + k - 1]);
             Rn[n] = fac * F;
             fac *= m2a;
         }
