@@ -1,0 +1,53 @@
+"""Host-side checks of the benchmark's command line and measurement helpers (no GPU).
+
+* ``--gpus N`` with N != 1 exits with status 2 and one JSON line saying why (the collectives of a
+  multi-GPU run are not implemented), before touching a GPU;
+* the flop model counts each Hermite evaluation from the generated recursion and the fixed
+  per-evaluation terms; the matvec is 14 flops per unordered pair;
+* the committed traffic summary parses, and its figure is reported only for the digest it states.
+"""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_multi_gpu_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def test_flop_model():
+    import bench
+    m = bench.flop_model()
+    assert m["matvec"] == 14
+    # L = 0: no Hermite recursion; 12 fixed terms, one contraction term (2) and the accumulation (1)
+    assert m["esp_L0"] == 12 + 0 + 2 * 1 + 1
+    assert m["fock_v_L0"] == 12 + 2 * 1
+    # every model grows with L
+    for k in ("esp", "fock_v", "grad_pts", "grad_v"):
+        vals = [m[f"{k}_L{L}"] for L in range(5)]
+        assert all(a < b for a, b in zip(vals, vals[1:])), k
+    assert bench.kernel_flops("matvec_f32", 10.0, m) == 140.0
+    assert bench.kernel_flops("esp_L2_f64", 1.0, m) == m["esp_L2"]
+
+
+def test_traffic_summary_digest(tmp_path, monkeypatch):
+    import bench
+    path = os.path.join(ROOT, "profiles", "traffic_protein600.txt")
+    vals = dict(l.split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
+    vals = {k.strip(): v.strip() for k, v in vals.items()}
+    assert float(vals["matvec_f64.hbm_bytes_per_launch"]) > 0
+    got = bench.measured_traffic("matvec_f64")
+    if vals["source_digest"] == bench.source_digest():
+        assert got == float(vals["matvec_f64.hbm_bytes_per_launch"])
+    else:
+        assert got is None
+    monkeypatch.setattr(bench, "source_digest", lambda: "0" * 16)
+    assert bench.measured_traffic("matvec_f64") is None
