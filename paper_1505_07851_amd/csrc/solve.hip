@@ -281,22 +281,32 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_sym(const CGMol *__restrict__
 //   mode 0: v[dst] = y, dp[0] <- partials of x.y
 //   mode 1: v[dst] = v[bvec] - y, dp[0] <- partials of its square
 //   mode 2: v[dst] = y
-__global__ __launch_bounds__(TILE) void k_mv_finish(const CGMol *__restrict__ tab, const CGState *__restrict__ st,
-                                                    const TileItem *__restrict__ items, int n, int gate, int src,
-                                                    int dst, int bvec, int mode) {
-    __shared__ double s[TILE];
+// Each row's nT partial slots are summed by FIN_G thread groups (slots r = g mod FIN_G), then
+// added in group order: four times the waves of one thread per row hide the load latency.
+constexpr int FIN_G = 4;
+__global__ __launch_bounds__(TILE * FIN_G) void k_mv_finish(const CGMol *__restrict__ tab,
+                                                            const CGState *__restrict__ st,
+                                                            const TileItem *__restrict__ items, int n, int gate,
+                                                            int src, int dst, int bvec, int mode) {
+    __shared__ double s[TILE * FIN_G];
+    const int row = threadIdx.x % TILE, g = threadIdx.x / TILE;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const TileItem w = items[it];
         if (skip(st[w.mol], gate)) continue;
         const CGMol &m = tab[w.mol];
-        const int k = w.t * TILE + threadIdx.x;
+        const int k = w.t * TILE + row;
+        double off = 0.0;
+        if (k < m.M)
+            for (int r = g; r < m.nT; r += FIN_G) off += m.part[(size_t)r * m.M + k];
+        s[threadIdx.x] = off;
+        __syncthreads();
         double d = 0.0;
-        if (k < m.M) {
+        if (g == 0 && k < m.M) {
+            double o = s[row];
+#pragma unroll
+            for (int q = 1; q < FIN_G; ++q) o += s[q * TILE + row];
             const double xk = m.v[src][k];
-            double acc = m.Akk[k] * xk;
-            double off = 0.0;
-            for (int r = 0; r < m.nT; ++r) off += m.part[(size_t)r * m.M + k];
-            acc += off;
+            const double acc = m.Akk[k] * xk + o;
             if (mode == 1) {
                 double res = m.v[bvec][k] - acc;
                 m.v[dst][k] = res;
@@ -306,8 +316,9 @@ __global__ __launch_bounds__(TILE) void k_mv_finish(const CGMol *__restrict__ ta
                 d = xk * acc;
             }
         }
+        __syncthreads();  // s is reused by the block sum
         if (mode != 2) {
-            double t = blk_sum(d, s);
+            double t = blk_sum(d, s);  // over the first TILE threads; the other groups hold 0
             if (threadIdx.x == 0) m.dp[w.t] = t;
         }
     }
@@ -835,7 +846,7 @@ static void matvec(pcm_ctx *ctx, SolveBatch &B, hipStream_t s, int prec, int gat
                      prof ? mv_work(B, gate) : 0.0);
         launch_mv(ctx, B, s, prec, gate, src, grid);
     }
-    k_mv_finish<<<grid_of(B.n_tiles), TILE, 0, s>>>(B.tab.p, B.st.p, B.tiles.p, B.n_tiles, gate, src, dst, bvec,
+    k_mv_finish<<<grid_of(B.n_tiles), TILE * FIN_G, 0, s>>>(B.tab.p, B.st.p, B.tiles.p, B.n_tiles, gate, src, dst, bvec,
                                                     mode);
     HIP_LAUNCH_OK();
 }
