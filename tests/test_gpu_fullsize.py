@@ -232,6 +232,22 @@ def test_conformer_batch_full_size(torch_cuda):
         v = (bzs[j] + cs[j]).cpu().numpy()
         r = om.matvec(qs[j].cpu().numpy(), kidx=kidx) + om.f * v[kidx]
         assert np.abs(r).max() < 1e-8
+    # Eq. 14 for the eight at their solved q: batched equals single calls bitwise, the surface
+    # gradient on sampled points matches the oracle, and the total force vanishes (a rigid
+    # translation of atoms and points leaves E unchanged at fixed P)
+    gb = b.grad(Ps, qs)
+    for j, (m, P, q) in enumerate(zip(mols, Ps, qs)):
+        gn1, gs1 = m.grad(P, q)
+        assert torch.equal(gn1, gb[j][0]) and torch.equal(gs1, gb[j][1])
+        tot = (gn1.sum(0) + gs1.sum(0)).abs().max().item()
+        assert tot <= 1e-10 * (gn1.abs().sum().item() + gs1.abs().sum().item())
+    for j in (0, 4):
+        s, m = systems[j], mols[j]
+        om = O.mol_from_system(s)
+        kidx = np.sort(rng.choice(m.M, 6, replace=False))
+        g_or = om.grad_surface_points(s.P, qs[j].cpu().numpy(), kidx)
+        g = gb[j][1].cpu().numpy()[kidx]
+        assert np.abs(g - g_or).max() <= 1e-8 * max(1.0, np.abs(g_or).max())
     b.close()
 
 
