@@ -524,6 +524,24 @@ static int grad_rows(pcm_mol *mol, ListSel ls) {
     return rows;
 }
 
+// pair-side point chunk of class cl of list ls, and the V' / per-pair buffer sizes of the list
+static int grad_v_chunk(pcm_mol *mol, ListSel ls, int cl) {
+    const PairList &pl = mol->*ls;
+    const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
+    int c = chunk_for(mol->Mpad, n ? n : 1, GRAD_MIN_PTS);
+    if (c < 32) c = 32;
+    return (c + PT_BATCH - 1) / PT_BATCH * PT_BATCH;
+}
+static void grad_v_sizes(pcm_mol *mol, ListSel ls, size_t &vneed, size_t &gneed) {
+    const PairList &pl = mol->*ls;
+    for (int cl = 0; cl < NCLS; ++cl) {
+        const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
+        const size_t v = (size_t)div_up(mol->Mpad, grad_v_chunk(mol, ls, cl)) * ntuv(CLS_LA[cl] + CLS_LB[cl] + 1) * n;
+        vneed = std::max(vneed, v);
+        gneed = std::max(gneed, (size_t)n * 6);
+    }
+}
+
 // Per molecule of a gradient call: its inputs, outputs and the partial-row layout.
 struct GradJob {
     pcm_mol *mol;
@@ -544,26 +562,11 @@ static void grad_cterm(pcm_ctx *ctx, std::vector<GradJob> &jobs, ListSel ls, boo
     const char *suffix = sizeof(T) == 8 ? "_f64" : "_f32";
     auto pts_of = [](pcm_mol *mol) -> const void * { return sizeof(T) == 8 ? (const void *)mol->pti64.p
                                                                              : (const void *)mol->pti32.p; };
-    // V' chunking per molecule and class; V' and per-pair buffers sized for the largest class
+    // V' chunking per molecule and class (vbuf and gpair were sized for every list in grad_run)
     const size_t nj = jobs.size();
     std::vector<std::array<int, NCLS>> chunk_v(nj);
-    for (size_t i = 0; i < nj; ++i) {
-        pcm_mol *mol = jobs[i].mol;
-        const PairList &pl = mol->*ls;
-        size_t vneed = 0, gneed = 0;
-        for (int cl = 0; cl < NCLS; ++cl) {
-            const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
-            int c = chunk_for(mol->Mpad, n ? n : 1, GRAD_MIN_PTS);
-            if (c < 32) c = 32;
-            c = (c + PT_BATCH - 1) / PT_BATCH * PT_BATCH;
-            chunk_v[i][cl] = c;
-            const size_t v = (size_t)div_up(mol->Mpad, c) * ntuv(CLS_LA[cl] + CLS_LB[cl] + 1) * n;
-            vneed = std::max(vneed, v);
-            gneed = std::max(gneed, (size_t)n * 6);
-        }
-        mol->vbuf.ensure(vneed + 1);
-        mol->gpair.ensure(gneed + 1);
-    }
+    for (size_t i = 0; i < nj; ++i)
+        for (int cl = 0; cl < NCLS; ++cl) chunk_v[i][cl] = grad_v_chunk(jobs[i].mol, ls, cl);
     for (int cl = 0; cl < NCLS; ++cl) {
         const int L = CLS_LA[cl] + CLS_LB[cl];
         const int stride = (int)rec_stride<T>(L);
@@ -714,6 +717,11 @@ static void grad_run(pcm_ctx *ctx, std::vector<GradJob> &all, int prec) {
         j.part_a = mol->part.p;
         j.part_c = mol->part.p + (size_t)j.rows_a * 3 * M;
         mol->gsp.ensure((size_t)mol->sp_cls_off[NCLS] * 6 + 6);
+        size_t vneed = 0, gneed = 0;  // every list's needs, so that no buffer moves between launches
+        grad_v_sizes(mol, &pcm_mol::esp, vneed, gneed);
+        if (dyn) grad_v_sizes(mol, &pcm_mol::esp_w, vneed, gneed);
+        mol->vbuf.ensure(vneed + 1);
+        mol->gpair.ensure(gneed + 1);
         ProfScope psa(ctx, "grad_aoff", (double)M * M);
         k_grad_aoff<<<dim3(div_up(M, 256), j.rows_a), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p,
                                                                                mol->zeta.p, j.q, M, len_a, j.part_a);
