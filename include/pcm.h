@@ -307,7 +307,8 @@ pcm_status pcm_solve_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const
  * per-molecule contraction and the per-point and per-atom sums.  Each molecule's work split
  * does not depend on the others, so the results equal those of pcm_grad bit for bit.  HOST
  * arrays of DEVICE pointers P[n] (nbf_i^2), q[n] (M_i), g_nuc[n] (n_atoms_i*3, written),
- * g_surf[n] (M_i*3, written).  Errors: PCM_E_ARG (NULL array or entry). */
+ * g_surf[n] (M_i*3, written).  Errors: PCM_E_ARG (NULL array or entry), PCM_E_UNSUPPORTED
+ * (one class of the batch needs more than 2^30 work items). */
 pcm_status pcm_grad_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *P, const double *const *q,
                             double *const *g_nuc, double *const *g_surf);
 
