@@ -12,6 +12,7 @@
 //   gc:      dC R_tuv = -R_{t+1,u,v}: lane = point, contracted with the esp coefficients.
 // Per-atom sums run over fixed per-atom lists, so every result is bitwise reproducible.
 #include "pcm_internal.h"
+#include "low_order.h"
 
 #include <array>
 #include <cstring>
@@ -69,6 +70,16 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
             }
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
+                if constexpr (L == 0 && sizeof(T) == 8) {  // D R_{e_i} = (D R^(1)) X_i
+                    T x, y, z, Rn[2];
+                    eval_Rn1<T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
+                                x, y, z, Rn);
+                    const T t1 = D[b][0] * Rn[1];
+                    gx = fma(t1, x, gx);
+                    gy = fma(t1, y, gy);
+                    gz = fma(t1, z, gz);
+                    continue;
+                }
                 T R[ntuv(L + 1)];
                 eval_R<L + 1, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
                                  R);
@@ -140,6 +151,17 @@ __global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds
             }
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
+                if constexpr (L == 0 && sizeof(T) == 8) {  // q R_t with q R^(1) formed once
+                    T x, y, z, Rn[2];
+                    eval_Rn1<T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
+                                pt[b].lim, tab, x, y, z, Rn);
+                    const double u = qk[b] * Rn[1];
+                    V[0] = fma(qk[b], Rn[0], V[0]);
+                    V[1] = fma(u, x, V[1]);
+                    V[2] = fma(u, y, V[2]);
+                    V[3] = fma(u, z, V[3]);
+                    continue;
+                }
                 T R[NT];
                 eval_R<L + 1, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
                                  pt[b].lim, tab, R);

@@ -23,6 +23,7 @@
 // kernels keep more workgroups resident.  The chunk shape of each (class, size bucket) is
 // chosen by timing a few candidates on first use.
 #include "pcm_internal.h"
+#include "low_order.h"
 
 #include <algorithm>
 #include <array>
@@ -92,6 +93,15 @@ __global__ __launch_bounds__(256) void k_esp(const EspDesc *__restrict__ ds, int
             }
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
+                if constexpr (L == 1 && sizeof(T) == 8) {  // sum_t D_t R_t with R^(1) factored out
+                    T x, y, z, Rn[2];
+                    eval_Rn1<T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
+                                x, y, z, Rn);
+                    const T w = fma(D[b][1], x, fma(D[b][2], y, D[b][3] * z));
+                    acc = fma(D[b][0], Rn[0], acc);
+                    acc = fma(w, Rn[1], acc);
+                    continue;
+                }
                 T R[NT];
                 eval_R<L, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
                              R);
@@ -187,6 +197,17 @@ __global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds,
             }
 #pragma unroll
             for (int b = 0; b < PT_BATCH; ++b) {
+                if constexpr (L == 1 && sizeof(T) == 8) {  // q R_t with q R^(1) formed once
+                    T x, y, z, Rn[2];
+                    eval_Rn1<T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
+                                pt[b].lim, tab, x, y, z, Rn);
+                    const double u = qk[b] * Rn[1];
+                    V[0] = fma(qk[b], Rn[0], V[0]);
+                    V[1] = fma(u, x, V[1]);
+                    V[2] = fma(u, y, V[2]);
+                    V[3] = fma(u, z, V[3]);
+                    continue;
+                }
                 T R[NT];
                 eval_R<L, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta, pt[b].lim,
                              tab, R);
