@@ -70,6 +70,19 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
             }
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
+                if constexpr (L == 1 && sizeof(T) == 8) {
+                    // g_i = sum_t D_t R_{t + e_i} = X_i (D_0 R^(1) + R^(2) w) + D_{e_i} R^(1),
+                    // w = D_100 X + D_010 Y + D_001 Z
+                    T x, y, z, Rn[3];
+                    eval_Rn<2, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim,
+                                  tab, x, y, z, Rn);
+                    const T w = fma(D[b][1], x, fma(D[b][2], y, D[b][3] * z));
+                    const T a = fma(Rn[2], w, D[b][0] * Rn[1]);
+                    gx = fma(a, x, fma(D[b][1], Rn[1], gx));
+                    gy = fma(a, y, fma(D[b][2], Rn[1], gy));
+                    gz = fma(a, z, fma(D[b][3], Rn[1], gz));
+                    continue;
+                }
                 if constexpr (L == 0 && sizeof(T) == 8) {  // D R_{e_i} = (D R^(1)) X_i
                     T x, y, z, Rn[2];
                     eval_Rn1<T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,

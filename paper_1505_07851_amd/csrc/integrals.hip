@@ -93,6 +93,22 @@ __global__ __launch_bounds__(256) void k_esp(const EspDesc *__restrict__ ds, int
             }
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
+                if constexpr (L == 2 && sizeof(T) == 8) {
+                    // sum_t D_t R_t = D_0 R^(0) + R^(1) (D_100 X + D_010 Y + D_001 Z + D_200 + D_020 + D_002)
+                    //               + R^(2) (the quadratic form of D_200 ... D_002 in X, Y, Z)
+                    const T *Db = D[b];
+                    T x, y, z, Rn[3];
+                    eval_Rn<2, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim,
+                                  tab, x, y, z, Rn);
+                    const T q1 = fma(Db[4], x, fma(Db[5], y, Db[6] * z));
+                    const T q2 = fma(Db[7], y, Db[8] * z);
+                    const T qf = fma(x, q1, fma(y, q2, z * (Db[9] * z)));
+                    const T lin = fma(Db[1], x, fma(Db[2], y, fma(Db[3], z, Db[4] + Db[7] + Db[9])));
+                    acc = fma(Db[0], Rn[0], acc);
+                    acc = fma(lin, Rn[1], acc);
+                    acc = fma(qf, Rn[2], acc);
+                    continue;
+                }
                 if constexpr (L == 1 && sizeof(T) == 8) {  // sum_t D_t R_t with R^(1) factored out
                     T x, y, z, Rn[2];
                     eval_Rn1<T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
