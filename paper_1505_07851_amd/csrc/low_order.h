@@ -20,3 +20,21 @@ __device__ __forceinline__ void eval_Rn1(double X, double Y, double Z, const Pai
                                          const T *__restrict__ tab, T &x, T &y, T &z, T (&Rn)[2]) {
     eval_Rn<1, T>(X, Y, Z, h, zeta2, zeta, limk, tab, x, y, z, Rn);
 }
+
+// V_t += q R_t for every t with t + u + v <= 2 (index order of the Hermite tables: 000, 100,
+// 010, 001, 200, 110, 101, 020, 011, 002), with q R^(1) and q R^(2) formed once
+template <typename T>
+__device__ __forceinline__ void acc_V2(double q, T x, T y, T z, const T (&Rn)[3], double (&V)[10]) {
+    const double u1 = q * Rn[1], u2 = q * Rn[2];
+    const double ux = u2 * x, uy = u2 * y, uz = u2 * z;
+    V[0] = fma(q, Rn[0], V[0]);
+    V[1] = fma(u1, x, V[1]);
+    V[2] = fma(u1, y, V[2]);
+    V[3] = fma(u1, z, V[3]);
+    V[4] = fma(ux, x, V[4] + u1);
+    V[5] = fma(ux, y, V[5]);
+    V[6] = fma(ux, z, V[6]);
+    V[7] = fma(uy, y, V[7] + u1);
+    V[8] = fma(uy, z, V[8]);
+    V[9] = fma(uz, z, V[9] + u1);
+}
