@@ -70,6 +70,28 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
             }
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
+                if constexpr (L == 2 && sizeof(T) == 8) {
+                    // g_i = d/dX_i of S = D_0 R^(0) + lin R^(1) + Q R^(2) (the L = 2 potential, with
+                    // d R^(n) / dX_i = X_i R^(n+1)): g_i = X_i (D_0 R^(1) + lin R^(2) + Q R^(3))
+                    //   + D_{e_i} R^(1) + (dQ/dX_i) R^(2)
+                    const T *Db = D[b];
+                    T x, y, z, Rn[4];
+                    eval_Rn<3, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim,
+                                  tab, x, y, z, Rn);
+                    const T q1 = fma(Db[4], x, fma(Db[5], y, Db[6] * z));  // D_200 X + D_110 Y + D_101 Z
+                    const T q2 = fma(Db[7], y, Db[8] * z);                 // D_020 Y + D_011 Z
+                    const T zz = Db[9] * z;                                // D_002 Z
+                    const T qf = fma(x, q1, fma(y, q2, z * zz));
+                    const T lin = fma(Db[1], x, fma(Db[2], y, fma(Db[3], z, Db[4] + Db[7] + Db[9])));
+                    const T a = fma(qf, Rn[3], fma(lin, Rn[2], Db[0] * Rn[1]));
+                    const T gqx = fma(Db[4], x, q1);
+                    const T gqy = fma(Db[5], x, fma(Db[7], y, q2));
+                    const T gqz = fma(Db[6], x, fma(Db[8], y, zz + zz));
+                    gx = fma(a, x, fma(Db[1], Rn[1], fma(gqx, Rn[2], gx)));
+                    gy = fma(a, y, fma(Db[2], Rn[1], fma(gqy, Rn[2], gy)));
+                    gz = fma(a, z, fma(Db[3], Rn[1], fma(gqz, Rn[2], gz)));
+                    continue;
+                }
                 if constexpr (L == 1 && sizeof(T) == 8) {
                     // g_i = sum_t D_t R_{t + e_i} = X_i (D_0 R^(1) + R^(2) w) + D_{e_i} R^(1),
                     // w = D_100 X + D_010 Y + D_001 Z
