@@ -220,6 +220,13 @@ __global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds,
                     acc_V2<T>(qk[b], x, y, z, Rn, V);
                     continue;
                 }
+                if constexpr (L == 3 && sizeof(T) == 8) {  // q R_t with q R^(1..3) formed once
+                    T x, y, z, Rn[4];
+                    eval_Rn<3, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
+                                  pt[b].lim, tab, x, y, z, Rn);
+                    acc_V3<T>(qk[b], x, y, z, Rn, V);
+                    continue;
+                }
                 if constexpr (L == 1 && sizeof(T) == 8) {  // q R_t with q R^(1) formed once
                     T x, y, z, Rn[2];
                     eval_Rn1<T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,

@@ -38,3 +38,34 @@ __device__ __forceinline__ void acc_V2(double q, T x, T y, T z, const T (&Rn)[3]
     V[8] = fma(uy, z, V[8]);
     V[9] = fma(uz, z, V[9] + u1);
 }
+
+// V_t += q R_t for every t with t + u + v <= 3 (third-order entries in the order 300, 210, 201,
+// 120, 111, 102, 030, 021, 012, 003): R_{3 e_i} = X_i^3 R^(3) + 3 X_i R^(2),
+// R_{2 e_i + e_j} = X_i^2 X_j R^(3) + X_j R^(2), R_111 = X Y Z R^(3)
+template <typename T>
+__device__ __forceinline__ void acc_V3(double q, T x, T y, T z, const T (&Rn)[4], double (&V)[20]) {
+    const double u1 = q * Rn[1], u2 = q * Rn[2], u3 = q * Rn[3];
+    const double ux = u2 * x, uy = u2 * y, uz = u2 * z;
+    V[0] = fma(q, Rn[0], V[0]);
+    V[1] = fma(u1, x, V[1]);
+    V[2] = fma(u1, y, V[2]);
+    V[3] = fma(u1, z, V[3]);
+    V[4] = fma(ux, x, V[4] + u1);
+    V[5] = fma(ux, y, V[5]);
+    V[6] = fma(ux, z, V[6]);
+    V[7] = fma(uy, y, V[7] + u1);
+    V[8] = fma(uy, z, V[8]);
+    V[9] = fma(uz, z, V[9] + u1);
+    const double wx = u3 * x, wy = u3 * y, wz = u3 * z;
+    const double wxx = wx * x, wxy = wx * y, wyy = wy * y, wzz = wz * z;
+    V[10] = fma(wxx, x, fma(3.0, ux, V[10]));
+    V[11] = fma(wxx, y, V[11] + uy);
+    V[12] = fma(wxx, z, V[12] + uz);
+    V[13] = fma(wyy, x, V[13] + ux);
+    V[14] = fma(wxy, z, V[14]);
+    V[15] = fma(wzz, x, V[15] + ux);
+    V[16] = fma(wyy, y, fma(3.0, uy, V[16]));
+    V[17] = fma(wyy, z, V[17] + uz);
+    V[18] = fma(wzz, y, V[18] + uy);
+    V[19] = fma(wzz, z, fma(3.0, uz, V[19]));
+}
