@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
             }
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
-                if constexpr (L == 2 && sizeof(T) == 8) {
+                if constexpr (L == 2) {
                     // g_i = d/dX_i of S = D_0 R^(0) + lin R^(1) + Q R^(2) (the L = 2 potential, with
                     // d R^(n) / dX_i = X_i R^(n+1)): g_i = X_i (D_0 R^(1) + lin R^(2) + Q R^(3))
                     //   + D_{e_i} R^(1) + (dQ/dX_i) R^(2)
@@ -87,12 +87,18 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
                     const T gqx = fma(Db[4], x, q1);
                     const T gqy = fma(Db[5], x, fma(Db[7], y, q2));
                     const T gqz = fma(Db[6], x, fma(Db[8], y, zz + zz));
-                    gx = fma(a, x, fma(Db[1], Rn[1], fma(gqx, Rn[2], gx)));
-                    gy = fma(a, y, fma(Db[2], Rn[1], fma(gqy, Rn[2], gy)));
-                    gz = fma(a, z, fma(Db[3], Rn[1], fma(gqz, Rn[2], gz)));
+                    if constexpr (sizeof(T) == 8) {
+                        gx = fma(a, x, fma(Db[1], Rn[1], fma(gqx, Rn[2], gx)));
+                        gy = fma(a, y, fma(Db[2], Rn[1], fma(gqy, Rn[2], gy)));
+                        gz = fma(a, z, fma(Db[3], Rn[1], fma(gqz, Rn[2], gz)));
+                    } else {  // FP32 evaluation, one FP64 add per pair and component
+                        gx += (double)fma(a, x, fma(Db[1], Rn[1], gqx * Rn[2]));
+                        gy += (double)fma(a, y, fma(Db[2], Rn[1], gqy * Rn[2]));
+                        gz += (double)fma(a, z, fma(Db[3], Rn[1], gqz * Rn[2]));
+                    }
                     continue;
                 }
-                if constexpr (L == 1 && sizeof(T) == 8) {
+                if constexpr (L == 1) {
                     // g_i = sum_t D_t R_{t + e_i} = X_i (D_0 R^(1) + R^(2) w) + D_{e_i} R^(1),
                     // w = D_100 X + D_010 Y + D_001 Z
                     T x, y, z, Rn[3];
@@ -100,19 +106,31 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
                                   tab, x, y, z, Rn);
                     const T w = fma(D[b][1], x, fma(D[b][2], y, D[b][3] * z));
                     const T a = fma(Rn[2], w, D[b][0] * Rn[1]);
-                    gx = fma(a, x, fma(D[b][1], Rn[1], gx));
-                    gy = fma(a, y, fma(D[b][2], Rn[1], gy));
-                    gz = fma(a, z, fma(D[b][3], Rn[1], gz));
+                    if constexpr (sizeof(T) == 8) {
+                        gx = fma(a, x, fma(D[b][1], Rn[1], gx));
+                        gy = fma(a, y, fma(D[b][2], Rn[1], gy));
+                        gz = fma(a, z, fma(D[b][3], Rn[1], gz));
+                    } else {
+                        gx += (double)fma(a, x, D[b][1] * Rn[1]);
+                        gy += (double)fma(a, y, D[b][2] * Rn[1]);
+                        gz += (double)fma(a, z, D[b][3] * Rn[1]);
+                    }
                     continue;
                 }
-                if constexpr (L == 0 && sizeof(T) == 8) {  // D R_{e_i} = (D R^(1)) X_i
+                if constexpr (L == 0) {  // D R_{e_i} = (D R^(1)) X_i
                     T x, y, z, Rn[2];
                     eval_Rn1<T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
                                 x, y, z, Rn);
                     const T t1 = D[b][0] * Rn[1];
-                    gx = fma(t1, x, gx);
-                    gy = fma(t1, y, gy);
-                    gz = fma(t1, z, gz);
+                    if constexpr (sizeof(T) == 8) {
+                        gx = fma(t1, x, gx);
+                        gy = fma(t1, y, gy);
+                        gz = fma(t1, z, gz);
+                    } else {
+                        gx += (double)(t1 * x);
+                        gy += (double)(t1 * y);
+                        gz += (double)(t1 * z);
+                    }
                     continue;
                 }
                 T R[ntuv(L + 1)];
@@ -186,21 +204,21 @@ __global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds
             }
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
-                if constexpr (L == 1 && sizeof(T) == 8) {  // q R_t with q R^(1), q R^(2) formed once
+                if constexpr (L == 1) {  // q R_t with q R^(1), q R^(2) formed once
                     T x, y, z, Rn[3];
                     eval_Rn<2, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
                                   pt[b].lim, tab, x, y, z, Rn);
                     acc_V2<T>(qk[b], x, y, z, Rn, V);
                     continue;
                 }
-                if constexpr (L == 2 && sizeof(T) == 8) {  // q R_t with q R^(1..3) formed once
+                if constexpr (L == 2) {  // q R_t with q R^(1..3) formed once
                     T x, y, z, Rn[4];
                     eval_Rn<3, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
                                   pt[b].lim, tab, x, y, z, Rn);
                     acc_V3<T>(qk[b], x, y, z, Rn, V);
                     continue;
                 }
-                if constexpr (L == 0 && sizeof(T) == 8) {  // q R_t with q R^(1) formed once
+                if constexpr (L == 0) {  // q R_t with q R^(1) formed once
                     T x, y, z, Rn[2];
                     eval_Rn1<T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
                                 pt[b].lim, tab, x, y, z, Rn);

@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void k_esp(const EspDesc *__restrict__ ds, int
             }
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
-                if constexpr (L == 2 && sizeof(T) == 8) {
+                if constexpr (L == 2) {
                     // sum_t D_t R_t = D_0 R^(0) + R^(1) (D_100 X + D_010 Y + D_001 Z + D_200 + D_020 + D_002)
                     //               + R^(2) (the quadratic form of D_200 ... D_002 in X, Y, Z)
                     const T *Db = D[b];
@@ -104,18 +104,26 @@ __global__ __launch_bounds__(256) void k_esp(const EspDesc *__restrict__ ds, int
                     const T q2 = fma(Db[7], y, Db[8] * z);
                     const T qf = fma(x, q1, fma(y, q2, z * (Db[9] * z)));
                     const T lin = fma(Db[1], x, fma(Db[2], y, fma(Db[3], z, Db[4] + Db[7] + Db[9])));
-                    acc = fma(Db[0], Rn[0], acc);
-                    acc = fma(lin, Rn[1], acc);
-                    acc = fma(qf, Rn[2], acc);
+                    if constexpr (sizeof(T) == 8) {
+                        acc = fma(Db[0], Rn[0], acc);
+                        acc = fma(lin, Rn[1], acc);
+                        acc = fma(qf, Rn[2], acc);
+                    } else {  // FP32 evaluation, one FP64 add per pair
+                        acc += (double)fma(qf, Rn[2], fma(lin, Rn[1], Db[0] * Rn[0]));
+                    }
                     continue;
                 }
-                if constexpr (L == 1 && sizeof(T) == 8) {  // sum_t D_t R_t with R^(1) factored out
+                if constexpr (L == 1) {  // sum_t D_t R_t with R^(1) factored out
                     T x, y, z, Rn[2];
                     eval_Rn1<T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
                                 x, y, z, Rn);
                     const T w = fma(D[b][1], x, fma(D[b][2], y, D[b][3] * z));
-                    acc = fma(D[b][0], Rn[0], acc);
-                    acc = fma(w, Rn[1], acc);
+                    if constexpr (sizeof(T) == 8) {
+                        acc = fma(D[b][0], Rn[0], acc);
+                        acc = fma(w, Rn[1], acc);
+                    } else {
+                        acc += (double)fma(w, Rn[1], D[b][0] * Rn[0]);
+                    }
                     continue;
                 }
                 T R[NT];
@@ -213,21 +221,21 @@ __global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds,
             }
 #pragma unroll
             for (int b = 0; b < PT_BATCH; ++b) {
-                if constexpr (L == 2 && sizeof(T) == 8) {  // q R_t with q R^(1), q R^(2) formed once
+                if constexpr (L == 2) {  // q R_t with q R^(1), q R^(2) formed once
                     T x, y, z, Rn[3];
                     eval_Rn<2, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
                                   pt[b].lim, tab, x, y, z, Rn);
                     acc_V2<T>(qk[b], x, y, z, Rn, V);
                     continue;
                 }
-                if constexpr (L == 3 && sizeof(T) == 8) {  // q R_t with q R^(1..3) formed once
+                if constexpr (L == 3) {  // q R_t with q R^(1..3) formed once
                     T x, y, z, Rn[4];
                     eval_Rn<3, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
                                   pt[b].lim, tab, x, y, z, Rn);
                     acc_V3<T>(qk[b], x, y, z, Rn, V);
                     continue;
                 }
-                if constexpr (L == 1 && sizeof(T) == 8) {  // q R_t with q R^(1) formed once
+                if constexpr (L == 1) {  // q R_t with q R^(1) formed once
                     T x, y, z, Rn[2];
                     eval_Rn1<T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
                                 pt[b].lim, tab, x, y, z, Rn);
