@@ -70,6 +70,49 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
             }
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
+                if constexpr (L == 3) {
+                    // g_i = d/dX_i of S = D_0 R^(0) + lin R^(1) + quad R^(2) + C R^(3) (the L = 3
+                    // potential; quad holds the second-order terms and the first-order parts of the
+                    // third-order R_tuv, C the cubic form): g_i = X_i (D_0 R^(1) + lin R^(2) + quad R^(3)
+                    //   + C R^(4)) + D_{e_i} R^(1) + (d quad/dX_i) R^(2) + (dC/dX_i) R^(3),
+                    // with C = (X dC/dX + Y dC/dY + Z dC/dZ) / 3 (C is homogeneous of degree 3)
+                    const T *Db = D[b];
+                    T x, y, z, Rn[5];
+                    eval_Rn<4, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim,
+                                  tab, x, y, z, Rn);
+                    const T xx = x * x, xy = x * y, xz = x * z, yy = y * y, yz = y * z, zz = z * z;
+                    const T two = T(2), three = T(3);
+                    // D index: 10 300, 11 210, 12 201, 13 120, 14 111, 15 102, 16 030, 17 021, 18 012, 19 003
+                    const T dcx = fma(three * Db[10], xx, fma(two * Db[11], xy, fma(two * Db[12], xz,
+                                  fma(Db[13], yy, fma(Db[14], yz, Db[15] * zz)))));
+                    const T dcy = fma(Db[11], xx, fma(two * Db[13], xy, fma(Db[14], xz,
+                                  fma(three * Db[16], yy, fma(two * Db[17], yz, Db[18] * zz)))));
+                    const T dcz = fma(Db[12], xx, fma(Db[14], xy, fma(two * Db[15], xz,
+                                  fma(Db[17], yy, fma(two * Db[18], yz, three * Db[19] * zz)))));
+                    const T cub = fma(x, dcx, fma(y, dcy, z * dcz)) * (T(1) / three);
+                    const T gqx = fma(two * Db[4], x, fma(Db[5], y, Db[6] * z));
+                    const T gqy = fma(Db[5], x, fma(two * Db[7], y, Db[8] * z));
+                    const T gqz = fma(Db[6], x, fma(Db[8], y, two * Db[9] * z));
+                    const T bx = fma(three, Db[10], Db[13] + Db[15]);
+                    const T by = fma(three, Db[16], Db[11] + Db[18]);
+                    const T bz = fma(three, Db[19], Db[12] + Db[17]);
+                    const T quad = fma(T(0.5), fma(x, gqx, fma(y, gqy, z * gqz)), fma(bx, x, fma(by, y, bz * z)));
+                    const T lin = fma(Db[1], x, fma(Db[2], y, fma(Db[3], z, Db[4] + Db[7] + Db[9])));
+                    const T a = fma(cub, Rn[4], fma(quad, Rn[3], fma(lin, Rn[2], Db[0] * Rn[1])));
+                    const T ex = fma(dcx, Rn[3], fma(gqx + bx, Rn[2], Db[1] * Rn[1]));
+                    const T ey = fma(dcy, Rn[3], fma(gqy + by, Rn[2], Db[2] * Rn[1]));
+                    const T ez = fma(dcz, Rn[3], fma(gqz + bz, Rn[2], Db[3] * Rn[1]));
+                    if constexpr (sizeof(T) == 8) {
+                        gx = fma(a, x, gx + ex);
+                        gy = fma(a, y, gy + ey);
+                        gz = fma(a, z, gz + ez);
+                    } else {
+                        gx += (double)fma(a, x, ex);
+                        gy += (double)fma(a, y, ey);
+                        gz += (double)fma(a, z, ez);
+                    }
+                    continue;
+                }
                 if constexpr (L == 2) {
                     // g_i = d/dX_i of S = D_0 R^(0) + lin R^(1) + Q R^(2) (the L = 2 potential, with
                     // d R^(n) / dX_i = X_i R^(n+1)): g_i = X_i (D_0 R^(1) + lin R^(2) + Q R^(3))
