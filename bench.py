@@ -86,7 +86,9 @@ def hermite_flops():
 def flop_model():
     """Algorithmic FP64 flops per (primitive pair x point) evaluation, far-field branch:
     P - C (3), r^2 (5), far test (1), 1/sqrt (1), 1/r^2 (1), R^(0) (1), R^(n) (2 per n),
-    Hermite recursion H(L), contraction (2 per coefficient), accumulation (1)."""
+    Hermite recursion H(L), contraction (2 per coefficient), accumulation (1).  This counts the
+    table form (every R_tuv, then the contraction); the low-order kernels that contract R^(n) in
+    factored form do fewer operations, so their per-kernel rates on this model read high."""
     H = hermite_flops()
     m = {}
     for L in range(5):
