@@ -1,5 +1,6 @@
 // Low-order evaluations written out for the kernels of the lowest classes.  With the
-// auxiliary R^(n) of Sec. 4a's Hermite scheme, R_000 = R^(0), R_{e_i} = X_i R^(1),
+// auxiliary R^(n) of the Hermite (McMurchie-Davidson) evaluation of the Eq. 5-6 integrals,
+// R_000 = R^(0), R_{e_i} = X_i R^(1),
 // R_{2 e_i} = X_i^2 R^(2) + R^(1) and R_{e_i + e_j} = X_i X_j R^(2) (i != j); the kernels
 // contract these in factored form instead of forming every R_tuv first.
 #pragma once
