@@ -93,6 +93,34 @@ __global__ __launch_bounds__(256) void k_esp(const EspDesc *__restrict__ ds, int
             }
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
+                if constexpr (L == 3) {
+                    // sum_t D_t R_t = D_0 R^(0) + lin R^(1) + quad R^(2) + C R^(3): quad holds the
+                    // second-order terms and the first-order parts of the third-order R_tuv, C the
+                    // cubic form (D index 10 .. 19: 300, 210, 201, 120, 111, 102, 030, 021, 012, 003)
+                    const T *Db = D[b];
+                    T x, y, z, Rn[4];
+                    eval_Rn<3, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim,
+                                  tab, x, y, z, Rn);
+                    const T zz = z * z, three = T(3);
+                    const T lin = fma(Db[1], x, fma(Db[2], y, fma(Db[3], z, Db[4] + Db[7] + Db[9])));
+                    const T bx = fma(three, Db[10], Db[13] + Db[15]);
+                    const T by = fma(three, Db[16], Db[11] + Db[18]);
+                    const T bz = fma(three, Db[19], Db[12] + Db[17]);
+                    const T quad = fma(x, fma(Db[4], x, fma(Db[5], y, fma(Db[6], z, bx))),
+                                       fma(y, fma(Db[7], y, fma(Db[8], z, by)), z * fma(Db[9], z, bz)));
+                    const T cub = fma(x, fma(x, fma(Db[10], x, fma(Db[11], y, Db[12] * z)),
+                                             fma(y, fma(Db[13], y, Db[14] * z), Db[15] * zz)),
+                                      fma(y, fma(y, fma(Db[16], y, Db[17] * z), Db[18] * zz), Db[19] * zz * z));
+                    if constexpr (sizeof(T) == 8) {
+                        acc = fma(Db[0], Rn[0], acc);
+                        acc = fma(lin, Rn[1], acc);
+                        acc = fma(quad, Rn[2], acc);
+                        acc = fma(cub, Rn[3], acc);
+                    } else {
+                        acc += (double)fma(cub, Rn[3], fma(quad, Rn[2], fma(lin, Rn[1], Db[0] * Rn[0])));
+                    }
+                    continue;
+                }
                 if constexpr (L == 2) {
                     // sum_t D_t R_t = D_0 R^(0) + R^(1) (D_100 X + D_010 Y + D_001 Z + D_200 + D_020 + D_002)
                     //               + R^(2) (the quadratic form of D_200 ... D_002 in X, Y, Z)
