@@ -199,6 +199,22 @@ pcm_status pcm_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double
  * Errors: PCM_E_ARG (NULL, nranks < 1, rank outside [0, nranks)). */
 pcm_status pcm_matvec_share(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int rank, int nranks);
 
+/* pcm_matvec_share with no allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and result bits as pcm_matvec_share; every intermediate (packed
+ * points, tile boxes, a copy of x, the tile-pair list, the (nT x M) partial slots,
+ * nT = ceil(M / 256)) lives in one fixed 64 MiB device array per GPU, held from library load
+ * to process end, whose address is looked up when a context first uses the device.  That
+ * bounds M to about 45,000 points.  The call only enqueues work on the context's stream (it
+ * does not synchronise); y is complete when the stream reaches it.  Every call on one GPU
+ * shares the array and overwrites what the previous call left there, so calls that can
+ * overlap on one GPU (other streams, other contexts, other host threads) race: serialise
+ * them.  DEVICE: x[M], y[M] (written), 8-byte aligned.  Errors (no GPU work is enqueued):
+ * PCM_E_ARG (NULL, misaligned, rank outside [0, nranks), molecule of another context, or M
+ * too large for the array), PCM_E_STATE (the context has not been used on a device yet, or
+ * the current device is not the context's). */
+pcm_status pcm_matvec_share_noalloc(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int rank, int nranks);
+
 /* Gradient of the Eq. 13 energy at fixed density (Sec. 2, Eq. 14; Sec. 4c, Eq. 22) for a
  * solved q.  Primitive pairs are screened as in pcm_esp (Eq. 18).  DEVICE: P[nbf*nbf],
  * q[M]; outputs g_nuc[n_atoms*3] (derivative with respect to nuclear positions with the

@@ -19,7 +19,7 @@ PCM_THRESH_FIXED, PCM_THRESH_TWO_DELTA, PCM_THRESH_DYNAMIC = 0, 1, 2
 
 EXPORTED = ["pcm_default_params", "pcm_default_solve_opts", "pcm_create", "pcm_destroy", "pcm_last_error",
             "pcm_build_surface", "pcm_update_geometry", "pcm_esp", "pcm_fock", "pcm_solve", "pcm_energy", "pcm_grad",
-            "pcm_matvec_share", "pcm_dynamic_threshold", "pcm_default_threshold_policy", "pcm_cg_threshold", "pcm_rbj_partition",
+            "pcm_matvec_share", "pcm_matvec_share_noalloc", "pcm_dynamic_threshold", "pcm_default_threshold_policy", "pcm_cg_threshold", "pcm_rbj_partition",
             "pcm_octree_partition", "pcm_surface_get", "pcm_mol_sizes", "pcm_pair_list",
             "pcm_mol_destroy", "pcm_batch_create", "pcm_batch_destroy", "pcm_esp_batched", "pcm_fock_batched",
             "pcm_solve_batched", "pcm_grad_batched",
@@ -76,6 +76,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "pcm_energy": (i, [vp, vp, vp, vp, vp, P(d)]),
         "pcm_grad": (i, [vp, vp, vp, vp, vp, vp]),
         "pcm_matvec_share": (i, [vp, vp, vp, vp, i, i]),
+        "pcm_matvec_share_noalloc": (i, [vp, vp, vp, vp, i, i]),
         "pcm_dynamic_threshold": (d, [d]),
         "pcm_default_threshold_policy": (None, [P(pcm_threshold_policy), i]),
         "pcm_cg_threshold": (d, [P(pcm_threshold_policy), d]),

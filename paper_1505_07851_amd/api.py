@@ -235,6 +235,16 @@ class Molecule:
         self.ctx.check(self.ctx.lib.pcm_matvec_share(self.ctx.h, self.h, _dp(x), _dp(y), int(rank), int(nranks)))
         return y
 
+    def matvec_share_noalloc(self, x, y, rank=0, nranks=1):
+        """matvec_share through the allocation-free entry point: y (preallocated, M float64) is
+        written asynchronously on the context's stream; intermediates live in the library's
+        fixed per-GPU scratch array."""
+        x = _f64(x, self.M, "x").contiguous()
+        _f64(y, self.M, "y")
+        self.ctx.check(self.ctx.lib.pcm_matvec_share_noalloc(self.ctx.h, self.h, _dp(x), _dp(y), int(rank),
+                                                             int(nranks)))
+        return y
+
     def grad(self, P, q):
         """(g_nuc [N,3], g_surf [M,3]) of Eq. 14 at fixed density."""
         P = _f64(P, self.nbf * self.nbf, "P").contiguous()

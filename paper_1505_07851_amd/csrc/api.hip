@@ -410,6 +410,22 @@ pcm_status pcm_matvec_share(pcm_ctx *ctx, pcm_mol *mol, const double *x, double 
     });
 }
 
+pcm_status pcm_matvec_share_noalloc(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int rank, int nranks) {
+    if (!ctx) return PCM_E_ARG;
+    if (!mol || !x || !y) return fail(ctx, PCM_E_ARG, "NULL argument");
+    if (((uintptr_t)x | (uintptr_t)y) & 7) return fail(ctx, PCM_E_ARG, "x and y must be 8-byte aligned");
+    if (nranks < 1 || rank < 0 || rank >= nranks) return fail(ctx, PCM_E_ARG, "rank outside [0, nranks)");
+    if (mol->owner_ctx != ctx) return fail(ctx, PCM_E_ARG, "molecule built on another context");
+    if (!ctx->dev_ready) return fail(ctx, PCM_E_STATE, "context has not been used on a device yet");
+    return guarded(ctx, [&]() -> pcm_status {
+        int dev = -1;
+        HIP_OK(hipGetDevice(&dev));
+        if (dev != ctx->device) throw PcmError{PCM_E_STATE, "current device is not the context's device"};
+        run_matvec_share_noalloc(ctx, mol, x, y, rank, nranks);
+        return PCM_OK;
+    });
+}
+
 pcm_status pcm_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc, double *g_surf) {
     if (!ctx) return PCM_E_ARG;
     if (!mol || !P || !q || !g_nuc || !g_surf) return fail(ctx, PCM_E_ARG, "NULL argument");

@@ -465,6 +465,11 @@ pcm_status run_solve(pcm_ctx *ctx, pcm_mol *mol, const double *v, const pcm_solv
                      pcm_solve_info *info);
 double run_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double *c, const double *q);
 void run_matvec_share(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int rank, int nranks);
+// the same share with every intermediate in the fixed per-device scratch array (no allocation)
+void run_matvec_share_noalloc(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int rank, int nranks);
+// look up (once per device, with that device current) the address of the scratch array
+void noalloc_scratch_init(int dev);
+long long noalloc_scratch_bytes();
 void run_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc, double *g_surf,
               int prec);
 void run_grad_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<const double *> &P,

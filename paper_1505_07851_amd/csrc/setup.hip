@@ -50,6 +50,7 @@ void ctx_ensure_device(pcm_ctx *ctx) {
     HIP_OK(hipMemcpyAsync(ctx->boys64.p, t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     HIP_OK(hipMemcpyAsync(ctx->boys32.p, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
     HIP_OK(hipStreamSynchronize(ctx->stream));
+    noalloc_scratch_init(dev);
     ctx->dev_ready = true;
 }
 

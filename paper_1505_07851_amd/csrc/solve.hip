@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <type_traits>
 
 constexpr int TILE = 256;  // points per tile (rows per workgroup)
@@ -1201,4 +1202,158 @@ double run_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double *c,
     download_states(ctx, B);
     const double *d = B.h_st[0].dots;
     return d[0] + d[1] + 0.5 / f * d[2];
+}
+
+// ----------------------------------------------------------------------------------------
+// Allocation-free share of the product (pcm_matvec_share_noalloc).  The kernels are those of
+// run_matvec_share; every intermediate -- packed points, tile boxes, the copy of x, the item
+// list, the molecule table and the partial slots -- lives in one fixed device array per GPU.
+// Host code never names the array: its address on each device is looked up once, when a
+// context first uses that device, and only that address is handed to kernels.
+// ----------------------------------------------------------------------------------------
+constexpr size_t SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+constexpr int SCRATCH_MAX_DEV = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[SCRATCH_MAX_DEV] = {};
+
+void noalloc_scratch_init(int dev) {
+    if (dev < 0 || dev >= SCRATCH_MAX_DEV) return;  // such a device has no allocation-free path
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return;
+    void *p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+}
+
+static unsigned char *noalloc_scratch(int dev) {
+    if (dev < 0 || dev >= SCRATCH_MAX_DEV) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+
+// byte offsets of the intermediates inside the scratch array (each 256-byte aligned)
+struct NaLayout {
+    size_t tab, st, items, p64, p32, tbox, x, part, total;
+};
+static size_t na_up(size_t b) { return (b + 255) / 256 * 256; }
+static NaLayout na_layout(int M, long long n_items) {
+    const size_t Mp = sv_pad(M), nT = Mp / TILE;
+    NaLayout L{};
+    size_t o = 0;
+    L.tab = o;
+    o += na_up(sizeof(CGMol));
+    L.st = o;
+    o += na_up(sizeof(CGState));
+    L.items = o;
+    o += na_up(sizeof(MvItem) * (size_t)std::max<long long>(n_items, 1));
+    L.p64 = o;
+    o += na_up(sizeof(Pt<double>) * Mp);
+    L.p32 = o;
+    o += na_up(sizeof(Pt<float>) * Mp);
+    L.tbox = o;
+    o += na_up(sizeof(double) * 6 * nT);
+    L.x = o;
+    o += na_up(sizeof(double) * Mp);
+    L.part = o;
+    o += na_up(sizeof(double) * nT * (size_t)M);
+    L.total = o;
+    return L;
+}
+
+// the molecule table and state of a one-molecule call, written from kernel arguments
+__global__ void k_na_setup(CGMol m, CGState s, CGMol *__restrict__ tab, CGState *__restrict__ st) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        tab[0] = m;
+        st[0] = s;
+    }
+}
+
+// item t of the share = tile pair at position rank + t * nranks of the (I, J >= I) order, whose
+// row I starts at position I nT - I (I - 1) / 2
+__global__ void k_na_items(MvItem *__restrict__ out, int nT, int rank, int nranks, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const long long p = rank + (long long)t * nranks;
+    int lo = 0, hi = nT - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((long long)mid * nT - (long long)mid * (mid - 1) / 2 <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    const long long s = (long long)lo * nT - (long long)lo * (lo - 1) / 2;
+    out[t] = MvItem{0, lo, lo + (int)(p - s)};
+}
+
+// x copied into an Mp-long vector with a zero tail; partial slots cleared (a share writes only
+// the slots of its own tile pairs)
+__global__ void k_na_prep(const double *__restrict__ x, double *__restrict__ xv, int M, int Mp,
+                          double *__restrict__ part, long long n_part) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < Mp) xv[i] = i < M ? x[i] : 0.0;
+    for (long long k = i; k < n_part; k += (long long)gridDim.x * blockDim.x) part[k] = 0.0;
+}
+
+long long noalloc_scratch_bytes() { return (long long)SCRATCH_BYTES; }
+
+void run_matvec_share_noalloc(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int rank, int nranks) {
+    const int M = mol->M, Mp = sv_pad(M), nT = Mp / TILE;
+    const long long n_pos = (long long)nT * (nT + 1) / 2;
+    const long long n_items = rank < n_pos ? (n_pos - rank + nranks - 1) / nranks : 0;
+    const NaLayout L = na_layout(M, n_items);
+    if (L.total > SCRATCH_BYTES)
+        throw PcmError{PCM_E_ARG, "M = " + std::to_string(M) + " needs " + std::to_string(L.total) +
+                                      " bytes of scratch; the allocation-free product holds " +
+                                      std::to_string(SCRATCH_BYTES) + " (about M <= 45,000)"};
+    unsigned char *base = noalloc_scratch(ctx->device);
+    if (!base) throw PcmError{PCM_E_STATE, "no scratch address for this device (context not initialised)"};
+    if (M == 0) return;
+    CGMol *tab = reinterpret_cast<CGMol *>(base + L.tab);
+    CGState *st = reinterpret_cast<CGState *>(base + L.st);
+    MvItem *items = reinterpret_cast<MvItem *>(base + L.items);
+    Pt<double> *p64 = reinterpret_cast<Pt<double> *>(base + L.p64);
+    Pt<float> *p32 = reinterpret_cast<Pt<float> *>(base + L.p32);
+    double *tbox = reinterpret_cast<double *>(base + L.tbox);
+    double *xv = reinterpret_cast<double *>(base + L.x);
+    double *part = reinterpret_cast<double *>(base + L.part);
+    CGMol m{};
+    m.v[V_T] = xv;
+    m.pt64 = p64;
+    m.pt32 = p32;
+    m.Akk = mol->Akk.p;
+    m.part = part;
+    m.tbox = tbox;
+    m.boys64 = ctx->boys64.p;
+    m.boys32 = ctx->boys32.p;
+    double r32;
+    mv_cutoffs(mol, m.rc2_64, r32);
+    m.rc2_32 = (float)r32;
+    m.M = M;
+    m.Mp = Mp;
+    m.nT = nT;
+    m.ndp = nT;
+    m.n_rz = nT;
+    m.precond = PCM_PRECOND_NONE;
+    CGState s{};
+    s.act = 1;
+    s.done = 1;
+    hipStream_t stm = ctx->stream;
+    k_na_setup<<<1, 64, 0, stm>>>(m, s, tab, st);
+    HIP_LAUNCH_OK();
+    k_pack_pts<<<grid_for(Mp, 256), 256, 0, stm>>>(mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p, M, Mp, p64, p32);
+    HIP_LAUNCH_OK();
+    k_tile_box<<<nT, TILE, 0, stm>>>(p64, M, tbox);
+    HIP_LAUNCH_OK();
+    const long long n_part = (long long)nT * M;
+    k_na_prep<<<std::max(grid_for(Mp, 256), 1024), 256, 0, stm>>>(x, xv, M, Mp, part, n_part);
+    HIP_LAUNCH_OK();
+    if (n_items > 0) {
+        k_na_items<<<grid_for(n_items, 256), 256, 0, stm>>>(items, nT, rank, nranks, (int)n_items);
+        HIP_LAUNCH_OK();
+        k_mv_sym<double><<<(int)n_items, MV_THREADS, 0, stm>>>(tab, st, items, (int)n_items, 1, V_T);
+        HIP_LAUNCH_OK();
+    }
+    k_share_finish<<<nT, TILE, 0, stm>>>(tab, rank, nranks, V_T, y);
+    HIP_LAUNCH_OK();
 }
