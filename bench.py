@@ -98,6 +98,8 @@ def flop_model():
         b1 = 12 + 2 * (L + 1) + H[L + 1]
         m[f"grad_pts_L{L}"] = b1 + 3 * 2 * ntuv(L) + 3
         m[f"grad_v_L{L}"] = b1 + 2 * ntuv(L + 1)
+        m[f"esp_grad_pts_L{L}"] = m[f"grad_pts_L{L}"] + 2 * ntuv(L)  # the potential beside its derivative
+        m[f"fock_grad_v_L{L}"] = m[f"grad_v_L{L}"]
     # per unordered point pair (A is symmetric and each pair is evaluated once): d (3), r^2 (5),
     # far test (1), 1/sqrt (1), row FMA (2), column product (1), column sum (1)
     m["matvec"] = 14
@@ -119,9 +121,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--tol-ref", type=float, default=1e-10,
+                    help="solve tolerance of the untimed accuracy pass that every form is compared on")
+    ap.add_argument("--prof-steps", type=int, default=3, help="steps of the profiled (per-kernel) pass")
     ap.add_argument("--block", type=int, default=100)
     ap.add_argument("--workload", default="protein600",
-                    choices=["protein600", "conformers64", "stress2000", "scf_policies", "eq21_fit", "shard8", "copy"],
+                    choices=["protein600", "conformers64", "stress2000", "scf_policies", "eq21_fit", "shard8", "copy",
+                             "oracle1t"],
                     help="copy: a plain device copy of known size, to calibrate rocprofv3 byte counters")
     ap.add_argument("--max-iter-none", type=int, default=300,
                     help="stress2000: matvec budget of each unpreconditioned outer solve")
@@ -146,6 +152,8 @@ def main():
         return bench_eq21_fit(args)
     if args.workload == "shard8":
         return bench_shard(args)
+    if args.workload == "oracle1t":
+        return bench_oracle1t(args)
 
     import numpy as np
     import torch
@@ -161,30 +169,34 @@ def main():
     P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
     model = flop_model()
 
-    def run_form(prec):
+    n_prof = max(1, min(args.steps, args.prof_steps))
+
+    def run_form(prec, solve_prec=None):
+        solve_prec = solve_prec or ("mixed" if prec == "mixed" else "fp64")
+        label = prec if solve_prec != "mixed" or prec == "mixed" else "solve_mixed"
         ctx = Context(precision=prec)
         t = time.time()
         mol = Molecule.from_system(ctx, s)
         torch.cuda.synchronize()
-        log(f"[bench] {prec}: surface + pair lists built in {time.time() - t:.2f}s, M={mol.M}")
+        log(f"[bench] {label}: surface + pair lists built in {time.time() - t:.2f}s, M={mol.M}")
         state = {}
 
-        def step():
+        def step(tol=args.tol):
+            # one pass of the path: geometry, c and dc_k = dc_k/dr_k with Bz (one integral pass), the
+            # RBJ-preconditioned solve, then F += L^T q and the Eq. 14 gradient (one integral pass)
             mol.update_geometry(s.xyz)
-            c, bz = mol.esp(P)
-            q, info = mol.solve(bz + c, precond="rbj", block=args.block, seed=s.seeds["rbj"], tol=args.tol,
-                                precision="mixed" if prec == "mixed" else "fp64", q0=state.get("q"))
-            F = mol.fock(q)
-            gn, gs = mol.grad(P, q)
+            c, bz, dc = mol.esp_deriv(P)
+            q, info = mol.solve(bz + c, precond="rbj", block=args.block, seed=s.seeds["rbj"], tol=tol,
+                                precision=solve_prec, q0=state.get("q"))
+            F, gn, gs = mol.fock_grad(P, q, dc)
             state.update(c=c, bz=bz, q=q, info=info, F=F, gn=gn, gs=gs)
             return info
 
         for w in range(args.warmup):
             info = step()
             torch.cuda.synchronize()
-            log(f"[bench] {prec}: warmup {w} done, solve {info['solve_ms']:.1f} ms, iters {info['iters']}")
-        state.pop("q", None)
-        ctx.profile(True)
+            log(f"[bench] {label}: warmup {w} done, solve {info['solve_ms']:.1f} ms, iters {info['iters']}")
+        # production pass: no per-kernel events, PCG iteration groups replayed from the captured graph
         torch.cuda.synchronize()
         t = time.perf_counter()
         infos = []
@@ -193,12 +205,29 @@ def main():
             infos.append(step())
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / args.steps
+        log(f"[bench] {label}: {args.steps} steps, {dt * 1e3:.1f} ms/step")
+        # profiled pass: HIP events around every heavy launch on the library's stream; the PCG then
+        # steps one iteration at a time with the states read back, so only the kernel table and the
+        # launch durations come from it
+        ctx.profile(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k in range(n_prof):
+            state.pop("q", None)
+            step()
+        torch.cuda.synchronize()
+        dt_prof = (time.perf_counter() - t) / n_prof
         prof = ctx.profile_read()
         ctx.profile(False)
-        log(f"[bench] {prec}: {args.steps} steps, {dt * 1e3:.1f} ms/step")
+        log(f"[bench] {label}: {n_prof} profiled steps, {dt_prof * 1e3:.1f} ms/step")
+        # accuracy pass at a tight solve tolerance (untimed): the state compared across forms
+        state.pop("q", None)
+        info_t = step(tol=args.tol_ref)
+        torch.cuda.synchronize()
+        tight = {k: v for k, v in state.items()}
         sz = mol.sizes()
-        return {"ctx": ctx, "mol": mol, "ms": dt * 1e3, "prof": prof, "sizes": sz, "infos": infos,
-                "state": state}
+        return {"ctx": ctx, "mol": mol, "ms": dt * 1e3, "ms_prof": dt_prof * 1e3, "prof": prof, "sizes": sz,
+                "infos": infos, "state": state, "tight": tight, "info_tight": info_t, "label": label}
 
     r64 = run_form("fp64")
     mol = r64["mol"]
@@ -208,7 +237,7 @@ def main():
     integrals = (2 * sp_esp + sp_fock) * M   # c, gradient (esp list) and F (Eq. 15 list)
     value = integrals / (r64["ms"] * 1e-3)
 
-    # dominant kernel and its roofline
+    # dominant kernel and its roofline (launch durations from the profiled pass)
     prof = r64["prof"]
     dom = max(prof, key=lambda k: prof[k]["ms"])
     d = prof[dom]
@@ -218,26 +247,27 @@ def main():
     roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_F64_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_TFLOPS, 4), "traffic": measured_traffic(dom),
             "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops}
-    kernels = {k: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches": v["launches"],
+    kernels = {k: {"ms_per_step": round(v["ms"] / n_prof, 3), "launches": v["launches"],
                    "tflops": round(kernel_flops(k, v["work"], model) / (v["ms"] * 1e-3) / 1e12, 3)
                    if v["ms"] > 0 else None,
                    "work_units_per_s": round(v["work"] / (v["ms"] * 1e-3), 1) if v["ms"] > 0 else None}
                for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
     info64 = r64["infos"][-1]
-    st64 = r64["state"]
-    # shell-pair x point integrals/s per total angular momentum L = l_a + l_b and kernel family
-    # (classes ss, sp, sd, pp, pd, dd have L = 0, 1, 2, 2, 3, 4)
+    ref = r64["tight"]
+    E_ref = r64["info_tight"]["energy"]
+    # shell-pair x point integrals/s per total angular momentum L = l_a + l_b (classes ss, sp, sd, pp,
+    # pd, dd have L = 0, 1, 2, 2, 3, 4): the c, F and gradient integrals of the L classes over the time
+    # of their two kernels (point side with c, pair side with F)
     cls_L = [0, 1, 2, 2, 3, 4]
     by_L = {}
     for L in range(5):
         spe = sum(n for n, l in zip(sz["sp_esp"], cls_L) if l == L)
         spf = sum(n for n, l in zip(sz["sp_fock"], cls_L) if l == L)
-        t_c = prof.get(f"esp_L{L}_f64", {}).get("ms", 0.0)
-        t_f = prof.get(f"fock_v_L{L}_f64", {}).get("ms", 0.0)
-        t_g = prof.get(f"grad_pts_L{L}_f64", {}).get("ms", 0.0) + prof.get(f"grad_v_L{L}_f64", {}).get("ms", 0.0)
-        rate = lambda sp, t: round(sp * M * args.steps / (t * 1e-3), 1) if t > 0 else None
-        by_L[f"L{L}"] = {"shell_pairs_esp": spe, "shell_pairs_fock": spf, "c": rate(spe, t_c), "F": rate(spf, t_f),
-                         "grad": rate(spe, t_g)}
+        t_p = prof.get(f"esp_grad_pts_L{L}_f64", {}).get("ms", 0.0)
+        t_v = prof.get(f"fock_grad_v_L{L}_f64", {}).get("ms", 0.0)
+        rate = lambda n, t: round(n * M * n_prof / (t * 1e-3), 1) if t > 0 else None
+        by_L[f"L{L}"] = {"shell_pairs_esp": spe, "shell_pairs_fock": spf, "point_side": rate(spe, t_p),
+                         "pair_side": rate(spf, t_v), "c_F_grad": rate(2 * spe + spf, t_p + t_v)}
 
     out = {"metric": METRIC, "value": value, "unit": "shell-pair×point integrals/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r64["ms"], 3),
@@ -249,59 +279,171 @@ def main():
                       "prim_pairs_fock": sum(sz["pairs_fock"]), "precond": f"rbj{args.block}", "tol": args.tol},
            "pcg_solve_ms": round(info64["solve_ms"], 3), "pcg_setup_ms": round(info64["setup_ms"], 3),
            "pcg_iters": info64["iters"], "pcg_resid": info64["resid"], "energy": info64["energy"],
-           "roofline": roof, "integrals_per_s_by_L": by_L, "kernels": kernels}
+           "profiled_ms_per_step": round(r64["ms_prof"], 3), "profiled_steps": n_prof,
+           "roofline": roof, "integrals_per_s_by_L": by_L, "kernels": kernels,
+           "reference": {"solve_tol": args.tol_ref, "energy": E_ref, "resid": r64["info_tight"]["resid"]}}
 
-    # the mixed form (FP32 integrals and FP32 matvec in FP64 refinement) and the per-pair dynamic
-    # form (FP64 or FP32 integrals by screening bound, FP64 solve), each against the FP64 path
+    def errors(st, info_t, info_prod):
+        rel = lambda a, b: (a - b).norm().item() / b.norm().item()
+        return {"E_abs": abs(info_t["energy"] - E_ref), "E_abs_at_tol": abs(info_prod["energy"] - E_ref),
+                "q_rel_max": (st["q"] - ref["q"]).abs().max().item() / ref["q"].abs().max().item(),
+                "c_rel": rel(st["c"], ref["c"]), "F_rel": rel(st["F"], ref["F"]),
+                "g_nuc_abs_max": (st["gn"] - ref["gn"]).abs().max().item(),
+                "g_surf_abs_max": (st["gs"] - ref["gs"]).abs().max().item()}
+
+    out["err_fp64_at_tol"] = {"E_abs": abs(info64["energy"] - E_ref)}
+    # the mixed form (FP32 integral evaluation and FP32 matvec in FP64 refinement), the per-pair
+    # dynamic form (FP64 or FP32 integrals by screening bound, FP64 solve) and the solve-only mixed form
+    # (FP64 integrals, FP32 matvec in FP64 refinement), each compared with the FP64 path's state at the
+    # tight tolerance
     forms = {}
-    for form in ([] if args.no_mixed else ["mixed", "dynamic"]):
-        rmx = forms[form] = run_form(form)
+    for form, sprec in ([] if args.no_mixed else [("mixed", None), ("dynamic", None), ("fp64", "mixed")]):
+        rmx = run_form(form, sprec)
+        key = rmx["label"]
+        forms[key] = rmx
         infm = rmx["infos"][-1]
-        stm = rmx["state"]
         sm = rmx["sizes"]
         integ_m = (2 * sum(sm["sp_esp"]) + sum(sm["sp_fock"])) * rmx["mol"].M
-        dc = (stm["c"] - st64["c"]).norm().item() / st64["c"].norm().item()
-        dq = (stm["q"] - st64["q"]).abs().max().item() / st64["q"].abs().max().item()
-        dF = (stm["F"] - st64["F"]).norm().item() / st64["F"].norm().item()
-        dg = (stm["gn"] - st64["gn"]).abs().max().item()
-        out[form] = {"value": integ_m / (rmx["ms"] * 1e-3), "ms_per_step": round(rmx["ms"], 3),
-                     "speedup_vs_fp64": round(r64["ms"] / rmx["ms"], 3),
-                     "pcg_solve_ms": round(infm["solve_ms"], 3), "pcg_iters": infm["iters"],
-                     "pcg_refinements": infm["refinements"], "pcg_resid": infm["resid"],
-                     "err_vs_fp64_path": {"E_abs": abs(infm["energy"] - info64["energy"]), "c_rel": dc,
-                                          "q_rel_max": dq, "F_rel": dF, "g_nuc_abs_max": dg},
-                     "kernels": {k: round(v["ms"] / args.steps, 3) for k, v in
-                                 sorted(rmx["prof"].items(), key=lambda kv: -kv[1]["ms"])[:8]}}
+        out[key] = {"value": integ_m / (rmx["ms"] * 1e-3), "ms_per_step": round(rmx["ms"], 3),
+                    "speedup_vs_fp64": round(r64["ms"] / rmx["ms"], 3),
+                    "pcg_solve_ms": round(infm["solve_ms"], 3),
+                    "solve_speedup_vs_fp64": round(info64["solve_ms"] / infm["solve_ms"], 3),
+                    "pcg_iters": infm["iters"], "pcg_refinements": infm["refinements"], "pcg_resid": infm["resid"],
+                    "err_vs_fp64_ref": errors(rmx["tight"], rmx["info_tight"], infm),
+                    "kernels": {k: round(v["ms"] / n_prof, 3) for k, v in
+                                sorted(rmx["prof"].items(), key=lambda kv: -kv[1]["ms"])[:8]}}
         if form == "dynamic":
-            out[form]["dp_thresh"] = 1e-6
+            out[key]["dp_thresh"] = 1e-6
+        del rmx["ctx"], rmx["mol"]
 
     if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out.update(oracle_baseline(s, r64, forms, sp_esp, sp_fock))
+    print(json.dumps(out))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_baseline(s, r64, forms, sp_esp, sp_fock):
+    """The FP64 oracle timed on the host cores as it stands (a baseline, not a target), on bounded
+    samples of the same workload, in the units the GPU kernels are timed in: c (the line's value),
+    F on sampled shell pairs, one matvec on sampled rows, g_surf on sampled points, dense Cholesky
+    solves of the water and of one 64-conformer member, and 1-thread numbers in a child process.
+    Sampled figures are scaled linearly to the full workload and labelled as extrapolated."""
+    import subprocess
+    import numpy as np
+    from oracle import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    res = {}
+    t = time.time()
+    om = O.mol_from_system(s)
+    pr = om.pairs(s.P)
+    pr15 = om.pairs()
+    log(f"[bench] oracle setup {time.time() - t:.1f}s, esp list {pr['a'].shape[0]} prim pairs")
+    M = om.M
+    rng = np.random.default_rng(s.seeds["pert"])
+    order = rng.permutation(M)
+    # c: sample sized to ~12 s of oracle work from a probe of one point per thread
+    t = time.time()
+    om.esp(s.P, kidx=np.sort(order[:threads]), pairs=pr)
+    t_probe = max(time.time() - t, 1e-3)
+    n_sample = int(min(M, max(threads, threads * 12.0 / t_probe)))
+    kidx = np.sort(order[:n_sample])
+    t = time.time()
+    c_or = om.esp(s.P, kidx=kidx, pairs=pr)
+    t_c = time.time() - t
+    st64 = r64["state"]
+    c_gpu = st64["c"].cpu().numpy()[kidx]
+    res["cpu_baseline"] = {"value": sp_esp * n_sample / t_c, "unit": "shell-pair×point integrals/s",
+                           "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+                           "sample": f"c_k = sum P L^k for {n_sample} seeded surface points over the full "
+                                     f"Eq. 18 pair list ({t_c:.1f} s)"}
+    res["c_sample_rel_err_fp64"] = float(np.abs(c_gpu - c_or).max() / np.abs(c_or).max())
+    for form, rf in forms.items():
+        c_m = rf["state"]["c"].cpu().numpy()[kidx]
+        res.setdefault(form, {})
+        res[form]["c_sample_rel_err_vs_oracle"] = float(np.abs(c_m - c_or).max() / np.abs(c_or).max())
+    units = {}
+    units["c"] = {"extrapolated_full_ms": round(M / n_sample * t_c * 1e3, 1), "sample_points": n_sample,
+                  "sample_s": round(t_c, 2)}
+    # F on sampled shell pairs of the Eq. 15 list
+    qh = st64["q"].cpu().numpy()
+    sps = sorted(set(zip(pr15["a"].tolist(), pr15["b"].tolist())))
+    pick = rng.choice(len(sps), size=min(len(sps), 400), replace=False)
+    t = time.time()
+    om.fock(qh, shell_pairs=[sps[i] for i in pick], pairs=pr15)
+    t_f = time.time() - t
+    n_f = len(pick)
+    units["F"] = {"extrapolated_full_ms": round(sp_fock / n_f * t_f * 1e3, 1), "sample_shell_pairs": n_f,
+                  "sample_s": round(t_f, 2), "shell_pair_x_point_per_s": round(n_f * M / t_f, 1)}
+    # one A x on sampled rows (the oracle evaluates whole rows: M evaluations each)
+    rows = np.sort(order[:min(M, 4 * threads * 64)])
+    x = rng.normal(size=M)
+    t = time.time()
+    om.matvec(x, kidx=rows)
+    t_m = time.time() - t
+    units["matvec"] = {"extrapolated_full_ms": round(M / rows.shape[0] * t_m * 1e3, 2),
+                       "sample_rows": int(rows.shape[0]), "sample_s": round(t_m, 3)}
+    # g_surf on sampled points (c term over the Eq. 18 list, the A and B terms of each point)
+    kg = np.sort(order[:max(threads, 2 * threads)])
+    t = time.time()
+    om.grad_surface_points(s.P, qh, kg, pairs=pr)
+    t_g = time.time() - t
+    units["g_surf"] = {"extrapolated_full_ms": round(M / kg.shape[0] * t_g * 1e3, 1),
+                       "sample_points": int(kg.shape[0]), "sample_s": round(t_g, 2)}
+    # dense solves (Cholesky of A, Eq. 1) at the water and at one member of the 64 conformers
+    from synth import inputs as I
+    for name, sysobj in (("water", I.water_tiny()), ("conformer0", I.conformer(0))):
+        omx = O.mol_from_system(sysobj)
         t = time.time()
-        om = O.mol_from_system(s)
-        pr = om.pairs(s.P)
-        log(f"[bench] oracle setup {time.time() - t:.1f}s, esp list {pr['a'].shape[0]} prim pairs")
-        # size the sample to ~15 s of oracle work: time one point per thread first
-        rng = np.random.default_rng(s.seeds["pert"])
-        order = rng.permutation(om.M)
-        t = time.time()
-        om.esp(s.P, kidx=np.sort(order[:threads]), pairs=pr)
-        t_probe = max(time.time() - t, 1e-3)
-        n_sample = int(min(om.M, max(threads, threads * 15.0 / t_probe)))
-        kidx = np.sort(order[:n_sample])
-        t = time.time()
-        c_or = om.esp(s.P, kidx=kidx, pairs=pr)
-        t_cpu = time.time() - t
-        c_gpu = st64["c"].cpu().numpy()[kidx]
-        out["cpu_baseline"] = {"value": sp_esp * n_sample / t_cpu, "unit": "shell-pair×point integrals/s",
-                               "cores": threads, "kind": "oracle",
-                               "sample": f"c_k = sum P L^k for {n_sample} seeded surface points over the full "
-                                         f"Eq. 18 pair list ({t_cpu:.1f} s)"}
-        out["c_sample_rel_err_fp64"] = float(np.abs(c_gpu - c_or).max() / np.abs(c_or).max())
-        for form, rf in forms.items():
-            c_m = rf["state"]["c"].cpu().numpy()[kidx]
-            out[form]["c_sample_rel_err_vs_oracle"] = float(np.abs(c_m - c_or).max() / np.abs(c_or).max())
+        v = omx.bz() + (omx.esp(sysobj.P) if name == "water" else 0.0)
+        A = omx.amat()
+        omx.solve_dense(v, A)
+        units[f"dense_solve_{name}"] = {"ms": round((time.time() - t) * 1e3, 2), "M": int(omx.M),
+                                        "note": "A built and Cholesky-solved" +
+                                                ("" if name == "water" else "; v = Bz only")}
+    res["cpu_baseline"]["units"] = units
+    # 1-thread numbers in a child process (OpenMP and BLAS read their thread counts at start)
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--workload", "oracle1t"], env=env,
+                           capture_output=True, text=True, timeout=300)
+        res["cpu_baseline"]["one_thread"] = json.loads(r.stdout.strip().splitlines()[-1])
+    except Exception as e:  # reported, not fatal: the baseline is context only
+        res["cpu_baseline"]["one_thread"] = {"error": str(e)[:200]}
+    return res
+
+
+def bench_oracle1t(args):
+    """1-thread oracle figures (run by oracle_baseline in a child process): the whole water case
+    (Bz, c, A, Cholesky, energy) and c on 64 points of one member of the 64 conformers."""
+    import numpy as np
+    from oracle import oracle as O
+    from synth import inputs as I
+    out = {"threads": int(os.environ.get("OMP_NUM_THREADS", "0"))}
+    s = I.water_tiny()
+    om = O.mol_from_system(s)
+    t = time.time()
+    O.full_solution(om, s.P)
+    out["water_full_path_ms"] = round((time.time() - t) * 1e3, 2)
+    s = I.conformer(0)
+    om = O.mol_from_system(s)
+    pr = om.pairs(s.P)
+    kidx = np.sort(np.random.default_rng(7).permutation(om.M)[:64])
+    t = time.time()
+    om.esp(s.P, kidx=kidx, pairs=pr)
+    dt = time.time() - t
+    n_sp = len(set(zip(pr["a"].tolist(), pr["b"].tolist())))
+    out["conformer0_c"] = {"M": int(om.M), "sample_points": 64, "sample_s": round(dt, 2),
+                           "extrapolated_full_ms": round(om.M / 64 * dt * 1e3, 1),
+                           "shell_pair_x_point_per_s": round(n_sp * 64 / dt, 1)}
     print(json.dumps(out))
 
 

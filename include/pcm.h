@@ -174,6 +174,30 @@ pcm_status pcm_update_geometry(pcm_ctx *ctx, pcm_mol *mol, const double *xyz, co
  * written with (B z)_k = sum_J Z_J erf(zeta_k |r_k-R_J|)/|r_k-R_J| (Eq. 4). */
 pcm_status pcm_esp(pcm_ctx *ctx, pcm_mol *mol, const double *P, double *c, double *bz);
 
+/* c (as pcm_esp) together with dc_k = d c_k / d r_k, the derivative of c_k with respect to the
+ * position of its own surface point (Sec. 4c, Eq. 22: the operator-centre term gc of the
+ * gradient, gc_k = q_k dc_k, reduced over primitive pairs like c).  One pass over the Eq. 18
+ * list: the Hermite auxiliary values R^(0..L+1) of each (pair, point) evaluation give both the
+ * potential and its derivative.  c equals pcm_esp's c to rounding (a different work split).
+ * DEVICE: P[nbf*nbf], c[M] (written), bz[M] (may be NULL; Eq. 4), dc[M*3] (written), each
+ * 8-byte aligned.  Errors: PCM_E_ARG (NULL or misaligned). */
+pcm_status pcm_esp_deriv(pcm_ctx *ctx, pcm_mol *mol, const double *P, double *c, double *bz, double *dc);
+
+/* F += sum_k q_k L^k (Eq. 10) and the Eq. 14 gradient (as pcm_fock followed by pcm_grad) in one
+ * integral pass.  The Fock sums V_tuv = sum_k q_k R_tuv(k) (t+u+v <= L) are the low orders of the
+ * V'_tuv (t+u+v <= L+1) that the basis-centre derivatives ga, gb of Eq. 22 contract, so both are
+ * accumulated once per primitive pair over the union of the Eq. 15 list (used for F) and the
+ * Eq. 18 list for P (used for the gradient); each entry contributes only to the terms whose list
+ * holds it, so F and the gradient equal pcm_fock's and pcm_grad's to rounding.  The
+ * operator-centre term takes dc from pcm_esp_deriv, which must have been called with the same P
+ * at the current geometry (not checked).  With PCM_DYNAMIC precision the two lists keep their
+ * own precision split and F is accumulated in a pass of its own.
+ * DEVICE: P[nbf*nbf], q[M], dc[M*3], F[nbf*nbf] (accumulated), g_nuc[n_atoms*3] and
+ * g_surf[M*3] (written; as pcm_grad), each 8-byte aligned.  Errors: PCM_E_ARG (NULL or
+ * misaligned), PCM_E_UNSUPPORTED (a class needs more than 2^30 work items). */
+pcm_status pcm_fock_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, const double *dc, double *F,
+                         double *g_nuc, double *g_surf);
+
 /* F_{mu nu} += sum_k q_k L^k_{mu nu} (Sec. 2, Eq. 10; Sec. 4a, Eqs. 16-17), over the Eq. 15
  * list; the full symmetric matrix is accumulated.  DEVICE: q[M], F[nbf*nbf] (in/out). */
 pcm_status pcm_fock(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F);

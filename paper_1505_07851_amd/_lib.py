@@ -18,7 +18,7 @@ PCM_PRECOND_NONE, PCM_PRECOND_JACOBI, PCM_PRECOND_RBJ, PCM_PRECOND_OCTREE = 0, 1
 PCM_THRESH_FIXED, PCM_THRESH_TWO_DELTA, PCM_THRESH_DYNAMIC = 0, 1, 2
 
 EXPORTED = ["pcm_default_params", "pcm_default_solve_opts", "pcm_create", "pcm_destroy", "pcm_last_error",
-            "pcm_build_surface", "pcm_update_geometry", "pcm_esp", "pcm_fock", "pcm_solve", "pcm_energy", "pcm_grad",
+            "pcm_build_surface", "pcm_update_geometry", "pcm_esp", "pcm_esp_deriv", "pcm_fock", "pcm_fock_grad", "pcm_solve", "pcm_energy", "pcm_grad",
             "pcm_matvec_share", "pcm_matvec_share_noalloc", "pcm_dynamic_threshold", "pcm_default_threshold_policy", "pcm_cg_threshold", "pcm_rbj_partition",
             "pcm_octree_partition", "pcm_surface_get", "pcm_mol_sizes", "pcm_pair_list",
             "pcm_mol_destroy", "pcm_batch_create", "pcm_batch_destroy", "pcm_esp_batched", "pcm_fock_batched",
@@ -72,6 +72,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "pcm_update_geometry": (i, [vp, vp, vp, vp]),
         "pcm_esp": (i, [vp, vp, vp, vp, vp]),
         "pcm_fock": (i, [vp, vp, vp, vp]),
+        "pcm_esp_deriv": (i, [vp, vp, vp, vp, vp, vp]),
+        "pcm_fock_grad": (i, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "pcm_solve": (i, [vp, vp, vp, P(pcm_solve_opts), vp, P(pcm_solve_info)]),
         "pcm_energy": (i, [vp, vp, vp, vp, vp, P(d)]),
         "pcm_grad": (i, [vp, vp, vp, vp, vp, vp]),

@@ -196,6 +196,28 @@ class Molecule:
         self.ctx.check(self.ctx.lib.pcm_esp(self.ctx.h, self.h, _dp(P), _dp(c), _dp(bz) if want_bz else None))
         return (c, bz) if want_bz else c
 
+    def esp_deriv(self, P, want_bz=True):
+        """(c, bz, dc): c = L P (Eqs. 5-6), Bz (Eq. 4) and dc [M, 3] = d c_k / d r_k in one pass."""
+        P = _f64(P, self.nbf * self.nbf, "P").contiguous()
+        c = self._zeros(self.M)
+        dc = self._zeros(self.M, 3)
+        bz = self._zeros(self.M) if want_bz else None
+        self.ctx.check(self.ctx.lib.pcm_esp_deriv(self.ctx.h, self.h, _dp(P), _dp(c), _dp(bz), _dp(dc)))
+        return c, bz, dc
+
+    def fock_grad(self, P, q, dc, F=None):
+        """(F, g_nuc, g_surf): F += sum_k q_k L^k (Eq. 10) and the Eq. 14 gradient in one pass;
+        dc from esp_deriv with the same P."""
+        P = _f64(P, self.nbf * self.nbf, "P").contiguous()
+        q = _f64(q, self.M, "q").contiguous()
+        dc = _f64(dc, 3 * self.M, "dc").contiguous()
+        F = self._zeros(self.nbf, self.nbf) if F is None else F
+        gn = self._zeros(self.n_atoms, 3)
+        gs = self._zeros(self.M, 3)
+        self.ctx.check(self.ctx.lib.pcm_fock_grad(self.ctx.h, self.h, _dp(P), _dp(q), _dp(dc), _dp(F), _dp(gn),
+                                                  _dp(gs)))
+        return F, gn, gs
+
     def fock(self, q, F=None):
         """F += sum_k q_k L^k (Eq. 10); returns F."""
         q = _f64(q, self.M, "q").contiguous()

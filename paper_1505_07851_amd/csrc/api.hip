@@ -12,6 +12,10 @@ namespace {
 
 bool is_fin(double x) { return std::isfinite(x); }
 
+// device arrays of FP64 (and int32 pairs) must be 8-byte aligned; NULL counts as aligned
+bool misaligned(const void *p) { return ((uintptr_t)p & 7) != 0; }
+template <typename... A> bool any_misaligned(const A *...p) { return (misaligned(p) || ...); }
+
 pcm_status fail(pcm_ctx *ctx, pcm_status st, const std::string &msg) {
     if (ctx) ctx->err = msg;
     return st;
@@ -44,7 +48,7 @@ void release_list(PairList &pl) {
 void release_mol(pcm_mol *m) {
     rbj_pending_drop(m);
     DevBuf<double> *dbl[] = {&m->xyz, &m->Z, &m->rad, &m->dirs, &m->w, &m->pexp, &m->pcoef, &m->cn, &m->px, &m->py,
-                             &m->pz, &m->zeta, &m->S, &m->Akk, &m->qpad, &m->part, &m->vbuf,
+                             &m->pz, &m->zeta, &m->S, &m->Akk, &m->qpad, &m->part, &m->vbuf, &m->r_surf_buf,
                              &m->fprim, &m->gpair, &m->gsp, &m->sv, &m->rbj_inv};
     for (auto *b : dbl) b->release();
     DevBuf<int> *ints[] = {&m->sl, &m->snp, &m->soff, &m->satom, &m->bfo, &m->cnoff, &m->keep, &m->spa, &m->spb,
@@ -60,6 +64,9 @@ void release_mol(pcm_mol *m) {
     release_list(m->esp);
     release_list(m->fock_w);
     release_list(m->esp_w);
+    release_list(m->fg);
+    m->m18.release();
+    m->c18.release();
 }
 
 // candidate shell pairs, classes concatenated; (a, b) with l_a <= l_b (a <= b for equal l)
@@ -325,12 +332,11 @@ pcm_status pcm_update_geometry(pcm_ctx *ctx, pcm_mol *mol, const double *xyz, co
         ctx_ensure_device(ctx);
         mol->h_xyz.assign(xyz, xyz + 3 * mol->N);
         upload(ctx, mol->xyz, mol->h_xyz.data(), mol->h_xyz.size());
-        DevBuf<double> rs;
-        if (r_surf) upload(ctx, rs, r_surf, 3 * (size_t)mol->M);
-        surface_points(ctx, mol, r_surf ? rs.p : nullptr);
+        // explicit points go through a buffer the molecule keeps (sized once, reused by later calls)
+        if (r_surf) upload(ctx, mol->r_surf_buf, r_surf, 3 * (size_t)mol->M);
+        surface_points(ctx, mol, r_surf ? mol->r_surf_buf.p : nullptr);
         lists_geometry(ctx, mol);
         HIP_OK(hipStreamSynchronize(ctx->stream));
-        rs.release();
         mol->esp_valid = false;
         mol->rbj_valid = false;
         rbj_prefetch(ctx, mol);
@@ -354,6 +360,7 @@ static pcm_status density_list(pcm_ctx *ctx, pcm_mol *mol, const double *P) {
 pcm_status pcm_esp(pcm_ctx *ctx, pcm_mol *mol, const double *P, double *c, double *bz) {
     if (!ctx) return PCM_E_ARG;
     if (!mol || !P || !c) return fail(ctx, PCM_E_ARG, "NULL argument");
+    if (any_misaligned(P, c, bz)) return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         density_list(ctx, mol, P);
@@ -363,9 +370,42 @@ pcm_status pcm_esp(pcm_ctx *ctx, pcm_mol *mol, const double *P, double *c, doubl
     });
 }
 
+pcm_status pcm_esp_deriv(pcm_ctx *ctx, pcm_mol *mol, const double *P, double *c, double *bz, double *dc) {
+    if (!ctx) return PCM_E_ARG;
+    if (!mol || !P || !c || !dc) return fail(ctx, PCM_E_ARG, "NULL argument");
+    if (any_misaligned(P, c, bz, dc))
+        return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
+    return guarded(ctx, [&]() -> pcm_status {
+        ctx_ensure_device(ctx);
+        density_list(ctx, mol, P);
+        run_esp_deriv(ctx, mol, c, dc, ctx->prm.precision);
+        if (bz) run_bz(ctx, mol, bz);
+        return PCM_OK;
+    });
+}
+
+pcm_status pcm_fock_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, const double *dc, double *F,
+                         double *g_nuc, double *g_surf) {
+    if (!ctx) return PCM_E_ARG;
+    if (!mol || !P || !q || !dc || !F || !g_nuc || !g_surf) return fail(ctx, PCM_E_ARG, "NULL argument");
+    if (any_misaligned(P, q, dc, F, g_nuc, g_surf))
+        return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
+    return guarded(ctx, [&]() -> pcm_status {
+        ctx_ensure_device(ctx);
+        const int prec = ctx->prm.precision;
+        if (prec == PCM_DYNAMIC)
+            density_list(ctx, mol, P);  // the gradient's pair side runs over the split Eq. 18 lists
+        else
+            pairs_merged_build(ctx, mol, P, prec);
+        run_fock_grad(ctx, mol, P, q, dc, F, g_nuc, g_surf, prec);
+        return PCM_OK;
+    });
+}
+
 pcm_status pcm_fock(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F) {
     if (!ctx) return PCM_E_ARG;
     if (!mol || !q || !F) return fail(ctx, PCM_E_ARG, "NULL argument");
+    if (any_misaligned(q, F)) return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         run_fock(ctx, mol, q, F, ctx->prm.precision);
@@ -377,6 +417,7 @@ pcm_status pcm_solve(pcm_ctx *ctx, pcm_mol *mol, const double *v, const pcm_solv
                      pcm_solve_info *info) {
     if (!ctx) return PCM_E_ARG;
     if (!mol || !v || !q) return fail(ctx, PCM_E_ARG, "NULL argument");
+    if (any_misaligned(v, q)) return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
     pcm_solve_opts o;
     pcm_status vs = check_solve_opts(ctx, opts, o);
     if (vs != PCM_OK) return vs;
@@ -391,6 +432,7 @@ pcm_status pcm_solve(pcm_ctx *ctx, pcm_mol *mol, const double *v, const pcm_solv
 pcm_status pcm_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double *c, const double *q, double *E) {
     if (!ctx) return PCM_E_ARG;
     if (!mol || !bz || !c || !q || !E) return fail(ctx, PCM_E_ARG, "NULL argument");
+    if (any_misaligned(bz, c, q)) return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         *E = run_energy(ctx, mol, bz, c, q);
@@ -401,6 +443,7 @@ pcm_status pcm_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double
 pcm_status pcm_matvec_share(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int rank, int nranks) {
     if (!ctx) return PCM_E_ARG;
     if (!mol || !x || !y) return fail(ctx, PCM_E_ARG, "NULL argument");
+    if (any_misaligned(x, y)) return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
     if (nranks < 1 || rank < 0 || rank >= nranks) return fail(ctx, PCM_E_ARG, "rank outside [0, nranks)");
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
@@ -413,7 +456,7 @@ pcm_status pcm_matvec_share(pcm_ctx *ctx, pcm_mol *mol, const double *x, double 
 pcm_status pcm_matvec_share_noalloc(pcm_ctx *ctx, pcm_mol *mol, const double *x, double *y, int rank, int nranks) {
     if (!ctx) return PCM_E_ARG;
     if (!mol || !x || !y) return fail(ctx, PCM_E_ARG, "NULL argument");
-    if (((uintptr_t)x | (uintptr_t)y) & 7) return fail(ctx, PCM_E_ARG, "x and y must be 8-byte aligned");
+    if (any_misaligned(x, y)) return fail(ctx, PCM_E_ARG, "x and y must be 8-byte aligned");
     if (nranks < 1 || rank < 0 || rank >= nranks) return fail(ctx, PCM_E_ARG, "rank outside [0, nranks)");
     if (mol->owner_ctx != ctx) return fail(ctx, PCM_E_ARG, "molecule built on another context");
     if (!ctx->dev_ready) return fail(ctx, PCM_E_STATE, "context has not been used on a device yet");
@@ -429,6 +472,7 @@ pcm_status pcm_matvec_share_noalloc(pcm_ctx *ctx, pcm_mol *mol, const double *x,
 pcm_status pcm_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc, double *g_surf) {
     if (!ctx) return PCM_E_ARG;
     if (!mol || !P || !q || !g_nuc || !g_surf) return fail(ctx, PCM_E_ARG, "NULL argument");
+    if (any_misaligned(P, q, g_nuc, g_surf)) return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         density_list(ctx, mol, P);
@@ -501,6 +545,8 @@ pcm_status pcm_surface_get(pcm_ctx *ctx, const pcm_mol *mol, double *r, double *
                            int *owner, int *sph) {
     if (!ctx) return PCM_E_ARG;
     if (!mol) return fail(ctx, PCM_E_ARG, "NULL molecule");
+    if (any_misaligned(r, zeta, S, Akk)) return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
+    if (((uintptr_t)owner | (uintptr_t)sph) & 3) return fail(ctx, PCM_E_ARG, "device int arrays must be 4-byte aligned");
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         const size_t M = mol->M;
@@ -670,8 +716,11 @@ pcm_status pcm_esp_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *
     if (!ctx) return PCM_E_ARG;
     if (!batch || !P || !c) return fail(ctx, PCM_E_ARG, "NULL argument");
     const int n = (int)batch->mols.size();
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
         if (!P[i] || !c[i]) return fail(ctx, PCM_E_ARG, "NULL matrix or vector in batch");
+        if (any_misaligned(P[i], c[i], bz ? bz[i] : nullptr))
+            return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
+    }
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         for (int i = 0; i < n; ++i) density_list(ctx, batch->mols[i], P[i]);
@@ -687,8 +736,10 @@ pcm_status pcm_fock_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const 
     if (!ctx) return PCM_E_ARG;
     if (!batch || !q || !F) return fail(ctx, PCM_E_ARG, "NULL argument");
     const int n = (int)batch->mols.size();
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
         if (!q[i] || !F[i]) return fail(ctx, PCM_E_ARG, "NULL matrix or vector in batch");
+        if (any_misaligned(q[i], F[i])) return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
+    }
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         run_fock_batch(ctx, batch->mols, std::vector<const double *>(q, q + n), std::vector<double *>(F, F + n),
@@ -702,8 +753,11 @@ pcm_status pcm_grad_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const 
     if (!ctx) return PCM_E_ARG;
     if (!batch || !P || !q || !g_nuc || !g_surf) return fail(ctx, PCM_E_ARG, "NULL argument");
     const int n = (int)batch->mols.size();
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
         if (!P[i] || !q[i] || !g_nuc[i] || !g_surf[i]) return fail(ctx, PCM_E_ARG, "NULL matrix or vector in batch");
+        if (any_misaligned(P[i], q[i], g_nuc[i], g_surf[i]))
+            return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
+    }
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         for (int i = 0; i < n; ++i) density_list(ctx, batch->mols[i], P[i]);
@@ -719,8 +773,10 @@ pcm_status pcm_solve_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const
     if (!ctx) return PCM_E_ARG;
     if (!batch || !v || !q) return fail(ctx, PCM_E_ARG, "NULL argument");
     const int n = (int)batch->mols.size();
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
         if (!v[i] || !q[i]) return fail(ctx, PCM_E_ARG, "NULL vector in batch");
+        if (any_misaligned(v[i], q[i])) return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
+    }
     pcm_solve_opts o;
     pcm_status vs = check_solve_opts(ctx, opts, o);
     if (vs != PCM_OK) return vs;

@@ -37,7 +37,9 @@ struct GradVDesc {
     int stride, n_pairs, Mpad, chunk, nptile;
 };
 
-template <int L, typename T>
+// WC: also accumulate the potential c_k = sum_t D_t R_t (Eqs. 5-6), which the R^(n) of the
+// derivative contain (orders 0 .. L of the L+1 evaluated); rows are then 4 wide (gx, gy, gz, c)
+template <int L, typename T, bool WC>
 __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict__ ds, int nd, long long n_items,
                                                   const T *__restrict__ boys_g) {
     constexpr int NT = ntuv(L), PB = pair_batch<L + 1>();
@@ -56,7 +58,7 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
         const PtInt<T> me = pts[k < M ? k : M - 1];
         const int p0 = ch * d.chunk;
         const int p1 = min(d.n_pad, p0 + d.chunk);
-        double gx = 0.0, gy = 0.0, gz = 0.0;
+        double gx = 0.0, gy = 0.0, gz = 0.0, cc = 0.0;
         for (int ip = p0; ip < p1; ip += PB) {
             PairHdr<T> h[PB];
             T D[PB][NT];
@@ -106,10 +108,17 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
                         gx = fma(a, x, gx + ex);
                         gy = fma(a, y, gy + ey);
                         gz = fma(a, z, gz + ez);
+                        if constexpr (WC) {
+                            cc = fma(Db[0], Rn[0], cc);
+                            cc = fma(lin, Rn[1], cc);
+                            cc = fma(quad, Rn[2], cc);
+                            cc = fma(cub, Rn[3], cc);
+                        }
                     } else {
                         gx += (double)fma(a, x, ex);
                         gy += (double)fma(a, y, ey);
                         gz += (double)fma(a, z, ez);
+                        if constexpr (WC) cc += (double)fma(cub, Rn[3], fma(quad, Rn[2], fma(lin, Rn[1], Db[0] * Rn[0])));
                     }
                     continue;
                 }
@@ -134,10 +143,16 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
                         gx = fma(a, x, fma(Db[1], Rn[1], fma(gqx, Rn[2], gx)));
                         gy = fma(a, y, fma(Db[2], Rn[1], fma(gqy, Rn[2], gy)));
                         gz = fma(a, z, fma(Db[3], Rn[1], fma(gqz, Rn[2], gz)));
+                        if constexpr (WC) {
+                            cc = fma(Db[0], Rn[0], cc);
+                            cc = fma(lin, Rn[1], cc);
+                            cc = fma(qf, Rn[2], cc);
+                        }
                     } else {  // FP32 evaluation, one FP64 add per pair and component
                         gx += (double)fma(a, x, fma(Db[1], Rn[1], gqx * Rn[2]));
                         gy += (double)fma(a, y, fma(Db[2], Rn[1], gqy * Rn[2]));
                         gz += (double)fma(a, z, fma(Db[3], Rn[1], gqz * Rn[2]));
+                        if constexpr (WC) cc += (double)fma(qf, Rn[2], fma(lin, Rn[1], Db[0] * Rn[0]));
                     }
                     continue;
                 }
@@ -153,10 +168,15 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
                         gx = fma(a, x, fma(D[b][1], Rn[1], gx));
                         gy = fma(a, y, fma(D[b][2], Rn[1], gy));
                         gz = fma(a, z, fma(D[b][3], Rn[1], gz));
+                        if constexpr (WC) {
+                            cc = fma(D[b][0], Rn[0], cc);
+                            cc = fma(w, Rn[1], cc);
+                        }
                     } else {
                         gx += (double)fma(a, x, D[b][1] * Rn[1]);
                         gy += (double)fma(a, y, D[b][2] * Rn[1]);
                         gz += (double)fma(a, z, D[b][3] * Rn[1]);
+                        if constexpr (WC) cc += (double)fma(w, Rn[1], D[b][0] * Rn[0]);
                     }
                     continue;
                 }
@@ -169,10 +189,12 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
                         gx = fma(t1, x, gx);
                         gy = fma(t1, y, gy);
                         gz = fma(t1, z, gz);
+                        if constexpr (WC) cc = fma(D[b][0], Rn[0], cc);
                     } else {
                         gx += (double)(t1 * x);
                         gy += (double)(t1 * y);
                         gz += (double)(t1 * z);
+                        if constexpr (WC) cc += (double)(D[b][0] * Rn[0]);
                     }
                     continue;
                 }
@@ -185,26 +207,30 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
                         gx = fma(D[b][t], R[TuvShift<L>::x(t)], gx);
                         gy = fma(D[b][t], R[TuvShift<L>::y(t)], gy);
                         gz = fma(D[b][t], R[TuvShift<L>::z(t)], gz);
+                        if constexpr (WC) cc = fma(D[b][t], R[t], cc);  // orders <= L come first in R
                     }
                 } else {  // FP32 evaluation, one FP64 add per pair
-                    T sx = T(0), sy = T(0), sz = T(0);
+                    T sx = T(0), sy = T(0), sz = T(0), sc = T(0);
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
                         sx = fma(D[b][t], R[TuvShift<L>::x(t)], sx);
                         sy = fma(D[b][t], R[TuvShift<L>::y(t)], sy);
                         sz = fma(D[b][t], R[TuvShift<L>::z(t)], sz);
+                        if constexpr (WC) sc = fma(D[b][t], R[t], sc);
                     }
                     gx += (double)sx;
                     gy += (double)sy;
                     gz += (double)sz;
+                    if constexpr (WC) cc += (double)sc;
                 }
             }
         }
         if (k < M) {
-            const size_t base = (size_t)(d.row0 + ch) * 3 * M;
+            const size_t base = (size_t)(d.row0 + ch) * (WC ? 4 : 3) * M;
             d.part[base + k] = gx;
             d.part[base + M + k] = gy;
             d.part[base + 2 * M + k] = gz;
+            if constexpr (WC) d.part[base + 3 * M + k] = cc;
         }
     }
 }
@@ -295,10 +321,15 @@ __global__ void k_grad_contract(long long n, int nch, const double *__restrict__
                                 const int *__restrict__ satom, const int *__restrict__ bfo,
                                 const int *__restrict__ cnoff, const double *__restrict__ pexp,
                                 const double *__restrict__ cn, const double *__restrict__ xyz,
-                                const double *__restrict__ P, int nbf, double *__restrict__ gpair) {
+                                const double *__restrict__ P, int nbf, double *__restrict__ gpair,
+                                const unsigned long long *__restrict__ memb) {
     constexpr int L = LA + LB, NT = ntuv(L + 1);
     long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
+    if (memb && !((memb[ent_sp[q]] >> ent_ij[q]) & 1ull)) {  // entry of a merged list outside this term's list
+        for (int d = 0; d < 6; ++d) gpair[(size_t)q * 6 + d] = 0.0;
+        return;
+    }
     double V[NT];
     for (int t = 0; t < NT; ++t) {
         double s = 0.0;
@@ -373,7 +404,7 @@ __global__ __launch_bounds__(64 * GCW_WAVES) void k_grad_contract_w(
     const int *__restrict__ snp, const int *__restrict__ soff, const int *__restrict__ satom,
     const int *__restrict__ bfo, const int *__restrict__ cnoff, const double *__restrict__ pexp,
     const double *__restrict__ cn, const double *__restrict__ xyz, const double *__restrict__ P, int nbf,
-    double *__restrict__ gpair) {
+    double *__restrict__ gpair, const unsigned long long *__restrict__ memb) {
     constexpr int L = LA + LB, NT = ntuv(L + 1), IM = LA + 1, JM = LB + 1, TS = IM + JM + 1;
     constexpr int ES = herm1d_size<IM, JM>(), NA = ncart(LA), NB = ncart(LB);
     static_assert(NA * NB <= 64, "one lane per product of Cartesian components");
@@ -382,7 +413,8 @@ __global__ __launch_bounds__(64 * GCW_WAVES) void k_grad_contract_w(
     __shared__ double sG[GCW_WAVES][6][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const long long q = (long long)blockIdx.x * GCW_WAVES + w;
-    const bool valid = q < n;
+    // an entry of a merged list outside this term's list contributes zeros
+    const bool valid = q < n && (!memb || ((memb[ent_sp[q]] >> ent_ij[q]) & 1ull));
     int a = 0, b = 0, i = 0, j = 0;
     double ea = 0.0, eb = 0.0;
     if (valid) {
@@ -453,7 +485,7 @@ __global__ __launch_bounds__(64 * GCW_WAVES) void k_grad_contract_w(
 #pragma unroll
     for (int d = 0; d < 6; ++d) sG[w][d][lane] = g[d];
     __syncthreads();
-    if (valid && lane < 6) {
+    if (q < n && lane < 6) {
         double acc = 0.0;
         for (int l = 0; l < NA * NB; ++l) acc += sG[w][lane][l];
         gpair[(size_t)q * 6 + lane] = acc;
@@ -557,7 +589,7 @@ __global__ __launch_bounds__(256) void k_grad_surf(int M, const double *__restri
                                                    const double *__restrict__ rad, int N, double inv_f,
                                                    const double *__restrict__ part_a, int rows_a,
                                                    const double *__restrict__ part_c, int rows_c,
-                                                   double *__restrict__ gs) {
+                                                   const double *__restrict__ dc, double *__restrict__ gs) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= M) return;
     double qk = q[k];
@@ -565,6 +597,10 @@ __global__ __launch_bounds__(256) void k_grad_surf(int M, const double *__restri
     for (int d = 0; d < 3; ++d) {
         double sa = 0.0, sc = 0.0;
         for (int r = 0; r < rows_a; ++r) sa += part_a[((size_t)r * 3 + d) * M + k];
+        if (dc) {  // c term from dc_k = d c_k / d r_k given by the caller
+            g[d] = fma(qk, dc[3 * k + d], inv_f * qk * sa);
+            continue;
+        }
         for (int r = 0; r < rows_c; ++r) sc += part_c[((size_t)r * 3 + d) * M + k];
         g[d] = inv_f * qk * sa - qk * sc;
     }
@@ -681,6 +717,7 @@ struct GradJob {
     double *g_nuc, *g_surf;
     int rows_a, rows_c, row0;  // A_off rows, c-term rows, next free c-term row
     double *part_a, *part_c;
+    const double *dc = nullptr;  // given d c_k / d r_k: the c term's point side is not evaluated
 };
 
 // c term of one pair list for every molecule (charges already in qpad): per class, one launch of
@@ -688,8 +725,10 @@ struct GradJob {
 // (V' up to L+1) over all molecules, then per molecule the contraction to ga/gb and the sums per
 // candidate shell pair into gsp (added when `add`).  The work split of a molecule does not
 // depend on the other molecules, so a batched call gives the same bits as single calls.
+// do_pts / do_pairs select the sides; with_c makes the point side also evaluate c (4-wide rows).
 template <typename T>
-static void grad_cterm(pcm_ctx *ctx, std::vector<GradJob> &jobs, ListSel ls, bool add) {
+static void grad_cterm(pcm_ctx *ctx, std::vector<GradJob> &jobs, ListSel ls, bool add, bool do_pts = true,
+                       bool do_pairs = true, bool with_c = false) {
     const T *tab = sizeof(T) == 8 ? (const T *)ctx->boys64.p : (const T *)ctx->boys32.p;
     const char *suffix = sizeof(T) == 8 ? "_f64" : "_f32";
     auto pts_of = [](pcm_mol *mol) -> const void * { return sizeof(T) == 8 ? (const void *)mol->pti64.p
@@ -754,19 +793,22 @@ static void grad_cterm(pcm_ctx *ctx, std::vector<GradJob> &jobs, ListSel ls, boo
             const GradPtsDesc *dpp = reinterpret_cast<const GradPtsDesc *>(dev);
             const GradVDesc *dvp = reinterpret_cast<const GradVDesc *>(dev + pb);
             const int nd = (int)dp.size();
-            {
-                ProfScope ps(ctx, "grad_pts_L" + std::to_string(L) + suffix, work);
+            if (do_pts) {
+                ProfScope ps(ctx, (with_c ? "esp_grad_pts_L" : "grad_pts_L") + std::to_string(L) + suffix, work);
                 switch (L) {
 #define GP_CASE(LL)                                                                                    \
     case LL:                                                                                           \
-        k_grad_pts<LL, T><<<int_grid(items_p), 256, 0, ctx->stream>>>(dpp, nd, items_p, tab);          \
+        if (with_c)                                                                                    \
+            k_grad_pts<LL, T, true><<<int_grid(items_p), 256, 0, ctx->stream>>>(dpp, nd, items_p, tab); \
+        else                                                                                           \
+            k_grad_pts<LL, T, false><<<int_grid(items_p), 256, 0, ctx->stream>>>(dpp, nd, items_p, tab); \
         break;
                     GP_CASE(0) GP_CASE(1) GP_CASE(2) GP_CASE(3) GP_CASE(4)
 #undef GP_CASE
                 }
                 HIP_LAUNCH_OK();
             }
-            {
+            if (do_pairs) {
                 ProfScope ps(ctx, "grad_v_L" + std::to_string(L) + suffix, work);
                 switch (L) {
 #define GV_CASE(LL)                                                                                    \
@@ -780,7 +822,7 @@ static void grad_cterm(pcm_ctx *ctx, std::vector<GradJob> &jobs, ListSel ls, boo
             }
         }
         // per molecule: contraction of V' to (ga, gb) per primitive pair, sums per shell pair
-        for (size_t i = 0; i < nj; ++i) {
+        for (size_t i = 0; i < nj && do_pairs; ++i) {
             GradJob &j = jobs[i];
             pcm_mol *mol = j.mol;
             const PairList &pl = mol->*ls;
@@ -801,13 +843,13 @@ static void grad_cterm(pcm_ctx *ctx, std::vector<GradJob> &jobs, ListSel ls, boo
         k_grad_contract<LA_, LB_><<<g, 64, 0, ctx->stream>>>(n, nch, mol->vbuf.p, es, ei, mol->spa.p, mol->spb.p,  \
                                                              mol->snp.p, mol->soff.p, mol->satom.p, mol->bfo.p,    \
                                                              mol->cnoff.p, mol->pexp.p, mol->cn.p, mol->xyz.p,     \
-                                                             P, mol->nbf, mol->gpair.p);                               \
+                                                             P, mol->nbf, mol->gpair.p, nullptr);                      \
         break;
 #define GCW_CASE(CI, LA_, LB_)                                                                                     \
     case CI:                                                                                                       \
         k_grad_contract_w<LA_, LB_><<<div_up(n, GCW_WAVES), 64 * GCW_WAVES, 0, ctx->stream>>>(                      \
             n, nch, mol->vbuf.p, es, ei, mol->spa.p, mol->spb.p, mol->snp.p, mol->soff.p, mol->satom.p, mol->bfo.p, \
-            mol->cnoff.p, mol->pexp.p, mol->cn.p, mol->xyz.p, P, mol->nbf, mol->gpair.p);                           \
+            mol->cnoff.p, mol->pexp.p, mol->cn.p, mol->xyz.p, P, mol->nbf, mol->gpair.p, nullptr);                  \
         break;
             switch (cl) {
                 GC_CASE(0, 0, 0)
@@ -826,6 +868,8 @@ static void grad_cterm(pcm_ctx *ctx, std::vector<GradJob> &jobs, ListSel ls, boo
         }
     }
 }
+
+static void grad_finish(pcm_ctx *ctx, std::vector<GradJob> &jobs, double inv_f);
 
 // Eq. 14 at fixed density for one or more molecules: A off-diagonal rows, the c term of the
 // list(s), then per point (g_surf) and per atom (g_nuc) with the B and switching terms
@@ -867,6 +911,11 @@ static void grad_run(pcm_ctx *ctx, std::vector<GradJob> &all, int prec) {
         grad_cterm<double>(ctx, jobs, &pcm_mol::esp, false);
         if (dyn) grad_cterm<float>(ctx, jobs, &pcm_mol::esp_w, true);
     }
+    grad_finish(ctx, jobs, inv_f);
+}
+
+// per point (g_surf: A off-diagonal rows, c term, B and switching terms) and per atom (g_nuc)
+static void grad_finish(pcm_ctx *ctx, std::vector<GradJob> &jobs, double inv_f) {
     for (GradJob &j : jobs) {
         pcm_mol *mol = j.mol;
         const int M = mol->M;
@@ -874,7 +923,7 @@ static void grad_run(pcm_ctx *ctx, std::vector<GradJob> &all, int prec) {
         k_grad_surf<<<div_up(M, 256), 256, 0, ctx->stream>>>(M, mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p,
                                                              mol->Akk.p, mol->keep.p, mol->nsph, j.q, mol->xyz.p,
                                                              mol->Z.p, mol->rad.p, mol->N, inv_f, j.part_a, j.rows_a,
-                                                             j.part_c, j.rows_c, j.g_surf);
+                                                             j.part_c, j.rows_c, j.dc, j.g_surf);
         HIP_LAUNCH_OK();
         k_grad_nuc<<<mol->N, 256, 0, ctx->stream>>>(mol->N, M, mol->px.p, mol->py.p, mol->pz.p, mol->zeta.p,
                                                     mol->Akk.p, mol->keep.p, mol->nsph, j.q, mol->xyz.p, mol->Z.p,
@@ -898,4 +947,186 @@ void run_grad_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std:
     for (size_t i = 0; i < mols.size(); ++i)
         jobs.push_back(GradJob{mols[i], P[i], q[i], g_nuc[i], g_surf[i], 0, 0, 0, nullptr, nullptr});
     grad_run(ctx, jobs, prec);
+}
+
+// -------------------------------------------------------------------------------------------
+// One-pass forms.  c and dc_k = d c_k / d r_k come from the gradient's point side with the
+// potential accumulated beside the derivative (the R^(n) it needs are a subset of those the
+// derivative evaluates); the Fock sums V_tuv (t + u + v <= L) are the low orders of the V'_tuv
+// the gradient's pair side accumulates, so one pass over the merged Eq. 15 / Eq. 18 list feeds
+// both contractions.
+// -------------------------------------------------------------------------------------------
+// c[k] = sum_r part[r][3][k], dc[3k + d] = -sum_r part[r][d][k] (rows in a fixed order)
+__global__ __launch_bounds__(256) void k_field_sum(const double *__restrict__ part, int rows, int M,
+                                                   double *__restrict__ c, double *__restrict__ dc) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int r = 0; r < rows; ++r) {
+        const double *p = part + (size_t)r * 4 * M + k;
+        s0 += p[0];
+        s1 += p[(size_t)M];
+        s2 += p[2 * (size_t)M];
+        s3 += p[3 * (size_t)M];
+    }
+    c[k] = s3;
+    dc[3 * k] = -s0;
+    dc[3 * k + 1] = -s1;
+    dc[3 * k + 2] = -s2;
+}
+
+void run_esp_deriv(pcm_ctx *ctx, pcm_mol *mol, double *c, double *dc, int prec) {
+    const int M = mol->M;
+    const bool dyn = prec == PCM_DYNAMIC;
+    GradJob j{mol, nullptr, nullptr, nullptr, nullptr, 0, 0, 0, nullptr, nullptr};
+    j.rows_c = grad_rows(mol, &pcm_mol::esp) + (dyn ? grad_rows(mol, &pcm_mol::esp_w) : 0);
+    mol->part.ensure((size_t)(j.rows_c + 1) * 4 * M);
+    j.part_c = mol->part.p;
+    std::vector<GradJob> jobs{j};
+    if (prec == PCM_MIXED) {
+        grad_cterm<float>(ctx, jobs, &pcm_mol::esp, false, true, false, true);
+    } else {
+        grad_cterm<double>(ctx, jobs, &pcm_mol::esp, false, true, false, true);
+        if (dyn) grad_cterm<float>(ctx, jobs, &pcm_mol::esp_w, false, true, false, true);
+    }
+    k_field_sum<<<grid_for(M, 256), 256, 0, ctx->stream>>>(mol->part.p, jobs[0].row0, M, c, dc);
+    HIP_LAUNCH_OK();
+}
+
+// pair side over the merged list, the Fock contraction (Eq. 15 entries) and the gradient
+// contraction (Eq. 18 entries) of each class, sums per candidate shell pair into gsp
+template <typename T>
+static void fock_grad_pairs(pcm_ctx *ctx, pcm_mol *mol, const double *P, double *F) {
+    const T *tab = sizeof(T) == 8 ? (const T *)ctx->boys64.p : (const T *)ctx->boys32.p;
+    const char *suffix = sizeof(T) == 8 ? "_f64" : "_f32";
+    const PairList &pl = mol->fg;
+    for (int cl = 0; cl < NCLS; ++cl) {
+        const int L = CLS_LA[cl] + CLS_LB[cl];
+        const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
+        const long long sp0 = mol->sp_cls_off[cl], ncs = mol->sp_cls_off[cl + 1] - sp0;
+        if (!n) {
+            if (ncs) HIP_OK(hipMemsetAsync(mol->gsp.p + sp0 * 6, 0, sizeof(double) * 6 * ncs, ctx->stream));
+            continue;
+        }
+        GradVDesc b{};
+        b.rec = pl.rec.p + pl.rec_off[cl];
+        b.pts = sizeof(T) == 8 ? (const void *)mol->pti64.p : (const void *)mol->pti32.p;
+        b.q = mol->qpad.p;
+        b.vout = mol->vbuf.p;
+        b.base = 0;
+        b.stride = (int)align16(sizeof(PairHdr<T>));
+        b.n_pairs = (int)n;
+        b.Mpad = mol->Mpad;
+        b.chunk = grad_v_chunk(mol, &pcm_mol::fg, cl);
+        b.nptile = div_up(n, 256);
+        const int nch = div_up(mol->Mpad, b.chunk);
+        const long long items = (long long)b.nptile * nch;
+        if (items > (1LL << 30)) throw PcmError{PCM_E_UNSUPPORTED, "Fock + gradient pass too large for one launch"};
+        const GradVDesc *dv = (const GradVDesc *)upload_desc(ctx, &b, sizeof(b));
+        {
+            ProfScope ps(ctx, "fock_grad_v_L" + std::to_string(L) + suffix, (double)n * mol->M);
+            switch (L) {
+#define GV_CASE(LL)                                                                                    \
+    case LL:                                                                                           \
+        k_grad_v<LL, T><<<int_grid(items), 256, 0, ctx->stream>>>(dv, 1, items, tab);                  \
+        break;
+                GV_CASE(0) GV_CASE(1) GV_CASE(2) GV_CASE(3) GV_CASE(4)
+#undef GV_CASE
+            }
+            HIP_LAUNCH_OK();
+        }
+        fock_contract_scatter(ctx, mol, pl, cl, mol->vbuf.p, nch, ntuv(L + 1), mol->fock.mask.p, F);
+        const int *es = pl.ent_sp.p + pl.cls_off[cl], *ei = pl.ent_ij.p + pl.cls_off[cl];
+        const unsigned long long *memb = mol->m18.p;
+        ProfScope ps2(ctx, "grad_contract", (double)n);
+#define GC_CASE(CI, LA_, LB_)                                                                                      \
+    case CI:                                                                                                       \
+        k_grad_contract<LA_, LB_><<<div_up(n, 64), 64, 0, ctx->stream>>>(                                          \
+            n, nch, mol->vbuf.p, es, ei, mol->spa.p, mol->spb.p, mol->snp.p, mol->soff.p, mol->satom.p, mol->bfo.p, \
+            mol->cnoff.p, mol->pexp.p, mol->cn.p, mol->xyz.p, P, mol->nbf, mol->gpair.p, memb);                     \
+        break;
+#define GCW_CASE(CI, LA_, LB_)                                                                                     \
+    case CI:                                                                                                       \
+        k_grad_contract_w<LA_, LB_><<<div_up(n, GCW_WAVES), 64 * GCW_WAVES, 0, ctx->stream>>>(                      \
+            n, nch, mol->vbuf.p, es, ei, mol->spa.p, mol->spb.p, mol->snp.p, mol->soff.p, mol->satom.p, mol->bfo.p, \
+            mol->cnoff.p, mol->pexp.p, mol->cn.p, mol->xyz.p, P, mol->nbf, mol->gpair.p, memb);                     \
+        break;
+        switch (cl) {
+            GC_CASE(0, 0, 0)
+            GC_CASE(1, 0, 1)
+            GC_CASE(2, 0, 2)
+            GC_CASE(3, 1, 1)
+            GCW_CASE(4, 1, 2)
+            GCW_CASE(5, 2, 2)
+        }
+#undef GC_CASE
+#undef GCW_CASE
+        HIP_LAUNCH_OK();
+        k_grad_sp<<<div_up(ncs, 128), 128, 0, ctx->stream>>>(sp0, ncs, pl.cls_off[cl], pl.spo.p, mol->gpair.p,
+                                                             mol->gsp.p, 0);
+        HIP_LAUNCH_OK();
+    }
+}
+
+void run_fock_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, const double *dc, double *F,
+                   double *g_nuc, double *g_surf, int prec) {
+    const double inv_f = (ctx->prm.eps + ctx->prm.k_factor) / (ctx->prm.eps - 1.0);
+    const int M = mol->M;
+    if (prec == PCM_DYNAMIC) {
+        // the precision split differs between the two lists: F and the gradient's pair side run
+        // over their own lists, the point side comes from dc
+        run_fock(ctx, mol, q, F, prec);
+        GradJob j{mol, P, q, g_nuc, g_surf, 0, 0, 0, nullptr, nullptr};
+        j.dc = dc;
+        std::vector<GradJob> all{j};
+        HIP_OK(hipMemcpyAsync(mol->qpad.p, q, sizeof(double) * M, hipMemcpyDeviceToDevice, ctx->stream));
+        const int len_a = chunk_for(M, M, GRAD_MIN_AOFF);
+        GradJob &g = all[0];
+        g.rows_a = div_up(M, len_a);
+        mol->part.ensure((size_t)(g.rows_a + 1) * 3 * M);
+        g.part_a = mol->part.p;
+        mol->gsp.ensure((size_t)mol->sp_cls_off[NCLS] * 6 + 6);
+        size_t vneed = 0, gneed = 0;
+        grad_v_sizes(mol, &pcm_mol::esp, vneed, gneed);
+        grad_v_sizes(mol, &pcm_mol::esp_w, vneed, gneed);
+        mol->vbuf.ensure(vneed + 1);
+        mol->gpair.ensure(gneed + 1);
+        {
+            ProfScope psa(ctx, "grad_aoff", (double)M * M);
+            k_grad_aoff<<<dim3(div_up(M, 256), g.rows_a), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p,
+                                                                                  mol->zeta.p, q, M, len_a, g.part_a);
+            HIP_LAUNCH_OK();
+        }
+        grad_cterm<double>(ctx, all, &pcm_mol::esp, false, false, true);
+        grad_cterm<float>(ctx, all, &pcm_mol::esp_w, true, false, true);
+        grad_finish(ctx, all, inv_f);
+    } else {
+        HIP_OK(hipMemcpyAsync(mol->qpad.p, q, sizeof(double) * M, hipMemcpyDeviceToDevice, ctx->stream));
+        const int len_a = chunk_for(M, M, GRAD_MIN_AOFF);
+        const int rows_a = div_up(M, len_a);
+        mol->part.ensure((size_t)(rows_a + 1) * 3 * M);
+        mol->gsp.ensure((size_t)mol->sp_cls_off[NCLS] * 6 + 6);
+        size_t vneed = 0, gneed = 0, fneed = 0;
+        grad_v_sizes(mol, &pcm_mol::fg, vneed, gneed);
+        for (int cl = 0; cl < NCLS; ++cl)
+            fneed = std::max(fneed, (size_t)(mol->fg.cls_off[cl + 1] - mol->fg.cls_off[cl]) * ncart(CLS_LA[cl]) *
+                                        ncart(CLS_LB[cl]));
+        mol->vbuf.ensure(vneed + 1);
+        mol->gpair.ensure(gneed + 1);
+        mol->fprim.ensure(fneed + 1);
+        {
+            ProfScope psa(ctx, "grad_aoff", (double)M * M);
+            k_grad_aoff<<<dim3(div_up(M, 256), rows_a), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p,
+                                                                                mol->zeta.p, q, M, len_a, mol->part.p);
+            HIP_LAUNCH_OK();
+        }
+        if (prec == PCM_MIXED)
+            fock_grad_pairs<float>(ctx, mol, P, F);
+        else
+            fock_grad_pairs<double>(ctx, mol, P, F);
+        GradJob j{mol, P, q, g_nuc, g_surf, rows_a, 0, 0, mol->part.p, nullptr};
+        j.dc = dc;
+        std::vector<GradJob> all{j};
+        grad_finish(ctx, all, inv_f);
+    }
 }

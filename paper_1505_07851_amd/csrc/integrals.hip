@@ -297,6 +297,9 @@ struct FockCDesc {
     long long n, nsp;        // primitive pairs of the class, candidate shell pairs of the class
     long long sp0, cls_off;  // first candidate shell pair, offset of the class in the list
     int nch, nbf;
+    int vnt;                          // V entries per (chunk, pair): ntuv(L), or ntuv(L+1) for V' of the gradient
+    const unsigned long long *memb;   // null, or per candidate shell pair the bits of this term's list: an
+                                      // entry of a merged list without its bit gets a zero block
     const double *vin;
     const int *es, *ei, *spo, *spa, *spb, *snp, *soff, *satom, *cnoff, *bfo;
     const double *pexp, *cn, *xyz;
@@ -321,13 +324,17 @@ __global__ void k_fock_contract(const FockCDesc *__restrict__ ds, int nd, long l
     if (it >= total) return;
     const FockCDesc &d = ds[find_desc(ds, nd, it)];
     const long long q = it - d.base, n = d.n;
+    int sp = d.es[q], ij = d.ei[q];
+    if (d.memb && !((d.memb[sp] >> ij) & 1ull)) {
+        for (int c = 0; c < NC; ++c) d.fprim[(size_t)q * NC + c] = 0.0;
+        return;
+    }
     double V[NT];
     for (int t = 0; t < NT; ++t) {
         double s = 0.0;
-        for (int c = 0; c < d.nch; ++c) s += d.vin[((size_t)c * NT + t) * n + q];
+        for (int c = 0; c < d.nch; ++c) s += d.vin[((size_t)c * d.vnt + t) * n + q];
         V[t] = s;
     }
-    int sp = d.es[q], ij = d.ei[q];
     int a = d.spa[sp], b = d.spb[sp], i = ij >> 3, j = ij & 7;
     double ea = d.pexp[d.soff[a] + i], eb = d.pexp[d.soff[b] + j], p = ea + eb;
     const double *A = d.xyz + 3 * d.satom[a], *B = d.xyz + 3 * d.satom[b];
@@ -368,9 +375,10 @@ __global__ __launch_bounds__(64 * FCW_WAVES) void k_fock_contract_w(const FockCD
     __shared__ double sE[FCW_WAVES][3][ES];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const long long it = (long long)blockIdx.x * FCW_WAVES + w;
-    const bool valid = it < total;
-    const FockCDesc &d = ds[valid ? find_desc(ds, nd, it) : 0];
+    const bool in_range = it < total;
+    const FockCDesc &d = ds[in_range ? find_desc(ds, nd, it) : 0];
     const long long q = it - d.base, n = d.n;
+    const bool valid = in_range && (!d.memb || ((d.memb[d.es[q]] >> d.ei[q]) & 1ull));
     int a = 0, b = 0, i = 0, j = 0;
     if (valid) {
         const int sp = d.es[q], ij = d.ei[q];
@@ -380,7 +388,7 @@ __global__ __launch_bounds__(64 * FCW_WAVES) void k_fock_contract_w(const FockCD
         j = ij & 7;
         if (lane < NT) {
             double acc = 0.0;
-            for (int c = 0; c < d.nch; ++c) acc += d.vin[((size_t)c * NT + lane) * n + q];
+            for (int c = 0; c < d.nch; ++c) acc += d.vin[((size_t)c * d.vnt + lane) * n + q];
             sV[w][lane] = acc;
         }
         if (lane < 3) {
@@ -391,7 +399,11 @@ __global__ __launch_bounds__(64 * FCW_WAVES) void k_fock_contract_w(const FockCD
         }
     }
     __syncthreads();
-    if (!valid || lane >= NC) return;
+    if (!in_range || lane >= NC) return;
+    if (!valid) {
+        d.fprim[(size_t)q * NC + lane] = 0.0;
+        return;
+    }
     const int mu = lane / NB, nu = lane - mu * NB;
     int ax, ay, az, bx, by, bz;
     cart_comp(LA, mu, ax, ay, az);
@@ -780,6 +792,8 @@ static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const s
             d.cls_off = pl.cls_off[cl];
             d.nch = div_up(mol->Mpad, chunk[i][cl]);
             d.nbf = mol->nbf;
+            d.vnt = ntuv(CLS_LA[cl] + CLS_LB[cl]);
+            d.memb = nullptr;
             d.vin = mol->vbuf.p;
             d.es = pl.ent_sp.p + pl.cls_off[cl];
             d.ei = pl.ent_ij.p + pl.cls_off[cl];
@@ -866,4 +880,67 @@ void run_fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std:
 
 void run_fock(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F, int prec) {
     run_fock_batch(ctx, {mol}, {q}, {F}, prec);
+}
+
+// Contraction to F blocks and scatter into F (one molecule, class cl of list pl) of V sums that
+// another pass accumulated: vin[(c * vnt + t) * n + q] for chunk c < nch, vnt >= ntuv(L); with
+// memb, entries of pl whose bit is clear add zero blocks (pl is then a merged list).
+void fock_contract_scatter(pcm_ctx *ctx, pcm_mol *mol, const PairList &pl, int cl, const double *vin, int nch,
+                           int vnt, const unsigned long long *memb, double *F) {
+    const long long np = pl.cls_off[cl + 1] - pl.cls_off[cl];
+    const long long nsp = mol->sp_cls_off[cl + 1] - mol->sp_cls_off[cl];
+    if (np == 0 || nsp == 0) return;
+    FockCDesc d{};
+    d.base = 0;
+    d.sbase = 0;
+    d.n = np;
+    d.sp0 = mol->sp_cls_off[cl];
+    d.nsp = nsp;
+    d.cls_off = pl.cls_off[cl];
+    d.nch = nch;
+    d.nbf = mol->nbf;
+    d.vnt = vnt;
+    d.memb = memb;
+    d.vin = vin;
+    d.es = pl.ent_sp.p + pl.cls_off[cl];
+    d.ei = pl.ent_ij.p + pl.cls_off[cl];
+    d.spo = pl.spo.p;
+    d.spa = mol->spa.p;
+    d.spb = mol->spb.p;
+    d.snp = mol->snp.p;
+    d.soff = mol->soff.p;
+    d.satom = mol->satom.p;
+    d.cnoff = mol->cnoff.p;
+    d.bfo = mol->bfo.p;
+    d.pexp = mol->pexp.p;
+    d.cn = mol->cn.p;
+    d.xyz = mol->xyz.p;
+    d.fprim = mol->fprim.p;
+    d.F = F;
+    const FockCDesc *cdc = (const FockCDesc *)upload_desc(ctx, &d, sizeof(d));
+    const int g = grid_for(np, 128), gs = grid_for(nsp, 128);
+    ProfScope ps(ctx, "fock_contract", (double)np);
+#define FC_CASE(CI, LA_, LB_)                                                                                      \
+    case CI:                                                                                                       \
+        k_fock_contract<LA_, LB_><<<g, 128, 0, ctx->stream>>>(cdc, 1, np);                                         \
+        HIP_LAUNCH_OK();                                                                                           \
+        k_fock_scatter<LA_, LB_><<<gs, 128, 0, ctx->stream>>>(cdc, 1, nsp);                                        \
+        break;
+#define FCW_CASE(CI, LA_, LB_)                                                                                     \
+    case CI:                                                                                                       \
+        k_fock_contract_w<LA_, LB_><<<grid_for(np, FCW_WAVES), 64 * FCW_WAVES, 0, ctx->stream>>>(cdc, 1, np);       \
+        HIP_LAUNCH_OK();                                                                                           \
+        k_fock_scatter<LA_, LB_><<<gs, 128, 0, ctx->stream>>>(cdc, 1, nsp);                                        \
+        break;
+    switch (cl) {
+        FC_CASE(0, 0, 0)
+        FC_CASE(1, 0, 1)
+        FC_CASE(2, 0, 2)
+        FC_CASE(3, 1, 1)
+        FCW_CASE(4, 1, 2)
+        FCW_CASE(5, 2, 2)
+    }
+#undef FC_CASE
+#undef FCW_CASE
+    HIP_LAUNCH_OK();
 }

@@ -13,8 +13,7 @@ __device__ __forceinline__ void eval_Rn(double X, double Y, double Z, const Pair
     x = T(X);
     y = T(Y);
     z = T(Z);
-    const T r2 = x * x + y * y + z * z;
-    aux_Rn<N, T>(r2, h.p, h.limp, h.pf, h.pref, zeta2, zeta, limk, tab, Rn);
+    aux_Rn<N, T>(dist2<T>(X, Y, Z), h.p, h.limp, h.pf, h.pref, zeta2, zeta, limk, tab, Rn);
 }
 template <typename T>
 __device__ __forceinline__ void eval_Rn1(double X, double Y, double Z, const PairHdr<T> &h, T zeta2, T zeta, T limk,

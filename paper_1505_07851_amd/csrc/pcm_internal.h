@@ -64,8 +64,8 @@ __host__ __device__ inline void cart_comp(int l, int c, int &ax, int &ay, int &a
 // ----------------------------------------------------------------------------------------
 // Boys function tables.  F_m(T_i) at T_i = i/8; Taylor expansion around the nearest node:
 // F_m(T) = sum_k F_{m+k}(T_i) (T_i - T)^k / k!.  FP64: order 8 on [0, 40); FP32: order 4 on
-// [0, 30).  Above the range the asymptotic form is exact to the working precision (see
-// aux_Rn).
+// [0, 30).  Above the range the asymptotic form is used, whose neglected tail is bounded in
+// aux_Rn (below 2e-12 relative at T = 40 for the orders used here).
 // ----------------------------------------------------------------------------------------
 template <typename T> struct BoysCfg;
 template <> struct BoysCfg<double> {
@@ -96,8 +96,15 @@ template <typename T> __host__ __device__ constexpr size_t rec_stride(int L) {
 // Auxiliary values R^(n)_000 (n = 0..L) of one (pair, point) evaluation, prefactors included.
 //   near: (2 pi/p) sqrt(u) (-2 a)^n F_n(a r^2),  u = z^2/(z^2+p), a = p u;
 //   far (a r^2 >= TMAX): the smeared charge acts as a point charge and the attenuation
-//   drops out: (pi/p)^{3/2} (-1)^n (2n-1)!! / r^{2n+1}.
-// The far test a r^2 >= TMAX is r^2 >= TMAX/p + TMAX/z^2.
+//   drops out: (pi/p)^{3/2} (-1)^n (2n-1)!! / r^{2n+1}.  The terms left out are bounded by the
+//   upper incomplete gamma tail, e^{-T} T^{n-1/2} / Gamma(n+1/2) relative to F_n(T): below
+//   2e-12 at T = 40 for n <= 5 (FP64), below 1e-8 at T = 30 (FP32 kernels).
+// The far test a r^2 >= TMAX is r^2 >= TMAX/p + TMAX/z^2.  r^2 comes in FP64 (the squared FP64
+// differences P - C).  In the FP32 kernels the large-T branch still runs in FP64 (reciprocal
+// square root and the R^(n) chain, each value rounded once to FP32): only the Boys-table
+// interpolation of the near field and the Hermite build run in FP32.  The hardware FP32
+// reciprocal square root is biased (about -7e-9 relative on average), and the far field
+// carries most of every potential, so an FP32 far branch would shift c coherently.
 // ----------------------------------------------------------------------------------------
 __device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
 __device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
@@ -127,11 +134,25 @@ constexpr int PT_PAD = 64;  // point arrays are padded to a multiple of this wit
 template <typename T, int L> __host__ __device__ constexpr int boys_cols() { return L + BoysCfg<T>::ORD + 1; }
 
 template <int L, typename T>
-__device__ __forceinline__ void aux_Rn(T r2, T p, T limp, T pf, T pref, T zeta2, T zeta, T limk,
+__device__ __forceinline__ void aux_Rn(double r2d, T p, T limp, T pf, T pref, T zeta2, T zeta, T limk,
                                        const T *__restrict__ tab, T (&Rn)[L + 1]) {
     using C = BoysCfg<T>;
     static_assert(boys_cols<T, L>() <= C::MT, "Boys table has too few columns for this L");
-    if (r2 >= limp + limk) {
+    if constexpr (sizeof(T) == 4) {
+        if (r2d >= (double)(limp + limk)) {  // large T: FP64 (see above)
+            const double ri = rsq_fast(r2d), ri2 = ri * ri;
+            double R = (double)pf * ri;
+            Rn[0] = (T)R;
+#pragma unroll
+            for (int n = 1; n <= L; ++n) {
+                R *= double(-(2 * n - 1)) * ri2;
+                Rn[n] = (T)R;
+            }
+            return;
+        }
+    }
+    const T r2 = (T)r2d;
+    if (sizeof(T) == 8 && r2 >= limp + limk) {
         T ri = rsq_fast(r2);
         T ri2 = ri * ri;
         Rn[0] = pf * ri;
@@ -164,14 +185,20 @@ __device__ __forceinline__ void aux_Rn(T r2, T p, T limp, T pf, T pref, T zeta2,
     }
 }
 
+// squared distance of the FP64 differences (X, Y, Z) = P - C: the FP64 kernels square their
+// (unchanged) components, the FP32 kernels keep the FP64 square for the large-T branch
+template <typename T> __device__ __forceinline__ double dist2(double X, double Y, double Z) {
+    if constexpr (sizeof(T) == 8) return X * X + Y * Y + Z * Z;
+    else return fma(X, X, fma(Y, Y, Z * Z));
+}
+
 // R_tuv (t+u+v <= L) of one pair against one point; (X, Y, Z) = P - C.
 template <int L, typename T>
 __device__ __forceinline__ void eval_R(double X, double Y, double Z, const PairHdr<T> &h, T zeta2, T zeta, T limk,
                                        const T *__restrict__ tab, T (&R)[ntuv(L)]) {
     T x = T(X), y = T(Y), z = T(Z);
-    T r2 = x * x + y * y + z * z;
     T Rn[L + 1];
-    aux_Rn<L, T>(r2, h.p, h.limp, h.pf, h.pref, zeta2, zeta, limk, tab, Rn);
+    aux_Rn<L, T>(dist2<T>(X, Y, Z), h.p, h.limp, h.pf, h.pref, zeta2, zeta, limk, tab, Rn);
     MdR<L>::run(x, y, z, Rn, R);
 }
 
@@ -390,6 +417,7 @@ struct pcm_mol {
     DevBuf<unsigned char> pti64;      // [Mpad] PtInt<double> (far dummies past M)
     DevBuf<unsigned char> pti32;      // [Mpad] PtInt<float>
     DevBuf<double> qpad;              // [Mpad] charges copied for the point loops (zeros past M)
+    DevBuf<double> r_surf_buf;        // [3M] explicit surface positions of pcm_update_geometry
     // candidate shell pairs (classes concatenated)
     long long sp_cls_off[NCLS + 1] = {0};
     std::vector<int> h_spa, h_spb;
@@ -399,6 +427,11 @@ struct pcm_mol {
     // screened lists; with PCM_DYNAMIC precision fock / esp hold the pairs whose bound reaches
     // dp_thresh (FP64 records) and fock_w / esp_w the others (FP32 records), both in list order
     PairList fock, esp, fock_w, esp_w;
+    // merged list of the one-pass Fock + gradient pair side: survivors of Eq. 15 or of Eq. 18 (its
+    // bits per candidate shell pair in m18); header-only records
+    PairList fg;
+    DevBuf<unsigned long long> m18;
+    DevBuf<int> c18;
     bool esp_valid = false;
     // workspaces
     DevBuf<double> part;   // partial sums (esp / gradient)
@@ -472,6 +505,18 @@ void noalloc_scratch_init(int dev);
 long long noalloc_scratch_bytes();
 void run_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, double *g_nuc, double *g_surf,
               int prec);
+// c (Eqs. 5-6) and dc_k = d c_k / d r_k (M x 3) in one pass over the Eq. 18 list(s): the point
+// side of the Eq. 22 gradient with the potential accumulated beside it
+void run_esp_deriv(pcm_ctx *ctx, pcm_mol *mol, double *c, double *dc, int prec);
+// F += L^T q (Eq. 10) and the Eq. 14 gradient with the c term's point side from dc; FP64 and mixed
+// precision take one pair-side pass over the merged list fg (built by pairs_merged_build)
+void run_fock_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, const double *dc, double *F,
+                   double *g_nuc, double *g_surf, int prec);
+// screen with P (Eq. 18 bits into m18) and build fg = Eq. 15 list | Eq. 18 list with header records
+void pairs_merged_build(pcm_ctx *ctx, pcm_mol *mol, const double *P, int prec);
+// contraction to F blocks and scatter of V sums held in vin (stride vnt), class cl of list pl
+void fock_contract_scatter(pcm_ctx *ctx, pcm_mol *mol, const PairList &pl, int cl, const double *vin, int nch,
+                           int vnt, const unsigned long long *memb, double *F);
 void run_grad_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<const double *> &P,
                     const std::vector<const double *> &q, const std::vector<double *> &g_nuc,
                     const std::vector<double *> &g_surf, int prec);
@@ -498,7 +543,8 @@ inline int grid_for(long long n, int block) { return n > 0 ? div_up(n, block) : 
 inline int int_grid(long long n_items) { return (int)std::min<long long>(std::max<long long>(n_items, 1), 1 << 30); }
 // copy a host descriptor table into the context's descriptor buffer (stream ordered)
 inline void *upload_desc(pcm_ctx *ctx, const void *h, size_t bytes) {
-    ctx->desc.ensure(bytes ? bytes : 1);
+    // at least 64 KiB, so that the small per-class tables of a call never move the buffer
+    ctx->desc.ensure(std::max<size_t>(bytes, size_t(1) << 16));
     if (bytes) HIP_OK(hipMemcpyAsync(ctx->desc.p, h, bytes, hipMemcpyHostToDevice, ctx->stream));
     return ctx->desc.p;
 }

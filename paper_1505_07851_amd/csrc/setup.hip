@@ -652,3 +652,36 @@ void pairs_prepare_density(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const doubl
     else
         prep_lists<double>(ctx, mol, pl, P);
 }
+
+// ----------------------------------------------------------------------------------------
+// Merged list of the one-pass Fock + gradient pair side: the Eq. 18 survivors for P (bits kept in
+// m18) together with the Eq. 15 survivors already in fock.mask; header-only records in the
+// precision of the pass.  Entries keep the list order (class, shell pair, i, j).
+// ----------------------------------------------------------------------------------------
+__global__ void k_mask_or(int nsp, const unsigned long long *__restrict__ a, const unsigned long long *__restrict__ b,
+                          unsigned long long *__restrict__ mask, int *__restrict__ cnt) {
+    int sp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sp >= nsp) return;
+    const unsigned long long m = a[sp] | b[sp];
+    mask[sp] = m;
+    cnt[sp] = __popcll(m);
+}
+
+void pairs_merged_build(pcm_ctx *ctx, pcm_mol *mol, const double *P, int prec) {
+    const long long nsp = mol->sp_cls_off[NCLS];
+    PairList &fg = mol->fg;
+    mol->m18.ensure(nsp + 1);
+    mol->c18.ensure(nsp + 1);
+    fg.mask.ensure(nsp + 1);
+    fg.cnt.ensure(nsp + 1);
+    fg.spo.ensure(nsp + 1);
+    if (nsp > 0) {
+        screen_launch(ctx, mol, P, ctx->prm.schwarz_thresh, mol->m18.p, mol->c18.p);
+        k_mask_or<<<div_up(nsp, 256), 256, 0, ctx->stream>>>((int)nsp, mol->fock.mask.p, mol->m18.p, fg.mask.p,
+                                                             fg.cnt.p);
+        HIP_LAUNCH_OK();
+    }
+    pairs_compact(ctx, mol, fg);
+    for (int c = 0; c < NCLS; ++c) fg.sp_union[c] = fg.sp_count[c];
+    pairs_prepare_geometry(ctx, mol, fg, prec);
+}

@@ -240,3 +240,32 @@ def test_matvec_share_bad_arguments(L):
     for rank, nranks in [(0, 0), (-1, 2), (2, 2)]:
         assert L.pcm_matvec_share(ctx, fake_mol, _hp(x), _hp(x), rank, nranks) == _lib.PCM_E_ARG
     L.pcm_destroy(ctx)
+
+
+def test_misaligned_device_pointers_rejected(L):
+    """Host validation rejects device arrays that are not 8-byte aligned before any GPU call (the
+    molecule handle is not dereferenced on this path, so a placeholder stands in for it)."""
+    from paper_1505_07851_amd import _lib
+    h = ctypes.c_void_p()
+    assert L.pcm_create(None, None, ctypes.byref(h)) == _lib.PCM_OK
+    try:
+        holder = ctypes.create_string_buffer(64)
+        mol = ctypes.c_void_p(ctypes.addressof(holder))
+        good, bad = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x10004)
+        calls = [
+            lambda: L.pcm_esp(h, mol, bad, good, None),
+            lambda: L.pcm_esp(h, mol, good, good, bad),
+            lambda: L.pcm_esp_deriv(h, mol, good, good, None, bad),
+            lambda: L.pcm_fock(h, mol, good, bad),
+            lambda: L.pcm_fock_grad(h, mol, good, good, good, good, bad, good),
+            lambda: L.pcm_grad(h, mol, good, bad, good, good),
+            lambda: L.pcm_energy(h, mol, good, bad, good, ctypes.byref(ctypes.c_double())),
+            lambda: L.pcm_matvec_share(h, mol, bad, good, 0, 1),
+            lambda: L.pcm_matvec_share_noalloc(h, mol, good, bad, 0, 1),
+            lambda: L.pcm_solve(h, mol, bad, None, good, None),
+        ]
+        for i, fn in enumerate(calls):
+            assert fn() == _lib.PCM_E_ARG, i
+            assert b"aligned" in L.pcm_last_error(h), i
+    finally:
+        L.pcm_destroy(h)
