@@ -65,6 +65,10 @@ void release_mol(pcm_mol *m) {
     release_list(m->fock_w);
     release_list(m->esp_w);
     release_list(m->fg);
+    release_list(m->fg_w);
+    m->m15.release();
+    m->mtmp.release();
+    m->ctmp.release();
     m->m18.release();
     m->c18.release();
 }
@@ -154,14 +158,12 @@ pcm_status check_solve_opts(pcm_ctx *ctx, const pcm_solve_opts *opts, pcm_solve_
     return PCM_OK;
 }
 
-// pair-geometry records of the Fock list(s) in the context's precision
+// Pair records are FP64 in the FP64 and mixed forms (the mixed kernels interpolate the Boys
+// function in FP32 but read FP64 pair data); with PCM_DYNAMIC the weak lists hold FP32 records
+// (pairs_prepare_* take PCM_MIXED to mean FP32 records).
 static void lists_geometry(pcm_ctx *ctx, pcm_mol *mol) {
-    if (ctx->prm.precision == PCM_DYNAMIC) {
-        pairs_prepare_geometry(ctx, mol, mol->fock, PCM_FP64);
-        pairs_prepare_geometry(ctx, mol, mol->fock_w, PCM_MIXED);
-    } else {
-        pairs_prepare_geometry(ctx, mol, mol->fock, ctx->prm.precision);
-    }
+    pairs_prepare_geometry(ctx, mol, mol->fock, PCM_FP64);
+    if (ctx->prm.precision == PCM_DYNAMIC) pairs_prepare_geometry(ctx, mol, mol->fock_w, PCM_MIXED);
 }
 
 }  // namespace
@@ -224,6 +226,7 @@ void pcm_destroy(pcm_ctx *ctx) {
     ctx->boys32.release();
     ctx->scal.release();
     ctx->iscal.release();
+    ctx->lscal.release();
     delete ctx;
 }
 
@@ -351,7 +354,7 @@ static pcm_status density_list(pcm_ctx *ctx, pcm_mol *mol, const double *P) {
         pairs_prepare_density(ctx, mol, mol->esp, P, PCM_FP64);
         pairs_prepare_density(ctx, mol, mol->esp_w, P, PCM_MIXED);
     } else {
-        pairs_prepare_density(ctx, mol, mol->esp, P, ctx->prm.precision);
+        pairs_prepare_density(ctx, mol, mol->esp, P, PCM_FP64);
     }
     mol->esp_valid = true;
     return PCM_OK;
@@ -393,10 +396,7 @@ pcm_status pcm_fock_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const doub
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         const int prec = ctx->prm.precision;
-        if (prec == PCM_DYNAMIC)
-            density_list(ctx, mol, P);  // the gradient's pair side runs over the split Eq. 18 lists
-        else
-            pairs_merged_build(ctx, mol, P, prec);
+        pairs_merged_build(ctx, mol, P, prec == PCM_DYNAMIC);
         run_fock_grad(ctx, mol, P, q, dc, F, g_nuc, g_surf, prec);
         return PCM_OK;
     });

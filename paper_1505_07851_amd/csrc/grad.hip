@@ -39,12 +39,12 @@ struct GradVDesc {
 
 // WC: also accumulate the potential c_k = sum_t D_t R_t (Eqs. 5-6), which the R^(n) of the
 // derivative contain (orders 0 .. L of the L+1 evaluated); rows are then 4 wide (gx, gy, gz, c)
-template <int L, typename T, bool WC>
+template <int L, typename T, typename B, bool WC>
 __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict__ ds, int nd, long long n_items,
-                                                  const T *__restrict__ boys_g) {
+                                                  const B *__restrict__ boys_g) {
     constexpr int NT = ntuv(L), PB = pair_batch<L + 1>();
-    __shared__ T tab[boys_lds_size<T, L + 1>()];
-    load_boys<T, L + 1>(tab, boys_g);
+    __shared__ B tab[boys_lds_size<B, L + 1>()];
+    load_boys<B, L + 1>(tab, boys_g);
     {  // one item per block (the grid covers every item; a loop over items costs registers here)
         const long long it = blockIdx.x;
         if (it >= n_items) return;
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
                     // with C = (X dC/dX + Y dC/dY + Z dC/dZ) / 3 (C is homogeneous of degree 3)
                     const T *Db = D[b];
                     T x, y, z, Rn[5];
-                    eval_Rn<4, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim,
+                    eval_Rn<4, T, B>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim,
                                   tab, x, y, z, Rn);
                     const T xx = x * x, xy = x * y, xz = x * z, yy = y * y, yz = y * z, zz = z * z;
                     const T two = T(2), three = T(3);
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
                     //   + D_{e_i} R^(1) + (dQ/dX_i) R^(2)
                     const T *Db = D[b];
                     T x, y, z, Rn[4];
-                    eval_Rn<3, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim,
+                    eval_Rn<3, T, B>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim,
                                   tab, x, y, z, Rn);
                     const T q1 = fma(Db[4], x, fma(Db[5], y, Db[6] * z));  // D_200 X + D_110 Y + D_101 Z
                     const T q2 = fma(Db[7], y, Db[8] * z);                 // D_020 Y + D_011 Z
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
                     // g_i = sum_t D_t R_{t + e_i} = X_i (D_0 R^(1) + R^(2) w) + D_{e_i} R^(1),
                     // w = D_100 X + D_010 Y + D_001 Z
                     T x, y, z, Rn[3];
-                    eval_Rn<2, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim,
+                    eval_Rn<2, T, B>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim,
                                   tab, x, y, z, Rn);
                     const T w = fma(D[b][1], x, fma(D[b][2], y, D[b][3] * z));
                     const T a = fma(Rn[2], w, D[b][0] * Rn[1]);
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
                 }
                 if constexpr (L == 0) {  // D R_{e_i} = (D R^(1)) X_i
                     T x, y, z, Rn[2];
-                    eval_Rn1<T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
+                    eval_Rn1<T, B>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
                                 x, y, z, Rn);
                     const T t1 = D[b][0] * Rn[1];
                     if constexpr (sizeof(T) == 8) {
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
                     continue;
                 }
                 T R[ntuv(L + 1)];
-                eval_R<L + 1, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
+                eval_R<L + 1, T, B>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
                                  R);
                 if constexpr (sizeof(T) == 8) {  // FP64: straight into the accumulators
 #pragma unroll
@@ -238,11 +238,11 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
 // -------------------------------------------------------------------------------------------
 // V'_tuv up to L+1 per pair (lane = pair), weights q_k; same as the Fock accumulation
 // -------------------------------------------------------------------------------------------
-template <int L, typename T>
+template <int L, typename T, typename B>
 __global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds, int nd, long long n_items,
-                                                const T *__restrict__ boys_g) {
-    __shared__ T tab[boys_lds_size<T, L + 1>()];
-    load_boys<T, L + 1>(tab, boys_g);
+                                                const B *__restrict__ boys_g) {
+    __shared__ B tab[boys_lds_size<B, L + 1>()];
+    load_boys<B, L + 1>(tab, boys_g);
     constexpr int NT = ntuv(L + 1);
     // points per batch: fewer for the larger V' sets so that more waves stay resident
     constexpr int PB = L <= 1 ? PT_BATCH : (L == 2 ? 2 : 1);
@@ -275,21 +275,21 @@ __global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds
             for (int b = 0; b < PB; ++b) {
                 if constexpr (L == 1) {  // q R_t with q R^(1), q R^(2) formed once
                     T x, y, z, Rn[3];
-                    eval_Rn<2, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
+                    eval_Rn<2, T, B>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
                                   pt[b].lim, tab, x, y, z, Rn);
                     acc_V2<T>(qk[b], x, y, z, Rn, V);
                     continue;
                 }
                 if constexpr (L == 2) {  // q R_t with q R^(1..3) formed once
                     T x, y, z, Rn[4];
-                    eval_Rn<3, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
+                    eval_Rn<3, T, B>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
                                   pt[b].lim, tab, x, y, z, Rn);
                     acc_V3<T>(qk[b], x, y, z, Rn, V);
                     continue;
                 }
                 if constexpr (L == 0) {  // q R_t with q R^(1) formed once
                     T x, y, z, Rn[2];
-                    eval_Rn1<T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
+                    eval_Rn1<T, B>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
                                 pt[b].lim, tab, x, y, z, Rn);
                     const double u = qk[b] * Rn[1];
                     V[0] = fma(qk[b], Rn[0], V[0]);
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds
                     continue;
                 }
                 T R[NT];
-                eval_R<L + 1, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
+                eval_R<L + 1, T, B>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
                                  pt[b].lim, tab, R);
 #pragma unroll
                 for (int t = 0; t < NT; ++t) V[t] = fma(qk[b], (double)R[t], V[t]);
@@ -726,11 +726,11 @@ struct GradJob {
 // candidate shell pair into gsp (added when `add`).  The work split of a molecule does not
 // depend on the other molecules, so a batched call gives the same bits as single calls.
 // do_pts / do_pairs select the sides; with_c makes the point side also evaluate c (4-wide rows).
-template <typename T>
+template <typename T, typename B>
 static void grad_cterm(pcm_ctx *ctx, std::vector<GradJob> &jobs, ListSel ls, bool add, bool do_pts = true,
                        bool do_pairs = true, bool with_c = false) {
-    const T *tab = sizeof(T) == 8 ? (const T *)ctx->boys64.p : (const T *)ctx->boys32.p;
-    const char *suffix = sizeof(T) == 8 ? "_f64" : "_f32";
+    const B *tab = sizeof(B) == 8 ? (const B *)ctx->boys64.p : (const B *)ctx->boys32.p;
+    const std::string suffix = std::string("_") + prec_tag<T, B>();
     auto pts_of = [](pcm_mol *mol) -> const void * { return sizeof(T) == 8 ? (const void *)mol->pti64.p
                                                                              : (const void *)mol->pti32.p; };
     // V' chunking per molecule and class (vbuf and gpair were sized for every list in grad_run)
@@ -799,9 +799,9 @@ static void grad_cterm(pcm_ctx *ctx, std::vector<GradJob> &jobs, ListSel ls, boo
 #define GP_CASE(LL)                                                                                    \
     case LL:                                                                                           \
         if (with_c)                                                                                    \
-            k_grad_pts<LL, T, true><<<int_grid(items_p), 256, 0, ctx->stream>>>(dpp, nd, items_p, tab); \
+            k_grad_pts<LL, T, B, true><<<int_grid(items_p), 256, 0, ctx->stream>>>(dpp, nd, items_p, tab); \
         else                                                                                           \
-            k_grad_pts<LL, T, false><<<int_grid(items_p), 256, 0, ctx->stream>>>(dpp, nd, items_p, tab); \
+            k_grad_pts<LL, T, B, false><<<int_grid(items_p), 256, 0, ctx->stream>>>(dpp, nd, items_p, tab); \
         break;
                     GP_CASE(0) GP_CASE(1) GP_CASE(2) GP_CASE(3) GP_CASE(4)
 #undef GP_CASE
@@ -813,7 +813,7 @@ static void grad_cterm(pcm_ctx *ctx, std::vector<GradJob> &jobs, ListSel ls, boo
                 switch (L) {
 #define GV_CASE(LL)                                                                                    \
     case LL:                                                                                           \
-        k_grad_v<LL, T><<<int_grid(items_v), 256, 0, ctx->stream>>>(dvp, nd, items_v, tab);            \
+        k_grad_v<LL, T, B><<<int_grid(items_v), 256, 0, ctx->stream>>>(dvp, nd, items_v, tab);         \
         break;
                     GV_CASE(0) GV_CASE(1) GV_CASE(2) GV_CASE(3) GV_CASE(4)
 #undef GV_CASE
@@ -906,10 +906,10 @@ static void grad_run(pcm_ctx *ctx, std::vector<GradJob> &all, int prec) {
     }
     if (jobs.empty()) return;
     if (prec == PCM_MIXED) {
-        grad_cterm<float>(ctx, jobs, &pcm_mol::esp, false);
+        grad_cterm<double, float>(ctx, jobs, &pcm_mol::esp, false);
     } else {
-        grad_cterm<double>(ctx, jobs, &pcm_mol::esp, false);
-        if (dyn) grad_cterm<float>(ctx, jobs, &pcm_mol::esp_w, true);
+        grad_cterm<double, double>(ctx, jobs, &pcm_mol::esp, false);
+        if (dyn) grad_cterm<float, float>(ctx, jobs, &pcm_mol::esp_w, true);
     }
     grad_finish(ctx, jobs, inv_f);
 }
@@ -984,10 +984,10 @@ void run_esp_deriv(pcm_ctx *ctx, pcm_mol *mol, double *c, double *dc, int prec) 
     j.part_c = mol->part.p;
     std::vector<GradJob> jobs{j};
     if (prec == PCM_MIXED) {
-        grad_cterm<float>(ctx, jobs, &pcm_mol::esp, false, true, false, true);
+        grad_cterm<double, float>(ctx, jobs, &pcm_mol::esp, false, true, false, true);
     } else {
-        grad_cterm<double>(ctx, jobs, &pcm_mol::esp, false, true, false, true);
-        if (dyn) grad_cterm<float>(ctx, jobs, &pcm_mol::esp_w, false, true, false, true);
+        grad_cterm<double, double>(ctx, jobs, &pcm_mol::esp, false, true, false, true);
+        if (dyn) grad_cterm<float, float>(ctx, jobs, &pcm_mol::esp_w, false, true, false, true);
     }
     k_field_sum<<<grid_for(M, 256), 256, 0, ctx->stream>>>(mol->part.p, jobs[0].row0, M, c, dc);
     HIP_LAUNCH_OK();
@@ -995,17 +995,17 @@ void run_esp_deriv(pcm_ctx *ctx, pcm_mol *mol, double *c, double *dc, int prec) 
 
 // pair side over the merged list, the Fock contraction (Eq. 15 entries) and the gradient
 // contraction (Eq. 18 entries) of each class, sums per candidate shell pair into gsp
-template <typename T>
-static void fock_grad_pairs(pcm_ctx *ctx, pcm_mol *mol, const double *P, double *F) {
-    const T *tab = sizeof(T) == 8 ? (const T *)ctx->boys64.p : (const T *)ctx->boys32.p;
-    const char *suffix = sizeof(T) == 8 ? "_f64" : "_f32";
-    const PairList &pl = mol->fg;
+template <typename T, typename B>
+static void fock_grad_pairs(pcm_ctx *ctx, pcm_mol *mol, const double *P, double *F, const PairList &pl, ListSel ls,
+                            bool add) {
+    const B *tab = sizeof(B) == 8 ? (const B *)ctx->boys64.p : (const B *)ctx->boys32.p;
+    const std::string suffix = std::string("_") + prec_tag<T, B>();
     for (int cl = 0; cl < NCLS; ++cl) {
         const int L = CLS_LA[cl] + CLS_LB[cl];
         const long long n = pl.cls_off[cl + 1] - pl.cls_off[cl];
         const long long sp0 = mol->sp_cls_off[cl], ncs = mol->sp_cls_off[cl + 1] - sp0;
         if (!n) {
-            if (ncs) HIP_OK(hipMemsetAsync(mol->gsp.p + sp0 * 6, 0, sizeof(double) * 6 * ncs, ctx->stream));
+            if (ncs && !add) HIP_OK(hipMemsetAsync(mol->gsp.p + sp0 * 6, 0, sizeof(double) * 6 * ncs, ctx->stream));
             continue;
         }
         GradVDesc b{};
@@ -1017,7 +1017,7 @@ static void fock_grad_pairs(pcm_ctx *ctx, pcm_mol *mol, const double *P, double 
         b.stride = (int)align16(sizeof(PairHdr<T>));
         b.n_pairs = (int)n;
         b.Mpad = mol->Mpad;
-        b.chunk = grad_v_chunk(mol, &pcm_mol::fg, cl);
+        b.chunk = grad_v_chunk(mol, ls, cl);
         b.nptile = div_up(n, 256);
         const int nch = div_up(mol->Mpad, b.chunk);
         const long long items = (long long)b.nptile * nch;
@@ -1028,14 +1028,14 @@ static void fock_grad_pairs(pcm_ctx *ctx, pcm_mol *mol, const double *P, double 
             switch (L) {
 #define GV_CASE(LL)                                                                                    \
     case LL:                                                                                           \
-        k_grad_v<LL, T><<<int_grid(items), 256, 0, ctx->stream>>>(dv, 1, items, tab);                  \
+        k_grad_v<LL, T, B><<<int_grid(items), 256, 0, ctx->stream>>>(dv, 1, items, tab);               \
         break;
                 GV_CASE(0) GV_CASE(1) GV_CASE(2) GV_CASE(3) GV_CASE(4)
 #undef GV_CASE
             }
             HIP_LAUNCH_OK();
         }
-        fock_contract_scatter(ctx, mol, pl, cl, mol->vbuf.p, nch, ntuv(L + 1), mol->fock.mask.p, F);
+        fock_contract_scatter(ctx, mol, pl, cl, mol->vbuf.p, nch, ntuv(L + 1), mol->m15.p, F);
         const int *es = pl.ent_sp.p + pl.cls_off[cl], *ei = pl.ent_ij.p + pl.cls_off[cl];
         const unsigned long long *memb = mol->m18.p;
         ProfScope ps2(ctx, "grad_contract", (double)n);
@@ -1063,7 +1063,7 @@ static void fock_grad_pairs(pcm_ctx *ctx, pcm_mol *mol, const double *P, double 
 #undef GCW_CASE
         HIP_LAUNCH_OK();
         k_grad_sp<<<div_up(ncs, 128), 128, 0, ctx->stream>>>(sp0, ncs, pl.cls_off[cl], pl.spo.p, mol->gpair.p,
-                                                             mol->gsp.p, 0);
+                                                             mol->gsp.p, add ? 1 : 0);
         HIP_LAUNCH_OK();
     }
 }
@@ -1072,61 +1072,38 @@ void run_fock_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q,
                    double *g_nuc, double *g_surf, int prec) {
     const double inv_f = (ctx->prm.eps + ctx->prm.k_factor) / (ctx->prm.eps - 1.0);
     const int M = mol->M;
-    if (prec == PCM_DYNAMIC) {
-        // the precision split differs between the two lists: F and the gradient's pair side run
-        // over their own lists, the point side comes from dc
-        run_fock(ctx, mol, q, F, prec);
-        GradJob j{mol, P, q, g_nuc, g_surf, 0, 0, 0, nullptr, nullptr};
-        j.dc = dc;
-        std::vector<GradJob> all{j};
-        HIP_OK(hipMemcpyAsync(mol->qpad.p, q, sizeof(double) * M, hipMemcpyDeviceToDevice, ctx->stream));
-        const int len_a = chunk_for(M, M, GRAD_MIN_AOFF);
-        GradJob &g = all[0];
-        g.rows_a = div_up(M, len_a);
-        mol->part.ensure((size_t)(g.rows_a + 1) * 3 * M);
-        g.part_a = mol->part.p;
-        mol->gsp.ensure((size_t)mol->sp_cls_off[NCLS] * 6 + 6);
-        size_t vneed = 0, gneed = 0;
-        grad_v_sizes(mol, &pcm_mol::esp, vneed, gneed);
-        grad_v_sizes(mol, &pcm_mol::esp_w, vneed, gneed);
-        mol->vbuf.ensure(vneed + 1);
-        mol->gpair.ensure(gneed + 1);
-        {
-            ProfScope psa(ctx, "grad_aoff", (double)M * M);
-            k_grad_aoff<<<dim3(div_up(M, 256), g.rows_a), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p,
-                                                                                  mol->zeta.p, q, M, len_a, g.part_a);
-            HIP_LAUNCH_OK();
-        }
-        grad_cterm<double>(ctx, all, &pcm_mol::esp, false, false, true);
-        grad_cterm<float>(ctx, all, &pcm_mol::esp_w, true, false, true);
-        grad_finish(ctx, all, inv_f);
-    } else {
-        HIP_OK(hipMemcpyAsync(mol->qpad.p, q, sizeof(double) * M, hipMemcpyDeviceToDevice, ctx->stream));
-        const int len_a = chunk_for(M, M, GRAD_MIN_AOFF);
-        const int rows_a = div_up(M, len_a);
-        mol->part.ensure((size_t)(rows_a + 1) * 3 * M);
-        mol->gsp.ensure((size_t)mol->sp_cls_off[NCLS] * 6 + 6);
-        size_t vneed = 0, gneed = 0, fneed = 0;
-        grad_v_sizes(mol, &pcm_mol::fg, vneed, gneed);
+    const bool dyn = prec == PCM_DYNAMIC;
+    HIP_OK(hipMemcpyAsync(mol->qpad.p, q, sizeof(double) * M, hipMemcpyDeviceToDevice, ctx->stream));
+    const int len_a = chunk_for(M, M, GRAD_MIN_AOFF);
+    const int rows_a = div_up(M, len_a);
+    mol->part.ensure((size_t)(rows_a + 1) * 3 * M);
+    mol->gsp.ensure((size_t)mol->sp_cls_off[NCLS] * 6 + 6);
+    // V', per-pair blocks and gradient rows sized for every part before the first launch
+    size_t vneed = 0, gneed = 0, fneed = 0;
+    for (ListSel ls : {&pcm_mol::fg, &pcm_mol::fg_w}) {
+        const PairList &pl = mol->*ls;
+        grad_v_sizes(mol, ls, vneed, gneed);
         for (int cl = 0; cl < NCLS; ++cl)
-            fneed = std::max(fneed, (size_t)(mol->fg.cls_off[cl + 1] - mol->fg.cls_off[cl]) * ncart(CLS_LA[cl]) *
+            fneed = std::max(fneed, (size_t)(pl.cls_off[cl + 1] - pl.cls_off[cl]) * ncart(CLS_LA[cl]) *
                                         ncart(CLS_LB[cl]));
-        mol->vbuf.ensure(vneed + 1);
-        mol->gpair.ensure(gneed + 1);
-        mol->fprim.ensure(fneed + 1);
-        {
-            ProfScope psa(ctx, "grad_aoff", (double)M * M);
-            k_grad_aoff<<<dim3(div_up(M, 256), rows_a), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p,
-                                                                                mol->zeta.p, q, M, len_a, mol->part.p);
-            HIP_LAUNCH_OK();
-        }
-        if (prec == PCM_MIXED)
-            fock_grad_pairs<float>(ctx, mol, P, F);
-        else
-            fock_grad_pairs<double>(ctx, mol, P, F);
-        GradJob j{mol, P, q, g_nuc, g_surf, rows_a, 0, 0, mol->part.p, nullptr};
-        j.dc = dc;
-        std::vector<GradJob> all{j};
-        grad_finish(ctx, all, inv_f);
     }
+    mol->vbuf.ensure(vneed + 1);
+    mol->gpair.ensure(gneed + 1);
+    mol->fprim.ensure(fneed + 1);
+    {
+        ProfScope psa(ctx, "grad_aoff", (double)M * M);
+        k_grad_aoff<<<dim3(div_up(M, 256), rows_a), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p,
+                                                                            mol->zeta.p, q, M, len_a, mol->part.p);
+        HIP_LAUNCH_OK();
+    }
+    if (prec == PCM_MIXED) {
+        fock_grad_pairs<double, float>(ctx, mol, P, F, mol->fg, &pcm_mol::fg, false);
+    } else {
+        fock_grad_pairs<double, double>(ctx, mol, P, F, mol->fg, &pcm_mol::fg, false);
+        if (dyn) fock_grad_pairs<float, float>(ctx, mol, P, F, mol->fg_w, &pcm_mol::fg_w, true);
+    }
+    GradJob j{mol, P, q, g_nuc, g_surf, rows_a, 0, 0, mol->part.p, nullptr};
+    j.dc = dc;
+    std::vector<GradJob> all{j};
+    grad_finish(ctx, all, inv_f);
 }

@@ -62,12 +62,12 @@ struct SumDesc {
 // ----------------------------------------------------------------------------------------
 // esp: partial c over one chunk of pairs of one class; lane = surface point
 // ----------------------------------------------------------------------------------------
-template <int L, typename T>
+template <int L, typename T, typename B>
 __global__ __launch_bounds__(256) void k_esp(const EspDesc *__restrict__ ds, int nd, long long n_items,
-                                             const T *__restrict__ boys_g) {
+                                             const B *__restrict__ boys_g) {
     constexpr int NT = ntuv(L), PB = pair_batch<L>();
-    __shared__ T tab[boys_lds_size<T, L>()];
-    load_boys<T, L>(tab, boys_g);
+    __shared__ B tab[boys_lds_size<B, L>()];
+    load_boys<B, L>(tab, boys_g);
     for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
         const EspDesc &d = ds[find_desc(ds, nd, it)];
         const long long local = it - d.base;
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void k_esp(const EspDesc *__restrict__ ds, int
                     // cubic form (D index 10 .. 19: 300, 210, 201, 120, 111, 102, 030, 021, 012, 003)
                     const T *Db = D[b];
                     T x, y, z, Rn[4];
-                    eval_Rn<3, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim,
+                    eval_Rn<3, T, B>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim,
                                   tab, x, y, z, Rn);
                     const T zz = z * z, three = T(3);
                     const T lin = fma(Db[1], x, fma(Db[2], y, fma(Db[3], z, Db[4] + Db[7] + Db[9])));
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void k_esp(const EspDesc *__restrict__ ds, int
                     //               + R^(2) (the quadratic form of D_200 ... D_002 in X, Y, Z)
                     const T *Db = D[b];
                     T x, y, z, Rn[3];
-                    eval_Rn<2, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim,
+                    eval_Rn<2, T, B>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim,
                                   tab, x, y, z, Rn);
                     const T q1 = fma(Db[4], x, fma(Db[5], y, Db[6] * z));
                     const T q2 = fma(Db[7], y, Db[8] * z);
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_esp(const EspDesc *__restrict__ ds, int
                 }
                 if constexpr (L == 1) {  // sum_t D_t R_t with R^(1) factored out
                     T x, y, z, Rn[2];
-                    eval_Rn1<T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
+                    eval_Rn1<T, B>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
                                 x, y, z, Rn);
                     const T w = fma(D[b][1], x, fma(D[b][2], y, D[b][3] * z));
                     if constexpr (sizeof(T) == 8) {
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void k_esp(const EspDesc *__restrict__ ds, int
                     continue;
                 }
                 T R[NT];
-                eval_R<L, T>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
+                eval_R<L, T, B>(h[b].Px - me.x, h[b].Py - me.y, h[b].Pz - me.z, h[b], me.zeta2, me.zeta, me.lim, tab,
                              R);
                 if constexpr (sizeof(T) == 8) {  // FP64: straight into the accumulator
 #pragma unroll
@@ -219,12 +219,12 @@ void run_bz(pcm_ctx *ctx, pcm_mol *mol, double *bz) {
 // ----------------------------------------------------------------------------------------
 // Fock: V_tuv(pair) = sum_k q_k R_tuv(pair, k) over one chunk of points; lane = primitive pair
 // ----------------------------------------------------------------------------------------
-template <int L, typename T>
+template <int L, typename T, typename B>
 __global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds, int nd, long long n_items,
-                                                const T *__restrict__ boys_g) {
+                                                const B *__restrict__ boys_g) {
     constexpr int NT = ntuv(L);
-    __shared__ T tab[boys_lds_size<T, L>()];
-    load_boys<T, L>(tab, boys_g);
+    __shared__ B tab[boys_lds_size<B, L>()];
+    load_boys<B, L>(tab, boys_g);
     for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
         const FockDesc &d = ds[find_desc(ds, nd, it)];
         const long long local = it - d.base;
@@ -251,21 +251,21 @@ __global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds,
             for (int b = 0; b < PT_BATCH; ++b) {
                 if constexpr (L == 2) {  // q R_t with q R^(1), q R^(2) formed once
                     T x, y, z, Rn[3];
-                    eval_Rn<2, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
+                    eval_Rn<2, T, B>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
                                   pt[b].lim, tab, x, y, z, Rn);
                     acc_V2<T>(qk[b], x, y, z, Rn, V);
                     continue;
                 }
                 if constexpr (L == 3) {  // q R_t with q R^(1..3) formed once
                     T x, y, z, Rn[4];
-                    eval_Rn<3, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
+                    eval_Rn<3, T, B>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
                                   pt[b].lim, tab, x, y, z, Rn);
                     acc_V3<T>(qk[b], x, y, z, Rn, V);
                     continue;
                 }
                 if constexpr (L == 1) {  // q R_t with q R^(1) formed once
                     T x, y, z, Rn[2];
-                    eval_Rn1<T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
+                    eval_Rn1<T, B>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
                                 pt[b].lim, tab, x, y, z, Rn);
                     const double u = qk[b] * Rn[1];
                     V[0] = fma(qk[b], Rn[0], V[0]);
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds,
                     continue;
                 }
                 T R[NT];
-                eval_R<L, T>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta, pt[b].lim,
+                eval_R<L, T, B>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta, pt[b].lim,
                              tab, R);
 #pragma unroll
                 for (int t = 0; t < NT; ++t) V[t] = fma(qk[b], (double)R[t], V[t]);
@@ -515,9 +515,9 @@ static int ilog2(long long x) {
     return r;
 }
 
-static std::string shape_key(const char *kind, int L, bool f64, long long n, long long M) {
-    return std::string(kind) + ":L" + std::to_string(L) + (f64 ? ":f64:" : ":f32:") + std::to_string(ilog2(n)) +
-           ":" + std::to_string(ilog2(M));
+static std::string shape_key(const char *kind, int L, const char *prec, long long n, long long M) {
+    return std::string(kind) + ":L" + std::to_string(L) + ":" + prec + ":" + std::to_string(ilog2(n)) + ":" +
+           std::to_string(ilog2(M));
 }
 
 // Grid of the integral item loops: one item per workgroup and the hardware scheduler balances
@@ -527,13 +527,13 @@ static std::string shape_key(const char *kind, int L, bool f64, long long n, lon
 
 // device scratch for descriptor tables of one call (all classes uploaded at once)
 
-template <typename T>
+template <typename T, typename B>
 static void esp_class_launch(pcm_ctx *ctx, int L, const EspDesc *d, int nd, long long n_items) {
-    const T *tab = boys_tab<T>(ctx);
+    const B *tab = boys_tab<B>(ctx);
     switch (L) {
 #define ESP_CASE(LL)                                                                        \
     case LL:                                                                                \
-        k_esp<LL, T><<<int_grid(n_items), 256, 0, ctx->stream>>>(d, nd, n_items, tab);      \
+        k_esp<LL, T, B><<<int_grid(n_items), 256, 0, ctx->stream>>>(d, nd, n_items, tab);      \
         break;
         ESP_CASE(0) ESP_CASE(1) ESP_CASE(2) ESP_CASE(3) ESP_CASE(4)
 #undef ESP_CASE
@@ -559,7 +559,7 @@ template <typename T> static EspDesc esp_desc(pcm_mol *mol, ListSel ls, int cl, 
 }
 
 // chunk of (molecule, class), autotuned on first use of its shape key
-template <typename T> static int esp_chunk(pcm_ctx *ctx, pcm_mol *mol, ListSel ls, int cl) {
+template <typename T, typename B> static int esp_chunk(pcm_ctx *ctx, pcm_mol *mol, ListSel ls, int cl) {
     const long long n = (mol->*ls).cls_off[cl + 1] - (mol->*ls).cls_off[cl];
     const int L = CLS_LA[cl] + CLS_LB[cl];
     if (!ctx->prm.autotune) return esp_chunk_len(n, mol->M, TARGET_DEFAULT);
@@ -568,7 +568,7 @@ template <typename T> static int esp_chunk(pcm_ctx *ctx, pcm_mol *mol, ListSel l
         int c = esp_chunk_len(n, mol->M, t);
         if (std::find(cands.begin(), cands.end(), c) == cands.end()) cands.push_back(c);
     }
-    const std::string key = shape_key("esp", L, sizeof(T) == 8, n, mol->M);
+    const std::string key = shape_key("esp", L, prec_tag<T, B>(), n, mol->M);
     if (ctx->tuned.count(key)) {  // cached target for this shape bucket: map it to this size
         return esp_chunk_len(n, mol->M, ctx->tuned[key]);
     }
@@ -580,7 +580,7 @@ template <typename T> static int esp_chunk(pcm_ctx *ctx, pcm_mol *mol, ListSel l
         d.base = 0;
         long long items = (long long)d.ntile * div_up(n, c);
         EspDesc *dd = (EspDesc *)upload_desc(ctx, &d, sizeof(d));
-        esp_class_launch<T>(ctx, L, dd, 1, items);
+        esp_class_launch<T, B>(ctx, L, dd, 1, items);
     });
     int target = TARGET_DEFAULT;
     for (int t : TARGETS)
@@ -593,7 +593,7 @@ template <typename T> static int esp_chunk(pcm_ctx *ctx, pcm_mol *mol, ListSel l
 }
 
 // c[i] = (acc ? c[i] : 0) + the contribution of list `ls` of every molecule
-template <typename T>
+template <typename T, typename B>
 static void esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<double *> &c, ListSel ls,
                       bool acc) {
     const int n = (int)mols.size();
@@ -602,7 +602,7 @@ static void esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const st
     for (int i = 0; i < n; ++i) {
         for (int cl = 0; cl < NCLS; ++cl) {
             long long np = (mols[i]->*ls).cls_off[cl + 1] - (mols[i]->*ls).cls_off[cl];
-            chunk[i][cl] = np ? esp_chunk<T>(ctx, mols[i], ls, cl) : REC_PAD;
+            chunk[i][cl] = np ? esp_chunk<T, B>(ctx, mols[i], ls, cl) : REC_PAD;
             rows[i] += np ? div_up(np, chunk[i][cl]) : 0;
         }
         mols[i]->part.ensure((size_t)std::max(rows[i], 1) * mols[i]->M);
@@ -646,8 +646,8 @@ static void esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const st
         double work = 0.0;
         for (int i = 0; i < n; ++i)
             work += (double)((mols[i]->*ls).cls_off[cl + 1] - (mols[i]->*ls).cls_off[cl]) * mols[i]->M;
-        ProfScope ps(ctx, "esp_L" + std::to_string(L) + (sizeof(T) == 8 ? "_f64" : "_f32"), work);
-        esp_class_launch<T>(ctx, L, dd + cls_first[cl], cls_n[cl], cls_items[cl]);
+        ProfScope ps(ctx, "esp_L" + std::to_string(L) + "_" + prec_tag<T, B>(), work);
+        esp_class_launch<T, B>(ctx, L, dd + cls_first[cl], cls_n[cl], cls_items[cl]);
     }
     k_sum_rows<<<int_grid(sbase), 256, 0, ctx->stream>>>(reinterpret_cast<const SumDesc *>(dev + eb), n, sbase);
     HIP_LAUNCH_OK();
@@ -655,25 +655,25 @@ static void esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const st
 
 void run_esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<double *> &c, int prec) {
     if (prec == PCM_MIXED) {
-        esp_batch<float>(ctx, mols, c, &pcm_mol::esp, false);
+        esp_batch<double, float>(ctx, mols, c, &pcm_mol::esp, false);
     } else if (prec == PCM_DYNAMIC) {  // strong pairs in FP64, then the weak ones in FP32 added on
-        esp_batch<double>(ctx, mols, c, &pcm_mol::esp, false);
-        esp_batch<float>(ctx, mols, c, &pcm_mol::esp_w, true);
+        esp_batch<double, double>(ctx, mols, c, &pcm_mol::esp, false);
+        esp_batch<float, float>(ctx, mols, c, &pcm_mol::esp_w, true);
     } else {
-        esp_batch<double>(ctx, mols, c, &pcm_mol::esp, false);
+        esp_batch<double, double>(ctx, mols, c, &pcm_mol::esp, false);
     }
 }
 
 void run_esp(pcm_ctx *ctx, pcm_mol *mol, double *c, int prec) { run_esp_batch(ctx, {mol}, {c}, prec); }
 
 // ---------------------------------------------------------------------------------- Fock
-template <typename T>
+template <typename T, typename B>
 static void fock_class_launch(pcm_ctx *ctx, int L, const FockDesc *d, int nd, long long n_items) {
-    const T *tab = boys_tab<T>(ctx);
+    const B *tab = boys_tab<B>(ctx);
     switch (L) {
 #define FV_CASE(LL)                                                                                      \
     case LL:                                                                                             \
-        k_fock_v<LL, T><<<int_grid(n_items), 256, 0, ctx->stream>>>(d, nd, n_items, tab);                \
+        k_fock_v<LL, T, B><<<int_grid(n_items), 256, 0, ctx->stream>>>(d, nd, n_items, tab);                \
         break;
         FV_CASE(0) FV_CASE(1) FV_CASE(2) FV_CASE(3) FV_CASE(4)
 #undef FV_CASE
@@ -696,11 +696,11 @@ template <typename T> static FockDesc fock_desc(pcm_mol *mol, ListSel ls, int cl
     return d;
 }
 
-template <typename T> static int fock_chunk(pcm_ctx *ctx, pcm_mol *mol, ListSel ls, int cl) {
+template <typename T, typename B> static int fock_chunk(pcm_ctx *ctx, pcm_mol *mol, ListSel ls, int cl) {
     const long long n = (mol->*ls).cls_off[cl + 1] - (mol->*ls).cls_off[cl];
     const int L = CLS_LA[cl] + CLS_LB[cl];
     if (!ctx->prm.autotune) return fock_chunk_len(n, mol->Mpad, TARGET_DEFAULT);
-    const std::string key = shape_key("fock", L, sizeof(T) == 8, n, mol->M);
+    const std::string key = shape_key("fock", L, prec_tag<T, B>(), n, mol->M);
     if (ctx->tuned.count(key)) return fock_chunk_len(n, mol->Mpad, ctx->tuned[key]);
     std::vector<int> cands;
     for (int t : TARGETS) {
@@ -712,7 +712,7 @@ template <typename T> static int fock_chunk(pcm_ctx *ctx, pcm_mol *mol, ListSel 
         d.base = 0;
         long long items = (long long)d.nptile * div_up(mol->Mpad, c);
         FockDesc *dd = (FockDesc *)upload_desc(ctx, &d, sizeof(d));
-        fock_class_launch<T>(ctx, L, dd, 1, items);
+        fock_class_launch<T, B>(ctx, L, dd, 1, items);
     });
     int target = TARGET_DEFAULT;
     for (int t : TARGETS)
@@ -740,7 +740,7 @@ static void fock_buffers(pcm_mol *mol, ListSel ls) {
     mol->fprim.ensure(fneed + 1);
 }
 
-template <typename T>
+template <typename T, typename B>
 static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<const double *> &q,
                        const std::vector<double *> &F, ListSel ls) {
     const int n = (int)mols.size();
@@ -753,7 +753,7 @@ static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const s
     for (int i = 0; i < n; ++i)
         for (int cl = 0; cl < NCLS; ++cl)
             chunk[i][cl] = (mols[i]->*ls).cls_off[cl + 1] > (mols[i]->*ls).cls_off[cl]
-                               ? fock_chunk<T>(ctx, mols[i], ls, cl)
+                               ? fock_chunk<T, B>(ctx, mols[i], ls, cl)
                                : PT_BATCH;
     std::vector<FockDesc> all;
     long long cls_items[NCLS];
@@ -832,8 +832,8 @@ static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const s
         for (int i = 0; i < n; ++i)
             work += (double)((mols[i]->*ls).cls_off[cl + 1] - (mols[i]->*ls).cls_off[cl]) * mols[i]->M;
         {
-            ProfScope ps(ctx, "fock_v_L" + std::to_string(L) + (sizeof(T) == 8 ? "_f64" : "_f32"), work);
-            fock_class_launch<T>(ctx, L, dd + cls_first[cl], cls_n[cl], cls_items[cl]);
+            ProfScope ps(ctx, "fock_v_L" + std::to_string(L) + "_" + prec_tag<T, B>(), work);
+            fock_class_launch<T, B>(ctx, L, dd + cls_first[cl], cls_n[cl], cls_items[cl]);
         }
         const FockCDesc *cdc = cd + c_first[cl];
         const int ncd = c_n[cl];
@@ -869,12 +869,12 @@ static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const s
 void run_fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<const double *> &q,
                     const std::vector<double *> &F, int prec) {
     if (prec == PCM_MIXED) {
-        fock_batch<float>(ctx, mols, q, F, &pcm_mol::fock);
+        fock_batch<double, float>(ctx, mols, q, F, &pcm_mol::fock);
     } else if (prec == PCM_DYNAMIC) {  // both lists add their blocks to F
-        fock_batch<double>(ctx, mols, q, F, &pcm_mol::fock);
-        fock_batch<float>(ctx, mols, q, F, &pcm_mol::fock_w);
+        fock_batch<double, double>(ctx, mols, q, F, &pcm_mol::fock);
+        fock_batch<float, float>(ctx, mols, q, F, &pcm_mol::fock_w);
     } else {
-        fock_batch<double>(ctx, mols, q, F, &pcm_mol::fock);
+        fock_batch<double, double>(ctx, mols, q, F, &pcm_mol::fock);
     }
 }
 

@@ -7,18 +7,19 @@
 #include "pcm_internal.h"
 
 // X_i = P_i - C_i in the kernel precision and R^(0) .. R^(N) of one (pair, point) evaluation
-template <int N, typename T>
+template <int N, typename T, typename B = T>
 __device__ __forceinline__ void eval_Rn(double X, double Y, double Z, const PairHdr<T> &h, T zeta2, T zeta, T limk,
-                                        const T *__restrict__ tab, T &x, T &y, T &z, T (&Rn)[N + 1]) {
+                                        const B *__restrict__ tab, T &x, T &y, T &z, T (&Rn)[N + 1]) {
     x = T(X);
     y = T(Y);
     z = T(Z);
-    aux_Rn<N, T>(dist2<T>(X, Y, Z), h.p, h.limp, h.pf, h.pref, zeta2, zeta, limk, tab, Rn);
+    const T r2 = x * x + y * y + z * z;
+    aux_Rn<N, T, B>(r2, h.p, h.limp, h.pf, h.pref, zeta2, zeta, limk, tab, Rn);
 }
-template <typename T>
+template <typename T, typename B = T>
 __device__ __forceinline__ void eval_Rn1(double X, double Y, double Z, const PairHdr<T> &h, T zeta2, T zeta, T limk,
-                                         const T *__restrict__ tab, T &x, T &y, T &z, T (&Rn)[2]) {
-    eval_Rn<1, T>(X, Y, Z, h, zeta2, zeta, limk, tab, x, y, z, Rn);
+                                         const B *__restrict__ tab, T &x, T &y, T &z, T (&Rn)[2]) {
+    eval_Rn<1, T, B>(X, Y, Z, h, zeta2, zeta, limk, tab, x, y, z, Rn);
 }
 
 // V_t += q R_t for every t with t + u + v <= 2 (index order of the Hermite tables: 000, 100,

@@ -73,7 +73,9 @@ template <> struct BoysCfg<double> {
     static constexpr double TMAX = 40.0;
 };
 template <> struct BoysCfg<float> {
-    static constexpr int ORD = 4, MT = 10, NROW = 241;
+    // rows up to T = 40: the mixed kernels interpolate in FP32 over the FP64 kernels' near range
+    // [0, 40); the all-FP32 kernels switch to the asymptotic form at 30
+    static constexpr int ORD = 4, MT = 10, NROW = 321;
     static constexpr float TMAX = 30.0f;
 };
 constexpr int LMAX_TOT = 5;  // highest total L handled (d-d gradient)
@@ -98,13 +100,16 @@ template <typename T> __host__ __device__ constexpr size_t rec_stride(int L) {
 //   far (a r^2 >= TMAX): the smeared charge acts as a point charge and the attenuation
 //   drops out: (pi/p)^{3/2} (-1)^n (2n-1)!! / r^{2n+1}.  The terms left out are bounded by the
 //   upper incomplete gamma tail, e^{-T} T^{n-1/2} / Gamma(n+1/2) relative to F_n(T): below
-//   2e-12 at T = 40 for n <= 5 (FP64), below 1e-8 at T = 30 (FP32 kernels).
-// The far test a r^2 >= TMAX is r^2 >= TMAX/p + TMAX/z^2.  r^2 comes in FP64 (the squared FP64
-// differences P - C).  In the FP32 kernels the large-T branch still runs in FP64 (reciprocal
-// square root and the R^(n) chain, each value rounded once to FP32): only the Boys-table
-// interpolation of the near field and the Hermite build run in FP32.  The hardware FP32
-// reciprocal square root is biased (about -7e-9 relative on average), and the far field
-// carries most of every potential, so an FP32 far branch would shift c coherently.
+//   2e-12 at T = 40 for n <= 5 (FP64 and mixed kernels), below 1e-8 at T = 30 (FP32 kernels).
+// The far test a r^2 >= TMAX is r^2 >= TMAX/p + TMAX/z^2.
+//
+// Precisions: T is the type of the pair records, the far field and the accumulation, B the type
+// of the Boys-table interpolation of the near field.
+//   T = B = double: FP64 throughout.
+//   T = double, B = float (mixed): the near-field Taylor interpolation of F_n(T) runs in FP32 on
+//     the FP32 table (order 4); its argument, the prefactors and the scaling to R^(n) stay FP64,
+//     and the large-T branch is FP64.
+//   T = B = float: FP32 throughout (used only for pairs whose screening bound is small).
 // ----------------------------------------------------------------------------------------
 __device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
 __device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
@@ -133,26 +138,12 @@ constexpr int PT_PAD = 64;  // point arrays are padded to a multiple of this wit
 // n <= L.  Kernels stage only these columns, so low-L kernels keep more workgroups resident.
 template <typename T, int L> __host__ __device__ constexpr int boys_cols() { return L + BoysCfg<T>::ORD + 1; }
 
-template <int L, typename T>
-__device__ __forceinline__ void aux_Rn(double r2d, T p, T limp, T pf, T pref, T zeta2, T zeta, T limk,
-                                       const T *__restrict__ tab, T (&Rn)[L + 1]) {
-    using C = BoysCfg<T>;
-    static_assert(boys_cols<T, L>() <= C::MT, "Boys table has too few columns for this L");
-    if constexpr (sizeof(T) == 4) {
-        if (r2d >= (double)(limp + limk)) {  // large T: FP64 (see above)
-            const double ri = rsq_fast(r2d), ri2 = ri * ri;
-            double R = (double)pf * ri;
-            Rn[0] = (T)R;
-#pragma unroll
-            for (int n = 1; n <= L; ++n) {
-                R *= double(-(2 * n - 1)) * ri2;
-                Rn[n] = (T)R;
-            }
-            return;
-        }
-    }
-    const T r2 = (T)r2d;
-    if (sizeof(T) == 8 && r2 >= limp + limk) {
+template <int L, typename T, typename B = T>
+__device__ __forceinline__ void aux_Rn(T r2, T p, T limp, T pf, T pref, T zeta2, T zeta, T limk,
+                                       const B *__restrict__ tab, T (&Rn)[L + 1]) {
+    using C = BoysCfg<B>;
+    static_assert(boys_cols<B, L>() <= C::MT, "Boys table has too few columns for this L");
+    if (r2 >= limp + limk) {
         T ri = rsq_fast(r2);
         T ri2 = ri * ri;
         Rn[0] = pf * ri;
@@ -166,40 +157,40 @@ __device__ __forceinline__ void aux_Rn(double r2d, T p, T limp, T pf, T pref, T 
         T tb = a * r2;
         int i = (int)(tb * T(8) + T(0.5));
         i = i < C::NROW - 1 ? i : C::NROW - 1;
-        T d = T(i) * T(0.125) - tb;
-        // F_n(T) = sum_k F_{n+k}(T_i) d^k / k!, nested: F_n + d (F_{n+1} + d/2 (F_{n+2} + ...))
-        T dk[C::ORD + 1];
+        const B d = (B)(T(i) * T(0.125) - tb);
+        // F_n(T) = sum_k F_{n+k}(T_i) d^k / k!, nested: F_n + d (F_{n+1} + d/2 (F_{n+2} + ...)),
+        // in the table's precision
+        B dk[C::ORD + 1];
 #pragma unroll
-        for (int k = 1; k <= C::ORD; ++k) dk[k] = d * (T(1) / T(k));
-        const T *row = tab + i * boys_cols<T, L>();
+        for (int k = 1; k <= C::ORD; ++k) dk[k] = d * (B(1) / B(k));
+        const B *row = tab + i * boys_cols<B, L>();
         T fac = pref * su;
         T m2a = T(-2) * a;
 #pragma unroll
         for (int n = 0; n <= L; ++n) {
-            T F = row[n + C::ORD];
+            B F = row[n + C::ORD];
 #pragma unroll
             for (int k = C::ORD; k >= 1; --k) F = fma(F, dk[k], row[n + k - 1]);
-            Rn[n] = fac * F;
+            Rn[n] = fac * (T)F;
             fac *= m2a;
         }
     }
 }
 
-// squared distance of the FP64 differences (X, Y, Z) = P - C: the FP64 kernels square their
-// (unchanged) components, the FP32 kernels keep the FP64 square for the large-T branch
-template <typename T> __device__ __forceinline__ double dist2(double X, double Y, double Z) {
-    if constexpr (sizeof(T) == 8) return X * X + Y * Y + Z * Z;
-    else return fma(X, X, fma(Y, Y, Z * Z));
+// R_tuv (t+u+v <= L) of one pair against one point; (X, Y, Z) = P - C.
+template <int L, typename T, typename B = T>
+__device__ __forceinline__ void eval_R(double X, double Y, double Z, const PairHdr<T> &h, T zeta2, T zeta, T limk,
+                                       const B *__restrict__ tab, T (&R)[ntuv(L)]) {
+    T x = T(X), y = T(Y), z = T(Z);
+    T r2 = x * x + y * y + z * z;
+    T Rn[L + 1];
+    aux_Rn<L, T, B>(r2, h.p, h.limp, h.pf, h.pref, zeta2, zeta, limk, tab, Rn);
+    MdR<L>::run(x, y, z, Rn, R);
 }
 
-// R_tuv (t+u+v <= L) of one pair against one point; (X, Y, Z) = P - C.
-template <int L, typename T>
-__device__ __forceinline__ void eval_R(double X, double Y, double Z, const PairHdr<T> &h, T zeta2, T zeta, T limk,
-                                       const T *__restrict__ tab, T (&R)[ntuv(L)]) {
-    T x = T(X), y = T(Y), z = T(Z);
-    T Rn[L + 1];
-    aux_Rn<L, T>(dist2<T>(X, Y, Z), h.p, h.limp, h.pf, h.pref, zeta2, zeta, limk, tab, Rn);
-    MdR<L>::run(x, y, z, Rn, R);
+// name of a kernel precision (records/accumulation T, Boys interpolation B) in profiles and keys
+template <typename T, typename B> constexpr const char *prec_tag() {
+    return sizeof(T) == 4 ? "f32" : (sizeof(B) == 4 ? "mix" : "f64");
 }
 
 // pairs per batch of wave-uniform record loads in the point-per-lane kernels
@@ -370,6 +361,7 @@ struct pcm_ctx {
     DevBuf<float> boys32;
     DevBuf<double> scal;  // small scalar workspace (reductions, solver scalars)
     DevBuf<int> iscal;
+    DevBuf<long long> lscal;
     std::map<std::string, int> tuned;  // autotuner choices by kernel / shape key
     DevBuf<unsigned char> desc;        // descriptor tables of the current integral launch
 };
@@ -429,9 +421,11 @@ struct pcm_mol {
     PairList fock, esp, fock_w, esp_w;
     // merged list of the one-pass Fock + gradient pair side: survivors of Eq. 15 or of Eq. 18 (its
     // bits per candidate shell pair in m18); header-only records
-    PairList fg;
-    DevBuf<unsigned long long> m18;
+    PairList fg, fg_w;                  // fg_w: the FP32 part of a PCM_DYNAMIC split (else empty)
+    DevBuf<unsigned long long> m18, m15;  // Eq. 18 and Eq. 15 survivor bits per candidate shell pair
     DevBuf<int> c18;
+    DevBuf<unsigned long long> mtmp;    // screening scratch of the precision splits [3 x candidates]
+    DevBuf<int> ctmp;
     bool esp_valid = false;
     // workspaces
     DevBuf<double> part;   // partial sums (esp / gradient)
@@ -512,8 +506,10 @@ void run_esp_deriv(pcm_ctx *ctx, pcm_mol *mol, double *c, double *dc, int prec);
 // precision take one pair-side pass over the merged list fg (built by pairs_merged_build)
 void run_fock_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, const double *dc, double *F,
                    double *g_nuc, double *g_surf, int prec);
-// screen with P (Eq. 18 bits into m18) and build fg = Eq. 15 list | Eq. 18 list with header records
-void pairs_merged_build(pcm_ctx *ctx, pcm_mol *mol, const double *P, int prec);
+// screen with P (Eq. 18 bits into m18, Eq. 15 bits into m15) and build fg = Eq. 15 list | Eq. 18
+// list with FP64 header records; `dynamic` splits it at dp_thresh (Eq. 15 bound or Eq. 18 weight)
+// into fg (FP64 records) and fg_w (FP32 records)
+void pairs_merged_build(pcm_ctx *ctx, pcm_mol *mol, const double *P, bool dynamic);
 // contraction to F blocks and scatter of V sums held in vin (stride vnt), class cl of list pl
 void fock_contract_scatter(pcm_ctx *ctx, pcm_mol *mol, const PairList &pl, int cl, const double *vin, int nch,
                            int vnt, const unsigned long long *memb, double *F);

@@ -47,6 +47,7 @@ void ctx_ensure_device(pcm_ctx *ctx) {
     ctx->boys32.ensure(t32.size());
     ctx->scal.ensure(4096);
     ctx->iscal.ensure(64);
+    ctx->lscal.ensure(64);
     HIP_OK(hipMemcpyAsync(ctx->boys64.p, t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     HIP_OK(hipMemcpyAsync(ctx->boys32.p, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
     HIP_OK(hipStreamSynchronize(ctx->stream));
@@ -417,15 +418,12 @@ static void pairs_compact(pcm_ctx *ctx, pcm_mol *mol, PairList &pl) {
     // shell-pair survivor counts per class
     std::vector<int> spc(NCLS, 0);
     if (nsp > 0) {
-        DevBuf<long long> off;
-        off.ensure(NCLS + 1);
-        HIP_OK(hipMemcpyAsync(off.p, mol->sp_cls_off, sizeof(long long) * (NCLS + 1), hipMemcpyHostToDevice,
+        HIP_OK(hipMemcpyAsync(ctx->lscal.p, mol->sp_cls_off, sizeof(long long) * (NCLS + 1), hipMemcpyHostToDevice,
                               ctx->stream));
-        k_count_sp<<<NCLS, 256, 0, ctx->stream>>>((int)nsp, pl.cnt.p, off.p, ctx->iscal.p);
+        k_count_sp<<<NCLS, 256, 0, ctx->stream>>>((int)nsp, pl.cnt.p, ctx->lscal.p, ctx->iscal.p);
         HIP_LAUNCH_OK();
         HIP_OK(hipMemcpyAsync(spc.data(), ctx->iscal.p, sizeof(int) * NCLS, hipMemcpyDeviceToHost, ctx->stream));
         HIP_OK(hipStreamSynchronize(ctx->stream));
-        off.release();
     }
     HIP_OK(hipStreamSynchronize(ctx->stream));
     for (int c = 0; c <= NCLS; ++c) pl.cls_off[c] = bnd[c];
@@ -472,13 +470,11 @@ void pairs_split(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, PairList &weak, const
     weak.cnt.ensure(nsp + 1);
     weak.spo.ensure(nsp + 1);
     if (nsp > 0) {
-        DevBuf<unsigned long long> sbits;
-        DevBuf<int> scnt;
-        sbits.ensure(nsp);
-        scnt.ensure(nsp);
-        screen_launch(ctx, mol, P, std::max(thresh, ctx->prm.schwarz_thresh), sbits.p, scnt.p);
-        k_mask_split<<<div_up(nsp, 256), 256, 0, ctx->stream>>>((int)nsp, sbits.p, pl.mask.p, pl.cnt.p, weak.mask.p,
-                                                                weak.cnt.p);
+        mol->mtmp.ensure(3 * (size_t)nsp);
+        mol->ctmp.ensure(nsp);
+        screen_launch(ctx, mol, P, std::max(thresh, ctx->prm.schwarz_thresh), mol->mtmp.p, mol->ctmp.p);
+        k_mask_split<<<div_up(nsp, 256), 256, 0, ctx->stream>>>((int)nsp, mol->mtmp.p, pl.mask.p, pl.cnt.p,
+                                                                weak.mask.p, weak.cnt.p);
         HIP_LAUNCH_OK();
         HIP_OK(hipStreamSynchronize(ctx->stream));
     }
@@ -667,21 +663,49 @@ __global__ void k_mask_or(int nsp, const unsigned long long *__restrict__ a, con
     cnt[sp] = __popcll(m);
 }
 
-void pairs_merged_build(pcm_ctx *ctx, pcm_mol *mol, const double *P, int prec) {
+void pairs_merged_build(pcm_ctx *ctx, pcm_mol *mol, const double *P, bool dynamic) {
     const long long nsp = mol->sp_cls_off[NCLS];
-    PairList &fg = mol->fg;
+    PairList &fg = mol->fg, &fw = mol->fg_w;
     mol->m18.ensure(nsp + 1);
     mol->c18.ensure(nsp + 1);
-    fg.mask.ensure(nsp + 1);
-    fg.cnt.ensure(nsp + 1);
-    fg.spo.ensure(nsp + 1);
+    mol->m15.ensure(nsp + 1);
+    for (PairList *l : {&fg, &fw}) {
+        l->mask.ensure(nsp + 1);
+        l->cnt.ensure(nsp + 1);
+        l->spo.ensure(nsp + 1);
+    }
     if (nsp > 0) {
+        const int g = div_up(nsp, 256);
         screen_launch(ctx, mol, P, ctx->prm.schwarz_thresh, mol->m18.p, mol->c18.p);
-        k_mask_or<<<div_up(nsp, 256), 256, 0, ctx->stream>>>((int)nsp, mol->fock.mask.p, mol->m18.p, fg.mask.p,
-                                                             fg.cnt.p);
+        // the Eq. 15 bits: the Fock list, or both of its parts when the precision is split
+        k_mask_or<<<g, 256, 0, ctx->stream>>>((int)nsp, mol->fock.mask.p, dynamic ? mol->fock_w.mask.p : mol->fock.mask.p,
+                                              mol->m15.p, fw.cnt.p);
         HIP_LAUNCH_OK();
+        k_mask_or<<<g, 256, 0, ctx->stream>>>((int)nsp, mol->m15.p, mol->m18.p, fg.mask.p, fg.cnt.p);
+        HIP_LAUNCH_OK();
+        if (dynamic) {
+            // FP64 part: entries whose Eq. 15 bound or Eq. 18 weight reaches dp_thresh
+            const double th = std::max(ctx->prm.dp_thresh, ctx->prm.schwarz_thresh);
+            mol->mtmp.ensure(3 * (size_t)nsp);
+            mol->ctmp.ensure(nsp);
+            unsigned long long *s1 = mol->mtmp.p, *s2 = s1 + nsp, *s3 = s2 + nsp;
+            screen_launch(ctx, mol, nullptr, th, s1, mol->ctmp.p);
+            screen_launch(ctx, mol, P, th, s2, mol->ctmp.p);
+            k_mask_or<<<g, 256, 0, ctx->stream>>>((int)nsp, s1, s2, s3, mol->ctmp.p);
+            HIP_LAUNCH_OK();
+            k_mask_split<<<g, 256, 0, ctx->stream>>>((int)nsp, s3, fg.mask.p, fg.cnt.p, fw.mask.p, fw.cnt.p);
+            HIP_LAUNCH_OK();
+            HIP_OK(hipStreamSynchronize(ctx->stream));
+        }
     }
     pairs_compact(ctx, mol, fg);
     for (int c = 0; c < NCLS; ++c) fg.sp_union[c] = fg.sp_count[c];
-    pairs_prepare_geometry(ctx, mol, fg, prec);
+    pairs_prepare_geometry(ctx, mol, fg, PCM_FP64);
+    if (dynamic) {
+        pairs_compact(ctx, mol, fw);
+        pairs_prepare_geometry(ctx, mol, fw, PCM_MIXED);  // FP32 records
+    } else {
+        fw.n = 0;
+        for (int c = 0; c <= NCLS; ++c) fw.cls_off[c] = 0;
+    }
 }

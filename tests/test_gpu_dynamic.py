@@ -3,8 +3,10 @@ dp_thresh are evaluated in FP64, the others in FP32 with FP64 accumulation.
 
 * The two parts together are the FP64 lists exactly (merged entries and sizes).
 * dp_thresh = 0 puts every pair in the FP64 part: c, F and the gradient equal the FP64 form bit
-  for bit.  A threshold above every bound puts every pair in the FP32 part: they equal the mixed
-  form bit for bit.
+  for bit.  A threshold above every bound puts every pair in the FP32 part (FP32 records, Boys
+  interpolation and far field, FP64 accumulation): the results then carry FP32 evaluation
+  errors, within 1e-6 of the FP64 form, and differ from the mixed form (FP64 records, FP32
+  Boys interpolation only).
 * At the default 1e-6 the results stay within 1e-10 (c, F) and 1e-9 (gradient) of the oracle.
 * Batched calls equal single calls bit for bit.
 """
@@ -64,7 +66,10 @@ def test_limits_are_the_fixed_precisions(case, torch_cuda):
     _, dinf = _run(case, torch, precision="dynamic", dp_thresh=1e30, autotune=False)
     for k in r64:
         assert torch.equal(d0[k], r64[k]), k
-        assert torch.equal(dinf[k], r32[k]), k
+        scale = r64[k].abs().max().item()
+        assert (dinf[k] - r64[k]).abs().max().item() <= 1e-6 * max(1.0, scale), k
+        assert (r32[k] - r64[k]).abs().max().item() <= 1e-7 * max(1.0, scale), k
+    assert not torch.equal(dinf["c"], r32["c"])
 
 
 def test_split_lists_cover_the_fp64_lists(case, torch_cuda):

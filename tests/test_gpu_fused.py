@@ -128,14 +128,16 @@ def test_fused_other_precisions(case, torch_cuda, prec):
     torch_cuda.cuda.synchronize()
     g = om.grad_terms(s.P, ref["q"])
     sc = max(1.0, np.abs(g["g_nuc"]).max(), np.abs(g["g_surf"]).max())
-    tol_c, tol_g = (1e-10, 1e-9) if prec == "dynamic" else (1e-6, 1e-5)
+    tol_c, tol_g = (1e-10, 1e-9) if prec == "dynamic" else (1e-8, 1e-7)
     assert rel(c.cpu().numpy(), ref["c"]) <= tol_c
     assert rel(F.cpu().numpy(), om.fock(ref["q"])) <= tol_c
     assert np.abs(gn.cpu().numpy() - g["g_nuc"]).max() <= tol_g * sc
     assert np.abs(gs.cpu().numpy() - g["g_surf"]).max() <= tol_g * sc
-    # against the separate calls in the same precision
-    assert rel(F.cpu().numpy(), F_sep.cpu().numpy()) <= (1e-12 if prec == "dynamic" else 1e-6)
-    assert np.abs(gn.cpu().numpy() - gn_sep.cpu().numpy()).max() <= (1e-12 if prec == "dynamic" else 1e-6) * sc
+    # against the separate calls in the same precision (the dynamic form splits the merged list by
+    # the larger of its two weights, so a few pairs change precision: FP32-level differences on
+    # weak pairs only)
+    assert rel(F.cpu().numpy(), F_sep.cpu().numpy()) <= (1e-10 if prec == "dynamic" else 1e-9)
+    assert np.abs(gn.cpu().numpy() - gn_sep.cpu().numpy()).max() <= (1e-10 if prec == "dynamic" else 1e-8) * sc
 
 
 def test_fused_bitwise_reproducible(case, torch_cuda):

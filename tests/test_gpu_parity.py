@@ -177,11 +177,13 @@ def test_mixed_integrals_error_statement(case, torch_cuda):
            "g_nuc_abs": np.abs(gn.cpu().numpy() - g["g_nuc"]).max(),
            "g_surf_abs": np.abs(gs.cpu().numpy() - g["g_surf"]).max()}
     print("mixed-precision errors vs FP64 oracle:", {k: f"{v:.2e}" for k, v in err.items()}, flush=True)
-    # stated bounds of the mixed form (measured errors are printed above)
-    assert err["c_rel"] <= 1e-6 and err["F_rel"] <= 1e-6
+    # stated bounds of the mixed form (measured errors are printed above); q carries the
+    # condition number of A times the relative error of c, so it is held to a looser bound
+    # (measured: c 3e-9 to 9e-9, F 2e-8 to 2e-7 for these random charges of both signs)
+    assert err["c_rel"] <= 3e-8 and err["F_rel"] <= 1e-6
     assert err["E_abs"] <= 1e-6
     assert err["q_rel_max"] <= 1e-3
-    assert err["g_nuc_abs"] <= 1e-5 and err["g_surf_abs"] <= 1e-5
+    assert err["g_nuc_abs"] <= 1e-6 and err["g_surf_abs"] <= 1e-6
 
 
 def test_matvec_shares_add_up(case, torch_cuda):
