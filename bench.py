@@ -21,10 +21,12 @@ against the same 64 done one after another with the plain FP64 single-molecule c
 The geometries are fixed, so surfaces, pair lists and RBJ blocks are built before timing.
 
 Third workload (--workload stress2000): the 2,000-atom solute (M ~ 150k).  Fifteen
-SCF-like outer iterations t = 1..15 solve A q = -f v_t with v_t = Bz + L (P + dP_t) for a
-sparse seeded perturbation dP_t, the threshold tightening as delta_t = 10^(-3 - 4(t-1)/14)
-(the Eq. 21 range), each solve warm-started from the previous q; unpreconditioned and RBJ
-with blocks of 1,024 points, FP64 and mixed (FP32 matvec in FP64 refinement).
+SCF-like outer iterations t = 1..15, each with its own density P_t = 2 C_t C_t^T,
+C_t = orth(C_{t-1} + e_t G_t), and its own c_t = L P_t evaluated on the GPU (timed
+separately), solve A q = -f (Bz + c_t) with the threshold tightening as
+delta_t = 10^(-3 - 4(t-1)/14) (the Eq. 21 range), each solve warm-started from the previous q;
+unpreconditioned and RBJ with blocks of 1,024 points, FP64 and mixed (FP32 matvec in FP64
+refinement).
 
 One GPU's share of the sharded matvec (--workload shard8): the 2,000-atom solute's product split
 over 8 ranks as a multi-GPU solve would split it; each rank's kernel time at its real shape,
@@ -517,42 +519,50 @@ def bench_stress(args):
     t = time.time()
     s = I.linear_solve_stress()
     log(f"[bench] inputs in {time.time() - t:.1f}s: {s.n_atoms} atoms, nbf {s.basis.nbf}")
-    P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
     nbf = s.basis.nbf
     n_out = 15
-    # thresholds from Eq. 21 (pcm_dynamic_threshold) fed a synthetic DIIS error sequence chosen
-    # so that the schedule tightens geometrically from 1e-3 to 1e-7
-    target = [10.0 ** (-3.0 - 4.0 * t / (n_out - 1)) for t in range(n_out)]
-    diis_err = [10.0 * d ** 1.07 for d in target]
+    # thresholds from Eq. 21 (pcm_dynamic_threshold) fed the synthetic DIIS error sequence of the
+    # schedule, which tightens geometrically from 1e-3 to 1e-7
+    diis_err, target = I.stress_outer_errors(n_out)
     deltas = [dynamic_threshold(e) for e in diis_err]
     assert all(abs(d / t - 1.0) < 1e-9 for d, t in zip(deltas, target)), (deltas, target)
-    rng = np.random.default_rng(s.seeds["pert"])
-    # sparse symmetric perturbations: 256 local entries per step, size ~ 10 delta_t
-    dPs = []
-    for t in range(n_out):
-        i = rng.integers(0, nbf, 256)
-        j = np.clip(i + rng.integers(-32, 33, 256), 0, nbf - 1)
-        val = rng.normal(size=256) * 10.0 * deltas[t]
-        dPs.append((torch.tensor(i), torch.tensor(j), torch.tensor(val)))
+    # the outer densities P_t = 2 C_t C_t^T, C_t = orth(C_{t-1} + e_t G_t) (block-diagonal C)
+    t = time.time()
+    seq = I.stress_density_sequence(s, n_out)
+    log(f"[bench] {n_out} perturbed occupied blocks in {time.time() - t:.1f}s")
     runs = {}
     ctx = Context(precision="fp64")  # integrals in FP64: this workload measures the solver
     t = time.time()
     mol = Molecule.from_system(ctx, s)
     torch.cuda.synchronize()
     log(f"[bench] surface + lists in {time.time() - t:.1f}s, M = {mol.M}")
-    t = time.time()
-    c0, bz = mol.esp(P)
-    dP = torch.zeros_like(P)
-    vs = []
-    for (i, j, val) in dPs:
-        dP.zero_()
-        dP.index_put_((i.cuda(), j.cuda()), val.cuda(), accumulate=True)
-        dP.index_put_((j.cuda(), i.cuda()), val.cuda(), accumulate=True)
-        dc = mol.esp(dP, want_bz=False)
-        vs.append(bz + c0 + dc)
-    del dP
+    P = torch.zeros((nbf, nbf), dtype=torch.float64, device="cuda")
+
+    def density_on_gpu(windows):
+        # input synthesis (untimed): the block-diagonal P_t assembled in HBM from its windows
+        P.zero_()
+        for s0, C in windows:
+            Cg = torch.tensor(C, dtype=torch.float64, device="cuda")
+            B = 2.0 * torch.mm(Cg, Cg.t().contiguous())
+            P[s0:s0 + C.shape[0], s0:s0 + C.shape[0]] = 0.5 * (B + B.t())
+
+    vs, esp_ms, esp_pairs = [], [], []
+    # one untimed c with the unperturbed density first: chunk shapes are tuned on first use
+    P.copy_(torch.tensor(s.P, dtype=torch.float64))
+    c_t, bz = mol.esp(P)
     torch.cuda.synchronize()
-    log(f"[bench] c = L P and the 15 perturbed right-hand sides in {time.time() - t:.1f}s")
+    for t_ in range(n_out):
+        density_on_gpu(seq[t_])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c_t = mol.esp(P, want_bz=False)
+        torch.cuda.synchronize()
+        esp_ms.append(round((time.perf_counter() - t0) * 1e3, 1))
+        esp_pairs.append(int(sum(mol.sizes()["pairs_esp"])))
+        vs.append(bz + c_t)
+    del P
+    torch.cuda.synchronize()
+    log(f"[bench] c_t = L P_t for the {n_out} outer densities: {esp_ms} ms")
     for prec in ("fp64", "mixed"):
         for pc, blk, cap in (("rbj", 1024, 10000), ("none", 0, args.max_iter_none)):
             q = None
@@ -581,7 +591,8 @@ def bench_stress(args):
            "config": {"workload": "protein2000_631gs_stress", "atoms": s.n_atoms, "nbf": nbf, "surface_points": mol.M,
                       "outer_iterations": n_out, "deltas": deltas, "rbj_block": 1024,
                       "max_iter_unpreconditioned": args.max_iter_none},
-           "runs": runs}
+           "esp_ms_per_outer": esp_ms, "esp_prim_pairs_per_outer": esp_pairs,
+           "esp_ms_total": round(sum(esp_ms), 1), "runs": runs}
     print(json.dumps(out))
 
 

@@ -369,20 +369,28 @@ __global__ void k_screen_write(int nsp, const unsigned long long *__restrict__ m
 }
 
 __global__ void k_count_sp(int nsp, const int *__restrict__ cnt, const long long *__restrict__ cls_sp_off,
-                           int *__restrict__ out /* [NCLS] */) {
-    // one block per class, deterministic count of shell pairs with survivors
+                           int *__restrict__ out /* [NCLS], zeroed */) {
+    // shell pairs with survivors per class: blockIdx.y = class, grid-stride over its shell pairs;
+    // integer sums, so the result does not depend on the order of the atomic adds
     __shared__ int s[256];
-    int c = blockIdx.x;
-    long long b0 = cls_sp_off[c], b1 = cls_sp_off[c + 1];
+    const int c = blockIdx.y;
+    const long long b0 = cls_sp_off[c], b1 = cls_sp_off[c + 1];
     int acc = 0;
-    for (long long sp = b0 + threadIdx.x; sp < b1; sp += blockDim.x) acc += cnt[sp] > 0;
+    for (long long sp = b0 + (long long)blockIdx.x * blockDim.x + threadIdx.x; sp < b1;
+         sp += (long long)gridDim.x * blockDim.x)
+        acc += cnt[sp] > 0;
     s[threadIdx.x] = acc;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[c] = s[0];
+    if (threadIdx.x == 0 && s[0]) atomicAdd(out + c, s[0]);
+}
+
+__global__ void k_zero_int(int *__restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 static void screen_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, double thresh, unsigned long long *mask,
@@ -420,7 +428,9 @@ static void pairs_compact(pcm_ctx *ctx, pcm_mol *mol, PairList &pl) {
     if (nsp > 0) {
         HIP_OK(hipMemcpyAsync(ctx->lscal.p, mol->sp_cls_off, sizeof(long long) * (NCLS + 1), hipMemcpyHostToDevice,
                               ctx->stream));
-        k_count_sp<<<NCLS, 256, 0, ctx->stream>>>((int)nsp, pl.cnt.p, ctx->lscal.p, ctx->iscal.p);
+        k_zero_int<<<1, 64, 0, ctx->stream>>>(ctx->iscal.p, NCLS);
+        HIP_LAUNCH_OK();
+        k_count_sp<<<dim3(64, NCLS), 256, 0, ctx->stream>>>((int)nsp, pl.cnt.p, ctx->lscal.p, ctx->iscal.p);
         HIP_LAUNCH_OK();
         HIP_OK(hipMemcpyAsync(spc.data(), ctx->iscal.p, sizeof(int) * NCLS, hipMemcpyDeviceToHost, ctx->stream));
         HIP_OK(hipStreamSynchronize(ctx->stream));

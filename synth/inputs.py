@@ -229,24 +229,77 @@ def density_matrix(nbf: int, n_occ: int, p_seed: int):
     return 0.5 * (P + P.T)
 
 
-def density_matrix_blocked(nbf: int, n_occ: int, p_seed: int, window: int = 1024):
-    """P = 2 C C^T with C block-diagonal over windows of `window` consecutive functions, each
-    window holding its share of the n_occ occupied columns as a seeded orthonormal block.
-    The columns of C are orthonormal, so P/2 is a projector of rank n_occ, as for the dense
-    generator, but the cost is linear in nbf (used where nbf ~ 17k)."""
+def occupied_windows(nbf: int, n_occ: int, p_seed: int, window: int = 1024):
+    """Block-diagonal occupied coefficients: windows of `window` consecutive functions, each
+    holding its share of the n_occ occupied columns as a seeded orthonormal block.  Returns a
+    list of (first function, block) with blocks of shape (window, k)."""
     rng = np.random.default_rng(p_seed)
-    P = np.zeros((nbf, nbf))
-    starts = list(range(0, nbf, window))
+    out = []
     done = 0
-    for b, s0 in enumerate(starts):
+    for s0 in range(0, nbf, window):
         s1 = min(nbf, s0 + window)
         k = round(n_occ * s1 / nbf) - done
         k = max(0, min(k, s1 - s0))
         done += k
         if k:
-            C = orthonormal_columns(s1 - s0, k, rng)
-            P[s0:s1, s0:s1] = 2.0 * (C @ C.T)
-    return 0.5 * (P + P.T)
+            out.append((s0, orthonormal_columns(s1 - s0, k, rng)))
+    return out
+
+
+def density_from_windows(nbf: int, windows):
+    """P = 2 C C^T for block-diagonal C, symmetrised block by block (P is block-diagonal, so
+    this equals symmetrising the whole matrix)."""
+    P = np.empty((nbf, nbf))
+    P.fill(0.0)  # touched once in order (first-touch page faults of a lazy zero array are slow here)
+    for s0, C in windows:
+        B = 2.0 * (C @ C.T)
+        s1 = s0 + C.shape[0]
+        P[s0:s1, s0:s1] = 0.5 * (B + B.T)
+    return P
+
+
+def density_matrix_blocked(nbf: int, n_occ: int, p_seed: int, window: int = 1024):
+    """P = 2 C C^T with C block-diagonal over windows of `window` consecutive functions, each
+    window holding its share of the n_occ occupied columns as a seeded orthonormal block.
+    The columns of C are orthonormal, so P/2 is a projector of rank n_occ, as for the dense
+    generator, but the cost is linear in nbf (used where nbf ~ 17k)."""
+    return density_from_windows(nbf, occupied_windows(nbf, n_occ, p_seed, window))
+
+
+def stress_outer_errors(n_out: int = 15):
+    """Synthetic DIIS errors of the 2,000-atom stress schedule: e_t = 10 delta_t^1.07 with
+    delta_t = 10^(-3 - 4 (t-1)/(n_out-1)), t = 1..n_out, so that Eq. 21 gives back delta_t
+    (1e-3 down to 1e-7)."""
+    deltas = [10.0 ** (-3.0 - 4.0 * t / (n_out - 1)) for t in range(n_out)]
+    return [10.0 * d ** 1.07 for d in deltas], deltas
+
+
+def perturbed_windows(windows, e_t: float, rng):
+    """One outer step of the stress schedule: C_t = orth(C_{t-1} + e_t G_t) window by window,
+    G_t seeded Gaussian, orth = QR with diag(R) > 0 (the columns stay orthonormal, so
+    P_t = 2 C_t C_t^T is again a rank-n_occ projector times 2)."""
+    out = []
+    for s0, C in windows:
+        Q, R = np.linalg.qr(C + e_t * rng.normal(size=C.shape))
+        sg = np.sign(np.diag(R))
+        sg[sg == 0] = 1.0
+        out.append((s0, Q * sg))
+    return out
+
+
+def stress_density_sequence(s, n_out: int = 15):
+    """The occupied windows C_1 .. C_n_out of the stress schedule for system s (2,000 atoms,
+    blocked density): C_0 from the system's P seed, G_t from its perturbation seed."""
+    nbf = s.basis.nbf
+    n_occ = min(int(s.Z.sum()) // 2, nbf)
+    C = occupied_windows(nbf, n_occ, s.seeds["P"])
+    errs, _ = stress_outer_errors(n_out)
+    rng = np.random.default_rng(s.seeds["pert"])
+    seq = []
+    for e in errs:
+        C = perturbed_windows(C, e, rng)
+        seq.append(C)
+    return seq
 
 
 # ----------------------------------------------------------------------------

@@ -9,6 +9,10 @@
   bohr) on 20 seeded coordinates and the oracle on sampled surface points; the mixed form's
   analytic gradient is compared with the FP64 one.
 * Per-pair dynamic precision at both sizes: c, F and the gradient against the FP64 form.
+* The one-pass calls (c with dc; F with the gradient) and the mixed form on the 600-atom protein:
+  c on sampled points and F on sampled shell pairs of every class against the oracle.
+* 2,000-atom stress case (M ~ 150k, nbf 17,000): RBJ-1024 solves through oracle rows of A q - b,
+  and c_t = L P_t at the first and last outer densities of the stress schedule on sampled rows.
 """
 import numpy as np
 import pytest
@@ -324,23 +328,29 @@ def test_conformer_batch_full_size(torch_cuda):
 
 # ------------------------------------------------------------------ 2,000-atom solve
 
-def test_stress_solve_residual_rows(torch_cuda):
-    """M ~ 150k: RBJ-1024 solves, FP64 and mixed, at the tightest threshold of the stress
-    schedule (1e-7), checked through oracle rows of A q - b (the oracle computes rows one by
-    one); the symmetric tile matvec spans ~586 tiles here."""
+@pytest.fixture(scope="module")
+def stress(torch_cuda):
     from paper_1505_07851_amd import Context, Molecule
-    torch = torch_cuda
     print("\n[case protein2000 stress]", flush=True)
     s = I.linear_solve_stress()
     ctx = Context()
     mol = Molecule.from_system(ctx, s)
+    print("  M =", mol.M, flush=True)
+    om = O.mol_from_system(s)
+    assert om.M == mol.M
+    return s, ctx, mol, om
+
+
+def test_stress_solve_residual_rows(stress, torch_cuda):
+    """M ~ 150k: RBJ-1024 solves, FP64 and mixed, at the tightest threshold of the stress
+    schedule (1e-7), checked through oracle rows of A q - b (the oracle computes rows one by
+    one); the symmetric tile matvec spans ~586 tiles here."""
+    torch = torch_cuda
+    s, ctx, mol, om = stress
     P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
     c, bz = mol.esp(P)
     v = bz + c
     del P
-    print("  M =", mol.M, flush=True)
-    om = O.mol_from_system(s)
-    assert om.M == mol.M
     rng = np.random.default_rng(2024)
     kidx = np.sort(rng.choice(mol.M, 48, replace=False))
     vh = v.cpu().numpy()
@@ -351,6 +361,27 @@ def test_stress_solve_residual_rows(torch_cuda):
         assert info["resid"] < 1e-7
         r = om.matvec(q.cpu().numpy(), kidx=kidx) + om.f * vh[kidx]
         assert np.abs(r).max() < 1e-7
+
+
+def test_stress_outer_densities_c_sampled(stress, torch_cuda):
+    """M ~ 150k, nbf 17,000: c_t = L P_t for the first and the last outer density of the stress
+    schedule (P_t = 2 C_t C_t^T, C_t = orth(C_{t-1} + e_t G_t)), on 24 sampled rows each against
+    the oracle (1e-10 relative to the largest sampled |c|)."""
+    torch = torch_cuda
+    s, ctx, mol, om = stress
+    seq = I.stress_density_sequence(s)
+    rng = np.random.default_rng(2025)
+    for t in (0, len(seq) - 1):
+        Ph = I.density_from_windows(s.basis.nbf, seq[t])
+        P = torch.tensor(Ph, dtype=torch.float64, device="cuda")
+        c = mol.esp(P, want_bz=False).cpu().numpy()
+        del P
+        kidx = np.sort(rng.choice(mol.M, 24, replace=False))
+        c_or = om.esp(Ph, kidx=kidx)
+        err = np.abs(c[kidx] - c_or).max() / np.abs(c_or).max()
+        print(f"  t = {t + 1}: sampled c max rel err {err:.2e}", flush=True)
+        assert err <= 1e-10
+        del Ph
 
 
 def test_dynamic_precision_full_size(big, pep, torch_cuda):
