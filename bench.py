@@ -16,8 +16,10 @@ FP32 integral evaluation by screening bound, FP64 solve).  Inputs are synthetic 
 Second workload (--workload conformers64): 64 seeded conformers of a 150-atom peptide
 (6-31G-shaped basis, nbf 825, 3.9k-9k kept points each).  One step = c = L P with Bz,
 the RBJ-100 PCG solve, the Eq. 13 energy and F += L^T q for all 64, batched (one launch per
-class for the integrals, hipGraph-replayed PCG iteration groups over all conformers),
-against the same 64 done one after another with the plain FP64 single-molecule calls.
+class for the integrals, hipGraph-replayed PCG iteration groups over all conformers), and the
+same pass captured whole as one hipGraph (pcm_graph_capture: one launch per step, FP64 PCG
+with a fixed iteration budget), against the same 64 done one after another with the plain FP64
+single-molecule calls.
 The geometries are fixed, so surfaces, pair lists and RBJ blocks are built before timing.
 
 Third workload (--workload stress2000): the 2,000-atom solute (M ~ 150k).  Fifteen
@@ -657,6 +659,24 @@ def bench_conformers(args):
     ms_gb, g_b = timed(lambda: b64.grad(Ps, qs64))
     g_bitwise = all(torch.equal(a[0], c[0]) and torch.equal(a[1], c[1]) for a, c in zip(g_seq, g_b))
     log(f"[bench] gradient FP64: sequential {ms_gseq:.1f} ms, batched {ms_gb:.1f} ms, bitwise equal {g_bitwise}")
+    # the same pass captured as one hipGraph (c, Bz, FP64 PCG with an iteration budget, E, F); the
+    # budget is the largest count of the eager batched solve plus a margin
+    it_b = [r[1]["iters"] for r in r_b64]
+    budget = int(max(it_b) * 1.25) + 8
+    t = time.time()
+    g = b64.capture(Ps, precond="rbj", block=args.block, seed=7, tol=args.tol, max_iter=budget)
+    t_cap = time.time() - t
+
+    def graph_step():
+        for F in g.Fs:
+            F.zero_()
+        g.replay()
+        return g
+
+    ms_g, _ = timed(graph_step)
+    ginfo, nodes = g.info()
+    r_g = [(q, {"iters": d["iters"], "energy": d["energy"]}, F) for q, d, F in zip(g.qs, ginfo, g.Fs)]
+    log(f"[bench] captured graph ({nodes} nodes, budget {budget}, capture {t_cap:.1f}s): {ms_g:.1f} ms per step")
     ctxm, molsm = setup("mixed")
     bm = Batch(ctxm, molsm)
     ms_bm, r_bm = timed(lambda: batch_step(bm, "mixed"))
@@ -684,7 +704,14 @@ def bench_conformers(args):
            "batched_mixed": {"ms_per_step": round(ms_bm, 3), "ms_per_conformer": round(ms_bm / n_conf, 3),
                              "speedup_vs_sequential": round(ms_seq / ms_bm, 3), "err_vs_sequential": errs(r_bm)},
            "gradient_fp64": {"sequential_ms": round(ms_gseq, 3), "batched_ms": round(ms_gb, 3),
-                             "speedup": round(ms_gseq / ms_gb, 3), "bitwise_equal": g_bitwise}}
+                             "speedup": round(ms_gseq / ms_gb, 3), "bitwise_equal": g_bitwise},
+           "graph_fp64": {"ms_per_step": round(ms_g, 3), "ms_per_conformer": round(ms_g / n_conf, 3),
+                          "speedup_vs_sequential": round(ms_seq / ms_g, 3),
+                          "speedup_vs_batched": round(ms_b64 / ms_g, 3), "graph_nodes": nodes,
+                          "iteration_budget": budget, "capture_s": round(t_cap, 2),
+                          "all_converged": all(d["converged"] for d in ginfo),
+                          "err_vs_sequential": errs(r_g)}}
+    g.close()
     print(json.dumps(out))
 
 

@@ -57,6 +57,7 @@ enum { PCM_PRECOND_NONE = 0, PCM_PRECOND_JACOBI = 1, PCM_PRECOND_RBJ = 2, PCM_PR
 typedef struct pcm_ctx pcm_ctx;
 typedef struct pcm_mol pcm_mol;
 typedef struct pcm_batch pcm_batch;
+typedef struct pcm_graph pcm_graph;
 
 /* Model parameters (Sec. 2 and Sec. 3).
  *   eps            dielectric constant; f = (eps-1)/(eps+k_factor) (Eq. 1). Default 78.39.
@@ -351,6 +352,38 @@ pcm_status pcm_solve_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const
  * (one class of the batch needs more than 2^30 work items). */
 pcm_status pcm_grad_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *P, const double *const *q,
                             double *const *g_nuc, double *const *g_surf);
+
+/* One solvation pass of every molecule of a batch captured as a single hipGraph (many conformers
+ * with uneven surfaces in one launch): for molecule i, the Eq. 18 list screened with P[i] at
+ * capture and its density coefficients rebuilt from the current contents of P[i] at every replay,
+ * c[i] = L P[i] (Sec. 2, Eqs. 5-6) and bz[i] (Eq. 4), the preconditioned CG solve of
+ * A q = -f (bz + c) (Eq. 1, Sec. 4b) in FP64 from q = 0 with a fixed budget of opts->max_iter
+ * iterations (a molecule stops on the device once ||r|| < opts->tol on the CG recurrence; its
+ * remaining iterations skip), the explicit residual, q[i], the Eq. 13 energy E[i], and
+ * F[i] += L^T q[i] (Eq. 10).  Capture does all host work (screening, chunk choice and tuning,
+ * descriptor and solver tables, the block-Jacobi partition and inverses); a replay launches
+ * kernels only and allocates nothing.  The arrays are bound by address: HOST arrays of DEVICE
+ * pointers P[n] (nbf_i^2, read at each replay), c[n], bz[n], q[n] (M_i, written), F[n]
+ * (nbf_i^2, accumulated at each replay); DEVICE E[n] (written).  opts: NULL = defaults; precond,
+ * block, seed and tol as for pcm_solve, max_iter is the iteration budget (1..100000), precision
+ * must be PCM_FP64.  The pair lists stay as screened at capture: capture again (after
+ * pcm_graph_destroy) when the densities change enough to change the Eq. 18 screening.
+ * While the graph exists its batch and molecules refuse every call that could move their buffers
+ * (PCM_E_STATE); destroy the graph before the batch, the molecules or the context.
+ * Errors: PCM_E_ARG, PCM_E_UNSUPPORTED (precision other than FP64), PCM_E_STATE (batch or a
+ * molecule already bound), PCM_E_HIP, PCM_E_ALLOC. */
+pcm_status pcm_graph_capture(pcm_ctx *ctx, pcm_batch *batch, const double *const *P, double *const *c,
+                             double *const *bz, double *const *q, double *const *F, double *E,
+                             const pcm_solve_opts *opts, pcm_graph **out);
+/* Replay the captured pass on the context's stream (asynchronous; one hipGraphLaunch). */
+pcm_status pcm_graph_launch(pcm_ctx *ctx, pcm_graph *g);
+/* After a replay (synchronises the stream): HOST info[n] (may be NULL) with iters (CG iterations),
+ * resid (explicit ||A q - b||_2) and energy of each molecule; HOST *nodes (may be NULL) = kernel
+ * nodes in the graph.  Returns PCM_E_NOCONV when a molecule's explicit residual is not below tol
+ * (the budget ran out, or the recurrence converged ahead of the explicit residual: the captured
+ * solve has no restarts). */
+pcm_status pcm_graph_info(pcm_ctx *ctx, pcm_graph *g, pcm_solve_info *info, long long *nodes);
+void pcm_graph_destroy(pcm_graph *g);
 
 /* Per-kernel timing.  pcm_profile_enable(ctx, 1) clears previous records and makes every
  * heavy launch (integral, matvec, gradient and preconditioner kernels) record a pair of HIP

@@ -7,9 +7,9 @@ from ._lib import lib as _load_lib
 
 _load_lib()
 
-from .api import (Batch, Context, Molecule, PCMError, ThresholdPolicy, dynamic_threshold,  # noqa: E402
+from .api import (Batch, Context, Graph, Molecule, PCMError, ThresholdPolicy, dynamic_threshold,  # noqa: E402
                   octree_partition, rbj_partition)
 from .autograd import PCMEnergy, pcm_energy  # noqa: E402
 
-__all__ = ["Batch", "Context", "Molecule", "PCMError", "PCMEnergy", "ThresholdPolicy", "dynamic_threshold",
+__all__ = ["Batch", "Context", "Graph", "Molecule", "PCMError", "PCMEnergy", "ThresholdPolicy", "dynamic_threshold",
            "octree_partition", "pcm_energy", "rbj_partition"]

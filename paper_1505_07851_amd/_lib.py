@@ -23,6 +23,7 @@ EXPORTED = ["pcm_default_params", "pcm_default_solve_opts", "pcm_create", "pcm_d
             "pcm_octree_partition", "pcm_surface_get", "pcm_mol_sizes", "pcm_pair_list",
             "pcm_mol_destroy", "pcm_batch_create", "pcm_batch_destroy", "pcm_esp_batched", "pcm_fock_batched",
             "pcm_solve_batched", "pcm_grad_batched",
+            "pcm_graph_capture", "pcm_graph_launch", "pcm_graph_info", "pcm_graph_destroy",
             "pcm_profile_enable", "pcm_profile_collect", "pcm_profile_entry"]
 
 
@@ -94,6 +95,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "pcm_fock_batched": (i, [vp, vp, P(vp), P(vp)]),
         "pcm_solve_batched": (i, [vp, vp, P(vp), P(pcm_solve_opts), P(vp), P(pcm_solve_info)]),
         "pcm_grad_batched": (i, [vp, vp, P(vp), P(vp), P(vp), P(vp)]),
+        "pcm_graph_capture": (i, [vp, vp, P(vp), P(vp), P(vp), P(vp), P(vp), vp, P(pcm_solve_opts), P(vp)]),
+        "pcm_graph_launch": (i, [vp, vp]),
+        "pcm_graph_info": (i, [vp, vp, P(pcm_solve_info), P(ctypes.c_longlong)]),
+        "pcm_graph_destroy": (None, [vp]),
         "pcm_profile_enable": (i, [vp, i]),
         "pcm_profile_collect": (i, [vp]),
         "pcm_profile_entry": (i, [vp, i, ctypes.c_char_p, i, P(d), P(ctypes.c_longlong), P(d)]),

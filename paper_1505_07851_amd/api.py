@@ -372,7 +372,16 @@ class Batch:
             self.ctx.check(st)
         return qs, res
 
+    def capture(self, Ps, precond="rbj", block=100, seed=0, tol=1e-8, max_iter=500):
+        """The whole pass (c, Bz, FP64 PCG with an iteration budget, E, F += L^T q) of every molecule
+        captured as one hipGraph; returns a Graph whose replay() fills its c, bz, q, F, E."""
+        g = Graph(self, Ps, precond, block, seed, tol, max_iter)
+        self._graphs = getattr(self, "_graphs", []) + [g]
+        return g
+
     def close(self):
+        for g in getattr(self, "_graphs", []):
+            g.close()
         if getattr(self, "h", None):
             self.ctx.lib.pcm_batch_destroy(self.h)
             self.h = None
@@ -445,3 +454,58 @@ def default_f(eps=78.39, k=0.0):
 
 __all__ = ["Context", "Molecule", "Batch", "PCMError", "ThresholdPolicy", "dynamic_threshold", "octree_partition",
            "rbj_partition", "math"]
+
+
+class Graph:
+    """A captured batched pass (pcm_graph_capture).  Buffers: Ps (read at each replay), cs, bzs, qs,
+    Fs (F accumulates at each replay; zero it between replays for a fresh F) and E (energies).
+    While it exists the batch and its molecules refuse other calls; close() it first."""
+
+    def __init__(self, batch: "Batch", Ps, precond, block, seed, tol, max_iter):
+        import torch
+        self.batch, self.ctx = batch, batch.ctx
+        mols = batch.mols
+        self.Ps = [_f64(P, m.nbf * m.nbf, "P").contiguous() for P, m in zip(Ps, mols)]
+        self.cs = [m._zeros(m.M) for m in mols]
+        self.bzs = [m._zeros(m.M) for m in mols]
+        self.qs = [m._zeros(m.M) for m in mols]
+        self.Fs = [m._zeros(m.nbf, m.nbf) for m in mols]
+        self.E = torch.zeros(len(mols), dtype=torch.float64, device="cuda")
+        self.tol = float(tol)
+        o = _solve_opts(self.ctx.lib, precond, block, seed, tol, max_iter, "fp64", 1e-4)
+        h = ctypes.c_void_p()
+        p = batch._ptrs
+        self.ctx.check(self.ctx.lib.pcm_graph_capture(self.ctx.h, batch.h, p(self.Ps), p(self.cs), p(self.bzs),
+                                                      p(self.qs), p(self.Fs), _dp(self.E), ctypes.byref(o),
+                                                      ctypes.byref(h)))
+        self.h = h
+
+    def replay(self):
+        self.ctx.check(self.ctx.lib.pcm_graph_launch(self.ctx.h, self.h))
+
+    def info(self):
+        """(list of info dicts, graph node count) after a replay; a molecule whose explicit residual
+        is not below tol has 'converged' False."""
+        n = len(self.batch.mols)
+        infos = (C.pcm_solve_info * n)()
+        nodes = ctypes.c_longlong()
+        st = self.ctx.lib.pcm_graph_info(self.ctx.h, self.h, infos, ctypes.byref(nodes))
+        if st not in (C.PCM_OK, C.PCM_E_NOCONV):
+            self.ctx.check(st)
+        out = []
+        for i in infos:
+            d = _info_dict(i, st)
+            d["converged"] = i.resid < self.tol
+            out.append(d)
+        return out, nodes.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.pcm_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libpcm.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.hip", "setup.hip", "integrals.hip", "solve.hip", "rbj.hip", "grad.hip"]
+SOURCES = ["api.hip", "setup.hip", "integrals.hip", "solve.hip", "rbj.hip", "grad.hip", "graph.hip"]
 # the setup unit makes keep/screen decisions: plain IEEE expressions, no contraction
 EXTRA = {"setup.hip": ["-ffp-contract=off"]}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

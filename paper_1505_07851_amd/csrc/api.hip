@@ -16,25 +16,6 @@ bool is_fin(double x) { return std::isfinite(x); }
 bool misaligned(const void *p) { return ((uintptr_t)p & 7) != 0; }
 template <typename... A> bool any_misaligned(const A *...p) { return (misaligned(p) || ...); }
 
-pcm_status fail(pcm_ctx *ctx, pcm_status st, const std::string &msg) {
-    if (ctx) ctx->err = msg;
-    return st;
-}
-
-template <typename F> pcm_status guarded(pcm_ctx *ctx, F &&f) {
-    try {
-        pcm_status st = f();
-        if (st == PCM_OK && ctx) ctx->err.clear();
-        return st;
-    } catch (const PcmError &e) {
-        return fail(ctx, e.st, e.msg);
-    } catch (const std::bad_alloc &) {
-        return fail(ctx, PCM_E_ALLOC, "host allocation failed");
-    } catch (...) {
-        return fail(ctx, PCM_E_HIP, "unexpected failure");
-    }
-}
-
 template <typename T> void upload(pcm_ctx *ctx, DevBuf<T> &d, const T *h, size_t n) {
     d.ensure(n ? n : 1);
     if (n) HIP_OK(hipMemcpyAsync(d.p, h, n * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
@@ -144,6 +125,8 @@ pcm_status check_basis(pcm_ctx *ctx, int n_atoms, const pcm_basis *b, int *nprim
     return PCM_OK;
 }
 
+}  // namespace
+
 pcm_status check_solve_opts(pcm_ctx *ctx, const pcm_solve_opts *opts, pcm_solve_opts &o) {
     pcm_default_solve_opts(&o);
     if (opts) o = *opts;
@@ -158,6 +141,8 @@ pcm_status check_solve_opts(pcm_ctx *ctx, const pcm_solve_opts *opts, pcm_solve_
     return PCM_OK;
 }
 
+namespace {
+
 // Pair records are FP64 in the FP64 and mixed forms (the mixed kernels interpolate the Boys
 // function in FP32 but read FP64 pair data); with PCM_DYNAMIC the weak lists hold FP32 records
 // (pairs_prepare_* take PCM_MIXED to mean FP32 records).
@@ -168,10 +153,18 @@ static void lists_geometry(pcm_ctx *ctx, pcm_mol *mol) {
 
 }  // namespace
 
-struct pcm_batch {
-    std::vector<pcm_mol *> mols;
-    SolveBatch *solve = nullptr;
-};
+pcm_status density_list(pcm_ctx *ctx, pcm_mol *mol, const double *P) {
+    pairs_build(ctx, mol, mol->esp, P, 1);
+    if (ctx->prm.precision == PCM_DYNAMIC) {
+        pairs_split(ctx, mol, mol->esp, mol->esp_w, P, ctx->prm.dp_thresh);
+        pairs_prepare_density(ctx, mol, mol->esp, P, PCM_FP64);
+        pairs_prepare_density(ctx, mol, mol->esp_w, P, PCM_MIXED);
+    } else {
+        pairs_prepare_density(ctx, mol, mol->esp, P, PCM_FP64);
+    }
+    mol->esp_valid = true;
+    return PCM_OK;
+}
 
 extern "C" {
 
@@ -326,6 +319,7 @@ pcm_status pcm_build_surface(pcm_ctx *ctx, int n_atoms, const double *xyz, const
 pcm_status pcm_update_geometry(pcm_ctx *ctx, pcm_mol *mol, const double *xyz, const double *r_surf) {
     if (!ctx) return PCM_E_ARG;
     if (!mol || !xyz) return fail(ctx, PCM_E_ARG, "NULL argument");
+    if (mol->graph) return fail(ctx, PCM_E_STATE, "molecule is bound to a captured graph (destroy the graph first)");
     for (int i = 0; i < 3 * mol->N; ++i)
         if (!is_fin(xyz[i])) return fail(ctx, PCM_E_ARG, "non-finite coordinate");
     if (r_surf)
@@ -347,23 +341,12 @@ pcm_status pcm_update_geometry(pcm_ctx *ctx, pcm_mol *mol, const double *xyz, co
     });
 }
 
-static pcm_status density_list(pcm_ctx *ctx, pcm_mol *mol, const double *P) {
-    pairs_build(ctx, mol, mol->esp, P, 1);
-    if (ctx->prm.precision == PCM_DYNAMIC) {
-        pairs_split(ctx, mol, mol->esp, mol->esp_w, P, ctx->prm.dp_thresh);
-        pairs_prepare_density(ctx, mol, mol->esp, P, PCM_FP64);
-        pairs_prepare_density(ctx, mol, mol->esp_w, P, PCM_MIXED);
-    } else {
-        pairs_prepare_density(ctx, mol, mol->esp, P, PCM_FP64);
-    }
-    mol->esp_valid = true;
-    return PCM_OK;
-}
 
 pcm_status pcm_esp(pcm_ctx *ctx, pcm_mol *mol, const double *P, double *c, double *bz) {
     if (!ctx) return PCM_E_ARG;
     if (!mol || !P || !c) return fail(ctx, PCM_E_ARG, "NULL argument");
     if (any_misaligned(P, c, bz)) return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
+    if (mol->graph) return fail(ctx, PCM_E_STATE, "molecule is bound to a captured graph (destroy the graph first)");
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         density_list(ctx, mol, P);
@@ -378,6 +361,7 @@ pcm_status pcm_esp_deriv(pcm_ctx *ctx, pcm_mol *mol, const double *P, double *c,
     if (!mol || !P || !c || !dc) return fail(ctx, PCM_E_ARG, "NULL argument");
     if (any_misaligned(P, c, bz, dc))
         return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
+    if (mol->graph) return fail(ctx, PCM_E_STATE, "molecule is bound to a captured graph (destroy the graph first)");
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         density_list(ctx, mol, P);
@@ -393,6 +377,7 @@ pcm_status pcm_fock_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const doub
     if (!mol || !P || !q || !dc || !F || !g_nuc || !g_surf) return fail(ctx, PCM_E_ARG, "NULL argument");
     if (any_misaligned(P, q, dc, F, g_nuc, g_surf))
         return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
+    if (mol->graph) return fail(ctx, PCM_E_STATE, "molecule is bound to a captured graph (destroy the graph first)");
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         const int prec = ctx->prm.precision;
@@ -406,6 +391,7 @@ pcm_status pcm_fock(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F) {
     if (!ctx) return PCM_E_ARG;
     if (!mol || !q || !F) return fail(ctx, PCM_E_ARG, "NULL argument");
     if (any_misaligned(q, F)) return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
+    if (mol->graph) return fail(ctx, PCM_E_STATE, "molecule is bound to a captured graph (destroy the graph first)");
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         run_fock(ctx, mol, q, F, ctx->prm.precision);
@@ -418,6 +404,7 @@ pcm_status pcm_solve(pcm_ctx *ctx, pcm_mol *mol, const double *v, const pcm_solv
     if (!ctx) return PCM_E_ARG;
     if (!mol || !v || !q) return fail(ctx, PCM_E_ARG, "NULL argument");
     if (any_misaligned(v, q)) return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
+    if (mol->graph) return fail(ctx, PCM_E_STATE, "molecule is bound to a captured graph (destroy the graph first)");
     pcm_solve_opts o;
     pcm_status vs = check_solve_opts(ctx, opts, o);
     if (vs != PCM_OK) return vs;
@@ -433,6 +420,7 @@ pcm_status pcm_energy(pcm_ctx *ctx, pcm_mol *mol, const double *bz, const double
     if (!ctx) return PCM_E_ARG;
     if (!mol || !bz || !c || !q || !E) return fail(ctx, PCM_E_ARG, "NULL argument");
     if (any_misaligned(bz, c, q)) return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
+    if (mol->graph) return fail(ctx, PCM_E_STATE, "molecule is bound to a captured graph (destroy the graph first)");
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         *E = run_energy(ctx, mol, bz, c, q);
@@ -445,6 +433,7 @@ pcm_status pcm_matvec_share(pcm_ctx *ctx, pcm_mol *mol, const double *x, double 
     if (!mol || !x || !y) return fail(ctx, PCM_E_ARG, "NULL argument");
     if (any_misaligned(x, y)) return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
     if (nranks < 1 || rank < 0 || rank >= nranks) return fail(ctx, PCM_E_ARG, "rank outside [0, nranks)");
+    if (mol->graph) return fail(ctx, PCM_E_STATE, "molecule is bound to a captured graph (destroy the graph first)");
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         run_matvec_share(ctx, mol, x, y, rank, nranks);
@@ -459,6 +448,7 @@ pcm_status pcm_matvec_share_noalloc(pcm_ctx *ctx, pcm_mol *mol, const double *x,
     if (any_misaligned(x, y)) return fail(ctx, PCM_E_ARG, "x and y must be 8-byte aligned");
     if (nranks < 1 || rank < 0 || rank >= nranks) return fail(ctx, PCM_E_ARG, "rank outside [0, nranks)");
     if (mol->owner_ctx != ctx) return fail(ctx, PCM_E_ARG, "molecule built on another context");
+    if (mol->graph) return fail(ctx, PCM_E_STATE, "molecule is bound to a captured graph (destroy the graph first)");
     if (!ctx->dev_ready) return fail(ctx, PCM_E_STATE, "context has not been used on a device yet");
     return guarded(ctx, [&]() -> pcm_status {
         int dev = -1;
@@ -473,6 +463,7 @@ pcm_status pcm_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q
     if (!ctx) return PCM_E_ARG;
     if (!mol || !P || !q || !g_nuc || !g_surf) return fail(ctx, PCM_E_ARG, "NULL argument");
     if (any_misaligned(P, q, g_nuc, g_surf)) return fail(ctx, PCM_E_ARG, "device arrays must be 8-byte aligned");
+    if (mol->graph) return fail(ctx, PCM_E_STATE, "molecule is bound to a captured graph (destroy the graph first)");
     return guarded(ctx, [&]() -> pcm_status {
         ctx_ensure_device(ctx);
         density_list(ctx, mol, P);
@@ -680,6 +671,7 @@ pcm_status pcm_profile_entry(const pcm_ctx *ctx, int i, char *name, int name_cap
 
 void pcm_mol_destroy(pcm_mol *mol) {
     if (!mol) return;
+    if (mol->graph) graph_drop(mol->graph);
     release_mol(mol);
     delete mol;
 }
@@ -693,6 +685,7 @@ pcm_status pcm_batch_create(pcm_ctx *ctx, pcm_mol *const *mols, int n, pcm_batch
     for (int i = 0; i < n; ++i) {
         if (!v[i]) return fail(ctx, PCM_E_ARG, "NULL molecule in batch");
         if (v[i]->owner_ctx != ctx) return fail(ctx, PCM_E_ARG, "molecule built on another context");
+        if (v[i]->graph) return fail(ctx, PCM_E_STATE, "molecule is bound to a captured graph (destroy the graph first)");
         for (int j = 0; j < i; ++j)
             if (v[j] == v[i]) return fail(ctx, PCM_E_ARG, "molecule listed twice in batch");
     }
@@ -707,6 +700,7 @@ pcm_status pcm_batch_create(pcm_ctx *ctx, pcm_mol *const *mols, int n, pcm_batch
 
 void pcm_batch_destroy(pcm_batch *batch) {
     if (!batch) return;
+    if (batch->graph) graph_drop(batch->graph);
     if (batch->solve) solve_batch_free(batch->solve);
     delete batch;
 }
@@ -715,6 +709,7 @@ pcm_status pcm_esp_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *
                            double *const *bz) {
     if (!ctx) return PCM_E_ARG;
     if (!batch || !P || !c) return fail(ctx, PCM_E_ARG, "NULL argument");
+    if (batch->graph) return fail(ctx, PCM_E_STATE, "batch is bound to a captured graph (destroy the graph first)");
     const int n = (int)batch->mols.size();
     for (int i = 0; i < n; ++i) {
         if (!P[i] || !c[i]) return fail(ctx, PCM_E_ARG, "NULL matrix or vector in batch");
@@ -735,6 +730,7 @@ pcm_status pcm_esp_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *
 pcm_status pcm_fock_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const *q, double *const *F) {
     if (!ctx) return PCM_E_ARG;
     if (!batch || !q || !F) return fail(ctx, PCM_E_ARG, "NULL argument");
+    if (batch->graph) return fail(ctx, PCM_E_STATE, "batch is bound to a captured graph (destroy the graph first)");
     const int n = (int)batch->mols.size();
     for (int i = 0; i < n; ++i) {
         if (!q[i] || !F[i]) return fail(ctx, PCM_E_ARG, "NULL matrix or vector in batch");
@@ -752,6 +748,7 @@ pcm_status pcm_grad_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const 
                             double *const *g_nuc, double *const *g_surf) {
     if (!ctx) return PCM_E_ARG;
     if (!batch || !P || !q || !g_nuc || !g_surf) return fail(ctx, PCM_E_ARG, "NULL argument");
+    if (batch->graph) return fail(ctx, PCM_E_STATE, "batch is bound to a captured graph (destroy the graph first)");
     const int n = (int)batch->mols.size();
     for (int i = 0; i < n; ++i) {
         if (!P[i] || !q[i] || !g_nuc[i] || !g_surf[i]) return fail(ctx, PCM_E_ARG, "NULL matrix or vector in batch");
@@ -772,6 +769,7 @@ pcm_status pcm_solve_batched(pcm_ctx *ctx, pcm_batch *batch, const double *const
                              double *const *q, pcm_solve_info *info) {
     if (!ctx) return PCM_E_ARG;
     if (!batch || !v || !q) return fail(ctx, PCM_E_ARG, "NULL argument");
+    if (batch->graph) return fail(ctx, PCM_E_STATE, "batch is bound to a captured graph (destroy the graph first)");
     const int n = (int)batch->mols.size();
     for (int i = 0; i < n; ++i) {
         if (!v[i] || !q[i]) return fail(ctx, PCM_E_ARG, "NULL vector in batch");

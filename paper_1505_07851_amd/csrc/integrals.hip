@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <array>
 #include <cstring>
+#include <memory>
 
 // ----------------------------------------------------------------------------------------
 // Work items.  A launch covers one class for a set of molecules; each (molecule, class) has
@@ -207,6 +208,16 @@ __global__ void k_bz(const double *__restrict__ px, const double *__restrict__ p
         s += Z[J] * v;
     }
     bz[k] = s;
+}
+
+void bz_launches(pcm_ctx *ctx, pcm_mol *mol, double *bz, Launches &out) {
+    const int M = mol->M, N = mol->N;
+    const double *px = mol->px.p, *py = mol->py.p, *pz = mol->pz.p, *zeta = mol->zeta.p, *xyz = mol->xyz.p,
+                 *Z = mol->Z.p;
+    out.add("bz", (double)M * N, [=](hipStream_t st) {
+        k_bz<<<grid_for(M, 256), 256, 0, st>>>(px, py, pz, M, zeta, xyz, Z, N, bz);
+        HIP_LAUNCH_OK();
+    });
 }
 
 void run_bz(pcm_ctx *ctx, pcm_mol *mol, double *bz) {
@@ -528,12 +539,14 @@ static std::string shape_key(const char *kind, int L, const char *prec, long lon
 // device scratch for descriptor tables of one call (all classes uploaded at once)
 
 template <typename T, typename B>
-static void esp_class_launch(pcm_ctx *ctx, int L, const EspDesc *d, int nd, long long n_items) {
+static void esp_class_launch(pcm_ctx *ctx, int L, const EspDesc *d, int nd, long long n_items,
+                             hipStream_t stream = nullptr) {
     const B *tab = boys_tab<B>(ctx);
+    if (!stream) stream = ctx->stream;
     switch (L) {
 #define ESP_CASE(LL)                                                                        \
     case LL:                                                                                \
-        k_esp<LL, T, B><<<int_grid(n_items), 256, 0, ctx->stream>>>(d, nd, n_items, tab);      \
+        k_esp<LL, T, B><<<int_grid(n_items), 256, 0, stream>>>(d, nd, n_items, tab);           \
         break;
         ESP_CASE(0) ESP_CASE(1) ESP_CASE(2) ESP_CASE(3) ESP_CASE(4)
 #undef ESP_CASE
@@ -593,9 +606,18 @@ template <typename T, typename B> static int esp_chunk(pcm_ctx *ctx, pcm_mol *mo
 }
 
 // c[i] = (acc ? c[i] : 0) + the contribution of list `ls` of every molecule
+// the descriptor tables of a pass go to `desc` (the context's buffer for an immediate run, a
+// buffer of their own for a captured graph)
+static unsigned char *upload_tables(pcm_ctx *ctx, DevBuf<unsigned char> &desc, const std::vector<unsigned char> &blob) {
+    desc.ensure(std::max<size_t>(blob.size(), size_t(1) << 16));
+    if (!blob.empty())
+        HIP_OK(hipMemcpyAsync(desc.p, blob.data(), blob.size(), hipMemcpyHostToDevice, ctx->stream));
+    return desc.p;
+}
+
 template <typename T, typename B>
-static void esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<double *> &c, ListSel ls,
-                      bool acc) {
+static void esp_batch_plan(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<double *> &c,
+                           ListSel ls, bool acc, DevBuf<unsigned char> &desc, Launches &out) {
     const int n = (int)mols.size();
     std::vector<std::array<int, NCLS>> chunk(n);
     std::vector<int> rows(n, 0);
@@ -638,7 +660,7 @@ static void esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const st
     std::vector<unsigned char> blob(eb + sb);
     if (eb) std::memcpy(blob.data(), all.data(), eb);
     std::memcpy(blob.data() + eb, sums.data(), sb);
-    unsigned char *dev = (unsigned char *)upload_desc(ctx, blob.data(), blob.size());
+    unsigned char *dev = upload_tables(ctx, desc, blob);
     const EspDesc *dd = reinterpret_cast<const EspDesc *>(dev);
     for (int cl = 0; cl < NCLS; ++cl) {
         if (!cls_n[cl]) continue;
@@ -646,11 +668,42 @@ static void esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const st
         double work = 0.0;
         for (int i = 0; i < n; ++i)
             work += (double)((mols[i]->*ls).cls_off[cl + 1] - (mols[i]->*ls).cls_off[cl]) * mols[i]->M;
-        ProfScope ps(ctx, "esp_L" + std::to_string(L) + "_" + prec_tag<T, B>(), work);
-        esp_class_launch<T, B>(ctx, L, dd + cls_first[cl], cls_n[cl], cls_items[cl]);
+        const EspDesc *d0 = dd + cls_first[cl];
+        const int nd = cls_n[cl];
+        const long long items = cls_items[cl];
+        out.add("esp_L" + std::to_string(L) + "_" + prec_tag<T, B>(), work,
+                [=](hipStream_t st) { esp_class_launch<T, B>(ctx, L, d0, nd, items, st); });
     }
-    k_sum_rows<<<int_grid(sbase), 256, 0, ctx->stream>>>(reinterpret_cast<const SumDesc *>(dev + eb), n, sbase);
-    HIP_LAUNCH_OK();
+    const SumDesc *sd = reinterpret_cast<const SumDesc *>(dev + eb);
+    out.add("", 0.0, [=](hipStream_t st) {
+        k_sum_rows<<<int_grid(sbase), 256, 0, st>>>(sd, n, sbase);
+        HIP_LAUNCH_OK();
+    });
+}
+
+template <typename T, typename B>
+static void esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<double *> &c, ListSel ls,
+                      bool acc) {
+    Launches run;
+    esp_batch_plan<T, B>(ctx, mols, c, ls, acc, ctx->desc, run);
+    run.run(ctx, ctx->stream, ctx->prof);
+}
+
+// the launches of run_esp_batch, each pass with a descriptor buffer from `bufs`
+void esp_batch_launches(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<double *> &c, int prec,
+                        std::vector<std::unique_ptr<DevBuf<unsigned char>>> &bufs, Launches &out) {
+    auto buf = [&]() -> DevBuf<unsigned char> & {
+        bufs.emplace_back(new DevBuf<unsigned char>());
+        return *bufs.back();
+    };
+    if (prec == PCM_MIXED) {
+        esp_batch_plan<double, float>(ctx, mols, c, &pcm_mol::esp, false, buf(), out);
+    } else if (prec == PCM_DYNAMIC) {
+        esp_batch_plan<double, double>(ctx, mols, c, &pcm_mol::esp, false, buf(), out);
+        esp_batch_plan<float, float>(ctx, mols, c, &pcm_mol::esp_w, true, buf(), out);
+    } else {
+        esp_batch_plan<double, double>(ctx, mols, c, &pcm_mol::esp, false, buf(), out);
+    }
 }
 
 void run_esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<double *> &c, int prec) {
@@ -668,12 +721,14 @@ void run_esp(pcm_ctx *ctx, pcm_mol *mol, double *c, int prec) { run_esp_batch(ct
 
 // ---------------------------------------------------------------------------------- Fock
 template <typename T, typename B>
-static void fock_class_launch(pcm_ctx *ctx, int L, const FockDesc *d, int nd, long long n_items) {
+static void fock_class_launch(pcm_ctx *ctx, int L, const FockDesc *d, int nd, long long n_items,
+                              hipStream_t stream = nullptr) {
     const B *tab = boys_tab<B>(ctx);
+    if (!stream) stream = ctx->stream;
     switch (L) {
 #define FV_CASE(LL)                                                                                      \
     case LL:                                                                                             \
-        k_fock_v<LL, T, B><<<int_grid(n_items), 256, 0, ctx->stream>>>(d, nd, n_items, tab);                \
+        k_fock_v<LL, T, B><<<int_grid(n_items), 256, 0, stream>>>(d, nd, n_items, tab);                     \
         break;
         FV_CASE(0) FV_CASE(1) FV_CASE(2) FV_CASE(3) FV_CASE(4)
 #undef FV_CASE
@@ -740,14 +795,26 @@ static void fock_buffers(pcm_mol *mol, ListSel ls) {
     mol->fprim.ensure(fneed + 1);
 }
 
+// charges into the padded copy the point loops read (the tail past M stays zero)
+__global__ void k_copy_q(const double *__restrict__ q, double *__restrict__ qpad, int M) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < M) qpad[k] = q[k];
+}
+
 template <typename T, typename B>
-static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<const double *> &q,
-                       const std::vector<double *> &F, ListSel ls) {
+static void fock_batch_plan(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<const double *> &q,
+                            const std::vector<double *> &F, ListSel ls, DevBuf<unsigned char> &desc,
+                            Launches &out) {
     const int n = (int)mols.size();
     for (int i = 0; i < n; ++i) {
-        HIP_OK(hipMemcpyAsync(mols[i]->qpad.p, q[i], sizeof(double) * mols[i]->M, hipMemcpyDeviceToDevice,
-                              ctx->stream));
         fock_buffers(mols[i], ls);
+        const int M = mols[i]->M;
+        const double *qi = q[i];
+        double *qp = mols[i]->qpad.p;
+        out.add("", 0.0, [=](hipStream_t st) {
+            k_copy_q<<<grid_for(M, 256), 256, 0, st>>>(qi, qp, M);
+            HIP_LAUNCH_OK();
+        });
     }
     std::vector<std::array<int, NCLS>> chunk(n);
     for (int i = 0; i < n; ++i)
@@ -822,7 +889,7 @@ static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const s
     std::vector<unsigned char> blob(fb + cb);
     if (fb) std::memcpy(blob.data(), all.data(), fb);
     if (cb) std::memcpy(blob.data() + fb, cds.data(), cb);
-    unsigned char *dev = (unsigned char *)upload_desc(ctx, blob.data(), blob.size());
+    unsigned char *dev = upload_tables(ctx, desc, blob);
     const FockDesc *dd = reinterpret_cast<const FockDesc *>(dev);
     const FockCDesc *cd = reinterpret_cast<const FockCDesc *>(dev + fb);
     for (int cl = 0; cl < NCLS; ++cl) {
@@ -831,38 +898,66 @@ static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const s
         double work = 0.0;
         for (int i = 0; i < n; ++i)
             work += (double)((mols[i]->*ls).cls_off[cl + 1] - (mols[i]->*ls).cls_off[cl]) * mols[i]->M;
-        {
-            ProfScope ps(ctx, "fock_v_L" + std::to_string(L) + "_" + prec_tag<T, B>(), work);
-            fock_class_launch<T, B>(ctx, L, dd + cls_first[cl], cls_n[cl], cls_items[cl]);
-        }
+        const FockDesc *d0 = dd + cls_first[cl];
+        const int nd = cls_n[cl];
+        const long long items = cls_items[cl];
+        out.add("fock_v_L" + std::to_string(L) + "_" + prec_tag<T, B>(), work,
+                [=](hipStream_t st) { fock_class_launch<T, B>(ctx, L, d0, nd, items, st); });
         const FockCDesc *cdc = cd + c_first[cl];
         const int ncd = c_n[cl];
         const long long np = c_items[cl], nsp = s_items[cl];
         const int g = grid_for(np, 128), gs = grid_for(nsp, 128);
-        ProfScope ps2(ctx, "fock_contract", (double)np);
+        out.add("fock_contract", (double)np, [=](hipStream_t st) {
 #define FC_CASE(CI, LA_, LB_)                                                                                      \
     case CI:                                                                                                       \
-        k_fock_contract<LA_, LB_><<<g, 128, 0, ctx->stream>>>(cdc, ncd, np);                                       \
+        k_fock_contract<LA_, LB_><<<g, 128, 0, st>>>(cdc, ncd, np);                                                \
         HIP_LAUNCH_OK();                                                                                           \
-        k_fock_scatter<LA_, LB_><<<gs, 128, 0, ctx->stream>>>(cdc, ncd, nsp);                                      \
+        k_fock_scatter<LA_, LB_><<<gs, 128, 0, st>>>(cdc, ncd, nsp);                                               \
         break;
 #define FCW_CASE(CI, LA_, LB_)                                                                                     \
     case CI:                                                                                                       \
-        k_fock_contract_w<LA_, LB_><<<grid_for(np, FCW_WAVES), 64 * FCW_WAVES, 0, ctx->stream>>>(cdc, ncd, np);     \
+        k_fock_contract_w<LA_, LB_><<<grid_for(np, FCW_WAVES), 64 * FCW_WAVES, 0, st>>>(cdc, ncd, np);              \
         HIP_LAUNCH_OK();                                                                                           \
-        k_fock_scatter<LA_, LB_><<<gs, 128, 0, ctx->stream>>>(cdc, ncd, nsp);                                      \
+        k_fock_scatter<LA_, LB_><<<gs, 128, 0, st>>>(cdc, ncd, nsp);                                               \
         break;
-        switch (cl) {
-            FC_CASE(0, 0, 0)
-            FC_CASE(1, 0, 1)
-            FC_CASE(2, 0, 2)
-            FC_CASE(3, 1, 1)
-            FCW_CASE(4, 1, 2)
-            FCW_CASE(5, 2, 2)
-        }
+            switch (cl) {
+                FC_CASE(0, 0, 0)
+                FC_CASE(1, 0, 1)
+                FC_CASE(2, 0, 2)
+                FC_CASE(3, 1, 1)
+                FCW_CASE(4, 1, 2)
+                FCW_CASE(5, 2, 2)
+            }
 #undef FC_CASE
 #undef FCW_CASE
-        HIP_LAUNCH_OK();
+            HIP_LAUNCH_OK();
+        });
+    }
+}
+
+template <typename T, typename B>
+static void fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<const double *> &q,
+                       const std::vector<double *> &F, ListSel ls) {
+    Launches run;
+    fock_batch_plan<T, B>(ctx, mols, q, F, ls, ctx->desc, run);
+    run.run(ctx, ctx->stream, ctx->prof);
+}
+
+// the launches of run_fock_batch, each pass with a descriptor buffer from `bufs`
+void fock_batch_launches(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<const double *> &q,
+                         const std::vector<double *> &F, int prec,
+                         std::vector<std::unique_ptr<DevBuf<unsigned char>>> &bufs, Launches &out) {
+    auto buf = [&]() -> DevBuf<unsigned char> & {
+        bufs.emplace_back(new DevBuf<unsigned char>());
+        return *bufs.back();
+    };
+    if (prec == PCM_MIXED) {
+        fock_batch_plan<double, float>(ctx, mols, q, F, &pcm_mol::fock, buf(), out);
+    } else if (prec == PCM_DYNAMIC) {
+        fock_batch_plan<double, double>(ctx, mols, q, F, &pcm_mol::fock, buf(), out);
+        fock_batch_plan<float, float>(ctx, mols, q, F, &pcm_mol::fock_w, buf(), out);
+    } else {
+        fock_batch_plan<double, double>(ctx, mols, q, F, &pcm_mol::fock, buf(), out);
     }
 }
 

@@ -9,6 +9,8 @@
 #include <cstdint>
 #include <functional>
 #include <map>
+#include <memory>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -29,6 +31,11 @@ struct PcmError {
         if (e_ != hipSuccess)                                                                  \
             throw PcmError{PCM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)};      \
     } while (0)
+
+// failure with a message kept in the context; calls wrapped in guarded() turn exceptions into
+// status codes (nothing throws across the C ABI)
+inline pcm_status fail(pcm_ctx *ctx, pcm_status st, const std::string &msg);
+template <typename F> pcm_status guarded(pcm_ctx *ctx, F &&f);
 
 #define HIP_LAUNCH_OK()                                                                        \
     do {                                                                                       \
@@ -387,6 +394,7 @@ struct PairList {
 
 struct SolveBatch;
 struct RbjPending;
+struct pcm_graph;
 
 struct pcm_mol {
     int N = 0, nsph = 0, M = 0, Mraw = 0;
@@ -446,10 +454,40 @@ struct pcm_mol {
     unsigned long long rbj_seed = 0;
     bool rbj_valid = false;
     pcm_ctx *owner_ctx = nullptr;
+    pcm_graph *graph = nullptr;  // a captured graph that holds this molecule's buffers (calls refused)
+};
+
+struct pcm_batch {
+    std::vector<pcm_mol *> mols;
+    SolveBatch *solve = nullptr;
+    pcm_graph *graph = nullptr;
 };
 
 // which list of a molecule a kernel sequence reads
 using ListSel = PairList pcm_mol::*;
+
+inline pcm_status fail(pcm_ctx *ctx, pcm_status st, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+template <typename F> pcm_status guarded(pcm_ctx *ctx, F &&f) {
+    try {
+        pcm_status st = f();
+        if (st == PCM_OK && ctx) ctx->err.clear();
+        return st;
+    } catch (const PcmError &e) {
+        return fail(ctx, e.st, e.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, PCM_E_ALLOC, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, PCM_E_HIP, "unexpected failure");
+    }
+}
+
+// API helpers shared by the C-ABI units (api.hip, graph.hip)
+pcm_status check_solve_opts(pcm_ctx *ctx, const pcm_solve_opts *opts, pcm_solve_opts &o);
+pcm_status density_list(pcm_ctx *ctx, pcm_mol *mol, const double *P);
 
 // records one launch (or a short sequence) between construction and destruction
 struct ProfScope {
@@ -469,6 +507,32 @@ struct ProfScope {
     }
 };
 
+// A recorded sequence of kernel launches: the host work of a pass (screening, chunk choice,
+// descriptor uploads) is done when the sequence is built, so running it only launches kernels
+// (immediately on the context's stream, or under capture into a hipGraph).
+struct Launch {
+    std::string name;  // profiling name ("" = not profiled)
+    double work;
+    std::function<void(hipStream_t)> fn;
+};
+struct Launches {
+    std::vector<Launch> v;
+    void add(const std::string &name, double work, std::function<void(hipStream_t)> fn) {
+        v.push_back(Launch{name, work, std::move(fn)});
+    }
+    // prof: wrap each named launch in HIP events on the context's stream (immediate runs only)
+    void run(pcm_ctx *ctx, hipStream_t s, bool prof) const {
+        for (const Launch &l : v) {
+            if (prof && !l.name.empty()) {
+                ProfScope ps(ctx, l.name, l.work);
+                l.fn(s);
+            } else {
+                l.fn(s);
+            }
+        }
+    }
+};
+
 // ----------------------------------------------------------------------------------------
 // internal entry points implemented in the .hip translation units
 // ----------------------------------------------------------------------------------------
@@ -483,6 +547,14 @@ void pairs_prepare_density(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const doubl
 // move the others to `weak`; both keep the list order
 void pairs_split(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, PairList &weak, const double *P, double thresh);
 void run_bz(pcm_ctx *ctx, pcm_mol *mol, double *bz);
+// Recorded launches (no host work when run) of the passes a captured graph replays
+void bz_launches(pcm_ctx *ctx, pcm_mol *mol, double *bz, Launches &out);
+void density_record_launches(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P, int prec, Launches &out);
+void esp_batch_launches(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<double *> &c, int prec,
+                        std::vector<std::unique_ptr<DevBuf<unsigned char>>> &bufs, Launches &out);
+void fock_batch_launches(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<const double *> &q,
+                         const std::vector<double *> &F, int prec,
+                         std::vector<std::unique_ptr<DevBuf<unsigned char>>> &bufs, Launches &out);
 void run_esp(pcm_ctx *ctx, pcm_mol *mol, double *c, int prec);
 void run_fock(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F, int prec);
 void run_esp_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std::vector<double *> &c, int prec);
@@ -525,6 +597,17 @@ SolveBatch *solve_batch_new(const std::vector<pcm_mol *> &mols);
 void solve_batch_free(SolveBatch *b);
 pcm_status solve_batch_run(pcm_ctx *ctx, SolveBatch &B, const std::vector<const double *> &v,
                            const std::vector<double *> &q, const pcm_solve_opts &o, pcm_solve_info *info);
+// the batched FP64 solve as recorded launches for a captured graph (tables set up now), and the
+// per-molecule report after a replay
+// destroy a captured graph (if still alive): used when its batch or one of its molecules goes
+void graph_drop(pcm_graph *g);
+struct GraphSolveBufs;
+GraphSolveBufs *graph_solve_bufs_new();
+void graph_solve_bufs_free(GraphSolveBufs *b);
+void solve_graph_launches(pcm_ctx *ctx, SolveBatch &B, const std::vector<const double *> &bz,
+                          const std::vector<const double *> &c, const std::vector<double *> &q, double *E,
+                          const pcm_solve_opts &o, int budget, GraphSolveBufs &gb, Launches &out);
+void solve_graph_info(pcm_ctx *ctx, SolveBatch &B, double tol, pcm_solve_info *info, int *converged);
 int host_rbj_partition(int M, const double *r, const double *zeta, int l, unsigned long long seed, int *perm,
                        int *blk_off);
 int host_octree_partition(int M, const double *r, int leaf_max, int *perm, int *blk_off);

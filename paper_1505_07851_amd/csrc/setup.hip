@@ -596,7 +596,7 @@ __global__ void k_zero_records(unsigned char *__restrict__ rec, int n, size_t st
 }
 
 template <typename T>
-static void prep_lists(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P) {
+static void prep_lists_plan(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P, Launches &out) {
     // byte layout: classes back to back, each with its own stride
     size_t off = 0;
     for (int c = 0; c < NCLS; ++c) {
@@ -615,34 +615,54 @@ static void prep_lists(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P
         const int *es = pl.ent_sp.p + pl.cls_off[c], *ei = pl.ent_ij.p + pl.cls_off[c];
         unsigned char *rec = pl.rec.p + pl.rec_off[c];
         int g = div_up(n, TB);
+        const int *spa = mol->spa.p, *spb = mol->spb.p, *snp = mol->snp.p, *soff = mol->soff.p,
+                  *satom = mol->satom.p, *bfo = mol->bfo.p, *cnoff = mol->cnoff.p;
+        const double *pexp = mol->pexp.p, *cn = mol->cn.p, *xyz = mol->xyz.p;
+        const int nbf = mol->nbf;
+        out.add("", 0.0, [=](hipStream_t st) {
 #define PREP_CASE(CI, LA_, LB_)                                                                                     \
     case CI:                                                                                                        \
         if (P)                                                                                                      \
-            k_prep_density<LA_, LB_, T><<<g, TB, 0, ctx->stream>>>(                                                 \
-                n, es, ei, mol->spa.p, mol->spb.p, mol->snp.p, mol->soff.p, mol->satom.p, mol->bfo.p, mol->cnoff.p, \
-                mol->pexp.p, mol->cn.p, mol->xyz.p, P, mol->nbf, rec, rec_stride<T>(LA_ + LB_));                   \
+            k_prep_density<LA_, LB_, T><<<g, TB, 0, st>>>(n, es, ei, spa, spb, snp, soff, satom, bfo, cnoff, pexp,  \
+                                                          cn, xyz, P, nbf, rec, rec_stride<T>(LA_ + LB_));          \
         else                                                                                                        \
-            k_prep_geom<LA_, LB_, T><<<g, TB, 0, ctx->stream>>>(n, es, ei, mol->spa.p, mol->spb.p, mol->soff.p,     \
-                                                                mol->satom.p, mol->pexp.p, mol->xyz.p, rec,         \
-                                                                align16(sizeof(PairHdr<T>)));                       \
+            k_prep_geom<LA_, LB_, T><<<g, TB, 0, st>>>(n, es, ei, spa, spb, soff, satom, pexp, xyz, rec,            \
+                                                       align16(sizeof(PairHdr<T>)));                                \
         break;
-        switch (c) {
-            PREP_CASE(0, 0, 0)
-            PREP_CASE(1, 0, 1)
-            PREP_CASE(2, 0, 2)
-            PREP_CASE(3, 1, 1)
-            PREP_CASE(4, 1, 2)
-            PREP_CASE(5, 2, 2)
-        }
+            switch (c) {
+                PREP_CASE(0, 0, 0)
+                PREP_CASE(1, 0, 1)
+                PREP_CASE(2, 0, 2)
+                PREP_CASE(3, 1, 1)
+                PREP_CASE(4, 1, 2)
+                PREP_CASE(5, 2, 2)
+            }
 #undef PREP_CASE
-        HIP_LAUNCH_OK();
-        if (P && n % REC_PAD) {
-            size_t stride = rec_stride<T>(CLS_LA[c] + CLS_LB[c]);
-            int npad = (int)(REC_PAD - n % REC_PAD);
-            k_zero_records<T><<<1, 64, 0, ctx->stream>>>(rec + n * stride, npad, stride, ntuv(CLS_LA[c] + CLS_LB[c]));
             HIP_LAUNCH_OK();
-        }
+            if (P && n % REC_PAD) {
+                size_t stride = rec_stride<T>(CLS_LA[c] + CLS_LB[c]);
+                int npad = (int)(REC_PAD - n % REC_PAD);
+                k_zero_records<T><<<1, 64, 0, st>>>(rec + n * stride, npad, stride, ntuv(CLS_LA[c] + CLS_LB[c]));
+                HIP_LAUNCH_OK();
+            }
+        });
     }
+}
+
+template <typename T>
+static void prep_lists(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P) {
+    Launches run;
+    prep_lists_plan<T>(ctx, mol, pl, P, run);
+    run.run(ctx, ctx->stream, false);
+}
+
+// the kernels that rebuild a density list's records (header + D_tuv) from the current P; the
+// record buffer is laid out now, so the launches themselves allocate nothing
+void density_record_launches(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P, int prec, Launches &out) {
+    if (prec == PCM_MIXED)
+        prep_lists_plan<float>(ctx, mol, pl, P, out);
+    else
+        prep_lists_plan<double>(ctx, mol, pl, P, out);
 }
 
 void pairs_prepare_geometry(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, int prec) {

@@ -478,6 +478,7 @@ __global__ __launch_bounds__(TILE) void k_vec_op(const CGMol *__restrict__ tab, 
         case 1: const_cast<double *>(ext[w.mol])[k] = m.v[src][k]; break;  // store to caller
         case 2: m.v[dst][k] = a * m.v[src][k]; break;                     // scale
         case 3: m.v[dst][k] += a * m.v[src][k]; break;                    // axpy
+        case 5: m.v[dst][k] += ext[w.mol][k]; break;                      // add caller vector
         default: m.v[dst][k] = 0.0; break;                                // zero
         }
     }
@@ -1121,6 +1122,111 @@ pcm_status solve_batch_run(pcm_ctx *ctx, SolveBatch &B, const std::vector<const 
         I.solve_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
     }
     return all ? PCM_OK : PCM_E_NOCONV;
+}
+
+// ----------------------------------------------------------------------------------------
+// The batched solve as recorded launches for a captured graph: FP64 PCG from q = 0 with a fixed
+// iteration budget (each molecule stops on the device when sqrt(r.r) < tol; its later
+// iterations skip), the explicit residual, q copied out and the Eq. 13 energy.  All tables,
+// the RBJ blocks and the matvec grid are set up now; the launches only read device memory.
+// ----------------------------------------------------------------------------------------
+struct GraphSolveBufs {
+    DevBuf<const double *> bz, c, q;  // caller vectors per molecule
+    DevBuf<CGState> init;             // the states every replay starts from
+    ~GraphSolveBufs() {
+        bz.release();
+        c.release();
+        q.release();
+        init.release();
+    }
+};
+GraphSolveBufs *graph_solve_bufs_new() { return new GraphSolveBufs(); }
+void graph_solve_bufs_free(GraphSolveBufs *b) { delete b; }
+
+__global__ void k_states_reset(CGState *__restrict__ st, const CGState *__restrict__ init, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) st[i] = init[i];
+}
+
+__global__ void k_energy_out(const CGState *__restrict__ st, int n, double half_inv_f, double *__restrict__ E) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) E[i] = st[i].dots[0] + half_inv_f * (st[i].dots[1] - st[i].dots[2]);
+}
+
+void solve_graph_launches(pcm_ctx *ctx, SolveBatch &B, const std::vector<const double *> &bz,
+                          const std::vector<const double *> &c, const std::vector<double *> &q, double *E,
+                          const pcm_solve_opts &o, int budget, GraphSolveBufs &gb, Launches &out) {
+    const int n = B.n;
+    const double f = (ctx->prm.eps - 1.0) / (ctx->prm.eps + ctx->prm.k_factor);
+    const bool blocks = o.precond == PCM_PRECOND_RBJ || o.precond == PCM_PRECOND_OCTREE;
+    for (pcm_mol *mol : B.mols) {
+        solver_prepare(ctx, mol);
+        if (blocks && mol->M > 0) rbj_setup(ctx, mol, o.precond, o.block, o.seed);
+    }
+    batch_tables(ctx, B, o.precond);
+    auto ptrs = [&](DevBuf<const double *> &d, const std::vector<const double *> &h) {
+        d.ensure(n);
+        HIP_OK(hipMemcpyAsync(d.p, h.data(), n * sizeof(double *), hipMemcpyHostToDevice, ctx->stream));
+    };
+    ptrs(gb.bz, bz);
+    ptrs(gb.c, c);
+    ptrs(gb.q, std::vector<const double *>(q.begin(), q.end()));
+    set_all(B, 1, o.tol, budget);
+    upload_states(ctx, B);  // also the state the matvec grid is tuned with
+    gb.init.ensure(n);
+    HIP_OK(hipMemcpyAsync(gb.init.p, B.h_st.data(), n * sizeof(CGState), hipMemcpyHostToDevice, ctx->stream));
+    const int grid = mv_grid(ctx, B, PCM_FP64, 1, V_XQ);
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    SolveBatch *Bp = &B;
+    const CGState *init = gb.init.p;
+    const double *const *ebz = gb.bz.p, *const *ec = gb.c.p, *const *eq = gb.q.p;
+    out.add("", 0.0, [=](hipStream_t st) {
+        SolveBatch &b = *Bp;
+        k_states_reset<<<div_up(n, 64), 64, 0, st>>>(b.st.p, init, n);
+        HIP_LAUNCH_OK();
+        const int gt = grid_of(b.n_tiles);
+        k_vec_op<<<gt, TILE, 0, st>>>(b.tab.p, b.st.p, b.tiles.p, b.n_tiles, 0, 0.0, 0, V_V, ebz);  // v = Bz
+        k_vec_op<<<gt, TILE, 0, st>>>(b.tab.p, b.st.p, b.tiles.p, b.n_tiles, 5, 0.0, 0, V_V, ec);   // v += c
+        k_vec_op<<<gt, TILE, 0, st>>>(b.tab.p, b.st.p, b.tiles.p, b.n_tiles, 2, -f, V_V, V_B, ebz);  // b = -f v
+        k_cg_init<<<gt, TILE, 0, st>>>(b.tab.p, b.st.p, b.tiles.p, b.n_tiles, V_XQ, V_B, 1);
+        HIP_LAUNCH_OK();
+        if (blocks) {
+            k_rbj_items<<<grid_of(b.n_rbj), TILE, 0, st>>>(b.tab.p, b.st.p, b.rbj.p, b.n_rbj);
+            HIP_LAUNCH_OK();
+        }
+        k_cg_dir<<<gt, TILE, 0, st>>>(b.tab.p, b.st.p, b.tiles.p, b.n_tiles, 0, 1, 0);
+        HIP_LAUNCH_OK();
+    });
+    for (int g = 1; g <= budget; ++g)
+        out.add("", 0.0, [=](hipStream_t st) { pcg_iteration(ctx, *Bp, st, PCM_FP64, V_XQ, g & 1, grid, blocks, false); });
+    out.add("", 0.0, [=](hipStream_t st) {
+        SolveBatch &b = *Bp;
+        const int gt = grid_of(b.n_tiles);
+        matvec(ctx, b, st, PCM_FP64, 1, V_XQ, V_RES, V_B, 1, grid, false);  // r = b - A q, |r|^2 partials
+        k_mol_reduce<<<b.n, TILE, 0, st>>>(b.tab.p, b.st.p, 0);
+        k_vec_op<<<gt, TILE, 0, st>>>(b.tab.p, b.st.p, b.tiles.p, b.n_tiles, 1, 0.0, V_XQ, 0, eq);  // q out
+        // Eq. 13 at q: v.q + 1/(2f) q.Aq with A q = b - r
+        k_dots3<<<gt, TILE, 0, st>>>(b.tab.p, b.st.p, b.tiles.p, b.n_tiles, V_V, V_XQ, V_B, V_XQ, V_RES, V_XQ);
+        k_mol_reduce<<<b.n, TILE, 0, st>>>(b.tab.p, b.st.p, 1);
+        k_energy_out<<<div_up(b.n, 64), 64, 0, st>>>(b.st.p, b.n, 0.5 / f, E);
+        HIP_LAUNCH_OK();
+    });
+}
+
+// per molecule after a replay: iterations, explicit residual and the convergence flag
+void solve_graph_info(pcm_ctx *ctx, SolveBatch &B, double tol, pcm_solve_info *info, int *converged) {
+    download_states(ctx, B);
+    const double f = (ctx->prm.eps - 1.0) / (ctx->prm.eps + ctx->prm.k_factor);
+    for (int i = 0; i < B.n; ++i) {
+        const CGState &h = B.h_st[i];
+        const double r = std::sqrt(h.res2);
+        if (converged) converged[i] = r < tol || B.h_tab[i].M == 0;
+        if (!info) continue;
+        info[i] = pcm_solve_info{};
+        info[i].iters = h.it;
+        info[i].resid = r;
+        info[i].energy = h.dots[0] + 0.5 / f * (h.dots[1] - h.dots[2]);
+    }
 }
 
 static SolveBatch &solo(pcm_mol *mol) {
