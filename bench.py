@@ -87,12 +87,26 @@ def hermite_flops():
     return out
 
 
+# FP64 flops (FMA = 2, 1/sqrt = 1) per (primitive pair x point) evaluation of the kernels that
+# contract the auxiliary R^(n) in factored form (L <= 3), counted from the far-field branch of
+# their source: the common part 13 + 2N (P - C 3, r^2 5, far test 2, 1/sqrt 1, r^-2 1, R^(0) 1,
+# R^(n) 2 each up to N) plus the kernel's contraction and accumulation.
+#   point side, c only (N = L):               esp_L          15  24  45  87
+#   point side, dc (N = L + 1):               grad_pts_L     22  37  75 156
+#   point side, c and dc:                     esp_grad_pts_L 24  41  81 164
+#   pair side, V up to L (N = L):             fock_v_L       15  24  45  87
+#   pair side, V' up to L + 1 (N = L + 1):    grad_v_L       24  45  87
+#                                             fock_grad_v_L  24  45  87
+FACTORED = {"esp": (15, 24, 45, 87), "grad_pts": (22, 37, 75, 156), "esp_grad_pts": (24, 41, 81, 164),
+            "fock_v": (15, 24, 45, 87), "grad_v": (24, 45, 87), "fock_grad_v": (24, 45, 87)}
+
+
 def flop_model():
-    """Algorithmic FP64 flops per (primitive pair x point) evaluation, far-field branch:
-    P - C (3), r^2 (5), far test (1), 1/sqrt (1), 1/r^2 (1), R^(0) (1), R^(n) (2 per n),
-    Hermite recursion H(L), contraction (2 per coefficient), accumulation (1).  This counts the
-    table form (every R_tuv, then the contraction); the low-order kernels that contract R^(n) in
-    factored form do fewer operations, so their per-kernel rates on this model read high."""
+    """Algorithmic FP64 flops per (primitive pair x point) evaluation, far-field branch.  The
+    kernels that contract R^(n) in factored form (FACTORED) are counted from their own source;
+    the others form every R_tuv and contract it (table form): P - C (3), r^2 (5), far test (1),
+    1/sqrt (1), 1/r^2 (1), R^(0) (1), R^(n) (2 per n), Hermite recursion H(L), contraction (2 per
+    coefficient), accumulation (1)."""
     H = hermite_flops()
     m = {}
     for L in range(5):
@@ -104,6 +118,9 @@ def flop_model():
         m[f"grad_v_L{L}"] = b1 + 2 * ntuv(L + 1)
         m[f"esp_grad_pts_L{L}"] = m[f"grad_pts_L{L}"] + 2 * ntuv(L)  # the potential beside its derivative
         m[f"fock_grad_v_L{L}"] = m[f"grad_v_L{L}"]
+    for fam, counts in FACTORED.items():
+        for L, n in enumerate(counts):
+            m[f"{fam}_L{L}"] = n
     # per unordered point pair (A is symmetric and each pair is evaluated once): d (3), r^2 (5),
     # far test (1), 1/sqrt (1), row FMA (2), column product (1), column sum (1)
     m["matvec"] = 14
@@ -112,7 +129,7 @@ def flop_model():
 
 
 def kernel_flops(name, work, model):
-    key = re.sub(r"_f(64|32)$", "", name)
+    key = re.sub(r"_(f64|f32|mix)$", "", name)
     key = "matvec" if key.startswith("matvec") else key
     return model.get(key, 0) * work
 
@@ -251,6 +268,17 @@ def main():
     roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_F64_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_TFLOPS, 4), "traffic": measured_traffic(dom),
             "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": flops}
+    # the dominant integral kernel on the factored flop model (ALU bound, FP64 peak)
+    ints = {k: v for k, v in prof.items() if re.match(r"(esp|fock|grad)", k) and kernel_flops(k, 1.0, model) > 0}
+    dom_i = max(ints, key=lambda k: ints[k]["ms"])
+    di = ints[dom_i]
+    avg_i = di["ms"] / di["launches"]
+    flops_i = kernel_flops(dom_i, di["work"] / di["launches"], model)
+    ach_i = flops_i / (avg_i * 1e-3) / 1e12
+    roof_int = {"bound": "alu", "kernel": dom_i, "achieved": round(ach_i, 3), "peak": PEAK_F64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach_i / PEAK_F64_TFLOPS, 4), "avg_launch_ms": round(avg_i, 4),
+                "flops_per_launch": flops_i, "flops_per_evaluation": kernel_flops(dom_i, 1.0, model),
+                "evaluations_per_launch": di["work"] / di["launches"]}
     kernels = {k: {"ms_per_step": round(v["ms"] / n_prof, 3), "launches": v["launches"],
                    "tflops": round(kernel_flops(k, v["work"], model) / (v["ms"] * 1e-3) / 1e12, 3)
                    if v["ms"] > 0 else None,
@@ -284,7 +312,7 @@ def main():
            "pcg_solve_ms": round(info64["solve_ms"], 3), "pcg_setup_ms": round(info64["setup_ms"], 3),
            "pcg_iters": info64["iters"], "pcg_resid": info64["resid"], "energy": info64["energy"],
            "profiled_ms_per_step": round(r64["ms_prof"], 3), "profiled_steps": n_prof,
-           "roofline": roof, "integrals_per_s_by_L": by_L, "kernels": kernels,
+           "roofline": roof, "roofline_integrals": roof_int, "integrals_per_s_by_L": by_L, "kernels": kernels,
            "reference": {"solve_tol": args.tol_ref, "energy": E_ref, "resid": r64["info_tight"]["resid"]}}
 
     def errors(st, info_t, info_prod):

@@ -2,8 +2,9 @@
 
 * ``--gpus N`` with N != 1 exits with status 2 and one JSON line saying why (the collectives of a
   multi-GPU run are not implemented), before touching a GPU;
-* the flop model counts each Hermite evaluation from the generated recursion and the fixed
-  per-evaluation terms; the matvec is 14 flops per unordered pair;
+* the flop model counts the factored kernels from their far-field code and the others (L = 4)
+  from the generated Hermite recursion and the fixed per-evaluation terms; the matvec is 14 flops
+  per unordered pair;
 * the committed traffic summary parses, and its figure is reported only for the digest it states.
 """
 import json
@@ -27,15 +28,22 @@ def test_flop_model():
     import bench
     m = bench.flop_model()
     assert m["matvec"] == 14
-    # L = 0: no Hermite recursion; 12 fixed terms, one contraction term (2) and the accumulation (1)
-    assert m["esp_L0"] == 12 + 0 + 2 * 1 + 1
-    assert m["fock_v_L0"] == 12 + 2 * 1
+    # factored kernels: the common far-field part 13 + 2N, then the contraction as written
+    assert m["esp_L0"] == 13 + 0 + 2            # one FMA D_0 R^(0)
+    assert m["fock_v_L1"] == 13 + 2 + 1 + 2 + 6  # q R^(1), then V_0 and three V_i by FMA
+    assert m["esp_grad_pts_L0"] == m["grad_pts_L0"] + 2  # the potential's FMA beside the derivative
+    for fam, counts in bench.FACTORED.items():
+        assert [m[f"{fam}_L{L}"] for L in range(len(counts))] == list(counts), fam
+    # the L = 4 kernels form every R_tuv: table form with the generated Hermite recursion
+    H = bench.hermite_flops()
+    assert m["esp_L4"] == 12 + 2 * 4 + H[4] + 2 * bench.ntuv(4) + 1
     # every model grows with L
-    for k in ("esp", "fock_v", "grad_pts", "grad_v"):
+    for k in ("esp", "fock_v", "grad_pts", "grad_v", "esp_grad_pts", "fock_grad_v"):
         vals = [m[f"{k}_L{L}"] for L in range(5)]
         assert all(a < b for a, b in zip(vals, vals[1:])), k
     assert bench.kernel_flops("matvec_f32", 10.0, m) == 140.0
     assert bench.kernel_flops("esp_L2_f64", 1.0, m) == m["esp_L2"]
+    assert bench.kernel_flops("fock_grad_v_L1_mix", 1.0, m) == m["fock_grad_v_L1"]
 
 
 def test_traffic_summary_digest(tmp_path, monkeypatch):
