@@ -145,10 +145,11 @@ def main():
     ap.add_argument("--tol-ref", type=float, default=1e-10,
                     help="solve tolerance of the untimed accuracy pass that every form is compared on")
     ap.add_argument("--prof-steps", type=int, default=3, help="steps of the profiled (per-kernel) pass")
+    ap.add_argument("--nearfar-points", type=int, default=2048, help="nearfar: sampled surface points")
     ap.add_argument("--block", type=int, default=100)
     ap.add_argument("--workload", default="protein600",
                     choices=["protein600", "conformers64", "stress2000", "scf_policies", "eq21_fit", "shard8", "copy",
-                             "oracle1t"],
+                             "oracle1t", "nearfar"],
                     help="copy: a plain device copy of known size, to calibrate rocprofv3 byte counters")
     ap.add_argument("--max-iter-none", type=int, default=300,
                     help="stress2000: matvec budget of each unpreconditioned outer solve")
@@ -175,6 +176,8 @@ def main():
         return bench_shard(args)
     if args.workload == "oracle1t":
         return bench_oracle1t(args)
+    if args.workload == "nearfar":
+        return bench_nearfar(args)
 
     import numpy as np
     import torch
@@ -459,6 +462,62 @@ def oracle_baseline(s, r64, forms, sp_esp, sp_fock):
     except Exception as e:  # reported, not fatal: the baseline is context only
         res["cpu_baseline"]["one_thread"] = {"error": str(e)[:200]}
     return res
+
+
+def bench_nearfar(args):
+    """Share of (primitive pair, point) evaluations in the near field (T = p z^2/(p + z^2) r^2 below
+    40, the FP64 Boys-table range) per class, for the Eq. 18 and Eq. 15 lists of the 600-atom
+    protein, counted over a seeded sample of surface points (all pairs each).  The far field is the
+    asymptotic branch of the integral kernels."""
+    import numpy as np
+    import torch
+
+    from paper_1505_07851_amd import Context, Molecule
+    from synth import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    s = I.protein_single_solve()
+    ctx = Context()
+    mol = Molecule.from_system(ctx, s)
+    P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
+    mol.esp(P)
+    sf = mol.surface()
+    rng = np.random.default_rng(s.seeds["pert"])
+    kidx = torch.tensor(np.sort(rng.choice(mol.M, min(mol.M, args.nearfar_points), replace=False)), device="cuda")
+    r = sf["r"][kidx]
+    z2 = sf["zeta"][kidx] ** 2
+    b = s.basis
+    exps = torch.tensor(b.prim_exp, dtype=torch.float64, device="cuda")
+    soff = torch.tensor(b.shell_off, dtype=torch.int64, device="cuda")
+    satom = torch.tensor(b.shell_atom, dtype=torch.int64, device="cuda")
+    xyz = torch.tensor(s.xyz, dtype=torch.float64, device="cuda")
+    names = ["ss", "sp", "sd", "pp", "pd", "dd"]
+    out = {"workload": "nearfar_protein600", "sample_points": int(kidx.numel()), "M": mol.M, "T_far": 40.0}
+    for which, label in ((1, "eq18_list"), (0, "eq15_list")):
+        pl = mol.pair_list(which)
+        cls = torch.tensor(pl["cls"], device="cuda")
+        a = torch.tensor(pl["a"], dtype=torch.int64, device="cuda")
+        bb = torch.tensor(pl["b"], dtype=torch.int64, device="cuda")
+        ea = exps[soff[a] + torch.tensor(pl["i"], dtype=torch.int64, device="cuda")]
+        eb = exps[soff[bb] + torch.tensor(pl["j"], dtype=torch.int64, device="cuda")]
+        p = ea + eb
+        Pc = (ea[:, None] * xyz[satom[a]] + eb[:, None] * xyz[satom[bb]]) / p[:, None]
+        res = {}
+        for c in range(6):
+            sel = cls == c
+            n = int(sel.sum().item())
+            if not n:
+                continue
+            near = 0
+            for k0 in range(0, r.shape[0], 64):
+                d2 = ((Pc[sel][:, None, :] - r[None, k0:k0 + 64, :]) ** 2).sum(-1)
+                pz = p[sel][:, None] * z2[None, k0:k0 + 64]
+                T = pz / (p[sel][:, None] + z2[None, k0:k0 + 64]) * d2
+                near += int((T < 40.0).sum().item())
+            res[names[c]] = {"prim_pairs": n, "near_fraction": round(near / (n * r.shape[0]), 5)}
+        out[label] = res
+    print(json.dumps(out))
 
 
 def bench_oracle1t(args):
