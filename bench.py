@@ -636,9 +636,12 @@ def bench_stress(args):
             P[s0:s0 + C.shape[0], s0:s0 + C.shape[0]] = 0.5 * (B + B.t())
 
     vs, esp_ms, esp_pairs = [], [], []
-    # one untimed c with the unperturbed density first: chunk shapes are tuned on first use
+    # untimed c with the unperturbed and the first perturbed density first: chunk shapes are tuned
+    # on first use of a (class, size bucket), and the density-screened class sizes can cross a bucket
     P.copy_(torch.tensor(s.P, dtype=torch.float64))
     c_t, bz = mol.esp(P)
+    density_on_gpu(seq[0])
+    mol.esp(P, want_bz=False)
     torch.cuda.synchronize()
     for t_ in range(n_out):
         density_on_gpu(seq[t_])
@@ -673,6 +676,34 @@ def bench_stress(args):
     ref = runs["fp64_rbj1024"]["energies"]
     for k, r in runs.items():
         r["E_abs_err_vs_fp64_rbj_max"] = max(abs(a - b) for a, b in zip(r.pop("energies"), ref))
+    # one profiled cold solve of the last outer system per precision (untimed above): per-kernel
+    # launch means, the product's rate on the 14-flop model and the RBJ apply's bandwidth, whose
+    # algorithmic bytes are the inverse blocks (8 sum l_b^2) plus the residual read and z written
+    prof_solve = {}
+    for prec in ("fp64", "mixed"):
+        ctx.profile(True)
+        _, info = mol.solve(vs[-1], precond="rbj", block=1024, seed=s.seeds["rbj"], tol=deltas[-1], max_iter=10000,
+                            precision=prec, raise_noconv=False)
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        ent = {"iters": info["iters"], "kernels": {}}
+        for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"]):
+            if v["launches"] == 0 or v["ms"] <= 0:
+                continue
+            e = {"ms_per_launch": round(v["ms"] / v["launches"], 4), "launches": v["launches"]}
+            if k.startswith("matvec"):
+                e["tflops"] = round(14.0 * v["work"] / (v["ms"] * 1e-3) / 1e12, 3)
+                e["frac"] = round(e["tflops"] / PEAK_F64_TFLOPS, 4)
+            if k == "rbj_apply":
+                nbytes = 8.0 * v["work"] + 2 * 8.0 * mol.M * v["launches"]
+                e["bytes_per_launch"] = nbytes / v["launches"]
+                e["GB_per_s"] = round(nbytes / (v["ms"] * 1e-3) / 1e9, 1)
+                e["frac_hbm"] = round(e["GB_per_s"] / 8000.0, 4)
+            ent["kernels"][k] = e
+        prof_solve[prec] = ent
+        rb = ent["kernels"].get("rbj_apply", {})
+        log(f"[bench] profiled {prec} solve: {info['iters']} iters, rbj_apply {rb.get('ms_per_launch')} ms "
+            f"= {rb.get('GB_per_s')} GB/s")
     out = {"metric": "PCG solve ms over 15 outer iterations at the Eq. 21 thresholds (1e-3 -> 1e-7)",
            "value": runs["mixed_rbj1024"]["wall_ms"], "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 0,
            "ms_per_step": runs["mixed_rbj1024"]["wall_ms"], "higher_is_better": False, "scaling": "weak",
@@ -681,7 +712,7 @@ def bench_stress(args):
                       "outer_iterations": n_out, "deltas": deltas, "rbj_block": 1024,
                       "max_iter_unpreconditioned": args.max_iter_none},
            "esp_ms_per_outer": esp_ms, "esp_prim_pairs_per_outer": esp_pairs,
-           "esp_ms_total": round(sum(esp_ms), 1), "runs": runs}
+           "esp_ms_total": round(sum(esp_ms), 1), "runs": runs, "profiled_solve": prof_solve}
     print(json.dumps(out))
 
 
@@ -768,6 +799,11 @@ def bench_conformers(args):
     bm = Batch(ctxm, molsm)
     ms_bm, r_bm = timed(lambda: batch_step(bm, "mixed"))
     log(f"[bench] batched mixed: {ms_bm:.1f} ms per step")
+    # per-pair dynamic precision of the integrals (the equal-accuracy form) with the FP32-product solve
+    ctxd, molsd = setup("dynamic")
+    bd = Batch(ctxd, molsd)
+    ms_bd, r_bd = timed(lambda: batch_step(bd, "mixed"))
+    log(f"[bench] batched dynamic: {ms_bd:.1f} ms per step")
 
     def errs(res):
         dE = max(abs(r[1]["energy"] - s[1]["energy"]) for r, s in zip(res, r_seq))
@@ -790,6 +826,8 @@ def bench_conformers(args):
                             "speedup_vs_sequential": round(ms_seq / ms_b64, 3), "err_vs_sequential": errs(r_b64)},
            "batched_mixed": {"ms_per_step": round(ms_bm, 3), "ms_per_conformer": round(ms_bm / n_conf, 3),
                              "speedup_vs_sequential": round(ms_seq / ms_bm, 3), "err_vs_sequential": errs(r_bm)},
+           "batched_dynamic": {"ms_per_step": round(ms_bd, 3), "ms_per_conformer": round(ms_bd / n_conf, 3),
+                               "speedup_vs_sequential": round(ms_seq / ms_bd, 3), "err_vs_sequential": errs(r_bd)},
            "gradient_fp64": {"sequential_ms": round(ms_gseq, 3), "batched_ms": round(ms_gb, 3),
                              "speedup": round(ms_gseq / ms_gb, 3), "bitwise_equal": g_bitwise},
            "graph_fp64": {"ms_per_step": round(ms_g, 3), "ms_per_conformer": round(ms_g / n_conf, 3),

@@ -180,6 +180,25 @@ def test_big_solve_residual_rows(big, torch_cuda, precision, precond, block):
     assert abs(info["energy"] - E) <= 1e-6 * abs(E)
 
 
+def test_big_fixed_shapes_reproducible(big, torch_cuda):
+    """With the autotuner off every chunk shape is fixed by the sizes alone, so two separate
+    contexts sum in the same order: c, F, q and E agree bit for bit across contexts (the
+    reductions are fixed-order, with no floating-point atomics)."""
+    from paper_1505_07851_amd import Context, Molecule
+    s, _, _, _, P = big
+    out = []
+    for _ in range(2):
+        mol = Molecule.from_system(Context(autotune=False), s)
+        c, bz = mol.esp(P)
+        q, info = mol.solve(bz + c, precond="rbj", block=100, seed=s.seeds["rbj"], tol=1e-8)
+        F = mol.fock(q)
+        out.append((c.cpu().numpy(), q.cpu().numpy(), F.cpu().numpy(), info["energy"], info["iters"]))
+        mol.close()
+    (c0, q0, F0, E0, n0), (c1, q1, F1, E1, n1) = out
+    assert np.array_equal(c0, c1) and np.array_equal(q0, q1) and np.array_equal(F0, F1)
+    assert E0 == E1 and n0 == n1
+
+
 # ------------------------------------------------------------------ gradient path
 
 @pytest.fixture(scope="module")

@@ -117,3 +117,24 @@ def test_graph_refuses_mixed_solve(torch_cuda):
                                    ctypes.c_void_p(E.data_ptr()), ctypes.byref(o), ctypes.byref(h))
     assert st == C.PCM_E_UNSUPPORTED
     b.close()
+
+
+def test_graph_budget_too_small_reports_noconv(torch_cuda):
+    torch = torch_cuda
+    from paper_1505_07851_amd import Batch, Context, Molecule
+    from paper_1505_07851_amd import _lib as C
+    systems = [f() for f in SYSTEMS[1:3]]
+    ctx = Context()
+    mols = [Molecule.from_system(ctx, s) for s in systems]
+    Ps = [torch.tensor(s.P, dtype=torch.float64, device="cuda") for s in systems]
+    b = Batch(ctx, mols)
+    g = b.capture(Ps, max_iter=3, **KW)  # three iterations cannot reach 1e-9
+    g.replay()
+    torch.cuda.synchronize()
+    infos, _ = g.info()
+    for d in infos:
+        assert d["status"] == C.PCM_E_NOCONV
+        assert not d["converged"] and 1 <= d["iters"] <= 3
+        assert np.isfinite(d["resid"]) and d["resid"] > KW["tol"]
+    g.close()
+    b.close()
