@@ -184,15 +184,15 @@ pcm_status pcm_esp(pcm_ctx *ctx, pcm_mol *mol, const double *P, double *c, doubl
  * 8-byte aligned.  Errors: PCM_E_ARG (NULL or misaligned). */
 pcm_status pcm_esp_deriv(pcm_ctx *ctx, pcm_mol *mol, const double *P, double *c, double *bz, double *dc);
 
-/* F += sum_k q_k L^k (Eq. 10) and the Eq. 14 gradient (as pcm_fock followed by pcm_grad) in one
- * integral pass.  The Fock sums V_tuv = sum_k q_k R_tuv(k) (t+u+v <= L) are the low orders of the
- * V'_tuv (t+u+v <= L+1) that the basis-centre derivatives ga, gb of Eq. 22 contract, so both are
- * accumulated once per primitive pair over the union of the Eq. 15 list (used for F) and the
- * Eq. 18 list for P (used for the gradient); each entry contributes only to the terms whose list
- * holds it, so F and the gradient equal pcm_fock's and pcm_grad's to rounding.  The
+/* F += sum_k q_k L^k (Eq. 10) and the Eq. 14 gradient (as pcm_fock followed by pcm_grad) with
+ * one integral pass per primitive pair.  The Fock sums V_tuv = sum_k q_k R_tuv(k) (t+u+v <= L)
+ * are the low orders of the V'_tuv (t+u+v <= L+1) that the basis-centre derivatives ga, gb of
+ * Eq. 22 contract: the pairs of the Eq. 18 list for P accumulate V' once, for the gradient and,
+ * where the Eq. 15 list holds them, for F; the Eq. 15 pairs outside the Eq. 18 list accumulate V
+ * up to L for F alone.  F and the gradient equal pcm_fock's and pcm_grad's to rounding.  The
  * operator-centre term takes dc from pcm_esp_deriv, which must have been called with the same P
- * at the current geometry (not checked).  With PCM_DYNAMIC precision the two lists keep their
- * own precision split and F is accumulated in a pass of its own.
+ * at the current geometry (not checked).  With PCM_DYNAMIC precision both lists are split at
+ * dp_thresh by the larger of an entry's Eq. 15 bound and Eq. 18 weight.
  * DEVICE: P[nbf*nbf], q[M], dc[M*3], F[nbf*nbf] (accumulated), g_nuc[n_atoms*3] and
  * g_surf[M*3] (written; as pcm_grad), each 8-byte aligned.  Errors: PCM_E_ARG (NULL or
  * misaligned), PCM_E_UNSUPPORTED (a class needs more than 2^30 work items). */

@@ -47,6 +47,8 @@ void release_mol(pcm_mol *m) {
     release_list(m->esp_w);
     release_list(m->fg);
     release_list(m->fg_w);
+    release_list(m->fo);
+    release_list(m->fo_w);
     m->m15.release();
     m->mtmp.release();
     m->ctmp.release();

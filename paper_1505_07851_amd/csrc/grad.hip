@@ -953,8 +953,8 @@ void run_grad_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std:
 // One-pass forms.  c and dc_k = d c_k / d r_k come from the gradient's point side with the
 // potential accumulated beside the derivative (the R^(n) it needs are a subset of those the
 // derivative evaluates); the Fock sums V_tuv (t + u + v <= L) are the low orders of the V'_tuv
-// the gradient's pair side accumulates, so one pass over the merged Eq. 15 / Eq. 18 list feeds
-// both contractions.
+// the gradient's pair side accumulates, so one pass over the Eq. 18 list feeds both contractions;
+// the Eq. 15 pairs outside that list need V up to L only, in a Fock pass of their own.
 // -------------------------------------------------------------------------------------------
 // c[k] = sum_r part[r][3][k], dc[3k + d] = -sum_r part[r][d][k] (rows in a fixed order)
 __global__ __launch_bounds__(256) void k_field_sum(const double *__restrict__ part, int rows, int M,
@@ -993,8 +993,8 @@ void run_esp_deriv(pcm_ctx *ctx, pcm_mol *mol, double *c, double *dc, int prec) 
     HIP_LAUNCH_OK();
 }
 
-// pair side over the merged list, the Fock contraction (Eq. 15 entries) and the gradient
-// contraction (Eq. 18 entries) of each class, sums per candidate shell pair into gsp
+// pair side over the Eq. 18 list, the Fock contraction (its Eq. 15 entries) and the gradient
+// contraction of each class, sums per candidate shell pair into gsp
 template <typename T, typename B>
 static void fock_grad_pairs(pcm_ctx *ctx, pcm_mol *mol, const double *P, double *F, const PairList &pl, ListSel ls,
                             bool add) {
@@ -1090,6 +1090,8 @@ void run_fock_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q,
     mol->vbuf.ensure(vneed + 1);
     mol->gpair.ensure(gneed + 1);
     mol->fprim.ensure(fneed + 1);
+    fock_buffers(mol, &pcm_mol::fo);
+    fock_buffers(mol, &pcm_mol::fo_w);
     {
         ProfScope psa(ctx, "grad_aoff", (double)M * M);
         k_grad_aoff<<<dim3(div_up(M, 256), rows_a), 256, 0, ctx->stream>>>(mol->px.p, mol->py.p, mol->pz.p,
@@ -1102,6 +1104,8 @@ void run_fock_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q,
         fock_grad_pairs<double, double>(ctx, mol, P, F, mol->fg, &pcm_mol::fg, false);
         if (dyn) fock_grad_pairs<float, float>(ctx, mol, P, F, mol->fg_w, &pcm_mol::fg_w, true);
     }
+    // the Eq. 15 pairs outside the Eq. 18 list contribute to F only
+    run_fock_lists(ctx, mol, q, F, prec, &pcm_mol::fo, &pcm_mol::fo_w);
     GradJob j{mol, P, q, g_nuc, g_surf, rows_a, 0, 0, mol->part.p, nullptr};
     j.dc = dc;
     std::vector<GradJob> all{j};

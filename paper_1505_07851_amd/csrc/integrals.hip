@@ -780,7 +780,7 @@ template <typename T, typename B> static int fock_chunk(pcm_ctx *ctx, pcm_mol *m
 }
 
 // V buffer and primitive-block buffer large enough for every class and every tuning candidate
-static void fock_buffers(pcm_mol *mol, ListSel ls) {
+void fock_buffers(pcm_mol *mol, ListSel ls) {
     PairList &pl = mol->*ls;
     size_t vneed = 0, fneed = 0;
     for (int cl = 0; cl < NCLS; ++cl) {
@@ -975,6 +975,15 @@ void run_fock_batch(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, const std:
 
 void run_fock(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F, int prec) {
     run_fock_batch(ctx, {mol}, {q}, {F}, prec);
+}
+
+void run_fock_lists(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F, int prec, ListSel strong, ListSel weak) {
+    if (prec == PCM_MIXED) {
+        fock_batch<double, float>(ctx, {mol}, {q}, {F}, strong);
+    } else {
+        fock_batch<double, double>(ctx, {mol}, {q}, {F}, strong);
+        if (prec == PCM_DYNAMIC) fock_batch<float, float>(ctx, {mol}, {q}, {F}, weak);
+    }
 }
 
 // Contraction to F blocks and scatter into F (one molecule, class cl of list pl) of V sums that

@@ -427,9 +427,11 @@ struct pcm_mol {
     // screened lists; with PCM_DYNAMIC precision fock / esp hold the pairs whose bound reaches
     // dp_thresh (FP64 records) and fock_w / esp_w the others (FP32 records), both in list order
     PairList fock, esp, fock_w, esp_w;
-    // merged list of the one-pass Fock + gradient pair side: survivors of Eq. 15 or of Eq. 18 (its
-    // bits per candidate shell pair in m18); header-only records
+    // lists of the one-pass Fock + gradient pair side (header-only records): fg holds the Eq. 18
+    // survivors for the current P (V' up to L + 1 feeds the gradient and, for its Eq. 15 members,
+    // the Fock matrix), fo the Eq. 15 survivors outside Eq. 18 (V up to L, Fock only)
     PairList fg, fg_w;                  // fg_w: the FP32 part of a PCM_DYNAMIC split (else empty)
+    PairList fo, fo_w;                  // fo_w: likewise
     DevBuf<unsigned long long> m18, m15;  // Eq. 18 and Eq. 15 survivor bits per candidate shell pair
     DevBuf<int> c18;
     DevBuf<unsigned long long> mtmp;    // screening scratch of the precision splits [3 x candidates]
@@ -574,14 +576,21 @@ void run_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, doub
 // c (Eqs. 5-6) and dc_k = d c_k / d r_k (M x 3) in one pass over the Eq. 18 list(s): the point
 // side of the Eq. 22 gradient with the potential accumulated beside it
 void run_esp_deriv(pcm_ctx *ctx, pcm_mol *mol, double *c, double *dc, int prec);
-// F += L^T q (Eq. 10) and the Eq. 14 gradient with the c term's point side from dc; FP64 and mixed
-// precision take one pair-side pass over the merged list fg (built by pairs_merged_build)
+// F += L^T q (Eq. 10) and the Eq. 14 gradient with the c term's point side from dc: one pair-side
+// pass over the Eq. 18 list fg for both, and the Fock pass over the rest of the Eq. 15 list fo
+// (both built by pairs_merged_build)
 void run_fock_grad(pcm_ctx *ctx, pcm_mol *mol, const double *P, const double *q, const double *dc, double *F,
                    double *g_nuc, double *g_surf, int prec);
-// screen with P (Eq. 18 bits into m18, Eq. 15 bits into m15) and build fg = Eq. 15 list | Eq. 18
-// list with FP64 header records; `dynamic` splits it at dp_thresh (Eq. 15 bound or Eq. 18 weight)
-// into fg (FP64 records) and fg_w (FP32 records)
+// screen with P (Eq. 18 bits into m18, Eq. 15 bits into m15) and build fg = the Eq. 18 list and
+// fo = the Eq. 15 list without the Eq. 18 survivors, with FP64 header records; `dynamic` splits
+// each at dp_thresh (Eq. 15 bound or Eq. 18 weight) into an FP64 part (fg, fo) and an FP32 part
+// (fg_w, fo_w)
 void pairs_merged_build(pcm_ctx *ctx, pcm_mol *mol, const double *P, bool dynamic);
+// F += sum_k q_k L^k over the lists `strong` (FP64 records; FP32 Boys table when prec is mixed)
+// and, for PCM_DYNAMIC, `weak` (FP32 records)
+void run_fock_lists(pcm_ctx *ctx, pcm_mol *mol, const double *q, double *F, int prec, ListSel strong, ListSel weak);
+// grow the V and primitive-block buffers for every class and tuning candidate of the Fock pass over ls
+void fock_buffers(pcm_mol *mol, ListSel ls);
 // contraction to F blocks and scatter of V sums held in vin (stride vnt), class cl of list pl
 void fock_contract_scatter(pcm_ctx *ctx, pcm_mol *mol, const PairList &pl, int cl, const double *vin, int nch,
                            int vnt, const unsigned long long *memb, double *F);

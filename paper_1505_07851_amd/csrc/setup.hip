@@ -680,9 +680,10 @@ void pairs_prepare_density(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const doubl
 }
 
 // ----------------------------------------------------------------------------------------
-// Merged list of the one-pass Fock + gradient pair side: the Eq. 18 survivors for P (bits kept in
-// m18) together with the Eq. 15 survivors already in fock.mask; header-only records in the
-// precision of the pass.  Entries keep the list order (class, shell pair, i, j).
+// Lists of the one-pass Fock + gradient pair side: the Eq. 18 survivors for P (bits kept in m18),
+// whose V' up to L + 1 serves the gradient and the Fock matrix, and the Eq. 15 survivors (bits in
+// m15, from fock.mask) outside them, which need V up to L for the Fock matrix only; header-only
+// records in the precision of the pass.  Entries keep the list order (class, shell pair, i, j).
 // ----------------------------------------------------------------------------------------
 __global__ void k_mask_or(int nsp, const unsigned long long *__restrict__ a, const unsigned long long *__restrict__ b,
                           unsigned long long *__restrict__ mask, int *__restrict__ cnt) {
@@ -693,13 +694,23 @@ __global__ void k_mask_or(int nsp, const unsigned long long *__restrict__ a, con
     cnt[sp] = __popcll(m);
 }
 
+// bits of a that are not in b
+__global__ void k_mask_andnot(int nsp, const unsigned long long *__restrict__ a, const unsigned long long *__restrict__ b,
+                              unsigned long long *__restrict__ mask, int *__restrict__ cnt) {
+    int sp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sp >= nsp) return;
+    const unsigned long long m = a[sp] & ~b[sp];
+    mask[sp] = m;
+    cnt[sp] = __popcll(m);
+}
+
 void pairs_merged_build(pcm_ctx *ctx, pcm_mol *mol, const double *P, bool dynamic) {
     const long long nsp = mol->sp_cls_off[NCLS];
-    PairList &fg = mol->fg, &fw = mol->fg_w;
+    PairList &fg = mol->fg, &fgw = mol->fg_w, &fo = mol->fo, &fow = mol->fo_w;
     mol->m18.ensure(nsp + 1);
     mol->c18.ensure(nsp + 1);
     mol->m15.ensure(nsp + 1);
-    for (PairList *l : {&fg, &fw}) {
+    for (PairList *l : {&fg, &fgw, &fo, &fow}) {
         l->mask.ensure(nsp + 1);
         l->cnt.ensure(nsp + 1);
         l->spo.ensure(nsp + 1);
@@ -709,12 +720,15 @@ void pairs_merged_build(pcm_ctx *ctx, pcm_mol *mol, const double *P, bool dynami
         screen_launch(ctx, mol, P, ctx->prm.schwarz_thresh, mol->m18.p, mol->c18.p);
         // the Eq. 15 bits: the Fock list, or both of its parts when the precision is split
         k_mask_or<<<g, 256, 0, ctx->stream>>>((int)nsp, mol->fock.mask.p, dynamic ? mol->fock_w.mask.p : mol->fock.mask.p,
-                                              mol->m15.p, fw.cnt.p);
+                                              mol->m15.p, fgw.cnt.p);
         HIP_LAUNCH_OK();
-        k_mask_or<<<g, 256, 0, ctx->stream>>>((int)nsp, mol->m15.p, mol->m18.p, fg.mask.p, fg.cnt.p);
+        // fg: the Eq. 18 survivors; fo: the Eq. 15 survivors outside them
+        k_mask_or<<<g, 256, 0, ctx->stream>>>((int)nsp, mol->m18.p, mol->m18.p, fg.mask.p, fg.cnt.p);
+        HIP_LAUNCH_OK();
+        k_mask_andnot<<<g, 256, 0, ctx->stream>>>((int)nsp, mol->m15.p, mol->m18.p, fo.mask.p, fo.cnt.p);
         HIP_LAUNCH_OK();
         if (dynamic) {
-            // FP64 part: entries whose Eq. 15 bound or Eq. 18 weight reaches dp_thresh
+            // FP64 parts: entries whose Eq. 15 bound or Eq. 18 weight reaches dp_thresh
             const double th = std::max(ctx->prm.dp_thresh, ctx->prm.schwarz_thresh);
             mol->mtmp.ensure(3 * (size_t)nsp);
             mol->ctmp.ensure(nsp);
@@ -723,19 +737,25 @@ void pairs_merged_build(pcm_ctx *ctx, pcm_mol *mol, const double *P, bool dynami
             screen_launch(ctx, mol, P, th, s2, mol->ctmp.p);
             k_mask_or<<<g, 256, 0, ctx->stream>>>((int)nsp, s1, s2, s3, mol->ctmp.p);
             HIP_LAUNCH_OK();
-            k_mask_split<<<g, 256, 0, ctx->stream>>>((int)nsp, s3, fg.mask.p, fg.cnt.p, fw.mask.p, fw.cnt.p);
+            k_mask_split<<<g, 256, 0, ctx->stream>>>((int)nsp, s3, fg.mask.p, fg.cnt.p, fgw.mask.p, fgw.cnt.p);
+            HIP_LAUNCH_OK();
+            k_mask_split<<<g, 256, 0, ctx->stream>>>((int)nsp, s3, fo.mask.p, fo.cnt.p, fow.mask.p, fow.cnt.p);
             HIP_LAUNCH_OK();
             HIP_OK(hipStreamSynchronize(ctx->stream));
         }
     }
-    pairs_compact(ctx, mol, fg);
-    for (int c = 0; c < NCLS; ++c) fg.sp_union[c] = fg.sp_count[c];
-    pairs_prepare_geometry(ctx, mol, fg, PCM_FP64);
-    if (dynamic) {
-        pairs_compact(ctx, mol, fw);
-        pairs_prepare_geometry(ctx, mol, fw, PCM_MIXED);  // FP32 records
-    } else {
-        fw.n = 0;
-        for (int c = 0; c <= NCLS; ++c) fw.cls_off[c] = 0;
+    for (PairList *l : {&fg, &fo}) {
+        pairs_compact(ctx, mol, *l);
+        for (int c = 0; c < NCLS; ++c) l->sp_union[c] = l->sp_count[c];
+        pairs_prepare_geometry(ctx, mol, *l, PCM_FP64);
+    }
+    for (PairList *l : {&fgw, &fow}) {
+        if (dynamic) {
+            pairs_compact(ctx, mol, *l);
+            pairs_prepare_geometry(ctx, mol, *l, PCM_MIXED);  // FP32 records
+        } else {
+            l->n = 0;
+            for (int c = 0; c <= NCLS; ++c) l->cls_off[c] = 0;
+        }
     }
 }

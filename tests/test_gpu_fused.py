@@ -2,9 +2,10 @@
 
 pcm_esp_deriv: c (Eqs. 5-6) and dc_k = d c_k / d r_k from one pass; the oracle's c-term surface
 gradient at q = 1 is dc itself (gc_k = q_k dc_k, Eq. 22).  pcm_fock_grad: F (Eq. 10) and the
-Eq. 14 gradient from one pair-side pass over the union of the Eq. 15 and Eq. 18 lists.  The
-density is also scaled up and down, so that the Eq. 18 list holds pairs the Eq. 15 list does not
-(|P| > 1) and the other way round (|P| < 1): each list's entries must reach only their own term.
+Eq. 14 gradient from one pair-side pass over the Eq. 18 list (the Fock sums are the low orders of
+the gradient's) and a Fock pass over the Eq. 15 pairs outside it.  The density is also scaled up
+and down, so that the Eq. 18 list holds pairs the Eq. 15 list does not (|P| > 1) and the other
+way round (|P| < 1): each list's entries must reach only their own term.
 
 Tolerances (FP64): c 1e-10 relative in norm; dc, gradient 1e-8 hartree/bohr x max(1, |g|max);
 F 1e-10 relative; against the separate calls (same arithmetic, other work split) 1e-12.
@@ -133,9 +134,9 @@ def test_fused_other_precisions(case, torch_cuda, prec):
     assert rel(F.cpu().numpy(), om.fock(ref["q"])) <= tol_c
     assert np.abs(gn.cpu().numpy() - g["g_nuc"]).max() <= tol_g * sc
     assert np.abs(gs.cpu().numpy() - g["g_surf"]).max() <= tol_g * sc
-    # against the separate calls in the same precision (the dynamic form splits the merged list by
-    # the larger of its two weights, so a few pairs change precision: FP32-level differences on
-    # weak pairs only)
+    # against the separate calls in the same precision (the dynamic form splits the one-pass lists
+    # by the larger of an entry's two weights, so a few pairs change precision: FP32-level
+    # differences on weak pairs only)
     assert rel(F.cpu().numpy(), F_sep.cpu().numpy()) <= (1e-10 if prec == "dynamic" else 1e-9)
     assert np.abs(gn.cpu().numpy() - gn_sep.cpu().numpy()).max() <= (1e-10 if prec == "dynamic" else 1e-8) * sc
 
