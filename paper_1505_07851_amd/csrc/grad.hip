@@ -37,12 +37,29 @@ struct GradVDesc {
     int stride, n_pairs, Mpad, chunk, nptile;
 };
 
+// Empty statements that need a wave-uniform value in scalar registers at this point: a scalar load
+// of it must have completed here (the compiler places its wait just before)
+template <typename T> __device__ __forceinline__ void pin_sgpr(const T &v) { asm volatile("" ::"s"(v)); }
+template <typename T> __device__ __forceinline__ void pin_sgpr(const PairHdr<T> &h) {
+    pin_sgpr(h.Px);
+    pin_sgpr(h.Py);
+    pin_sgpr(h.Pz);
+    pin_sgpr(h.p);
+    pin_sgpr(h.limp);
+    pin_sgpr(h.pf);
+    pin_sgpr(h.pref);
+}
+
 // WC: also accumulate the potential c_k = sum_t D_t R_t (Eqs. 5-6), which the R^(n) of the
 // derivative contain (orders 0 .. L of the L+1 evaluated); rows are then 4 wide (gx, gy, gz, c)
 template <int L, typename T, typename B, bool WC>
 __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict__ ds, int nd, long long n_items,
                                                   const B *__restrict__ boys_g) {
-    constexpr int NT = ntuv(L), PB = pair_batch<L + 1>();
+    // PF: the records of the next batch are requested before the current batch is evaluated and
+    // waited for after it, so the scalar-load latency overlaps the evaluation; both batches must fit
+    // in the scalar registers, which holds for L <= 2 with one batch of 2 (L = 0) or 1 pairs
+    constexpr bool PF = L <= 2;
+    constexpr int NT = ntuv(L), PB = PF ? (L == 0 ? 2 : 1) : pair_batch<L + 1>();
     __shared__ B tab[boys_lds_size<B, L + 1>()];
     load_boys<B, L + 1>(tab, boys_g);
     {  // one item per block (the grid covers every item; a loop over items costs registers here)
@@ -59,17 +76,26 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
         const int p0 = ch * d.chunk;
         const int p1 = min(d.n_pad, p0 + d.chunk);
         double gx = 0.0, gy = 0.0, gz = 0.0, cc = 0.0;
-        for (int ip = p0; ip < p1; ip += PB) {
-            PairHdr<T> h[PB];
-            T D[PB][NT];
+        auto load = [&](int i0, PairHdr<T>(&hh)[PB], T(&DD)[PB][NT]) {
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
-                const cptr<unsigned char> r = rec + (size_t)(ip + b) * stride;
-                h[b] = *(cptr<PairHdr<T>>)(r);
+                const cptr<unsigned char> r = rec + (size_t)(i0 + b) * stride;
+                hh[b] = *(cptr<PairHdr<T>>)(r);
                 const cptr<T> dd = (cptr<T>)(r + sizeof(PairHdr<T>));
 #pragma unroll
-                for (int t = 0; t < NT; ++t) D[b][t] = dd[t];
+                for (int t = 0; t < NT; ++t) DD[b][t] = dd[t];
             }
+        };
+        PairHdr<T> h[PB];
+        T D[PB][NT];
+        if constexpr (PF) load(p0, h, D);
+        for (int ip = p0; ip < p1; ip += PB) {
+            PairHdr<T> hn[PB];
+            T Dn[PB][NT];
+            if constexpr (PF)
+                load(ip + PB < p1 ? ip + PB : ip, hn, Dn);  // the last batch re-reads itself
+            else
+                load(ip, h, D);
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
                 if constexpr (L == 3) {
@@ -222,6 +248,20 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
                     gy += (double)sy;
                     gz += (double)sz;
                     if constexpr (WC) cc += (double)sc;
+                }
+            }
+            if constexpr (PF) {
+                // the next batch's records are needed only here, after this batch's evaluation
+                // (the empty statements order the wait after the accumulations)
+                asm volatile("" ::"v"(gx), "v"(gy), "v"(gz), "v"(cc));
+#pragma unroll
+                for (int b = 0; b < PB; ++b) {
+                    pin_sgpr(hn[b]);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) pin_sgpr(Dn[b][t]);
+                    h[b] = hn[b];
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) D[b][t] = Dn[b][t];
                 }
             }
         }
