@@ -37,29 +37,15 @@ struct GradVDesc {
     int stride, n_pairs, Mpad, chunk, nptile;
 };
 
-// Empty statements that need a wave-uniform value in scalar registers at this point: a scalar load
-// of it must have completed here (the compiler places its wait just before)
-template <typename T> __device__ __forceinline__ void pin_sgpr(const T &v) { asm volatile("" ::"s"(v)); }
-template <typename T> __device__ __forceinline__ void pin_sgpr(const PairHdr<T> &h) {
-    pin_sgpr(h.Px);
-    pin_sgpr(h.Py);
-    pin_sgpr(h.Pz);
-    pin_sgpr(h.p);
-    pin_sgpr(h.limp);
-    pin_sgpr(h.pf);
-    pin_sgpr(h.pref);
-}
-
 // WC: also accumulate the potential c_k = sum_t D_t R_t (Eqs. 5-6), which the R^(n) of the
 // derivative contain (orders 0 .. L of the L+1 evaluated); rows are then 4 wide (gx, gy, gz, c)
 template <int L, typename T, typename B, bool WC>
 __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict__ ds, int nd, long long n_items,
                                                   const B *__restrict__ boys_g) {
     // PF: the records of the next batch are requested before the current batch is evaluated and
-    // waited for after it, so the scalar-load latency overlaps the evaluation; both batches must fit
-    // in the scalar registers, which holds for L <= 2 with one batch of 2 (L = 0) or 1 pairs
+    // waited for after it, so the scalar-load latency overlaps the evaluation
     constexpr bool PF = L <= 2;
-    constexpr int NT = ntuv(L), PB = PF ? (L == 0 ? 2 : 1) : pair_batch<L + 1>();
+    constexpr int NT = ntuv(L), PB = PF ? pair_batch_pf<L>() : pair_batch<L + 1>();
     __shared__ B tab[boys_lds_size<B, L + 1>()];
     load_boys<B, L + 1>(tab, boys_g);
     {  // one item per block (the grid covers every item; a loop over items costs registers here)

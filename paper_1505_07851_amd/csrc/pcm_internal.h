@@ -202,6 +202,22 @@ template <typename T, typename B> constexpr const char *prec_tag() {
 
 // pairs per batch of wave-uniform record loads in the point-per-lane kernels
 template <int L> __host__ __device__ constexpr int pair_batch() { return L == 0 ? 4 : (L <= 2 ? 2 : 1); }
+// Pair batch of the point-side kernels that request the next batch's records during the current
+// evaluation (classes with L <= 2): both batches of records fit in the scalar registers
+template <int L> __host__ __device__ constexpr int pair_batch_pf() { return L == 0 ? 2 : 1; }
+
+// Empty statements that need a wave-uniform value in scalar registers at this point: a scalar load
+// of it must have completed here (the compiler places its wait just before)
+template <typename T> __device__ __forceinline__ void pin_sgpr(const T &v) { asm volatile("" ::"s"(v)); }
+template <typename T> __device__ __forceinline__ void pin_sgpr(const PairHdr<T> &h) {
+    pin_sgpr(h.Px);
+    pin_sgpr(h.Py);
+    pin_sgpr(h.Pz);
+    pin_sgpr(h.p);
+    pin_sgpr(h.limp);
+    pin_sgpr(h.pf);
+    pin_sgpr(h.pref);
+}
 constexpr int REC_PAD = 4;  // pair record lists are padded to a multiple of this with zero records
 constexpr int PT_BATCH = 4; // points per batch in the pair-per-lane kernels
 
