@@ -341,7 +341,7 @@ __global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds
 
 // per primitive pair: ga (3) and gb (3) from V' (sum of chunks)
 template <int LA, int LB>
-__global__ void k_grad_contract(long long n, int nch, const double *__restrict__ vin, const int *__restrict__ ent_sp,
+__global__ __launch_bounds__(64) void k_grad_contract(long long n, int nch, const double *__restrict__ vin, const int *__restrict__ ent_sp,
                                 const int *__restrict__ ent_ij, const int *__restrict__ spa,
                                 const int *__restrict__ spb, const int *__restrict__ snp, const int *__restrict__ soff,
                                 const int *__restrict__ satom, const int *__restrict__ bfo,
@@ -357,6 +357,7 @@ __global__ void k_grad_contract(long long n, int nch, const double *__restrict__
         return;
     }
     double V[NT];
+#pragma unroll
     for (int t = 0; t < NT; ++t) {
         double s = 0.0;
         for (int c = 0; c < nch; ++c) s += vin[((size_t)c * NT + t) * n + q];
@@ -374,25 +375,32 @@ __global__ void k_grad_contract(long long n, int nch, const double *__restrict__
     ez.build(Pc[2] - A[2], Pc[2] - B[2], inv2p);
     double w = (a == b) ? -1.0 : -2.0;
     double g[6] = {0, 0, 0, 0, 0, 0};
-    // sum over tuv of E^{a' b'}_{tuv} V_tuv for shifted Cartesian exponents
+    // sum over tuv of E^{a' b'}_{tuv} V_tuv for shifted Cartesian exponents; every loop here is
+    // unrolled so that the exponents are constants and the tables stay in registers
     auto hv = [&](int ax, int ay, int az, int bx, int by, int bz) -> double {
         double s = 0.0;
+#pragma unroll
         for (int t = 0; t <= ax + bx; ++t)
+#pragma unroll
             for (int u = 0; u <= ay + by; ++u) {
                 double etu = ex.e[ax][bx][t] * ey.e[ay][by][u];
+#pragma unroll
                 for (int v = 0; v <= az + bz; ++v) s += etu * ez.e[az][bz][v] * V[tuv_idx(t, u, v)];
             }
         return s;
     };
+#pragma unroll
     for (int mu = 0; mu < ncart(LA); ++mu) {
         int a3[3];
         cart_comp(LA, mu, a3[0], a3[1], a3[2]);
         double cmu = cn[cnoff[a] + mu * snp[a] + i];
+#pragma unroll
         for (int nu = 0; nu < ncart(LB); ++nu) {
             int b3[3];
             cart_comp(LB, nu, b3[0], b3[1], b3[2]);
             double cf = w * P[(long long)(bfo[a] + mu) * nbf + bfo[b] + nu] * cmu * cn[cnoff[b] + nu * snp[b] + j];
             if (cf == 0.0) continue;
+#pragma unroll
             for (int d = 0; d < 3; ++d) {
                 int ap[3] = {a3[0], a3[1], a3[2]};
                 ap[d] += 1;
