@@ -128,6 +128,24 @@ def flop_model():
     return m
 
 
+def family_rooflines(prof, model, n_prof):
+    """Model TFLOP/s and fraction of the FP64 peak per kernel family of the FP64 step, over all its
+    classes: the point side (c with dc), the pair side over the Eq. 18 list (F and the gradient),
+    the Fock-only pass over the rest of the Eq. 15 list, and the product."""
+    fams = {"point_side": r"esp_grad_pts_L\d_f64", "pair_side": r"fock_grad_v_L\d_f64", "fock_only": r"fock_v_L\d_f64",
+            "matvec": r"matvec_f64"}
+    out = {}
+    for fam, pat in fams.items():
+        ks = [k for k in prof if re.fullmatch(pat, k)]
+        ms = sum(prof[k]["ms"] for k in ks)
+        if not ks or ms <= 0:
+            continue
+        tf = sum(kernel_flops(k, prof[k]["work"], model) for k in ks) / (ms * 1e-3) / 1e12
+        out[fam] = {"ms_per_step": round(ms / n_prof, 3), "model_tflops": round(tf, 3),
+                    "frac": round(tf / PEAK_F64_TFLOPS, 4)}
+    return out
+
+
 def kernel_flops(name, work, model):
     key = re.sub(r"_(f64|f32|mix)$", "", name)
     key = "matvec" if key.startswith("matvec") else key
@@ -299,7 +317,8 @@ def main():
         spe = sum(n for n, l in zip(sz["sp_esp"], cls_L) if l == L)
         spf = sum(n for n, l in zip(sz["sp_fock"], cls_L) if l == L)
         t_p = prof.get(f"esp_grad_pts_L{L}_f64", {}).get("ms", 0.0)
-        t_v = prof.get(f"fock_grad_v_L{L}_f64", {}).get("ms", 0.0)
+        # the pair side: F and the gradient over the Eq. 18 list, F alone over the rest of Eq. 15
+        t_v = prof.get(f"fock_grad_v_L{L}_f64", {}).get("ms", 0.0) + prof.get(f"fock_v_L{L}_f64", {}).get("ms", 0.0)
         rate = lambda n, t: round(n * M * n_prof / (t * 1e-3), 1) if t > 0 else None
         by_L[f"L{L}"] = {"shell_pairs_esp": spe, "shell_pairs_fock": spf, "point_side": rate(spe, t_p),
                          "pair_side": rate(spf, t_v), "c_F_grad": rate(2 * spe + spf, t_p + t_v)}
@@ -315,7 +334,9 @@ def main():
            "pcg_solve_ms": round(info64["solve_ms"], 3), "pcg_setup_ms": round(info64["setup_ms"], 3),
            "pcg_iters": info64["iters"], "pcg_resid": info64["resid"], "energy": info64["energy"],
            "profiled_ms_per_step": round(r64["ms_prof"], 3), "profiled_steps": n_prof,
-           "roofline": roof, "roofline_integrals": roof_int, "integrals_per_s_by_L": by_L, "kernels": kernels,
+           "roofline": roof, "roofline_integrals": roof_int,
+           "roofline_by_family": family_rooflines(prof, model, n_prof), "integrals_per_s_by_L": by_L,
+           "kernels": kernels,
            "reference": {"solve_tol": args.tol_ref, "energy": E_ref, "resid": r64["info_tight"]["resid"]}}
 
     def errors(st, info_t, info_prod):

@@ -5,7 +5,8 @@
 * the flop model counts the factored kernels from their far-field code and the others (L = 4)
   from the generated Hermite recursion and the fixed per-evaluation terms; the matvec is 14 flops
   per unordered pair;
-* the committed traffic summary parses, and its figure is reported only for the digest it states.
+* the committed traffic summary parses, and its figure is reported only for the digest it states;
+* the per-family roofline sums the model flops of a family's FP64 classes over their time.
 """
 import json
 import os
@@ -59,3 +60,20 @@ def test_traffic_summary_digest(tmp_path, monkeypatch):
         assert got is None
     monkeypatch.setattr(bench, "source_digest", lambda: "0" * 16)
     assert bench.measured_traffic("matvec_f64") is None
+
+
+def test_family_rooflines():
+    import bench
+    m = bench.flop_model()
+    prof = {"esp_grad_pts_L0_f64": {"ms": 10.0, "work": 1e9, "launches": 1},
+            "esp_grad_pts_L1_f64": {"ms": 10.0, "work": 1e9, "launches": 1},
+            "fock_v_L0_f64": {"ms": 2.0, "work": 1e8, "launches": 1},
+            "matvec_f64": {"ms": 3.0, "work": 4.5e8, "launches": 10},
+            "esp_grad_pts_L0_f32": {"ms": 99.0, "work": 1.0, "launches": 1}}
+    fam = bench.family_rooflines(prof, m, 2)
+    pts = (m["esp_grad_pts_L0"] + m["esp_grad_pts_L1"]) * 1e9 / 20e-3 / 1e12
+    assert abs(fam["point_side"]["model_tflops"] - round(pts, 3)) < 1e-9
+    assert fam["point_side"]["ms_per_step"] == 10.0  # 20 ms over 2 profiled steps; FP32 entries excluded
+    assert abs(fam["matvec"]["frac"] - round(14 * 4.5e8 / 3e-3 / 1e12 / bench.PEAK_F64_TFLOPS, 4)) < 1e-12
+    assert "pair_side" not in fam
+
