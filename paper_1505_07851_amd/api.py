@@ -452,8 +452,8 @@ def default_f(eps=78.39, k=0.0):
     return (eps - 1.0) / (eps + k)
 
 
-__all__ = ["Context", "Molecule", "Batch", "PCMError", "ThresholdPolicy", "dynamic_threshold", "octree_partition",
-           "rbj_partition", "math"]
+__all__ = ["Context", "Molecule", "Batch", "Graph", "PCMError", "ThresholdPolicy", "dynamic_threshold",
+           "octree_partition", "rbj_partition"]
 
 
 class Graph:
