@@ -3,19 +3,21 @@
 
 One step = one pass of the whole path over the 600-atom protein-shaped solute
 (6-31G*-shaped basis, ~50 kept surface points per atom, M ~ 30k):
-  geometry update (surface switching values, A_kk, pair geometry), c = L P with Bz,
-  the randomized block-Jacobi PCG solve of A q = -f (Bz + c), the Eq. 13 energy,
-  F += L^T q, and the Eq. 14 gradient.
-The value is shell-pair x point integrals per second over the whole step (three integral
-passes: c, F and the gradient), with the PCG solve time and its residual reported beside
-it, for the FP64 path (the line's value), for the mixed form (FP32 evaluation, FP64
-accumulation, FP32 matvec inside FP64 refinement) and for the per-pair dynamic form (FP64 or
-FP32 integral evaluation by screening bound, FP64 solve).  Inputs are synthetic and seeded
-(see synth/inputs.py).
+  geometry update (surface switching values, A_kk, pair geometry), c = L P with its point
+  derivative dc and Bz (one point-side integral pass), the randomized block-Jacobi PCG solve of
+  A q = -f (Bz + c) from q = 0 (blocks of 256 points), the Eq. 13 energy, then F += L^T q with the
+  Eq. 14 gradient (one pair-side pass over the Eq. 18 list and a Fock pass over the rest of the
+  Eq. 15 list).
+The value is shell-pair x point integrals per second over the whole step (c, the gradient and
+F counted), with the PCG solve time and its residual reported beside it.  The FP64 path gives
+the line's value; beside it the mixed form (FP32 Boys-table interpolation, FP32 matvec inside
+FP64 refinement), the per-pair dynamic form (FP64 or FP32 integral evaluation by screening
+bound, FP32 matvec inside FP64 refinement) and the solve-only mixed form, each compared with
+the FP64 state solved to 1e-10.  Inputs are synthetic and seeded (see synth/inputs.py).
 
 Second workload (--workload conformers64): 64 seeded conformers of a 150-atom peptide
 (6-31G-shaped basis, nbf 825, 3.9k-9k kept points each).  One step = c = L P with Bz,
-the RBJ-100 PCG solve, the Eq. 13 energy and F += L^T q for all 64, batched (one launch per
+the RBJ PCG solve, the Eq. 13 energy and F += L^T q for all 64, batched (one launch per
 class for the integrals, hipGraph-replayed PCG iteration groups over all conformers), and the
 same pass captured whole as one hipGraph (pcm_graph_capture: one launch per step, FP64 PCG
 with a fixed iteration budget), against the same 64 done one after another with the plain FP64
@@ -164,10 +166,11 @@ def main():
                     help="solve tolerance of the untimed accuracy pass that every form is compared on")
     ap.add_argument("--prof-steps", type=int, default=3, help="steps of the profiled (per-kernel) pass")
     ap.add_argument("--nearfar-points", type=int, default=2048, help="nearfar: sampled surface points")
-    ap.add_argument("--block", type=int, default=100)
+    ap.add_argument("--block", type=int, default=256,
+                    help="RBJ block size of the solves (--workload rbj_blocks sweeps it on the 600-atom system)")
     ap.add_argument("--workload", default="protein600",
                     choices=["protein600", "conformers64", "stress2000", "scf_policies", "eq21_fit", "shard8", "copy",
-                             "oracle1t", "nearfar"],
+                             "oracle1t", "nearfar", "rbj_blocks"],
                     help="copy: a plain device copy of known size, to calibrate rocprofv3 byte counters")
     ap.add_argument("--max-iter-none", type=int, default=300,
                     help="stress2000: matvec budget of each unpreconditioned outer solve")
@@ -196,6 +199,8 @@ def main():
         return bench_oracle1t(args)
     if args.workload == "nearfar":
         return bench_nearfar(args)
+    if args.workload == "rbj_blocks":
+        return bench_rbj_blocks(args)
 
     import numpy as np
     import torch
@@ -549,6 +554,48 @@ def bench_nearfar(args):
     print(json.dumps(out))
 
 
+def bench_rbj_blocks(args):
+    """Randomized block-Jacobi block size for the 600-atom solve (Sec. 4b-ii): cold FP64 solves of
+    A q = -f (Bz + c) to 1e-8 for block sizes 100 ... 512, eight partition seeds each.  Reported per
+    size: PCG iterations (mean, spread), the solve time and the setup time (host partition, fill and
+    block inversion; in a benchmark step the partition runs on a host thread while c is evaluated)."""
+    import numpy as np
+    import torch
+
+    from paper_1505_07851_amd import Context, Molecule
+    from synth import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    s = I.protein_single_solve()
+    mol = Molecule.from_system(Context(), s)
+    P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
+    c, bz = mol.esp(P)
+    v = bz + c
+    sizes = {}
+    for blk in (100, 192, 256, 320, 384, 512):
+        rows = []
+        for k in range(8):
+            mol.update_geometry(s.xyz)  # drops the partition and the inverses, as a step does
+            torch.cuda.synchronize()
+            _, info = mol.solve(v, precond="rbj", block=blk, seed=s.seeds["rbj"] + k, tol=args.tol)
+            rows.append(info)
+        it = [i["iters"] for i in rows]
+        sizes[str(blk)] = {"iters_mean": float(np.mean(it)), "iters_std": float(np.std(it)),
+                           "iters_min": min(it), "iters_max": max(it),
+                           "solve_ms_mean": round(float(np.mean([i["solve_ms"] for i in rows])), 3),
+                           "setup_ms_mean": round(float(np.mean([i["setup_ms"] for i in rows])), 3)}
+        log(f"[bench] rbj block {blk}: {sizes[str(blk)]}")
+    best = min(sizes, key=lambda b: sizes[b]["solve_ms_mean"])
+    out = {"metric": "PCG iterations and solve ms against the RBJ block size (8 partition seeds each)",
+           "value": sizes[best]["solve_ms_mean"], "unit": "ms", "n_gpus": 1, "steps": 8, "warmup": 0,
+           "ms_per_step": sizes[best]["solve_ms_mean"], "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "protein600_631gs_rbj_blocks", "atoms": s.n_atoms, "surface_points": mol.M,
+                      "tol": args.tol}, "block_sizes": sizes, "fastest_solve_block": int(best)}
+    print(json.dumps(out))
+
+
 def bench_oracle1t(args):
     """1-thread oracle figures (run by oracle_baseline in a child process): the whole water case
     (Bz, c, A, Cholesky, energy) and c on 64 points of one member of the 64 conformers."""
@@ -575,13 +622,18 @@ def bench_oracle1t(args):
     print(json.dumps(out))
 
 
-def source_digest():
-    """Digest of the sources of the counted kernel (the matvec's translation unit and the shared
-    header): counter figures are reported only for the code they measured."""
+# translation units of the kernels whose HBM counters are committed (profiles/traffic_protein600.txt)
+TRAFFIC_SOURCES = {"matvec": ("pcm_internal.h", "solve.hip"),
+                   "integrals": ("pcm_internal.h", "low_order.h", "integrals.hip", "grad.hip")}
+
+
+def source_digest(kernel="matvec_f64"):
+    """Digest of the sources of a counted kernel (its translation units and the shared headers):
+    counter figures are reported only for the code they measured."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1505_07851_amd", "csrc")
-    for name in ("pcm_internal.h", "solve.hip"):
+    for name in TRAFFIC_SOURCES["matvec" if kernel.startswith("matvec") else "integrals"]:
         h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()[:16]
 
@@ -599,7 +651,7 @@ def measured_traffic(kernel):
             continue
         k, v = line.split("=", 1)
         vals[k.strip()] = v.strip()
-    if vals.get("source_digest") != source_digest():
+    if vals.get(f"{kernel}.source_digest") != source_digest(kernel):
         return None
     key = f"{kernel}.hbm_bytes_per_launch"
     return float(vals[key]) if key in vals else None

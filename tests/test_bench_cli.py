@@ -52,13 +52,18 @@ def test_traffic_summary_digest(tmp_path, monkeypatch):
     path = os.path.join(ROOT, "profiles", "traffic_protein600.txt")
     vals = dict(l.split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
     vals = {k.strip(): v.strip() for k, v in vals.items()}
-    assert float(vals["matvec_f64.hbm_bytes_per_launch"]) > 0
-    got = bench.measured_traffic("matvec_f64")
-    if vals["source_digest"] == bench.source_digest():
-        assert got == float(vals["matvec_f64.hbm_bytes_per_launch"])
-    else:
-        assert got is None
-    monkeypatch.setattr(bench, "source_digest", lambda: "0" * 16)
+    kernels = [k[: -len(".hbm_bytes_per_launch")] for k in vals if k.endswith(".hbm_bytes_per_launch")]
+    assert "matvec_f64" in kernels and len(kernels) >= 2
+    for kern in kernels:
+        assert float(vals[f"{kern}.hbm_bytes_per_launch"]) > 0
+        got = bench.measured_traffic(kern)
+        if vals[f"{kern}.source_digest"] == bench.source_digest(kern):
+            assert got == float(vals[f"{kern}.hbm_bytes_per_launch"])
+        else:
+            assert got is None
+    # the matvec and the integral kernels are digested over their own sources
+    assert bench.source_digest("matvec_f64") != bench.source_digest("fock_grad_v_L1_f64")
+    monkeypatch.setattr(bench, "source_digest", lambda kernel="matvec_f64": "0" * 16)
     assert bench.measured_traffic("matvec_f64") is None
 
 
