@@ -133,7 +133,8 @@ def flop_model():
 def family_rooflines(prof, model, n_prof):
     """Model TFLOP/s and fraction of the FP64 peak per kernel family of the FP64 step, over all its
     classes: the point side (c with dc), the pair side over the Eq. 18 list (F and the gradient),
-    the Fock-only pass over the rest of the Eq. 15 list, and the product."""
+    the Fock-only pass over the rest of the Eq. 15 list, and the product; and the HBM rate of the
+    block-Jacobi apply against the 8 TB/s peak."""
     fams = {"point_side": r"esp_grad_pts_L\d_f64", "pair_side": r"fock_grad_v_L\d_f64", "fock_only": r"fock_v_L\d_f64",
             "matvec": r"matvec_f64"}
     out = {}
@@ -145,6 +146,14 @@ def family_rooflines(prof, model, n_prof):
         tf = sum(kernel_flops(k, prof[k]["work"], model) for k in ks) / (ms * 1e-3) / 1e12
         out[fam] = {"ms_per_step": round(ms / n_prof, 3), "model_tflops": round(tf, 3),
                     "frac": round(tf / PEAK_F64_TFLOPS, 4)}
+    # the block-Jacobi apply is bound by HBM: every inverse entry of every block is read once per
+    # application (8 bytes each; the gathered residual and the written z add under 1%)
+    ra = prof.get("rbj_apply")
+    if ra and ra["ms"] > 0:
+        gbs = 8.0 * ra["work"] / (ra["ms"] * 1e-3) / 1e9
+        out["rbj_apply"] = {"ms_per_step": round(ra["ms"] / n_prof, 3), "bound": "hbm",
+                            "bytes_per_launch": round(8.0 * ra["work"] / ra["launches"]),
+                            "GB_per_s": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
     return out
 
 
@@ -632,7 +641,7 @@ def bench_oracle1t(args):
 
 
 # translation units of the kernels whose HBM counters are committed (profiles/traffic_protein600.txt)
-TRAFFIC_SOURCES = {"matvec": ("pcm_internal.h", "solve.hip"),
+TRAFFIC_SOURCES = {"solver": ("pcm_internal.h", "solve.hip"),
                    "integrals": ("pcm_internal.h", "low_order.h", "integrals.hip", "grad.hip")}
 
 
@@ -642,7 +651,7 @@ def source_digest(kernel="matvec_f64"):
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1505_07851_amd", "csrc")
-    for name in TRAFFIC_SOURCES["matvec" if kernel.startswith("matvec") else "integrals"]:
+    for name in TRAFFIC_SOURCES["solver" if kernel.startswith(("matvec", "rbj")) else "integrals"]:
         h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()[:16]
 

@@ -36,7 +36,7 @@ __global__ void k_rbj_fill(const double *__restrict__ px, const double *__restri
 
 // In-place blocked Gauss-Jordan inversion of every SPD block (no pivoting is needed for SPD
 // matrices).  Panel K of width GJ_PB is eliminated in four launches over all blocks:
-//   diag      A_KK <- P^-1, P = A_KK (scalar Gauss-Jordan in LDS; a non-positive pivot flags
+//   diag      A_KK <- P^-1, P = A_KK (scalar Gauss-Jordan, rows in registers; a non-positive pivot flags
 //             the block as not positive definite)
 //   row       A_Kj <- P^-1 A_Kj                  (j outside K)
 //   trailing  A_ij <- A_ij - A_iK A_Kj           (i, j outside K; A_Kj already updated)
@@ -56,127 +56,152 @@ __device__ inline bool gj_panel(const int *__restrict__ off, const long long *__
     return true;
 }
 
+// Diagonal tile: thread (i, q) = (threadIdx.x % 64, threadIdx.x / 64) keeps row i, columns
+// 16 q .. 16 q + 15 of the panel in registers, so wave q holds one column quarter of all rows.  Pivot
+// step k publishes row k and column k through LDS (double-buffered: one barrier per step), then
+// every thread updates its 16 entries with one FMA each:
+//   row k:        P_kj <- P_kj / P_kk,            P_kk <- 1 / P_kk
+//   other rows i: P_ij <- P_ij - (P_ik / P_kk) P_kj,  P_ik <- -P_ik / P_kk
+// A ragged last panel (kb < 64) is padded with the identity, which the steps k < kb leave alone.
 __global__ __launch_bounds__(256) void k_gj_diag(const int *__restrict__ off, const long long *__restrict__ ioff,
                                                  double *__restrict__ blk, int p, int *__restrict__ bad) {
     double *A;
     int l, K0, kb;
     if (!gj_panel(off, ioff, blockIdx.x, p, blk, A, l, K0, kb)) return;
-    __shared__ double T[GJ_PB * GJ_LD];
-    __shared__ double rowk[GJ_PB], colk[GJ_PB];
-    for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
-        const int i = e / kb, j = e % kb;
-        T[i * GJ_LD + j] = A[(long long)(K0 + i) * l + K0 + j];
+    __shared__ double rowb[2][GJ_PB];
+    __shared__ double colb[2][GJ_PB];
+    const int i = threadIdx.x % GJ_PB, q = threadIdx.x / GJ_PB;
+    constexpr int QW = GJ_PB / 4;  // columns per thread
+    double v[QW];
+#pragma unroll
+    for (int c = 0; c < QW; ++c) {
+        const int j = QW * q + c;
+        v[c] = (i < kb && j < kb) ? A[(long long)(K0 + i) * l + K0 + j] : (i == j ? 1.0 : 0.0);
     }
-    __syncthreads();
-    for (int k = 0; k < kb; ++k) {
-        const double piv = T[k * GJ_LD + k];
-        if (!(piv > 0.0)) {  // uniform: every lane read the same pivot
-            if (threadIdx.x == 0) bad[0] = 1;
-            return;
+    for (int kq = 0; kq < 4; ++kq) {  // pivot k = QW kq + kc: kc indexes the registers statically
+#pragma unroll
+        for (int kc = 0; kc < QW; ++kc) {
+            const int k = QW * kq + kc;
+            if (k >= kb) break;
+            const int bs = kc & 1;
+            if (i == k) {
+#pragma unroll
+                for (int c = 0; c < QW; ++c) rowb[bs][QW * q + c] = v[c];
+            }
+            if (q == kq) colb[bs][i] = v[kc];
+            __syncthreads();
+            const double piv = rowb[bs][k];
+            if (!(piv > 0.0)) {  // uniform: every thread read the same pivot
+                if (threadIdx.x == 0) bad[0] = 1;
+                return;
+            }
+            const double ip = 1.0 / piv;
+            const bool rk = i == k;
+            const double g = rk ? ip : -(colb[bs][i] * ip);  // the new P_ik
+            const double h = rk ? ip - 1.0 : g;              // row k: P_kj + (1/P_kk - 1) P_kj
+#pragma unroll
+            for (int c = 0; c < QW; ++c) {
+                const double nv = fma(h, rowb[bs][QW * q + c], v[c]);
+                v[c] = (c == kc && q == kq) ? g : nv;
+            }
         }
-        const double ip = 1.0 / piv;
-        if (threadIdx.x < kb) {
-            rowk[threadIdx.x] = T[k * GJ_LD + threadIdx.x] * ip;
-            colk[threadIdx.x] = T[threadIdx.x * GJ_LD + k];
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
-            const int i = e / kb, j = e % kb;
-            double v;
-            if (i == k)
-                v = j == k ? ip : rowk[j];
-            else
-                v = j == k ? -colk[i] * ip : T[i * GJ_LD + j] - colk[i] * rowk[j];
-            T[i * GJ_LD + j] = v;
-        }
-        __syncthreads();
     }
-    for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
-        const int i = e / kb, j = e % kb;
-        A[(long long)(K0 + i) * l + K0 + j] = T[i * GJ_LD + j];
+#pragma unroll
+    for (int c = 0; c < QW; ++c) {
+        const int j = QW * q + c;
+        if (i < kb && j < kb) A[(long long)(K0 + i) * l + K0 + j] = v[c];
     }
 }
 
-// row (side = 0): A_Kj <- P^-1 A_Kj for the 64-column tile blockIdx.y of block blockIdx.x;
-// column (side = 1): A_iK <- -A_iK P^-1 for the 64-row tile blockIdx.y
-__global__ __launch_bounds__(256) void k_gj_side(const int *__restrict__ off, const long long *__restrict__ ioff,
-                                                 double *__restrict__ blk, int p, int side) {
-    double *A;
-    int l, K0, kb;
-    if (!gj_panel(off, ioff, blockIdx.x, p, blk, A, l, K0, kb)) return;
-    const int t0 = blockIdx.y * GJ_PB;
-    if (t0 >= l || (int)blockIdx.y == p) return;
-    const int tn = min(GJ_PB, l - t0);
-    __shared__ double Pi[GJ_PB * GJ_LD];
-    __shared__ double X[GJ_PB * GJ_LD];
-    for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
-        const int i = e / kb, j = e % kb;
-        Pi[i * GJ_LD + j] = A[(long long)(K0 + i) * l + K0 + j];
-    }
-    // X holds the tile with the panel index first: X[m][t] = A[K0+m][t0+t] (row) or A[t0+t][K0+m]
-    for (int e = threadIdx.x; e < kb * tn; e += blockDim.x) {
-        if (side == 0) {
-            const int m = e / tn, t = e % tn;
-            X[m * GJ_LD + t] = A[(long long)(K0 + m) * l + t0 + t];
-        } else {
-            const int t = e / kb, m = e % kb;
-            X[m * GJ_LD + t] = A[(long long)(t0 + t) * l + K0 + m];
-        }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < kb * tn; e += blockDim.x) {
-        if (side == 0) {
-            const int r = e / tn, t = e % tn;  // out[r][t] = sum_m Pi[r][m] X[m][t]
-            double acc = 0.0;
-            for (int m = 0; m < kb; ++m) acc = fma(Pi[r * GJ_LD + m], X[m * GJ_LD + t], acc);
-            A[(long long)(K0 + r) * l + t0 + t] = acc;
-        } else {
-            const int t = e / kb, c = e % kb;  // out[t][c] = -sum_m X[m][t] Pi[m][c]
-            double acc = 0.0;
-            for (int m = 0; m < kb; ++m) acc = fma(X[m * GJ_LD + t], Pi[m * GJ_LD + c], acc);
-            A[(long long)(t0 + t) * l + K0 + c] = -acc;
-        }
-    }
-}
+// Off-diagonal tiles of panel K, one 64 x 64 tile per workgroup:
+//   GJ_ROW    tile (K, t):  A_Kt <- P^-1 A_Kt          (P^-1 = the inverted diagonal tile)
+//   GJ_TRAIL  tile (s, t):  A_st <- A_st - A_sK A_Kt   (s, t != K; A_Kt already updated)
+//   GJ_COL    tile (s, K):  A_sK <- -A_sK P^-1
+// Each is out = L R with L[i][m] = A[r0 + i][K0 + m] and R[m][j] = A[K0 + m][c0 + j] for the
+// tile's row and column origins (r0, c0), staged in LDS.  A lane accumulates a 4 x 4 sub-tile
+// (rows 4 (lane / 16) + u, columns lane % 16 + 16 v), reading 8 LDS values per 16 FMAs.
+// Workgroup w serves block 8 (w / (8 T)) + w % 8, tile (w / 8) % T of its T tiles: workgroups
+// are dealt to the 8 XCDs in turn, so every tile of a block runs on one XCD and the panel row and
+// column it shares are fetched into that XCD's L2 once.
+enum { GJ_ROW = 0, GJ_TRAIL = 1, GJ_COL = 2 };
+constexpr int GJ_XCD = 8;
 
-// trailing update of the 64x64 tile (ti, tj) = (blockIdx.y / nt, blockIdx.y % nt) of block
-// blockIdx.x; each lane owns a 4x4 sub-tile (rows 4 (lane / 16) .., columns lane % 16 + 16 c)
-__global__ __launch_bounds__(256) void k_gj_trail(const int *__restrict__ off, const long long *__restrict__ ioff,
-                                                  double *__restrict__ blk, int p, int nt) {
+__global__ __launch_bounds__(256) void k_gj_update(const int *__restrict__ off, const long long *__restrict__ ioff,
+                                                   double *__restrict__ blk, int nb, int p, int nt, int mode) {
+    const int T = mode == GJ_TRAIL ? nt * nt : nt;
+    const int w = blockIdx.x;
+    const int b = GJ_XCD * (w / (GJ_XCD * T)) + w % GJ_XCD, tile = (w / GJ_XCD) % T;
+    if (b >= nb) return;
     double *A;
     int l, K0, kb;
-    if (!gj_panel(off, ioff, blockIdx.x, p, blk, A, l, K0, kb)) return;
-    const int ti = blockIdx.y / nt, tj = blockIdx.y % nt;
-    const int i0 = ti * GJ_PB, j0 = tj * GJ_PB;
-    if (i0 >= l || j0 >= l || ti == p || tj == p) return;
-    const int in = min(GJ_PB, l - i0), jn = min(GJ_PB, l - j0);
-    __shared__ double C[GJ_PB * GJ_LD];  // C[m][i] = A[i0+i][K0+m]
-    __shared__ double R[GJ_PB * GJ_LD];  // R[m][j] = A[K0+m][j0+j]
-    for (int e = threadIdx.x; e < in * kb; e += blockDim.x) {
-        const int i = e / kb, m = e % kb;
-        C[m * GJ_LD + i] = A[(long long)(i0 + i) * l + K0 + m];
+    if (!gj_panel(off, ioff, b, p, blk, A, l, K0, kb)) return;
+    int ts, tt;  // tile row and column
+    if (mode == GJ_TRAIL) {
+        ts = tile / nt;
+        tt = tile % nt;
+        if (ts == p || tt == p) return;
+    } else {
+        if (tile == p) return;
+        ts = mode == GJ_ROW ? p : tile;
+        tt = mode == GJ_ROW ? tile : p;
     }
-    for (int e = threadIdx.x; e < kb * jn; e += blockDim.x) {
-        const int m = e / jn, j = e % jn;
-        R[m * GJ_LD + j] = A[(long long)(K0 + m) * l + j0 + j];
-    }
-    __syncthreads();
-    const int r0 = 4 * (threadIdx.x / 16), c0 = threadIdx.x % 16;
+    const int r0 = ts * GJ_PB, c0 = tt * GJ_PB;
+    if (r0 >= l || c0 >= l) return;
+    const int in = min(GJ_PB, l - r0), jn = min(GJ_PB, l - c0);
+    const int u0 = 4 * (threadIdx.x / 16), v0 = threadIdx.x % 16;
     double acc[4][4] = {};
-    for (int m = 0; m < kb; ++m) {
-        double a[4], bb[4];
-        for (int u = 0; u < 4; ++u) a[u] = C[m * GJ_LD + r0 + u];
-        for (int v = 0; v < 4; ++v) bb[v] = R[m * GJ_LD + c0 + 16 * v];
+    if (mode == GJ_TRAIL) {  // the old tile, loaded while the panels are staged
+#pragma unroll
         for (int u = 0; u < 4; ++u)
-            for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], bb[v], acc[u][v]);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (u0 + u < in && v0 + 16 * v < jn) acc[u][v] = A[(long long)(r0 + u0 + u) * l + c0 + v0 + 16 * v];
     }
+    // staging: thread (x, y) = (threadIdx.x % 64, threadIdx.x / 64) loads rows y + 4 s of both
+    // panels at column x, all 32 loads in flight before the first LDS store
+    __shared__ double Ls[GJ_PB * GJ_LD];  // Ls[m][i] = A[r0 + i][K0 + m] (negated when trailing)
+    __shared__ double Rs[GJ_PB * GJ_LD];  // Rs[m][j] = A[K0 + m][c0 + j]
+    constexpr int NS = GJ_PB * GJ_PB / 256;
+    const int x = threadIdx.x % GJ_PB, y = threadIdx.x / GJ_PB;
+    double lv[NS], rv[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        const int i = y + 4 * t;
+        lv[t] = i < in && x < kb ? A[(long long)(r0 + i) * l + K0 + x] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        const int m = y + 4 * t;
+        rv[t] = m < kb && x < jn ? A[(long long)(K0 + m) * l + c0 + x] : 0.0;
+    }
+    const double sg = mode == GJ_TRAIL ? -1.0 : 1.0;  // trailing: acc = A_st - sum, else sum
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        Ls[x * GJ_LD + y + 4 * t] = sg * lv[t];
+        Rs[(y + 4 * t) * GJ_LD + x] = rv[t];
+    }
+    __syncthreads();
+    for (int m = 0; m < kb; ++m) {
+        double a[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = Ls[m * GJ_LD + u0 + u];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bv[v] = Rs[m * GJ_LD + v0 + 16 * v];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], bv[v], acc[u][v]);
+    }
+#pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const int i = r0 + u;
+        const int i = u0 + u;
         if (i >= in) continue;
-        double *Ai = A + (long long)(i0 + i) * l + j0;
+        double *Ai = A + (long long)(r0 + i) * l + c0;
+#pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int j = c0 + 16 * v;
-            if (j < jn) Ai[j] -= acc[u][v];
+            const int j = v0 + 16 * v;
+            if (j >= jn) continue;
+            Ai[j] = mode == GJ_COL ? -acc[u][v] : acc[u][v];
         }
     }
 }
@@ -295,13 +320,12 @@ void rbj_setup(pcm_ctx *ctx, pcm_mol *mol, int kind, int l, unsigned long long s
             k_gj_diag<<<nb, 256, 0, ctx->stream>>>(mol->rbj_off.p, mol->rbj_ioff.p, mol->rbj_inv.p, p, ctx->iscal.p);
             HIP_LAUNCH_OK();
             if (nt == 1) continue;  // a single panel: the block is inverted
-            k_gj_side<<<dim3(nb, nt), 256, 0, ctx->stream>>>(mol->rbj_off.p, mol->rbj_ioff.p, mol->rbj_inv.p, p, 0);
-            HIP_LAUNCH_OK();
-            k_gj_trail<<<dim3(nb, nt * nt), 256, 0, ctx->stream>>>(mol->rbj_off.p, mol->rbj_ioff.p,
-                                                                    mol->rbj_inv.p, p, nt);
-            HIP_LAUNCH_OK();
-            k_gj_side<<<dim3(nb, nt), 256, 0, ctx->stream>>>(mol->rbj_off.p, mol->rbj_ioff.p, mol->rbj_inv.p, p, 1);
-            HIP_LAUNCH_OK();
+            for (int mode : {GJ_ROW, GJ_TRAIL, GJ_COL}) {
+                const long long T = mode == GJ_TRAIL ? (long long)nt * nt : nt;
+                k_gj_update<<<(unsigned)(div_up(nb, GJ_XCD) * GJ_XCD * T), 256, 0, ctx->stream>>>(
+                    mol->rbj_off.p, mol->rbj_ioff.p, mol->rbj_inv.p, nb, p, nt, mode);
+                HIP_LAUNCH_OK();
+            }
         }
     }
     int bad = 0;

@@ -393,32 +393,57 @@ __global__ __launch_bounds__(TILE) void k_cg_update(const CGMol *__restrict__ ta
 }
 
 // randomized block-Jacobi: z[perm[o+i]] = sum_j inv[j][i] r[perm[o+j]] (inverse symmetric);
-// partials of r.z per item
+// partials of r.z per item.  An item is a slab of RBJ_ROWS rows of one block, one row per lane;
+// the block's columns are split into TILE / RBJ_ROWS contiguous chunks, one per wave, so a block
+// of l points streams its l^2 inverse entries through l / 16 waves.  Each lane has a column
+// element of RBJ_UNROLL inverse rows in flight per step (each wave load a 512-byte row segment);
+// the chunk sums are added in wave order, so the result is bitwise reproducible.
+constexpr int RBJ_ROWS = 64;
+constexpr int RBJ_UNROLL = 16;
+constexpr int RBJ_SPLIT = TILE / RBJ_ROWS;
 __global__ __launch_bounds__(TILE) void k_rbj_items(const CGMol *__restrict__ tab, const CGState *__restrict__ st,
                                                     const RbjItem *__restrict__ items, int n) {
-    __shared__ double s[TILE];
     __shared__ double rb[1024];  // the block's residual entries, gathered once (l <= 1024)
+    __shared__ double red[RBJ_SPLIT - 1][RBJ_ROWS];
+    const int lane = threadIdx.x % RBJ_ROWS, wv = threadIdx.x / RBJ_ROWS;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const RbjItem w = items[it];
         if (st[w.mol].done) continue;
         const CGMol &m = tab[w.mol];
         const int o = m.boff[w.blk], l = m.boff[w.blk + 1] - o;
-        const int i = w.i0 + threadIdx.x;
         const double *__restrict__ r = m.v[V_R];
         const int *__restrict__ pm = m.perm + o;
         for (int j = threadIdx.x; j < l; j += TILE) rb[j] = r[pm[j]];
         __syncthreads();
-        double rz = 0.0;
+        const int i = w.i0 + lane;
+        const int cl = (l + RBJ_SPLIT - 1) / RBJ_SPLIT;
+        const int j1 = min(l, (wv + 1) * cl);
+        double acc = 0.0;
         if (i < l) {
-            const double *__restrict__ Ab = m.inv + m.ioff[w.blk];
-            double acc = 0.0;
-            for (int j = 0; j < l; ++j) acc = fma(Ab[(long long)j * l + i], rb[j], acc);
-            const int ki = pm[i];
-            m.v[V_Z][ki] = acc;
-            rz = acc * rb[i];
+            const double *__restrict__ Ab = m.inv + m.ioff[w.blk] + i;
+            for (int j = wv * cl; j < j1; j += RBJ_UNROLL) {
+                double a[RBJ_UNROLL];
+#pragma unroll
+                for (int u = 0; u < RBJ_UNROLL; ++u) a[u] = j + u < j1 ? Ab[(long long)(j + u) * l] : 0.0;
+#pragma unroll
+                for (int u = 0; u < RBJ_UNROLL; ++u)
+                    if (j + u < j1) acc = fma(a[u], rb[j + u], acc);
+            }
         }
-        double t = blk_sum(rz, s);  // its barriers also keep rb intact until every lane is done
-        if (threadIdx.x == 0) m.dp[2 * m.ndp + w.slot] = t;
+        if (wv > 0) red[wv - 1][lane] = acc;
+        __syncthreads();
+        if (wv == 0) {
+#pragma unroll
+            for (int u = 0; u < RBJ_SPLIT - 1; ++u) acc += red[u][lane];
+            double rz = 0.0;
+            if (i < l) {
+                m.v[V_Z][pm[i]] = acc;
+                rz = acc * rb[i];
+            }
+            for (int d = RBJ_ROWS / 2; d > 0; d >>= 1) rz += __shfl_xor(rz, d, RBJ_ROWS);
+            if (lane == 0) m.dp[2 * m.ndp + w.slot] = rz;
+        }
+        __syncthreads();  // rb and red are rewritten by the next item
     }
 }
 
@@ -697,7 +722,7 @@ static void batch_tables(pcm_ctx *ctx, SolveBatch &B, int precond) {
             int slot = 0;
             for (int bk = 0; bk < nb; ++bk) {
                 const int l = mol->h_rbj_off[bk + 1] - mol->h_rbj_off[bk];
-                for (int i0 = 0; i0 < l; i0 += TILE) rb.push_back(RbjItem{i, bk, i0, slot++});
+                for (int i0 = 0; i0 < l; i0 += RBJ_ROWS) rb.push_back(RbjItem{i, bk, i0, slot++});
             }
             n_rz = slot;
         }

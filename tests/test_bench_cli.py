@@ -63,6 +63,7 @@ def test_traffic_summary_digest(tmp_path, monkeypatch):
             assert got is None
     # the matvec and the integral kernels are digested over their own sources
     assert bench.source_digest("matvec_f64") != bench.source_digest("fock_grad_v_L1_f64")
+    assert bench.source_digest("rbj_apply") == bench.source_digest("matvec_f64")  # both in solve.hip
     monkeypatch.setattr(bench, "source_digest", lambda kernel="matvec_f64": "0" * 16)
     assert bench.measured_traffic("matvec_f64") is None
 
@@ -74,11 +75,16 @@ def test_family_rooflines():
             "esp_grad_pts_L1_f64": {"ms": 10.0, "work": 1e9, "launches": 1},
             "fock_v_L0_f64": {"ms": 2.0, "work": 1e8, "launches": 1},
             "matvec_f64": {"ms": 3.0, "work": 4.5e8, "launches": 10},
-            "esp_grad_pts_L0_f32": {"ms": 99.0, "work": 1.0, "launches": 1}}
+            "esp_grad_pts_L0_f32": {"ms": 99.0, "work": 1.0, "launches": 1},
+            "rbj_apply": {"ms": 0.5, "work": 2.5e8, "launches": 20}}
     fam = bench.family_rooflines(prof, m, 2)
     pts = (m["esp_grad_pts_L0"] + m["esp_grad_pts_L1"]) * 1e9 / 20e-3 / 1e12
     assert abs(fam["point_side"]["model_tflops"] - round(pts, 3)) < 1e-9
     assert fam["point_side"]["ms_per_step"] == 10.0  # 20 ms over 2 profiled steps; FP32 entries excluded
     assert abs(fam["matvec"]["frac"] - round(14 * 4.5e8 / 3e-3 / 1e12 / bench.PEAK_F64_TFLOPS, 4)) < 1e-12
     assert "pair_side" not in fam
+    # RBJ apply: 8 bytes per inverse entry, 2e9 bytes in 0.5 ms = 4000 GB/s, half the HBM peak
+    ra = fam["rbj_apply"]
+    assert ra["bound"] == "hbm" and ra["GB_per_s"] == 4000.0 and ra["frac"] == 0.5
+    assert ra["bytes_per_launch"] == 1e8 and ra["ms_per_step"] == 0.25
 

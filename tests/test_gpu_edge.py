@@ -4,6 +4,8 @@
   such a surface is refused with PCM_E_ARG.
 * A single hydrogen atom: M = 50 points in one ragged tile, two basis functions; c, q, E
   and the gradient against the oracle.
+* One randomized block-Jacobi block holding every point: the preconditioner is A^-1, so the
+  device's blocked inversion is checked by a one-step solve.
 """
 import numpy as np
 import pytest
@@ -159,3 +161,33 @@ def test_zero_density(torch_cuda):
     assert torch.equal(gn0b, gn) and torch.equal(gs0b, gs)
     assert torch.equal(gn1b, single1[0]) and torch.equal(gs1b, single1[1])
     b.close()
+
+
+@pytest.mark.parametrize("n_atoms,n_sph,seed", [(2, 110, 3), (20, 110, 5)])
+def test_rbj_single_block_is_the_inverse(torch_cuda, n_atoms, n_sph, seed):
+    """A randomized block-Jacobi block as large as the surface holds every point, so the
+    preconditioner is A^-1 itself (Sec. 4b-ii with l = M): the first PCG direction is the exact
+    solution, and the solve stops after one step (two when rounding leaves the first residual
+    just above the threshold).  Covers the blocked inversion on the device: three 64-wide panels,
+    the last one ragged, for M = 179, and fourteen (the last 49 wide) for M = 881.  q is compared
+    with the oracle's dense Cholesky solve of the same right-hand side."""
+    from paper_1505_07851_amd import Context, Molecule
+    torch = torch_cuda
+    s = I.small_protein(n_atoms, n_sph, seed=seed)
+    om = O.mol_from_system(s)
+    print(f"\n[case rbj single block: {n_atoms} atoms, M = {om.M}]", flush=True)
+    assert om.M <= 1024
+    mol = Molecule.from_system(Context(), s)
+    assert mol.M == om.M
+    P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
+    c, bz = mol.esp(P)
+    v = (bz + c).cpu().numpy()
+    q_ref = om.solve_dense(v)
+    tol = 1e-9 * np.linalg.norm(v)
+    for block in (mol.M, 1024):
+        q, info = mol.solve(bz + c, precond="rbj", block=block, seed=11, tol=tol)
+        assert info["iters"] <= 2, (block, info)
+        assert np.abs(q.cpu().numpy() - q_ref).max() <= 1e-7 * np.abs(q_ref).max()
+    # against ordinary blocks the same partition code needs many more steps
+    _, info = mol.solve(bz + c, precond="rbj", block=64, seed=11, tol=tol)
+    assert info["iters"] > 4
