@@ -23,7 +23,7 @@ template <typename T> void upload(pcm_ctx *ctx, DevBuf<T> &d, const T *h, size_t
 
 void release_list(PairList &pl) {
     pl.spo.release(); pl.cnt.release(); pl.mask.release();
-    pl.ent_sp.release(); pl.ent_ij.release(); pl.rec.release();
+    pl.ent_sp.release(); pl.ent_ij.release(); pl.rec.release(); pl.vperm.release();
 }
 
 void release_mol(pcm_mol *m) {
@@ -52,6 +52,9 @@ void release_mol(pcm_mol *m) {
     m->m15.release();
     m->mtmp.release();
     m->ctmp.release();
+    m->okey.release();
+    m->oval.release();
+    m->osort.release();
     m->m18.release();
     m->c18.release();
 }

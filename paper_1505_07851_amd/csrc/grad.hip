@@ -30,6 +30,7 @@ struct GradPtsDesc {
 };
 struct GradVDesc {
     const unsigned char *rec;  // class records
+    const int *perm;           // record taken by each lane, class-local (null: list order)
     const void *pts;           // PtInt<T> [Mpad]
     const double *q;           // charges, zero past M [Mpad]
     double *vout;              // [chunk][tuv][pair]
@@ -280,7 +281,7 @@ __global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds
         const int ptile = (int)(local % d.nptile), ch = (int)(local / d.nptile);
         const int n_pairs = d.n_pairs;
         const int ip = ptile * 256 + threadIdx.x;
-        const int ipp = ip < n_pairs ? ip : n_pairs - 1;
+        const int ipp = d.perm ? d.perm[ip < n_pairs ? ip : n_pairs - 1] : (ip < n_pairs ? ip : n_pairs - 1);
         const PairHdr<T> h = *reinterpret_cast<const PairHdr<T> *>(d.rec + (size_t)ipp * d.stride);
         const cptr<PtInt<T>> pts = as_const(reinterpret_cast<const PtInt<T> *>(d.pts));
         const cptr<double> q = as_const(d.q);
@@ -334,7 +335,7 @@ __global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds
         if (ip < n_pairs) {
             double *o = d.vout + (size_t)ch * NT * n_pairs;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) o[(size_t)t * n_pairs + ip] = V[t];
+            for (int t = 0; t < NT; ++t) o[(size_t)t * n_pairs + ipp] = V[t];
         }
     }
 }
@@ -803,6 +804,7 @@ static void grad_cterm(pcm_ctx *ctx, std::vector<GradJob> &jobs, ListSel ls, boo
             dp.push_back(a);
             GradVDesc b{};
             b.rec = rec;
+            b.perm = pair_order(pl, cl);
             b.pts = a.pts;
             b.q = mol->qpad.p;
             b.vout = mol->vbuf.p;
@@ -1044,6 +1046,7 @@ static void fock_grad_pairs(pcm_ctx *ctx, pcm_mol *mol, const double *P, double 
         }
         GradVDesc b{};
         b.rec = pl.rec.p + pl.rec_off[cl];
+        b.perm = pair_order(pl, cl);
         b.pts = sizeof(T) == 8 ? (const void *)mol->pti64.p : (const void *)mol->pti32.p;
         b.q = mol->qpad.p;
         b.vout = mol->vbuf.p;

@@ -45,6 +45,7 @@ struct EspDesc {
 
 struct FockDesc {
     const unsigned char *rec;  // class headers
+    const int *perm;           // record taken by each lane, class-local (null: list order)
     const void *pts;           // PtInt<T> [Mpad]
     const double *q;           // charges, zero past M [Mpad]
     double *vout;              // [nch][NT][n_pairs]
@@ -242,7 +243,8 @@ __global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds,
         const int pt_tile = (int)(local % d.nptile), ch = (int)(local / d.nptile);
         const int n = d.n_pairs;
         const int ip = pt_tile * 256 + threadIdx.x;
-        const PairHdr<T> h = *reinterpret_cast<const PairHdr<T> *>(d.rec + (size_t)(ip < n ? ip : n - 1) * d.stride);
+        const int ipp = d.perm ? d.perm[ip < n ? ip : n - 1] : (ip < n ? ip : n - 1);
+        const PairHdr<T> h = *reinterpret_cast<const PairHdr<T> *>(d.rec + (size_t)ipp * d.stride);
         const cptr<PtInt<T>> pts = as_const(reinterpret_cast<const PtInt<T> *>(d.pts));
         const cptr<double> q = as_const(d.q);
         const int k0 = ch * d.chunk;
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds,
         if (ip < n) {
             double *o = d.vout + (size_t)ch * NT * n;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) o[(size_t)t * n + ip] = V[t];
+            for (int t = 0; t < NT; ++t) o[(size_t)t * n + ipp] = V[t];
         }
     }
 }
@@ -740,6 +742,7 @@ template <typename T> static FockDesc fock_desc(pcm_mol *mol, ListSel ls, int cl
     PairList &pl = mol->*ls;
     FockDesc d{};
     d.rec = pl.rec.p + pl.rec_off[cl];
+    d.perm = pair_order(pl, cl);
     d.pts = points<T>(mol);
     d.q = mol->qpad.p;
     d.vout = mol->vbuf.p;

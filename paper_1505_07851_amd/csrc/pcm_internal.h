@@ -406,7 +406,17 @@ struct PairList {
     DevBuf<int> ent_sp, ent_ij;       // [n] candidate shell pair index, i*8+j
     DevBuf<unsigned char> rec;        // pair records (type and stride depend on use)
     size_t rec_off[NCLS + 1] = {0};   // byte offsets of each class in rec
+    // [n] per class, the class-local record index each lane of a pair-per-lane kernel takes (it
+    // writes its sums back at that index): the records grouped by exponent, then along a Morton
+    // curve of the product centre, so that a wave's pairs are alike in p and close together and
+    // the near-field branch is taken by fewer waves.  Results do not depend on this order.
+    DevBuf<int> vperm;
 };
+
+// the pair order of class cl for the pair-per-lane kernels (null when the list has none)
+inline const int *pair_order(const PairList &pl, int cl) {
+    return pl.vperm.p && pl.cls_off[cl + 1] > pl.cls_off[cl] ? pl.vperm.p + pl.cls_off[cl] : nullptr;
+}
 
 struct SolveBatch;
 struct RbjPending;
@@ -452,6 +462,9 @@ struct pcm_mol {
     DevBuf<int> c18;
     DevBuf<unsigned long long> mtmp;    // screening scratch of the precision splits [3 x candidates]
     DevBuf<int> ctmp;
+    DevBuf<unsigned> okey;              // pair-order sort scratch: keys in and out [2 x entries]
+    DevBuf<int> oval;                   // class-local indexes to sort [entries]
+    DevBuf<unsigned char> osort;        // radix sort temporary storage
     bool esp_valid = false;
     // workspaces
     DevBuf<double> part;   // partial sums (esp / gradient)

@@ -7,6 +7,8 @@
 // formulas.
 #include "pcm_internal.h"
 
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include <algorithm>
 #include <cstring>
 
@@ -405,6 +407,64 @@ static void screen_launch(pcm_ctx *ctx, pcm_mol *mol, const double *P, double th
     HIP_LAUNCH_OK();
 }
 
+// Order of the records for the pair-per-lane kernels: key = class (3 bits), exponent octave of
+// p = a + b (4 bits: p from 1/4 to 2^14), Morton code of the product centre on a 256^3 grid over
+// the molecule (24 bits); value = the class-local record index.
+struct ClsBounds {
+    long long o[NCLS + 1];
+};
+__global__ void k_pair_key(long long n, ClsBounds cb, const int *__restrict__ ent_sp, const int *__restrict__ ent_ij,
+                           const int *__restrict__ spa, const int *__restrict__ spb, const int *__restrict__ soff,
+                           const int *__restrict__ satom, const double *__restrict__ pexp,
+                           const double *__restrict__ xyz, double lox, double loy, double loz, double inv_cell,
+                           unsigned *__restrict__ key, int *__restrict__ val) {
+    long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    int c = 0;
+    while (c < NCLS - 1 && q >= cb.o[c + 1]) ++c;
+    const int sp = ent_sp[q], ij = ent_ij[q];
+    const int a = spa[sp], b = spb[sp];
+    const double ea = pexp[soff[a] + (ij >> 3)], eb = pexp[soff[b] + (ij & 7)], p = ea + eb;
+    const double *A = xyz + 3 * satom[a], *B = xyz + 3 * satom[b];
+    const double P[3] = {(ea * A[0] + eb * B[0]) / p, (ea * A[1] + eb * B[1]) / p, (ea * A[2] + eb * B[2]) / p};
+    const double lo[3] = {lox, loy, loz};
+    unsigned m = 0;
+    for (int d = 0; d < 3; ++d) {
+        const int g = min(255, max(0, (int)((P[d] - lo[d]) * inv_cell)));
+        for (int bit = 0; bit < 8; ++bit) m |= (unsigned)((g >> bit) & 1) << (3 * bit + d);
+    }
+    const int oct = min(15, max(0, (int)floor(log2(p)) + 2));
+    key[q] = ((unsigned)c << 28) | ((unsigned)oct << 24) | m;
+    val[q] = (int)(q - cb.o[c]);
+}
+
+static void pairs_order(pcm_ctx *ctx, pcm_mol *mol, PairList &pl) {
+    const long long n = pl.n;
+    pl.vperm.ensure(n + 1);
+    if (n == 0) return;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int i = 0; i < mol->N; ++i)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], mol->h_xyz[3 * i + d]);
+            hi[d] = std::max(hi[d], mol->h_xyz[3 * i + d]);
+        }
+    const double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1.0});
+    ClsBounds cb;
+    for (int c = 0; c <= NCLS; ++c) cb.o[c] = pl.cls_off[c];
+    mol->okey.ensure(2 * (size_t)n);
+    mol->oval.ensure(n);
+    k_pair_key<<<div_up(n, 256), 256, 0, ctx->stream>>>(n, cb, pl.ent_sp.p, pl.ent_ij.p, mol->spa.p, mol->spb.p,
+                                                       mol->soff.p, mol->satom.p, mol->pexp.p, mol->xyz.p, lo[0],
+                                                       lo[1], lo[2], 255.999 / ext, mol->okey.p, mol->oval.p);
+    HIP_LAUNCH_OK();
+    size_t bytes = 0;
+    HIP_OK(rocprim::radix_sort_pairs(nullptr, bytes, mol->okey.p, mol->okey.p + n, mol->oval.p, pl.vperm.p, n, 0,
+                                     31, ctx->stream));
+    mol->osort.ensure(bytes + 1);
+    HIP_OK(rocprim::radix_sort_pairs(mol->osort.p, bytes, mol->okey.p, mol->okey.p + n, mol->oval.p, pl.vperm.p, n,
+                                     0, 31, ctx->stream));
+}
+
 // entries, per-shell-pair offsets and class offsets of a list from its survivor masks and counts
 static void pairs_compact(pcm_ctx *ctx, pcm_mol *mol, PairList &pl) {
     const long long nsp = mol->sp_cls_off[NCLS];
@@ -448,6 +508,7 @@ static void pairs_compact(pcm_ctx *ctx, pcm_mol *mol, PairList &pl) {
         HIP_OK(hipMemcpyAsync(pl.spo.p + nsp, &t, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
         HIP_OK(hipStreamSynchronize(ctx->stream));
     }
+    pairs_order(ctx, mol, pl);
 }
 
 void pairs_build(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, const double *P, int kind) {
