@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds
     load_boys<B, L + 1>(tab, boys_g);
     constexpr int NT = ntuv(L + 1);
     // points per batch: fewer for the larger V' sets so that more waves stay resident
-    constexpr int PB = L <= 1 ? PT_BATCH : (L == 2 ? 2 : 1);
+    constexpr int PB = L <= 1 ? PT_BATCH : (L == 2 && sizeof(T) == 4 ? 2 : 1);
     {  // one item per block, as in k_grad_pts
         const long long it = blockIdx.x;
         if (it >= n_items) return;
@@ -290,6 +290,15 @@ __global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds
         double V[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) V[t] = 0.0;
+        // FP64 records, V' up to order 2 or 3: the far-field factored sums of low_order.h
+        constexpr bool FS = sizeof(T) == 8 && (L == 1 || L == 2);
+        constexpr int NS = FS ? L + 1 : 2;
+        double S[nsums<NS>()], ipf = 0.0;
+        if constexpr (FS) {
+#pragma unroll
+            for (int t = 0; t < nsums<NS>(); ++t) S[t] = 0.0;
+            ipf = far_scale(h.pf);
+        }
         for (int k = k0; k < k1; k += PB) {
             PtInt<T> pt[PB];
             double qk[PB];
@@ -300,6 +309,13 @@ __global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds
             }
 #pragma unroll
             for (int b = 0; b < PB; ++b) {
+                if constexpr (FS) {
+                    double x, y, z, sv[NS + 1];
+                    eval_s<NS, B>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, ipf, pt[b].zeta2, pt[b].zeta,
+                                  pt[b].lim, tab, qk[b], x, y, z, sv);
+                    acc_S<NS>(sv, x, y, z, S);
+                    continue;
+                }
                 if constexpr (L == 1) {  // q R_t with q R^(1), q R^(2) formed once
                     T x, y, z, Rn[3];
                     eval_Rn<2, T, B>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
@@ -332,6 +348,7 @@ __global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds
                 for (int t = 0; t < NT; ++t) V[t] = fma(qk[b], (double)R[t], V[t]);
             }
         }
+        if constexpr (FS) fin_S<NS>(h.pf, S, V);
         if (ip < n_pairs) {
             double *o = d.vout + (size_t)ch * NT * n_pairs;
 #pragma unroll

@@ -252,6 +252,15 @@ __global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds,
         double V[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) V[t] = 0.0;
+        // FP64 records, V up to order 2 or 3: the far-field factored sums of low_order.h
+        constexpr bool FS = sizeof(T) == 8 && (L == 2 || L == 3);
+        constexpr int NS = FS ? L : 2;
+        double S[nsums<NS>()], ipf = 0.0;
+        if constexpr (FS) {
+#pragma unroll
+            for (int t = 0; t < nsums<NS>(); ++t) S[t] = 0.0;
+            ipf = far_scale(h.pf);
+        }
         for (int k = k0; k < k1; k += PT_BATCH) {
             PtInt<T> pt[PT_BATCH];
             double qk[PT_BATCH];
@@ -262,6 +271,13 @@ __global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds,
             }
 #pragma unroll
             for (int b = 0; b < PT_BATCH; ++b) {
+                if constexpr (FS) {
+                    double x, y, z, sv[NS + 1];
+                    eval_s<NS, B>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, ipf, pt[b].zeta2, pt[b].zeta,
+                                  pt[b].lim, tab, qk[b], x, y, z, sv);
+                    acc_S<NS>(sv, x, y, z, S);
+                    continue;
+                }
                 if constexpr (L == 2) {  // q R_t with q R^(1), q R^(2) formed once
                     T x, y, z, Rn[3];
                     eval_Rn<2, T, B>(h.Px - pt[b].x, h.Py - pt[b].y, h.Pz - pt[b].z, h, pt[b].zeta2, pt[b].zeta,
@@ -294,6 +310,7 @@ __global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds,
                 for (int t = 0; t < NT; ++t) V[t] = fma(qk[b], (double)R[t], V[t]);
             }
         }
+        if constexpr (FS) fin_S<NS>(h.pf, S, V);
         if (ip < n) {
             double *o = d.vout + (size_t)ch * NT * n;
 #pragma unroll

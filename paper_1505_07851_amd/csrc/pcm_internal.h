@@ -145,11 +145,41 @@ constexpr int PT_PAD = 64;  // point arrays are padded to a multiple of this wit
 // n <= L.  Kernels stage only these columns, so low-L kernels keep more workgroups resident.
 template <typename T, int L> __host__ __device__ constexpr int boys_cols() { return L + BoysCfg<T>::ORD + 1; }
 
+// near field (a r^2 < TMAX) of aux_Rn: the Boys-table interpolation
+template <int L, typename T, typename B = T>
+__device__ __forceinline__ void aux_Rn_near(T r2, T p, T pref, T zeta2, T zeta, const B *__restrict__ tab,
+                                            T (&Rn)[L + 1]) {
+    using C = BoysCfg<B>;
+    static_assert(boys_cols<B, L>() <= C::MT, "Boys table has too few columns for this L");
+    // sqrt(u) = zeta / sqrt(zeta^2 + p), u = sqrt(u)^2, a = p u
+    T su = zeta * rsq_fast(zeta2 + p);
+    T u = su * su;
+    T a = p * u;
+    T tb = a * r2;
+    int i = (int)(tb * T(8) + T(0.5));
+    i = i < C::NROW - 1 ? i : C::NROW - 1;
+    const B d = (B)(T(i) * T(0.125) - tb);
+    // F_n(T) = sum_k F_{n+k}(T_i) d^k / k!, nested: F_n + d (F_{n+1} + d/2 (F_{n+2} + ...)),
+    // in the table's precision
+    B dk[C::ORD + 1];
+#pragma unroll
+    for (int k = 1; k <= C::ORD; ++k) dk[k] = d * (B(1) / B(k));
+    const B *row = tab + i * boys_cols<B, L>();
+    T fac = pref * su;
+    T m2a = T(-2) * a;
+#pragma unroll
+    for (int n = 0; n <= L; ++n) {
+        B F = row[n + C::ORD];
+#pragma unroll
+        for (int k = C::ORD; k >= 1; --k) F = fma(F, dk[k], row[n + k - 1]);
+        Rn[n] = fac * (T)F;
+        fac *= m2a;
+    }
+}
+
 template <int L, typename T, typename B = T>
 __device__ __forceinline__ void aux_Rn(T r2, T p, T limp, T pf, T pref, T zeta2, T zeta, T limk,
                                        const B *__restrict__ tab, T (&Rn)[L + 1]) {
-    using C = BoysCfg<B>;
-    static_assert(boys_cols<B, L>() <= C::MT, "Boys table has too few columns for this L");
     if (r2 >= limp + limk) {
         T ri = rsq_fast(r2);
         T ri2 = ri * ri;
@@ -157,30 +187,7 @@ __device__ __forceinline__ void aux_Rn(T r2, T p, T limp, T pf, T pref, T zeta2,
 #pragma unroll
         for (int n = 1; n <= L; ++n) Rn[n] = T(-(2 * n - 1)) * ri2 * Rn[n - 1];
     } else {
-        // sqrt(u) = zeta / sqrt(zeta^2 + p), u = sqrt(u)^2, a = p u
-        T su = zeta * rsq_fast(zeta2 + p);
-        T u = su * su;
-        T a = p * u;
-        T tb = a * r2;
-        int i = (int)(tb * T(8) + T(0.5));
-        i = i < C::NROW - 1 ? i : C::NROW - 1;
-        const B d = (B)(T(i) * T(0.125) - tb);
-        // F_n(T) = sum_k F_{n+k}(T_i) d^k / k!, nested: F_n + d (F_{n+1} + d/2 (F_{n+2} + ...)),
-        // in the table's precision
-        B dk[C::ORD + 1];
-#pragma unroll
-        for (int k = 1; k <= C::ORD; ++k) dk[k] = d * (B(1) / B(k));
-        const B *row = tab + i * boys_cols<B, L>();
-        T fac = pref * su;
-        T m2a = T(-2) * a;
-#pragma unroll
-        for (int n = 0; n <= L; ++n) {
-            B F = row[n + C::ORD];
-#pragma unroll
-            for (int k = C::ORD; k >= 1; --k) F = fma(F, dk[k], row[n + k - 1]);
-            Rn[n] = fac * (T)F;
-            fac *= m2a;
-        }
+        aux_Rn_near<L, T, B>(r2, p, pref, zeta2, zeta, tab, Rn);
     }
 }
 
