@@ -52,6 +52,7 @@ void release_mol(pcm_mol *m) {
     m->m15.release();
     m->mtmp.release();
     m->ctmp.release();
+    m->pperm.release();
     m->okey.release();
     m->oval.release();
     m->osort.release();

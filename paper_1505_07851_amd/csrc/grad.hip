@@ -24,6 +24,7 @@
 struct GradPtsDesc {
     const unsigned char *rec;  // class records (header + D_tuv), padded to REC_PAD
     const void *pts;           // PtInt<T> [Mpad]
+    const int *pperm;          // point taken by each lane (null: surface order)
     double *part;              // partial rows [row][3][M]
     long long base;            // first item: (point tile, pair chunk), tile fastest
     int stride, n_pad, chunk, M, ntile, row0;
@@ -59,7 +60,8 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
         const PtInt<T> *__restrict__ pts = reinterpret_cast<const PtInt<T> *>(d.pts);
         const int M = d.M, stride = d.stride;
         const int k = tile * 256 + threadIdx.x;
-        const PtInt<T> me = pts[k < M ? k : M - 1];
+        const int kk = k < M ? (d.pperm ? d.pperm[k] : k) : M - 1;
+        const PtInt<T> me = pts[kk];
         const int p0 = ch * d.chunk;
         const int p1 = min(d.n_pad, p0 + d.chunk);
         double gx = 0.0, gy = 0.0, gz = 0.0, cc = 0.0;
@@ -254,10 +256,10 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
         }
         if (k < M) {
             const size_t base = (size_t)(d.row0 + ch) * (WC ? 4 : 3) * M;
-            d.part[base + k] = gx;
-            d.part[base + M + k] = gy;
-            d.part[base + 2 * M + k] = gz;
-            if constexpr (WC) d.part[base + 3 * M + k] = cc;
+            d.part[base + kk] = gx;
+            d.part[base + M + kk] = gy;
+            d.part[base + 2 * M + kk] = gz;
+            if constexpr (WC) d.part[base + 3 * M + kk] = cc;
         }
     }
 }
@@ -290,8 +292,8 @@ __global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds
         double V[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) V[t] = 0.0;
-        // FP64 records, V' up to order 2 or 3: the far-field factored sums of low_order.h
-        constexpr bool FS = sizeof(T) == 8 && (L == 1 || L == 2);
+        // FP64 records (V' up to order 1, 2 or 3): the far-field factored sums of low_order.h
+        constexpr bool FS = sizeof(T) == 8 && L <= 2;
         constexpr int NS = FS ? L + 1 : 2;
         double S[nsums<NS>()], ipf = 0.0;
         if constexpr (FS) {
@@ -807,6 +809,7 @@ static void grad_cterm(pcm_ctx *ctx, std::vector<GradJob> &jobs, ListSel ls, boo
             GradPtsDesc a{};
             a.rec = rec;
             a.pts = pts_of(mol);
+            a.pperm = mol->pperm.p;
             a.part = j.part_c;
             a.base = items_p;
             a.stride = stride;

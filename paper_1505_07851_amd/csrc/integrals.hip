@@ -38,6 +38,7 @@
 struct EspDesc {
     const unsigned char *rec;  // class records (header + D_tuv), padded to REC_PAD
     const void *pts;           // PtInt<T> [Mpad]
+    const int *pperm;          // point taken by each lane (null: surface order)
     double *part;              // partial rows of this molecule
     long long base;            // first item
     int M, stride, n_pad, chunk, ntile, row0;
@@ -78,7 +79,8 @@ __global__ __launch_bounds__(256) void k_esp(const EspDesc *__restrict__ ds, int
         const PtInt<T> *__restrict__ pts = reinterpret_cast<const PtInt<T> *>(d.pts);
         const int M = d.M, stride = d.stride;
         const int k = tile * 256 + threadIdx.x;
-        const PtInt<T> me = pts[k < M ? k : M - 1];
+        const int kk = k < M ? (d.pperm ? d.pperm[k] : k) : M - 1;
+        const PtInt<T> me = pts[kk];
         const int p0 = ch * d.chunk;
         const int p1 = min(d.n_pad, p0 + d.chunk);
         double acc = 0.0;
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(256) void k_esp(const EspDesc *__restrict__ ds, int
                 }
             }
         }
-        if (k < M) d.part[(size_t)(d.row0 + ch) * M + k] = acc;
+        if (k < M) d.part[(size_t)(d.row0 + ch) * M + kk] = acc;
     }
 }
 
@@ -252,9 +254,9 @@ __global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds,
         double V[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) V[t] = 0.0;
-        // FP64 records, V up to order 2 or 3: the far-field factored sums of low_order.h
-        constexpr bool FS = sizeof(T) == 8 && (L == 2 || L == 3);
-        constexpr int NS = FS ? L : 2;
+        // FP64 records (V up to order 1, 2 or 3): the far-field factored sums of low_order.h
+        constexpr bool FS = sizeof(T) == 8 && L >= 1 && L <= 3;
+        constexpr int NS = FS ? L : 2;  // L = 0 (V_000 alone) keeps its plain form
         double S[nsums<NS>()], ipf = 0.0;
         if constexpr (FS) {
 #pragma unroll
@@ -580,6 +582,7 @@ template <typename T> static EspDesc esp_desc(pcm_mol *mol, ListSel ls, int cl, 
     EspDesc d{};
     d.rec = pl.rec.p + pl.rec_off[cl];
     d.pts = points<T>(mol);
+    d.pperm = mol->pperm.p;
     d.part = mol->part.p;
     d.M = mol->M;
     d.stride = (int)rec_stride<T>(L);

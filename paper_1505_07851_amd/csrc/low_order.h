@@ -79,10 +79,12 @@ __device__ __forceinline__ void acc_V3(double q, T x, T y, T z, const T (&Rn)[4]
 // e.g. V_200 = pf (3 S2_xx - S1) and V_300 = pf (9 S2_x - 15 S3_xxx).  A far evaluation then
 // steps s_n = s_(n-1) / r^2 instead of forming R^(n) and multiplying each by q; a near one enters
 // the same sums with s_n = q R^(n) (-1)^n / ((2n-1)!! pf).  pf is applied once per item.
-// Sum layout (N = 2, 11 sums): S0, S1, S1_x, S1_y, S1_z, S2_xx, S2_xy, S2_xz, S2_yy, S2_yz, S2_zz;
+// Sum layout (N = 1, 5 sums): S0, S1, S1_x, S1_y, S1_z (S1 unused at this order);
+// N = 2 adds (11 sums): S2_xx, S2_xy, S2_xz, S2_yy, S2_yz, S2_zz;
 // N = 3 adds (24 sums): S2_x, S2_y, S2_z, S3_xxx, S3_xxy, S3_xxz, S3_xyy, S3_xyz, S3_xzz, S3_yyy,
 // S3_yyz, S3_yzz, S3_zzz.
-template <int N> __host__ __device__ constexpr int nsums() { return N == 2 ? 11 : 24; }
+template <int N> __host__ __device__ constexpr int nsums() { return N == 1 ? 5 : (N == 2 ? 11 : 24); }
+template <int N> __host__ __device__ constexpr int nvsum() { return N == 1 ? 4 : (N == 2 ? 10 : 20); }
 
 // s_0 .. s_N of one (pair, point) evaluation; (X, Y, Z) = P - C, ipf = 1 / pf (far_scale)
 template <int N, typename B>
@@ -115,60 +117,64 @@ template <int N>
 __device__ __forceinline__ void acc_S(const double (&s)[N + 1], double x, double y, double z,
                                       double (&S)[nsums<N>()]) {
     S[0] += s[0];
-    S[1] += s[1];
     S[2] = fma(s[1], x, S[2]);
     S[3] = fma(s[1], y, S[3]);
     S[4] = fma(s[1], z, S[4]);
-    const double ax = s[2] * x, ay = s[2] * y, az = s[2] * z;
-    S[5] = fma(ax, x, S[5]);
-    S[6] = fma(ax, y, S[6]);
-    S[7] = fma(ax, z, S[7]);
-    S[8] = fma(ay, y, S[8]);
-    S[9] = fma(ay, z, S[9]);
-    S[10] = fma(az, z, S[10]);
-    if constexpr (N == 3) {
-        S[11] += ax;
-        S[12] += ay;
-        S[13] += az;
-        const double bx = s[3] * x, by = s[3] * y, bz = s[3] * z;
-        const double bxx = bx * x, bxy = bx * y, byy = by * y, bzz = bz * z;
-        S[14] = fma(bxx, x, S[14]);
-        S[15] = fma(bxx, y, S[15]);
-        S[16] = fma(bxx, z, S[16]);
-        S[17] = fma(byy, x, S[17]);
-        S[18] = fma(bxy, z, S[18]);
-        S[19] = fma(bzz, x, S[19]);
-        S[20] = fma(byy, y, S[20]);
-        S[21] = fma(byy, z, S[21]);
-        S[22] = fma(bzz, y, S[22]);
-        S[23] = fma(bzz, z, S[23]);
+    if constexpr (N >= 2) {
+        S[1] += s[1];
+        const double ax = s[2] * x, ay = s[2] * y, az = s[2] * z;
+        S[5] = fma(ax, x, S[5]);
+        S[6] = fma(ax, y, S[6]);
+        S[7] = fma(ax, z, S[7]);
+        S[8] = fma(ay, y, S[8]);
+        S[9] = fma(ay, z, S[9]);
+        S[10] = fma(az, z, S[10]);
+        if constexpr (N == 3) {
+            S[11] += ax;
+            S[12] += ay;
+            S[13] += az;
+            const double bx = s[3] * x, by = s[3] * y, bz = s[3] * z;
+            const double bxx = bx * x, bxy = bx * y, byy = by * y, bzz = bz * z;
+            S[14] = fma(bxx, x, S[14]);
+            S[15] = fma(bxx, y, S[15]);
+            S[16] = fma(bxx, z, S[16]);
+            S[17] = fma(byy, x, S[17]);
+            S[18] = fma(bxy, z, S[18]);
+            S[19] = fma(bzz, x, S[19]);
+            S[20] = fma(byy, y, S[20]);
+            S[21] = fma(byy, z, S[21]);
+            S[22] = fma(bzz, y, S[22]);
+            S[23] = fma(bzz, z, S[23]);
+        }
     }
 }
 
 // V_tuv (the index order of acc_V2 / acc_V3) from the sums
 template <int N>
-__device__ __forceinline__ void fin_S(double pf, const double (&S)[nsums<N>()], double (&V)[N == 2 ? 10 : 20]) {
-    const double p3 = 3.0 * pf;
+__device__ __forceinline__ void fin_S(double pf, const double (&S)[nsums<N>()], double (&V)[nvsum<N>()]) {
     V[0] = pf * S[0];
     V[1] = -pf * S[2];
     V[2] = -pf * S[3];
     V[3] = -pf * S[4];
-    V[4] = pf * fma(3.0, S[5], -S[1]);
-    V[5] = p3 * S[6];
-    V[6] = p3 * S[7];
-    V[7] = pf * fma(3.0, S[8], -S[1]);
-    V[8] = p3 * S[9];
-    V[9] = pf * fma(3.0, S[10], -S[1]);
-    if constexpr (N == 3) {
-        V[10] = pf * fma(-15.0, S[14], 9.0 * S[11]);
-        V[11] = pf * fma(-15.0, S[15], 3.0 * S[12]);
-        V[12] = pf * fma(-15.0, S[16], 3.0 * S[13]);
-        V[13] = pf * fma(-15.0, S[17], 3.0 * S[11]);
-        V[14] = -15.0 * pf * S[18];
-        V[15] = pf * fma(-15.0, S[19], 3.0 * S[11]);
-        V[16] = pf * fma(-15.0, S[20], 9.0 * S[12]);
-        V[17] = pf * fma(-15.0, S[21], 3.0 * S[13]);
-        V[18] = pf * fma(-15.0, S[22], 3.0 * S[12]);
-        V[19] = pf * fma(-15.0, S[23], 9.0 * S[13]);
+    if constexpr (N >= 2) {
+        const double p3 = 3.0 * pf;
+        V[4] = pf * fma(3.0, S[5], -S[1]);
+        V[5] = p3 * S[6];
+        V[6] = p3 * S[7];
+        V[7] = pf * fma(3.0, S[8], -S[1]);
+        V[8] = p3 * S[9];
+        V[9] = pf * fma(3.0, S[10], -S[1]);
+        if constexpr (N == 3) {
+            V[10] = pf * fma(-15.0, S[14], 9.0 * S[11]);
+            V[11] = pf * fma(-15.0, S[15], 3.0 * S[12]);
+            V[12] = pf * fma(-15.0, S[16], 3.0 * S[13]);
+            V[13] = pf * fma(-15.0, S[17], 3.0 * S[11]);
+            V[14] = -15.0 * pf * S[18];
+            V[15] = pf * fma(-15.0, S[19], 3.0 * S[11]);
+            V[16] = pf * fma(-15.0, S[20], 9.0 * S[12]);
+            V[17] = pf * fma(-15.0, S[21], 3.0 * S[13]);
+            V[18] = pf * fma(-15.0, S[22], 3.0 * S[12]);
+            V[19] = pf * fma(-15.0, S[23], 9.0 * S[13]);
+        }
     }
 }

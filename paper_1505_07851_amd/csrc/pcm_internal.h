@@ -469,6 +469,7 @@ struct pcm_mol {
     DevBuf<int> c18;
     DevBuf<unsigned long long> mtmp;    // screening scratch of the precision splits [3 x candidates]
     DevBuf<int> ctmp;
+    DevBuf<int> pperm;                  // [M] point taken by each lane of the point-per-lane kernels
     DevBuf<unsigned> okey;              // pair-order sort scratch: keys in and out [2 x entries]
     DevBuf<int> oval;                   // class-local indexes to sort [entries]
     DevBuf<unsigned char> osort;        // radix sort temporary storage

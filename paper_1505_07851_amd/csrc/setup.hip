@@ -253,6 +253,55 @@ void surface_build(pcm_ctx *ctx, pcm_mol *mol, bool prune) {
     }
 }
 
+// Order in which the point-per-lane kernels take the surface points: along a Morton curve of
+// their positions (30 bits on a 1024^3 grid over the cavity), so that a wave's points are close
+// together and fewer waves take the near-field branch for a pair.  Results do not depend on it.
+__global__ void k_point_key(int M, const double *__restrict__ px, const double *__restrict__ py,
+                            const double *__restrict__ pz, double lox, double loy, double loz, double inv_cell,
+                            unsigned *__restrict__ key, int *__restrict__ val) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    const double r[3] = {px[k] - lox, py[k] - loy, pz[k] - loz};
+    unsigned m = 0;
+    for (int d = 0; d < 3; ++d) {
+        const int g = min(1023, max(0, (int)(r[d] * inv_cell)));
+        for (int bit = 0; bit < 10; ++bit) m |= (unsigned)((g >> bit) & 1) << (3 * bit + d);
+    }
+    key[k] = m;
+    val[k] = k;
+}
+
+static void points_order(pcm_ctx *ctx, pcm_mol *mol) {
+    const int M = mol->M;
+    mol->pperm.ensure(M + 1);
+    if (M <= 0) return;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, rmax = 0.0;
+    for (int i = 0; i < mol->N; ++i) {
+        rmax = std::max(rmax, mol->h_rad[i]);
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], mol->h_xyz[3 * i + d]);
+            hi[d] = std::max(hi[d], mol->h_xyz[3 * i + d]);
+        }
+    }
+    const double pad = 2.0 * rmax + 1.0;  // covers points moved or given explicitly nearby
+    for (int d = 0; d < 3; ++d) {
+        lo[d] -= pad;
+        hi[d] += pad;
+    }
+    const double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]});
+    mol->okey.ensure(2 * (size_t)M);
+    mol->oval.ensure(M);
+    k_point_key<<<div_up(M, 256), 256, 0, ctx->stream>>>(M, mol->px.p, mol->py.p, mol->pz.p, lo[0], lo[1], lo[2],
+                                                         1023.999 / ext, mol->okey.p, mol->oval.p);
+    HIP_LAUNCH_OK();
+    size_t bytes = 0;
+    HIP_OK(rocprim::radix_sort_pairs(nullptr, bytes, mol->okey.p, mol->okey.p + M, mol->oval.p, mol->pperm.p, M, 0,
+                                     30, ctx->stream));
+    mol->osort.ensure(bytes + 1);
+    HIP_OK(rocprim::radix_sort_pairs(mol->osort.p, bytes, mol->okey.p, mol->okey.p + M, mol->oval.p, mol->pperm.p,
+                                     M, 0, 30, ctx->stream));
+}
+
 void surface_points(pcm_ctx *ctx, pcm_mol *mol, const double *r_explicit_dev) {
     const int T = 256;
     k_surface_points<<<grid_for(mol->Mpad, T), T, 0, ctx->stream>>>(
@@ -261,6 +310,7 @@ void surface_points(pcm_ctx *ctx, pcm_mol *mol, const double *r_explicit_dev) {
         mol->Mpad, reinterpret_cast<PtInt<double> *>(mol->pti64.p), reinterpret_cast<PtInt<float> *>(mol->pti32.p),
         mol->qpad.p);
     HIP_LAUNCH_OK();
+    points_order(ctx, mol);
 }
 
 // ----------------------------------------------------------------------------------------
