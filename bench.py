@@ -91,16 +91,18 @@ def hermite_flops():
 
 # FP64 flops (FMA = 2, 1/sqrt = 1) per (primitive pair x point) evaluation of the kernels that
 # contract the auxiliary R^(n) in factored form (L <= 3), counted from the far-field branch of
-# their source: the common part 13 + 2N (P - C 3, r^2 5, far test 2, 1/sqrt 1, r^-2 1, R^(0) 1,
-# R^(n) 2 each up to N) plus the kernel's contraction and accumulation.
+# their source.  Point side: the common part 13 + 2N (P - C 3, r^2 5, far test 2, 1/sqrt 1,
+# r^-2 1, R^(0) 1, R^(n) 2 each up to N) plus the contraction and accumulation.  Pair side with
+# FP64 records (V up to order N >= 1): the far-field factored sums, 12 (P - C 3, r^2 5, far
+# test 2, 1/sqrt 1, r^-2 1) + s_0 .. s_N (N + 1) + the sums: 7 (N = 1), 23 (N = 2), 53 (N = 3).
 #   point side, c only (N = L):               esp_L          15  24  45  87
 #   point side, dc (N = L + 1):               grad_pts_L     22  37  75 156
 #   point side, c and dc:                     esp_grad_pts_L 24  41  81 164
-#   pair side, V up to L (N = L):             fock_v_L       15  24  45  87
-#   pair side, V' up to L + 1 (N = L + 1):    grad_v_L       24  45  87
-#                                             fock_grad_v_L  24  45  87
+#   pair side, V up to L (N = L):             fock_v_L       15  21  38  69
+#   pair side, V' up to L + 1 (N = L + 1):    grad_v_L       21  38  69
+#                                             fock_grad_v_L  21  38  69
 FACTORED = {"esp": (15, 24, 45, 87), "grad_pts": (22, 37, 75, 156), "esp_grad_pts": (24, 41, 81, 164),
-            "fock_v": (15, 24, 45, 87), "grad_v": (24, 45, 87), "fock_grad_v": (24, 45, 87)}
+            "fock_v": (15, 21, 38, 69), "grad_v": (21, 38, 69), "fock_grad_v": (21, 38, 69)}
 
 
 def flop_model():
@@ -514,7 +516,11 @@ def bench_nearfar(args):
     """Share of (primitive pair, point) evaluations in the near field (T = p z^2/(p + z^2) r^2 below
     40, the FP64 Boys-table range) per class, for the Eq. 18 and Eq. 15 lists of the 600-atom
     protein, counted over a seeded sample of surface points (all pairs each).  The far field is the
-    asymptotic branch of the integral kernels."""
+    asymptotic branch of the integral kernels.  A wave of 64 lanes takes the near branch when any
+    lane needs it, so for the Eq. 18 list the share of wave evaluations that do is reported too:
+    pair side (64 pairs x one sampled point) with the pairs in list order and in the kernels' order
+    (exponent octave, then a Morton curve of the product centre), point side (64 points x one pair,
+    48 sampled point waves) with the points in surface order and in the kernels' Morton order."""
     import numpy as np
     import torch
 
@@ -540,6 +546,46 @@ def bench_nearfar(args):
     xyz = torch.tensor(s.xyz, dtype=torch.float64, device="cuda")
     names = ["ss", "sp", "sd", "pp", "pd", "dd"]
     out = {"workload": "nearfar_protein600", "sample_points": int(kidx.numel()), "M": mol.M, "T_far": 40.0}
+
+    def morton(g, bits):
+        code = torch.zeros(g.shape[0], dtype=torch.int64, device="cuda")
+        for bit in range(bits):
+            for ax in range(3):
+                code |= ((g[:, ax] >> bit) & 1) << (3 * bit + ax)
+        return code
+
+    def near_of(Pc, p, rr, zz):
+        d2 = ((Pc[:, None, :] - rr[None, :, :]) ** 2).sum(-1)
+        return p[:, None] * zz[None, :] / (p[:, None] + zz[None, :]) * d2 < 40.0
+
+    def pair_wave_share(Pc, p):
+        n = Pc.shape[0]
+        nw = (n + 63) // 64
+        hit = 0
+        for k0 in range(0, r.shape[0], 64):
+            nr = near_of(Pc, p, r[k0:k0 + 64], z2[k0:k0 + 64])
+            nr = torch.cat([nr, torch.zeros(nw * 64 - n, nr.shape[1], dtype=torch.bool, device="cuda")])
+            hit += int(nr.view(nw, 64, -1).any(1).sum().item())
+        return hit / (nw * r.shape[0])
+
+    # the kernels' orders (the same keys as the library's device sorts)
+    lo = xyz.min(0).values
+    ext = max(float((xyz.max(0).values - lo).max()), 1.0)
+    rad = torch.tensor(s.radius, dtype=torch.float64, device="cuda")
+    plo = lo - (2.0 * float(rad.max()) + 1.0)
+    pext = ext + 2.0 * (2.0 * float(rad.max()) + 1.0)
+    rall, zall = sf["r"], sf["zeta"] ** 2
+    gp = ((rall - plo) * (1023.999 / pext)).long().clamp(0, 1023)
+    porder = torch.argsort(morton(gp, 10), stable=True)
+    wsel = np.sort(rng.choice(mol.M // 64, min(48, mol.M // 64), replace=False))
+
+    def point_wave_share(Pc, p, order):
+        hit = 0
+        for w in wsel:
+            kk = order[int(w) * 64:int(w) * 64 + 64]
+            hit += int(near_of(Pc, p, rall[kk], zall[kk]).any(1).sum().item())
+        return hit / (Pc.shape[0] * len(wsel))
+
     for which, label in ((1, "eq18_list"), (0, "eq15_list")):
         pl = mol.pair_list(which)
         cls = torch.tensor(pl["cls"], device="cuda")
@@ -557,11 +603,20 @@ def bench_nearfar(args):
                 continue
             near = 0
             for k0 in range(0, r.shape[0], 64):
-                d2 = ((Pc[sel][:, None, :] - r[None, k0:k0 + 64, :]) ** 2).sum(-1)
-                pz = p[sel][:, None] * z2[None, k0:k0 + 64]
-                T = pz / (p[sel][:, None] + z2[None, k0:k0 + 64]) * d2
-                near += int((T < 40.0).sum().item())
+                near += int(near_of(Pc[sel], p[sel], r[k0:k0 + 64], z2[k0:k0 + 64]).sum().item())
             res[names[c]] = {"prim_pairs": n, "near_fraction": round(near / (n * r.shape[0]), 5)}
+            if which == 1:
+                Pcs, ps = Pc[sel], p[sel]
+                g = ((Pcs - lo) * (255.999 / ext)).long().clamp(0, 255)
+                octv = (torch.floor(torch.log2(ps)).long() + 2).clamp(0, 15)
+                o = torch.argsort((octv << 24) | morton(g, 8), stable=True)
+                res[names[c]].update({
+                    "pair_side_wave_near_list_order": round(pair_wave_share(Pcs, ps), 4),
+                    "pair_side_wave_near_kernel_order": round(pair_wave_share(Pcs[o], ps[o]), 4),
+                    "point_side_wave_near_surface_order": round(point_wave_share(Pcs, ps, torch.arange(
+                        mol.M, device="cuda")), 4),
+                    "point_side_wave_near_kernel_order": round(point_wave_share(Pcs, ps, porder), 4)})
+            log(f"[bench] nearfar {label} {names[c]}: {res[names[c]]}")
         out[label] = res
     print(json.dumps(out))
 

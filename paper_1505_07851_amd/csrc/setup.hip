@@ -115,11 +115,8 @@ static void scan_rec(pcm_ctx *ctx, const int *in, int *out, long long n, int *tm
     HIP_LAUNCH_OK();
 }
 
-void scan_exclusive(pcm_ctx *ctx, pcm_mol *mol, const int *in, int *out, long long n, long long *total) {
-    if (n <= 0) {
-        if (total) *total = 0;
-        return;
-    }
+// exclusive prefix sum on the stream; returns the device address of the total (n >= 1)
+static int *scan_exclusive_dev(pcm_ctx *ctx, pcm_mol *mol, const int *in, int *out, long long n) {
     long long need = 16, m = n;
     while (m > 1) {
         m = (m + SCAN_B - 1) / SCAN_B;
@@ -128,6 +125,15 @@ void scan_exclusive(pcm_ctx *ctx, pcm_mol *mol, const int *in, int *out, long lo
     mol->scan_tmp.ensure(need + 1);
     int *tot = mol->scan_tmp.p + need;
     scan_rec(ctx, in, out, n, mol->scan_tmp.p, tot);
+    return tot;
+}
+
+void scan_exclusive(pcm_ctx *ctx, pcm_mol *mol, const int *in, int *out, long long n, long long *total) {
+    if (n <= 0) {
+        if (total) *total = 0;
+        return;
+    }
+    int *tot = scan_exclusive_dev(ctx, mol, in, out, n);
     if (total) {
         int t = 0;
         HIP_OK(hipMemcpyAsync(&t, tot, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
@@ -420,26 +426,6 @@ __global__ void k_screen_write(int nsp, const unsigned long long *__restrict__ m
         }
 }
 
-__global__ void k_count_sp(int nsp, const int *__restrict__ cnt, const long long *__restrict__ cls_sp_off,
-                           int *__restrict__ out /* [NCLS], zeroed */) {
-    // shell pairs with survivors per class: blockIdx.y = class, grid-stride over its shell pairs;
-    // integer sums, so the result does not depend on the order of the atomic adds
-    __shared__ int s[256];
-    const int c = blockIdx.y;
-    const long long b0 = cls_sp_off[c], b1 = cls_sp_off[c + 1];
-    int acc = 0;
-    for (long long sp = b0 + (long long)blockIdx.x * blockDim.x + threadIdx.x; sp < b1;
-         sp += (long long)gridDim.x * blockDim.x)
-        acc += cnt[sp] > 0;
-    s[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && s[0]) atomicAdd(out + c, s[0]);
-}
-
 __global__ void k_zero_int(int *__restrict__ p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -515,48 +501,60 @@ static void pairs_order(pcm_ctx *ctx, pcm_mol *mol, PairList &pl) {
                                      0, 31, ctx->stream));
 }
 
+// Per-class metadata of a compacted list in one launch (grid (64, NCLS)): the shell pairs with
+// survivors per class (blockIdx.y = class, integer atomics into out[0 .. NCLS), zeroed before, so the
+// sums do not depend on their order) and, from block (0, 0), the entry offset of every class boundary
+// (out[NCLS .. 2 NCLS]) and the terminating offset spo[nsp] = total.
+__global__ void k_list_meta(int nsp, const int *__restrict__ cnt, int *__restrict__ spo, ClsBounds cb,
+                            const int *__restrict__ total, int *__restrict__ out) {
+    __shared__ int s[256];
+    const int c = blockIdx.y;
+    const long long b0 = cb.o[c], b1 = cb.o[c + 1];
+    int acc = 0;
+    for (long long sp = b0 + (long long)blockIdx.x * blockDim.x + threadIdx.x; sp < b1;
+         sp += (long long)gridDim.x * blockDim.x)
+        acc += cnt[sp] > 0;
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && s[0]) atomicAdd(out + c, s[0]);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x <= NCLS) {
+        const long long sb = cb.o[threadIdx.x];
+        out[NCLS + threadIdx.x] = sb >= nsp ? *total : spo[sb];
+        if (threadIdx.x == 0) spo[nsp] = *total;
+    }
+}
+
 // entries, per-shell-pair offsets and class offsets of a list from its survivor masks and counts
+// (one readback of the class metadata per list)
 static void pairs_compact(pcm_ctx *ctx, pcm_mol *mol, PairList &pl) {
     const long long nsp = mol->sp_cls_off[NCLS];
     const int T = 256;
-    long long total = 0;
-    scan_exclusive(ctx, mol, pl.cnt.p, pl.spo.p, nsp, &total);
-    if (total > 2000000000LL) throw PcmError{PCM_E_ALLOC, "screened pair list exceeds 2^31 entries"};
-    pl.n = total;
-    // class offsets: spo at the class boundaries
-    std::vector<int> bnd(NCLS + 1, 0);
-    for (int c = 0; c <= NCLS; ++c) {
-        long long s = mol->sp_cls_off[c];
-        if (s >= nsp) {
-            bnd[c] = (int)total;
-        } else {
-            HIP_OK(hipMemcpyAsync(&bnd[c], pl.spo.p + s, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-        }
-    }
-    // shell-pair survivor counts per class
-    std::vector<int> spc(NCLS, 0);
+    int meta[2 * NCLS + 1] = {0};
     if (nsp > 0) {
-        HIP_OK(hipMemcpyAsync(ctx->lscal.p, mol->sp_cls_off, sizeof(long long) * (NCLS + 1), hipMemcpyHostToDevice,
-                              ctx->stream));
-        k_zero_int<<<1, 64, 0, ctx->stream>>>(ctx->iscal.p, NCLS);
+        const int *tot = scan_exclusive_dev(ctx, mol, pl.cnt.p, pl.spo.p, nsp);
+        ClsBounds cb;
+        for (int c = 0; c <= NCLS; ++c) cb.o[c] = mol->sp_cls_off[c];
+        k_zero_int<<<1, 64, 0, ctx->stream>>>(ctx->iscal.p, 2 * NCLS + 1);
         HIP_LAUNCH_OK();
-        k_count_sp<<<dim3(64, NCLS), 256, 0, ctx->stream>>>((int)nsp, pl.cnt.p, ctx->lscal.p, ctx->iscal.p);
+        k_list_meta<<<dim3(64, NCLS), 256, 0, ctx->stream>>>((int)nsp, pl.cnt.p, pl.spo.p, cb, tot, ctx->iscal.p);
         HIP_LAUNCH_OK();
-        HIP_OK(hipMemcpyAsync(spc.data(), ctx->iscal.p, sizeof(int) * NCLS, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipMemcpyAsync(meta, ctx->iscal.p, sizeof(meta), hipMemcpyDeviceToHost, ctx->stream));
         HIP_OK(hipStreamSynchronize(ctx->stream));
     }
-    HIP_OK(hipStreamSynchronize(ctx->stream));
-    for (int c = 0; c <= NCLS; ++c) pl.cls_off[c] = bnd[c];
-    for (int c = 0; c < NCLS; ++c) pl.sp_count[c] = spc[c];
+    const long long total = meta[2 * NCLS];
+    if (total < 0 || total > 2000000000LL) throw PcmError{PCM_E_ALLOC, "screened pair list exceeds 2^31 entries"};
+    pl.n = total;
+    for (int c = 0; c <= NCLS; ++c) pl.cls_off[c] = meta[NCLS + c];
+    for (int c = 0; c < NCLS; ++c) pl.sp_count[c] = meta[c];
     pl.ent_sp.ensure(total + 1);
     pl.ent_ij.ensure(total + 1);
     if (nsp > 0) {
         k_screen_write<<<div_up(nsp, T), T, 0, ctx->stream>>>((int)nsp, pl.mask.p, pl.spo.p, pl.ent_sp.p, pl.ent_ij.p);
         HIP_LAUNCH_OK();
-        // terminating offset for per-shell-pair ranges: spo[nsp] = total
-        int t = (int)total;
-        HIP_OK(hipMemcpyAsync(pl.spo.p + nsp, &t, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
-        HIP_OK(hipStreamSynchronize(ctx->stream));
     }
     pairs_order(ctx, mol, pl);
 }
@@ -597,7 +595,6 @@ void pairs_split(pcm_ctx *ctx, pcm_mol *mol, PairList &pl, PairList &weak, const
         k_mask_split<<<div_up(nsp, 256), 256, 0, ctx->stream>>>((int)nsp, mol->mtmp.p, pl.mask.p, pl.cnt.p,
                                                                 weak.mask.p, weak.cnt.p);
         HIP_LAUNCH_OK();
-        HIP_OK(hipStreamSynchronize(ctx->stream));
     }
     pairs_compact(ctx, mol, pl);
     pairs_compact(ctx, mol, weak);
@@ -852,7 +849,6 @@ void pairs_merged_build(pcm_ctx *ctx, pcm_mol *mol, const double *P, bool dynami
             HIP_LAUNCH_OK();
             k_mask_split<<<g, 256, 0, ctx->stream>>>((int)nsp, s3, fo.mask.p, fo.cnt.p, fow.mask.p, fow.cnt.p);
             HIP_LAUNCH_OK();
-            HIP_OK(hipStreamSynchronize(ctx->stream));
         }
     }
     for (PairList *l : {&fg, &fo}) {

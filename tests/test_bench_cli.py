@@ -31,7 +31,9 @@ def test_flop_model():
     assert m["matvec"] == 14
     # factored kernels: the common far-field part 13 + 2N, then the contraction as written
     assert m["esp_L0"] == 13 + 0 + 2            # one FMA D_0 R^(0)
-    assert m["fock_v_L1"] == 13 + 2 + 1 + 2 + 6  # q R^(1), then V_0 and three V_i by FMA
+    # pair side, far-field factored sums: 12 + s_0, s_1, then S_0 and three S_1i by FMA
+    assert m["fock_v_L1"] == 12 + 2 + 1 + 6
+    assert m["fock_grad_v_L1"] == 12 + 3 + 1 + 6 + 1 + 3 + 12  # + S_1, three s_2 X_i, six S_2ij by FMA
     assert m["esp_grad_pts_L0"] == m["grad_pts_L0"] + 2  # the potential's FMA beside the derivative
     for fam, counts in bench.FACTORED.items():
         assert [m[f"{fam}_L{L}"] for L in range(len(counts))] == list(counts), fam
