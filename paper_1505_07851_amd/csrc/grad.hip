@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds
         if (ip < n_pairs) {
             double *o = d.vout + (size_t)ch * NT * n_pairs;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) o[(size_t)t * n_pairs + ipp] = V[t];
+            for (int t = 0; t < NT; ++t) o[(size_t)t * n_pairs + ip] = V[t];
         }
     }
 }
@@ -368,10 +368,12 @@ __global__ __launch_bounds__(64) void k_grad_contract(long long n, int nch, cons
                                 const int *__restrict__ cnoff, const double *__restrict__ pexp,
                                 const double *__restrict__ cn, const double *__restrict__ xyz,
                                 const double *__restrict__ P, int nbf, double *__restrict__ gpair,
-                                const unsigned long long *__restrict__ memb) {
+                                const unsigned long long *__restrict__ memb, const int *__restrict__ vperm) {
     constexpr int L = LA + LB, NT = ntuv(L + 1);
-    long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
+    // thread = slot of the pair order (V' is stored by slot), q = its list entry (null: the same)
+    const long long qs = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (qs >= n) return;
+    const long long q = vperm ? vperm[qs] : qs;
     if (memb && !((memb[ent_sp[q]] >> ent_ij[q]) & 1ull)) {  // entry of a merged list outside this term's list
         for (int d = 0; d < 6; ++d) gpair[(size_t)q * 6 + d] = 0.0;
         return;
@@ -380,7 +382,7 @@ __global__ __launch_bounds__(64) void k_grad_contract(long long n, int nch, cons
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         double s = 0.0;
-        for (int c = 0; c < nch; ++c) s += vin[((size_t)c * NT + t) * n + q];
+        for (int c = 0; c < nch; ++c) s += vin[((size_t)c * NT + t) * n + qs];
         V[t] = s;
     }
     int sp = ent_sp[q], ij = ent_ij[q];
@@ -458,7 +460,7 @@ __global__ __launch_bounds__(64 * GCW_WAVES) void k_grad_contract_w(
     const int *__restrict__ snp, const int *__restrict__ soff, const int *__restrict__ satom,
     const int *__restrict__ bfo, const int *__restrict__ cnoff, const double *__restrict__ pexp,
     const double *__restrict__ cn, const double *__restrict__ xyz, const double *__restrict__ P, int nbf,
-    double *__restrict__ gpair, const unsigned long long *__restrict__ memb) {
+    double *__restrict__ gpair, const unsigned long long *__restrict__ memb, const int *__restrict__ vperm) {
     constexpr int L = LA + LB, NT = ntuv(L + 1), IM = LA + 1, JM = LB + 1, TS = IM + JM + 1;
     constexpr int ES = herm1d_size<IM, JM>(), NA = ncart(LA), NB = ncart(LB);
     static_assert(NA * NB <= 64, "one lane per product of Cartesian components");
@@ -466,9 +468,10 @@ __global__ __launch_bounds__(64 * GCW_WAVES) void k_grad_contract_w(
     __shared__ double sE[GCW_WAVES][3][ES];
     __shared__ double sG[GCW_WAVES][6][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const long long q = (long long)blockIdx.x * GCW_WAVES + w;
+    const long long qs = (long long)blockIdx.x * GCW_WAVES + w;  // slot of the pair order
+    const long long q = qs < n && vperm ? vperm[qs] : qs;          // its list entry
     // an entry of a merged list outside this term's list contributes zeros
-    const bool valid = q < n && (!memb || ((memb[ent_sp[q]] >> ent_ij[q]) & 1ull));
+    const bool valid = qs < n && (!memb || ((memb[ent_sp[q]] >> ent_ij[q]) & 1ull));
     int a = 0, b = 0, i = 0, j = 0;
     double ea = 0.0, eb = 0.0;
     if (valid) {
@@ -481,7 +484,7 @@ __global__ __launch_bounds__(64 * GCW_WAVES) void k_grad_contract_w(
         eb = pexp[soff[b] + j];
         if (lane < NT) {
             double acc = 0.0;
-            for (int c = 0; c < nch; ++c) acc += vin[((size_t)c * NT + lane) * n + q];
+            for (int c = 0; c < nch; ++c) acc += vin[((size_t)c * NT + lane) * n + qs];
             sV[w][lane] = acc;
         }
         if (lane < 3) {
@@ -539,7 +542,7 @@ __global__ __launch_bounds__(64 * GCW_WAVES) void k_grad_contract_w(
 #pragma unroll
     for (int d = 0; d < 6; ++d) sG[w][d][lane] = g[d];
     __syncthreads();
-    if (q < n && lane < 6) {
+    if (qs < n && lane < 6) {
         double acc = 0.0;
         for (int l = 0; l < NA * NB; ++l) acc += sG[w][lane][l];
         gpair[(size_t)q * 6 + lane] = acc;
@@ -891,6 +894,7 @@ static void grad_cterm(pcm_ctx *ctx, std::vector<GradJob> &jobs, ListSel ls, boo
             }
             const int nch = div_up(mol->Mpad, chunk_v[i][cl]);
             const int *es = pl.ent_sp.p + pl.cls_off[cl], *ei = pl.ent_ij.p + pl.cls_off[cl];
+            const int *vp = pair_order(pl, cl);
             const int g = div_up(n, 64);
             const double *P = j.P;
             ProfScope ps2(ctx, "grad_contract", (double)n);
@@ -899,13 +903,13 @@ static void grad_cterm(pcm_ctx *ctx, std::vector<GradJob> &jobs, ListSel ls, boo
         k_grad_contract<LA_, LB_><<<g, 64, 0, ctx->stream>>>(n, nch, mol->vbuf.p, es, ei, mol->spa.p, mol->spb.p,  \
                                                              mol->snp.p, mol->soff.p, mol->satom.p, mol->bfo.p,    \
                                                              mol->cnoff.p, mol->pexp.p, mol->cn.p, mol->xyz.p,     \
-                                                             P, mol->nbf, mol->gpair.p, nullptr);                      \
+                                                             P, mol->nbf, mol->gpair.p, nullptr, vp);                  \
         break;
 #define GCW_CASE(CI, LA_, LB_)                                                                                     \
     case CI:                                                                                                       \
         k_grad_contract_w<LA_, LB_><<<div_up(n, GCW_WAVES), 64 * GCW_WAVES, 0, ctx->stream>>>(                      \
             n, nch, mol->vbuf.p, es, ei, mol->spa.p, mol->spb.p, mol->snp.p, mol->soff.p, mol->satom.p, mol->bfo.p, \
-            mol->cnoff.p, mol->pexp.p, mol->cn.p, mol->xyz.p, P, mol->nbf, mol->gpair.p, nullptr);                  \
+            mol->cnoff.p, mol->pexp.p, mol->cn.p, mol->xyz.p, P, mol->nbf, mol->gpair.p, nullptr, vp);              \
         break;
             switch (cl) {
                 GC_CASE(0, 0, 0)
@@ -1094,19 +1098,20 @@ static void fock_grad_pairs(pcm_ctx *ctx, pcm_mol *mol, const double *P, double 
         }
         fock_contract_scatter(ctx, mol, pl, cl, mol->vbuf.p, nch, ntuv(L + 1), mol->m15.p, F);
         const int *es = pl.ent_sp.p + pl.cls_off[cl], *ei = pl.ent_ij.p + pl.cls_off[cl];
+        const int *vp = pair_order(pl, cl);
         const unsigned long long *memb = mol->m18.p;
         ProfScope ps2(ctx, "grad_contract", (double)n);
 #define GC_CASE(CI, LA_, LB_)                                                                                      \
     case CI:                                                                                                       \
         k_grad_contract<LA_, LB_><<<div_up(n, 64), 64, 0, ctx->stream>>>(                                          \
             n, nch, mol->vbuf.p, es, ei, mol->spa.p, mol->spb.p, mol->snp.p, mol->soff.p, mol->satom.p, mol->bfo.p, \
-            mol->cnoff.p, mol->pexp.p, mol->cn.p, mol->xyz.p, P, mol->nbf, mol->gpair.p, memb);                     \
+            mol->cnoff.p, mol->pexp.p, mol->cn.p, mol->xyz.p, P, mol->nbf, mol->gpair.p, memb, vp);                 \
         break;
 #define GCW_CASE(CI, LA_, LB_)                                                                                     \
     case CI:                                                                                                       \
         k_grad_contract_w<LA_, LB_><<<div_up(n, GCW_WAVES), 64 * GCW_WAVES, 0, ctx->stream>>>(                      \
             n, nch, mol->vbuf.p, es, ei, mol->spa.p, mol->spb.p, mol->snp.p, mol->soff.p, mol->satom.p, mol->bfo.p, \
-            mol->cnoff.p, mol->pexp.p, mol->cn.p, mol->xyz.p, P, mol->nbf, mol->gpair.p, memb);                     \
+            mol->cnoff.p, mol->pexp.p, mol->cn.p, mol->xyz.p, P, mol->nbf, mol->gpair.p, memb, vp);                 \
         break;
         switch (cl) {
             GC_CASE(0, 0, 0)

@@ -316,7 +316,7 @@ __global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds,
         if (ip < n) {
             double *o = d.vout + (size_t)ch * NT * n;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) o[(size_t)t * n + ipp] = V[t];
+            for (int t = 0; t < NT; ++t) o[(size_t)t * n + ip] = V[t];
         }
     }
 }
@@ -332,7 +332,8 @@ struct FockCDesc {
     int vnt;                          // V entries per (chunk, pair): ntuv(L), or ntuv(L+1) for V' of the gradient
     const unsigned long long *memb;   // null, or per candidate shell pair the bits of this term's list: an
                                       // entry of a merged list without its bit gets a zero block
-    const double *vin;
+    const double *vin;                // V by slot of the pair order (vperm), else by list entry
+    const int *vperm;                 // slot -> class-local list entry (null: the identity)
     const int *es, *ei, *spo, *spa, *spb, *snp, *soff, *satom, *cnoff, *bfo;
     const double *pexp, *cn, *xyz;
     double *fprim, *F;
@@ -355,7 +356,8 @@ __global__ void k_fock_contract(const FockCDesc *__restrict__ ds, int nd, long l
     const long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (it >= total) return;
     const FockCDesc &d = ds[find_desc(ds, nd, it)];
-    const long long q = it - d.base, n = d.n;
+    const long long qs = it - d.base, n = d.n;  // slot of the pair order
+    const long long q = d.vperm ? d.vperm[qs] : qs;
     int sp = d.es[q], ij = d.ei[q];
     if (d.memb && !((d.memb[sp] >> ij) & 1ull)) {
         for (int c = 0; c < NC; ++c) d.fprim[(size_t)q * NC + c] = 0.0;
@@ -364,7 +366,7 @@ __global__ void k_fock_contract(const FockCDesc *__restrict__ ds, int nd, long l
     double V[NT];
     for (int t = 0; t < NT; ++t) {
         double s = 0.0;
-        for (int c = 0; c < d.nch; ++c) s += d.vin[((size_t)c * d.vnt + t) * n + q];
+        for (int c = 0; c < d.nch; ++c) s += d.vin[((size_t)c * d.vnt + t) * n + qs];
         V[t] = s;
     }
     int a = d.spa[sp], b = d.spb[sp], i = ij >> 3, j = ij & 7;
@@ -409,7 +411,8 @@ __global__ __launch_bounds__(64 * FCW_WAVES) void k_fock_contract_w(const FockCD
     const long long it = (long long)blockIdx.x * FCW_WAVES + w;
     const bool in_range = it < total;
     const FockCDesc &d = ds[in_range ? find_desc(ds, nd, it) : 0];
-    const long long q = it - d.base, n = d.n;
+    const long long qs = it - d.base, n = d.n;  // slot of the pair order
+    const long long q = in_range && d.vperm ? d.vperm[qs] : qs;
     const bool valid = in_range && (!d.memb || ((d.memb[d.es[q]] >> d.ei[q]) & 1ull));
     int a = 0, b = 0, i = 0, j = 0;
     if (valid) {
@@ -420,7 +423,7 @@ __global__ __launch_bounds__(64 * FCW_WAVES) void k_fock_contract_w(const FockCD
         j = ij & 7;
         if (lane < NT) {
             double acc = 0.0;
-            for (int c = 0; c < d.nch; ++c) acc += d.vin[((size_t)c * d.vnt + lane) * n + q];
+            for (int c = 0; c < d.nch; ++c) acc += d.vin[((size_t)c * d.vnt + lane) * n + qs];
             sV[w][lane] = acc;
         }
         if (lane < 3) {
@@ -885,6 +888,7 @@ static void fock_batch_plan(pcm_ctx *ctx, const std::vector<pcm_mol *> &mols, co
             d.vnt = ntuv(CLS_LA[cl] + CLS_LB[cl]);
             d.memb = nullptr;
             d.vin = mol->vbuf.p;
+            d.vperm = pair_order(pl, cl);
             d.es = pl.ent_sp.p + pl.cls_off[cl];
             d.ei = pl.ent_ij.p + pl.cls_off[cl];
             d.spo = pl.spo.p;
@@ -1029,6 +1033,7 @@ void fock_contract_scatter(pcm_ctx *ctx, pcm_mol *mol, const PairList &pl, int c
     d.vnt = vnt;
     d.memb = memb;
     d.vin = vin;
+    d.vperm = pair_order(pl, cl);
     d.es = pl.ent_sp.p + pl.cls_off[cl];
     d.ei = pl.ent_ij.p + pl.cls_off[cl];
     d.spo = pl.spo.p;

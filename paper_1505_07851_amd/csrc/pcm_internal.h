@@ -413,10 +413,12 @@ struct PairList {
     DevBuf<int> ent_sp, ent_ij;       // [n] candidate shell pair index, i*8+j
     DevBuf<unsigned char> rec;        // pair records (type and stride depend on use)
     size_t rec_off[NCLS + 1] = {0};   // byte offsets of each class in rec
-    // [n] per class, the class-local record index each lane of a pair-per-lane kernel takes (it
-    // writes its sums back at that index): the records grouped by exponent, then along a Morton
-    // curve of the product centre, so that a wave's pairs are alike in p and close together and
-    // the near-field branch is taken by fewer waves.  Results do not depend on this order.
+    // [n] per class, the class-local record index each lane of a pair-per-lane kernel takes: the
+    // records grouped by exponent, then along a Morton curve of the product centre, so that a
+    // wave's pairs are alike in p and close together and the near-field branch is taken by fewer
+    // waves.  The kernels write their per-pair sums in this order (slot = lane), and the
+    // contraction kernels that read them walk the same slots and write per list entry.  Results
+    // do not depend on this order.
     DevBuf<int> vperm;
 };
 
