@@ -186,9 +186,10 @@ def main():
                     help="copy: a plain device copy of known size, to calibrate rocprofv3 byte counters")
     ap.add_argument("--max-iter-none", type=int, default=300,
                     help="stress2000: matvec budget of each unpreconditioned outer solve")
-    ap.add_argument("--seeds", type=int, default=20, help="scf_policies: RBJ seeds per block size")
+    ap.add_argument("--seeds", type=int, default=20,
+                    help="scf_policies, and rbj_blocks on protein2000: RBJ seeds per block size")
     ap.add_argument("--scf-system", default="protein600", choices=["protein600", "protein2000"],
-                    help="scf_policies: the 600-atom solute (M ~ 30k) or the 2,000-atom one (M ~ 150k)")
+                    help="scf_policies and rbj_blocks: the 600-atom solute (M ~ 30k) or the 2,000-atom one (M ~ 150k)")
     args = ap.parse_args()
     if args.block is None:
         args.block = 100 if args.workload == "conformers64" else 512
@@ -622,11 +623,13 @@ def bench_nearfar(args):
 
 
 def bench_rbj_blocks(args):
-    """Randomized block-Jacobi block size for the 600-atom solve (Sec. 4b-ii): for block sizes
+    """Randomized block-Jacobi block size (Sec. 4b-ii).  600-atom solute (default): for block sizes
     100 ... 1024 and twelve partition seeds each, the solve of a benchmark step.  As in a step, the
     geometry update starts the partition on a host thread, c is evaluated meanwhile, and the solve
-    (FP64, from q = 0 to 1e-8) then fills and inverts the blocks on the GPU.  Reported per size:
-    PCG iterations (each seed's, mean, spread), solve ms and setup ms (what the step waits for)."""
+    (FP64, from q = 0 to 1e-8) then fills and inverts the blocks on the GPU.  With --scf-system
+    protein2000 (M ~ 150k): block sizes 100 ... 1024 and --seeds partition seeds each, one FP64
+    solve from q = 0 to 1e-8 of the same right-hand side per seed, the partition not overlapped.
+    Reported per size: PCG iterations (each seed's, mean, spread), solve ms and setup ms."""
     import numpy as np
     import torch
 
@@ -635,36 +638,47 @@ def bench_rbj_blocks(args):
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    s = I.protein_single_solve()
+    big = args.scf_system == "protein2000"
+    s = I.linear_solve_stress() if big else I.protein_single_solve()
     mol = Molecule.from_system(Context(), s)
     P = torch.tensor(s.P, dtype=torch.float64, device="cuda")
+    n_seeds = args.seeds if big else 12
+    blocks = (100, 256, 512, 768, 1024) if big else (100, 192, 256, 320, 384, 512, 768, 1024)
+    if big:
+        c, bz = mol.esp(P)
+        v = bz + c
     sizes = {}
-    for blk in (100, 192, 256, 320, 384, 512, 768, 1024):
+    for blk in blocks:
         rows = []
-        for k in range(12):
+        for k in range(n_seeds):
             seed = s.seeds["rbj"] + k
-            c, bz = mol.esp(P)
-            mol.solve(bz + c, precond="rbj", block=blk, seed=seed, tol=args.tol)  # last partition = this one
-            mol.update_geometry(s.xyz)  # starts the partition for it on a host thread
-            c, bz = mol.esp(P)
-            _, info = mol.solve(bz + c, precond="rbj", block=blk, seed=seed, tol=args.tol)
+            if big:
+                _, info = mol.solve(v, precond="rbj", block=blk, seed=seed, tol=args.tol)
+            else:
+                c, bz = mol.esp(P)
+                mol.solve(bz + c, precond="rbj", block=blk, seed=seed, tol=args.tol)  # last partition = this one
+                mol.update_geometry(s.xyz)  # starts the partition for it on a host thread
+                c, bz = mol.esp(P)
+                _, info = mol.solve(bz + c, precond="rbj", block=blk, seed=seed, tol=args.tol)
             torch.cuda.synchronize()
             rows.append(info)
         it = [i["iters"] for i in rows]
         solve = [i["solve_ms"] for i in rows]
         setup = [i["setup_ms"] for i in rows]
         sizes[str(blk)] = {"iters": it, "iters_mean": float(np.mean(it)), "iters_std": float(np.std(it)),
+                           "iters_min": int(np.min(it)), "iters_max": int(np.max(it)),
                            "solve_ms_mean": round(float(np.mean(solve)), 3),
                            "setup_ms_mean": round(float(np.mean(setup)), 3),
                            "solve_plus_setup_ms_mean": round(float(np.mean(solve) + np.mean(setup)), 3)}
         log(f"[bench] rbj block {blk}: {sizes[str(blk)]}")
     best = min(sizes, key=lambda b: sizes[b]["solve_plus_setup_ms_mean"])
-    out = {"metric": "PCG solve + setup ms of a benchmark step against the RBJ block size (12 partition seeds each)",
-           "value": sizes[best]["solve_plus_setup_ms_mean"], "unit": "ms", "n_gpus": 1, "steps": 12, "warmup": 0,
-           "ms_per_step": sizes[best]["solve_plus_setup_ms_mean"], "higher_is_better": False, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "protein600_631gs_rbj_blocks", "atoms": s.n_atoms, "surface_points": mol.M,
-                      "tol": args.tol, "first_seed": s.seeds["rbj"]},
+    label = "a cold solve" if big else "a benchmark step"
+    out = {"metric": f"PCG solve + setup ms of {label} against the RBJ block size ({n_seeds} partition seeds each)",
+           "value": sizes[best]["solve_plus_setup_ms_mean"], "unit": "ms", "n_gpus": 1, "steps": n_seeds,
+           "warmup": 0, "ms_per_step": sizes[best]["solve_plus_setup_ms_mean"], "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": ("protein2000" if big else "protein600") + "_631gs_rbj_blocks", "atoms": s.n_atoms,
+                      "surface_points": mol.M, "tol": args.tol, "first_seed": s.seeds["rbj"]},
            "block_sizes": sizes, "fastest_block": int(best)}
     print(json.dumps(out))
 
