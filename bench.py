@@ -90,19 +90,20 @@ def hermite_flops():
 
 
 # FP64 flops (FMA = 2, 1/sqrt = 1) per (primitive pair x point) evaluation of the kernels that
-# contract the auxiliary R^(n) in factored form (L <= 3), counted from the far-field branch of
+# contract the auxiliary R^(n) in factored form, counted from the far-field branch of
 # their source.  Point side: the common part 13 + 2N (P - C 3, r^2 5, far test 2, 1/sqrt 1,
 # r^-2 1, R^(0) 1, R^(n) 2 each up to N) plus the contraction and accumulation.  Pair side with
 # FP64 records (V up to order N >= 1): the far-field factored sums, 12 (P - C 3, r^2 5, far
-# test 2, 1/sqrt 1, r^-2 1) + s_0 .. s_N (N + 1) + the sums: 7 (N = 1), 23 (N = 2), 53 (N = 3).
+# test 2, 1/sqrt 1, r^-2 1) + s_0 .. s_N (N + 1) + the sums: 7 (N = 1), 23 (N = 2), 53 (N = 3),
+# 106 (N = 4).
 #   point side, c only (N = L):               esp_L          15  24  45  87
 #   point side, dc (N = L + 1):               grad_pts_L     22  37  75 156
 #   point side, c and dc:                     esp_grad_pts_L 24  41  81 164
-#   pair side, V up to L (N = L):             fock_v_L       15  21  38  69
-#   pair side, V' up to L + 1 (N = L + 1):    grad_v_L       21  38  69
-#                                             fock_grad_v_L  21  38  69
+#   pair side, V up to L (N = L):             fock_v_L       15  21  38  69 123
+#   pair side, V' up to L + 1 (N = L + 1):    grad_v_L       21  38  69 123
+#                                             fock_grad_v_L  21  38  69 123
 FACTORED = {"esp": (15, 24, 45, 87), "grad_pts": (22, 37, 75, 156), "esp_grad_pts": (24, 41, 81, 164),
-            "fock_v": (15, 21, 38, 69), "grad_v": (21, 38, 69), "fock_grad_v": (21, 38, 69)}
+            "fock_v": (15, 21, 38, 69, 123), "grad_v": (21, 38, 69, 123), "fock_grad_v": (21, 38, 69, 123)}
 
 
 def flop_model():

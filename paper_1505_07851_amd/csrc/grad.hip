@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256) void k_grad_pts(const GradPtsDesc *__restrict_
 // V'_tuv up to L+1 per pair (lane = pair), weights q_k; same as the Fock accumulation
 // -------------------------------------------------------------------------------------------
 template <int L, typename T, typename B>
-__global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds, int nd, long long n_items,
+__global__ __launch_bounds__(256, L == 3 ? 3 : 1) void k_grad_v(const GradVDesc *__restrict__ ds, int nd, long long n_items,
                                                 const B *__restrict__ boys_g) {
     __shared__ B tab[boys_lds_size<B, L + 1>()];
     load_boys<B, L + 1>(tab, boys_g);
@@ -292,8 +292,8 @@ __global__ __launch_bounds__(256) void k_grad_v(const GradVDesc *__restrict__ ds
         double V[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) V[t] = 0.0;
-        // FP64 records (V' up to order 1, 2 or 3): the far-field factored sums of low_order.h
-        constexpr bool FS = sizeof(T) == 8 && L <= 2;
+        // FP64 records (V' up to order 1 .. 4): the far-field factored sums of low_order.h
+        constexpr bool FS = sizeof(T) == 8 && L <= 3;
         constexpr int NS = FS ? L + 1 : 2;
         double S[nsums<NS>()], ipf = 0.0;
         if constexpr (FS) {

@@ -254,8 +254,8 @@ __global__ __launch_bounds__(256) void k_fock_v(const FockDesc *__restrict__ ds,
         double V[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) V[t] = 0.0;
-        // FP64 records (V up to order 1, 2 or 3): the far-field factored sums of low_order.h
-        constexpr bool FS = sizeof(T) == 8 && L >= 1 && L <= 3;
+        // FP64 records (V up to order 1 .. 4): the far-field factored sums of low_order.h
+        constexpr bool FS = sizeof(T) == 8 && L >= 1;
         constexpr int NS = FS ? L : 2;  // L = 0 (V_000 alone) keeps its plain form
         double S[nsums<NS>()], ipf = 0.0;
         if constexpr (FS) {

@@ -82,9 +82,11 @@ __device__ __forceinline__ void acc_V3(double q, T x, T y, T z, const T (&Rn)[4]
 // Sum layout (N = 1, 5 sums): S0, S1, S1_x, S1_y, S1_z (S1 unused at this order);
 // N = 2 adds (11 sums): S2_xx, S2_xy, S2_xz, S2_yy, S2_yz, S2_zz;
 // N = 3 adds (24 sums): S2_x, S2_y, S2_z, S3_xxx, S3_xxy, S3_xxz, S3_xyy, S3_xyz, S3_xzz, S3_yyy,
-// S3_yyz, S3_yzz, S3_zzz.
-template <int N> __host__ __device__ constexpr int nsums() { return N == 1 ? 5 : (N == 2 ? 11 : 24); }
-template <int N> __host__ __device__ constexpr int nvsum() { return N == 1 ? 4 : (N == 2 ? 10 : 20); }
+// S3_yyz, S3_yzz, S3_zzz;
+// N = 4 adds (46 sums): S2, S3_xx, S3_xy, S3_xz, S3_yy, S3_yz, S3_zz, then S4 over the quartic
+// monomials xxxx, xxxy, xxxz, xxyy, xxyz, xxzz, xyyy, xyyz, xyzz, xzzz, yyyy, yyyz, yyzz, yzzz, zzzz.
+template <int N> __host__ __device__ constexpr int nsums() { return N == 1 ? 5 : (N == 2 ? 11 : (N == 3 ? 24 : 46)); }
+template <int N> __host__ __device__ constexpr int nvsum() { return N == 1 ? 4 : (N == 2 ? 10 : (N == 3 ? 20 : 35)); }
 
 // s_0 .. s_N of one (pair, point) evaluation; (X, Y, Z) = P - C, ipf = 1 / pf (far_scale)
 template <int N, typename B>
@@ -103,7 +105,7 @@ __device__ __forceinline__ void eval_s(double X, double Y, double Z, const PairH
     } else {
         double Rn[N + 1];
         aux_Rn_near<N, double, B>(r2, h.p, h.pref, zeta2, zeta, tab, Rn);
-        constexpr double c[4] = {1.0, -1.0, 1.0 / 3.0, -1.0 / 15.0};  // (-1)^n / (2n-1)!!
+        constexpr double c[5] = {1.0, -1.0, 1.0 / 3.0, -1.0 / 15.0, 1.0 / 105.0};  // (-1)^n / (2n-1)!!
         const double qi = q * ipf;
 #pragma unroll
         for (int n = 0; n <= N; ++n) s[n] = (qi * Rn[n]) * c[n];
@@ -129,7 +131,7 @@ __device__ __forceinline__ void acc_S(const double (&s)[N + 1], double x, double
         S[8] = fma(ay, y, S[8]);
         S[9] = fma(ay, z, S[9]);
         S[10] = fma(az, z, S[10]);
-        if constexpr (N == 3) {
+        if constexpr (N >= 3) {
             S[11] += ax;
             S[12] += ay;
             S[13] += az;
@@ -145,6 +147,34 @@ __device__ __forceinline__ void acc_S(const double (&s)[N + 1], double x, double
             S[21] = fma(byy, z, S[21]);
             S[22] = fma(bzz, y, S[22]);
             S[23] = fma(bzz, z, S[23]);
+            if constexpr (N == 4) {
+                S[24] += s[2];
+                S[25] += bxx;
+                S[26] += bxy;
+                S[27] = fma(bx, z, S[27]);
+                S[28] += byy;
+                S[29] = fma(by, z, S[29]);
+                S[30] += bzz;
+                const double cx = s[4] * x, cy = s[4] * y, cz = s[4] * z;
+                const double cxx = cx * x, cxy = cx * y, cyy = cy * y, czz = cz * z;
+                const double cxxx = cxx * x, cxyy = cyy * x, cxzz = czz * x, cxyz = cxy * z;
+                const double cyyy = cyy * y, cyzz = czz * y, czzz = czz * z;
+                S[31] = fma(cxxx, x, S[31]);  // xxxx
+                S[32] = fma(cxxx, y, S[32]);  // xxxy
+                S[33] = fma(cxxx, z, S[33]);  // xxxz
+                S[34] = fma(cxyy, x, S[34]);  // xxyy
+                S[35] = fma(cxyz, x, S[35]);  // xxyz
+                S[36] = fma(cxzz, x, S[36]);  // xxzz
+                S[37] = fma(cxyy, y, S[37]);  // xyyy
+                S[38] = fma(cxyy, z, S[38]);  // xyyz
+                S[39] = fma(cxzz, y, S[39]);  // xyzz
+                S[40] = fma(cxzz, z, S[40]);  // xzzz
+                S[41] = fma(cyyy, y, S[41]);  // yyyy
+                S[42] = fma(cyyy, z, S[42]);  // yyyz
+                S[43] = fma(cyzz, y, S[43]);  // yyzz
+                S[44] = fma(cyzz, z, S[44]);  // yzzz
+                S[45] = fma(czzz, z, S[45]);  // zzzz
+            }
         }
     }
 }
@@ -164,7 +194,7 @@ __device__ __forceinline__ void fin_S(double pf, const double (&S)[nsums<N>()], 
         V[7] = pf * fma(3.0, S[8], -S[1]);
         V[8] = p3 * S[9];
         V[9] = pf * fma(3.0, S[10], -S[1]);
-        if constexpr (N == 3) {
+        if constexpr (N >= 3) {
             V[10] = pf * fma(-15.0, S[14], 9.0 * S[11]);
             V[11] = pf * fma(-15.0, S[15], 3.0 * S[12]);
             V[12] = pf * fma(-15.0, S[16], 3.0 * S[13]);
@@ -175,6 +205,27 @@ __device__ __forceinline__ void fin_S(double pf, const double (&S)[nsums<N>()], 
             V[17] = pf * fma(-15.0, S[21], 3.0 * S[13]);
             V[18] = pf * fma(-15.0, S[22], 3.0 * S[12]);
             V[19] = pf * fma(-15.0, S[23], 9.0 * S[13]);
+            if constexpr (N == 4) {
+                // order 4: R_400 = X^4 R4 + 6 X^2 R3 + 3 R2, R_310 = X^3 Y R4 + 3 X Y R3,
+                // R_220 = X^2 Y^2 R4 + (X^2 + Y^2) R3 + R2, R_211 = X^2 Y Z R4 + Y Z R3, with
+                // R^(n) = pf (-1)^n (2n-1)!! s_n / q: the constants 105, -15 and 3
+                const double s2 = 3.0 * S[24];
+                V[20] = pf * fma(105.0, S[31], fma(-90.0, S[25], 3.0 * s2));  // 400
+                V[21] = pf * fma(105.0, S[32], -45.0 * S[26]);               // 310
+                V[22] = pf * fma(105.0, S[33], -45.0 * S[27]);               // 301
+                V[23] = pf * fma(105.0, S[34], fma(-15.0, S[25] + S[28], s2)); // 220
+                V[24] = pf * fma(105.0, S[35], -15.0 * S[29]);               // 211
+                V[25] = pf * fma(105.0, S[36], fma(-15.0, S[25] + S[30], s2)); // 202
+                V[26] = pf * fma(105.0, S[37], -45.0 * S[26]);               // 130
+                V[27] = pf * fma(105.0, S[38], -15.0 * S[27]);               // 121
+                V[28] = pf * fma(105.0, S[39], -15.0 * S[26]);               // 112
+                V[29] = pf * fma(105.0, S[40], -45.0 * S[27]);               // 103
+                V[30] = pf * fma(105.0, S[41], fma(-90.0, S[28], 3.0 * s2));  // 040
+                V[31] = pf * fma(105.0, S[42], -45.0 * S[29]);               // 031
+                V[32] = pf * fma(105.0, S[43], fma(-15.0, S[28] + S[30], s2)); // 022
+                V[33] = pf * fma(105.0, S[44], -45.0 * S[29]);               // 013
+                V[34] = pf * fma(105.0, S[45], fma(-90.0, S[30], 3.0 * s2));  // 004
+            }
         }
     }
 }

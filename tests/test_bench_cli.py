@@ -37,7 +37,9 @@ def test_flop_model():
     assert m["esp_grad_pts_L0"] == m["grad_pts_L0"] + 2  # the potential's FMA beside the derivative
     for fam, counts in bench.FACTORED.items():
         assert [m[f"{fam}_L{L}"] for L in range(len(counts))] == list(counts), fam
-    # the L = 4 kernels form every R_tuv: table form with the generated Hermite recursion
+    # order-4 pair-side sums: 12 + s_0 .. s_4 + 53 (to order 3) + 53 for order 4
+    assert m["fock_grad_v_L3"] == m["fock_v_L4"] == 12 + 5 + 53 + 53
+    # the other L = 4 kernels form every R_tuv: table form with the generated Hermite recursion
     H = bench.hermite_flops()
     assert m["esp_L4"] == 12 + 2 * 4 + H[4] + 2 * bench.ntuv(4) + 1
     # every model grows with L
