@@ -210,8 +210,9 @@ template <typename T, typename B> constexpr const char *prec_tag() {
 // pairs per batch of wave-uniform record loads in the point-per-lane kernels
 template <int L> __host__ __device__ constexpr int pair_batch() { return L == 0 ? 4 : (L <= 2 ? 2 : 1); }
 // Pair batch of the point-side kernels that request the next batch's records during the current
-// evaluation (classes with L <= 2): both batches of records fit in the scalar registers
-template <int L> __host__ __device__ constexpr int pair_batch_pf() { return L == 0 ? 2 : 1; }
+// evaluation (classes with L <= 2): both batches of records fit in the scalar registers (at L = 1
+// with a few scalars of the item set aside in vector lanes outside the pair loop)
+template <int L> __host__ __device__ constexpr int pair_batch_pf() { return L <= 1 ? 2 : 1; }
 
 // Empty statements that need a wave-uniform value in scalar registers at this point: a scalar load
 // of it must have completed here (the compiler places its wait just before)
