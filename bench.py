@@ -712,7 +712,7 @@ def bench_oracle1t(args):
 
 # translation units of the kernels whose HBM counters are committed (profiles/traffic_protein600.txt)
 TRAFFIC_SOURCES = {"solver": ("pcm_internal.h", "solve.hip"),
-                   "integrals": ("pcm_internal.h", "low_order.h", "integrals.hip", "grad.hip")}
+                   "integrals": ("pcm_internal.h", "low_order.h", "contract.h", "integrals.hip", "grad.hip")}
 
 
 def source_digest(kernel="matvec_f64"):

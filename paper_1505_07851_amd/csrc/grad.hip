@@ -13,6 +13,7 @@
 // Per-atom sums run over fixed per-atom lists, so every result is bitwise reproducible.
 #include "pcm_internal.h"
 #include "low_order.h"
+#include "contract.h"
 
 #include <array>
 #include <cstring>
@@ -378,12 +379,17 @@ __global__ __launch_bounds__(64) void k_grad_contract(long long n, int nch, cons
         for (int d = 0; d < 6; ++d) gpair[(size_t)q * 6 + d] = 0.0;
         return;
     }
+    // sums over the chunks in chunk order; the loads of one chunk are issued together
     double V[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        double s = 0.0;
-        for (int c = 0; c < nch; ++c) s += vin[((size_t)c * NT + t) * n + qs];
-        V[t] = s;
+    for (int t = 0; t < NT; ++t) V[t] = 0.0;
+    for (int c = 0; c < nch; ++c) {
+        const double *__restrict__ vc = vin + (size_t)c * NT * n + qs;
+        double u[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) u[t] = vc[(size_t)t * n];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) V[t] += u[t];
     }
     int sp = ent_sp[q], ij = ent_ij[q];
     int a = spa[sp], b = spb[sp], i = ij >> 3, j = ij & 7;
@@ -482,11 +488,7 @@ __global__ __launch_bounds__(64 * GCW_WAVES) void k_grad_contract_w(
         j = ij & 7;
         ea = pexp[soff[a] + i];
         eb = pexp[soff[b] + j];
-        if (lane < NT) {
-            double acc = 0.0;
-            for (int c = 0; c < nch; ++c) acc += vin[((size_t)c * NT + lane) * n + qs];
-            sV[w][lane] = acc;
-        }
+        if (lane < NT) sV[w][lane] = chunk_sum(vin + (size_t)lane * n + qs, (size_t)NT * n, nch);
         if (lane < 3) {
             const double p = ea + eb;
             const double Ad = xyz[3 * satom[a] + lane], Bd = xyz[3 * satom[b] + lane];

@@ -24,6 +24,7 @@
 // chosen by timing a few candidates on first use.
 #include "pcm_internal.h"
 #include "low_order.h"
+#include "contract.h"
 
 #include <algorithm>
 #include <array>
@@ -363,11 +364,17 @@ __global__ void k_fock_contract(const FockCDesc *__restrict__ ds, int nd, long l
         for (int c = 0; c < NC; ++c) d.fprim[(size_t)q * NC + c] = 0.0;
         return;
     }
+    // sums over the chunks in chunk order; the loads of one chunk are issued together
     double V[NT];
-    for (int t = 0; t < NT; ++t) {
-        double s = 0.0;
-        for (int c = 0; c < d.nch; ++c) s += d.vin[((size_t)c * d.vnt + t) * n + qs];
-        V[t] = s;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) V[t] = 0.0;
+    for (int c = 0; c < d.nch; ++c) {
+        const double *__restrict__ vc = d.vin + (size_t)c * d.vnt * n + qs;
+        double u[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) u[t] = vc[(size_t)t * n];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) V[t] += u[t];
     }
     int a = d.spa[sp], b = d.spb[sp], i = ij >> 3, j = ij & 7;
     double ea = d.pexp[d.soff[a] + i], eb = d.pexp[d.soff[b] + j], p = ea + eb;
@@ -422,9 +429,7 @@ __global__ __launch_bounds__(64 * FCW_WAVES) void k_fock_contract_w(const FockCD
         i = ij >> 3;
         j = ij & 7;
         if (lane < NT) {
-            double acc = 0.0;
-            for (int c = 0; c < d.nch; ++c) acc += d.vin[((size_t)c * d.vnt + lane) * n + qs];
-            sV[w][lane] = acc;
+            sV[w][lane] = chunk_sum(d.vin + (size_t)lane * n + qs, (size_t)d.vnt * n, d.nch);
         }
         if (lane < 3) {
             const double ea = d.pexp[d.soff[a] + i], eb = d.pexp[d.soff[b] + j], p = ea + eb;
